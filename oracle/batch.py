@@ -1,0 +1,69 @@
+"""Array front end of the oracle: elementwise evaluation over a process pool.
+
+Test infrastructure only.  Workers are started with the 'spawn' method (a
+fresh interpreter, never a fork of a process that may hold GPU state) and
+touch no GPU.
+"""
+import multiprocessing as mp
+import os
+
+import numpy as np
+
+from .functions import evaluate1
+
+__all__ = ["evaluate", "default_workers"]
+
+_pool = None
+_pool_size = 0
+
+
+def default_workers():
+    n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _chunk(args):
+    fn, fmt, a, b = args
+    out = np.empty((3, len(a)), dtype=np.float64)
+    if b is None:
+        for i, x in enumerate(a.tolist()):
+            out[:, i] = evaluate1(fn, fmt, x)
+    else:
+        for i, (x, y) in enumerate(zip(a.tolist(), b.tolist())):
+            out[:, i] = evaluate1(fn, fmt, x, y)
+    return out
+
+
+def _get_pool(workers):
+    global _pool, _pool_size
+    if _pool is None or _pool_size != workers:
+        if _pool is not None:
+            _pool.terminate()
+        _pool = mp.get_context("spawn").Pool(workers)
+        _pool_size = workers
+    return _pool
+
+
+def evaluate(fn, fmt, a, b=None, workers=None, serial_below=256):
+    """Correctly rounded fn over numpy arrays ``a`` (and ``b``).
+
+    Inputs may be float64/float32/float16 arrays or bfloat16 values already
+    widened to float32; every value is converted exactly to a Python float.
+    Returns three float64 arrays (rn, hi, lo)."""
+    a = np.asarray(a).astype(np.float64).ravel()
+    if b is not None:
+        b = np.asarray(b).astype(np.float64).ravel()
+        assert b.shape == a.shape
+    n = a.shape[0]
+    if workers is None:
+        workers = default_workers()
+    if n < serial_below or workers <= 1:
+        out = _chunk((fn, fmt, a, b))
+    else:
+        nchunks = min(n, workers * 8)
+        bounds = np.linspace(0, n, nchunks + 1).astype(np.int64)
+        jobs = [(fn, fmt, a[s:e], None if b is None else b[s:e])
+                for s, e in zip(bounds[:-1], bounds[1:]) if e > s]
+        parts = _get_pool(workers).map(_chunk, jobs)
+        out = np.concatenate(parts, axis=1)
+    return out[0], out[1], out[2]

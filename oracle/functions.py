@@ -1,0 +1,483 @@
+"""The oracle proper: correctly rounded C99 real functions, one element at a time.
+
+Test infrastructure only: only ``tests/``, the smoke check and the benchmark's
+CPU-baseline leg may import this package.  Nothing here is shared with, or
+imported by, the GPU library.
+
+For a finite, non-special argument the oracle returns RN_fmt(f(x)), the exact
+value rounded to nearest-even in the output format (gradual underflow, overflow
+to infinity), found with Ziv's strategy: evaluate a rigorous ball at precision
+P; if both ends round to the same number that is the answer, else double P.
+The cap is 16384 bits; hitting it raises instead of returning a guess.  Ziv's
+loop only stops when the exact value is not itself a rounding boundary
+(a representable number or a midpoint); the cases where it can be one are
+detected and computed exactly (exp2 and log2 at powers of two, pow when x^y is
+a dyadic rational).  exp, sin, cos, tan, log (x != 1), atan (x != 0) and the
+hyperbolic functions of a nonzero dyadic are transcendental, hence never a
+boundary.
+
+Special inputs (zeros, infinities, NaN) follow C99 Annex F (F.9), which the
+paper adopts: "same results as libm, as specified in the ANSI C standard"
+(Section 5, opening paragraphs, and "Handling of Special Numbers").
+
+fmod is n - d*trunc(n/d) and remainder is n - d*rint_even(n/d); both results
+are exactly representable, so the oracle computes them with exact integer
+arithmetic (Section 5, "FP Remainder", Algorithm 1's postcondition).
+
+Besides the rounded value the oracle returns a high-precision approximation of
+the exact value as a pair of binary64 numbers (hi, lo), from which the tests
+compute ULP errors.
+"""
+import math
+
+from . import ball as B
+from .ball import Ball, exact, from_float, add, sub, mul, div, PrecisionError
+from .consts import pi, ln2
+from .elementary import (exp_ball, log_ball, sincos_reduced, sin_cos_ball,
+                         atan_ball, sinh_cosh_small)
+from .rounding import FORMATS, rn_dyadic, rn_ball
+
+__all__ = ["UNARY", "BINARY", "evaluate1", "OracleError"]
+
+NAN = float("nan")
+INF = float("inf")
+PREC_CAP = 16384
+
+UNARY = ("sin", "cos", "tan", "exp", "exp2", "log", "log2",
+         "sinh", "cosh", "tanh")
+BINARY = ("pow", "atan2", "fmod", "remainder")
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _sgn(x):
+    return -1 if math.copysign(1.0, x) < 0 else 1
+
+
+def _dyadic(x):
+    """Exact (m, e) with x = m * 2**e and m odd (x finite, nonzero)."""
+    n, d = x.as_integer_ratio()
+    e = -(d.bit_length() - 1)
+    tz = (n & -n).bit_length() - 1
+    return n >> tz, e + tz
+
+
+def _is_int(x):
+    return math.isfinite(x) and x == math.floor(x)
+
+
+def _is_odd_int(x):
+    if not _is_int(x) or abs(x) >= 2.0 ** 53:
+        return False
+    return int(x) & 1 == 1
+
+
+# --------------------------------------------------------------------------
+# Annex F special cases.  Each returns a float, or None for "compute".
+# --------------------------------------------------------------------------
+
+def _special_unary(fn, x):
+    if math.isnan(x):
+        return NAN
+    if fn in ("sin", "tan", "sinh", "tanh"):
+        if x == 0.0:
+            return x
+        if math.isinf(x):
+            if fn == "sinh":
+                return x
+            if fn == "tanh":
+                return math.copysign(1.0, x)
+            return NAN
+    elif fn == "cos":
+        if x == 0.0:
+            return 1.0
+        if math.isinf(x):
+            return NAN
+    elif fn == "cosh":
+        if x == 0.0:
+            return 1.0
+        if math.isinf(x):
+            return INF
+    elif fn in ("exp", "exp2"):
+        if x == 0.0:
+            return 1.0
+        if math.isinf(x):
+            return INF if x > 0 else 0.0
+    elif fn in ("log", "log2"):
+        if x == 0.0:
+            return -INF
+        if x < 0:
+            return NAN
+        if math.isinf(x):
+            return INF
+        if x == 1.0:
+            return 0.0
+    return None
+
+
+def _special_atan2(y, x, fmt):
+    """atan2(y, x) per Annex F; the pi-related constants are correctly
+    rounded into the output format (callers pass the same constants through
+    the normal path, so only the case analysis lives here)."""
+    if math.isnan(x) or math.isnan(y):
+        return NAN
+    sy = _sgn(y)
+    if y == 0.0:
+        if _sgn(x) < 0:              # x is -0 or negative (incl. -inf)
+            return sy * _round_const("pi", fmt)
+        return math.copysign(0.0, y)
+    if x == 0.0:
+        return sy * _round_const("pi/2", fmt)
+    if math.isinf(y):
+        if math.isinf(x):
+            return sy * _round_const("3pi/4" if x < 0 else "pi/4", fmt)
+        return sy * _round_const("pi/2", fmt)
+    if math.isinf(x):
+        if x < 0:
+            return sy * _round_const("pi", fmt)
+        return math.copysign(0.0, y)
+    return None
+
+
+def _special_pow(x, y):
+    """pow(x, y) per Annex F.  Returns a float or None."""
+    if y == 0.0:
+        return 1.0
+    if x == 1.0:
+        return 1.0
+    if math.isnan(x) or math.isnan(y):
+        return NAN
+    odd = _is_odd_int(y)
+    if x == 0.0:
+        if y < 0:
+            return math.copysign(INF, x) if odd else INF
+        return x if odd else 0.0
+    if math.isinf(y):
+        if x == -1.0:
+            return 1.0
+        if (abs(x) < 1.0) == (y < 0):
+            return INF
+        return 0.0
+    if math.isinf(x):
+        if x < 0:
+            if y < 0:
+                return -0.0 if odd else 0.0
+            return -INF if odd else INF
+        return 0.0 if y < 0 else INF
+    if x < 0 and not _is_int(y):
+        return NAN
+    return None
+
+
+def _special_fmod(x, y):
+    if math.isnan(x) or math.isnan(y) or math.isinf(x) or y == 0.0:
+        return NAN
+    if x == 0.0:
+        return x
+    if math.isinf(y):
+        return x
+    return None
+
+
+# --------------------------------------------------------------------------
+# Correctly rounded constants (used by atan2 specials)
+# --------------------------------------------------------------------------
+
+_const_cache = {}
+
+
+def _round_const(name, fmt):
+    key = (name, fmt.name)
+    if key not in _const_cache:
+        p = 200
+        num, den = {"pi": (1, 1), "pi/2": (1, 2), "pi/4": (1, 4),
+                    "3pi/4": (3, 4)}[name]
+        b = pi(p)
+        b = div(mul(b, exact(num), p), exact(den), p)
+        v = rn_ball(b, fmt)
+        assert v is not None
+        _const_cache[key] = v
+    return _const_cache[key]
+
+
+# --------------------------------------------------------------------------
+# Ball evaluators for finite, non-special arguments
+# --------------------------------------------------------------------------
+
+def _clamp_exp_arg(xb):
+    """Arguments beyond +-2100 give results outside every format's range
+    (2**3000 overflows, 2**-3000 is below half the smallest subnormal); clamp
+    so the ball code never sees astronomically large reduction integers."""
+    a = B.approx(xb)
+    if a > 2100:
+        return exact(2100)
+    if a < -2100:
+        return exact(-2100)
+    return xb
+
+
+def _ball_exp(x, prec):
+    return exp_ball(_clamp_exp_arg(from_float(x)), prec)
+
+
+def _ball_exp2(x, prec):
+    xb = mul(from_float(x), ln2(prec + 40), prec + 40)
+    return exp_ball(_clamp_exp_arg(xb), prec)
+
+
+def _ball_log(x, prec):
+    m, e = _dyadic(x)
+    return log_ball(m, e, prec)
+
+
+def _ball_log2(x, prec):
+    m, e = _dyadic(x)
+    return div(log_ball(m, e, prec + 8), ln2(prec + 16), prec + 8)
+
+
+def _ball_sin(x, prec):
+    m, e = _dyadic(x)
+    k, r = sincos_reduced(m, e, prec)
+    s, c = sin_cos_ball(r, prec + 8)
+    return (s, c, B.neg(s), B.neg(c))[k]
+
+
+def _ball_cos(x, prec):
+    m, e = _dyadic(x)
+    k, r = sincos_reduced(m, e, prec)
+    s, c = sin_cos_ball(r, prec + 8)
+    return (c, B.neg(s), B.neg(c), s)[k]
+
+
+def _ball_tan(x, prec):
+    m, e = _dyadic(x)
+    k, r = sincos_reduced(m, e, prec)
+    s, c = sin_cos_ball(r, prec + 8)
+    if k & 1:
+        return B.neg(div(c, s, prec + 8))
+    return div(s, c, prec + 8)
+
+
+def _ball_sinh(x, prec):
+    ax = abs(x)
+    if ax < 1.0:
+        s, _ = sinh_cosh_small(from_float(x), prec)
+        return s
+    E = exp_ball(_clamp_exp_arg(from_float(ax)), prec + 8)
+    s = B.scale2(sub(E, div(exact(1), E, prec + 8), prec + 8), -1)
+    return s if x > 0 else B.neg(s)
+
+
+def _ball_cosh(x, prec):
+    ax = abs(x)
+    if ax < 1.0:
+        _, c = sinh_cosh_small(from_float(ax), prec)
+        return c
+    E = exp_ball(_clamp_exp_arg(from_float(ax)), prec + 8)
+    return B.scale2(add(E, div(exact(1), E, prec + 8), prec + 8), -1)
+
+
+def _ball_tanh(x, prec):
+    ax = abs(x)
+    if ax < 1.0:
+        s, c = sinh_cosh_small(from_float(x), prec + 8)
+        return div(s, c, prec + 8)
+    # tanh = 1 - 2 / (E^2 + 1), E = exp|x|; |x| >= 1 so no cancellation issue
+    # for the rounding decision (the result is in [0.76, 1]).
+    a = min(ax, 40.0 + prec)          # tanh(a) = 1 - O(e^-2a): beyond this the
+    E2 = exp_ball(from_float(2 * a), prec + 8)
+    t = sub(exact(1), div(exact(2), add(E2, exact(1), prec + 8), prec + 8),
+            prec + 8)
+    if a < ax:
+        # exact tanh lies in (t_lo, 1): widen the ball to cover up to 1
+        t = add(t, Ball(1, 1, -(prec + 30)), prec + 8)
+    return t if x > 0 else B.neg(t)
+
+
+def _ball_atan2(y, x, prec):
+    ay, ax = abs(y), abs(x)
+    wp = prec + 16
+    if ay <= ax:
+        t = div(from_float(ay), from_float(ax), wp)
+        a = atan_ball(t, wp)
+    else:
+        t = div(from_float(ax), from_float(ay), wp)
+        a = sub(B.scale2(pi(wp + 8), -1), atan_ball(t, wp), wp)
+    if x < 0:
+        a = sub(pi(wp + 8), a, wp)
+    return a if y > 0 else B.neg(a)
+
+
+def _ball_pow(x, y, prec):
+    """|x|^y (sign handled by the caller) for finite nonzero x, y."""
+    m, e = _dyadic(abs(x))
+    wp = prec + 40
+    L = log_ball(m, e, wp)
+    z = mul(L, from_float(y), wp)
+    return exp_ball(_clamp_exp_arg(z), prec + 8)
+
+
+# --------------------------------------------------------------------------
+# Exact cases (Ziv would not terminate on them)
+# --------------------------------------------------------------------------
+
+def _int_root(n, k):
+    """Exact integer k-th root of n if n is a perfect k-th power, else None."""
+    if n == 1:
+        return 1
+    r = int(round(n ** (1.0 / k)))
+    for c in (r - 1, r, r + 1):
+        if c > 0 and c ** k == n:
+            return c
+    return None
+
+
+def _pow_exact(x, y):
+    """If |x|^y is a dyadic rational with few enough bits to possibly be a
+    representable number or a rounding midpoint, return it as (m, e);
+    otherwise None (then it is no rounding boundary and Ziv terminates)."""
+    mx, ex = _dyadic(abs(x))
+    my, ey = _dyadic(y)
+    if ey >= 0:                         # y is an integer
+        Y = my << ey
+        if mx == 1:
+            return 1, ex * Y
+        if Y < 0:
+            return None                 # 1 / odd^|Y| is not dyadic
+        if Y * mx.bit_length() > 400:
+            return None                 # odd result with > 54 significant bits
+        return mx ** Y, ex * Y
+    j = -ey                             # y = my / 2**j, my odd
+    if j > 12:
+        return None                     # only x == 1 qualifies (handled)
+    k = 1 << j
+    if ex % k != 0:
+        return None
+    root = _int_root(mx, k)
+    if root is None:
+        return None
+    ez = ex // k
+    if root == 1:
+        return 1, ez * my
+    if my < 0:
+        return None
+    if my * root.bit_length() > 400:
+        return None
+    return root ** my, ez * my
+
+
+# --------------------------------------------------------------------------
+# Exact fmod / remainder
+# --------------------------------------------------------------------------
+
+def _fmod_exact(x, y, ieee_remainder):
+    mx, ex = _dyadic(abs(x))
+    my, ey = _dyadic(abs(y))
+    e = min(ex, ey)
+    X = mx << (ex - e)
+    Y = my << (ey - e)
+    q, r = divmod(X, Y)
+    if ieee_remainder:
+        twice = 2 * r
+        if twice > Y or (twice == Y and (q & 1)):
+            r -= Y
+    return r, e
+
+
+# --------------------------------------------------------------------------
+# Driver
+# --------------------------------------------------------------------------
+
+_BALLS = {"sin": _ball_sin, "cos": _ball_cos, "tan": _ball_tan,
+          "exp": _ball_exp, "exp2": _ball_exp2, "log": _ball_log,
+          "log2": _ball_log2, "sinh": _ball_sinh, "cosh": _ball_cosh,
+          "tanh": _ball_tanh}
+
+
+def _dd(b):
+    """Midpoint of ball b as a binary64 pair (hi, lo); hi may be +-inf."""
+    hi = rn_dyadic(b.m, b.e, FORMATS["f64"])
+    if math.isinf(hi) or hi == 0.0:
+        return hi, 0.0
+    n, d = hi.as_integer_ratio()
+    eh = -(d.bit_length() - 1)
+    e = min(eh, b.e)
+    rest = (b.m << (b.e - e)) - (n << (eh - e))
+    lo = rn_dyadic(rest, e, FORMATS["f64"])
+    return hi, lo
+
+
+def _ziv(fn_ball, args, fmt, prec0):
+    prec = prec0
+    while prec <= PREC_CAP:
+        try:
+            b = fn_ball(*args, prec)
+        except PrecisionError:
+            prec *= 2
+            continue
+        v = rn_ball(b, fmt)
+        if v is not None:
+            hi, lo = _dd(b)
+            return v, hi, lo
+        prec *= 2
+    raise OracleError("precision cap reached for %r" % (args,))
+
+
+def evaluate1(fn, fmt_name, x, y=None):
+    """Correctly rounded fn(x) (or fn(x, y)) in format ``fmt_name``.
+
+    Binary functions take their arguments in C order: pow(x, y),
+    atan2(x=y_c, y=x_c) -- i.e. evaluate1("atan2", f, a, b) is atan2(a, b) --
+    fmod(x, y) and remainder(x, y).  Arguments are Python floats holding
+    values of that format (binary64 for 'f64', binary32 values for 'f32', and
+    so on).  Returns (rn, hi, lo): the
+    rounded result and a binary64 pair approximating the exact value (equal to
+    (rn, 0) when the result is exact or special)."""
+    fmt = FORMATS[fmt_name]
+    prec0 = fmt.p + 40
+    if fn in UNARY:
+        sp = _special_unary(fn, x)
+        if sp is not None:
+            return sp, sp, 0.0
+        if fn == "exp2" and _is_int(x):
+            k = int(max(-5000.0, min(5000.0, x)))
+            v = rn_dyadic(1, k, fmt)
+            return v, v, 0.0
+        if fn == "log2":
+            m, e = _dyadic(x)
+            if m == 1:
+                v = rn_dyadic(e, 0, fmt, zero_sign=1)
+                return v, v, 0.0
+        return _ziv(_BALLS[fn], (x,), fmt, prec0)
+    if fn == "atan2":
+        sp = _special_atan2(x, y, fmt)       # atan2(x, y) in C order
+        if sp is not None:
+            return sp, sp, 0.0
+        return _ziv(_ball_atan2, (x, y), fmt, prec0)
+    if fn == "pow":
+        sp = _special_pow(x, y)
+        if sp is not None:
+            return sp, sp, 0.0
+        neg = x < 0 and _is_odd_int(y)
+        ex = _pow_exact(x, y)
+        if ex is not None:
+            m, e = ex
+            v = rn_dyadic(-m if neg else m, e, fmt, zero_sign=-1 if neg else 1)
+            return v, v, 0.0
+        v, hi, lo = _ziv(_ball_pow, (x, y), fmt, prec0)
+        if neg:
+            return -v, -hi, -lo
+        return v, hi, lo
+    if fn in ("fmod", "remainder"):
+        sp = _special_fmod(x, y)
+        if sp is not None:
+            return sp, sp, 0.0
+        r, e = _fmod_exact(x, y, fn == "remainder")
+        if r == 0:
+            v = math.copysign(0.0, x)
+        else:
+            v = rn_dyadic(r if x > 0 else -r, e, fmt)
+        return v, v, 0.0
+    raise ValueError("unknown function %r" % fn)

@@ -1,0 +1,335 @@
+"""Pins for the oracle's functions against things it does not compute itself.
+
+* Annex F special values against the host C library (numpy calls glibc, whose
+  special-value behaviour follows C99 Annex F).
+* Correct rounding against mpmath evaluated at 400 bits (an independent
+  multiprecision implementation), on regular grids, random bit patterns and
+  huge trigonometric arguments (the paper's tester uses regular intervals,
+  arguments near multiples of pi/2 and random bit patterns; Section 6).
+* binary32 results against glibc's binary64 functions rounded to binary32:
+  where they disagree, the binary64 value must lie within two binary64 ulps
+  of a binary32 rounding midpoint (double rounding), which is the only way a
+  correctly rounded binary32 result can differ from it.
+* Exact cases: pow(x, 1/2) = sqrt(x), pow(x, 2) = x*x, pow(x, -1) = 1/x (IEEE
+  operations are correctly rounded), exp2 and log2 at powers of two, fmod and
+  remainder against the host's exact fmod/remainder, and the paper's worked
+  remainder example fmod(1e40, 0.75) = 0.25 (Section 5, "FP Remainder").
+* Identities evaluated on the oracle's balls: sin^2 + cos^2 = 1,
+  cosh^2 - sinh^2 = 1, exp(log x) = x.
+"""
+import math
+import random
+import warnings
+
+import mpmath
+import numpy as np
+import pytest
+
+from oracle import evaluate, evaluate1
+from oracle import ball as B
+from oracle.elementary import exp_ball, log_ball, sincos_reduced, sin_cos_ball, sinh_cosh_small
+from oracle.rounding import FORMATS, rn_ball
+
+warnings.simplefilter("ignore", RuntimeWarning)
+
+SPECIALS = [0.0, -0.0, math.inf, -math.inf, math.nan, 1.0, -1.0, 0.5, -0.5,
+            2.0, -2.0, 3.0, -3.0, 2.5, -2.5, 5e-324, -5e-324, 1e300, -1e300]
+
+NP_UNARY = {"sin": np.sin, "cos": np.cos, "tan": np.tan, "exp": np.exp,
+            "exp2": np.exp2, "log": np.log, "log2": np.log2, "sinh": np.sinh,
+            "cosh": np.cosh, "tanh": np.tanh}
+
+
+def same(a, b):
+    if math.isnan(a) or math.isnan(b):
+        return math.isnan(a) and math.isnan(b)
+    return a == b and math.copysign(1, a) == math.copysign(1, b)
+
+
+# --------------------------------------------------------------------------
+# Annex F
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("fn", sorted(NP_UNARY))
+def test_unary_specials_match_host_libm(fn):
+    for x in [0.0, -0.0, math.inf, -math.inf, math.nan, 1.0, -1.0]:
+        got = evaluate1(fn, "f64", x)[0]
+        want = float(NP_UNARY[fn](np.float64(x)))
+        assert same(got, want), (fn, x, got, want)
+
+
+def _is_special(v):
+    return v == 0 or not math.isfinite(v)
+
+
+def test_pow_atan2_fmod_remainder_special_grid_matches_host_libm():
+    # only the Annex F cases: a special argument or a special result (numpy's
+    # own atan2 is not correctly rounded for ordinary arguments)
+    for x in SPECIALS:
+        for y in SPECIALS:
+            if not (_is_special(x) or _is_special(y) or x in (1.0, -1.0)):
+                continue
+            for fn, host in (("pow", np.power), ("atan2", np.arctan2),
+                             ("fmod", np.fmod), ("remainder", None)):
+                got = evaluate1(fn, "f64", x, y)[0]
+                if host is None:
+                    try:
+                        want = math.remainder(x, y)
+                    except ValueError:
+                        want = math.nan
+                else:
+                    want = float(host(np.float64(x), np.float64(y)))
+                if fn == "atan2" and math.isfinite(want) and want != 0:
+                    want = math.atan2(x, y)     # glibc's atan2
+                assert same(got, want), (fn, x, y, got, want)
+
+
+def test_binary32_specials_match_host_libm():
+    for x in SPECIALS:
+        xf = float(np.float32(x))
+        for fn, f in NP_UNARY.items():
+            got = evaluate1(fn, "f32", xf)[0]
+            want = float(f(np.float32(xf)))
+            if math.isnan(want) or math.isinf(want) or want == 0.0:
+                assert same(got, want), (fn, xf)
+        for y in SPECIALS:
+            yf = float(np.float32(y))
+            for fn, host in (("pow", np.power), ("atan2", np.arctan2)):
+                got = evaluate1(fn, "f32", xf, yf)[0]
+                want = float(host(np.float32(xf), np.float32(yf)))
+                if math.isnan(want) or math.isinf(want) or want == 0.0 or \
+                        not math.isfinite(xf) or not math.isfinite(yf) or xf == 0 or yf == 0:
+                    assert same(got, want), (fn, xf, yf, got, want)
+
+
+# --------------------------------------------------------------------------
+# correct rounding vs mpmath at 400 bits
+# --------------------------------------------------------------------------
+
+MP = {"sin": mpmath.sin, "cos": mpmath.cos, "tan": mpmath.tan,
+      "exp": mpmath.exp, "exp2": lambda x: mpmath.power(2, x),
+      "log": mpmath.log, "log2": lambda x: mpmath.log(x, 2),
+      "sinh": mpmath.sinh, "cosh": mpmath.cosh, "tanh": mpmath.tanh}
+
+
+def _mp_f64(fn, x, y=None):
+    with mpmath.workprec(400):
+        if fn == "pow":
+            v = mpmath.power(mpmath.mpf(x), mpmath.mpf(y))
+        elif fn == "atan2":
+            v = mpmath.atan2(mpmath.mpf(x), mpmath.mpf(y))
+        else:
+            v = MP[fn](mpmath.mpf(x))
+        return v
+
+
+def _to_f64(v):
+    # mpmath's float() rounds to nearest; beyond the double range it gives inf
+    try:
+        return float(v)
+    except OverflowError:
+        return math.inf if v > 0 else -math.inf
+
+
+def _inputs(fn, rng, n):
+    xs = []
+    for _ in range(n):
+        c = rng.random()
+        if fn in ("log", "log2"):
+            xs.append(abs(_rand_bits(rng)) if c < 0.5 else rng.uniform(0, 1000))
+        elif fn in ("exp", "exp2", "sinh", "cosh", "tanh"):
+            lim = 1100 if fn == "exp2" else 760
+            xs.append(rng.uniform(-lim, lim) if c < 0.5 else
+                      math.copysign(10 ** rng.uniform(-300, 3), rng.random() - 0.5))
+        else:
+            xs.append(rng.uniform(-10, 10) if c < 0.4 else _rand_bits(rng))
+    return [x for x in xs if math.isfinite(x) and x != 0]
+
+
+def _rand_bits(rng):
+    import struct
+    return struct.unpack("<d", rng.getrandbits(64).to_bytes(8, "little"))[0]
+
+
+@pytest.mark.parametrize("fn", sorted(MP))
+def test_unary_correct_rounding_vs_mpmath(fn):
+    rng = random.Random(hash(fn) & 0xffff)
+    for x in _inputs(fn, rng, 250):
+        got, hi, lo = evaluate1(fn, "f64", x)
+        v = _mp_f64(fn, x)
+        want = _to_f64(v)
+        assert same(got, want), (fn, x.hex(), got, want)
+        if math.isfinite(got) and got != 0 and abs(got) > 1e-290:
+            with mpmath.workprec(400):
+                err = abs((mpmath.mpf(hi) + mpmath.mpf(lo)) - v) / abs(v)
+            assert err < mpmath.mpf(2) ** -100, (fn, x)
+
+
+def test_trig_huge_and_near_multiples_of_half_pi_vs_mpmath():
+    rng = random.Random(11)
+    xs = [6381956970095103.0 * 2.0 ** 797, 1e22, 1e300, 1.7976931348623157e308,
+          5.319372648326541e255, 2.0 ** 1000]
+    # doubles nearest to k pi/2 for assorted k (the reduction's hard cases)
+    with mpmath.workprec(300):
+        for k in [1, 2, 3, 7, 11, 355, 710, 1e6, 123456789, 2 ** 40 + 3, 2 ** 50 + 1]:
+            xs.append(float(mpmath.mpf(k) * mpmath.pi / 2))
+    xs += [math.ldexp(rng.random(), rng.randint(10, 1023)) for _ in range(60)]
+    for fn in ("sin", "cos", "tan"):
+        for x in xs:
+            got = evaluate1(fn, "f64", x)[0]
+            with mpmath.workprec(2600):
+                v = MP[fn](mpmath.mpf(x))
+            assert same(got, _to_f64(v)), (fn, x)
+
+
+def test_pow_atan2_correct_rounding_vs_mpmath():
+    rng = random.Random(7)
+    for _ in range(300):
+        x = rng.uniform(0, 30) if rng.random() < 0.6 else abs(_rand_bits(rng))
+        y = rng.uniform(-30, 30) if rng.random() < 0.6 else rng.uniform(-1e3, 1e3)
+        if not (math.isfinite(x) and x > 0):
+            continue
+        got = evaluate1("pow", "f64", x, y)[0]
+        want = _to_f64(_mp_f64("pow", x, y))
+        if want != 0 and abs(want) < 2.2250738585072014e-308:
+            with mpmath.workprec(400):
+                want = float(mpmath.mpf(_mp_f64("pow", x, y)))
+        assert same(got, want), ("pow", x, y, got, want)
+    for _ in range(300):
+        y = _rand_bits(rng) if rng.random() < 0.5 else rng.uniform(-10, 10)
+        x = _rand_bits(rng) if rng.random() < 0.5 else rng.uniform(-10, 10)
+        if not (math.isfinite(x) and math.isfinite(y)) or x == 0 or y == 0:
+            continue
+        got = evaluate1("atan2", "f64", y, x)[0]
+        want = _to_f64(_mp_f64("atan2", y, x))
+        assert same(got, want), ("atan2", y, x, got, want)
+
+
+def test_negative_base_integer_exponent_sign():
+    for x, y in ((-2.0, 3.0), (-2.0, 4.0), (-1.5, 7.0), (-3.0, -3.0), (-0.7, 101.0)):
+        got = evaluate1("pow", "f64", x, y)[0]
+        with mpmath.workprec(400):
+            want = float(mpmath.power(mpmath.mpf(x), mpmath.mpf(y)))
+        assert same(got, want), (x, y)
+
+
+# --------------------------------------------------------------------------
+# binary32 against glibc binary64 rounded once more
+# --------------------------------------------------------------------------
+
+def _midpoint_distance_in_dulps(d):
+    """Distance of the binary64 value d to the nearest binary32 rounding
+    midpoint, in binary64 ulps of d."""
+    f = np.float32(d)
+    lo = np.nextafter(f, np.float32(-np.inf))
+    hi = np.nextafter(f, np.float32(np.inf))
+    mids = [(float(f) + float(lo)) / 2, (float(f) + float(hi)) / 2]
+    u = math.ulp(d)
+    return min(abs(d - m) for m in mids) / u
+
+
+@pytest.mark.parametrize("fn", ["sin", "cos", "tan", "exp", "log", "exp2", "log2",
+                                "sinh", "cosh", "tanh"])
+def test_binary32_vs_glibc_double_rounded(fn):
+    # a strided sweep over all positive and negative binary32 bit patterns
+    stride = 1 << 16
+    bits = np.arange(0, 1 << 32, stride, dtype=np.uint64) + 12345
+    xs = bits.astype(np.uint32).view(np.float32)
+    xs = xs[np.isfinite(xs)]
+    rn, _, _ = evaluate(fn, "f32", xs)
+    d = NP_UNARY[fn](xs.astype(np.float64))
+    f = d.astype(np.float32).astype(np.float64)
+    bad = ~((rn == f) | (np.isnan(rn) & np.isnan(f)))
+    for i in np.nonzero(bad)[0]:
+        assert math.isfinite(d[i]) and _midpoint_distance_in_dulps(d[i]) <= 2.0, \
+            (fn, float(xs[i]), rn[i], f[i])
+    assert bad.sum() <= max(2, len(xs) // 1000)
+
+
+# --------------------------------------------------------------------------
+# exact cases
+# --------------------------------------------------------------------------
+
+def test_pow_exact_cases_against_ieee_operations():
+    rng = random.Random(9)
+    for _ in range(2000):
+        x = abs(_rand_bits(rng))
+        if not math.isfinite(x) or x == 0:
+            continue
+        assert evaluate1("pow", "f64", x, 0.5)[0] == math.sqrt(x), x
+        assert evaluate1("pow", "f64", x, -1.0)[0] == 1.0 / x, x
+        assert evaluate1("pow", "f64", x, 1.0)[0] == x
+        sq = x * x
+        assert same(evaluate1("pow", "f64", x, 2.0)[0], sq), x
+        assert same(evaluate1("pow", "f64", -x, 2.0)[0], sq), x
+    for n in range(-1080, 1030, 7):
+        want = math.inf if n >= 1024 else (math.ldexp(1.0, n) if n > -1075 else 0.0)
+        assert evaluate1("pow", "f64", 2.0, float(n))[0] == want
+        assert evaluate1("exp2", "f64", float(n))[0] == want
+    for n in range(-1074, 1024, 5):
+        assert evaluate1("log2", "f64", 2.0 ** n)[0] == float(n)
+    # small odd bases: exact products
+    for b in (3.0, 5.0, 7.0, 0.75, 1.5):
+        for k in range(1, 40):
+            assert evaluate1("pow", "f64", b, float(k))[0] == float(mpmath.mpf(b) ** k)
+
+
+def test_fmod_remainder_exact_against_host():
+    rng = random.Random(10)
+    for _ in range(20000):
+        x = _rand_bits(rng)
+        y = _rand_bits(rng) if rng.random() < 0.7 else rng.uniform(-10, 10)
+        if not (math.isfinite(x) and math.isfinite(y)) or y == 0:
+            continue
+        assert same(evaluate1("fmod", "f64", x, y)[0], math.fmod(x, y)), (x, y)
+        assert same(evaluate1("remainder", "f64", x, y)[0], math.remainder(x, y)), (x, y)
+
+
+def test_fmod_paper_worked_example():
+    # Section 5, "FP Remainder": fmod(1e40, 0.75); the exact answer is 0.25
+    assert evaluate1("fmod", "f64", 1e40, 0.75)[0] == 0.25
+
+
+def test_atan2_quadrant_constants():
+    q = evaluate1("atan2", "f64", 1.0, 1.0)[0]
+    assert q == math.pi / 4
+    for y in (1e-300, 3.0, 1e300):
+        assert evaluate1("atan2", "f64", y, y)[0] == math.pi / 4
+        assert evaluate1("atan2", "f64", y, 0.0)[0] == math.pi / 2
+        assert evaluate1("atan2", "f64", -y, -y)[0] == -3 * math.pi / 4
+
+
+# --------------------------------------------------------------------------
+# identities on balls
+# --------------------------------------------------------------------------
+
+def _contains_one(b):
+    lo, hi, e = b.lo_hi()
+    return lo * 2 ** e <= 1 <= hi * 2 ** e if e >= 0 else (lo <= (1 << -e) <= hi)
+
+
+def test_identities_on_balls():
+    rng = random.Random(12)
+    for _ in range(200):
+        x = _rand_bits(rng)
+        if not math.isfinite(x) or x == 0:
+            continue
+        n, d = x.as_integer_ratio()
+        k, r = sincos_reduced(n, -(d.bit_length() - 1), 120)
+        s, c = sin_cos_ball(r, 120)
+        one = B.add(B.mul(s, s, 200), B.mul(c, c, 200), 200)
+        assert _contains_one(one)
+    for _ in range(200):
+        x = rng.uniform(-0.99, 0.99)
+        s, c = sinh_cosh_small(B.from_float(x), 120)
+        one = B.sub(B.mul(c, c, 200), B.mul(s, s, 200), 200)
+        assert _contains_one(one)
+    for _ in range(200):
+        x = abs(_rand_bits(rng))
+        if not math.isfinite(x) or x == 0:
+            continue
+        n, d = x.as_integer_ratio()
+        L = log_ball(n, -(d.bit_length() - 1), 200)
+        back = exp_ball(L, 200)
+        ratio = B.div(back, B.from_float(x), 200)
+        assert _contains_one(ratio)
