@@ -1,0 +1,161 @@
+/*
+ * libm_hip -- elementwise C99 real math functions on AMD Instinct MI355X
+ * (gfx950), after N. Shibata and F. Petrogalli, "SLEEF: A Portable
+ * Vectorized Library of C Standard Mathematical Functions" (IEEE TPDS 2020).
+ *
+ * One entry point per (function, accuracy variant, element type) over device
+ * arrays.  Semantics follow the paper's library contract (Section 5,
+ * "Overview of Library Implementation" and "Handling of Special Numbers"):
+ *
+ *   - u10 variants are within 1.0 ULP of the exact result, u35 variants
+ *     within 3.5 ULP; fmod and remainder are exact;
+ *   - special arguments (zeros, infinities, NaN) give the values C99 Annex F
+ *     prescribes; no errno, no floating-point exception flags;
+ *   - round-to-nearest mode only; subnormal inputs and outputs are honoured.
+ *
+ * Conventions shared by every entry point
+ *   pointers   device pointers (hipMalloc / torch allocations on the current
+ *              device).  Any alignment is accepted; 16-byte aligned arrays use
+ *              128-bit loads and stores.  The caller owns all buffers.
+ *   n          element count (64-bit); n == 0 returns LIBM_HIP_OK and launches
+ *              nothing.
+ *   aliasing   in place (out == an input) is allowed; partial overlap is not.
+ *   stream     a hipStream_t passed as void* (NULL = the null stream).  Calls
+ *              only enqueue work: they return before the results exist.
+ *   errors     LIBM_HIP_ERR_INVALID for a NULL pointer with n > 0 (checked
+ *              before any HIP call), LIBM_HIP_ERR_UNSUPPORTED for an unknown
+ *              combination in the generic dispatcher, LIBM_HIP_ERR_HIP when
+ *              the kernel launch fails; libm_hip_last_error() then returns a
+ *              thread-local message.  There are no per-element errors.
+ *   threads    every call is thread-safe.
+ *
+ * Element types: f64 = double, f32 = float, bf16 and f16 = uint16_t bit
+ * patterns of bfloat16 / IEEE binary16 (evaluated in binary32 and rounded to
+ * nearest-even once).  "f32_via_f64" variants take and return float but
+ * evaluate the binary64 u10 function and round once.
+ */
+#ifndef LIBM_HIP_H
+#define LIBM_HIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LIBM_HIP_OK = 0,
+  LIBM_HIP_ERR_INVALID = 1,
+  LIBM_HIP_ERR_UNSUPPORTED = 2,
+  LIBM_HIP_ERR_HIP = 3,
+  LIBM_HIP_ERR_NOMEM = 4
+} libm_hip_status;
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char* libm_hip_last_error(void);
+/* Library version string. */
+const char* libm_hip_version(void);
+
+/* ------------------------------------------------------------------------
+ * Unary functions, y[i] = f(x[i]).
+ *
+ * sin, cos, tan (Section 5, "sin and cos", "tan", "The Payne-Hanek Range
+ * Reduction"): two Cody-Waite levels (|x| < 15, |x| < 1e14) and the
+ * vectorised Payne-Hanek reduction for larger |x|; a sine polynomial on
+ * [-pi/2, pi/2]; tan through the double-angle formula on [-pi/8, pi/8].
+ * exp (Section 5, "exp"), log (Section 5, "log").  exp2, log2, sinh, cosh
+ * and tanh are not described in the paper and are built from the same
+ * reductions and double-double pieces.
+ * ---------------------------------------------------------------------- */
+#define LIBM_HIP_DECL_UNARY(fn, var)                                                       \
+  libm_hip_status libm_hip_##fn##_##var##_f64(const double* x, double* y, size_t n,        \
+                                              void* stream);                               \
+  libm_hip_status libm_hip_##fn##_##var##_f32(const float* x, float* y, size_t n,          \
+                                              void* stream);
+#define LIBM_HIP_DECL_UNARY_HALF(fn)                                                       \
+  libm_hip_status libm_hip_##fn##_u10_bf16(const uint16_t* x, uint16_t* y, size_t n,       \
+                                           void* stream);                                  \
+  libm_hip_status libm_hip_##fn##_u10_f16(const uint16_t* x, uint16_t* y, size_t n,        \
+                                          void* stream);                                   \
+  libm_hip_status libm_hip_##fn##_u10_f32_via_f64(const float* x, float* y, size_t n,      \
+                                                  void* stream);
+
+LIBM_HIP_DECL_UNARY(sin, u10)
+LIBM_HIP_DECL_UNARY(sin, u35)
+LIBM_HIP_DECL_UNARY(cos, u10)
+LIBM_HIP_DECL_UNARY(cos, u35)
+LIBM_HIP_DECL_UNARY(tan, u10)
+LIBM_HIP_DECL_UNARY(tan, u35)
+LIBM_HIP_DECL_UNARY(exp, u10)
+LIBM_HIP_DECL_UNARY(exp2, u10)
+LIBM_HIP_DECL_UNARY(log, u10)
+LIBM_HIP_DECL_UNARY(log2, u10)
+LIBM_HIP_DECL_UNARY(sinh, u10)
+LIBM_HIP_DECL_UNARY(cosh, u10)
+LIBM_HIP_DECL_UNARY(tanh, u10)
+LIBM_HIP_DECL_UNARY_HALF(sin)
+LIBM_HIP_DECL_UNARY_HALF(cos)
+LIBM_HIP_DECL_UNARY_HALF(tan)
+LIBM_HIP_DECL_UNARY_HALF(exp)
+LIBM_HIP_DECL_UNARY_HALF(exp2)
+LIBM_HIP_DECL_UNARY_HALF(log)
+LIBM_HIP_DECL_UNARY_HALF(log2)
+LIBM_HIP_DECL_UNARY_HALF(sinh)
+LIBM_HIP_DECL_UNARY_HALF(cosh)
+LIBM_HIP_DECL_UNARY_HALF(tanh)
+
+/* ------------------------------------------------------------------------
+ * Binary functions, C argument order.
+ *
+ * pow(x, y) (Section 5, "pow": e^(y log x) in double-double), out = x^y.
+ * atan2(y, x): quadrant logic around the atan polynomial on [0, 1]
+ *   (Section 5, "atan"); out = atan2(y, x).
+ * fmod(x, y), remainder(x, y): exact; long division with floating-point
+ *   digits (Section 5, "FP Remainder", Algorithm 1, Appendices B and C),
+ *   extended to quotients beyond DBL_MAX.  remainder rounds the quotient to
+ *   nearest-even (IEEE 754).
+ * ---------------------------------------------------------------------- */
+#define LIBM_HIP_DECL_BINARY(fn, var, T, tag)                                              \
+  libm_hip_status libm_hip_##fn##var##_##tag(const T* a, const T* b, T* out, size_t n,     \
+                                             void* stream);
+LIBM_HIP_DECL_BINARY(pow, _u10, double, f64)
+LIBM_HIP_DECL_BINARY(pow, _u10, float, f32)
+LIBM_HIP_DECL_BINARY(pow, _u10, uint16_t, bf16)
+LIBM_HIP_DECL_BINARY(pow, _u10, uint16_t, f16)
+LIBM_HIP_DECL_BINARY(pow, _u10, float, f32_via_f64)
+LIBM_HIP_DECL_BINARY(atan2, _u10, double, f64)
+LIBM_HIP_DECL_BINARY(atan2, _u10, float, f32)
+LIBM_HIP_DECL_BINARY(atan2, _u10, uint16_t, bf16)
+LIBM_HIP_DECL_BINARY(atan2, _u10, uint16_t, f16)
+LIBM_HIP_DECL_BINARY(atan2, _u10, float, f32_via_f64)
+LIBM_HIP_DECL_BINARY(fmod, , double, f64)
+LIBM_HIP_DECL_BINARY(fmod, , float, f32)
+LIBM_HIP_DECL_BINARY(remainder, , double, f64)
+LIBM_HIP_DECL_BINARY(remainder, , float, f32)
+
+/* ------------------------------------------------------------------------
+ * Generic dispatcher: the same kernels selected by enums.  b must be NULL
+ * for unary functions.  Returns LIBM_HIP_ERR_UNSUPPORTED for a combination
+ * the library does not serve (e.g. u35 in bf16).
+ * ---------------------------------------------------------------------- */
+typedef enum {
+  LIBM_HIP_SIN = 0, LIBM_HIP_COS, LIBM_HIP_TAN, LIBM_HIP_EXP, LIBM_HIP_EXP2,
+  LIBM_HIP_LOG, LIBM_HIP_LOG2, LIBM_HIP_POW, LIBM_HIP_ATAN2, LIBM_HIP_SINH,
+  LIBM_HIP_COSH, LIBM_HIP_TANH, LIBM_HIP_FMOD, LIBM_HIP_REMAINDER,
+  LIBM_HIP_NUM_FN
+} libm_hip_fn;
+typedef enum { LIBM_HIP_U10 = 0, LIBM_HIP_U35 = 1, LIBM_HIP_EXACT = 2 } libm_hip_variant;
+typedef enum {
+  LIBM_HIP_F64 = 0, LIBM_HIP_F32 = 1, LIBM_HIP_BF16 = 2, LIBM_HIP_F16 = 3,
+  LIBM_HIP_F32_VIA_F64 = 4
+} libm_hip_dtype;
+
+libm_hip_status libm_hip_eval(libm_hip_fn fn, libm_hip_variant v, libm_hip_dtype t,
+                              const void* a, const void* b, void* out, size_t n,
+                              void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBM_HIP_H */

@@ -6,6 +6,7 @@ touch no GPU.
 """
 import multiprocessing as mp
 import os
+import sys
 
 import numpy as np
 
@@ -39,7 +40,20 @@ def _get_pool(workers):
     if _pool is None or _pool_size != workers:
         if _pool is not None:
             _pool.terminate()
-        _pool = mp.get_context("spawn").Pool(workers)
+        # The workers only need this module.  Hide the main script from the
+        # spawn bootstrap so that scripts without a __main__ guard are not
+        # re-executed in every worker.
+        main = sys.modules.get("__main__")
+        saved = {}
+        for attr in ("__file__", "__spec__"):
+            if main is not None and hasattr(main, attr):
+                saved[attr] = getattr(main, attr)
+                setattr(main, attr, None)
+        try:
+            _pool = mp.get_context("spawn").Pool(workers)
+        finally:
+            for attr, v in saved.items():
+                setattr(main, attr, v)
         _pool_size = workers
     return _pool
 

@@ -1,0 +1,208 @@
+"""Python binding of libm_hip (argument marshalling only).
+
+Every computation runs in the HIP kernels of ``libm_hip.so`` (built from
+``csrc/`` by ``paper_2001_09258_amd.build``).  PyTorch supplies device memory
+and the current stream; nothing here evaluates a math function, and there is
+no CPU fallback: if the shared library is missing, every call raises.
+
+Two layers:
+
+* ``libm_hip_<fn>_<variant>_<dtype>(a_ptr, [b_ptr,] out_ptr, n, stream)`` --
+  one Python callable per C-ABI entry point, same name and argument order
+  (pointers and the stream as integers), returning the status code;
+* ``sin(x, variant="u10")``, ``pow(x, y)``, ``atan2(y, x)``, ... -- torch
+  front ends: contiguous device tensors of float64 / float32 / bfloat16 /
+  float16 in, a new tensor (or ``out=``) back, enqueued on the current stream.
+"""
+import ctypes
+import os
+
+__all__ = ["load", "library_path", "UNARY", "BINARY", "VARIANTS", "entry_name",
+           "call", "evaluate", "sin", "cos", "tan", "exp", "exp2", "log", "log2",
+           "sinh", "cosh", "tanh", "pow", "atan2", "fmod", "remainder",
+           "LibmHipError"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBNAME = "libm_hip.so"
+
+UNARY = ("sin", "cos", "tan", "exp", "exp2", "log", "log2", "sinh", "cosh", "tanh")
+BINARY = ("pow", "atan2", "fmod", "remainder")
+# accuracy variants served per function
+VARIANTS = {fn: ("u10",) for fn in UNARY + ("pow", "atan2")}
+VARIANTS.update({"sin": ("u10", "u35"), "cos": ("u10", "u35"), "tan": ("u10", "u35"),
+                 "fmod": ("exact",), "remainder": ("exact",)})
+DTYPES = ("f64", "f32", "bf16", "f16", "f32_via_f64")
+
+
+class LibmHipError(RuntimeError):
+    pass
+
+
+def library_path():
+    return os.path.join(_HERE, _LIBNAME)
+
+
+def entry_name(fn, variant, dtype):
+    if fn in ("fmod", "remainder"):
+        return "libm_hip_%s_%s" % (fn, dtype)
+    return "libm_hip_%s_%s_%s" % (fn, variant, dtype)
+
+
+def served(fn, variant, dtype):
+    """True if the library exports this combination."""
+    if variant not in VARIANTS.get(fn, ()):
+        return False
+    if fn in ("fmod", "remainder"):
+        return dtype in ("f64", "f32")
+    if variant == "u35":
+        return dtype in ("f64", "f32")
+    return dtype in DTYPES
+
+
+def all_entry_points():
+    out = []
+    for fn in UNARY + BINARY:
+        for v in VARIANTS[fn]:
+            for dt in DTYPES:
+                if served(fn, v, dt):
+                    out.append((fn, v, dt, entry_name(fn, v, dt)))
+    return out
+
+
+_lib = None
+
+
+def load():
+    """Load libm_hip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise LibmHipError("libm_hip.so not found at %s; run "
+                           "python -m paper_2001_09258_amd.build" % path)
+    lib = ctypes.CDLL(path)
+    lib.libm_hip_last_error.restype = ctypes.c_char_p
+    lib.libm_hip_version.restype = ctypes.c_char_p
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    for fn, v, dt, name in all_entry_points():
+        f = getattr(lib, name)
+        f.restype = ctypes.c_int
+        if fn in UNARY:
+            f.argtypes = [vp, vp, sz, vp]
+        else:
+            f.argtypes = [vp, vp, vp, sz, vp]
+    lib.libm_hip_eval.restype = ctypes.c_int
+    lib.libm_hip_eval.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp, sz, vp]
+    _lib = lib
+    return lib
+
+
+def _check(status, name):
+    if status != 0:
+        msg = load().libm_hip_last_error().decode()
+        raise LibmHipError("%s failed with status %d: %s" % (name, status, msg))
+
+
+def _make_raw(name):
+    def raw(*args):
+        return getattr(load(), name)(*args)
+    raw.__name__ = name
+    raw.__doc__ = "Direct call of the C-ABI entry point %s (pointers as ints)." % name
+    return raw
+
+
+for _fn, _v, _dt, _name in all_entry_points():
+    globals()[_name] = _make_raw(_name)
+    __all__.append(_name)
+
+
+def call(fn, variant, dtype, a_ptr, b_ptr, out_ptr, n, stream=0):
+    """Call one entry point with raw device pointers; raises on error."""
+    name = entry_name(fn, variant, dtype)
+    f = getattr(load(), name)
+    if fn in UNARY:
+        st = f(a_ptr, out_ptr, n, stream)
+    else:
+        st = f(a_ptr, b_ptr, out_ptr, n, stream)
+    _check(st, name)
+
+
+# ---------------------------------------------------------------------------
+# torch front ends
+# ---------------------------------------------------------------------------
+def _dtype_tag(t, via_f64):
+    import torch
+    tag = {torch.float64: "f64", torch.float32: "f32", torch.bfloat16: "bf16",
+           torch.float16: "f16"}.get(t.dtype)
+    if tag is None:
+        raise TypeError("unsupported dtype %s" % t.dtype)
+    if via_f64:
+        if tag != "f32":
+            raise TypeError("via_f64 applies to float32 tensors only")
+        tag = "f32_via_f64"
+    return tag
+
+
+def _stream_handle():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def evaluate(fn, a, b=None, variant=None, out=None, via_f64=False):
+    """fn over device tensors (C argument order for binary functions)."""
+    import torch
+    load()
+    if variant is None:
+        variant = VARIANTS[fn][0]
+    if not a.is_cuda:
+        raise ValueError("libm_hip evaluates device tensors only")
+    a = a.contiguous()
+    if fn in BINARY:
+        if b is None or b.shape != a.shape or b.dtype != a.dtype or b.device != a.device:
+            raise ValueError("binary functions need two tensors of equal shape, dtype, device")
+        b = b.contiguous()
+    tag = _dtype_tag(a, via_f64)
+    if not served(fn, variant, tag):
+        raise ValueError("%s %s is not served for %s" % (fn, variant, tag))
+    if out is None:
+        out = torch.empty_like(a)
+    elif out.shape != a.shape or out.dtype != a.dtype or not out.is_contiguous():
+        raise ValueError("out must be a contiguous tensor like the input")
+    with torch.cuda.device(a.device):
+        call(fn, variant, tag, a.data_ptr(), 0 if b is None else b.data_ptr(),
+             out.data_ptr(), a.numel(), _stream_handle())
+    return out
+
+
+def _unary(fn):
+    def f(x, variant="u10", out=None, via_f64=False):
+        return evaluate(fn, x, None, variant, out, via_f64)
+    f.__name__ = fn
+    f.__doc__ = "Elementwise %s on a device tensor (variant 'u10' or 'u35')." % fn
+    return f
+
+
+sin, cos, tan = _unary("sin"), _unary("cos"), _unary("tan")
+exp, exp2, log, log2 = _unary("exp"), _unary("exp2"), _unary("log"), _unary("log2")
+sinh, cosh, tanh = _unary("sinh"), _unary("cosh"), _unary("tanh")
+
+
+def pow(x, y, out=None, via_f64=False):
+    """x ** y elementwise (C pow semantics, 1-ULP)."""
+    return evaluate("pow", x, y, "u10", out, via_f64)
+
+
+def atan2(y, x, out=None, via_f64=False):
+    """atan2(y, x) elementwise (C semantics, 1-ULP)."""
+    return evaluate("atan2", y, x, "u10", out, via_f64)
+
+
+def fmod(x, y, out=None):
+    """Exact C fmod(x, y) elementwise."""
+    return evaluate("fmod", x, y, "exact", out)
+
+
+def remainder(x, y, out=None):
+    """Exact IEEE remainder(x, y) elementwise."""
+    return evaluate("remainder", x, y, "exact", out)

@@ -1,0 +1,498 @@
+// Binary32 evaluators.  The paper covers binary64 only; these follow the same
+// reduction / polynomial / reconstruction structure in binary32, with
+// float-float pairs only where the 1-ULP bound needs them (the reduced
+// argument, the lowest polynomial terms, the reconstructions).  No binary64
+// arithmetic is used.
+#pragma once
+#include "dd.h"
+#include "generated/consts.inc"
+#include "generated/poly_coeffs.inc"
+#include "generated/ph_table_f32.inc"
+
+namespace lmh {
+
+typedef dd2<float> fff;
+
+// v * 2^q correctly rounded into binary32, including subnormal results
+LMH_INLINE float ff_ldexp(fff v, int q) {
+  float r = ldexp_(v.hi + v.lo, q);
+  if (q < -122) {
+    v = dd2_norm(v);                                // |lo| <= ulp(hi)/2
+    float h = ldexp_(v.hi, q + 149);
+    float l = ldexp_(v.lo, q + 149);
+    float n = rint_(h);
+    float d = (h - n) + l;
+    n = d > 0.5f ? n + 1.0f : (d < -0.5f ? n - 1.0f : n);
+    float s = ldexp_(n, -149);
+    r = fabs_(h) < 0x1p23f ? s : r;
+  }
+  return r;
+}
+
+LMH_INLINE float mod4f(float v) { return v - 4.0f * rint_(v * 0.25f); }
+LMH_INLINE bool is_odd_intf(float q) { return q - 2.0f * rint_(q * 0.5f) != 0.0f; }
+
+// ---------------------------------------------------------------------------
+// exp family
+// ---------------------------------------------------------------------------
+LMH_INLINE fff expf_core(float rh, float rl) {
+  float p = poly_estrin(rh, EXP_P_F32);
+  float w = fma_(rh * rh, p, fma_(rl, rh, rl));
+  fff s = dd2_add(1.0f, rh);
+  return mk(s.hi, s.lo + w);
+}
+
+LMH_INLINE float expf_u10(float x) {
+  // beyond +-104 the result overflows / rounds to zero; the clamp keeps
+  // k * LN2_HI exact (|k| <= 150)
+  float xc = x > 104.0f ? 104.0f : (x < -104.0f ? -104.0f : x);
+  float k = rint_(xc * LOG2E_F);
+  float s = fma_(k, -LN2_HI_F, xc);
+  float t = k * -LN2_LO_F;
+  float rh = s + t;
+  float rl = (s - rh) + t;
+  float r = ff_ldexp(expf_core(rh, rl), (int)k);
+  return isnan_(x) ? x : r;
+}
+
+LMH_INLINE float exp2f_u10(float x) {
+  float xc = x > 150.0f ? 150.0f : (x < -150.0f ? -150.0f : x);
+  float k = rint_(xc);
+  float f = xc - k;
+  fff t = dd2_mul(f, LN2_F_H);
+  t.lo = fma_(f, LN2_F_L, t.lo);
+  t = dd2_norm(t);
+  float r = ff_ldexp(expf_core(t.hi, t.lo), (int)k);
+  return isnan_(x) ? x : r;
+}
+
+LMH_INLINE fff expf_ff(fff w, float& k) {
+  float wh = w.hi > 104.0f ? 104.0f : (w.hi < -104.0f ? -104.0f : w.hi);
+  k = rint_(wh * LOG2E_F);
+  float s = fma_(k, -LN2_HI_F, wh);
+  fff r = dd2_add2(s, w.lo + k * -LN2_LO_F);
+  return dd2_norm(expf_core(r.hi, r.lo));
+}
+
+// ---------------------------------------------------------------------------
+// log family: a = m 2^e, m in [0.75, 1.5), t = (m-1)/(m+1) as a float pair
+// ---------------------------------------------------------------------------
+LMH_INLINE fff logf_t(float a, float& e) {
+  float m = frexp_mant_(a);
+  int ie = frexp_exp_(a);
+  bool low = m < 0.75f;
+  m = low ? m + m : m;
+  e = (float)(low ? ie - 1 : ie);
+  fff den = dd2_add2(m, 1.0f);
+  return dd2_div(mk(m - 1.0f, 0.0f), den);
+}
+
+LMH_INLINE float logf_u10(float x) {
+  float e;
+  fff t = logf_t(x, e);
+  float z = t.hi * t.hi;
+  float q = poly_estrin(z, LOG_Q_F32);
+  float t3q = (t.hi * z) * q;
+  fff s = dd2_add2(e * LN2_HI_F, t.hi + t.hi);
+  float r = s.hi + (s.lo + (e * LN2_LO_F + ((t.lo + t.lo) + t3q)));
+  r = x == 0.0f ? -__builtin_inff() : r;
+  r = x < 0.0f ? __builtin_nanf("") : r;
+  r = (isinf_(x) && x > 0.0f) || isnan_(x) ? x : r;
+  return r;
+}
+
+LMH_INLINE float log2f_u10(float x) {
+  float e;
+  fff t = logf_t(x, e);
+  float z = t.hi * t.hi;
+  float q = poly_estrin(z, LOG_Q_F32);
+  float t3q = (t.hi * z) * q;
+  fff lm = dd2_add(t.hi + t.hi, (t.lo + t.lo) + t3q);
+  fff l2 = dd2_mul(lm, mk(INVLN2_F_H, INVLN2_F_L));
+  fff s = dd2_add2(e, l2.hi);
+  float r = s.hi + (s.lo + l2.lo);
+  r = x == 0.0f ? -__builtin_inff() : r;
+  r = x < 0.0f ? __builtin_nanf("") : r;
+  r = (isinf_(x) && x > 0.0f) || isnan_(x) ? x : r;
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// trigonometric reductions in binary32
+// ---------------------------------------------------------------------------
+// Cody-Waite with the period split in four floats; exact partial sums for
+// |q| < 2^17 by the same argument as in binary64.
+LMH_INLINE fff cwf_reduce(float x, float q, float c0, float c1, float c2, float c3) {
+  fff s = dd2_add2(mk(x, 0.0f), dd2_mul(q, -c0));
+  s = dd2_norm(s);
+  s = dd2_norm(dd2_add2(s, dd2_mul(q, -c1)));
+  s = dd2_norm(dd2_add2(s, dd2_mul(q, -c2)));
+  return dd2_add2(s, q * -c3);
+}
+
+// Payne-Hanek in binary32: |x| = m 2^(ex-23), m < 2^24 an integer; the
+// table row holds (2^(ex-23) 2/pi) mod 4 in four 23-bit fixed-position limbs.
+LMH_INLINE fff phf_reduce(float ax, float& k) {
+  int ex = frexp_exp_(ax) - 1;
+  ex = ex < 0 ? 0 : (ex > 127 ? 127 : ex);
+  float m = ldexp_(frexp_mant_(ax), 24);
+  const float* W = PH_TABLE_F32 + 4 * ex;
+  float w0 = W[0], w1 = W[1], w2 = W[2], w3 = W[3];
+  fff p = dd2_mul(m, w0);
+  float i0 = rint_(p.hi), j0 = rint_(p.lo);
+  float x0 = (p.hi - i0) + (p.lo - j0);
+  float k0 = rint_(x0);
+  x0 -= k0;
+  float q = mod4f(i0) + mod4f(j0) + k0;
+  fff s = mk(x0, 0.0f);
+  s = dd2_add2(s, dd2_mul(m, w1));
+  float k1 = rint_(s.hi);
+  s = dd2_norm(mk(s.hi - k1, s.lo));
+  s = dd2_add2(s, dd2_mul(m, w2));
+  float k2 = rint_(s.hi);
+  s = dd2_norm(mk(s.hi - k2, s.lo));
+  s = dd2_add2(s, dd2_mul(m, w3));
+  float k3 = rint_(s.hi);
+  s = dd2_norm(mk(s.hi - k3, s.lo));
+  k = mod4f(q + k1 + k2 + k3);
+  return dd2_mul(s, mk(PIH2_F_H, PIH2_F_L));
+}
+
+LMH_INLINE fff phf_reduce_signed(float x, float& k) {
+  fff r = phf_reduce(fabs_(x), k);
+  if (x < 0.0f) {
+    r = dd2_neg(r);
+    k = -k;
+  }
+  return r;
+}
+
+LMH_INLINE fff quadrant_to_half_periodf(fff r, float k, float& j) {
+  if (is_odd_intf(k)) {
+    float sg = r.hi >= 0.0f ? 1.0f : -1.0f;
+    r = dd2_add2(r, mk(-sg * PIH2_F_H, -sg * PIH2_F_L));
+    k += sg;
+  }
+  j = k * 0.5f;
+  return r;
+}
+
+constexpr float CWF_LIMIT = 65536.0f;
+
+LMH_INLINE fff sincosf_reduce(float x, bool is_cos, float& j) {
+  fff r;
+  if (fabs_(x) < CWF_LIMIT) {
+    float q;
+    if (is_cos) {
+      q = 2.0f * rint_(fma_(x, INV_PI_F, -0.5f)) + 1.0f;
+      r = cwf_reduce(x, q, PIH_F_0, PIH_F_1, PIH_F_2, PIH_F_3);
+      j = (q - 1.0f) * 0.5f + 1.0f;
+    } else {
+      q = rint_(x * INV_PI_F);
+      r = cwf_reduce(x, q, PI_F_0, PI_F_1, PI_F_2, PI_F_3);
+      j = q;
+    }
+  } else {
+    float k;
+    r = phf_reduce_signed(x, k);
+    if (is_cos) k += 1.0f;
+    r = quadrant_to_half_periodf(r, k, j);
+    r.hi = isfinite_(x) ? r.hi : __builtin_nanf("");
+  }
+  return r;
+}
+
+LMH_INLINE float sinf_poly_u10(fff r) {
+  float z = r.hi * r.hi;
+  float s3 = poly_estrin(z, SIN_S3_F32);
+  fff r2 = dd2_squ(r);
+  fff r3 = dd2_mul(r2, r);
+  fff r5 = dd2_mul(r3, r2);
+  fff c3 = dd2_mul(r3, mk(-SIXTH_F_H, -SIXTH_F_L));
+  fff c5 = dd2_mul(r5, mk(INV120_F_H, INV120_F_L));
+  float p7 = (r5.hi * z) * s3;
+  fff s = dd2_add(r, c3);
+  s = dd2_add(s, c5);
+  return s.hi + (s.lo + p7);
+}
+
+LMH_INLINE float sinf_poly_u35(float r) {
+  float z = r * r;
+  return fma_(r * z, poly_estrin(z, SIN_S_F32), r);
+}
+
+LMH_INLINE float sinf_u10(float x) {
+  float j;
+  fff r = sincosf_reduce(x, false, j);
+  float s = sinf_poly_u10(r);
+  s = is_odd_intf(j) ? -s : s;
+  return x == 0.0f ? x : s;
+}
+
+LMH_INLINE float cosf_u10(float x) {
+  float j;
+  fff r = sincosf_reduce(x, true, j);
+  float s = sinf_poly_u10(r);
+  return is_odd_intf(j) ? -s : s;
+}
+
+LMH_INLINE float sinf_u35(float x) {
+  float j;
+  fff r = sincosf_reduce(x, false, j);
+  float s = sinf_poly_u35(r.hi + r.lo);
+  s = is_odd_intf(j) ? -s : s;
+  return x == 0.0f ? x : s;
+}
+
+LMH_INLINE float cosf_u35(float x) {
+  float j;
+  fff r = sincosf_reduce(x, true, j);
+  float s = sinf_poly_u35(r.hi + r.lo);
+  return is_odd_intf(j) ? -s : s;
+}
+
+LMH_INLINE fff tanf_reduce(float x, float& k) {
+  fff r;
+  if (fabs_(x) < CWF_LIMIT) {
+    k = rint_(x * TWO_OVER_PI_F);
+    r = cwf_reduce(x, k, PIH_F_0, PIH_F_1, PIH_F_2, PIH_F_3);
+  } else {
+    r = phf_reduce_signed(x, k);
+    r.hi = isfinite_(x) ? r.hi : __builtin_nanf("");
+  }
+  return r;
+}
+
+LMH_INLINE float tanf_u10(float x) {
+  float k;
+  fff r = tanf_reduce(x, k);
+  fff y = dd2_scale(r, 0.5f);
+  float z = y.hi * y.hi;
+  float tp = poly_estrin(z, TAN_T_F32);
+  fff y3 = dd2_mul(dd2_squ(y), y);
+  fff t = dd2_add(y, dd2_mul(y3, tp));
+  fff num = dd2_scale(t, 2.0f);
+  fff den = dd2_add(1.0f, dd2_neg(dd2_squ(t)));
+  if (is_odd_intf(k)) {
+    fff tmp = num;
+    num = den;
+    den = dd2_neg(tmp);
+  }
+  fff q = dd2_div(num, den);
+  float res = q.hi + q.lo;
+  return fabs_(x) < 0x1p-12f ? x : res;
+}
+
+LMH_INLINE float tanf_u35(float x) {
+  float k;
+  fff r = tanf_reduce(x, k);
+  float y = (r.hi + r.lo) * 0.5f;
+  float z = y * y;
+  float t = fma_(y * z, poly_estrin(z, TAN_T_F32), y);
+  float num = t + t;
+  float den = fma_(-t, t, 1.0f);
+  bool odd = is_odd_intf(k);
+  float n2 = odd ? den : num;
+  float d2 = odd ? -num : den;
+  float res = n2 / d2;
+  return fabs_(x) < 0x1p-12f ? x : res;
+}
+
+// ---------------------------------------------------------------------------
+// pow, atan2
+// ---------------------------------------------------------------------------
+LMH_INLINE fff logf_ff(float a) {
+  float e;
+  fff t = logf_t(a, e);
+  fff t2 = dd2_squ(t);
+  float z = t2.hi;
+  float rr = poly_estrin(z, LOG_R_F32);
+  fff t3 = dd2_mul(t2, t);
+  fff c3 = dd2_mul(t3, mk(TWOTHIRD_F_H, TWOTHIRD_F_L));
+  float p5 = (t3.hi * z) * rr;
+  fff l = dd2_add(dd2_scale(t, 2.0f), c3);
+  l = dd2_add(l, p5);
+  // e * LN2_HI_F is exact (16-bit head, |e| <= 150)
+  fff el = mk(e * LN2_HI_F, e * LN2_LO_F);
+  return dd2_add2(el, l);
+}
+
+LMH_INLINE float powf_u10(float x, float y) {
+  float ax = fabs_(x);
+  fff lg = logf_ff(ax);
+  fff w = dd2_mul(lg, y);
+  float k;
+  fff e = expf_ff(w, k);
+  float r = ff_ldexp(e, (int)k);
+  r = w.hi > 89.0f ? __builtin_inff() : r;
+  r = w.hi < -104.0f ? 0.0f : r;
+  bool yint = rint_(y) == y;
+  bool yodd = yint && fabs_(y) < 0x1p24f && is_odd_intf(y);
+  r = (x < 0.0f && yodd) ? -r : r;
+  r = (x < 0.0f && !yint && isfinite_(x) && isfinite_(y)) ? __builtin_nanf("") : r;
+  if (isinf_(x)) {
+    bool neg = x < 0.0f;
+    float mag = y < 0.0f ? 0.0f : __builtin_inff();
+    r = (neg && yodd) ? -mag : mag;
+  }
+  if (isinf_(y)) {
+    float mag = (ax < 1.0f) == (y < 0.0f) ? __builtin_inff() : 0.0f;
+    r = ax == 1.0f ? 1.0f : mag;
+  }
+  if (x == 0.0f) {
+    float mag = y < 0.0f ? __builtin_inff() : 0.0f;
+    r = yodd ? copysign_(mag, x) : mag;
+  }
+  r = (isnan_(x) || isnan_(y)) ? __builtin_nanf("") : r;
+  r = (y == 0.0f || x == 1.0f) ? 1.0f : r;
+  return r;
+}
+
+LMH_INLINE float atan2f_u10(float y, float x) {
+  float ay = fabs_(y), ax = fabs_(x);
+  bool both_inf = isinf_(ax) && isinf_(ay);
+  ay = both_inf ? 1.0f : ay;
+  ax = both_inf ? 1.0f : ax;
+  bool swap = ay > ax;
+  float n = swap ? ax : ay;
+  float d = swap ? ay : ax;
+  int de = frexp_exp_(d);
+  float dn = ldexp_(d, -de);
+  float nn = ldexp_(n, -de);
+  fff t = dd2_div(mk(nn, 0.0f), mk(dn, 0.0f));
+  t = isinf_(d) ? mk(0.0f, 0.0f) : t;
+  float z = t.hi * t.hi;
+  float a2 = poly_estrin(z, ATAN_A2_F32);
+  fff t3 = dd2_mul(dd2_squ(t), t);
+  fff c3 = dd2_mul(t3, mk(-THIRD_F_H, -THIRD_F_L));
+  float p5 = (t3.hi * z) * a2;
+  fff a = dd2_add(dd2_add(t, c3), p5);
+  if (t.hi < 0x1p-100f) a = mk(n / d, 0.0f);
+  if (swap) a = dd2_add(mk(PIH2_F_H, PIH2_F_L), dd2_neg(a));
+  bool xneg = __builtin_signbit(x);
+  if (xneg) a = dd2_add(mk(PI2_F_H, PI2_F_L), dd2_neg(a));
+  float r = copysign_(a.hi + a.lo, y);
+  if (y == 0.0f) r = xneg ? copysign_(PI2_F_H, y) : copysign_(0.0f, y);
+  r = (isnan_(x) || isnan_(y)) ? __builtin_nanf("") : r;
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// hyperbolic functions
+// ---------------------------------------------------------------------------
+LMH_INLINE fff expf_half(float ax, float& k) {   // e^ax / 2
+  fff w = dd2_add2(ax, -LN2_F_H);
+  w.lo += -LN2_F_L;
+  return expf_ff(dd2_norm(w), k);
+}
+
+LMH_INLINE float sinhf_u10(float x) {
+  float ax = fabs_(x);
+  float r;
+  if (ax < 1.0f) {
+    float z = x * x;
+    r = fma_(x * z, poly_estrin(z, SINH_H_F32), x);
+  } else {
+    float k;
+    fff e = expf_half(ax > 90.0f ? 90.0f : ax, k);
+    fff h = mk(ldexp_(e.hi, (int)k), ldexp_(e.lo, (int)k));
+    fff rc = dd2_rec(e);
+    fff g = mk(ldexp_(rc.hi, -(int)k - 2), ldexp_(rc.lo, -(int)k - 2));
+    fff s = dd2_add(h, dd2_neg(g));
+    r = s.hi + s.lo;
+    r = isinf_(h.hi) ? __builtin_inff() : r;
+    r = copysign_(r, x);
+  }
+  return isnan_(x) ? x : r;
+}
+
+LMH_INLINE float coshf_u10(float x) {
+  float ax = fabs_(x);
+  float k;
+  fff e = expf_half(ax > 90.0f ? 90.0f : ax, k);
+  fff h = mk(ldexp_(e.hi, (int)k), ldexp_(e.lo, (int)k));
+  fff rc = dd2_rec(e);
+  fff g = mk(ldexp_(rc.hi, -(int)k - 2), ldexp_(rc.lo, -(int)k - 2));
+  fff s = dd2_add(h, g);
+  float r = s.hi + s.lo;
+  r = isinf_(h.hi) ? __builtin_inff() : r;
+  return isnan_(x) ? x : r;
+}
+
+LMH_INLINE float tanhf_u10(float x) {
+  float ax = fabs_(x);
+  float r;
+  if (ax < 0.625f) {
+    float z = x * x;
+    r = fma_(x * z, poly_estrin(z, TANH_G_F32), x);
+  } else {
+    float a2 = ax > 20.0f ? 40.0f : ax + ax;
+    float k;
+    fff e = expf_ff(mk(a2, 0.0f), k);
+    fff E = mk(ldexp_(e.hi, (int)k), ldexp_(e.lo, (int)k));
+    fff den = dd2_add(E, 1.0f);
+    fff q = dd2_div(mk(2.0f, 0.0f), den);
+    fff s = dd2_add(1.0f, dd2_neg(q));
+    r = copysign_(s.hi + s.lo, x);
+  }
+  r = fabs_(x) < 0x1p-12f ? x : r;
+  return isnan_(x) ? x : r;
+}
+
+// ---------------------------------------------------------------------------
+// exact remainders in binary32 (same long division as binary64)
+// ---------------------------------------------------------------------------
+LMH_INLINE float fmodf_core(float n, float d) {
+  float dm = frexp_mant_(d);
+  int de = frexp_exp_(d);
+  float rdm = pred_(1.0f / dm);
+  fff r = mk(n, 0.0f);
+  bool active = r.hi > d || (r.hi == d && r.lo >= 0.0f);
+  for (int it = 0; it < 64 && any_lane(active); ++it) {
+    if (active) {
+      float rm = frexp_mant_(r.hi);
+      int re = frexp_exp_(r.hi);
+      int E = re - de;
+      float qf = pred_(rm) * rdm;
+      float qs = E < 25 ? ldexp_(trunc_(ldexp_(qf, E)), -E) : qf;
+      qs = (r.hi < 3.0f * d && r.hi > d) ? ldexp_(2.0f, -E) : qs;
+      qs = (r.hi < 2.0f * d && r.hi > d) ? ldexp_(1.0f, -E) : qs;
+      qs = r.hi == d ? (r.lo >= 0.0f ? ldexp_(1.0f, -E) : 0.0f) : qs;
+      fff p = dd2_mul(qs, dm);
+      p = mk(ldexp_(p.hi, re), ldexp_(p.lo, re));
+      r = dd2_norm(dd2_add2(r, dd2_neg(p)));
+      active = r.hi > d || (r.hi == d && r.lo >= 0.0f);
+    }
+  }
+  return r.hi;
+}
+
+LMH_INLINE float fmodf_f32(float x, float y) {
+  float n = fabs_(x), d = fabs_(y);
+  bool special = !isfinite_(x) || !isfinite_(d) || d == 0.0f || n < d;
+  float r = fmodf_core(special ? 0.0f : n, special ? 1.0f : d);
+  r = copysign_(r, x);
+  r = n < d ? x : r;
+  r = isinf_(d) && isfinite_(x) ? x : r;
+  r = (d == 0.0f || !isfinite_(x) || isnan_(y)) ? __builtin_nanf("") : r;
+  return r;
+}
+
+LMH_INLINE float remainderf_f32(float x, float y) {
+  float n = fabs_(x), d = fabs_(y);
+  float d2 = d + d;
+  bool special = !isfinite_(x) || !isfinite_(d) || d == 0.0f;
+  bool small = n < d2;
+  float r2 = fmodf_core(special || small ? 0.0f : n, special || small ? 1.0f : d2);
+  r2 = small ? n : r2;
+  bool odd = r2 >= d;
+  float r1 = odd ? r2 - d : r2;
+  float tw = r1 + r1;
+  r1 = (tw > d || (tw == d && odd)) ? r1 - d : r1;
+  float r = r1 * copysign_(1.0f, x);
+  r = isinf_(d) && isfinite_(x) ? x : r;
+  r = (d == 0.0f || !isfinite_(x) || isnan_(y)) ? __builtin_nanf("") : r;
+  return r;
+}
+
+}  // namespace lmh

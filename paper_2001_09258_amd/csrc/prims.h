@@ -1,0 +1,58 @@
+// Scalar primitives of the gfx950 vector ALU used by every evaluator.
+//
+// Each maps to one CDNA instruction (or a short fixed sequence): v_fma_f64,
+// v_rndne_f64 (round to nearest even), v_trunc_f64, v_ldexp_f64,
+// v_frexp_mant_f64 / v_frexp_exp_i32_f64 (exact for subnormals too),
+// v_rcp_f64, and the float counterparts.  The paper builds its functions from
+// the same small set -- FMA, round-to-integer, mantissa/exponent extraction
+// and conditional moves (Section 3.1, sub-features) -- so the evaluators stay
+// branch-free except where a wave may skip a whole path no lane needs.
+#pragma once
+#include <stdint.h>
+
+#define LMH_INLINE __device__ __forceinline__
+
+namespace lmh {
+
+LMH_INLINE double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+LMH_INLINE float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+LMH_INLINE double rint_(double x) { return __builtin_rint(x); }
+LMH_INLINE float rint_(float x) { return __builtin_rintf(x); }
+LMH_INLINE double trunc_(double x) { return __builtin_trunc(x); }
+LMH_INLINE float trunc_(float x) { return __builtin_truncf(x); }
+LMH_INLINE double fabs_(double x) { return __builtin_fabs(x); }
+LMH_INLINE float fabs_(float x) { return __builtin_fabsf(x); }
+LMH_INLINE double copysign_(double a, double b) { return __builtin_copysign(a, b); }
+LMH_INLINE float copysign_(float a, float b) { return __builtin_copysignf(a, b); }
+LMH_INLINE double ldexp_(double x, int e) { return __builtin_amdgcn_ldexp(x, e); }
+LMH_INLINE float ldexp_(float x, int e) { return __builtin_amdgcn_ldexpf(x, e); }
+// mantissa in [0.5, 1) with the sign of x, exponent such that x = m * 2^e;
+// for +-0, inf and NaN the mantissa is x itself and the exponent 0
+LMH_INLINE double frexp_mant_(double x) { return __builtin_amdgcn_frexp_mant(x); }
+LMH_INLINE float frexp_mant_(float x) { return __builtin_amdgcn_frexp_mantf(x); }
+LMH_INLINE int frexp_exp_(double x) { return __builtin_amdgcn_frexp_exp(x); }
+LMH_INLINE int frexp_exp_(float x) { return __builtin_amdgcn_frexp_expf(x); }
+// hardware reciprocal estimate (refined by the callers with Newton steps)
+LMH_INLINE double rcp_(double x) { return __builtin_amdgcn_rcp(x); }
+LMH_INLINE float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+LMH_INLINE bool isnan_(double x) { return __builtin_isnan(x); }
+LMH_INLINE bool isnan_(float x) { return __builtin_isnan(x); }
+LMH_INLINE bool isinf_(double x) { return __builtin_isinf(x); }
+LMH_INLINE bool isinf_(float x) { return __builtin_isinf(x); }
+LMH_INLINE bool isfinite_(double x) { return __builtin_isfinite(x); }
+LMH_INLINE bool isfinite_(float x) { return __builtin_isfinite(x); }
+
+LMH_INLINE int64_t as_i64(double x) { return __builtin_bit_cast(int64_t, x); }
+LMH_INLINE double as_f64(int64_t x) { return __builtin_bit_cast(double, x); }
+LMH_INLINE int32_t as_i32(float x) { return __builtin_bit_cast(int32_t, x); }
+LMH_INLINE float as_f32(int32_t x) { return __builtin_bit_cast(float, x); }
+
+// true if the predicate holds on any active lane of the wavefront (used only
+// to end a loop once every lane is done; the loop body stays exec-masked)
+LMH_INLINE bool any_lane(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
+
+// the neighbour of a positive finite x towards zero (x > 0, not subnormal 0)
+LMH_INLINE double pred_(double x) { return as_f64(as_i64(x) - 1); }
+LMH_INLINE float pred_(float x) { return as_f32(as_i32(x) - 1); }
+
+}  // namespace lmh

@@ -1,0 +1,181 @@
+"""GPU parity: every C-ABI entry point against the oracle, element by element.
+
+Sizes span many 256-lane tiles plus a ragged tail; inputs are the seeded
+workload mixtures (config 2 / 4 mixtures, config 3 large arguments, config 1
+at its full 2^20 size) plus the Annex F special set.  Bounds: 1.0 ULP (u10),
+3.5 ULP (u35), bit-exact for fmod/remainder and for every NaN, +-inf, +-0 and
+subnormal result (the paper's accuracy contract, Section 5, overview, and its
+testers, Section 6).
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_common import check, run_gpu, run_oracle, to_device, BOUND
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2001_09258_amd as L  # noqa: E402
+
+N_PAR = 3 * 4096 + 37            # 24+ tiles of 512 f64 elements, ragged tail
+CASES = [(fn, v, dt) for fn, v, dt, _ in L.all_entry_points()]
+BINARY = ("pow", "atan2", "fmod", "remainder")
+
+
+def _inputs(cfg, fn, dt, n, operand):
+    base = "f32" if dt == "f32_via_f64" else dt
+    if cfg == 2:
+        if base in ("bf16", "f16"):
+            return W.config4(fn, base, n, operand)
+        return W.config2(fn, base, n, operand)
+    return W.config3(fn, base, n, operand)
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L.load()
+    yield
+
+
+@pytest.mark.parametrize("fn,variant,dt", CASES, ids=["-".join(c) for c in CASES])
+def test_parity_mixture(fn, variant, dt):
+    a = _inputs(2, fn, dt, N_PAR, 0)
+    b = _inputs(2, fn, dt, N_PAR, 1) if fn in BINARY else None
+    print("parity mixture", fn, variant, dt, flush=True)
+    check(fn, variant, dt, a, b, label="mixture")
+
+
+TRIG_CASES = [c for c in CASES if c[0] in ("sin", "cos", "tan", "fmod", "remainder")
+              and c[2] in ("f64", "f32")]
+
+
+@pytest.mark.parametrize("fn,variant,dt", TRIG_CASES, ids=["-".join(c) for c in TRIG_CASES])
+def test_parity_large_arguments(fn, variant, dt):
+    a = _inputs(3, fn, dt, N_PAR, 0)
+    b = _inputs(3, fn, dt, N_PAR, 1) if fn in BINARY else None
+    print("parity config3", fn, variant, dt, flush=True)
+    check(fn, variant, dt, a, b, label="config3")
+
+
+@pytest.mark.parametrize("fn", ["sin", "cos", "exp", "log"])
+def test_config1_full(fn):
+    """Config 1 at its full size: FP64 u10 on 2^20 elements."""
+    a = W.config1(fn)
+    print("config1", fn, flush=True)
+    res = check(fn, "u10", "f64", a, None, label="config1")
+    assert res["max_ulp"] <= 1.0
+
+
+SPECIAL_F64 = [0.0, -0.0, math.inf, -math.inf, math.nan, 5e-324, -5e-324,
+               2.2250738585072009e-308, -2.2250738585072009e-308, 2.2250738585072014e-308,
+               1.0, -1.0, 0.5, -0.5, 2.0, -2.0, 3.0, -3.0, 1.7976931348623157e308,
+               -1.7976931348623157e308, 709.782712893384, 709.7827128933841, -745.1332191019411,
+               -745.1332191019412, 710.4758600739439, 1e-300, 1e22, 1e300, 0.75, 1.5]
+
+
+def _special_inputs(dt, binary):
+    vals = np.array(SPECIAL_F64)
+    if dt in ("f32", "f32_via_f64"):
+        vals = np.concatenate([vals.astype(np.float32).astype(np.float64),
+                               [1.401298464324817e-45, -1.401298464324817e-45,
+                                1.1754942106924411e-38, 88.72283935546875, 88.72284, -103.97208,
+                                89.41598, 3.4028234663852886e+38]])
+    elif dt == "bf16":
+        vals = W.round_to_bf16(vals.astype(np.float32)).astype(np.float64)
+    elif dt == "f16":
+        vals = np.concatenate([vals.astype(np.float16).astype(np.float64),
+                               [2.0 ** -24, -(2.0 ** -24), 6.097555160522461e-05, 11.0859375,
+                                65504.0]])
+    vals = np.unique(vals[~np.isnan(vals)])
+    vals = np.concatenate([vals, [np.nan]])
+    if binary:
+        pairs = np.array(list(itertools.product(vals, vals)))
+        return pairs[:, 0], pairs[:, 1]
+    return vals, None
+
+
+@pytest.mark.parametrize("fn,variant,dt", CASES, ids=["-".join(c) for c in CASES])
+def test_special_values(fn, variant, dt):
+    a, b = _special_inputs(dt, fn in BINARY)
+    print("specials", fn, variant, dt, flush=True)
+    check(fn, variant, dt, a, b, label="specials")
+
+
+# ---------------------------------------------------------------------------
+# boundary behaviour of the C-ABI
+# ---------------------------------------------------------------------------
+def test_abi_zero_length_and_null():
+    assert L.libm_hip_sin_u10_f64(0, 0, 0, 0) == 0          # n == 0: OK, no launch
+    assert L.libm_hip_sin_u10_f64(0, 0, 5, 0) == 1          # NULL with n > 0
+    assert L.libm_hip_pow_u10_f32(0, 0, 0, 7, 0) == 1
+    assert b"NULL" in L.load().libm_hip_last_error()
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16", "f16"])
+def test_misaligned_in_place_and_streams(dt):
+    """Unaligned views (scalar path), in-place calls, non-default stream."""
+    n = 5000
+    base = "f32" if dt == "f32_via_f64" else dt
+    a = W.config4("exp", base, n + 3, 9) if base in ("bf16", "f16") else \
+        W.config2("exp", base, n + 3, 9)
+    ta = to_device(a, dt)
+    view = ta[1:n + 1]                                       # 1-element offset
+    assert view.data_ptr() % 16 != 0
+    out = L.exp(view)
+    want = L.exp(view.clone())
+    torch.cuda.synchronize()
+    assert torch.equal(out.view(torch.int8), want.view(torch.int8)) or \
+        torch.equal(torch.nan_to_num(out.float(), nan=7.0), torch.nan_to_num(want.float(), nan=7.0))
+    inplace = view.clone()
+    L.exp(inplace, out=inplace)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        other = L.exp(view)
+    s.synchronize()
+    torch.cuda.synchronize()
+    for t in (inplace, other):
+        assert torch.equal(torch.nan_to_num(t.float(), nan=7.0),
+                           torch.nan_to_num(want.float(), nan=7.0))
+
+
+def test_generic_dispatcher_matches_named_entry():
+    a = W.config2("sin", "f64", 4096, 3)
+    ta = to_device(a, "f64")
+    out1 = L.sin(ta)
+    out2 = torch.empty_like(ta)
+    st = L.load().libm_hip_eval(0, 0, 0, ta.data_ptr(), None, out2.data_ptr(), ta.numel(), 0)
+    assert st == 0
+    torch.cuda.synchronize()
+    assert torch.equal(torch.nan_to_num(out1, nan=7.0), torch.nan_to_num(out2, nan=7.0))
+    st = L.load().libm_hip_eval(0, 1, 2, ta.data_ptr(), None, out2.data_ptr(), 4, 0)
+    assert st == 2                                           # u35 not served in bf16
+
+
+# ---------------------------------------------------------------------------
+# full benchmark size, sampled
+# ---------------------------------------------------------------------------
+FULL = [("exp", "u10", "f64"), ("sin", "u10", "f64"), ("pow", "u10", "f64"),
+        ("tan", "u10", "f32"), ("log", "u10", "f32"), ("atan2", "u10", "f32")]
+
+
+@pytest.mark.parametrize("fn,variant,dt", FULL, ids=["-".join(c) for c in FULL])
+def test_full_size_sampled(fn, variant, dt):
+    """2^26 elements in the launch configuration the benchmark times; 4096
+    sampled outputs checked against the oracle one by one."""
+    n = 1 << 26
+    a = W.config2(fn, dt, n, 0)
+    b = W.config2(fn, dt, n, 1) if fn in BINARY else None
+    print("full size", fn, variant, dt, flush=True)
+    y = run_gpu(fn, variant, dt, a, b)
+    idx = np.random.default_rng(5).integers(0, n, 4096)
+    idx = np.concatenate([idx, [0, n - 1]])
+    from tests.ulp import compare
+    rn, hi, lo = run_oracle(fn, dt, a[idx], None if b is None else b[idx])
+    res = compare(y[idx], rn, hi, lo, dt, BOUND[variant])
+    assert res["violations"] == 0 and res["special_mismatch"] == 0, res

@@ -1,0 +1,219 @@
+"""Seeded synthetic input generators shared by the tests, the smoke check and
+the benchmark.
+
+This module holds no arithmetic of the math functions themselves: it only
+draws arguments.  Every array comes from
+``np.random.default_rng(SeedSequence([2001, 9258, config, fn_id, operand]))``
+and is generated on the host in the target format.
+
+The paper measures on uniformly distributed arguments in fixed intervals
+(Section 7, Table of reciprocal throughputs; the "paper domains" below) and
+tests with regular grids, arguments near multiples of pi/2 and random bit
+patterns (Section 6).  The five workload mixtures stand in for those; none of
+them is a public dataset.
+
+bf16 arrays are returned as float32 arrays holding bf16-representable values
+(numpy has no bfloat16); ``to_bf16_bits`` gives the 16-bit patterns.
+"""
+import numpy as np
+
+__all__ = ["FN_IDS", "rng_for", "specials", "config1", "config2", "config3",
+           "config4", "config5_requests", "autograd_inputs", "paper_domain",
+           "PAPER_DOMAINS", "round_to_bf16", "to_bf16_bits",
+           "from_bf16_bits", "np_dtype"]
+
+FN_IDS = {name: i for i, name in enumerate(
+    ["sin", "cos", "tan", "exp", "exp2", "log", "log2", "pow", "atan2",
+     "sinh", "cosh", "tanh", "fmod", "remainder"])}
+
+DTYPE_MAX = {"f64": np.finfo(np.float64).max, "f32": float(np.finfo(np.float32).max),
+             "f16": 65504.0, "bf16": 3.3895313892515355e38}
+DTYPE_MIN_SUB = {"f64": 5e-324, "f32": float(np.float32(1.401298464324817e-45)),
+                 "f16": 2.0 ** -24, "bf16": 9.183549615799121e-41}
+
+
+def np_dtype(dt):
+    return {"f64": np.float64, "f32": np.float32, "f16": np.float16,
+            "bf16": np.float32}[dt]
+
+
+def rng_for(config, fn, operand=0):
+    fid = FN_IDS[fn] if isinstance(fn, str) else int(fn)
+    return np.random.default_rng(np.random.SeedSequence([2001, 9258, config, fid, operand]))
+
+
+def round_to_bf16(a):
+    """Round float32 values to the nearest bfloat16 (ties to even); NaN stays
+    NaN.  Returned as float32."""
+    a = np.asarray(a, dtype=np.float32)
+    bits = a.view(np.uint32).astype(np.uint64)
+    nan = np.isnan(a)
+    lsb = (bits >> 16) & 1
+    bits = (bits + 0x7FFF + lsb) & 0xFFFF0000
+    out = bits.astype(np.uint32).view(np.float32).copy()
+    out[nan] = np.float32("nan")
+    return out
+
+
+def to_bf16_bits(a):
+    return (round_to_bf16(a).view(np.uint32) >> 16).astype(np.uint16)
+
+
+def from_bf16_bits(b):
+    return (np.asarray(b, dtype=np.uint32) << 16).view(np.float32)
+
+
+def _cast(x64, dt):
+    if dt == "f64":
+        return x64.astype(np.float64)
+    if dt == "f32":
+        return x64.astype(np.float32)
+    if dt == "f16":
+        return x64.astype(np.float16)
+    if dt == "bf16":
+        return round_to_bf16(x64.astype(np.float32))
+    raise ValueError(dt)
+
+
+def specials(dt):
+    """The special set S of a format: +-0, +-inf, NaN, +-min and +-max
+    subnormal."""
+    if dt == "f64":
+        mins, maxs = 5e-324, float.fromhex("0x0.fffffffffffffp-1022")
+    elif dt in ("f32", "bf16"):
+        mins = float(np.float32(float.fromhex("0x1p-149")))
+        maxs = float(np.float32(float.fromhex("0x1.fffffcp-127")))
+        if dt == "bf16":
+            mins = float.fromhex("0x1p-133")
+            maxs = float.fromhex("0x1.fcp-127")
+    else:
+        mins, maxs = 2.0 ** -24, float.fromhex("0x1.ff8p-15")
+    return np.array([0.0, -0.0, np.inf, -np.inf, np.nan, mins, -mins, maxs, -maxs])
+
+
+def config1(fn, n=1 << 20):
+    """FP64 sin/cos/exp: U[-10, 10]; log: 1000 * (1 - U[0, 1)) in (0, 1000]."""
+    rng = rng_for(1, fn)
+    if fn == "log":
+        return 1000.0 * (1.0 - rng.random(n))
+    return rng.uniform(-10.0, 10.0, n)
+
+
+def _mixture(rng, n, dt, lo_exp, hi_exp):
+    """49% U[-1e4, 1e4], 50% sign * 10^U[lo_exp, hi_exp], 1% uniform over S,
+    drawn per element (so waves are mixed)."""
+    cat = rng.random(n)
+    x = rng.uniform(-1e4, 1e4, n)
+    lg_mask = (cat >= 0.49) & (cat < 0.99)
+    m = int(lg_mask.sum())
+    mag = np.exp(rng.uniform(lo_exp, hi_exp, m) * np.log(10.0))
+    sign = np.where(rng.random(m) < 0.5, -1.0, 1.0)
+    x[lg_mask] = sign * mag
+    sp_mask = cat >= 0.99
+    x[sp_mask] = specials(dt)[rng.integers(0, 9, int(sp_mask.sum()))]
+    return x
+
+
+def config2(fn, dt, n=1 << 26, operand=0):
+    rng = rng_for(2, fn, operand)
+    if dt == "f64":
+        x = _mixture(rng, n, dt, -300.0, 300.0)
+    else:
+        x = _mixture(rng, n, dt, -38.0, 38.0)
+    with np.errstate(over="ignore"):
+        return _cast(x, dt)
+
+
+def config3(fn, dt, n=1 << 26, operand=0):
+    """Large-argument stress.  Trig: half sign * 10^U[5, log10(max)], half
+    x = k (pi/2)(1 + delta) with k = floor(10^U[0, 22 - log10(pi/2)]),
+    delta ~ U[-1e-3, 1e-3] and delta = 0 for a quarter of those (binary64
+    product, so x lies within a few ulps of k pi/2).  fmod/remainder: |x|, |y|
+    log-uniform over [min subnormal, max finite], random signs."""
+    rng = rng_for(3, fn, operand)
+    mx = DTYPE_MAX[dt]
+    sign = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    if fn in ("fmod", "remainder"):
+        lo = np.log10(DTYPE_MIN_SUB[dt])
+        hi = np.log10(mx)
+        x = sign * 10.0 ** rng.uniform(lo, hi, n)
+    else:
+        half = rng.random(n) < 0.5
+        big = 10.0 ** rng.uniform(5.0, np.log10(mx), n)
+        k = np.floor(10.0 ** rng.uniform(0.0, 22.0 - np.log10(np.pi / 2), n))
+        delta = rng.uniform(-1e-3, 1e-3, n)
+        delta[rng.random(n) < 0.25] = 0.0
+        near = k * (np.pi / 2) * (1.0 + delta)
+        if dt != "f64":
+            near = np.minimum(near, mx)
+        x = sign * np.where(half, big, near)
+    with np.errstate(over="ignore"):
+        return _cast(np.minimum(np.abs(x), mx) * np.sign(x), dt)
+
+
+def config4(fn, dt, n=1 << 28, operand=0):
+    """Config-2 mixture for bf16/f16 with the log-uniform bounds clamped to
+    [min subnormal, max finite] of the format; RNE conversion.  For 'f32' it
+    is exactly config 2's binary32 input."""
+    if dt == "f32":
+        return config2(fn, "f32", n, operand)
+    rng = rng_for(4, fn, operand)
+    lo = np.log10(DTYPE_MIN_SUB[dt])
+    hi = np.log10(DTYPE_MAX[dt])
+    lo = max(lo, -38.0)
+    hi = min(hi, 38.0)
+    x = _mixture(rng, n, dt, lo, hi)
+    with np.errstate(over="ignore"):
+        return _cast(x, dt)
+
+
+# every (fn, variant) the library serves, used to draw batched requests
+REQUEST_KINDS = [("sin", "u10"), ("sin", "u35"), ("cos", "u10"), ("cos", "u35"),
+                 ("tan", "u10"), ("tan", "u35"), ("exp", "u10"), ("exp2", "u10"),
+                 ("log", "u10"), ("log2", "u10"), ("pow", "u10"), ("atan2", "u10"),
+                 ("sinh", "u10"), ("cosh", "u10"), ("tanh", "u10")]
+
+
+def config5_requests(k=64, lo=3.0, hi=7.0):
+    """64 requests: (fn, variant) uniform over the served list, dtype uniform
+    over {f64, f32, bf16, f16} (u35 variants only in f64/f32), length
+    round(10^U[3, 7])."""
+    rng = rng_for(5, 0, 99)
+    reqs = []
+    for i in range(k):
+        fn, var = REQUEST_KINDS[rng.integers(0, len(REQUEST_KINDS))]
+        dts = ["f64", "f32"] if var == "u35" else ["f64", "f32", "bf16", "f16"]
+        dt = dts[rng.integers(0, len(dts))]
+        n = int(round(10.0 ** rng.uniform(lo, hi)))
+        reqs.append((fn, var, dt, n, i))
+    return reqs
+
+
+def request_inputs(fn, dt, n, idx):
+    a = config4(fn, dt, n, operand=1000 + 2 * idx) if dt in ("bf16", "f16") else \
+        config2(fn, dt, n, operand=1000 + 2 * idx)
+    b = None
+    if fn in ("pow", "atan2"):
+        b = config4(fn, dt, n, operand=1001 + 2 * idx) if dt in ("bf16", "f16") else \
+            config2(fn, dt, n, operand=1001 + 2 * idx)
+    return a, b
+
+
+def autograd_inputs(fn, n=1 << 24, operand=0):
+    rng = rng_for(6, fn, operand)
+    return rng.uniform(0.1, 10.0, n).astype(np.float32)
+
+
+PAPER_DOMAINS = {
+    "sin": [(0.4, 0.5), (0.0, 6.28), (0.0, 1e100)],
+    "cos": [(0.4, 0.5), (0.0, 6.28), (0.0, 1e100)],
+    "tan": [(0.4, 0.5), (0.0, 6.28), (0.0, 1e100)],
+    "log": [(0.0, 1e300)],
+    "exp": [(-700.0, 700.0)],
+    "pow": [(-30.0, 30.0)],
+}
+
+
+def paper_domain(fn, lo, hi, n, dt="f64", operand=0):
+    rng = rng_for(7, fn, operand)
+    return _cast(rng.uniform(lo, hi, n), dt)
