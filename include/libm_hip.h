@@ -135,6 +135,35 @@ LIBM_HIP_DECL_BINARY(remainder, , double, f64)
 LIBM_HIP_DECL_BINARY(remainder, , float, f32)
 
 /* ------------------------------------------------------------------------
+ * Backward (vector-Jacobian products) for autograd; not part of the paper.
+ * gx[i] = gy[i] * f'(x[i]) for sin, cos, tan, exp, log, tanh, evaluated from
+ * the u10 forward pieces (tanh' as 1/cosh^2, never 1 - tanh^2).  Binary:
+ *   pow:   gx = gout * y * x^(y-1),  gy = gout * x^y * log(x)  (x > 0;
+ *          gy = 0 at x == 0 with y >= 0, NaN for x < 0);
+ *   atan2: gy = gout * x / (x^2 + y^2), gx = -gout * y / (x^2 + y^2).
+ * Same conventions as the forward calls (device pointers, n, stream).
+ * ---------------------------------------------------------------------- */
+#define LIBM_HIP_DECL_BWD(fn)                                                              \
+  libm_hip_status libm_hip_##fn##_u10_f64_bwd(const double* x, const double* gy,           \
+                                              double* gx, size_t n, void* stream);         \
+  libm_hip_status libm_hip_##fn##_u10_f32_bwd(const float* x, const float* gy, float* gx,  \
+                                              size_t n, void* stream);
+LIBM_HIP_DECL_BWD(sin)
+LIBM_HIP_DECL_BWD(cos)
+LIBM_HIP_DECL_BWD(tan)
+LIBM_HIP_DECL_BWD(exp)
+LIBM_HIP_DECL_BWD(log)
+LIBM_HIP_DECL_BWD(tanh)
+libm_hip_status libm_hip_pow_u10_f64_bwd(const double* x, const double* y, const double* gout,
+                                         double* gx, double* gy, size_t n, void* stream);
+libm_hip_status libm_hip_pow_u10_f32_bwd(const float* x, const float* y, const float* gout,
+                                         float* gx, float* gy, size_t n, void* stream);
+libm_hip_status libm_hip_atan2_u10_f64_bwd(const double* y, const double* x, const double* gout,
+                                           double* gy, double* gx, size_t n, void* stream);
+libm_hip_status libm_hip_atan2_u10_f32_bwd(const float* y, const float* x, const float* gout,
+                                           float* gy, float* gx, size_t n, void* stream);
+
+/* ------------------------------------------------------------------------
  * Generic dispatcher: the same kernels selected by enums.  b must be NULL
  * for unary functions.  Returns LIBM_HIP_ERR_UNSUPPORTED for a combination
  * the library does not serve (e.g. u35 in bf16).

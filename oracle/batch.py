@@ -81,3 +81,39 @@ def evaluate(fn, fmt, a, b=None, workers=None, serial_below=256):
         parts = _get_pool(workers).map(_chunk, jobs)
         out = np.concatenate(parts, axis=1)
     return out[0], out[1], out[2]
+
+
+def _grad_chunk(args):
+    fn, fmt, a, b, g = args
+    from .derivatives import grad1, grad_pow, grad_atan2
+    k = 1 if b is None else 2
+    out = np.empty((k, 3, len(a)), dtype=np.float64)
+    for i in range(len(a)):
+        if b is None:
+            out[0, :, i] = grad1(fn, fmt, float(a[i]), float(g[i]))
+        else:
+            f = grad_pow if fn == "pow" else grad_atan2
+            r0, r1 = f(fmt, float(a[i]), float(b[i]), float(g[i]))
+            out[0, :, i] = r0
+            out[1, :, i] = r1
+    return out
+
+
+def evaluate_grad(fn, fmt, a, g, b=None, workers=None):
+    """Correctly rounded g * f'(x) (unary) or both partials of pow(a, b) /
+    atan2(a, b) times g.  Returns a list of (rn, hi, lo) triples."""
+    a = np.asarray(a, dtype=np.float64).ravel()
+    g = np.asarray(g, dtype=np.float64).ravel()
+    b = None if b is None else np.asarray(b, dtype=np.float64).ravel()
+    n = a.shape[0]
+    workers = workers or default_workers()
+    nchunks = max(1, min(n, workers * 8))
+    bounds = np.linspace(0, n, nchunks + 1).astype(np.int64)
+    jobs = [(fn, fmt, a[s:e], None if b is None else b[s:e], g[s:e])
+            for s, e in zip(bounds[:-1], bounds[1:]) if e > s]
+    if n < 256 or workers <= 1:
+        parts = [_grad_chunk(j) for j in jobs]
+    else:
+        parts = _get_pool(workers).map(_grad_chunk, jobs)
+    out = np.concatenate(parts, axis=2)
+    return [(out[k, 0], out[k, 1], out[k, 2]) for k in range(out.shape[0])]

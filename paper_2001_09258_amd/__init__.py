@@ -59,6 +59,16 @@ def served(fn, variant, dtype):
     return dtype in DTYPES
 
 
+BWD_UNARY = ("sin", "cos", "tan", "exp", "log", "tanh")
+BWD_BINARY = ("pow", "atan2")
+
+
+def bwd_entry_points():
+    """(fn, dtype, name) of every backward entry point."""
+    return [(fn, dt, "libm_hip_%s_u10_%s_bwd" % (fn, dt))
+            for fn in BWD_UNARY + BWD_BINARY for dt in ("f64", "f32")]
+
+
 def all_entry_points():
     out = []
     for fn in UNARY + BINARY:
@@ -92,6 +102,10 @@ def load():
             f.argtypes = [vp, vp, sz, vp]
         else:
             f.argtypes = [vp, vp, vp, sz, vp]
+    for fn, dt, name in bwd_entry_points():
+        f = getattr(lib, name)
+        f.restype = ctypes.c_int
+        f.argtypes = [vp, vp, vp, sz, vp] if fn in BWD_UNARY else [vp, vp, vp, vp, vp, sz, vp]
     lib.libm_hip_eval.restype = ctypes.c_int
     lib.libm_hip_eval.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp, sz, vp]
     _lib = lib
@@ -113,6 +127,9 @@ def _make_raw(name):
 
 
 for _fn, _v, _dt, _name in all_entry_points():
+    globals()[_name] = _make_raw(_name)
+    __all__.append(_name)
+for _fn, _dt, _name in bwd_entry_points():
     globals()[_name] = _make_raw(_name)
     __all__.append(_name)
 
@@ -206,3 +223,28 @@ def fmod(x, y, out=None):
 def remainder(x, y, out=None):
     """Exact IEEE remainder(x, y) elementwise."""
     return evaluate("remainder", x, y, "exact", out)
+
+
+def backward(fn, inputs, gout, outs=None):
+    """Raw backward call: ``inputs`` are the saved forward inputs (C order),
+    ``gout`` the upstream gradient; returns the input gradient(s)."""
+    import torch
+    load()
+    tag = _dtype_tag(inputs[0], False)
+    if tag not in ("f64", "f32"):
+        raise TypeError("backward kernels take float64 or float32")
+    name = "libm_hip_%s_u10_%s_bwd" % (fn, tag)
+    f = getattr(load(), name)
+    ins = [t.contiguous() for t in inputs]
+    g = gout.contiguous()
+    n = ins[0].numel()
+    with torch.cuda.device(ins[0].device):
+        if fn in BWD_UNARY:
+            gx = torch.empty_like(ins[0]) if outs is None else outs[0]
+            _check(f(ins[0].data_ptr(), g.data_ptr(), gx.data_ptr(), n, _stream_handle()), name)
+            return (gx,)
+        g0 = torch.empty_like(ins[0]) if outs is None else outs[0]
+        g1 = torch.empty_like(ins[0]) if outs is None else outs[1]
+        _check(f(ins[0].data_ptr(), ins[1].data_ptr(), g.data_ptr(), g0.data_ptr(),
+                 g1.data_ptr(), n, _stream_handle()), name)
+        return (g0, g1)

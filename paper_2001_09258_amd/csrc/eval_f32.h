@@ -263,7 +263,7 @@ LMH_INLINE fff tanf_reduce(float x, float& k) {
   return r;
 }
 
-LMH_INLINE float tanf_u10(float x) {
+LMH_INLINE fff tanf_ff(float x) {
   float k;
   fff r = tanf_reduce(x, k);
   fff y = dd2_scale(r, 0.5f);
@@ -279,8 +279,12 @@ LMH_INLINE float tanf_u10(float x) {
     den = dd2_neg(tmp);
   }
   fff q = dd2_div(num, den);
-  float res = q.hi + q.lo;
-  return fabs_(x) < 0x1p-12f ? x : res;
+  return fabs_(x) < 0x1p-12f ? mk(x, 0.0f) : q;
+}
+
+LMH_INLINE float tanf_u10(float x) {
+  fff q = tanf_ff(x);
+  return fabs_(x) < 0x1p-12f ? x : q.hi + q.lo;
 }
 
 LMH_INLINE float tanf_u35(float x) {
@@ -367,7 +371,12 @@ LMH_INLINE float atan2f_u10(float y, float x) {
   fff c3 = dd2_mul(t3, mk(-THIRD_F_H, -THIRD_F_L));
   float p5 = (t3.hi * z) * a2;
   fff a = dd2_add(dd2_add(t, c3), p5);
-  if (t.hi < 0x1p-100f) a = mk(n / d, 0.0f);
+  if (t.hi < 0x1p-100f) {                           // see atan2_u10
+    float q = n / d;
+    float r = fma_(-ldexp_(q, 60), d, ldexp_(n, 60));
+    bool tie_up = r < 0.0f && -r == ldexp_(d, -90);
+    a = mk(tie_up ? pred_(q) : q, 0.0f);
+  }
   if (swap) a = dd2_add(mk(PIH2_F_H, PIH2_F_L), dd2_neg(a));
   bool xneg = __builtin_signbit(x);
   if (xneg) a = dd2_add(mk(PI2_F_H, PI2_F_L), dd2_neg(a));

@@ -15,6 +15,7 @@
 
 #include "eval_f64.h"
 #include "eval_f32.h"
+#include "eval_grad.h"
 #include "../../include/libm_hip.h"
 
 namespace {
@@ -131,6 +132,44 @@ __global__ __launch_bounds__(BLOCK) void k_binary(const typename Io::S* __restri
   }
 }
 
+// three inputs, two outputs (backward of the binary functions)
+template <class Io, class Op, int EPT, bool VEC>
+__global__ __launch_bounds__(BLOCK) void k_ternary2(const typename Io::S* __restrict__ a,
+                                                    const typename Io::S* __restrict__ b,
+                                                    const typename Io::S* __restrict__ c,
+                                                    typename Io::S* __restrict__ y0,
+                                                    typename Io::S* __restrict__ y1, size_t n) {
+  typedef typename Io::S S;
+  typedef typename Io::C C;
+  size_t base = ((size_t)blockIdx.x * BLOCK + threadIdx.x) * EPT;
+  if (base >= n) return;
+  if (VEC && base + EPT <= n) {
+    Pack<S, EPT> ia = *reinterpret_cast<const Pack<S, EPT>*>(a + base);
+    Pack<S, EPT> ib = *reinterpret_cast<const Pack<S, EPT>*>(b + base);
+    Pack<S, EPT> ic = *reinterpret_cast<const Pack<S, EPT>*>(c + base);
+    Pack<S, EPT> o0, o1;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      C r0, r1;
+      Op::f(Io::in(ia.v[i]), Io::in(ib.v[i]), Io::in(ic.v[i]), r0, r1);
+      o0.v[i] = Io::out(r0);
+      o1.v[i] = Io::out(r1);
+    }
+    store_nt(o0, y0 + base);
+    store_nt(o1, y1 + base);
+  } else {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      if (base + i < n) {
+        C r0, r1;
+        Op::f(Io::in(a[base + i]), Io::in(b[base + i]), Io::in(c[base + i]), r0, r1);
+        y0[base + i] = Io::out(r0);
+        y1[base + i] = Io::out(r1);
+      }
+    }
+  }
+}
+
 // elements per lane: 16 bytes of storage per lane and operand
 template <class S>
 constexpr int ept_for() { return 16 / (int)sizeof(S); }
@@ -203,6 +242,39 @@ libm_hip_status launch_binary(const void* a, const void* b, void* y, size_t n, v
   return LIBM_HIP_OK;
 }
 
+template <class Io, class Op>
+libm_hip_status launch_ternary2(const void* a, const void* b, const void* c, void* y0, void* y1,
+                                size_t n, void* stream, const char* name) {
+  if (n == 0) return LIBM_HIP_OK;
+  if (!a || !b || !c || !y0 || !y1) {
+    set_error("libm_hip: NULL pointer with n > 0");
+    return LIBM_HIP_ERR_INVALID;
+  }
+  typedef typename Io::S S;
+  constexpr int EPT = ept_for<S>();
+  size_t per_block = (size_t)BLOCK * EPT;
+  size_t blocks = (n + per_block - 1) / per_block;
+  if (blocks > 0x7fffffffull) {
+    set_error("libm_hip: n too large for one launch");
+    return LIBM_HIP_ERR_INVALID;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const S *as = (const S*)a, *bs = (const S*)b, *cs = (const S*)c;
+  S *o0 = (S*)y0, *o1 = (S*)y1;
+  if (aligned16(a) && aligned16(b) && aligned16(c) && aligned16(y0) && aligned16(y1))
+    hipLaunchKernelGGL((k_ternary2<Io, Op, EPT, true>), dim3((unsigned)blocks), dim3(BLOCK), 0, s, as, bs, cs, o0, o1, n);
+  else
+    hipLaunchKernelGGL((k_ternary2<Io, Op, EPT, false>), dim3((unsigned)blocks), dim3(BLOCK), 0, s, as, bs, cs, o0, o1, n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    char buf[200];
+    snprintf(buf, sizeof(buf), "libm_hip: %s launch failed: %s", name, hipGetErrorString(e));
+    set_error(buf);
+    return LIBM_HIP_ERR_HIP;
+  }
+  return LIBM_HIP_OK;
+}
+
 // ---------------------------------------------------------------------------
 // operation tags: one per evaluator, overloaded on the compute type
 // ---------------------------------------------------------------------------
@@ -234,6 +306,27 @@ LMH_OP2(OpPowU10, pow_u10, powf_u10)
 LMH_OP2(OpAtan2U10, atan2_u10, atan2f_u10)
 LMH_OP2(OpFmod, fmod_f64, fmodf_f32)
 LMH_OP2(OpRemainder, remainder_f64, remainderf_f32)
+
+// backward tags: (x, g) -> g f'(x); (a, b, g) -> two partials
+#define LMH_OPB(NAME, FN)                                                                   \
+  struct NAME {                                                                           \
+    static __device__ __forceinline__ double f(double x, double g) { return lmh::FN(x, g); } \
+    static __device__ __forceinline__ float f(float x, float g) { return lmh::FN(x, g); }    \
+  };
+LMH_OPB(OpSinBwd, sin_bwd)
+LMH_OPB(OpCosBwd, cos_bwd)
+LMH_OPB(OpTanBwd, tan_bwd)
+LMH_OPB(OpExpBwd, exp_bwd)
+LMH_OPB(OpLogBwd, log_bwd)
+LMH_OPB(OpTanhBwd, tanh_bwd)
+struct OpPowBwd {
+  template <class T>
+  static __device__ __forceinline__ void f(T x, T y, T g, T& gx, T& gy) { lmh::pow_bwd(x, y, g, gx, gy); }
+};
+struct OpAtan2Bwd {
+  template <class T>
+  static __device__ __forceinline__ void f(T y, T x, T g, T& gy, T& gx) { lmh::atan2_bwd(y, x, g, gy, gx); }
+};
 
 }  // namespace
 
@@ -307,6 +400,44 @@ LMH_DEF_BINARY(fmod, , IoF32, float, f32, OpFmod)
 LMH_DEF_BINARY(remainder, , IoF64, double, f64, OpRemainder)
 LMH_DEF_BINARY(remainder, , IoF32, float, f32, OpRemainder)
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// backward entry points
+// ---------------------------------------------------------------------------
+extern "C" {
+#define LMH_DEF_BWD(fn, Op)                                                                        \
+  libm_hip_status libm_hip_##fn##_u10_f64_bwd(const double* x, const double* gy, double* gx,     \
+                                               size_t n, void* s) {                                \
+    return launch_binary<IoF64, Op>(x, gy, gx, n, s, #fn "_u10_f64_bwd");                          \
+  }                                                                                                \
+  libm_hip_status libm_hip_##fn##_u10_f32_bwd(const float* x, const float* gy, float* gx,        \
+                                               size_t n, void* s) {                                \
+    return launch_binary<IoF32, Op>(x, gy, gx, n, s, #fn "_u10_f32_bwd");                          \
+  }
+LMH_DEF_BWD(sin, OpSinBwd)
+LMH_DEF_BWD(cos, OpCosBwd)
+LMH_DEF_BWD(tan, OpTanBwd)
+LMH_DEF_BWD(exp, OpExpBwd)
+LMH_DEF_BWD(log, OpLogBwd)
+LMH_DEF_BWD(tanh, OpTanhBwd)
+
+libm_hip_status libm_hip_pow_u10_f64_bwd(const double* x, const double* y, const double* gout,
+                                         double* gx, double* gy, size_t n, void* s) {
+  return launch_ternary2<IoF64, OpPowBwd>(x, y, gout, gx, gy, n, s, "pow_u10_f64_bwd");
+}
+libm_hip_status libm_hip_pow_u10_f32_bwd(const float* x, const float* y, const float* gout,
+                                         float* gx, float* gy, size_t n, void* s) {
+  return launch_ternary2<IoF32, OpPowBwd>(x, y, gout, gx, gy, n, s, "pow_u10_f32_bwd");
+}
+libm_hip_status libm_hip_atan2_u10_f64_bwd(const double* y, const double* x, const double* gout,
+                                           double* gy, double* gx, size_t n, void* s) {
+  return launch_ternary2<IoF64, OpAtan2Bwd>(y, x, gout, gy, gx, n, s, "atan2_u10_f64_bwd");
+}
+libm_hip_status libm_hip_atan2_u10_f32_bwd(const float* y, const float* x, const float* gout,
+                                           float* gy, float* gx, size_t n, void* s) {
+  return launch_ternary2<IoF32, OpAtan2Bwd>(y, x, gout, gy, gx, n, s, "atan2_u10_f32_bwd");
+}
 }  // extern "C"
 
 // ---------------------------------------------------------------------------

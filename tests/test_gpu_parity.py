@@ -92,6 +92,14 @@ def _special_inputs(dt, binary):
         vals = np.concatenate([vals.astype(np.float16).astype(np.float64),
                                [2.0 ** -24, -(2.0 ** -24), 6.097555160522461e-05, 11.0859375,
                                 65504.0]])
+    # every value must be one of the format (the oracle sees exactly what the
+    # kernel sees)
+    if dt in ("f32", "f32_via_f64"):
+        vals = vals.astype(np.float32).astype(np.float64)
+    elif dt == "f16":
+        vals = vals.astype(np.float16).astype(np.float64)
+    elif dt == "bf16":
+        vals = W.round_to_bf16(vals.astype(np.float32)).astype(np.float64)
     vals = np.unique(vals[~np.isnan(vals)])
     vals = np.concatenate([vals, [np.nan]])
     if binary:
