@@ -22,7 +22,7 @@ def _floor_log2(hi, lo):
     return np.where(below, e - 1, e)
 
 
-def compare(y, rn, hi, lo, fmt, bound):
+def compare(y, rn, hi, lo, fmt, bound, double_rounded=False):
     """Returns a dict with max/mean ULP error, the number of bound
     violations, special-class mismatches and the indices of failures.
 
@@ -30,7 +30,8 @@ def compare(y, rn, hi, lo, fmt, bound):
     bf16 / f16 output can land on the other side of a tie of the narrow
     format (double rounding; the error stays below 0.5 + 2^-13 ulp): for those
     two formats subnormal outputs are held to the ULP bound, and zeros,
-    infinities and NaN stay bit-exact."""
+    infinities and NaN stay bit-exact.  ``double_rounded`` applies the same
+    rule to binary32 results obtained by rounding a binary64 evaluation."""
     p, emin, emax = FMT[fmt]
     y = np.asarray(y, dtype=np.float64)
     rn = np.asarray(rn, dtype=np.float64)
@@ -38,7 +39,7 @@ def compare(y, rn, hi, lo, fmt, bound):
     lo = np.asarray(lo, dtype=np.float64)
     tiny = 2.0 ** emin
     special = np.isnan(rn) | np.isinf(rn) | (rn == 0)
-    if fmt in ("f64", "f32"):
+    if fmt in ("f64", "f32") and not double_rounded:
         special |= np.abs(rn) < tiny
     same = (y == rn) & (np.signbit(y) == np.signbit(rn))
     same |= np.isnan(y) & np.isnan(rn)
