@@ -184,6 +184,44 @@ libm_hip_status libm_hip_eval(libm_hip_fn fn, libm_hip_variant v, libm_hip_dtype
                               const void* a, const void* b, void* out, size_t n,
                               void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batched evaluation (not part of the paper): one persistent kernel, captured
+ * once in a hip graph per plan, serves a list of requests of uneven lengths.
+ * Results are bit-identical to the per-function entry points (same
+ * evaluators).  Requests are cut into 4096-element tiles that workgroups take
+ * from a device counter, most expensive requests first.
+ *
+ * libm_hip_batch_plan_create: allocates the plan's device request table (up
+ *   to max_requests <= 1024 entries), a pinned staging copy, a tile counter,
+ *   a private capture stream; use_graph != 0 replays a captured graph, 0
+ *   launches the kernels directly.  The plan owns these; destroy frees them.
+ * libm_hip_batch_run: validates every request (LIBM_HIP_ERR_UNSUPPORTED for a
+ *   combination the library does not serve, LIBM_HIP_ERR_INVALID for NULL
+ *   pointers with n > 0), uploads the table on `stream` and enqueues the
+ *   kernels there; returns without waiting for them.  Requests with n == 0
+ *   are skipped.  A plan is not thread-safe: runs of one plan must be issued
+ *   from one thread, on one stream or with the streams ordered by the caller.
+ * Errors of these three calls are reported by libm_hip_batch_last_error().
+ * ---------------------------------------------------------------------- */
+typedef struct libm_hip_request {
+  int fn;           /* libm_hip_fn */
+  int variant;      /* libm_hip_variant */
+  int dtype;        /* libm_hip_dtype */
+  int reserved;
+  const void* a;    /* first operand (C argument order) */
+  const void* b;    /* second operand, NULL for unary functions */
+  void* out;
+  size_t n;
+} libm_hip_request;
+typedef struct libm_hip_batch_plan libm_hip_batch_plan;
+
+libm_hip_status libm_hip_batch_plan_create(libm_hip_batch_plan** plan, int max_requests,
+                                           int use_graph);
+libm_hip_status libm_hip_batch_run(libm_hip_batch_plan* plan, const libm_hip_request* requests,
+                                   int k, void* stream);
+void libm_hip_batch_plan_destroy(libm_hip_batch_plan* plan);
+const char* libm_hip_batch_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -248,3 +248,80 @@ def backward(fn, inputs, gout, outs=None):
         _check(f(ins[0].data_ptr(), ins[1].data_ptr(), g.data_ptr(), g0.data_ptr(),
                  g1.data_ptr(), n, _stream_handle()), name)
         return (g0, g1)
+
+
+# ---------------------------------------------------------------------------
+# batched evaluation (one persistent kernel per run, hip-graph replayed)
+# ---------------------------------------------------------------------------
+FN_CODES = {"sin": 0, "cos": 1, "tan": 2, "exp": 3, "exp2": 4, "log": 5, "log2": 6,
+            "pow": 7, "atan2": 8, "sinh": 9, "cosh": 10, "tanh": 11, "fmod": 12,
+            "remainder": 13}
+VARIANT_CODES = {"u10": 0, "u35": 1, "exact": 2}
+DTYPE_CODES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "f32_via_f64": 4}
+
+
+class Request(ctypes.Structure):
+    """Mirror of the C struct libm_hip_request."""
+    _fields_ = [("fn", ctypes.c_int), ("variant", ctypes.c_int), ("dtype", ctypes.c_int),
+                ("reserved", ctypes.c_int), ("a", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("out", ctypes.c_void_p), ("n", ctypes.c_size_t)]
+
+
+def _batch_lib():
+    lib = load()
+    if not getattr(lib, "_batch_ready", False):
+        lib.libm_hip_batch_plan_create.restype = ctypes.c_int
+        lib.libm_hip_batch_plan_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                                   ctypes.c_int]
+        lib.libm_hip_batch_run.restype = ctypes.c_int
+        lib.libm_hip_batch_run.argtypes = [ctypes.c_void_p, ctypes.POINTER(Request), ctypes.c_int,
+                                           ctypes.c_void_p]
+        lib.libm_hip_batch_plan_destroy.restype = None
+        lib.libm_hip_batch_plan_destroy.argtypes = [ctypes.c_void_p]
+        lib.libm_hip_batch_last_error.restype = ctypes.c_char_p
+        lib._batch_ready = True
+    return lib
+
+
+class BatchPlan:
+    """A libm_hip batch plan: ``run([(fn, variant, dtype, a, b, out), ...])``
+    with device tensors (``b`` None for unary functions); enqueued on the
+    current stream."""
+
+    def __init__(self, max_requests=64, use_graph=True):
+        lib = _batch_lib()
+        h = ctypes.c_void_p()
+        st = lib.libm_hip_batch_plan_create(ctypes.byref(h), max_requests, 1 if use_graph else 0)
+        if st != 0:
+            raise LibmHipError("batch_plan_create failed (%d): %s"
+                               % (st, lib.libm_hip_batch_last_error().decode()))
+        self._h = h
+        self.max_requests = max_requests
+
+    def run(self, requests, stream=None):
+        lib = _batch_lib()
+        arr = (Request * max(1, len(requests)))()
+        for i, (fn, v, dt, a, b, out) in enumerate(requests):
+            arr[i] = Request(FN_CODES[fn], VARIANT_CODES[v], DTYPE_CODES[dt], 0,
+                             a.data_ptr(), 0 if b is None else b.data_ptr(), out.data_ptr(),
+                             a.numel())
+        st = lib.libm_hip_batch_run(self._h, arr, len(requests),
+                                    _stream_handle() if stream is None else stream)
+        if st != 0:
+            raise LibmHipError("batch_run failed (%d): %s"
+                               % (st, lib.libm_hip_batch_last_error().decode()))
+
+    def run_raw(self, arr, k, stream):
+        """Run a prepared ctypes Request array (no Python-side marshalling)."""
+        return _batch_lib().libm_hip_batch_run(self._h, arr, k, stream)
+
+    def close(self):
+        if self._h:
+            _batch_lib().libm_hip_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -13,7 +13,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "csrc", "kernels.hip")
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "batch.hip")]
 OUT = os.path.join(HERE, "libm_hip.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -24,7 +24,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 
 
 def build(verbose=True, extra=()):
-    cmd = [HIPCC] + FLAGS + list(extra) + ["-o", OUT + ".tmp", SRC]
+    cmd = [HIPCC] + FLAGS + list(extra) + ["-o", OUT + ".tmp"] + SRCS
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

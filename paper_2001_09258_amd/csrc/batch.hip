@@ -1,0 +1,330 @@
+// Batched evaluation: one persistent kernel serves a list of requests
+// (function, variant, element type, arrays, n) of uneven lengths.
+//
+// Not part of the paper.  The requests are cut into tiles of TILE elements;
+// workgroups take tiles from a device counter until none is left, so long
+// and short requests share the machine without one launch per request.  The
+// host orders requests by estimated cost (elements x per-element work, most
+// expensive first) before numbering their tiles, so the costly tiles start
+// early and the tail of the batch is made of cheap ones.  Dispatch on the
+// request's operation is uniform across the workgroup.
+//
+// A plan owns the device copy of the request table and the tile counter, and
+// a hip graph of [counter reset kernel -> persistent kernel] captured on
+// first use: every run uploads the table and replays the graph.  The kernel
+// reads the table and the tile total from device memory, so the graph stays
+// valid for any request list that fits the plan.
+#include "ops.h"
+#include "../../include/libm_hip.h"
+
+#include <algorithm>
+#include <new>
+#include <stdio.h>
+#include <string.h>
+#include <vector>
+
+namespace {
+using namespace lmh_ops;
+
+constexpr int BBLOCK = 256;
+constexpr int TILE = 4096;          // elements per tile (16 per lane)
+constexpr int MAX_REQ = 1024;       // requests per plan
+
+struct Desc {
+  const void* a;
+  const void* b;
+  void* out;
+  unsigned long long n;
+  unsigned long long tile_begin;
+  int op;
+  int pad;
+};
+
+struct Header {
+  unsigned long long total_tiles;
+  int k;
+  int pad;
+};
+
+// ---- operation table -------------------------------------------------------
+// X(code, Io, Op, arity)
+#define LMH_BATCH_OPS(X)                                                       \
+  X(0, IoF64, OpSinU10, 1) X(1, IoF32, OpSinU10, 1) X(2, IoBF16, OpSinU10, 1)    \
+  X(3, IoF16, OpSinU10, 1) X(4, IoF32ViaF64, OpSinU10, 1)                       \
+  X(5, IoF64, OpSinU35, 1) X(6, IoF32, OpSinU35, 1)                             \
+  X(7, IoF64, OpCosU10, 1) X(8, IoF32, OpCosU10, 1) X(9, IoBF16, OpCosU10, 1)    \
+  X(10, IoF16, OpCosU10, 1) X(11, IoF32ViaF64, OpCosU10, 1)                     \
+  X(12, IoF64, OpCosU35, 1) X(13, IoF32, OpCosU35, 1)                           \
+  X(14, IoF64, OpTanU10, 1) X(15, IoF32, OpTanU10, 1) X(16, IoBF16, OpTanU10, 1) \
+  X(17, IoF16, OpTanU10, 1) X(18, IoF32ViaF64, OpTanU10, 1)                     \
+  X(19, IoF64, OpTanU35, 1) X(20, IoF32, OpTanU35, 1)                           \
+  X(21, IoF64, OpExpU10, 1) X(22, IoF32, OpExpU10, 1) X(23, IoBF16, OpExpU10, 1) \
+  X(24, IoF16, OpExpU10, 1) X(25, IoF32ViaF64, OpExpU10, 1)                     \
+  X(26, IoF64, OpExp2U10, 1) X(27, IoF32, OpExp2U10, 1) X(28, IoBF16, OpExp2U10, 1) \
+  X(29, IoF16, OpExp2U10, 1) X(30, IoF32ViaF64, OpExp2U10, 1)                   \
+  X(31, IoF64, OpLogU10, 1) X(32, IoF32, OpLogU10, 1) X(33, IoBF16, OpLogU10, 1) \
+  X(34, IoF16, OpLogU10, 1) X(35, IoF32ViaF64, OpLogU10, 1)                     \
+  X(36, IoF64, OpLog2U10, 1) X(37, IoF32, OpLog2U10, 1) X(38, IoBF16, OpLog2U10, 1) \
+  X(39, IoF16, OpLog2U10, 1) X(40, IoF32ViaF64, OpLog2U10, 1)                   \
+  X(41, IoF64, OpSinhU10, 1) X(42, IoF32, OpSinhU10, 1) X(43, IoBF16, OpSinhU10, 1) \
+  X(44, IoF16, OpSinhU10, 1) X(45, IoF32ViaF64, OpSinhU10, 1)                   \
+  X(46, IoF64, OpCoshU10, 1) X(47, IoF32, OpCoshU10, 1) X(48, IoBF16, OpCoshU10, 1) \
+  X(49, IoF16, OpCoshU10, 1) X(50, IoF32ViaF64, OpCoshU10, 1)                   \
+  X(51, IoF64, OpTanhU10, 1) X(52, IoF32, OpTanhU10, 1) X(53, IoBF16, OpTanhU10, 1) \
+  X(54, IoF16, OpTanhU10, 1) X(55, IoF32ViaF64, OpTanhU10, 1)                   \
+  X(56, IoF64, OpPowU10, 2) X(57, IoF32, OpPowU10, 2) X(58, IoBF16, OpPowU10, 2) \
+  X(59, IoF16, OpPowU10, 2) X(60, IoF32ViaF64, OpPowU10, 2)                     \
+  X(61, IoF64, OpAtan2U10, 2) X(62, IoF32, OpAtan2U10, 2) X(63, IoBF16, OpAtan2U10, 2) \
+  X(64, IoF16, OpAtan2U10, 2) X(65, IoF32ViaF64, OpAtan2U10, 2)                 \
+  X(66, IoF64, OpFmod, 2) X(67, IoF32, OpFmod, 2)                               \
+  X(68, IoF64, OpRemainder, 2) X(69, IoF32, OpRemainder, 2)
+constexpr int NUM_OPS = 70;
+
+// host-side code of a (fn, variant, dtype) triple, or -1
+int op_code(int fn, int v, int t) {
+  // dtype order in the table: f64, f32, bf16, f16, f32_via_f64
+  static const int u10_base[LIBM_HIP_NUM_FN] = {0, 7, 14, 21, 26, 31, 36, 56, 61, 41, 46, 51, -1, -1};
+  static const int u35_base[LIBM_HIP_NUM_FN] = {5, 12, 19, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
+  if (fn < 0 || fn >= LIBM_HIP_NUM_FN || t < 0 || t > 4) return -1;
+  if (fn == LIBM_HIP_FMOD || fn == LIBM_HIP_REMAINDER) {
+    if (v != LIBM_HIP_EXACT || t > 1) return -1;
+    return (fn == LIBM_HIP_FMOD ? 66 : 68) + t;
+  }
+  if (v == LIBM_HIP_U10) return u10_base[fn] + t;
+  if (v == LIBM_HIP_U35) return u35_base[fn] < 0 || t > 1 ? -1 : u35_base[fn] + t;
+  return -1;
+}
+
+// relative per-element cost used to order requests, by function family
+// (from the elementwise kernels' measured times: trig with Payne-Hanek and
+// the remainders are the most expensive, exp/log the cheapest)
+float op_cost(int code) {
+  if (code >= 66) return 1.5f;                 // fmod, remainder
+  if (code <= 20) return 1.0f;                 // sin, cos, tan
+  if (code >= 56) return 0.8f;                 // pow, atan2
+  if (code >= 41) return 0.5f;                 // sinh, cosh, tanh
+  return 0.35f;                                // exp, exp2, log, log2
+}
+
+size_t op_arity(int code) { return code >= 56 ? 2 : 1; }
+
+// ---- device side -------------------------------------------------------------
+template <class Io, class Op, int ARITY>
+__device__ __forceinline__ void run_tile(const Desc& d, unsigned long long start) {
+  typedef typename Io::S S;
+  const S* a = (const S*)d.a;
+  const S* b = (const S*)d.b;
+  S* y = (S*)d.out;
+  unsigned long long end = start + TILE < d.n ? start + TILE : d.n;
+  for (unsigned long long i = start + threadIdx.x; i < end; i += BBLOCK) {
+    if constexpr (ARITY == 1)
+      y[i] = Io::out(Op::f(Io::in(a[i])));
+    else
+      y[i] = Io::out(Op::f(Io::in(a[i]), Io::in(b[i])));
+  }
+}
+
+__global__ void k_batch_reset(unsigned long long* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0ull;
+}
+
+__global__ __launch_bounds__(BBLOCK) void k_batch(const Desc* __restrict__ descs,
+                                                  const Header* __restrict__ hdr,
+                                                  unsigned long long* counter) {
+  __shared__ unsigned long long s_tile;
+  const unsigned long long total = hdr->total_tiles;
+  const int k = hdr->k;
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1ull);
+    __syncthreads();
+    unsigned long long t = s_tile;
+    __syncthreads();
+    if (t >= total) break;                   // the counter only grows: every
+                                             // workgroup reaches this exit
+    // request owning tile t: last r with tile_begin <= t (binary search)
+    int lo = 0, hi = k - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (descs[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+    }
+    Desc d = descs[lo];
+    unsigned long long start = (t - d.tile_begin) * (unsigned long long)TILE;
+    switch (d.op) {
+#define LMH_CASE(code, Io, Op, ar) \
+  case code: run_tile<Io, Op, ar>(d, start); break;
+      LMH_BATCH_OPS(LMH_CASE)
+#undef LMH_CASE
+      default: break;
+    }
+  }
+}
+
+thread_local char g_batch_error[256] = "";
+void batch_error(const char* m) {
+  strncpy(g_batch_error, m, sizeof(g_batch_error) - 1);
+}
+
+}  // namespace
+
+struct libm_hip_batch_plan {
+  int device;
+  int max_requests;
+  Desc* d_descs;
+  Header* d_hdr;
+  unsigned long long* d_counter;
+  Desc* h_descs;          // pinned staging
+  Header* h_hdr;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  hipStream_t capture_stream;   // private stream used only to capture the graph
+  hipEvent_t staged;            // the last upload from the pinned table is done
+  bool staged_valid;
+  unsigned grid;
+  bool use_graph;
+};
+
+extern "C" {
+
+const char* libm_hip_batch_last_error(void) { return g_batch_error; }
+
+libm_hip_status libm_hip_batch_plan_create(libm_hip_batch_plan** out, int max_requests,
+                                           int use_graph) {
+  if (!out || max_requests <= 0 || max_requests > MAX_REQ) {
+    batch_error("libm_hip_batch_plan_create: invalid arguments (1 <= max_requests <= 1024)");
+    return LIBM_HIP_ERR_INVALID;
+  }
+  libm_hip_batch_plan* p = new (std::nothrow) libm_hip_batch_plan();
+  if (!p) return LIBM_HIP_ERR_NOMEM;
+  memset(p, 0, sizeof(*p));
+  p->max_requests = max_requests;
+  p->use_graph = use_graph != 0;
+  hipError_t e = hipGetDevice(&p->device);
+  int cus = 0;
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+  if (e == hipSuccess) e = hipMalloc((void**)&p->d_descs, sizeof(Desc) * max_requests);
+  if (e == hipSuccess) e = hipMalloc((void**)&p->d_hdr, sizeof(Header));
+  if (e == hipSuccess) e = hipMalloc((void**)&p->d_counter, sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_descs, sizeof(Desc) * max_requests, 0);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_hdr, sizeof(Header), 0);
+  if (e == hipSuccess) e = hipStreamCreate(&p->capture_stream);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->staged, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    batch_error(hipGetErrorString(e));
+    libm_hip_batch_plan_destroy(p);
+    return LIBM_HIP_ERR_NOMEM;
+  }
+  // enough workgroups to fill every CU several times over
+  p->grid = (unsigned)(cus > 0 ? cus * 8 : 2048);
+  *out = p;
+  return LIBM_HIP_OK;
+}
+
+void libm_hip_batch_plan_destroy(libm_hip_batch_plan* p) {
+  if (!p) return;
+  if (p->exec) hipGraphExecDestroy(p->exec);
+  if (p->graph) hipGraphDestroy(p->graph);
+  if (p->d_descs) hipFree(p->d_descs);
+  if (p->d_hdr) hipFree(p->d_hdr);
+  if (p->d_counter) hipFree(p->d_counter);
+  if (p->h_descs) hipHostFree(p->h_descs);
+  if (p->h_hdr) hipHostFree(p->h_hdr);
+  if (p->staged) hipEventDestroy(p->staged);
+  if (p->capture_stream) hipStreamDestroy(p->capture_stream);
+  delete p;
+}
+
+static hipError_t enqueue_kernels(libm_hip_batch_plan* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, p->d_counter);
+  hipLaunchKernelGGL(k_batch, dim3(p->grid), dim3(BBLOCK), 0, s, p->d_descs, p->d_hdr,
+                     p->d_counter);
+  return hipGetLastError();
+}
+
+libm_hip_status libm_hip_batch_run(libm_hip_batch_plan* p, const libm_hip_request* reqs, int k,
+                                   void* stream) {
+  if (!p || (k > 0 && !reqs) || k < 0 || k > p->max_requests) {
+    batch_error("libm_hip_batch_run: invalid arguments");
+    return LIBM_HIP_ERR_INVALID;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  // validate and order by estimated cost, most expensive first
+  std::vector<int> order;
+  std::vector<float> cost(k);
+  std::vector<int> codes(k);
+  for (int i = 0; i < k; ++i) {
+    const libm_hip_request& r = reqs[i];
+    int code = op_code(r.fn, r.variant, r.dtype);
+    if (code < 0) {
+      batch_error("libm_hip_batch_run: unsupported (fn, variant, dtype)");
+      return LIBM_HIP_ERR_UNSUPPORTED;
+    }
+    if (r.n > 0 && (!r.a || !r.out || (op_arity(code) == 2 && !r.b))) {
+      batch_error("libm_hip_batch_run: NULL pointer with n > 0");
+      return LIBM_HIP_ERR_INVALID;
+    }
+    codes[i] = code;
+    cost[i] = op_cost(code) * (float)r.n;
+    if (r.n > 0) order.push_back(i);
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  if (order.empty()) return LIBM_HIP_OK;
+  // the pinned table may still feed the previous run's upload
+  hipError_t e = p->staged_valid ? hipEventSynchronize(p->staged) : hipSuccess;
+  if (e != hipSuccess) {
+    batch_error(hipGetErrorString(e));
+    return LIBM_HIP_ERR_HIP;
+  }
+  unsigned long long tiles = 0;
+  int m = 0;
+  for (int i : order) {
+    const libm_hip_request& r = reqs[i];
+    Desc& d = p->h_descs[m++];
+    d.a = r.a;
+    d.b = r.b;
+    d.out = r.out;
+    d.n = r.n;
+    d.tile_begin = tiles;
+    d.op = codes[i];
+    d.pad = 0;
+    tiles += (r.n + TILE - 1) / TILE;
+  }
+  p->h_hdr->total_tiles = tiles;
+  p->h_hdr->k = m;
+  p->h_hdr->pad = 0;
+  e = hipMemcpyAsync(p->d_descs, p->h_descs, sizeof(Desc) * m, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->d_hdr, p->h_hdr, sizeof(Header), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(p->staged, s);
+  if (e != hipSuccess) {
+    batch_error(hipGetErrorString(e));
+    return LIBM_HIP_ERR_HIP;
+  }
+  p->staged_valid = true;
+  if (p->use_graph) {
+    if (!p->exec) {
+      // captured once on the plan's own stream (the caller's may be the null
+      // stream, which cannot be captured); replayed on the caller's stream
+      e = hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        hipError_t e2 = enqueue_kernels(p, p->capture_stream);
+        e = hipStreamEndCapture(p->capture_stream, &p->graph);
+        if (e == hipSuccess) e = e2;
+      }
+      if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        batch_error(hipGetErrorString(e));
+        return LIBM_HIP_ERR_HIP;
+      }
+    }
+    e = hipGraphLaunch(p->exec, s);
+  } else {
+    e = enqueue_kernels(p, s);
+  }
+  if (e != hipSuccess) {
+    batch_error(hipGetErrorString(e));
+    return LIBM_HIP_ERR_HIP;
+  }
+  return LIBM_HIP_OK;
+}
+
+}  // extern "C"

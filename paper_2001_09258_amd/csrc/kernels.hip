@@ -13,12 +13,11 @@
 #include <stdio.h>
 #include <string.h>
 
-#include "eval_f64.h"
-#include "eval_f32.h"
-#include "eval_grad.h"
+#include "ops.h"
 #include "../../include/libm_hip.h"
 
 namespace {
+using namespace lmh_ops;
 
 thread_local char g_last_error[256] = "";
 
@@ -26,49 +25,6 @@ void set_error(const char* msg) {
   strncpy(g_last_error, msg, sizeof(g_last_error) - 1);
   g_last_error[sizeof(g_last_error) - 1] = 0;
 }
-
-// ---------------------------------------------------------------------------
-// storage <-> compute conversions
-// ---------------------------------------------------------------------------
-struct IoF64 {
-  typedef double S;
-  typedef double C;
-  static __device__ __forceinline__ C in(S v) { return v; }
-  static __device__ __forceinline__ S out(C v) { return v; }
-};
-struct IoF32 {
-  typedef float S;
-  typedef float C;
-  static __device__ __forceinline__ C in(S v) { return v; }
-  static __device__ __forceinline__ S out(C v) { return v; }
-};
-// binary32 storage evaluated in binary64, rounded once
-struct IoF32ViaF64 {
-  typedef float S;
-  typedef double C;
-  static __device__ __forceinline__ C in(S v) { return (double)v; }
-  static __device__ __forceinline__ S out(C v) { return (float)v; }
-};
-// bfloat16 bit patterns: widening is a shift; narrowing rounds to nearest
-// even (NaN stays a quiet NaN)
-struct IoBF16 {
-  typedef uint16_t S;
-  typedef float C;
-  static __device__ __forceinline__ C in(S v) { return lmh::as_f32((int32_t)((uint32_t)v << 16)); }
-  static __device__ __forceinline__ S out(C v) {
-    uint32_t u = (uint32_t)lmh::as_i32(v);
-    uint32_t r = (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
-    return (uint16_t)(lmh::isnan_(v) ? ((u >> 16) | 0x40u) : r);
-  }
-};
-// IEEE binary16 bit patterns: hardware conversions (exact widening, RNE
-// narrowing with overflow to inf and gradual underflow)
-struct IoF16 {
-  typedef uint16_t S;
-  typedef float C;
-  static __device__ __forceinline__ C in(S v) { return (float)__builtin_bit_cast(_Float16, v); }
-  static __device__ __forceinline__ S out(C v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
-};
 
 // ---------------------------------------------------------------------------
 // kernels
@@ -275,59 +231,6 @@ libm_hip_status launch_ternary2(const void* a, const void* b, const void* c, voi
   return LIBM_HIP_OK;
 }
 
-// ---------------------------------------------------------------------------
-// operation tags: one per evaluator, overloaded on the compute type
-// ---------------------------------------------------------------------------
-#define LMH_OP1(NAME, F64FN, F32FN)                                              \
-  struct NAME {                                                                \
-    static __device__ __forceinline__ double f(double x) { return lmh::F64FN(x); } \
-    static __device__ __forceinline__ float f(float x) { return lmh::F32FN(x); }   \
-  };
-#define LMH_OP2(NAME, F64FN, F32FN)                                                        \
-  struct NAME {                                                                          \
-    static __device__ __forceinline__ double f(double a, double b) { return lmh::F64FN(a, b); } \
-    static __device__ __forceinline__ float f(float a, float b) { return lmh::F32FN(a, b); }    \
-  };
-
-LMH_OP1(OpSinU10, sin_u10, sinf_u10)
-LMH_OP1(OpSinU35, sin_u35, sinf_u35)
-LMH_OP1(OpCosU10, cos_u10, cosf_u10)
-LMH_OP1(OpCosU35, cos_u35, cosf_u35)
-LMH_OP1(OpTanU10, tan_u10, tanf_u10)
-LMH_OP1(OpTanU35, tan_u35, tanf_u35)
-LMH_OP1(OpExpU10, exp_u10, expf_u10)
-LMH_OP1(OpExp2U10, exp2_u10, exp2f_u10)
-LMH_OP1(OpLogU10, log_u10, logf_u10)
-LMH_OP1(OpLog2U10, log2_u10, log2f_u10)
-LMH_OP1(OpSinhU10, sinh_u10, sinhf_u10)
-LMH_OP1(OpCoshU10, cosh_u10, coshf_u10)
-LMH_OP1(OpTanhU10, tanh_u10, tanhf_u10)
-LMH_OP2(OpPowU10, pow_u10, powf_u10)
-LMH_OP2(OpAtan2U10, atan2_u10, atan2f_u10)
-LMH_OP2(OpFmod, fmod_f64, fmodf_f32)
-LMH_OP2(OpRemainder, remainder_f64, remainderf_f32)
-
-// backward tags: (x, g) -> g f'(x); (a, b, g) -> two partials
-#define LMH_OPB(NAME, FN)                                                                   \
-  struct NAME {                                                                           \
-    static __device__ __forceinline__ double f(double x, double g) { return lmh::FN(x, g); } \
-    static __device__ __forceinline__ float f(float x, float g) { return lmh::FN(x, g); }    \
-  };
-LMH_OPB(OpSinBwd, sin_bwd)
-LMH_OPB(OpCosBwd, cos_bwd)
-LMH_OPB(OpTanBwd, tan_bwd)
-LMH_OPB(OpExpBwd, exp_bwd)
-LMH_OPB(OpLogBwd, log_bwd)
-LMH_OPB(OpTanhBwd, tanh_bwd)
-struct OpPowBwd {
-  template <class T>
-  static __device__ __forceinline__ void f(T x, T y, T g, T& gx, T& gy) { lmh::pow_bwd(x, y, g, gx, gy); }
-};
-struct OpAtan2Bwd {
-  template <class T>
-  static __device__ __forceinline__ void f(T y, T x, T g, T& gy, T& gx) { lmh::atan2_bwd(y, x, g, gy, gx); }
-};
-
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -444,6 +347,7 @@ libm_hip_status libm_hip_atan2_u10_f32_bwd(const float* y, const float* x, const
 // generic dispatcher
 // ---------------------------------------------------------------------------
 namespace {
+using namespace lmh_ops;
 
 template <class Op>
 libm_hip_status dispatch_unary(libm_hip_dtype t, const void* a, void* out, size_t n, void* s,

@@ -1,0 +1,91 @@
+"""Batched persistent kernel (one hip-graph replay per run) against the
+per-function entry points: bit-identical outputs on the config-5 request mix
+(function, variant and dtype drawn uniformly, lengths log-uniform), graph
+replays interleaved with eager work, the direct-launch mode, and the
+validation errors."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_common import to_device
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+import paper_2001_09258_amd as L  # noqa: E402
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L.load()
+
+
+def _requests(hi=5.3):
+    reqs = []
+    for fn, var, dt, n, idx in W.config5_requests(64, 3.0, hi):
+        a, b = W.request_inputs(fn, dt, n, idx)
+        ta = to_device(a, dt)
+        tb = to_device(b, dt) if b is not None else None
+        reqs.append((fn, var, dt, ta, tb, torch.empty_like(ta)))
+    return reqs
+
+
+def _same(x, y):
+    x = x.float() if x.dtype in (torch.bfloat16, torch.float16) else x
+    y = y.float() if y.dtype in (torch.bfloat16, torch.float16) else y
+    return torch.equal(torch.nan_to_num(x, nan=7.0), torch.nan_to_num(y, nan=7.0)) and \
+        torch.equal(torch.isnan(x), torch.isnan(y))
+
+
+def _reference(reqs):
+    return [L.evaluate(fn, a, b, variant=v, via_f64=(dt == "f32_via_f64"))
+            for fn, v, dt, a, b, out in reqs]
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batch_bit_identical_to_per_function(use_graph):
+    reqs = _requests()
+    ref = _reference(reqs)
+    plan = L.BatchPlan(64, use_graph=use_graph)
+    plan.run(reqs)
+    torch.cuda.synchronize()
+    for (fn, v, dt, a, b, out), r in zip(reqs, ref):
+        assert _same(out, r), (fn, v, dt, a.numel())
+    plan.close()
+
+
+def test_graph_replays_with_eager_work_between():
+    reqs = _requests(4.5)
+    ref = _reference(reqs)
+    plan = L.BatchPlan(64, use_graph=True)
+    for rep in range(4):
+        for *_, out in reqs:
+            out.fill_(123.0)
+        junk = torch.randn(1 << 20, device="cuda").sum()     # eager work
+        plan.run(reqs)
+        torch.cuda.synchronize()
+        assert junk.isfinite()
+        for (fn, v, dt, a, b, out), r in zip(reqs, ref):
+            assert _same(out, r), (rep, fn, v, dt)
+    # a different request list through the same captured graph
+    reqs2 = list(reversed(reqs[:20]))
+    for *_, out in reqs2:
+        out.zero_()
+    plan.run(reqs2)
+    torch.cuda.synchronize()
+    for (fn, v, dt, a, b, out) in reqs2:
+        assert _same(out, L.evaluate(fn, a, b, variant=v, via_f64=(dt == "f32_via_f64")))
+    plan.close()
+
+
+def test_batch_validation_errors():
+    plan = L.BatchPlan(4)
+    x = torch.ones(8, dtype=torch.bfloat16, device="cuda")
+    with pytest.raises(L.LibmHipError):                 # u35 is not served in bf16
+        plan.run([("sin", "u35", "bf16", x, None, x)])
+    y = torch.ones(8, dtype=torch.float64, device="cuda")
+    with pytest.raises(L.LibmHipError):                 # more requests than the plan holds
+        plan.run([("exp", "u10", "f64", y, None, y)] * 5)
+    plan.run([])                                        # empty list: nothing to do
+    plan.close()
