@@ -185,6 +185,28 @@ libm_hip_status libm_hip_eval(libm_hip_fn fn, libm_hip_variant v, libm_hip_dtype
                               void* stream);
 
 /* ------------------------------------------------------------------------
+ * Launch-shape autotuner (not part of the paper).  Every entry point except
+ * the trigonometric ones (whose kernel gathers Payne-Hanek lanes through a
+ * queue sized to a 256-lane workgroup) launches with a (workgroup size,
+ * 16-byte packs per lane) pair looked up per entry point and size bucket
+ * floor(log2 n); the default is (256, 1).
+ *
+ * libm_hip_tune: times every pair in {64, 128, 256, 512, 1024} x {1, 2, 4}
+ *   on the caller's buffers (4 launches each, HIP events on `stream`; it
+ *   waits for the stream), records the fastest for (fn, v, t, bucket of n)
+ *   and returns it.  The buffers are overwritten with valid results.
+ * libm_hip_tune_save / _load: the table as text lines "key bucket block packs";
+ *   the environment variable LIBM_HIP_TUNE_CACHE names a file loaded at the
+ *   first launch.  libm_hip_tune_reset restores the defaults.
+ * ---------------------------------------------------------------------- */
+libm_hip_status libm_hip_tune(libm_hip_fn fn, libm_hip_variant v, libm_hip_dtype t,
+                              const void* a, const void* b, void* out, size_t n, void* stream,
+                              int* best_block, int* best_packs);
+libm_hip_status libm_hip_tune_save(const char* path);
+libm_hip_status libm_hip_tune_load(const char* path);
+void libm_hip_tune_reset(void);
+
+/* ------------------------------------------------------------------------
  * Batched evaluation (not part of the paper): one persistent kernel, captured
  * once in a hip graph per plan, serves a list of requests of uneven lengths.
  * Results are bit-identical to the per-function entry points (same

@@ -325,3 +325,52 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# launch-shape autotuner
+# ---------------------------------------------------------------------------
+def _tune_lib():
+    lib = load()
+    if not getattr(lib, "_tune_ready", False):
+        vp = ctypes.c_void_p
+        lib.libm_hip_tune.restype = ctypes.c_int
+        lib.libm_hip_tune.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp,
+                                      ctypes.c_size_t, vp, ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_int)]
+        lib.libm_hip_tune_save.restype = ctypes.c_int
+        lib.libm_hip_tune_save.argtypes = [ctypes.c_char_p]
+        lib.libm_hip_tune_load.restype = ctypes.c_int
+        lib.libm_hip_tune_load.argtypes = [ctypes.c_char_p]
+        lib.libm_hip_tune_reset.restype = None
+        lib.libm_hip_tune_reset.argtypes = []
+        lib._tune_ready = True
+    return lib
+
+
+def tune(fn, a, b=None, variant=None, out=None, via_f64=False):
+    """Autotune the launch shape of ``fn`` for tensors like ``a`` (the
+    buffers are used for timing); returns (workgroup size, packs per lane)."""
+    import torch
+    lib = _tune_lib()
+    variant = variant or VARIANTS[fn][0]
+    tag = _dtype_tag(a, via_f64)
+    out = torch.empty_like(a) if out is None else out
+    blk, pk = ctypes.c_int(0), ctypes.c_int(0)
+    st = lib.libm_hip_tune(FN_CODES[fn], VARIANT_CODES[variant], DTYPE_CODES[tag], a.data_ptr(),
+                           None if b is None else b.data_ptr(), out.data_ptr(), a.numel(),
+                           _stream_handle(), ctypes.byref(blk), ctypes.byref(pk))
+    _check(st, "libm_hip_tune")
+    return blk.value, pk.value
+
+
+def tune_save(path):
+    _check(_tune_lib().libm_hip_tune_save(os.fsencode(path)), "libm_hip_tune_save")
+
+
+def tune_load(path):
+    _check(_tune_lib().libm_hip_tune_load(os.fsencode(path)), "libm_hip_tune_load")
+
+
+def tune_reset():
+    _tune_lib().libm_hip_tune_reset()

@@ -179,27 +179,43 @@ LMH_INLINE fff quadrant_to_half_periodf(fff r, float k, float& j) {
 
 constexpr float CWF_LIMIT = 65536.0f;
 
-LMH_INLINE fff sincosf_reduce(float x, bool is_cos, float& j) {
+struct Trig32 {
   fff r;
-  if (fabs_(x) < CWF_LIMIT) {
-    float q;
-    if (is_cos) {
-      q = 2.0f * rint_(fma_(x, INV_PI_F, -0.5f)) + 1.0f;
-      r = cwf_reduce(x, q, PIH_F_0, PIH_F_1, PIH_F_2, PIH_F_3);
-      j = (q - 1.0f) * 0.5f + 1.0f;
-    } else {
-      q = rint_(x * INV_PI_F);
-      r = cwf_reduce(x, q, PI_F_0, PI_F_1, PI_F_2, PI_F_3);
-      j = q;
-    }
+  float j;
+};
+
+LMH_INLINE bool trigf_slow(float x) { return !(fabs_(x) < CWF_LIMIT); }
+
+LMH_INLINE Trig32 sincosf_fast(float x, bool is_cos) {
+  float q, j;
+  if (is_cos) {
+    q = 2.0f * rint_(fma_(x, INV_PI_F, -0.5f)) + 1.0f;
+    j = (q - 1.0f) * 0.5f + 1.0f;
   } else {
-    float k;
-    r = phf_reduce_signed(x, k);
-    if (is_cos) k += 1.0f;
-    r = quadrant_to_half_periodf(r, k, j);
-    r.hi = isfinite_(x) ? r.hi : __builtin_nanf("");
+    q = rint_(x * INV_PI_F);
+    j = q;
   }
-  return r;
+  fff r = is_cos ? cwf_reduce(x, q, PIH_F_0, PIH_F_1, PIH_F_2, PIH_F_3)
+                 : cwf_reduce(x, q, PI_F_0, PI_F_1, PI_F_2, PI_F_3);
+  return Trig32{r, j};
+}
+
+LMH_INLINE Trig32 sincosf_slow(float x, bool is_cos) {
+  float k, j;
+  fff r = phf_reduce_signed(x, k);
+  if (is_cos) k += 1.0f;
+  r = quadrant_to_half_periodf(r, k, j);
+  r.hi = isfinite_(x) ? r.hi : __builtin_nanf("");
+  return Trig32{r, j};
+}
+
+LMH_INLINE Trig32 sincosf_reduce(float x, bool is_cos) {
+  Trig32 s;
+  if (trigf_slow(x))
+    s = sincosf_slow(x, is_cos);
+  else
+    s = sincosf_fast(x, is_cos);
+  return s;
 }
 
 LMH_INLINE float sinf_poly_u10(fff r) {
@@ -221,59 +237,60 @@ LMH_INLINE float sinf_poly_u35(float r) {
   return fma_(r * z, poly_estrin(z, SIN_S_F32), r);
 }
 
-LMH_INLINE float sinf_u10(float x) {
-  float j;
-  fff r = sincosf_reduce(x, false, j);
-  float s = sinf_poly_u10(r);
-  s = is_odd_intf(j) ? -s : s;
-  return x == 0.0f ? x : s;
+LMH_INLINE float sinf_finish_u10(float x, Trig32 s) {
+  float v = sinf_poly_u10(s.r);
+  v = is_odd_intf(s.j) ? -v : v;
+  return x == 0.0f ? x : v;
+}
+LMH_INLINE float cosf_finish_u10(float x, Trig32 s) {
+  float v = sinf_poly_u10(s.r);
+  return is_odd_intf(s.j) ? -v : v;
+}
+LMH_INLINE float sinf_finish_u35(float x, Trig32 s) {
+  float v = sinf_poly_u35(s.r.hi + s.r.lo);
+  v = is_odd_intf(s.j) ? -v : v;
+  return x == 0.0f ? x : v;
+}
+LMH_INLINE float cosf_finish_u35(float x, Trig32 s) {
+  float v = sinf_poly_u35(s.r.hi + s.r.lo);
+  return is_odd_intf(s.j) ? -v : v;
 }
 
-LMH_INLINE float cosf_u10(float x) {
-  float j;
-  fff r = sincosf_reduce(x, true, j);
-  float s = sinf_poly_u10(r);
-  return is_odd_intf(j) ? -s : s;
+LMH_INLINE float sinf_u10(float x) { return sinf_finish_u10(x, sincosf_reduce(x, false)); }
+LMH_INLINE float cosf_u10(float x) { return cosf_finish_u10(x, sincosf_reduce(x, true)); }
+LMH_INLINE float sinf_u35(float x) { return sinf_finish_u35(x, sincosf_reduce(x, false)); }
+LMH_INLINE float cosf_u35(float x) { return cosf_finish_u35(x, sincosf_reduce(x, true)); }
+
+LMH_INLINE Trig32 tanf_fast(float x) {
+  float k = rint_(x * TWO_OVER_PI_F);
+  return Trig32{cwf_reduce(x, k, PIH_F_0, PIH_F_1, PIH_F_2, PIH_F_3), k};
 }
 
-LMH_INLINE float sinf_u35(float x) {
-  float j;
-  fff r = sincosf_reduce(x, false, j);
-  float s = sinf_poly_u35(r.hi + r.lo);
-  s = is_odd_intf(j) ? -s : s;
-  return x == 0.0f ? x : s;
-}
-
-LMH_INLINE float cosf_u35(float x) {
-  float j;
-  fff r = sincosf_reduce(x, true, j);
-  float s = sinf_poly_u35(r.hi + r.lo);
-  return is_odd_intf(j) ? -s : s;
-}
-
-LMH_INLINE fff tanf_reduce(float x, float& k) {
-  fff r;
-  if (fabs_(x) < CWF_LIMIT) {
-    k = rint_(x * TWO_OVER_PI_F);
-    r = cwf_reduce(x, k, PIH_F_0, PIH_F_1, PIH_F_2, PIH_F_3);
-  } else {
-    r = phf_reduce_signed(x, k);
-    r.hi = isfinite_(x) ? r.hi : __builtin_nanf("");
-  }
-  return r;
-}
-
-LMH_INLINE fff tanf_ff(float x) {
+LMH_INLINE Trig32 tanf_slow(float x) {
   float k;
-  fff r = tanf_reduce(x, k);
-  fff y = dd2_scale(r, 0.5f);
+  fff r = phf_reduce_signed(x, k);
+  r.hi = isfinite_(x) ? r.hi : __builtin_nanf("");
+  return Trig32{r, k};
+}
+
+LMH_INLINE Trig32 tanf_reduce(float x) {
+  Trig32 s;
+  if (trigf_slow(x))
+    s = tanf_slow(x);
+  else
+    s = tanf_fast(x);
+  return s;
+}
+
+LMH_INLINE fff tanf_ff_finish(float x, Trig32 s) {
+  fff y = dd2_scale(s.r, 0.5f);
   float z = y.hi * y.hi;
   float tp = poly_estrin(z, TAN_T_F32);
   fff y3 = dd2_mul(dd2_squ(y), y);
   fff t = dd2_add(y, dd2_mul(y3, tp));
   fff num = dd2_scale(t, 2.0f);
   fff den = dd2_add(1.0f, dd2_neg(dd2_squ(t)));
-  if (is_odd_intf(k)) {
+  if (is_odd_intf(s.j)) {
     fff tmp = num;
     num = den;
     den = dd2_neg(tmp);
@@ -282,25 +299,28 @@ LMH_INLINE fff tanf_ff(float x) {
   return fabs_(x) < 0x1p-12f ? mk(x, 0.0f) : q;
 }
 
-LMH_INLINE float tanf_u10(float x) {
-  fff q = tanf_ff(x);
+LMH_INLINE fff tanf_ff(float x) { return tanf_ff_finish(x, tanf_reduce(x)); }
+
+LMH_INLINE float tanf_finish_u10(float x, Trig32 s) {
+  fff q = tanf_ff_finish(x, s);
   return fabs_(x) < 0x1p-12f ? x : q.hi + q.lo;
 }
 
-LMH_INLINE float tanf_u35(float x) {
-  float k;
-  fff r = tanf_reduce(x, k);
-  float y = (r.hi + r.lo) * 0.5f;
+LMH_INLINE float tanf_finish_u35(float x, Trig32 s) {
+  float y = (s.r.hi + s.r.lo) * 0.5f;
   float z = y * y;
   float t = fma_(y * z, poly_estrin(z, TAN_T_F32), y);
   float num = t + t;
   float den = fma_(-t, t, 1.0f);
-  bool odd = is_odd_intf(k);
+  bool odd = is_odd_intf(s.j);
   float n2 = odd ? den : num;
   float d2 = odd ? -num : den;
   float res = n2 / d2;
   return fabs_(x) < 0x1p-12f ? x : res;
 }
+
+LMH_INLINE float tanf_u10(float x) { return tanf_finish_u10(x, tanf_reduce(x)); }
+LMH_INLINE float tanf_u35(float x) { return tanf_finish_u35(x, tanf_reduce(x)); }
 
 // ---------------------------------------------------------------------------
 // pow, atan2

@@ -9,8 +9,11 @@
 // GPU lane, and its conditional moves become exec-masked selects.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+#include <mutex>
 #include <stdint.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include "ops.h"
@@ -27,9 +30,58 @@ void set_error(const char* msg) {
 }
 
 // ---------------------------------------------------------------------------
+// launch configurations (autotuned)
+// ---------------------------------------------------------------------------
+// A launch is (workgroup size, packs per lane); a pack is 16 bytes of each
+// operand.  The table holds the tuned choice per entry point and size bucket
+// floor(log2 n); 0 means the default (256, 1).  Keys: (fn * 4 + variant) * 8
+// + dtype, variant 3 = backward.
+constexpr int NBUCKET = 48;
+constexpr int NKEY = LIBM_HIP_NUM_FN * 4 * 8;
+std::atomic<int> g_tune[NKEY][NBUCKET];
+thread_local int g_force_cfg = 0;             // set only while tuning
+std::once_flag g_tune_env_once;
+
+struct Cfg {
+  int block, packs;
+};
+inline int tune_key(int fn, int v, int t) { return (fn * 4 + v) * 8 + t; }
+inline int nbucket(size_t n) {
+  int b = 63 - __builtin_clzll((unsigned long long)n | 1ull);
+  return b < NBUCKET ? b : NBUCKET - 1;
+}
+inline Cfg unpack_cfg(int v) { return v ? Cfg{v & 0xffff, v >> 16} : Cfg{256, 1}; }
+int load_tune_file(const char* path);
+inline Cfg pick_cfg(int key, size_t n) {
+  std::call_once(g_tune_env_once, [] {
+    const char* p = getenv("LIBM_HIP_TUNE_CACHE");
+    if (p && *p) load_tune_file(p);
+  });
+  if (g_force_cfg) return unpack_cfg(g_force_cfg);
+  if (key < 0 || key >= NKEY) return Cfg{256, 1};
+  return unpack_cfg(g_tune[key][nbucket(n)].load(std::memory_order_relaxed));
+}
+
+int load_tune_file(const char* path) {
+  FILE* f = fopen(path, "r");
+  if (!f) return -1;
+  int key, b, blk, pk, count = 0;
+  while (fscanf(f, "%d %d %d %d", &key, &b, &blk, &pk) == 4) {
+    bool okb = blk == 64 || blk == 128 || blk == 256 || blk == 512 || blk == 1024;
+    if (key >= 0 && key < NKEY && b >= 0 && b < NBUCKET && okb && pk >= 1 && pk <= 8) {
+      g_tune[key][b].store(blk | (pk << 16), std::memory_order_relaxed);
+      ++count;
+    }
+  }
+  fclose(f);
+  return count;
+}
+
+// ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
-constexpr int BLOCK = 256;
+constexpr int BLOCK = 256;          // workgroup of the gathered-trig kernels
+constexpr int MAX_BLOCK = 1024;
 
 // 16 bytes of one operand for one lane; moved as a 128-bit vector so that the
 // store can carry the non-temporal hint
@@ -45,82 +97,177 @@ __device__ __forceinline__ void store_nt(const P& v, void* dst) {
   __builtin_nontemporal_store(__builtin_bit_cast(u32x4, v), reinterpret_cast<u32x4*>(dst));
 }
 
+// Each workgroup covers blockDim.x * packs packs; pack u of a lane is
+// (block_base + u * blockDim.x + lane), so every iteration is one fully
+// coalesced workgroup-wide access.
 template <class Io, class Op, int EPT, bool VEC>
-__global__ __launch_bounds__(BLOCK) void k_unary(const typename Io::S* __restrict__ x,
-                                                 typename Io::S* __restrict__ y, size_t n) {
+__global__ __launch_bounds__(MAX_BLOCK) void k_unary(const typename Io::S* __restrict__ x,
+                                                     typename Io::S* __restrict__ y, size_t n,
+                                                     int packs) {
   typedef typename Io::S S;
-  size_t base = ((size_t)blockIdx.x * BLOCK + threadIdx.x) * EPT;
-  if (base >= n) return;
-  if (VEC && base + EPT <= n) {
-    Pack<S, EPT> in = *reinterpret_cast<const Pack<S, EPT>*>(x + base);
-    Pack<S, EPT> out;
+  size_t pk0 = (size_t)blockIdx.x * blockDim.x * packs + threadIdx.x;
+  for (int u = 0; u < packs; ++u) {
+    size_t base = (pk0 + (size_t)u * blockDim.x) * EPT;
+    if (base >= n) return;
+    if (VEC && base + EPT <= n) {
+      Pack<S, EPT> in = *reinterpret_cast<const Pack<S, EPT>*>(x + base);
+      Pack<S, EPT> out;
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) out.v[i] = Io::out(Op::f(Io::in(in.v[i])));
-    store_nt(out, y + base);
-  } else {
+      for (int i = 0; i < EPT; ++i) out.v[i] = Io::out(Op::f(Io::in(in.v[i])));
+      store_nt(out, y + base);
+    } else {
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      if (base + i < n) y[base + i] = Io::out(Op::f(Io::in(x[base + i])));
+      for (int i = 0; i < EPT; ++i) {
+        if (base + i < n) y[base + i] = Io::out(Op::f(Io::in(x[base + i])));
+      }
     }
   }
 }
 
 template <class Io, class Op, int EPT, bool VEC>
-__global__ __launch_bounds__(BLOCK) void k_binary(const typename Io::S* __restrict__ a,
-                                                  const typename Io::S* __restrict__ b,
-                                                  typename Io::S* __restrict__ y, size_t n) {
+__global__ __launch_bounds__(MAX_BLOCK) void k_binary(const typename Io::S* __restrict__ a,
+                                                      const typename Io::S* __restrict__ b,
+                                                      typename Io::S* __restrict__ y, size_t n,
+                                                      int packs) {
   typedef typename Io::S S;
-  size_t base = ((size_t)blockIdx.x * BLOCK + threadIdx.x) * EPT;
-  if (base >= n) return;
-  if (VEC && base + EPT <= n) {
-    Pack<S, EPT> ia = *reinterpret_cast<const Pack<S, EPT>*>(a + base);
-    Pack<S, EPT> ib = *reinterpret_cast<const Pack<S, EPT>*>(b + base);
-    Pack<S, EPT> out;
+  size_t pk0 = (size_t)blockIdx.x * blockDim.x * packs + threadIdx.x;
+  for (int u = 0; u < packs; ++u) {
+    size_t base = (pk0 + (size_t)u * blockDim.x) * EPT;
+    if (base >= n) return;
+    if (VEC && base + EPT <= n) {
+      Pack<S, EPT> ia = *reinterpret_cast<const Pack<S, EPT>*>(a + base);
+      Pack<S, EPT> ib = *reinterpret_cast<const Pack<S, EPT>*>(b + base);
+      Pack<S, EPT> out;
 #pragma unroll
-    for (int i = 0; i < EPT; ++i)
-      out.v[i] = Io::out(Op::f(Io::in(ia.v[i]), Io::in(ib.v[i])));
-    store_nt(out, y + base);
+      for (int i = 0; i < EPT; ++i)
+        out.v[i] = Io::out(Op::f(Io::in(ia.v[i]), Io::in(ib.v[i])));
+      store_nt(out, y + base);
+    } else {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        if (base + i < n) y[base + i] = Io::out(Op::f(Io::in(a[base + i]), Io::in(b[base + i])));
+      }
+    }
+  }
+}
+
+// Trigonometric kernel with the Payne-Hanek lanes gathered.  Each lane
+// classifies its elements; the Cody-Waite ones are reduced in place, the
+// others are appended to a workgroup queue in LDS (one LDS atomic per wave:
+// ballot, popcount, mbcnt) and reduced densely by all lanes after a barrier,
+// so a wave that holds a few large arguments no longer pays the whole
+// Payne-Hanek path.  The reduced states come back through LDS and every lane
+// finishes its own elements.
+__device__ __forceinline__ unsigned wave_reserve(bool pred, unsigned* counter) {
+  unsigned long long m = __ballot(pred);
+  unsigned pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                           __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+  unsigned base = 0;
+  if (m != 0ull) {
+    int leader = __ffsll((long long)m) - 1;
+    if (pred && pre == 0u) base = atomicAdd(counter, (unsigned)__popcll(m));
+    base = __shfl(base, leader);
+  }
+  return base + pre;
+}
+
+template <class Io, class Op, int EPT, bool VEC>
+__global__ __launch_bounds__(BLOCK) void k_unary_split(const typename Io::S* __restrict__ x,
+                                                       typename Io::S* __restrict__ y, size_t n) {
+  typedef typename Io::S S;
+  typedef typename Io::C C;
+  typedef decltype(Op::fast(C())) St;
+  __shared__ C q_x[BLOCK * EPT];
+  __shared__ unsigned short q_slot[BLOCK * EPT];
+  __shared__ St q_res[BLOCK * EPT];
+  __shared__ unsigned q_cnt;
+  if (threadIdx.x == 0) q_cnt = 0;
+  size_t base = ((size_t)blockIdx.x * BLOCK + threadIdx.x) * EPT;
+  C xv[EPT];
+  bool ok[EPT];
+  if (VEC && base + EPT <= n) {
+    Pack<S, EPT> in = *reinterpret_cast<const Pack<S, EPT>*>(x + base);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      xv[i] = Io::in(in.v[i]);
+      ok[i] = true;
+    }
   } else {
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      if (base + i < n) y[base + i] = Io::out(Op::f(Io::in(a[base + i]), Io::in(b[base + i])));
+      ok[i] = base + i < n;
+      xv[i] = ok[i] ? Io::in(x[base + i]) : C(0);
     }
+  }
+  __syncthreads();                                   // q_cnt is initialised
+  St st[EPT];
+  bool slow[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    slow[i] = ok[i] && Op::is_slow(xv[i]);
+    if (!slow[i]) st[i] = Op::fast(xv[i]);
+    unsigned pos = wave_reserve(slow[i], &q_cnt);
+    if (slow[i]) {
+      q_x[pos] = xv[i];
+      q_slot[pos] = (unsigned short)(threadIdx.x * EPT + i);
+    }
+  }
+  __syncthreads();
+  const unsigned cnt = q_cnt;
+  for (unsigned p = threadIdx.x; p < cnt; p += BLOCK) q_res[q_slot[p]] = Op::slow(q_x[p]);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < EPT; ++i)
+    if (slow[i]) st[i] = q_res[threadIdx.x * EPT + i];
+  if (VEC && base + EPT <= n) {
+    Pack<S, EPT> out;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) out.v[i] = Io::out(Op::finish(xv[i], st[i]));
+    store_nt(out, y + base);
+  } else {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i)
+      if (ok[i]) y[base + i] = Io::out(Op::finish(xv[i], st[i]));
   }
 }
 
 // three inputs, two outputs (backward of the binary functions)
 template <class Io, class Op, int EPT, bool VEC>
-__global__ __launch_bounds__(BLOCK) void k_ternary2(const typename Io::S* __restrict__ a,
-                                                    const typename Io::S* __restrict__ b,
-                                                    const typename Io::S* __restrict__ c,
-                                                    typename Io::S* __restrict__ y0,
-                                                    typename Io::S* __restrict__ y1, size_t n) {
+__global__ __launch_bounds__(MAX_BLOCK) void k_ternary2(const typename Io::S* __restrict__ a,
+                                                        const typename Io::S* __restrict__ b,
+                                                        const typename Io::S* __restrict__ c,
+                                                        typename Io::S* __restrict__ y0,
+                                                        typename Io::S* __restrict__ y1, size_t n,
+                                                        int packs) {
   typedef typename Io::S S;
   typedef typename Io::C C;
-  size_t base = ((size_t)blockIdx.x * BLOCK + threadIdx.x) * EPT;
-  if (base >= n) return;
-  if (VEC && base + EPT <= n) {
-    Pack<S, EPT> ia = *reinterpret_cast<const Pack<S, EPT>*>(a + base);
-    Pack<S, EPT> ib = *reinterpret_cast<const Pack<S, EPT>*>(b + base);
-    Pack<S, EPT> ic = *reinterpret_cast<const Pack<S, EPT>*>(c + base);
-    Pack<S, EPT> o0, o1;
+  size_t pk0 = (size_t)blockIdx.x * blockDim.x * packs + threadIdx.x;
+  for (int u = 0; u < packs; ++u) {
+    size_t base = (pk0 + (size_t)u * blockDim.x) * EPT;
+    if (base >= n) return;
+    if (VEC && base + EPT <= n) {
+      Pack<S, EPT> ia = *reinterpret_cast<const Pack<S, EPT>*>(a + base);
+      Pack<S, EPT> ib = *reinterpret_cast<const Pack<S, EPT>*>(b + base);
+      Pack<S, EPT> ic = *reinterpret_cast<const Pack<S, EPT>*>(c + base);
+      Pack<S, EPT> o0, o1;
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      C r0, r1;
-      Op::f(Io::in(ia.v[i]), Io::in(ib.v[i]), Io::in(ic.v[i]), r0, r1);
-      o0.v[i] = Io::out(r0);
-      o1.v[i] = Io::out(r1);
-    }
-    store_nt(o0, y0 + base);
-    store_nt(o1, y1 + base);
-  } else {
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      if (base + i < n) {
+      for (int i = 0; i < EPT; ++i) {
         C r0, r1;
-        Op::f(Io::in(a[base + i]), Io::in(b[base + i]), Io::in(c[base + i]), r0, r1);
-        y0[base + i] = Io::out(r0);
-        y1[base + i] = Io::out(r1);
+        Op::f(Io::in(ia.v[i]), Io::in(ib.v[i]), Io::in(ic.v[i]), r0, r1);
+        o0.v[i] = Io::out(r0);
+        o1.v[i] = Io::out(r1);
+      }
+      store_nt(o0, y0 + base);
+      store_nt(o1, y1 + base);
+    } else {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        if (base + i < n) {
+          C r0, r1;
+          Op::f(Io::in(a[base + i]), Io::in(b[base + i]), Io::in(c[base + i]), r0, r1);
+          y0[base + i] = Io::out(r0);
+          y1[base + i] = Io::out(r1);
+        }
       }
     }
   }
@@ -132,8 +279,32 @@ constexpr int ept_for() { return 16 / (int)sizeof(S); }
 
 inline bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
+inline libm_hip_status launch_error(const char* name) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    char buf[200];
+    snprintf(buf, sizeof(buf), "libm_hip: %s launch failed: %s", name, hipGetErrorString(e));
+    set_error(buf);
+    return LIBM_HIP_ERR_HIP;
+  }
+  return LIBM_HIP_OK;
+}
+
+// grid for n elements, EPT per pack, cfg.packs packs per lane
+inline bool grid_for(size_t n, int ept, Cfg c, unsigned& blocks) {
+  size_t per_block = (size_t)c.block * c.packs * ept;
+  size_t b = (n + per_block - 1) / per_block;
+  if (b > 0x7fffffffull) {
+    set_error("libm_hip: n too large for one launch");
+    return false;
+  }
+  blocks = (unsigned)b;
+  return true;
+}
+
 template <class Io, class Op>
-libm_hip_status launch_unary(const void* x, void* y, size_t n, void* stream, const char* name) {
+libm_hip_status launch_unary(const void* x, void* y, size_t n, void* stream, const char* name,
+                             int key) {
   if (n == 0) return LIBM_HIP_OK;
   if (!x || !y) {
     set_error("libm_hip: NULL pointer with n > 0");
@@ -141,32 +312,32 @@ libm_hip_status launch_unary(const void* x, void* y, size_t n, void* stream, con
   }
   typedef typename Io::S S;
   constexpr int EPT = ept_for<S>();
-  size_t per_block = (size_t)BLOCK * EPT;
-  size_t blocks = (n + per_block - 1) / per_block;
-  if (blocks > 0x7fffffffull) {
-    set_error("libm_hip: n too large for one launch");
-    return LIBM_HIP_ERR_INVALID;
-  }
   hipStream_t s = (hipStream_t)stream;
   const S* xs = (const S*)x;
   S* ys = (S*)y;
-  if (aligned16(x) && aligned16(y))
-    hipLaunchKernelGGL((k_unary<Io, Op, EPT, true>), dim3((unsigned)blocks), dim3(BLOCK), 0, s, xs, ys, n);
-  else
-    hipLaunchKernelGGL((k_unary<Io, Op, EPT, false>), dim3((unsigned)blocks), dim3(BLOCK), 0, s, xs, ys, n);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) {
-    char buf[200];
-    snprintf(buf, sizeof(buf), "libm_hip: %s launch failed: %s", name, hipGetErrorString(e));
-    set_error(buf);
-    return LIBM_HIP_ERR_HIP;
+  bool vec = aligned16(x) && aligned16(y);
+  unsigned blocks;
+  if constexpr (Op::kSplit) {
+    // the gathering kernel sizes its LDS queue to a 256-lane workgroup
+    if (!grid_for(n, EPT, Cfg{BLOCK, 1}, blocks)) return LIBM_HIP_ERR_INVALID;
+    if (vec)
+      hipLaunchKernelGGL((k_unary_split<Io, Op, EPT, true>), dim3(blocks), dim3(BLOCK), 0, s, xs, ys, n);
+    else
+      hipLaunchKernelGGL((k_unary_split<Io, Op, EPT, false>), dim3(blocks), dim3(BLOCK), 0, s, xs, ys, n);
+  } else {
+    Cfg c = pick_cfg(key, n);
+    if (!grid_for(n, EPT, c, blocks)) return LIBM_HIP_ERR_INVALID;
+    if (vec)
+      hipLaunchKernelGGL((k_unary<Io, Op, EPT, true>), dim3(blocks), dim3(c.block), 0, s, xs, ys, n, c.packs);
+    else
+      hipLaunchKernelGGL((k_unary<Io, Op, EPT, false>), dim3(blocks), dim3(c.block), 0, s, xs, ys, n, c.packs);
   }
-  return LIBM_HIP_OK;
+  return launch_error(name);
 }
 
 template <class Io, class Op>
 libm_hip_status launch_binary(const void* a, const void* b, void* y, size_t n, void* stream,
-                              const char* name) {
+                              const char* name, int key) {
   if (n == 0) return LIBM_HIP_OK;
   if (!a || !b || !y) {
     set_error("libm_hip: NULL pointer with n > 0");
@@ -174,33 +345,23 @@ libm_hip_status launch_binary(const void* a, const void* b, void* y, size_t n, v
   }
   typedef typename Io::S S;
   constexpr int EPT = ept_for<S>();
-  size_t per_block = (size_t)BLOCK * EPT;
-  size_t blocks = (n + per_block - 1) / per_block;
-  if (blocks > 0x7fffffffull) {
-    set_error("libm_hip: n too large for one launch");
-    return LIBM_HIP_ERR_INVALID;
-  }
+  Cfg c = pick_cfg(key, n);
+  unsigned blocks;
+  if (!grid_for(n, EPT, c, blocks)) return LIBM_HIP_ERR_INVALID;
   hipStream_t s = (hipStream_t)stream;
   const S* as = (const S*)a;
   const S* bs = (const S*)b;
   S* ys = (S*)y;
   if (aligned16(a) && aligned16(b) && aligned16(y))
-    hipLaunchKernelGGL((k_binary<Io, Op, EPT, true>), dim3((unsigned)blocks), dim3(BLOCK), 0, s, as, bs, ys, n);
+    hipLaunchKernelGGL((k_binary<Io, Op, EPT, true>), dim3(blocks), dim3(c.block), 0, s, as, bs, ys, n, c.packs);
   else
-    hipLaunchKernelGGL((k_binary<Io, Op, EPT, false>), dim3((unsigned)blocks), dim3(BLOCK), 0, s, as, bs, ys, n);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) {
-    char buf[200];
-    snprintf(buf, sizeof(buf), "libm_hip: %s launch failed: %s", name, hipGetErrorString(e));
-    set_error(buf);
-    return LIBM_HIP_ERR_HIP;
-  }
-  return LIBM_HIP_OK;
+    hipLaunchKernelGGL((k_binary<Io, Op, EPT, false>), dim3(blocks), dim3(c.block), 0, s, as, bs, ys, n, c.packs);
+  return launch_error(name);
 }
 
 template <class Io, class Op>
 libm_hip_status launch_ternary2(const void* a, const void* b, const void* c, void* y0, void* y1,
-                                size_t n, void* stream, const char* name) {
+                                size_t n, void* stream, const char* name, int key) {
   if (n == 0) return LIBM_HIP_OK;
   if (!a || !b || !c || !y0 || !y1) {
     set_error("libm_hip: NULL pointer with n > 0");
@@ -208,27 +369,17 @@ libm_hip_status launch_ternary2(const void* a, const void* b, const void* c, voi
   }
   typedef typename Io::S S;
   constexpr int EPT = ept_for<S>();
-  size_t per_block = (size_t)BLOCK * EPT;
-  size_t blocks = (n + per_block - 1) / per_block;
-  if (blocks > 0x7fffffffull) {
-    set_error("libm_hip: n too large for one launch");
-    return LIBM_HIP_ERR_INVALID;
-  }
+  Cfg cf = pick_cfg(key, n);
+  unsigned blocks;
+  if (!grid_for(n, EPT, cf, blocks)) return LIBM_HIP_ERR_INVALID;
   hipStream_t s = (hipStream_t)stream;
   const S *as = (const S*)a, *bs = (const S*)b, *cs = (const S*)c;
   S *o0 = (S*)y0, *o1 = (S*)y1;
   if (aligned16(a) && aligned16(b) && aligned16(c) && aligned16(y0) && aligned16(y1))
-    hipLaunchKernelGGL((k_ternary2<Io, Op, EPT, true>), dim3((unsigned)blocks), dim3(BLOCK), 0, s, as, bs, cs, o0, o1, n);
+    hipLaunchKernelGGL((k_ternary2<Io, Op, EPT, true>), dim3(blocks), dim3(cf.block), 0, s, as, bs, cs, o0, o1, n, cf.packs);
   else
-    hipLaunchKernelGGL((k_ternary2<Io, Op, EPT, false>), dim3((unsigned)blocks), dim3(BLOCK), 0, s, as, bs, cs, o0, o1, n);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) {
-    char buf[200];
-    snprintf(buf, sizeof(buf), "libm_hip: %s launch failed: %s", name, hipGetErrorString(e));
-    set_error(buf);
-    return LIBM_HIP_ERR_HIP;
-  }
-  return LIBM_HIP_OK;
+    hipLaunchKernelGGL((k_ternary2<Io, Op, EPT, false>), dim3(blocks), dim3(cf.block), 0, s, as, bs, cs, o0, o1, n, cf.packs);
+  return launch_error(name);
 }
 
 }  // namespace
@@ -241,67 +392,69 @@ extern "C" {
 const char* libm_hip_last_error(void) { return g_last_error; }
 const char* libm_hip_version(void) { return "libm_hip 0.1 (gfx950)"; }
 
-#define LMH_DEF_UNARY(fn, var, Op)                                                              \
+#define LMH_KEY(FN, V, T) tune_key(LIBM_HIP_##FN, LIBM_HIP_##V, LIBM_HIP_##T)
+#define LMH_DEF_UNARY(fn, var, Op, FN, V)                                                       \
   libm_hip_status libm_hip_##fn##_##var##_f64(const double* x, double* y, size_t n, void* s) { \
-    return launch_unary<IoF64, Op>(x, y, n, s, #fn "_" #var "_f64");                           \
+    return launch_unary<IoF64, Op>(x, y, n, s, #fn "_" #var "_f64", LMH_KEY(FN, V, F64));      \
   }                                                                                             \
   libm_hip_status libm_hip_##fn##_##var##_f32(const float* x, float* y, size_t n, void* s) {   \
-    return launch_unary<IoF32, Op>(x, y, n, s, #fn "_" #var "_f32");                           \
+    return launch_unary<IoF32, Op>(x, y, n, s, #fn "_" #var "_f32", LMH_KEY(FN, V, F32));      \
   }
-#define LMH_DEF_UNARY_HALF(fn, Op)                                                                  \
+#define LMH_DEF_UNARY_HALF(fn, Op, FN)                                                              \
   libm_hip_status libm_hip_##fn##_u10_bf16(const uint16_t* x, uint16_t* y, size_t n, void* s) {  \
-    return launch_unary<IoBF16, Op>(x, y, n, s, #fn "_u10_bf16");                                \
+    return launch_unary<IoBF16, Op>(x, y, n, s, #fn "_u10_bf16", LMH_KEY(FN, U10, BF16));        \
   }                                                                                               \
   libm_hip_status libm_hip_##fn##_u10_f16(const uint16_t* x, uint16_t* y, size_t n, void* s) {   \
-    return launch_unary<IoF16, Op>(x, y, n, s, #fn "_u10_f16");                                  \
+    return launch_unary<IoF16, Op>(x, y, n, s, #fn "_u10_f16", LMH_KEY(FN, U10, F16));           \
   }                                                                                               \
   libm_hip_status libm_hip_##fn##_u10_f32_via_f64(const float* x, float* y, size_t n, void* s) { \
-    return launch_unary<IoF32ViaF64, Op>(x, y, n, s, #fn "_u10_f32_via_f64");                    \
+    return launch_unary<IoF32ViaF64, Op>(x, y, n, s, #fn "_u10_f32_via_f64",                     \
+                                         LMH_KEY(FN, U10, F32_VIA_F64));                         \
   }
 
-LMH_DEF_UNARY(sin, u10, OpSinU10)
-LMH_DEF_UNARY(sin, u35, OpSinU35)
-LMH_DEF_UNARY(cos, u10, OpCosU10)
-LMH_DEF_UNARY(cos, u35, OpCosU35)
-LMH_DEF_UNARY(tan, u10, OpTanU10)
-LMH_DEF_UNARY(tan, u35, OpTanU35)
-LMH_DEF_UNARY(exp, u10, OpExpU10)
-LMH_DEF_UNARY(exp2, u10, OpExp2U10)
-LMH_DEF_UNARY(log, u10, OpLogU10)
-LMH_DEF_UNARY(log2, u10, OpLog2U10)
-LMH_DEF_UNARY(sinh, u10, OpSinhU10)
-LMH_DEF_UNARY(cosh, u10, OpCoshU10)
-LMH_DEF_UNARY(tanh, u10, OpTanhU10)
-LMH_DEF_UNARY_HALF(sin, OpSinU10)
-LMH_DEF_UNARY_HALF(cos, OpCosU10)
-LMH_DEF_UNARY_HALF(tan, OpTanU10)
-LMH_DEF_UNARY_HALF(exp, OpExpU10)
-LMH_DEF_UNARY_HALF(exp2, OpExp2U10)
-LMH_DEF_UNARY_HALF(log, OpLogU10)
-LMH_DEF_UNARY_HALF(log2, OpLog2U10)
-LMH_DEF_UNARY_HALF(sinh, OpSinhU10)
-LMH_DEF_UNARY_HALF(cosh, OpCoshU10)
-LMH_DEF_UNARY_HALF(tanh, OpTanhU10)
+LMH_DEF_UNARY(sin, u10, OpSinU10, SIN, U10)
+LMH_DEF_UNARY(sin, u35, OpSinU35, SIN, U35)
+LMH_DEF_UNARY(cos, u10, OpCosU10, COS, U10)
+LMH_DEF_UNARY(cos, u35, OpCosU35, COS, U35)
+LMH_DEF_UNARY(tan, u10, OpTanU10, TAN, U10)
+LMH_DEF_UNARY(tan, u35, OpTanU35, TAN, U35)
+LMH_DEF_UNARY(exp, u10, OpExpU10, EXP, U10)
+LMH_DEF_UNARY(exp2, u10, OpExp2U10, EXP2, U10)
+LMH_DEF_UNARY(log, u10, OpLogU10, LOG, U10)
+LMH_DEF_UNARY(log2, u10, OpLog2U10, LOG2, U10)
+LMH_DEF_UNARY(sinh, u10, OpSinhU10, SINH, U10)
+LMH_DEF_UNARY(cosh, u10, OpCoshU10, COSH, U10)
+LMH_DEF_UNARY(tanh, u10, OpTanhU10, TANH, U10)
+LMH_DEF_UNARY_HALF(sin, OpSinU10, SIN)
+LMH_DEF_UNARY_HALF(cos, OpCosU10, COS)
+LMH_DEF_UNARY_HALF(tan, OpTanU10, TAN)
+LMH_DEF_UNARY_HALF(exp, OpExpU10, EXP)
+LMH_DEF_UNARY_HALF(exp2, OpExp2U10, EXP2)
+LMH_DEF_UNARY_HALF(log, OpLogU10, LOG)
+LMH_DEF_UNARY_HALF(log2, OpLog2U10, LOG2)
+LMH_DEF_UNARY_HALF(sinh, OpSinhU10, SINH)
+LMH_DEF_UNARY_HALF(cosh, OpCoshU10, COSH)
+LMH_DEF_UNARY_HALF(tanh, OpTanhU10, TANH)
 
-#define LMH_DEF_BINARY(fn, var, Io, T, tag, Op)                                                   \
+#define LMH_DEF_BINARY(fn, var, Io, T, tag, Op, KEY)                                              \
   libm_hip_status libm_hip_##fn##var##_##tag(const T* a, const T* b, T* out, size_t n, void* s) { \
-    return launch_binary<Io, Op>(a, b, out, n, s, #fn #var "_" #tag);                            \
+    return launch_binary<Io, Op>(a, b, out, n, s, #fn #var "_" #tag, KEY);                       \
   }
 
-LMH_DEF_BINARY(pow, _u10, IoF64, double, f64, OpPowU10)
-LMH_DEF_BINARY(pow, _u10, IoF32, float, f32, OpPowU10)
-LMH_DEF_BINARY(pow, _u10, IoBF16, uint16_t, bf16, OpPowU10)
-LMH_DEF_BINARY(pow, _u10, IoF16, uint16_t, f16, OpPowU10)
-LMH_DEF_BINARY(pow, _u10, IoF32ViaF64, float, f32_via_f64, OpPowU10)
-LMH_DEF_BINARY(atan2, _u10, IoF64, double, f64, OpAtan2U10)
-LMH_DEF_BINARY(atan2, _u10, IoF32, float, f32, OpAtan2U10)
-LMH_DEF_BINARY(atan2, _u10, IoBF16, uint16_t, bf16, OpAtan2U10)
-LMH_DEF_BINARY(atan2, _u10, IoF16, uint16_t, f16, OpAtan2U10)
-LMH_DEF_BINARY(atan2, _u10, IoF32ViaF64, float, f32_via_f64, OpAtan2U10)
-LMH_DEF_BINARY(fmod, , IoF64, double, f64, OpFmod)
-LMH_DEF_BINARY(fmod, , IoF32, float, f32, OpFmod)
-LMH_DEF_BINARY(remainder, , IoF64, double, f64, OpRemainder)
-LMH_DEF_BINARY(remainder, , IoF32, float, f32, OpRemainder)
+LMH_DEF_BINARY(pow, _u10, IoF64, double, f64, OpPowU10, LMH_KEY(POW, U10, F64))
+LMH_DEF_BINARY(pow, _u10, IoF32, float, f32, OpPowU10, LMH_KEY(POW, U10, F32))
+LMH_DEF_BINARY(pow, _u10, IoBF16, uint16_t, bf16, OpPowU10, LMH_KEY(POW, U10, BF16))
+LMH_DEF_BINARY(pow, _u10, IoF16, uint16_t, f16, OpPowU10, LMH_KEY(POW, U10, F16))
+LMH_DEF_BINARY(pow, _u10, IoF32ViaF64, float, f32_via_f64, OpPowU10, LMH_KEY(POW, U10, F32_VIA_F64))
+LMH_DEF_BINARY(atan2, _u10, IoF64, double, f64, OpAtan2U10, LMH_KEY(ATAN2, U10, F64))
+LMH_DEF_BINARY(atan2, _u10, IoF32, float, f32, OpAtan2U10, LMH_KEY(ATAN2, U10, F32))
+LMH_DEF_BINARY(atan2, _u10, IoBF16, uint16_t, bf16, OpAtan2U10, LMH_KEY(ATAN2, U10, BF16))
+LMH_DEF_BINARY(atan2, _u10, IoF16, uint16_t, f16, OpAtan2U10, LMH_KEY(ATAN2, U10, F16))
+LMH_DEF_BINARY(atan2, _u10, IoF32ViaF64, float, f32_via_f64, OpAtan2U10, LMH_KEY(ATAN2, U10, F32_VIA_F64))
+LMH_DEF_BINARY(fmod, , IoF64, double, f64, OpFmod, LMH_KEY(FMOD, EXACT, F64))
+LMH_DEF_BINARY(fmod, , IoF32, float, f32, OpFmod, LMH_KEY(FMOD, EXACT, F32))
+LMH_DEF_BINARY(remainder, , IoF64, double, f64, OpRemainder, LMH_KEY(REMAINDER, EXACT, F64))
+LMH_DEF_BINARY(remainder, , IoF32, float, f32, OpRemainder, LMH_KEY(REMAINDER, EXACT, F32))
 
 }  // extern "C"
 
@@ -309,37 +462,41 @@ LMH_DEF_BINARY(remainder, , IoF32, float, f32, OpRemainder)
 // backward entry points
 // ---------------------------------------------------------------------------
 extern "C" {
-#define LMH_DEF_BWD(fn, Op)                                                                        \
+#define LMH_DEF_BWD(fn, Op, FN)                                                                      \
   libm_hip_status libm_hip_##fn##_u10_f64_bwd(const double* x, const double* gy, double* gx,     \
                                                size_t n, void* s) {                                \
-    return launch_binary<IoF64, Op>(x, gy, gx, n, s, #fn "_u10_f64_bwd");                          \
+    return launch_binary<IoF64, Op>(x, gy, gx, n, s, #fn "_u10_f64_bwd", tune_key(FN, 3, 0));      \
   }                                                                                                \
   libm_hip_status libm_hip_##fn##_u10_f32_bwd(const float* x, const float* gy, float* gx,        \
                                                size_t n, void* s) {                                \
-    return launch_binary<IoF32, Op>(x, gy, gx, n, s, #fn "_u10_f32_bwd");                          \
+    return launch_binary<IoF32, Op>(x, gy, gx, n, s, #fn "_u10_f32_bwd", tune_key(FN, 3, 1));      \
   }
-LMH_DEF_BWD(sin, OpSinBwd)
-LMH_DEF_BWD(cos, OpCosBwd)
-LMH_DEF_BWD(tan, OpTanBwd)
-LMH_DEF_BWD(exp, OpExpBwd)
-LMH_DEF_BWD(log, OpLogBwd)
-LMH_DEF_BWD(tanh, OpTanhBwd)
+LMH_DEF_BWD(sin, OpSinBwd, LIBM_HIP_SIN)
+LMH_DEF_BWD(cos, OpCosBwd, LIBM_HIP_COS)
+LMH_DEF_BWD(tan, OpTanBwd, LIBM_HIP_TAN)
+LMH_DEF_BWD(exp, OpExpBwd, LIBM_HIP_EXP)
+LMH_DEF_BWD(log, OpLogBwd, LIBM_HIP_LOG)
+LMH_DEF_BWD(tanh, OpTanhBwd, LIBM_HIP_TANH)
 
 libm_hip_status libm_hip_pow_u10_f64_bwd(const double* x, const double* y, const double* gout,
                                          double* gx, double* gy, size_t n, void* s) {
-  return launch_ternary2<IoF64, OpPowBwd>(x, y, gout, gx, gy, n, s, "pow_u10_f64_bwd");
+  return launch_ternary2<IoF64, OpPowBwd>(x, y, gout, gx, gy, n, s, "pow_u10_f64_bwd",
+                                          tune_key(LIBM_HIP_POW, 3, 0));
 }
 libm_hip_status libm_hip_pow_u10_f32_bwd(const float* x, const float* y, const float* gout,
                                          float* gx, float* gy, size_t n, void* s) {
-  return launch_ternary2<IoF32, OpPowBwd>(x, y, gout, gx, gy, n, s, "pow_u10_f32_bwd");
+  return launch_ternary2<IoF32, OpPowBwd>(x, y, gout, gx, gy, n, s, "pow_u10_f32_bwd",
+                                          tune_key(LIBM_HIP_POW, 3, 1));
 }
 libm_hip_status libm_hip_atan2_u10_f64_bwd(const double* y, const double* x, const double* gout,
                                            double* gy, double* gx, size_t n, void* s) {
-  return launch_ternary2<IoF64, OpAtan2Bwd>(y, x, gout, gy, gx, n, s, "atan2_u10_f64_bwd");
+  return launch_ternary2<IoF64, OpAtan2Bwd>(y, x, gout, gy, gx, n, s, "atan2_u10_f64_bwd",
+                                            tune_key(LIBM_HIP_ATAN2, 3, 0));
 }
 libm_hip_status libm_hip_atan2_u10_f32_bwd(const float* y, const float* x, const float* gout,
                                            float* gy, float* gx, size_t n, void* s) {
-  return launch_ternary2<IoF32, OpAtan2Bwd>(y, x, gout, gy, gx, n, s, "atan2_u10_f32_bwd");
+  return launch_ternary2<IoF32, OpAtan2Bwd>(y, x, gout, gy, gx, n, s, "atan2_u10_f32_bwd",
+                                            tune_key(LIBM_HIP_ATAN2, 3, 1));
 }
 }  // extern "C"
 
@@ -351,14 +508,14 @@ using namespace lmh_ops;
 
 template <class Op>
 libm_hip_status dispatch_unary(libm_hip_dtype t, const void* a, void* out, size_t n, void* s,
-                               bool u35) {
+                               bool u35, int key) {
   switch (t) {
-    case LIBM_HIP_F64: return launch_unary<IoF64, Op>(a, out, n, s, "eval_f64");
-    case LIBM_HIP_F32: return launch_unary<IoF32, Op>(a, out, n, s, "eval_f32");
-    case LIBM_HIP_BF16: if (!u35) return launch_unary<IoBF16, Op>(a, out, n, s, "eval_bf16"); break;
-    case LIBM_HIP_F16: if (!u35) return launch_unary<IoF16, Op>(a, out, n, s, "eval_f16"); break;
+    case LIBM_HIP_F64: return launch_unary<IoF64, Op>(a, out, n, s, "eval_f64", key);
+    case LIBM_HIP_F32: return launch_unary<IoF32, Op>(a, out, n, s, "eval_f32", key);
+    case LIBM_HIP_BF16: if (!u35) return launch_unary<IoBF16, Op>(a, out, n, s, "eval_bf16", key); break;
+    case LIBM_HIP_F16: if (!u35) return launch_unary<IoF16, Op>(a, out, n, s, "eval_f16", key); break;
     case LIBM_HIP_F32_VIA_F64:
-      if (!u35) return launch_unary<IoF32ViaF64, Op>(a, out, n, s, "eval_f32_via_f64");
+      if (!u35) return launch_unary<IoF32ViaF64, Op>(a, out, n, s, "eval_f32_via_f64", key);
       break;
   }
   set_error("libm_hip_eval: unsupported dtype for this function/variant");
@@ -367,18 +524,18 @@ libm_hip_status dispatch_unary(libm_hip_dtype t, const void* a, void* out, size_
 
 template <class Op>
 libm_hip_status dispatch_binary(libm_hip_dtype t, const void* a, const void* b, void* out,
-                                size_t n, void* s, bool all_dtypes) {
+                                size_t n, void* s, bool all_dtypes, int key) {
   switch (t) {
-    case LIBM_HIP_F64: return launch_binary<IoF64, Op>(a, b, out, n, s, "eval_f64");
-    case LIBM_HIP_F32: return launch_binary<IoF32, Op>(a, b, out, n, s, "eval_f32");
+    case LIBM_HIP_F64: return launch_binary<IoF64, Op>(a, b, out, n, s, "eval_f64", key);
+    case LIBM_HIP_F32: return launch_binary<IoF32, Op>(a, b, out, n, s, "eval_f32", key);
     case LIBM_HIP_BF16:
-      if (all_dtypes) return launch_binary<IoBF16, Op>(a, b, out, n, s, "eval_bf16");
+      if (all_dtypes) return launch_binary<IoBF16, Op>(a, b, out, n, s, "eval_bf16", key);
       break;
     case LIBM_HIP_F16:
-      if (all_dtypes) return launch_binary<IoF16, Op>(a, b, out, n, s, "eval_f16");
+      if (all_dtypes) return launch_binary<IoF16, Op>(a, b, out, n, s, "eval_f16", key);
       break;
     case LIBM_HIP_F32_VIA_F64:
-      if (all_dtypes) return launch_binary<IoF32ViaF64, Op>(a, b, out, n, s, "eval_f32_via_f64");
+      if (all_dtypes) return launch_binary<IoF32ViaF64, Op>(a, b, out, n, s, "eval_f32_via_f64", key);
       break;
   }
   set_error("libm_hip_eval: unsupported dtype for this function");
@@ -391,36 +548,118 @@ extern "C" libm_hip_status libm_hip_eval(libm_hip_fn fn, libm_hip_variant v, lib
                                          const void* a, const void* b, void* out, size_t n,
                                          void* s) {
   bool u10 = v == LIBM_HIP_U10, u35 = v == LIBM_HIP_U35;
+  const int key = tune_key(fn, v, t);
   switch (fn) {
     case LIBM_HIP_SIN:
-      if (u10) return dispatch_unary<OpSinU10>(t, a, out, n, s, false);
-      if (u35) return dispatch_unary<OpSinU35>(t, a, out, n, s, true);
+      if (u10) return dispatch_unary<OpSinU10>(t, a, out, n, s, false, key);
+      if (u35) return dispatch_unary<OpSinU35>(t, a, out, n, s, true, key);
       break;
     case LIBM_HIP_COS:
-      if (u10) return dispatch_unary<OpCosU10>(t, a, out, n, s, false);
-      if (u35) return dispatch_unary<OpCosU35>(t, a, out, n, s, true);
+      if (u10) return dispatch_unary<OpCosU10>(t, a, out, n, s, false, key);
+      if (u35) return dispatch_unary<OpCosU35>(t, a, out, n, s, true, key);
       break;
     case LIBM_HIP_TAN:
-      if (u10) return dispatch_unary<OpTanU10>(t, a, out, n, s, false);
-      if (u35) return dispatch_unary<OpTanU35>(t, a, out, n, s, true);
+      if (u10) return dispatch_unary<OpTanU10>(t, a, out, n, s, false, key);
+      if (u35) return dispatch_unary<OpTanU35>(t, a, out, n, s, true, key);
       break;
-    case LIBM_HIP_EXP: if (u10) return dispatch_unary<OpExpU10>(t, a, out, n, s, false); break;
-    case LIBM_HIP_EXP2: if (u10) return dispatch_unary<OpExp2U10>(t, a, out, n, s, false); break;
-    case LIBM_HIP_LOG: if (u10) return dispatch_unary<OpLogU10>(t, a, out, n, s, false); break;
-    case LIBM_HIP_LOG2: if (u10) return dispatch_unary<OpLog2U10>(t, a, out, n, s, false); break;
-    case LIBM_HIP_SINH: if (u10) return dispatch_unary<OpSinhU10>(t, a, out, n, s, false); break;
-    case LIBM_HIP_COSH: if (u10) return dispatch_unary<OpCoshU10>(t, a, out, n, s, false); break;
-    case LIBM_HIP_TANH: if (u10) return dispatch_unary<OpTanhU10>(t, a, out, n, s, false); break;
-    case LIBM_HIP_POW: if (u10) return dispatch_binary<OpPowU10>(t, a, b, out, n, s, true); break;
-    case LIBM_HIP_ATAN2: if (u10) return dispatch_binary<OpAtan2U10>(t, a, b, out, n, s, true); break;
+    case LIBM_HIP_EXP: if (u10) return dispatch_unary<OpExpU10>(t, a, out, n, s, false, key); break;
+    case LIBM_HIP_EXP2: if (u10) return dispatch_unary<OpExp2U10>(t, a, out, n, s, false, key); break;
+    case LIBM_HIP_LOG: if (u10) return dispatch_unary<OpLogU10>(t, a, out, n, s, false, key); break;
+    case LIBM_HIP_LOG2: if (u10) return dispatch_unary<OpLog2U10>(t, a, out, n, s, false, key); break;
+    case LIBM_HIP_SINH: if (u10) return dispatch_unary<OpSinhU10>(t, a, out, n, s, false, key); break;
+    case LIBM_HIP_COSH: if (u10) return dispatch_unary<OpCoshU10>(t, a, out, n, s, false, key); break;
+    case LIBM_HIP_TANH: if (u10) return dispatch_unary<OpTanhU10>(t, a, out, n, s, false, key); break;
+    case LIBM_HIP_POW: if (u10) return dispatch_binary<OpPowU10>(t, a, b, out, n, s, true, key); break;
+    case LIBM_HIP_ATAN2: if (u10) return dispatch_binary<OpAtan2U10>(t, a, b, out, n, s, true, key); break;
     case LIBM_HIP_FMOD:
-      if (v == LIBM_HIP_EXACT) return dispatch_binary<OpFmod>(t, a, b, out, n, s, false);
+      if (v == LIBM_HIP_EXACT) return dispatch_binary<OpFmod>(t, a, b, out, n, s, false, key);
       break;
     case LIBM_HIP_REMAINDER:
-      if (v == LIBM_HIP_EXACT) return dispatch_binary<OpRemainder>(t, a, b, out, n, s, false);
+      if (v == LIBM_HIP_EXACT) return dispatch_binary<OpRemainder>(t, a, b, out, n, s, false, key);
       break;
     default: break;
   }
   set_error("libm_hip_eval: unsupported function/variant");
   return LIBM_HIP_ERR_UNSUPPORTED;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+extern "C" libm_hip_status libm_hip_tune(libm_hip_fn fn, libm_hip_variant v, libm_hip_dtype t,
+                                         const void* a, const void* b, void* out, size_t n,
+                                         void* stream, int* best_block, int* best_packs) {
+  static const int blocks[] = {64, 128, 256, 512, 1024};
+  static const int packs[] = {1, 2, 4};
+  if (n == 0 || !a || !out) {
+    set_error("libm_hip_tune: needs n > 0 and valid buffers");
+    return LIBM_HIP_ERR_INVALID;
+  }
+  if ((int)fn < 0 || fn >= LIBM_HIP_NUM_FN || (int)v < 0 || v > LIBM_HIP_EXACT || (int)t < 0 ||
+      t > LIBM_HIP_F32_VIA_F64) {
+    set_error("libm_hip_tune: unknown function, variant or dtype");
+    return LIBM_HIP_ERR_UNSUPPORTED;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    set_error("libm_hip_tune: event creation failed");
+    return LIBM_HIP_ERR_HIP;
+  }
+  float best_ms = 1e30f;
+  int best = 0;
+  libm_hip_status st = LIBM_HIP_OK;
+  for (int bi = 0; bi < 5 && st == LIBM_HIP_OK; ++bi) {
+    for (int pi = 0; pi < 3 && st == LIBM_HIP_OK; ++pi) {
+      g_force_cfg = blocks[bi] | (packs[pi] << 16);
+      st = libm_hip_eval(fn, v, t, a, b, out, n, stream);        // warm-up
+      hipEventRecord(e0, s);
+      for (int r = 0; r < 3 && st == LIBM_HIP_OK; ++r) st = libm_hip_eval(fn, v, t, a, b, out, n, stream);
+      hipEventRecord(e1, s);
+      hipEventSynchronize(e1);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (st == LIBM_HIP_OK && ms < best_ms) {
+        best_ms = ms;
+        best = g_force_cfg;
+      }
+    }
+  }
+  g_force_cfg = 0;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != LIBM_HIP_OK) return st;
+  g_tune[tune_key(fn, v, t)][nbucket(n)].store(best, std::memory_order_relaxed);
+  Cfg c = unpack_cfg(best);
+  if (best_block) *best_block = c.block;
+  if (best_packs) *best_packs = c.packs;
+  return LIBM_HIP_OK;
+}
+
+extern "C" libm_hip_status libm_hip_tune_save(const char* path) {
+  FILE* f = path ? fopen(path, "w") : nullptr;
+  if (!f) {
+    set_error("libm_hip_tune_save: cannot open file");
+    return LIBM_HIP_ERR_INVALID;
+  }
+  for (int k = 0; k < NKEY; ++k)
+    for (int b = 0; b < NBUCKET; ++b) {
+      int v = g_tune[k][b].load(std::memory_order_relaxed);
+      if (v) fprintf(f, "%d %d %d %d\n", k, b, v & 0xffff, v >> 16);
+    }
+  fclose(f);
+  return LIBM_HIP_OK;
+}
+
+extern "C" libm_hip_status libm_hip_tune_load(const char* path) {
+  if (!path || load_tune_file(path) < 0) {
+    set_error("libm_hip_tune_load: cannot read file");
+    return LIBM_HIP_ERR_INVALID;
+  }
+  return LIBM_HIP_OK;
+}
+
+extern "C" void libm_hip_tune_reset(void) {
+  for (int k = 0; k < NKEY; ++k)
+    for (int b = 0; b < NBUCKET; ++b) g_tune[k][b].store(0, std::memory_order_relaxed);
 }

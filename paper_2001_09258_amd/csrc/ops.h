@@ -58,6 +58,7 @@ struct IoF16 {
 // ---------------------------------------------------------------------------
 #define LMH_OP1(NAME, F64FN, F32FN)                                              \
   struct NAME {                                                                \
+    static constexpr bool kSplit = false;                                      \
     static __device__ __forceinline__ double f(double x) { return lmh::F64FN(x); } \
     static __device__ __forceinline__ float f(float x) { return lmh::F32FN(x); }   \
   };
@@ -67,12 +68,31 @@ struct IoF16 {
     static __device__ __forceinline__ float f(float a, float b) { return lmh::F32FN(a, b); }    \
   };
 
-LMH_OP1(OpSinU10, sin_u10, sinf_u10)
-LMH_OP1(OpSinU35, sin_u35, sinf_u35)
-LMH_OP1(OpCosU10, cos_u10, cosf_u10)
-LMH_OP1(OpCosU35, cos_u35, cosf_u35)
-LMH_OP1(OpTanU10, tan_u10, tanf_u10)
-LMH_OP1(OpTanU35, tan_u35, tanf_u35)
+// Trigonometric tags also expose their two reduction paths, so a kernel can
+// gather the lanes that need Payne-Hanek (slow) and run them densely:
+// is_slow(x), fast(x) / slow(x) -> reduced state, finish(x, state) -> result.
+#define LMH_TRIG_OP(NAME, F64FN, F32FN, RED64, RED32, ARG, FIN64, FIN32)                        \
+  struct NAME {                                                                                 \
+    static constexpr bool kSplit = true;                                                        \
+    static __device__ __forceinline__ double f(double x) { return lmh::F64FN(x); }              \
+    static __device__ __forceinline__ float f(float x) { return lmh::F32FN(x); }                \
+    static __device__ __forceinline__ bool is_slow(double x) { return lmh::trig_slow(x); }      \
+    static __device__ __forceinline__ bool is_slow(float x) { return lmh::trigf_slow(x); }      \
+    static __device__ __forceinline__ lmh::Trig64 fast(double x) { return lmh::RED64##_fast(x ARG); } \
+    static __device__ __forceinline__ lmh::Trig32 fast(float x) { return lmh::RED32##_fast(x ARG); }  \
+    static __device__ __forceinline__ lmh::Trig64 slow(double x) { return lmh::RED64##_slow(x ARG); } \
+    static __device__ __forceinline__ lmh::Trig32 slow(float x) { return lmh::RED32##_slow(x ARG); }  \
+    static __device__ __forceinline__ double finish(double x, lmh::Trig64 s) { return lmh::FIN64(x, s); } \
+    static __device__ __forceinline__ float finish(float x, lmh::Trig32 s) { return lmh::FIN32(x, s); }   \
+  };
+#define LMH_NOARG
+#define LMH_COMMA ,
+LMH_TRIG_OP(OpSinU10, sin_u10, sinf_u10, sincos, sincosf, LMH_COMMA false, sin_finish_u10, sinf_finish_u10)
+LMH_TRIG_OP(OpSinU35, sin_u35, sinf_u35, sincos, sincosf, LMH_COMMA false, sin_finish_u35, sinf_finish_u35)
+LMH_TRIG_OP(OpCosU10, cos_u10, cosf_u10, sincos, sincosf, LMH_COMMA true, cos_finish_u10, cosf_finish_u10)
+LMH_TRIG_OP(OpCosU35, cos_u35, cosf_u35, sincos, sincosf, LMH_COMMA true, cos_finish_u35, cosf_finish_u35)
+LMH_TRIG_OP(OpTanU10, tan_u10, tanf_u10, tan, tanf, LMH_NOARG, tan_finish_u10, tanf_finish_u10)
+LMH_TRIG_OP(OpTanU35, tan_u35, tanf_u35, tan, tanf, LMH_NOARG, tan_finish_u35, tanf_finish_u35)
 LMH_OP1(OpExpU10, exp_u10, expf_u10)
 LMH_OP1(OpExp2U10, exp2_u10, exp2f_u10)
 LMH_OP1(OpLogU10, log_u10, logf_u10)

@@ -56,3 +56,20 @@ def test_host_side_validation_without_gpu():
     assert lib.libm_hip_exp_u10_f64(None, None, 10, None) == 1
     assert b"NULL" in lib.libm_hip_last_error()
     assert lib.libm_hip_eval(99, 0, 0, None, None, None, 0, None) in (0, 2)
+
+
+def test_tune_cache_roundtrip_without_gpu(tmp_path):
+    """The tuning table loads from and saves to its text format (no device
+    work is involved)."""
+    import paper_2001_09258_amd as L
+    src = tmp_path / "in.txt"
+    src.write_text("24 20 512 2\n24 26 128 4\n999999 3 256 1\n24 5 300 1\n")
+    L.tune_reset()
+    L.tune_load(str(src))
+    dst = tmp_path / "out.txt"
+    L.tune_save(str(dst))
+    lines = sorted(dst.read_text().split("\n"))
+    assert [l for l in lines if l] == ["24 20 512 2", "24 26 128 4"]   # invalid rows dropped
+    L.tune_reset()
+    L.tune_save(str(dst))
+    assert dst.read_text() == ""

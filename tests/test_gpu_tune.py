@@ -1,0 +1,39 @@
+"""Autotuner on the GPU: a tuned launch shape is returned, recorded and used,
+and results are bit-identical to the default shape."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_common import to_device
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+import paper_2001_09258_amd as L  # noqa: E402
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L.load()
+
+
+@pytest.mark.parametrize("fn,dt", [("exp", "f64"), ("log", "f32"), ("pow", "f64"),
+                                    ("tanh", "bf16")])
+def test_tune_then_results_unchanged(fn, dt, tmp_path):
+    n = (1 << 20) + 123
+    mk = W.config4 if dt in ("bf16", "f16") else W.config2
+    a = to_device(mk(fn, dt, n, 0), dt)
+    b = to_device(mk(fn, dt, n, 1), dt) if fn == "pow" else None
+    L.tune_reset()
+    ref = L.evaluate(fn, a, b)
+    blk, pk = L.tune(fn, a, b)
+    assert blk in (64, 128, 256, 512, 1024) and pk in (1, 2, 4)
+    got = L.evaluate(fn, a, b)
+    torch.cuda.synchronize()
+    x, y = (t.float() if t.dtype in (torch.bfloat16, torch.float16) else t for t in (ref, got))
+    assert torch.equal(torch.nan_to_num(x, nan=3.0), torch.nan_to_num(y, nan=3.0))
+    path = tmp_path / "tune.txt"
+    L.tune_save(str(path))
+    assert path.read_text().strip() != ""
+    L.tune_reset()
