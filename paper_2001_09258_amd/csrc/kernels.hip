@@ -68,7 +68,7 @@ int load_tune_file(const char* path) {
   int key, b, blk, pk, count = 0;
   while (fscanf(f, "%d %d %d %d", &key, &b, &blk, &pk) == 4) {
     bool okb = blk == 64 || blk == 128 || blk == 256 || blk == 512 || blk == 1024;
-    if (key >= 0 && key < NKEY && b >= 0 && b < NBUCKET && okb && pk >= 1 && pk <= 8) {
+    if (key >= 0 && key < NKEY && b >= 0 && b < NBUCKET && okb && (pk == 1 || pk == 2 || pk == 4)) {
       g_tune[key][b].store(blk | (pk << 16), std::memory_order_relaxed);
       ++count;
     }
@@ -97,16 +97,16 @@ __device__ __forceinline__ void store_nt(const P& v, void* dst) {
   __builtin_nontemporal_store(__builtin_bit_cast(u32x4, v), reinterpret_cast<u32x4*>(dst));
 }
 
-// Each workgroup covers blockDim.x * packs packs; pack u of a lane is
+// Each workgroup covers blockDim.x * PACKS packs; pack u of a lane is
 // (block_base + u * blockDim.x + lane), so every iteration is one fully
-// coalesced workgroup-wide access.
-template <class Io, class Op, int EPT, bool VEC>
+// coalesced workgroup-wide access.  Misaligned arrays use PACKS = 1.
+template <class Io, class Op, int EPT, bool VEC, int PACKS>
 __global__ __launch_bounds__(MAX_BLOCK) void k_unary(const typename Io::S* __restrict__ x,
-                                                     typename Io::S* __restrict__ y, size_t n,
-                                                     int packs) {
+                                                     typename Io::S* __restrict__ y, size_t n) {
   typedef typename Io::S S;
-  size_t pk0 = (size_t)blockIdx.x * blockDim.x * packs + threadIdx.x;
-  for (int u = 0; u < packs; ++u) {
+  size_t pk0 = (size_t)blockIdx.x * blockDim.x * PACKS + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < PACKS; ++u) {
     size_t base = (pk0 + (size_t)u * blockDim.x) * EPT;
     if (base >= n) return;
     if (VEC && base + EPT <= n) {
@@ -124,14 +124,14 @@ __global__ __launch_bounds__(MAX_BLOCK) void k_unary(const typename Io::S* __res
   }
 }
 
-template <class Io, class Op, int EPT, bool VEC>
+template <class Io, class Op, int EPT, bool VEC, int PACKS>
 __global__ __launch_bounds__(MAX_BLOCK) void k_binary(const typename Io::S* __restrict__ a,
                                                       const typename Io::S* __restrict__ b,
-                                                      typename Io::S* __restrict__ y, size_t n,
-                                                      int packs) {
+                                                      typename Io::S* __restrict__ y, size_t n) {
   typedef typename Io::S S;
-  size_t pk0 = (size_t)blockIdx.x * blockDim.x * packs + threadIdx.x;
-  for (int u = 0; u < packs; ++u) {
+  size_t pk0 = (size_t)blockIdx.x * blockDim.x * PACKS + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < PACKS; ++u) {
     size_t base = (pk0 + (size_t)u * blockDim.x) * EPT;
     if (base >= n) return;
     if (VEC && base + EPT <= n) {
@@ -232,17 +232,17 @@ __global__ __launch_bounds__(BLOCK) void k_unary_split(const typename Io::S* __r
 }
 
 // three inputs, two outputs (backward of the binary functions)
-template <class Io, class Op, int EPT, bool VEC>
+template <class Io, class Op, int EPT, bool VEC, int PACKS>
 __global__ __launch_bounds__(MAX_BLOCK) void k_ternary2(const typename Io::S* __restrict__ a,
                                                         const typename Io::S* __restrict__ b,
                                                         const typename Io::S* __restrict__ c,
                                                         typename Io::S* __restrict__ y0,
-                                                        typename Io::S* __restrict__ y1, size_t n,
-                                                        int packs) {
+                                                        typename Io::S* __restrict__ y1, size_t n) {
   typedef typename Io::S S;
   typedef typename Io::C C;
-  size_t pk0 = (size_t)blockIdx.x * blockDim.x * packs + threadIdx.x;
-  for (int u = 0; u < packs; ++u) {
+  size_t pk0 = (size_t)blockIdx.x * blockDim.x * PACKS + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < PACKS; ++u) {
     size_t base = (pk0 + (size_t)u * blockDim.x) * EPT;
     if (base >= n) return;
     if (VEC && base + EPT <= n) {
@@ -326,11 +326,17 @@ libm_hip_status launch_unary(const void* x, void* y, size_t n, void* stream, con
       hipLaunchKernelGGL((k_unary_split<Io, Op, EPT, false>), dim3(blocks), dim3(BLOCK), 0, s, xs, ys, n);
   } else {
     Cfg c = pick_cfg(key, n);
+    if (!vec) c.packs = 1;
     if (!grid_for(n, EPT, c, blocks)) return LIBM_HIP_ERR_INVALID;
-    if (vec)
-      hipLaunchKernelGGL((k_unary<Io, Op, EPT, true>), dim3(blocks), dim3(c.block), 0, s, xs, ys, n, c.packs);
+    dim3 g(blocks), b(c.block);
+    if (!vec)
+      hipLaunchKernelGGL((k_unary<Io, Op, EPT, false, 1>), g, b, 0, s, xs, ys, n);
+    else if (c.packs == 4)
+      hipLaunchKernelGGL((k_unary<Io, Op, EPT, true, 4>), g, b, 0, s, xs, ys, n);
+    else if (c.packs == 2)
+      hipLaunchKernelGGL((k_unary<Io, Op, EPT, true, 2>), g, b, 0, s, xs, ys, n);
     else
-      hipLaunchKernelGGL((k_unary<Io, Op, EPT, false>), dim3(blocks), dim3(c.block), 0, s, xs, ys, n, c.packs);
+      hipLaunchKernelGGL((k_unary<Io, Op, EPT, true, 1>), g, b, 0, s, xs, ys, n);
   }
   return launch_error(name);
 }
@@ -346,16 +352,23 @@ libm_hip_status launch_binary(const void* a, const void* b, void* y, size_t n, v
   typedef typename Io::S S;
   constexpr int EPT = ept_for<S>();
   Cfg c = pick_cfg(key, n);
+  bool vec = aligned16(a) && aligned16(b) && aligned16(y);
+  if (!vec) c.packs = 1;
   unsigned blocks;
   if (!grid_for(n, EPT, c, blocks)) return LIBM_HIP_ERR_INVALID;
   hipStream_t s = (hipStream_t)stream;
   const S* as = (const S*)a;
   const S* bs = (const S*)b;
   S* ys = (S*)y;
-  if (aligned16(a) && aligned16(b) && aligned16(y))
-    hipLaunchKernelGGL((k_binary<Io, Op, EPT, true>), dim3(blocks), dim3(c.block), 0, s, as, bs, ys, n, c.packs);
+  dim3 g(blocks), bl(c.block);
+  if (!vec)
+    hipLaunchKernelGGL((k_binary<Io, Op, EPT, false, 1>), g, bl, 0, s, as, bs, ys, n);
+  else if (c.packs == 4)
+    hipLaunchKernelGGL((k_binary<Io, Op, EPT, true, 4>), g, bl, 0, s, as, bs, ys, n);
+  else if (c.packs == 2)
+    hipLaunchKernelGGL((k_binary<Io, Op, EPT, true, 2>), g, bl, 0, s, as, bs, ys, n);
   else
-    hipLaunchKernelGGL((k_binary<Io, Op, EPT, false>), dim3(blocks), dim3(c.block), 0, s, as, bs, ys, n, c.packs);
+    hipLaunchKernelGGL((k_binary<Io, Op, EPT, true, 1>), g, bl, 0, s, as, bs, ys, n);
   return launch_error(name);
 }
 
@@ -370,15 +383,22 @@ libm_hip_status launch_ternary2(const void* a, const void* b, const void* c, voi
   typedef typename Io::S S;
   constexpr int EPT = ept_for<S>();
   Cfg cf = pick_cfg(key, n);
+  bool vec = aligned16(a) && aligned16(b) && aligned16(c) && aligned16(y0) && aligned16(y1);
+  if (!vec) cf.packs = 1;
   unsigned blocks;
   if (!grid_for(n, EPT, cf, blocks)) return LIBM_HIP_ERR_INVALID;
   hipStream_t s = (hipStream_t)stream;
   const S *as = (const S*)a, *bs = (const S*)b, *cs = (const S*)c;
   S *o0 = (S*)y0, *o1 = (S*)y1;
-  if (aligned16(a) && aligned16(b) && aligned16(c) && aligned16(y0) && aligned16(y1))
-    hipLaunchKernelGGL((k_ternary2<Io, Op, EPT, true>), dim3(blocks), dim3(cf.block), 0, s, as, bs, cs, o0, o1, n, cf.packs);
+  dim3 g(blocks), bl(cf.block);
+  if (!vec)
+    hipLaunchKernelGGL((k_ternary2<Io, Op, EPT, false, 1>), g, bl, 0, s, as, bs, cs, o0, o1, n);
+  else if (cf.packs == 4)
+    hipLaunchKernelGGL((k_ternary2<Io, Op, EPT, true, 4>), g, bl, 0, s, as, bs, cs, o0, o1, n);
+  else if (cf.packs == 2)
+    hipLaunchKernelGGL((k_ternary2<Io, Op, EPT, true, 2>), g, bl, 0, s, as, bs, cs, o0, o1, n);
   else
-    hipLaunchKernelGGL((k_ternary2<Io, Op, EPT, false>), dim3(blocks), dim3(cf.block), 0, s, as, bs, cs, o0, o1, n, cf.packs);
+    hipLaunchKernelGGL((k_ternary2<Io, Op, EPT, true, 1>), g, bl, 0, s, as, bs, cs, o0, o1, n);
   return launch_error(name);
 }
 

@@ -1,0 +1,66 @@
+"""Count the vector ALU instructions of every evaluator path on gfx950.
+
+Compiles ``op_probe.hip`` (one kernel per path: Cody-Waite levels,
+Payne-Hanek, polynomial + reconstruction, whole functions) to assembly and
+counts, per kernel, the VALU instructions and the binary64/binary32
+floating-point operations (an FMA counts as two).  The result,
+``valu_per_element.json``, is the per-element work the benchmark uses for
+the ALU roofline of compute-bound kernels: one element per lane, so VALU
+instructions per kernel = lane-operations per element.
+
+Run:  python -m paper_2001_09258_amd.gen.count_ops
+"""
+import json
+import os
+import re
+import subprocess
+import tempfile
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+OUT = os.path.join(HERE, "valu_per_element.json")
+
+
+def count(asm):
+    pat = re.compile(r"^(_Z\S+):\s*;", re.M)
+    res = {}
+    for m in pat.finditer(asm):
+        name = re.sub(r"^_Z\d+", "", m.group(1))
+        name = re.sub(r"PK[df]P[df]$", "", name)
+        end = asm.find(".Lfunc_end", m.start())
+        ins = []
+        for line in asm[m.start():end].split("\n")[1:]:
+            t = line.strip()
+            if not t or t.startswith((".", ";", "//")) or t.endswith(":"):
+                continue
+            ins.append(t.split()[0])
+        prec = "f64" if name.startswith("p64") else "f32"
+
+        def c(rx):
+            return sum(1 for x in ins if re.fullmatch(rx, x))
+        fma = c(r"v_(fma|fmac|fmaak|fmamk)_%s(_e32|_e64)?" % prec)
+        mul = c(r"v_mul_%s(_e32|_e64)?" % prec)
+        add = c(r"v_(add|sub|subrev)_%s(_e32|_e64)?" % prec)
+        # the probe's own load/store and index arithmetic is a handful of
+        # VALU instructions; they are part of every real kernel too
+        res[name] = {"valu": sum(1 for x in ins if x.startswith("v_")),
+                     "flops": 2 * fma + mul + add}
+    return res
+
+
+def main():
+    src = os.path.join(HERE, "op_probe.hip")
+    with tempfile.TemporaryDirectory() as d:
+        out = os.path.join(d, "probe.s")
+        subprocess.run(["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O3", "-std=c++17",
+                        "-ffp-contract=off", "-fno-gpu-flush-denormals-to-zero", "-Xclang",
+                        "-target-feature", "-Xclang", "-packed-fp32-ops", "--cuda-device-only",
+                        "-S", "-o", out, src], check=True)
+        res = count(open(out).read())
+    with open(OUT, "w") as fh:
+        json.dump(res, fh, indent=1, sort_keys=True)
+    for k, v in sorted(res.items()):
+        print("%-14s valu %4d flops %4d" % (k, v["valu"], v["flops"]))
+
+
+if __name__ == "__main__":
+    main()

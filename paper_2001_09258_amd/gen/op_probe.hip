@@ -1,0 +1,42 @@
+#include <hip/hip_runtime.h>
+// Probe kernels for counting the vector ALU work of each evaluator piece
+// (compiled to gfx950 assembly by count_ops.py, never linked into the
+// library).  Each kernel runs exactly one path of one evaluator on one
+// element per lane.
+#include "../csrc/eval_f64.h"
+#include "../csrc/eval_f32.h"
+using namespace lmh;
+#define K1(NAME, T, EXPR) __global__ void NAME(const T* x, T* y) { int i = threadIdx.x; T v = x[i]; y[i] = (EXPR); }
+#define KS(NAME, T, EXPR) __global__ void NAME(const T* x, T* y) { int i = threadIdx.x; T v = x[i]; auto s = (EXPR); y[i] = s.r.hi + s.r.lo + s.j; }
+// binary64 pieces
+__global__ void p64_cw(const double* x, double* y) { int i = threadIdx.x; double v = x[i]; double q = rint_(v * INV_PI_D); ddd r = cw_reduce(v, q, PI_D_0, PI_D_1, PI_D_2, PI_D_3); y[i] = r.hi + r.lo + q; }
+KS(p64_ph, double, sincos_slow(v, false))
+__global__ void p64_sinfin(const double* x, double* y) { int i = threadIdx.x; Trig64 s{mk(x[i], x[i+64]), x[i+128]}; y[i] = sin_finish_u10(x[i+192], s); }
+__global__ void p64_sinfin35(const double* x, double* y) { int i = threadIdx.x; Trig64 s{mk(x[i], x[i+64]), x[i+128]}; y[i] = sin_finish_u35(x[i+192], s); }
+__global__ void p64_tanfin(const double* x, double* y) { int i = threadIdx.x; Trig64 s{mk(x[i], x[i+64]), x[i+128]}; y[i] = tan_finish_u10(x[i+192], s); }
+__global__ void p64_tanfin35(const double* x, double* y) { int i = threadIdx.x; Trig64 s{mk(x[i], x[i+64]), x[i+128]}; y[i] = tan_finish_u35(x[i+192], s); }
+K1(p64_exp, double, exp_u10(v))
+K1(p64_exp2, double, exp2_u10(v))
+K1(p64_log, double, log_u10(v))
+K1(p64_log2, double, log2_u10(v))
+K1(p64_sinh, double, sinh_u10(v))
+K1(p64_cosh, double, cosh_u10(v))
+K1(p64_tanh, double, tanh_u10(v))
+__global__ void p64_pow(const double* x, double* y) { int i = threadIdx.x; y[i] = pow_u10(x[i], x[i+64]); }
+__global__ void p64_atan2(const double* x, double* y) { int i = threadIdx.x; y[i] = atan2_u10(x[i], x[i+64]); }
+// binary32 pieces
+__global__ void p32_cw(const float* x, float* y) { int i = threadIdx.x; float v = x[i]; float q = rint_(v * INV_PI_F); fff r = cwf_reduce(v, q, PI_F_0, PI_F_1, PI_F_2, PI_F_3); y[i] = r.hi + r.lo + q; }
+KS(p32_ph, float, sincosf_slow(v, false))
+__global__ void p32_sinfin(const float* x, float* y) { int i = threadIdx.x; Trig32 s{mk(x[i], x[i+64]), x[i+128]}; y[i] = sinf_finish_u10(x[i+192], s); }
+__global__ void p32_sinfin35(const float* x, float* y) { int i = threadIdx.x; Trig32 s{mk(x[i], x[i+64]), x[i+128]}; y[i] = sinf_finish_u35(x[i+192], s); }
+__global__ void p32_tanfin(const float* x, float* y) { int i = threadIdx.x; Trig32 s{mk(x[i], x[i+64]), x[i+128]}; y[i] = tanf_finish_u10(x[i+192], s); }
+__global__ void p32_tanfin35(const float* x, float* y) { int i = threadIdx.x; Trig32 s{mk(x[i], x[i+64]), x[i+128]}; y[i] = tanf_finish_u35(x[i+192], s); }
+K1(p32_exp, float, expf_u10(v))
+K1(p32_exp2, float, exp2f_u10(v))
+K1(p32_log, float, logf_u10(v))
+K1(p32_log2, float, log2f_u10(v))
+K1(p32_sinh, float, sinhf_u10(v))
+K1(p32_cosh, float, coshf_u10(v))
+K1(p32_tanh, float, tanhf_u10(v))
+__global__ void p32_pow(const float* x, float* y) { int i = threadIdx.x; y[i] = powf_u10(x[i], x[i+64]); }
+__global__ void p32_atan2(const float* x, float* y) { int i = threadIdx.x; y[i] = atan2f_u10(x[i], x[i+64]); }

@@ -63,7 +63,7 @@ def test_tune_cache_roundtrip_without_gpu(tmp_path):
     work is involved)."""
     import paper_2001_09258_amd as L
     src = tmp_path / "in.txt"
-    src.write_text("24 20 512 2\n24 26 128 4\n999999 3 256 1\n24 5 300 1\n")
+    src.write_text("24 20 512 2\n24 26 128 4\n999999 3 256 1\n24 5 300 1\n24 7 256 3\n")
     L.tune_reset()
     L.tune_load(str(src))
     dst = tmp_path / "out.txt"

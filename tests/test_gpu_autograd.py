@@ -111,8 +111,10 @@ def test_binary_autograd_matches_central_differences():
 
 def test_gradcheck_float64():
     x = (torch.rand(24, dtype=torch.float64, device="cuda") * 2 + 0.2).requires_grad_(True)
+    xt = (torch.rand(24, dtype=torch.float64, device="cuda") * 1.2 + 0.1).requires_grad_(True)
     for fn, F in FNS.items():
-        assert torch.autograd.gradcheck(F, (x,), eps=1e-6, atol=1e-9, rtol=1e-7), fn
+        arg = xt if fn == "tan" else x            # keep tan away from its pole at pi/2
+        assert torch.autograd.gradcheck(F, (arg,), eps=1e-6, atol=1e-9, rtol=1e-7), fn
     y = (torch.rand(24, dtype=torch.float64, device="cuda") * 2 + 0.2).requires_grad_(True)
     assert torch.autograd.gradcheck(A.pow, (x, y), eps=1e-6, atol=1e-9, rtol=1e-7)
     assert torch.autograd.gradcheck(A.atan2, (y, x), eps=1e-6, atol=1e-9, rtol=1e-7)
