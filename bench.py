@@ -8,9 +8,23 @@ launches; the mixture of 49% U[-1e4, 1e4], 50% log-uniform magnitudes, 1%
 special values).  Inputs are resident in HBM before timing starts.
 
 Prints one JSON line: whole-step throughput in Gelem/s, the roofline of the
-dominant kernel (its own average duration measured with HIP events on the
-launch stream), per-function throughput, and the CPU oracle's rate on a
+dominant kernel (its own average duration, measured with HIP events recorded
+on the launch stream around every launch of the timed steps), per-function
+throughput with both roofline fractions, and the CPU oracle's rate on a
 bounded sample of the same inputs.
+
+Rooflines.  HBM: algorithmic bytes per element (inputs read once, output
+written once) against 8 TB/s.  VALU: the evaluator's vector-ALU instructions
+per element, counted in the gfx950 assembly of one-element probe kernels
+(``paper_2001_09258_amd/gen/valu_per_element.json``; trig functions weight
+the Cody-Waite and Payne-Hanek reductions by the share of inputs each one
+takes).  Issue model from the unit counts and clock (256 CUs x 4 SIMDs x 16
+lanes x 2.4 GHz = 39.3 T lane-slots/s): binary64 instructions take one slot
+each (the 78.6 TFLOP/s FP64 vector peak), other VALU instructions can
+dual-issue and take half a slot (the 157.3 TFLOP/s FP32 peak), so an element
+costs max(n_f64, n_valu / 2) slots.  The kernel's VALU peak in lane-ops/s is
+39.3 T x n_valu / that cost.  A kernel's bound is the one with the larger
+lower-bound time.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -24,9 +38,13 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK = 8.0e12           # bytes/s, MI355X HBM3E
-FP64_PEAK = 78.6e12         # flop/s, dense vector FP64
-FP32_PEAK = 157.3e12        # flop/s, vector FP32 (packed)
+HBM_PEAK = 8.0e12                       # bytes/s, MI355X HBM3E
+VALU_SLOTS = 256 * 4 * 16 * 2.4e9       # VALU lane-slots/s (one binary64 lane-op each)
+FP64_PEAK = 78.6e12                     # flop/s, dense vector FP64
+SLOW_TRIG = {"f64": 1e14, "f32": 65536.0}   # |x| at which trig switches to Payne-Hanek
+OPS_FILE = os.path.join(ROOT, "paper_2001_09258_amd", "gen", "valu_per_element.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "elementwise_step_hbm_traffic.json")
+CSRC = os.path.join(ROOT, "paper_2001_09258_amd", "csrc")
 
 FUNCS = [("sin", "u10"), ("sin", "u35"), ("cos", "u10"), ("cos", "u35"),
          ("tan", "u10"), ("tan", "u35"), ("exp", "u10"), ("exp2", "u10"),
@@ -44,7 +62,7 @@ def parse():
     p.add_argument("--n", type=int, default=1 << 26)
     p.add_argument("--reps", type=int, default=3, help="per-kernel timing repeats")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sample", type=int, default=2048,
+    p.add_argument("--cpu-sample", type=int, default=49152,
                    help="oracle sample per (function, dtype)")
     p.add_argument("--only", default="", help="comma list fn:var:dt to restrict the step")
     return p.parse_args()
@@ -72,6 +90,48 @@ def gen_inputs(plan, n):
         for item, a, b in ex.map(one, plan):
             out[item] = (a, b)
     return out
+
+
+def kernel_source_hash():
+    """sha256 over the kernel sources; HBM traffic counters taken for other
+    sources are not reported."""
+    import hashlib
+    h = hashlib.sha256()
+    for d, _, files in sorted(os.walk(CSRC)):
+        for f in sorted(files):
+            if f.endswith((".h", ".hip", ".inc")):
+                path = os.path.join(d, f)
+                h.update(os.path.relpath(path, CSRC).encode())
+                with open(path, "rb") as fh:
+                    h.update(fh.read())
+    return h.hexdigest()
+
+
+def load_traffic():
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return {}
+    return t.get("kernels", {}) if t.get("source_hash") == kernel_source_hash() else {}
+
+
+def valu_ops(fn, v, dt, a, ops):
+    """Evaluator VALU instructions per element for one input array:
+    (all VALU, binary64-unit instructions, share of Payne-Hanek inputs)."""
+    import numpy as np
+    pre = "p64_" if dt == "f64" else "p32_"
+
+    def get(key):
+        return np.array([ops[key]["valu"], ops[key]["valu_f64"]], dtype=float)
+    if fn in ("sin", "cos", "tan"):
+        slow = float(np.mean(~(np.abs(a) < SLOW_TRIG[dt])))
+        red = (1 - slow) * get(pre + "cw") + slow * get(pre + "ph")
+        fin = get(pre + ("tanfin" if fn == "tan" else "sinfin") + ("35" if v == "u35" else ""))
+        tot = red + fin
+        return float(tot[0]), float(tot[1]), slow
+    tot = get(pre + fn)
+    return float(tot[0]), float(tot[1]), 0.0
 
 
 def cpu_baseline(inputs, sample):
@@ -140,54 +200,101 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(args.steps):
-        step()
-    ev1.record(stream)
+    # timed region: one event before every launch and one after the last, all
+    # on the launch stream; kernel i of step s lasts ev[s][i] -> ev[s][i + 1]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(calls) + 1)]
+           for _ in range(args.steps)]
+    for s_i in range(args.steps):
+        row = evs[s_i]
+        for i, (item, f, cargs) in enumerate(calls):
+            row[i].record(stream)
+            st = f(*cargs)
+            if st != 0:
+                raise RuntimeError("%s: %s" % (item, lib.libm_hip_last_error()))
+        row[-1].record(stream)
     torch.cuda.synchronize()
-    ms_step = ev0.elapsed_time(ev1) / args.steps
+    ms_total = evs[0][0].elapsed_time(evs[-1][-1])
+    ms_step = ms_total / args.steps
     elems = n * len(plan)
     value = elems / (ms_step * 1e-3) / 1e9
     print("bench: %.3f ms per step" % ms_step, file=sys.stderr, flush=True)
 
-    # per-kernel durations: HIP events on the launch stream around each call
+    with open(OPS_FILE) as fh:
+        ops = json.load(fh)
+    traffic = load_traffic()
     per = {}
-    for item, f, cargs in calls:
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(args.reps):
-            f(*cargs)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.reps
+    for i, (item, f, cargs) in enumerate(calls):
+        ms = sum(evs[s_i][i].elapsed_time(evs[s_i][i + 1]) for s_i in range(args.steps)) \
+            / args.steps
         fn, v, dt = item
         nb = ESIZE[dt] * (3 if fn in BINARY else 2)
-        per["%s_%s_%s" % item] = {"ms": round(ms, 4), "gelem_s": round(n / ms / 1e6, 2),
-                                  "hbm_frac": round(nb * n / (ms * 1e-3) / HBM_PEAK, 4)}
+        vo, v64, slow = valu_ops(fn, v, dt, host[item][0], ops)
+        slots = max(v64, vo / 2)
+        t_hbm = nb * n / HBM_PEAK
+        t_alu = slots * n / VALU_SLOTS
+        rec = {"ms": round(ms, 4), "gelem_s": round(n / ms / 1e6, 2),
+               "bytes_per_elem": nb, "valu_per_elem": round(vo, 1),
+               "valu_f64_per_elem": round(v64, 1), "valu_slots_per_elem": round(slots, 1),
+               "hbm_frac": round(t_hbm / (ms * 1e-3), 4),
+               "alu_frac": round(t_alu / (ms * 1e-3), 4),
+               "bound": "alu" if t_alu > t_hbm else "hbm"}
+        if slow:
+            rec["payne_hanek_share"] = round(slow, 4)
+        per["%s_%s_%s" % item] = rec
     dom = max(per, key=lambda k: per[k]["ms"])
     fn, v, dt = dom.split("_")
-    nb = ESIZE[dt] * (3 if fn in BINARY else 2)
-    dom_ms = per[dom]["ms"]
-    achieved = nb * n / (dom_ms * 1e-3)
-    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved / 1e9, 1),
-                "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK, 4), "traffic": None,
-                "algorithmic_bytes_per_elem": nb, "elements_per_launch": n,
-                "avg_launch_ms": dom_ms}
+    d = per[dom]
+    dom_s = d["ms"] * 1e-3
+    tr = traffic.get(dom)
+    common = {"kernel": dom, "elements_per_launch": n, "avg_launch_ms": d["ms"],
+              "traffic": tr["bytes_per_launch"] if tr else None,
+              "traffic_unit": "bytes per launch",
+              "algorithmic_bytes_per_launch": d["bytes_per_elem"] * n}
+    if d["bound"] == "alu":
+        achieved = d["valu_per_elem"] * n / dom_s
+        peak = VALU_SLOTS * d["valu_per_elem"] / d["valu_slots_per_elem"]
+        roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 2),
+                    "peak": round(peak / 1e12, 2), "unit": "T VALU lane-op/s",
+                    "frac": round(achieved / peak, 4),
+                    "valu_per_elem": d["valu_per_elem"],
+                    "valu_f64_per_elem": d["valu_f64_per_elem"], "hbm_frac": d["hbm_frac"]}
+    else:
+        achieved = d["bytes_per_elem"] * n / dom_s
+        roofline = {"bound": "hbm", "achieved": round(achieved / 1e9, 1),
+                    "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK, 4), "alu_frac": d["alu_frac"]}
+    roofline.update(common)
+
+    # copy ceiling: a plain elementwise copy-like kernel (negation) over the
+    # same number of binary64 elements, 16 bytes per element
+    src = dev[calls[0][0]][0]
+    dst = torch.empty_like(src)
+    torch.neg(src, out=dst)
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(args.reps):
+        torch.neg(src, out=dst)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 16 * n / (c0.elapsed_time(c1) / args.reps * 1e-3) / 1e9
+    del dst
 
     result = {"metric": "Gelem/s per function at <=1.0/3.5 ULP; % of HBM or VALU roofline",
               "value": round(value, 3), "unit": "Gelem/s", "n_gpus": 1,
               "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
               "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
               "dtype": "f64+f32", "data": "synthetic",
-              "config": {"workload": "full FP64+FP32 function set (15 function-variants x 2 "
-                                     "dtypes) on 2^26 elements each, config-2 mixture",
+              "config": {"workload": "15 function-variants x {f64, f32} on 2^26 elements "
+                                     "each; per element 49% U[-1e4, 1e4], 50% sign*10^U[-300, "
+                                     "300] (f32: [-38, 38]), 1% special values",
                          "elements_per_step": elems, "functions": len(plan),
                          "parallelism": "single GPU"},
-              "roofline": roofline, "per_function": per}
+              "roofline": roofline,
+              "copy_ceiling": {"GB_s": round(copy_gbs, 1), "frac_of_peak":
+                               round(copy_gbs * 1e9 / HBM_PEAK, 4),
+                               "kernel": "torch.neg, f64, 2^26 elements"},
+              "per_function": per}
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(host, args.cpu_sample)
     print(json.dumps(result))

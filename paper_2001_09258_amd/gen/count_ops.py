@@ -1,8 +1,9 @@
 """Count the vector ALU instructions of every evaluator path on gfx950.
 
-Compiles ``op_probe.hip`` (one kernel per path: Cody-Waite levels,
+Compiles ``op_probe.hip`` (one kernel per path: Cody-Waite reduction,
 Payne-Hanek, polynomial + reconstruction, whole functions) to assembly and
-counts, per kernel, the VALU instructions and the binary64/binary32
+counts, per kernel, the VALU instructions, those of them that run on the
+binary64 units, the transcendental-unit instructions, and the
 floating-point operations (an FMA counts as two).  The result,
 ``valu_per_element.json``, is the per-element work the benchmark uses for
 the ALU roofline of compute-bound kernels: one element per lane, so VALU
@@ -42,7 +43,15 @@ def count(asm):
         add = c(r"v_(add|sub|subrev)_%s(_e32|_e64)?" % prec)
         # the probe's own load/store and index arithmetic is a handful of
         # VALU instructions; they are part of every real kernel too
-        res[name] = {"valu": sum(1 for x in ins if x.startswith("v_")),
+        valu = [x for x in ins if x.startswith("v_")]
+        res[name] = {"valu": len(valu),
+                     # instructions of the binary64 units (arithmetic, compare,
+                     # convert, ldexp/frexp, rounding): at most 64 lanes per
+                     # clock per CU, whereas other VALU instructions can
+                     # dual-issue
+                     "valu_f64": sum(1 for x in valu if "f64" in x),
+                     "trans": sum(1 for x in valu if re.match(
+                         r"v_(rcp|rsq|sqrt|exp|log|sin|cos)_", x)),
                      "flops": 2 * fma + mul + add}
     return res
 
@@ -59,7 +68,8 @@ def main():
     with open(OUT, "w") as fh:
         json.dump(res, fh, indent=1, sort_keys=True)
     for k, v in sorted(res.items()):
-        print("%-14s valu %4d flops %4d" % (k, v["valu"], v["flops"]))
+        print("%-14s valu %4d f64 %4d trans %2d flops %4d"
+              % (k, v["valu"], v["valu_f64"], v["trans"], v["flops"]))
 
 
 if __name__ == "__main__":
