@@ -26,6 +26,10 @@ costs max(n_f64, n_valu / 2) slots.  The kernel's VALU peak in lane-ops/s is
 39.3 T x n_valu / that cost.  A kernel's bound is the one with the larger
 lower-bound time.
 
+Before timing, every kernel's launch shape (workgroup size, packs per lane)
+is autotuned on its own buffers (the library's tuner; ``--no-tune`` keeps
+the defaults); the chosen shapes are part of the output.
+
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
 import argparse
@@ -65,6 +69,12 @@ def parse():
     p.add_argument("--cpu-sample", type=int, default=49152,
                    help="oracle sample per (function, dtype)")
     p.add_argument("--only", default="", help="comma list fn:var:dt to restrict the step")
+    p.add_argument("--no-tune", action="store_true",
+                   help="keep the default launch shapes instead of autotuning them first")
+    p.add_argument("--no-extras", action="store_true",
+                   help="skip the bf16/f16/via-f64, batched and autograd measurements")
+    p.add_argument("--narrow-n", type=int, default=1 << 28,
+                   help="elements per bf16/f16 function")
     return p.parse_args()
 
 
@@ -81,8 +91,8 @@ def gen_inputs(plan, n):
 
     def one(item):
         fn, v, dt = item
-        a = W.config2(fn, dt, n, 0)
-        b = W.config2(fn, dt, n, 1) if fn in BINARY else None
+        a = W.mixture(fn, dt, n, 0)
+        b = W.mixture(fn, dt, n, 1) if fn in BINARY else None
         return item, a, b
 
     out = {}
@@ -132,6 +142,162 @@ def valu_ops(fn, v, dt, a, ops):
         return float(tot[0]), float(tot[1]), slow
     tot = get(pre + fn)
     return float(tot[0]), float(tot[1]), 0.0
+
+
+U10_SET = ["sin", "cos", "tan", "exp", "exp2", "log", "log2", "pow", "atan2", "sinh",
+           "cosh", "tanh"]
+
+
+def time_launches(stream, fn_calls, reps):
+    """Average ms of each zero-argument launcher, HIP events on ``stream``."""
+    import torch
+    out = []
+    for f in fn_calls:
+        f()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            f()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1) / reps)
+    return out
+
+
+def checked(lib, name, f, *cargs):
+    def go():
+        st = f(*cargs)
+        if st != 0:
+            raise RuntimeError("%s: %s" % (name, lib.libm_hip_last_error()))
+    return go
+
+
+def extra_precision_forms(lib, L, stream, dev, n_main, n_narrow, reps):
+    """The binary32 u10 set through the binary64 evaluators (2^26, binary32
+    mixture) and in bf16/f16 I/O (n_narrow elements each, the mixture clamped
+    to the format; one shared input per dtype and operand)."""
+    import torch
+    import workloads as W
+    sh = stream.cuda_stream
+    res = {}
+    calls, names = [], []
+    for fn in U10_SET:
+        ta, tb, to = dev[(fn, "u10", "f32")]
+        nm = L.entry_name(fn, "u10", "f32_via_f64")
+        f = getattr(lib, nm)
+        cargs = (ta.data_ptr(), to.data_ptr(), n_main, sh) if tb is None else \
+            (ta.data_ptr(), tb.data_ptr(), to.data_ptr(), n_main, sh)
+        calls.append(checked(lib, nm, f, *cargs))
+        names.append(fn)
+    ms = time_launches(stream, calls, reps)
+    res["f32_via_f64"] = {"n": n_main, "ms_total": round(sum(ms), 4),
+                          "gelem_s": round(len(ms) * n_main / sum(ms) / 1e6, 2),
+                          "per_function_ms": {k: round(v, 4) for k, v in zip(names, ms)}}
+    base = 1 << 26
+    for dt, tdt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
+        ops = []
+        for operand in (0, 1):
+            h = W.narrow_mixture("exp", dt, base, 500 + operand)
+            t = torch.from_numpy(h.astype("float32")).cuda().to(tdt)
+            ops.append(t.repeat((n_narrow + base - 1) // base)[:n_narrow].contiguous())
+        out = torch.empty_like(ops[0])
+        calls, names = [], []
+        for fn in U10_SET:
+            nm = L.entry_name(fn, "u10", dt)
+            f = getattr(lib, nm)
+            cargs = (ops[0].data_ptr(), out.data_ptr(), n_narrow, sh) \
+                if fn not in BINARY else \
+                (ops[0].data_ptr(), ops[1].data_ptr(), out.data_ptr(), n_narrow, sh)
+            calls.append(checked(lib, nm, f, *cargs))
+            names.append(fn)
+        ms = time_launches(stream, calls, reps)
+        res[dt] = {"n": n_narrow, "ms_total": round(sum(ms), 4),
+                   "gelem_s": round(len(ms) * n_narrow / sum(ms) / 1e6, 2),
+                   "per_function_ms": {k: round(v, 4) for k, v in zip(names, ms)}}
+        del ops, out
+    return res
+
+
+TORCH_DT = {"f64": "float64", "f32": "float32", "bf16": "bfloat16", "f16": "float16"}
+
+
+def extra_batch(lib, L, stream, reps):
+    """The 64-request batch: one graph-replayed persistent launch against the
+    sum of the per-function launches on the same requests."""
+    import torch
+    import workloads as W
+    sh = stream.cuda_stream
+    reqs = W.batch_requests(64, 3.0, 7.0)
+    tensors = []
+    for fn, var, dt, n, idx in reqs:
+        a, b = W.request_inputs(fn, dt, n, idx)
+        tdt = getattr(torch, TORCH_DT[dt])
+        ta = torch.from_numpy(a.astype("float32" if dt == "bf16" else a.dtype)).cuda().to(tdt)
+        tb = None if b is None else \
+            torch.from_numpy(b.astype("float32" if dt == "bf16" else b.dtype)).cuda().to(tdt)
+        tensors.append((fn, var, dt, ta, tb, torch.empty_like(ta)))
+    total = sum(t[3].numel() for t in tensors)
+    plan = L.BatchPlan(64, use_graph=True)
+    arr = (L.Request * len(tensors))()
+    for i, (fn, var, dt, ta, tb, to) in enumerate(tensors):
+        arr[i] = L.Request(L.FN_CODES[fn], L.VARIANT_CODES[var], L.DTYPE_CODES[dt], 0,
+                           ta.data_ptr(), 0 if tb is None else tb.data_ptr(), to.data_ptr(),
+                           ta.numel())
+
+    def run_batch():
+        st = plan.run_raw(arr, len(tensors), sh)
+        if st != 0:
+            raise RuntimeError("batch_run: %s" % lib.libm_hip_batch_last_error())
+    singles = []
+    for fn, var, dt, ta, tb, to in tensors:
+        nm = L.entry_name(fn, var, dt)
+        f = getattr(lib, nm)
+        cargs = (ta.data_ptr(), to.data_ptr(), ta.numel(), sh) if tb is None else \
+            (ta.data_ptr(), tb.data_ptr(), to.data_ptr(), ta.numel(), sh)
+        singles.append(checked(lib, nm, f, *cargs))
+
+    def run_singles():
+        for f in singles:
+            f()
+    ms_b, ms_s = time_launches(stream, [run_batch, run_singles], reps)
+    plan.close()
+    return {"requests": len(tensors), "elements": total,
+            "graph_ms": round(ms_b, 4), "graph_gelem_s": round(total / ms_b / 1e6, 2),
+            "per_function_launches_ms": round(ms_s, 4),
+            "per_function_gelem_s": round(total / ms_s / 1e6, 2)}
+
+
+def extra_autograd(lib, L, stream, reps, n=1 << 24):
+    """Forward + backward kernels of the autograd functions, binary32,
+    U[0.1, 10] operands."""
+    import torch
+    import workloads as W
+    sh = stream.cuda_stream
+    res = {}
+    for fn in ("sin", "exp", "log", "tanh", "pow", "atan2"):
+        a = torch.from_numpy(W.autograd_inputs(fn, n, 0)).cuda()
+        b = torch.from_numpy(W.autograd_inputs(fn, n, 1)).cuda()
+        g = torch.from_numpy(W.autograd_inputs(fn, n, 2)).cuda()
+        y = torch.empty_like(a)
+        g0 = torch.empty_like(a)
+        g1 = torch.empty_like(a)
+        fwd = getattr(lib, L.entry_name(fn, "u10", "f32"))
+        bwd = getattr(lib, "libm_hip_%s_u10_f32_bwd" % fn)
+        if fn in ("pow", "atan2"):
+            cf = checked(lib, fn, fwd, a.data_ptr(), b.data_ptr(), y.data_ptr(), n, sh)
+            cb = checked(lib, fn + "_bwd", bwd, a.data_ptr(), b.data_ptr(), g.data_ptr(),
+                         g0.data_ptr(), g1.data_ptr(), n, sh)
+            nbytes = 4 * 5
+        else:
+            cf = checked(lib, fn, fwd, a.data_ptr(), y.data_ptr(), n, sh)
+            cb = checked(lib, fn + "_bwd", bwd, a.data_ptr(), g.data_ptr(), g0.data_ptr(), n, sh)
+            nbytes = 4 * 3
+        ms_f, ms_b = time_launches(stream, [cf, cb], reps)
+        res[fn] = {"fwd_ms": round(ms_f, 4), "bwd_ms": round(ms_b, 4),
+                   "fwd_bwd_gelem_s": round(n / (ms_f + ms_b) / 1e6, 2),
+                   "bwd_hbm_frac": round(nbytes * n / (ms_b * 1e-3) / HBM_PEAK, 4)}
+    return {"n": n, "dtype": "f32", "functions": res}
 
 
 def cpu_baseline(inputs, sample):
@@ -190,6 +356,15 @@ def main():
             calls.append((item, f, (ta.data_ptr(), to.data_ptr(), n, sh)))
         else:
             calls.append((item, f, (ta.data_ptr(), tb.data_ptr(), to.data_ptr(), n, sh)))
+
+    tuned = {}
+    if not args.no_tune:
+        for item, f, cargs in calls:
+            fn, v, dt = item
+            ta, tb, to = dev[item]
+            blk, pk = L.tune(fn, ta, tb, variant=v, out=to)
+            tuned["%s_%s_%s" % item] = [blk, pk]
+        torch.cuda.synchronize()
 
     def step():
         for item, f, cargs in calls:
@@ -295,6 +470,16 @@ def main():
                                round(copy_gbs * 1e9 / HBM_PEAK, 4),
                                "kernel": "torch.neg, f64, 2^26 elements"},
               "per_function": per}
+    if tuned:
+        result["tuned_launch_shapes"] = tuned
+    if not args.no_extras:
+        t_x = time.perf_counter()
+        result["precision_forms"] = extra_precision_forms(lib, L, stream, dev, n, args.narrow_n,
+                                                          args.reps)
+        result["batch"] = extra_batch(lib, L, stream, args.reps)
+        result["autograd"] = extra_autograd(lib, L, stream, args.reps)
+        print("bench: extras in %.1f s" % (time.perf_counter() - t_x), file=sys.stderr,
+              flush=True)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(host, args.cpu_sample)
     print(json.dumps(result))

@@ -216,7 +216,10 @@ void libm_hip_tune_reset(void);
  * libm_hip_batch_plan_create: allocates the plan's device request table (up
  *   to max_requests <= 1024 entries), a pinned staging copy, a tile counter,
  *   a private capture stream; use_graph != 0 replays a captured graph, 0
- *   launches the kernels directly.  The plan owns these; destroy frees them.
+ *   launches the kernels directly.  The plan owns these; destroy frees them
+ *   (call it once the plan's last run has completed, e.g. after synchronizing
+ *   its stream).  The persistent grid holds as many 256-lane workgroups per
+ *   CU as can be resident together.
  * libm_hip_batch_run: validates every request (LIBM_HIP_ERR_UNSUPPORTED for a
  *   combination the library does not serve, LIBM_HIP_ERR_INVALID for NULL
  *   pointers with n > 0), uploads the table on `stream` and enqueues the

@@ -83,20 +83,6 @@ int load_tune_file(const char* path) {
 constexpr int BLOCK = 256;          // workgroup of the gathered-trig kernels
 constexpr int MAX_BLOCK = 1024;
 
-// 16 bytes of one operand for one lane; moved as a 128-bit vector so that the
-// store can carry the non-temporal hint
-template <class S, int EPT>
-struct alignas(16) Pack {
-  S v[EPT];
-};
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
-template <class P>
-__device__ __forceinline__ void store_nt(const P& v, void* dst) {
-  static_assert(sizeof(P) == 16, "one 128-bit store per lane");
-  __builtin_nontemporal_store(__builtin_bit_cast(u32x4, v), reinterpret_cast<u32x4*>(dst));
-}
-
 // Each workgroup covers blockDim.x * PACKS packs; pack u of a lane is
 // (block_base + u * blockDim.x + lane), so every iteration is one fully
 // coalesced workgroup-wide access.  Misaligned arrays use PACKS = 1.
@@ -273,9 +259,6 @@ __global__ __launch_bounds__(MAX_BLOCK) void k_ternary2(const typename Io::S* __
   }
 }
 
-// elements per lane: 16 bytes of storage per lane and operand
-template <class S>
-constexpr int ept_for() { return 16 / (int)sizeof(S); }
 
 inline bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
@@ -629,26 +612,37 @@ extern "C" libm_hip_status libm_hip_tune(libm_hip_fn fn, libm_hip_variant v, lib
   float best_ms = 1e30f;
   int best = 0;
   libm_hip_status st = LIBM_HIP_OK;
-  for (int bi = 0; bi < 5 && st == LIBM_HIP_OK; ++bi) {
-    for (int pi = 0; pi < 3 && st == LIBM_HIP_OK; ++pi) {
+  hipError_t he = hipSuccess;
+  for (int bi = 0; bi < 5 && st == LIBM_HIP_OK && he == hipSuccess; ++bi) {
+    for (int pi = 0; pi < 3 && st == LIBM_HIP_OK && he == hipSuccess; ++pi) {
       g_force_cfg = blocks[bi] | (packs[pi] << 16);
       st = libm_hip_eval(fn, v, t, a, b, out, n, stream);        // warm-up
-      hipEventRecord(e0, s);
-      for (int r = 0; r < 3 && st == LIBM_HIP_OK; ++r) st = libm_hip_eval(fn, v, t, a, b, out, n, stream);
-      hipEventRecord(e1, s);
-      hipEventSynchronize(e1);
-      float ms = 0.f;
-      hipEventElapsedTime(&ms, e0, e1);
-      if (st == LIBM_HIP_OK && ms < best_ms) {
-        best_ms = ms;
+      // the faster of two rounds of three launches
+      float ms_cfg = 1e30f;
+      for (int round = 0; round < 2 && st == LIBM_HIP_OK && he == hipSuccess; ++round) {
+        he = hipEventRecord(e0, s);
+        for (int r = 0; r < 3 && st == LIBM_HIP_OK; ++r)
+          st = libm_hip_eval(fn, v, t, a, b, out, n, stream);
+        if (he == hipSuccess) he = hipEventRecord(e1, s);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he == hipSuccess && ms < ms_cfg) ms_cfg = ms;
+      }
+      if (st == LIBM_HIP_OK && he == hipSuccess && ms_cfg < best_ms) {
+        best_ms = ms_cfg;
         best = g_force_cfg;
       }
     }
   }
   g_force_cfg = 0;
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (st != LIBM_HIP_OK) return st;
+  if (he != hipSuccess) {
+    set_error(hipGetErrorString(he));
+    return LIBM_HIP_ERR_HIP;
+  }
   g_tune[tune_key(fn, v, t)][nbucket(n)].store(best, std::memory_order_relaxed);
   Cfg c = unpack_cfg(best);
   if (best_block) *best_block = c.block;

@@ -127,4 +127,22 @@ struct OpAtan2Bwd {
 };
 
 
+// 16 bytes of one operand for one lane; moved as a 128-bit vector so that the
+// store can carry the non-temporal hint (the elements are touched once)
+template <class S, int EPT>
+struct alignas(16) Pack {
+  S v[EPT];
+};
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <class P>
+__device__ __forceinline__ void store_nt(const P& v, void* dst) {
+  static_assert(sizeof(P) == 16, "one 128-bit store per lane");
+  __builtin_nontemporal_store(__builtin_bit_cast(u32x4, v), reinterpret_cast<u32x4*>(dst));
+}
+
+// elements per lane and pack: 16 bytes of storage per lane and operand
+template <class S>
+constexpr int ept_for() { return 16 / (int)sizeof(S); }
+
 }  // namespace lmh_ops

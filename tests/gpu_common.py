@@ -60,7 +60,7 @@ def check(fn, variant, dt, a, b=None, label=""):
             label, fn, variant, dt, bad, a[idx[:3]], y[idx[:3]], rn[idx[:3]])
         return {"n": len(y), "max_ulp": 0.0, "mean_ulp": 0.0}
     bound = BOUND[variant]
-    res = compare(y, rn, hi, lo, ORACLE_FMT[dt], bound, double_rounded=(dt == "f32_via_f64"))
+    res = compare(y, rn, hi, lo, ORACLE_FMT[dt], bound)
     if res["violations"] or res["special_mismatch"]:
         idx = res["bad_idx"][:4]
         msg = "%s %s %s %s: max %.3f ulp, %d over %.1f, %d special mismatches; " \

@@ -5,7 +5,7 @@
   atan2 partials (binary32 and binary64);
 * autograd through the wrappers against central finite differences of the
   forward kernels (binary64) and torch.autograd.gradcheck;
-* the config-5 autograd workload at its full size (2^24 binary32 elements,
+* the autograd workload at its full size (2^24 binary32 elements,
   x ~ U[0.1, 10]) with 4096 sampled gradients checked against the oracle.
 """
 import numpy as np
@@ -121,7 +121,7 @@ def test_gradcheck_float64():
 
 
 @pytest.mark.parametrize("fn", ["sin", "exp", "log", "tanh", "pow", "atan2"])
-def test_config5_autograd_full_size(fn):
+def test_autograd_full_size(fn):
     """Forward + backward on 2^24 binary32 elements x ~ U[0.1, 10]; 4096
     sampled gradients against the oracle."""
     import oracle.batch as OB
@@ -130,7 +130,7 @@ def test_config5_autograd_full_size(fn):
     y = W.autograd_inputs(fn, n, 1)
     tx = torch.from_numpy(x).cuda().requires_grad_(True)
     ty = torch.from_numpy(y).cuda().requires_grad_(True)
-    print("config5", fn, flush=True)
+    print("autograd full size", fn, flush=True)
     out = {"pow": lambda: A.pow(tx, ty), "atan2": lambda: A.atan2(tx, ty)}.get(
         fn, lambda: {"sin": A.sin, "exp": A.exp, "log": A.log, "tanh": A.tanh}[fn](tx))()
     out.backward(torch.ones_like(out))

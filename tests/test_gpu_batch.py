@@ -1,5 +1,5 @@
 """Batched persistent kernel (one hip-graph replay per run) against the
-per-function entry points: bit-identical outputs on the config-5 request mix
+per-function entry points: bit-identical outputs on the 64-request mix
 (function, variant and dtype drawn uniformly, lengths log-uniform), graph
 replays interleaved with eager work, the direct-launch mode, and the
 validation errors."""
@@ -23,7 +23,7 @@ def _gpu():
 
 def _requests(hi=5.3):
     reqs = []
-    for fn, var, dt, n, idx in W.config5_requests(64, 3.0, hi):
+    for fn, var, dt, n, idx in W.batch_requests(64, 3.0, hi):
         a, b = W.request_inputs(fn, dt, n, idx)
         ta = to_device(a, dt)
         tb = to_device(b, dt) if b is not None else None

@@ -1,0 +1,117 @@
+"""Sweeps over whole input formats (the paper's testers check random bit
+patterns and regular grids, Section 6; a GPU can afford every pattern).
+
+* binary32: every STRIDE-th bit pattern (default stride 61, an odd step so
+  every residue of the low mantissa bits is visited; LIBM_HIP_SWEEP_STRIDE=1
+  sweeps all 2^32) for sin u10/u35, cos, tan, exp and log.  The host's
+  binary64 functions screen the results (their error, at most a few binary64
+  ulps, is below 1e-7 binary32 ulp); every element the screen cannot clear
+  (estimated error within 1e-4 of the bound, a special-class difference, or a
+  subnormal/zero/infinite result different from the rounded binary64 value)
+  is decided by the oracle.
+* bf16 and f16: all 65 536 patterns of every unary u10 function against the
+  oracle directly.
+"""
+import concurrent.futures as cf
+import os
+
+import numpy as np
+import pytest
+
+from tests.gpu_common import run_gpu, run_oracle, BOUND
+from tests.ulp import compare
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2001_09258_amd as L  # noqa: E402
+
+STRIDE = int(os.environ.get("LIBM_HIP_SWEEP_STRIDE", "61"))
+CHUNK = 1 << 24
+NP_F = {"sin": np.sin, "cos": np.cos, "tan": np.tan, "exp": np.exp, "log": np.log}
+SWEEP = [("sin", "u10"), ("sin", "u35"), ("cos", "u10"), ("tan", "u10"), ("exp", "u10"),
+         ("log", "u10")]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L.load()
+
+
+def _host_ref(f, x64):
+    """binary64 reference over a thread pool (numpy releases the GIL)."""
+    parts = np.array_split(x64, 16)
+    with np.errstate(all="ignore"), cf.ThreadPoolExecutor(16) as ex:
+        return np.concatenate(list(ex.map(f, parts)))
+
+
+def _screen(y, ref, bound):
+    """Indices the binary64 screen cannot clear."""
+    with np.errstate(all="ignore"):
+        rn = ref.astype(np.float32).astype(np.float64)
+        tiny = 2.0 ** -126
+        e = np.maximum(np.frexp(np.abs(ref))[1].astype(np.int64) - 1, -126)
+        ulp = np.ldexp(1.0, (e - 23).astype(np.int32))
+        err = np.abs(y - ref) / ulp
+        finite = np.isfinite(y) & np.isfinite(rn)
+        same = (y == rn) & (np.signbit(y) == np.signbit(rn))
+        same |= np.isnan(y) & np.isnan(rn)
+        flag = finite & ~(err <= bound - 1e-4)
+        flag |= ~finite & ~same
+        flag |= ((np.abs(rn) < tiny) | (np.abs(y) < tiny)) & ~same
+    return np.nonzero(flag)[0]
+
+
+@pytest.mark.parametrize("fn,variant", SWEEP, ids=["-".join(c) for c in SWEEP])
+def test_binary32_sweep(fn, variant):
+    bound = BOUND[variant]
+    total = flagged = 0
+    worst = 0.0
+    for start in range(0, 1 << 32, CHUNK * STRIDE):
+        stop = min(start + CHUNK * STRIDE, 1 << 32)
+        bits = np.arange(start, stop, STRIDE, dtype=np.uint64).astype(np.uint32)
+        x32 = bits.view(np.float32)
+        xd = torch.from_numpy(x32).cuda()
+        yd = L.evaluate(fn, xd, variant=variant)
+        torch.cuda.synchronize()
+        y = yd.cpu().numpy().astype(np.float64)
+        x64 = x32.astype(np.float64)
+        ref = _host_ref(NP_F[fn], x64)
+        idx = _screen(y, ref, bound)
+        total += bits.size
+        if idx.size:
+            flagged += idx.size
+            assert idx.size < 100000, "%s %s: %d elements not cleared by the screen" % (
+                fn, variant, idx.size)
+            rn, hi, lo = run_oracle(fn, "f32", x64[idx])
+            res = compare(y[idx], rn, hi, lo, "f32", bound)
+            bad = res["bad_idx"][:4]
+            assert res["violations"] == 0 and res["special_mismatch"] == 0, \
+                "%s %s: x=%r y=%r want %r (max %.3f ulp)" % (
+                    fn, variant, x64[idx][bad], y[idx][bad], rn[bad], res["max_ulp"])
+            worst = max(worst, res["max_ulp"])
+    print("sweep %s %s f32: %d patterns (stride %d), %d decided by the oracle, worst of "
+          "those %.3f ulp" % (fn, variant, total, STRIDE, flagged, worst), flush=True)
+
+
+NARROW_UNARY = ["sin", "cos", "tan", "exp", "exp2", "log", "log2", "sinh", "cosh", "tanh"]
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+@pytest.mark.parametrize("fn", NARROW_UNARY)
+def test_narrow_all_patterns(fn, dt):
+    bits = np.arange(1 << 16, dtype=np.uint32)
+    if dt == "bf16":
+        x = (bits << 16).view(np.float32).astype(np.float64)
+    else:
+        x = bits.astype(np.uint16).view(np.float16).astype(np.float64)
+    y = run_gpu(fn, "u10", dt, x)
+    rn, hi, lo = run_oracle(fn, dt, x)
+    res = compare(y, rn, hi, lo, dt, 1.0)
+    bad = res["bad_idx"][:4]
+    assert res["violations"] == 0 and res["special_mismatch"] == 0, \
+        "%s %s: x=%r y=%r want %r (max %.3f ulp)" % (fn, dt, x[bad], y[bad], rn[bad],
+                                                    res["max_ulp"])
+    print("all %s patterns %s: max %.3f ulp" % (dt, fn, res["max_ulp"]), flush=True)

@@ -1,7 +1,8 @@
 """GPU parity: every C-ABI entry point against the oracle, element by element.
 
 Sizes span many 256-lane tiles plus a ragged tail; inputs are the seeded
-workload mixtures (config 2 / 4 mixtures, config 3 large arguments, config 1
+workload mixtures (the mixture and its bf16/f16 form, large arguments, the
+binary64 small set
 at its full 2^20 size) plus the Annex F special set.  Bounds: 1.0 ULP (u10),
 3.5 ULP (u35), bit-exact for fmod/remainder and for every NaN, +-inf, +-0 and
 subnormal result (the paper's accuracy contract, Section 5, overview, and its
@@ -30,9 +31,9 @@ def _inputs(cfg, fn, dt, n, operand):
     base = "f32" if dt == "f32_via_f64" else dt
     if cfg == 2:
         if base in ("bf16", "f16"):
-            return W.config4(fn, base, n, operand)
-        return W.config2(fn, base, n, operand)
-    return W.config3(fn, base, n, operand)
+            return W.narrow_mixture(fn, base, n, operand)
+        return W.mixture(fn, base, n, operand)
+    return W.large_args(fn, base, n, operand)
 
 
 @pytest.fixture(scope="session", autouse=True)
@@ -59,16 +60,16 @@ TRIG_CASES = [c for c in CASES if c[0] in ("sin", "cos", "tan", "fmod", "remaind
 def test_parity_large_arguments(fn, variant, dt):
     a = _inputs(3, fn, dt, N_PAR, 0)
     b = _inputs(3, fn, dt, N_PAR, 1) if fn in BINARY else None
-    print("parity config3", fn, variant, dt, flush=True)
-    check(fn, variant, dt, a, b, label="config3")
+    print("parity large arguments", fn, variant, dt, flush=True)
+    check(fn, variant, dt, a, b, label="large_args")
 
 
 @pytest.mark.parametrize("fn", ["sin", "cos", "exp", "log"])
-def test_config1_full(fn):
-    """Config 1 at its full size: FP64 u10 on 2^20 elements."""
-    a = W.config1(fn)
-    print("config1", fn, flush=True)
-    res = check(fn, "u10", "f64", a, None, label="config1")
+def test_small_set_full(fn):
+    """The binary64 small set at its full size: u10 on 2^20 elements."""
+    a = W.small_set(fn)
+    print("small set", fn, flush=True)
+    res = check(fn, "u10", "f64", a, None, label="small_set")
     assert res["max_ulp"] <= 1.0
 
 
@@ -130,8 +131,8 @@ def test_misaligned_in_place_and_streams(dt):
     """Unaligned views (scalar path), in-place calls, non-default stream."""
     n = 5000
     base = "f32" if dt == "f32_via_f64" else dt
-    a = W.config4("exp", base, n + 3, 9) if base in ("bf16", "f16") else \
-        W.config2("exp", base, n + 3, 9)
+    a = W.narrow_mixture("exp", base, n + 3, 9) if base in ("bf16", "f16") else \
+        W.mixture("exp", base, n + 3, 9)
     ta = to_device(a, dt)
     view = ta[1:n + 1]                                       # 1-element offset
     assert view.data_ptr() % 16 != 0
@@ -153,7 +154,7 @@ def test_misaligned_in_place_and_streams(dt):
 
 
 def test_generic_dispatcher_matches_named_entry():
-    a = W.config2("sin", "f64", 4096, 3)
+    a = W.mixture("sin", "f64", 4096, 3)
     ta = to_device(a, "f64")
     out1 = L.sin(ta)
     out2 = torch.empty_like(ta)
@@ -177,8 +178,8 @@ def test_full_size_sampled(fn, variant, dt):
     """2^26 elements in the launch configuration the benchmark times; 4096
     sampled outputs checked against the oracle one by one."""
     n = 1 << 26
-    a = W.config2(fn, dt, n, 0)
-    b = W.config2(fn, dt, n, 1) if fn in BINARY else None
+    a = W.mixture(fn, dt, n, 0)
+    b = W.mixture(fn, dt, n, 1) if fn in BINARY else None
     print("full size", fn, variant, dt, flush=True)
     y = run_gpu(fn, variant, dt, a, b)
     idx = np.random.default_rng(5).integers(0, n, 4096)

@@ -22,7 +22,7 @@ def _gpu():
                                     ("tanh", "bf16")])
 def test_tune_then_results_unchanged(fn, dt, tmp_path):
     n = (1 << 20) + 123
-    mk = W.config4 if dt in ("bf16", "f16") else W.config2
+    mk = W.narrow_mixture if dt in ("bf16", "f16") else W.mixture
     a = to_device(mk(fn, dt, n, 0), dt)
     b = to_device(mk(fn, dt, n, 1), dt) if fn == "pow" else None
     L.tune_reset()

@@ -3,7 +3,7 @@ the benchmark.
 
 This module holds no arithmetic of the math functions themselves: it only
 draws arguments.  Every array comes from
-``np.random.default_rng(SeedSequence([2001, 9258, config, fn_id, operand]))``
+``np.random.default_rng(SeedSequence([2001, 9258, workload, fn_id, operand]))``
 and is generated on the host in the target format.
 
 The paper measures on uniformly distributed arguments in fixed intervals
@@ -17,8 +17,8 @@ bf16 arrays are returned as float32 arrays holding bf16-representable values
 """
 import numpy as np
 
-__all__ = ["FN_IDS", "rng_for", "specials", "config1", "config2", "config3",
-           "config4", "config5_requests", "autograd_inputs", "paper_domain",
+__all__ = ["FN_IDS", "rng_for", "specials", "small_set", "mixture", "large_args",
+           "narrow_mixture", "batch_requests", "autograd_inputs", "paper_domain",
            "PAPER_DOMAINS", "round_to_bf16", "to_bf16_bits",
            "from_bf16_bits", "np_dtype"]
 
@@ -37,9 +37,9 @@ def np_dtype(dt):
             "bf16": np.float32}[dt]
 
 
-def rng_for(config, fn, operand=0):
+def rng_for(workload, fn, operand=0):
     fid = FN_IDS[fn] if isinstance(fn, str) else int(fn)
-    return np.random.default_rng(np.random.SeedSequence([2001, 9258, config, fid, operand]))
+    return np.random.default_rng(np.random.SeedSequence([2001, 9258, workload, fid, operand]))
 
 
 def round_to_bf16(a):
@@ -91,7 +91,7 @@ def specials(dt):
     return np.array([0.0, -0.0, np.inf, -np.inf, np.nan, mins, -mins, maxs, -maxs])
 
 
-def config1(fn, n=1 << 20):
+def small_set(fn, n=1 << 20):
     """FP64 sin/cos/exp: U[-10, 10]; log: 1000 * (1 - U[0, 1)) in (0, 1000]."""
     rng = rng_for(1, fn)
     if fn == "log":
@@ -114,7 +114,7 @@ def _mixture(rng, n, dt, lo_exp, hi_exp):
     return x
 
 
-def config2(fn, dt, n=1 << 26, operand=0):
+def mixture(fn, dt, n=1 << 26, operand=0):
     rng = rng_for(2, fn, operand)
     if dt == "f64":
         x = _mixture(rng, n, dt, -300.0, 300.0)
@@ -124,7 +124,7 @@ def config2(fn, dt, n=1 << 26, operand=0):
         return _cast(x, dt)
 
 
-def config3(fn, dt, n=1 << 26, operand=0):
+def large_args(fn, dt, n=1 << 26, operand=0):
     """Large-argument stress.  Trig: half sign * 10^U[5, log10(max)], half
     x = k (pi/2)(1 + delta) with k = floor(10^U[0, 22 - log10(pi/2)]),
     delta ~ U[-1e-3, 1e-3] and delta = 0 for a quarter of those (binary64
@@ -151,12 +151,12 @@ def config3(fn, dt, n=1 << 26, operand=0):
         return _cast(np.minimum(np.abs(x), mx) * np.sign(x), dt)
 
 
-def config4(fn, dt, n=1 << 28, operand=0):
-    """Config-2 mixture for bf16/f16 with the log-uniform bounds clamped to
+def narrow_mixture(fn, dt, n=1 << 28, operand=0):
+    """The mixture for bf16/f16 with the log-uniform bounds clamped to
     [min subnormal, max finite] of the format; RNE conversion.  For 'f32' it
-    is exactly config 2's binary32 input."""
+    is exactly the binary32 mixture."""
     if dt == "f32":
-        return config2(fn, "f32", n, operand)
+        return mixture(fn, "f32", n, operand)
     rng = rng_for(4, fn, operand)
     lo = np.log10(DTYPE_MIN_SUB[dt])
     hi = np.log10(DTYPE_MAX[dt])
@@ -174,7 +174,7 @@ REQUEST_KINDS = [("sin", "u10"), ("sin", "u35"), ("cos", "u10"), ("cos", "u35"),
                  ("sinh", "u10"), ("cosh", "u10"), ("tanh", "u10")]
 
 
-def config5_requests(k=64, lo=3.0, hi=7.0):
+def batch_requests(k=64, lo=3.0, hi=7.0):
     """64 requests: (fn, variant) uniform over the served list, dtype uniform
     over {f64, f32, bf16, f16} (u35 variants only in f64/f32), length
     round(10^U[3, 7])."""
@@ -190,12 +190,12 @@ def config5_requests(k=64, lo=3.0, hi=7.0):
 
 
 def request_inputs(fn, dt, n, idx):
-    a = config4(fn, dt, n, operand=1000 + 2 * idx) if dt in ("bf16", "f16") else \
-        config2(fn, dt, n, operand=1000 + 2 * idx)
+    a = narrow_mixture(fn, dt, n, operand=1000 + 2 * idx) if dt in ("bf16", "f16") else \
+        mixture(fn, dt, n, operand=1000 + 2 * idx)
     b = None
     if fn in ("pow", "atan2"):
-        b = config4(fn, dt, n, operand=1001 + 2 * idx) if dt in ("bf16", "f16") else \
-            config2(fn, dt, n, operand=1001 + 2 * idx)
+        b = narrow_mixture(fn, dt, n, operand=1001 + 2 * idx) if dt in ("bf16", "f16") else \
+            mixture(fn, dt, n, operand=1001 + 2 * idx)
     return a, b
 
 
