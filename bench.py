@@ -103,13 +103,15 @@ def gen_inputs(plan, n):
 
 
 def kernel_source_hash():
-    """sha256 over the kernel sources; HBM traffic counters taken for other
-    sources are not reported."""
+    """sha256 over the device code of the elementwise kernels (kernels.h, the
+    evaluator headers and the generated tables); HBM traffic counters taken
+    for other device code are not reported.  Host-side files (launchers, the
+    C ABI, the tuner, the batch plan) do not enter it."""
     import hashlib
     h = hashlib.sha256()
     for d, _, files in sorted(os.walk(CSRC)):
         for f in sorted(files):
-            if f.endswith((".h", ".hip", ".inc")):
+            if f.endswith((".h", ".inc")):
                 path = os.path.join(d, f)
                 h.update(os.path.relpath(path, CSRC).encode())
                 with open(path, "rb") as fh:

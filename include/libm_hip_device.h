@@ -1,0 +1,143 @@
+/* libm_hip_device.h -- the libm_hip evaluators as device functions.
+ *
+ * For HIP device code on gfx950 that wants to apply a math function inside
+ * its own kernel (a fused epilogue such as GELU-tanh, softplus or rotary
+ * embeddings) instead of launching the library's elementwise kernels.  The
+ * functions are the ones every entry point of libm_hip.h runs, so a value
+ * computed here is bit-identical to the entry point's result for the same
+ * input.  The paper builds its library as vector functions that
+ * vectorizing compilers call from user loops (Section 4, the vector
+ * function ABI); on a GPU that role is played by inlinable device
+ * functions.
+ *
+ * Usage: #include "libm_hip_device.h" in a .hip file and call, e.g.,
+ *   double y = libm_hip_device::sin_u10(x);            // binary64, 1.0 ULP
+ *   float  z = libm_hip_device::tanh_u10(v);           // binary32, 1.0 ULP
+ *   float  w = libm_hip_device::exp_u10_via_f64(v);    // binary64 evaluation
+ *   uint16_t h = libm_hip_device::log_u10_bf16(bits);  // bf16 bit patterns
+ *
+ * Compile with the default -ffp-contract (or =on / =off): the evaluator
+ * headers switch contraction off for their own code and restore the
+ * command-line mode at their end.  An explicit -ffp-contract=fast, or
+ * -ffast-math, overrides that and voids the accuracy bounds.  Denormals must
+ * not be flushed (the HIP default on gfx950).
+ *
+ * Every function is a pure function of its arguments: no memory, no state,
+ * no errno or flags; special values follow C99 Annex F as the entry points
+ * do.  Accuracy: *_u10 within 1.0 ULP, *_u35 within 3.5 ULP, fmod and
+ * remainder exact; bf16/f16 forms evaluate in binary32 and round once.
+ * The *_bwd functions return the vector-Jacobian product g * f'(x) (two
+ * partials for pow and atan2) as the backward entry points do.
+ */
+#ifndef LIBM_HIP_DEVICE_H
+#define LIBM_HIP_DEVICE_H
+
+#include <stdint.h>
+
+#include "../paper_2001_09258_amd/csrc/ops.h"
+
+namespace libm_hip_device {
+
+#define LIBM_HIP_DEVICE_UNARY(NAME, OP)                                                   \
+  __device__ __forceinline__ double NAME(double x) { return lmh_ops::OP::f(x); }            \
+  __device__ __forceinline__ float NAME(float x) { return lmh_ops::OP::f(x); }              \
+  __device__ __forceinline__ float NAME##_via_f64(float x) {                                \
+    return lmh_ops::IoF32ViaF64::out(lmh_ops::OP::f(lmh_ops::IoF32ViaF64::in(x)));          \
+  }                                                                                       \
+  __device__ __forceinline__ uint16_t NAME##_bf16(uint16_t x) {                             \
+    return lmh_ops::IoBF16::out(lmh_ops::OP::f(lmh_ops::IoBF16::in(x)));                    \
+  }                                                                                       \
+  __device__ __forceinline__ uint16_t NAME##_f16(uint16_t x) {                              \
+    return lmh_ops::IoF16::out(lmh_ops::OP::f(lmh_ops::IoF16::in(x)));                      \
+  }
+
+#define LIBM_HIP_DEVICE_UNARY_WIDE(NAME, OP)                                              \
+  __device__ __forceinline__ double NAME(double x) { return lmh_ops::OP::f(x); }            \
+  __device__ __forceinline__ float NAME(float x) { return lmh_ops::OP::f(x); }
+
+#define LIBM_HIP_DEVICE_BINARY(NAME, OP)                                                  \
+  __device__ __forceinline__ double NAME(double a, double b) { return lmh_ops::OP::f(a, b); } \
+  __device__ __forceinline__ float NAME(float a, float b) { return lmh_ops::OP::f(a, b); }    \
+  __device__ __forceinline__ float NAME##_via_f64(float a, float b) {                       \
+    return lmh_ops::IoF32ViaF64::out(                                                       \
+        lmh_ops::OP::f(lmh_ops::IoF32ViaF64::in(a), lmh_ops::IoF32ViaF64::in(b)));           \
+  }                                                                                       \
+  __device__ __forceinline__ uint16_t NAME##_bf16(uint16_t a, uint16_t b) {                 \
+    return lmh_ops::IoBF16::out(lmh_ops::OP::f(lmh_ops::IoBF16::in(a), lmh_ops::IoBF16::in(b))); \
+  }                                                                                       \
+  __device__ __forceinline__ uint16_t NAME##_f16(uint16_t a, uint16_t b) {                  \
+    return lmh_ops::IoF16::out(lmh_ops::OP::f(lmh_ops::IoF16::in(a), lmh_ops::IoF16::in(b)));   \
+  }
+
+/* sin, cos, tan (Section 5, sin/cos and tan), exp, log (Section 5, exp and
+   log), exp2, log2, sinh, cosh, tanh: 1.0-ULP forms */
+LIBM_HIP_DEVICE_UNARY(sin_u10, OpSinU10)
+LIBM_HIP_DEVICE_UNARY(cos_u10, OpCosU10)
+LIBM_HIP_DEVICE_UNARY(tan_u10, OpTanU10)
+LIBM_HIP_DEVICE_UNARY(exp_u10, OpExpU10)
+LIBM_HIP_DEVICE_UNARY(exp2_u10, OpExp2U10)
+LIBM_HIP_DEVICE_UNARY(log_u10, OpLogU10)
+LIBM_HIP_DEVICE_UNARY(log2_u10, OpLog2U10)
+LIBM_HIP_DEVICE_UNARY(sinh_u10, OpSinhU10)
+LIBM_HIP_DEVICE_UNARY(cosh_u10, OpCoshU10)
+LIBM_HIP_DEVICE_UNARY(tanh_u10, OpTanhU10)
+/* 3.5-ULP trigonometric forms (binary64 and binary32) */
+LIBM_HIP_DEVICE_UNARY_WIDE(sin_u35, OpSinU35)
+LIBM_HIP_DEVICE_UNARY_WIDE(cos_u35, OpCosU35)
+LIBM_HIP_DEVICE_UNARY_WIDE(tan_u35, OpTanU35)
+/* pow(x, y) (Section 5, pow) and atan2(y, x), C argument order */
+LIBM_HIP_DEVICE_BINARY(pow_u10, OpPowU10)
+LIBM_HIP_DEVICE_BINARY(atan2_u10, OpAtan2U10)
+
+/* fmod(x, y) and remainder(x, y), exact (Section 5, FP remainder, Algorithm 1) */
+__device__ __forceinline__ double fmod(double x, double y) { return lmh_ops::OpFmod::f(x, y); }
+__device__ __forceinline__ float fmod(float x, float y) { return lmh_ops::OpFmod::f(x, y); }
+__device__ __forceinline__ double remainder(double x, double y) {
+  return lmh_ops::OpRemainder::f(x, y);
+}
+__device__ __forceinline__ float remainder(float x, float y) {
+  return lmh_ops::OpRemainder::f(x, y);
+}
+
+/* backward: g * f'(x) */
+#define LIBM_HIP_DEVICE_BWD(NAME, FN)                                                     \
+  __device__ __forceinline__ double NAME(double x, double g) { return lmh::FN(x, g); }      \
+  __device__ __forceinline__ float NAME(float x, float g) { return lmh::FN(x, g); }
+LIBM_HIP_DEVICE_BWD(sin_u10_bwd, sin_bwd)
+LIBM_HIP_DEVICE_BWD(cos_u10_bwd, cos_bwd)
+LIBM_HIP_DEVICE_BWD(tan_u10_bwd, tan_bwd)
+LIBM_HIP_DEVICE_BWD(exp_u10_bwd, exp_bwd)
+LIBM_HIP_DEVICE_BWD(log_u10_bwd, log_bwd)
+LIBM_HIP_DEVICE_BWD(tanh_u10_bwd, tanh_bwd)
+__device__ __forceinline__ void pow_u10_bwd(double x, double y, double g, double* gx, double* gy) {
+  lmh::pow_bwd(x, y, g, *gx, *gy);
+}
+__device__ __forceinline__ void pow_u10_bwd(float x, float y, float g, float* gx, float* gy) {
+  lmh::pow_bwd(x, y, g, *gx, *gy);
+}
+__device__ __forceinline__ void atan2_u10_bwd(double y, double x, double g, double* gy,
+                                              double* gx) {
+  lmh::atan2_bwd(y, x, g, *gy, *gx);
+}
+__device__ __forceinline__ void atan2_u10_bwd(float y, float x, float g, float* gy, float* gx) {
+  lmh::atan2_bwd(y, x, g, *gy, *gx);
+}
+
+/* masked evaluation (a whole function computing only the elements an opmask
+   selects, Section 3.1): lanes whose mask is false return their argument
+   unchanged, and a wave whose lanes are all masked off skips the work */
+template <class T, class F>
+__device__ __forceinline__ T masked(bool active, T x, F f) {
+  T r = x;
+  if (active) r = f(x);
+  return r;
+}
+
+#undef LIBM_HIP_DEVICE_UNARY
+#undef LIBM_HIP_DEVICE_UNARY_WIDE
+#undef LIBM_HIP_DEVICE_BINARY
+#undef LIBM_HIP_DEVICE_BWD
+
+}  // namespace libm_hip_device
+
+#endif /* LIBM_HIP_DEVICE_H */

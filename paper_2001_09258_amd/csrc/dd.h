@@ -20,6 +20,7 @@
 // dd2_div ~5u^2 once the reciprocal estimate is within ~u of 1/y.
 #pragma once
 #include "prims.h"
+#pragma STDC FP_CONTRACT OFF
 
 namespace lmh {
 
@@ -194,3 +195,5 @@ LMH_INLINE T poly_estrin(T z, const T (&c)[N]) {
 }
 
 }  // namespace lmh
+
+#pragma STDC FP_CONTRACT DEFAULT

@@ -8,6 +8,7 @@
 #include "generated/consts.inc"
 #include "generated/poly_coeffs.inc"
 #include "generated/ph_table_f32.inc"
+#pragma STDC FP_CONTRACT OFF
 
 namespace lmh {
 
@@ -525,3 +526,5 @@ LMH_INLINE float remainderf_f32(float x, float y) {
 }
 
 }  // namespace lmh
+
+#pragma STDC FP_CONTRACT DEFAULT

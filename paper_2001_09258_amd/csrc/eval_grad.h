@@ -14,6 +14,7 @@
 #pragma once
 #include "eval_f64.h"
 #include "eval_f32.h"
+#pragma STDC FP_CONTRACT OFF
 
 namespace lmh {
 
@@ -139,3 +140,5 @@ LMH_INLINE void atan2_bwd(float y, float x, float g, float& gy, float& gx) {
 }
 
 }  // namespace lmh
+
+#pragma STDC FP_CONTRACT DEFAULT

@@ -7,6 +7,7 @@
 #include "eval_f64.h"
 #include "eval_f32.h"
 #include "eval_grad.h"
+#pragma STDC FP_CONTRACT OFF
 
 namespace lmh_ops {
 
@@ -146,3 +147,5 @@ template <class S>
 constexpr int ept_for() { return 16 / (int)sizeof(S); }
 
 }  // namespace lmh_ops
+
+#pragma STDC FP_CONTRACT DEFAULT

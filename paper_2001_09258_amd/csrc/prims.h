@@ -10,6 +10,12 @@
 #pragma once
 #include <stdint.h>
 
+// The evaluators depend on exactly where products are rounded: every fused
+// multiply-add is written out, and no other product may be contracted
+// (honoured under the default -ffp-contract; an explicit
+// -ffp-contract=fast overrides it and changes results).
+#pragma STDC FP_CONTRACT OFF
+
 #define LMH_INLINE __device__ __forceinline__
 
 namespace lmh {
@@ -56,3 +62,5 @@ LMH_INLINE double pred_(double x) { return as_f64(as_i64(x) - 1); }
 LMH_INLINE float pred_(float x) { return as_f32(as_i32(x) - 1); }
 
 }  // namespace lmh
+
+#pragma STDC FP_CONTRACT DEFAULT

@@ -1,0 +1,115 @@
+// Test helper (not part of the library): a kernel that evaluates through the
+// device-callable API of include/libm_hip_device.h, built WITHOUT
+// -ffp-contract=off so that the headers' own contraction control is what
+// keeps the results identical to the library's entry points.
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/libm_hip_device.h"
+
+namespace {
+namespace D = libm_hip_device;
+
+template <class S, class F>
+__global__ void k1(const S* a, S* y, size_t n, F f) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = f(a[i]);
+}
+template <class S, class F>
+__global__ void k2(const S* a, const S* b, S* y, size_t n, F f) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = f(a[i], b[i]);
+}
+// masked: every other element keeps its input
+template <class S, class F>
+__global__ void km(const S* a, S* y, size_t n, F f) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = D::masked((i & 1) == 0, a[i], f);
+}
+
+template <class S, class F>
+int launch1(const void* a, void* y, size_t n, void* s, F f) {
+  unsigned g = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL((k1<S, F>), dim3(g), dim3(256), 0, (hipStream_t)s, (const S*)a, (S*)y, n, f);
+  return hipGetLastError() == hipSuccess ? 0 : 3;
+}
+template <class S, class F>
+int launch2(const void* a, const void* b, void* y, size_t n, void* s, F f) {
+  unsigned g = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL((k2<S, F>), dim3(g), dim3(256), 0, (hipStream_t)s, (const S*)a, (const S*)b,
+                     (S*)y, n, f);
+  return hipGetLastError() == hipSuccess ? 0 : 3;
+}
+}  // namespace
+
+// fn, variant, dtype use the codes of libm_hip.h's enums
+#define U1(NAME)                                                                            \
+  switch (dtype) {                                                                          \
+    case 0: return launch1<double>(a, y, n, s, [] __device__(double x) { return D::NAME(x); }); \
+    case 1: return launch1<float>(a, y, n, s, [] __device__(float x) { return D::NAME(x); });   \
+    case 2: return launch1<uint16_t>(a, y, n, s, [] __device__(uint16_t x) { return D::NAME##_bf16(x); }); \
+    case 3: return launch1<uint16_t>(a, y, n, s, [] __device__(uint16_t x) { return D::NAME##_f16(x); });  \
+    case 4: return launch1<float>(a, y, n, s, [] __device__(float x) { return D::NAME##_via_f64(x); });    \
+  }                                                                                         \
+  return 2;
+#define U1W(NAME)                                                                           \
+  switch (dtype) {                                                                          \
+    case 0: return launch1<double>(a, y, n, s, [] __device__(double x) { return D::NAME(x); }); \
+    case 1: return launch1<float>(a, y, n, s, [] __device__(float x) { return D::NAME(x); });   \
+  }                                                                                         \
+  return 2;
+#define B2(NAME)                                                                            \
+  switch (dtype) {                                                                          \
+    case 0: return launch2<double>(a, b, y, n, s, [] __device__(double u, double v) { return D::NAME(u, v); }); \
+    case 1: return launch2<float>(a, b, y, n, s, [] __device__(float u, float v) { return D::NAME(u, v); });    \
+    case 2: return launch2<uint16_t>(a, b, y, n, s, [] __device__(uint16_t u, uint16_t v) { return D::NAME##_bf16(u, v); }); \
+    case 3: return launch2<uint16_t>(a, b, y, n, s, [] __device__(uint16_t u, uint16_t v) { return D::NAME##_f16(u, v); });  \
+    case 4: return launch2<float>(a, b, y, n, s, [] __device__(float u, float v) { return D::NAME##_via_f64(u, v); });       \
+  }                                                                                         \
+  return 2;
+#define B2W(NAME)                                                                           \
+  switch (dtype) {                                                                          \
+    case 0: return launch2<double>(a, b, y, n, s, [] __device__(double u, double v) { return D::NAME(u, v); }); \
+    case 1: return launch2<float>(a, b, y, n, s, [] __device__(float u, float v) { return D::NAME(u, v); });    \
+  }                                                                                         \
+  return 2;
+
+extern "C" int device_api_eval(int fn, int variant, int dtype, const void* a, const void* b,
+                               void* y, size_t n, void* s) {
+  if (n == 0) return 0;
+  if (variant == 1) {
+    switch (fn) {
+      case 0: U1W(sin_u35)
+      case 1: U1W(cos_u35)
+      case 2: U1W(tan_u35)
+    }
+    return 2;
+  }
+  switch (fn) {
+    case 0: U1(sin_u10)
+    case 1: U1(cos_u10)
+    case 2: U1(tan_u10)
+    case 3: U1(exp_u10)
+    case 4: U1(exp2_u10)
+    case 5: U1(log_u10)
+    case 6: U1(log2_u10)
+    case 7: B2(pow_u10)
+    case 8: B2(atan2_u10)
+    case 9: U1(sinh_u10)
+    case 10: U1(cosh_u10)
+    case 11: U1(tanh_u10)
+    case 12: B2W(fmod)
+    case 13: B2W(remainder)
+  }
+  return 2;
+}
+
+// sin u10 binary64 on the even elements only, the odd ones copied
+extern "C" int device_api_masked_sin(const double* a, double* y, size_t n, void* s) {
+  if (n == 0) return 0;
+  unsigned g = (unsigned)((n + 255) / 256);
+  auto f = [] __device__(double x) { return D::sin_u10(x); };
+  hipLaunchKernelGGL((km<double, decltype(f)>), dim3(g), dim3(256), 0, (hipStream_t)s, a, y, n, f);
+  return hipGetLastError() == hipSuccess ? 0 : 3;
+}

@@ -11,10 +11,16 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
+    """Functions declared by the C-ABI headers (those with an extern "C"
+    block; libm_hip_device.h holds device functions only and exports
+    nothing)."""
     names = set()
     for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
         if not h.endswith(".h"):
             continue
+        with open(os.path.join(ROOT, "include", h)) as fh:
+            if 'extern "C"' not in fh.read():
+                continue
         out = subprocess.run(["gcc", "-E", "-P", os.path.join(ROOT, "include", h)],
                              check=True, capture_output=True, text=True).stdout
         names |= set(re.findall(r"\b(libm_hip_\w+)\s*\(", out))
@@ -73,3 +79,21 @@ def test_tune_cache_roundtrip_without_gpu(tmp_path):
     L.tune_reset()
     L.tune_save(str(dst))
     assert dst.read_text() == ""
+
+
+def test_device_header_compiles_for_gfx950(tmp_path):
+    """include/libm_hip_device.h builds into a user kernel (device code only,
+    no GPU needed)."""
+    hipcc = "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not installed")
+    src = tmp_path / "user.hip"
+    src.write_text('#include "libm_hip_device.h"\n'
+                   "__global__ void k(const double* x, float* y) {\n"
+                   "  int i = threadIdx.x;\n"
+                   "  y[i] = libm_hip_device::tanh_u10((float)x[i]) +\n"
+                   "         (float)libm_hip_device::pow_u10(x[i], 0.5);\n"
+                   "}\n")
+    subprocess.run([hipcc, "--offload-arch=gfx950", "-O1", "-std=c++17", "--cuda-device-only",
+                    "-fsyntax-only", "-I", os.path.join(ROOT, "include"), str(src)],
+                   check=True, capture_output=True)

@@ -37,3 +37,10 @@ def test_tune_then_results_unchanged(fn, dt, tmp_path):
     L.tune_save(str(path))
     assert path.read_text().strip() != ""
     L.tune_reset()
+
+
+@pytest.mark.parametrize("fn", ["sin", "cos", "tan"])
+def test_trig_shape_is_fixed(fn):
+    """The gathering trig kernels keep their one launch shape."""
+    a = to_device(W.mixture(fn, "f64", 4096, 0), "f64")
+    assert L.tune(fn, a) == (256, 1)
