@@ -66,7 +66,7 @@ def parse():
     p.add_argument("--n", type=int, default=1 << 26)
     p.add_argument("--reps", type=int, default=3, help="per-kernel timing repeats")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sample", type=int, default=49152,
+    p.add_argument("--cpu-sample", type=int, default=163840,
                    help="oracle sample per (function, dtype)")
     p.add_argument("--only", default="", help="comma list fn:var:dt to restrict the step")
     p.add_argument("--no-tune", action="store_true",
@@ -302,6 +302,22 @@ def extra_autograd(lib, L, stream, reps, n=1 << 24):
     return {"n": n, "dtype": "f32", "functions": res}
 
 
+def extra_share(lib, L, stream, calls, n_share, reps):
+    """The whole step at one GPU's share of an eight-way split: the first
+    n_share elements of every array (launch shapes from the table for that
+    size, the defaults unless tuned)."""
+    shares = []
+    for item, f, cargs in calls:
+        shares.append(checked(lib, L.entry_name(*item), f, *(cargs[:-2] + (n_share, cargs[-1]))))
+
+    def run_all():
+        for g in shares:
+            g()
+    ms = time_launches(stream, [run_all], reps)[0]
+    return {"elements_per_kernel": n_share, "ms_per_step": round(ms, 4),
+            "gelem_s": round(n_share * len(calls) / ms / 1e6, 2)}
+
+
 def cpu_baseline(inputs, sample):
     """The oracle as it stands, on the first ``sample`` elements of every
     (function, dtype) input of the step, over a process pool on all cores."""
@@ -480,6 +496,7 @@ def main():
                                                           args.reps)
         result["batch"] = extra_batch(lib, L, stream, args.reps)
         result["autograd"] = extra_autograd(lib, L, stream, args.reps)
+        result["per_gpu_share"] = extra_share(lib, L, stream, calls, n // 8, args.reps)
         print("bench: extras in %.1f s" % (time.perf_counter() - t_x), file=sys.stderr,
               flush=True)
     if not args.no_cpu_baseline:

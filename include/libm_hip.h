@@ -192,11 +192,12 @@ libm_hip_status libm_hip_eval(libm_hip_fn fn, libm_hip_variant v, libm_hip_dtype
  * floor(log2 n); the default is (256, 1).
  *
  * libm_hip_tune: times every pair in {64, 128, 256, 512, 1024} x {1, 2, 4}
- *   on the caller's buffers (one warm-up and the faster of two rounds of
+ *   on the caller's buffers (one warm-up and the fastest of three rounds of
  *   three launches each, HIP events on `stream`; it waits for the stream),
- *   records the fastest for (fn, v, t, bucket of n) and returns it.  The
- *   buffers are overwritten with valid results.  sin, cos and tan have the
- *   fixed shape (256, 1): the call returns it without launching anything.
+ *   records the fastest for (fn, v, t, bucket of n) if it beats the default
+ *   (256, 1) by at least 2% (else the default) and returns it.  The buffers
+ *   are overwritten with valid results.  sin, cos and tan have the fixed
+ *   shape (256, 1): the call returns it without launching anything.
  * libm_hip_tune_save / _load: the table as text lines "key bucket block packs";
  *   the environment variable LIBM_HIP_TUNE_CACHE names a file loaded at the
  *   first launch.  libm_hip_tune_reset restores the defaults.
