@@ -44,7 +44,7 @@ INF = float("inf")
 PREC_CAP = 16384
 
 UNARY = ("sin", "cos", "tan", "exp", "exp2", "log", "log2",
-         "sinh", "cosh", "tanh")
+         "sinh", "cosh", "tanh", "asin", "acos", "atan")
 BINARY = ("pow", "atan2", "fmod", "remainder")
 
 
@@ -114,6 +114,16 @@ def _special_unary(fn, x):
             return INF
         if x == 1.0:
             return 0.0
+    elif fn in ("asin", "acos"):
+        if abs(x) > 1.0:                 # including +-inf
+            return NAN
+        if fn == "asin" and x == 0.0:
+            return x
+        if fn == "acos" and x == 1.0:
+            return 0.0
+    elif fn == "atan":
+        if x == 0.0:
+            return x
     return None
 
 
@@ -310,6 +320,48 @@ def _ball_atan2(y, x, prec):
     return a if y > 0 else B.neg(a)
 
 
+def _ball_atan(x, prec):
+    """atan x: atan|x| for |x| <= 1, pi/2 - atan(1/|x|) above; odd."""
+    ax = abs(x)
+    wp = prec + 16
+    if ax <= 1.0:
+        a = atan_ball(from_float(ax), wp)
+    else:
+        a = sub(B.scale2(pi(wp + 8), -1), atan_ball(div(exact(1), from_float(ax), wp), wp), wp)
+    return a if x > 0 else B.neg(a)
+
+
+def _ball_asin(x, prec):
+    """asin x = atan(x / sqrt(1 - x^2)) for |x| < 1, with 1 - x^2 formed
+    exactly as (1 - |x|)(1 + |x|); the atan argument is kept in [0, 1] by
+    taking pi/2 - atan(sqrt(1 - x^2) / |x|) when |x| > sqrt(1 - x^2)."""
+    ax = abs(x)
+    wp = prec + 24
+    X = from_float(ax)
+    one = exact(1)
+    c = B.sqrt(mul(sub(one, X, wp), add(one, X, wp), wp), wp)      # sqrt(1 - x^2)
+    if ax * ax <= 0.5:
+        a = atan_ball(div(X, c, wp), wp)
+    else:
+        a = sub(B.scale2(pi(wp + 8), -1), atan_ball(div(c, X, wp), wp), wp)
+    return a if x > 0 else B.neg(a)
+
+
+def _ball_acos(x, prec):
+    """acos x = 2 atan(sqrt((1 - x) / (1 + x))) for -1 < x < 1 (no
+    cancellation near x = 1); the atan argument exceeds 1 when x < 0, then
+    atan t = pi/2 - atan(1/t)."""
+    wp = prec + 24
+    X = from_float(x)
+    one = exact(1)
+    q = div(sub(one, X, wp), add(one, X, wp), wp)
+    if x >= 0.0:
+        a = atan_ball(B.sqrt(q, wp), wp)
+    else:
+        a = sub(B.scale2(pi(wp + 8), -1), atan_ball(B.sqrt(div(one, q, wp), wp), wp), wp)
+    return B.scale2(a, 1)
+
+
 def _ball_pow(x, y, prec):
     """|x|^y (sign handled by the caller) for finite nonzero x, y."""
     m, e = _dyadic(abs(x))
@@ -393,7 +445,8 @@ def _fmod_exact(x, y, ieee_remainder):
 _BALLS = {"sin": _ball_sin, "cos": _ball_cos, "tan": _ball_tan,
           "exp": _ball_exp, "exp2": _ball_exp2, "log": _ball_log,
           "log2": _ball_log2, "sinh": _ball_sinh, "cosh": _ball_cosh,
-          "tanh": _ball_tanh}
+          "tanh": _ball_tanh, "asin": _ball_asin, "acos": _ball_acos,
+          "atan": _ball_atan}
 
 
 def _dd(b):
@@ -450,6 +503,12 @@ def evaluate1(fn, fmt_name, x, y=None):
             if m == 1:
                 v = rn_dyadic(e, 0, fmt, zero_sign=1)
                 return v, v, 0.0
+        if fn == "atan" and math.isinf(x):
+            v = math.copysign(_round_const("pi/2", fmt), x)
+            return v, v, 0.0
+        if fn == "acos" and x == -1.0:
+            v = _round_const("pi", fmt)
+            return v, v, 0.0
         return _ziv(_BALLS[fn], (x,), fmt, prec0)
     if fn == "atan2":
         sp = _special_atan2(x, y, fmt)       # atan2(x, y) in C order

@@ -37,7 +37,8 @@ SPECIALS = [0.0, -0.0, math.inf, -math.inf, math.nan, 1.0, -1.0, 0.5, -0.5,
 
 NP_UNARY = {"sin": np.sin, "cos": np.cos, "tan": np.tan, "exp": np.exp,
             "exp2": np.exp2, "log": np.log, "log2": np.log2, "sinh": np.sinh,
-            "cosh": np.cosh, "tanh": np.tanh}
+            "cosh": np.cosh, "tanh": np.tanh, "asin": np.arcsin, "acos": np.arccos,
+            "atan": np.arctan}
 
 
 def same(a, b):
@@ -109,7 +110,8 @@ def test_binary32_specials_match_host_libm():
 MP = {"sin": mpmath.sin, "cos": mpmath.cos, "tan": mpmath.tan,
       "exp": mpmath.exp, "exp2": lambda x: mpmath.power(2, x),
       "log": mpmath.log, "log2": lambda x: mpmath.log(x, 2),
-      "sinh": mpmath.sinh, "cosh": mpmath.cosh, "tanh": mpmath.tanh}
+      "sinh": mpmath.sinh, "cosh": mpmath.cosh, "tanh": mpmath.tanh,
+      "asin": mpmath.asin, "acos": mpmath.acos, "atan": mpmath.atan}
 
 
 def _mp_f64(fn, x, y=None):
@@ -137,6 +139,13 @@ def _inputs(fn, rng, n):
         c = rng.random()
         if fn in ("log", "log2"):
             xs.append(abs(_rand_bits(rng)) if c < 0.5 else rng.uniform(0, 1000))
+        elif fn in ("asin", "acos"):
+            if c < 0.4:
+                xs.append(rng.uniform(-1, 1))
+            elif c < 0.7:                 # within 10^-16 .. 1 of +-1
+                xs.append(math.copysign(1 - 10 ** rng.uniform(-16, 0), rng.random() - 0.5))
+            else:
+                xs.append(math.copysign(10 ** rng.uniform(-310, 0), rng.random() - 0.5))
         elif fn in ("exp", "exp2", "sinh", "cosh", "tanh"):
             lim = 1100 if fn == "exp2" else 760
             xs.append(rng.uniform(-lim, lim) if c < 0.5 else
@@ -229,7 +238,7 @@ def _midpoint_distance_in_dulps(d):
 
 
 @pytest.mark.parametrize("fn", ["sin", "cos", "tan", "exp", "log", "exp2", "log2",
-                                "sinh", "cosh", "tanh"])
+                                "sinh", "cosh", "tanh", "asin", "acos", "atan"])
 def test_binary32_vs_glibc_double_rounded(fn):
     # a strided sweep over all positive and negative binary32 bit patterns
     stride = 1 << 16
@@ -306,6 +315,49 @@ def test_atan2_quadrant_constants():
 def _contains_one(b):
     lo, hi, e = b.lo_hi()
     return lo * 2 ** e <= 1 <= hi * 2 ** e if e >= 0 else (lo <= (1 << -e) <= hi)
+
+
+def test_inverse_trig_identities_on_balls():
+    """asin x + acos x = pi/2 with the oracle's own ball evaluators
+    (independent formulas: asin through atan(x / sqrt(1 - x^2)), acos through
+    2 atan(sqrt((1 - x)/(1 + x)))), and arctangent relations against pi."""
+    from oracle.functions import _ball_asin, _ball_acos, _ball_atan
+    from oracle.consts import pi
+    rng = random.Random(13)
+    for _ in range(200):
+        x = rng.uniform(-1, 1) if rng.random() < 0.5 else \
+            math.copysign(1 - 10 ** rng.uniform(-15, 0), rng.random() - 0.5)
+        if abs(x) >= 1 or x == 0:
+            continue
+        s = B.add(_ball_asin(x, 120), _ball_acos(x, 120), 200)
+        assert _contains_one(B.div(s, B.scale2(pi(220), -1), 200)), x
+    # Euler's and Machin's arctangent relations pin atan against pi, which
+    # the oracle computes from its own series (and which is pinned to the
+    # AGM): atan 1 = pi/4, atan 1/2 + atan 1/3 = pi/4,
+    # 4 atan 1/5 - atan 1/239 = pi/4, 2 atan 1/2 + atan 3/4 = pi/2
+    from oracle.elementary import atan_ball
+    q = lambda a, b: B.div(B.exact(a), B.exact(b), 260)
+    quarter = B.scale2(pi(260), -2)
+    checks = [(_ball_atan(1.0, 200), quarter),
+              (B.add(atan_ball(q(1, 2), 200), atan_ball(q(1, 3), 200), 240), quarter),
+              (B.sub(B.scale2(atan_ball(q(1, 5), 200), 2), atan_ball(q(1, 239), 200), 240),
+               quarter),
+              (B.add(B.scale2(atan_ball(q(1, 2), 200), 1), atan_ball(q(3, 4), 200), 240),
+               B.scale2(quarter, 1))]
+    for lhs, rhs in checks:
+        assert _contains_one(B.div(lhs, rhs, 240))
+
+
+def test_asin_acos_atan_small_arguments():
+    """asin x, atan x -> x and acos x -> pi/2 - x for tiny x (Taylor)."""
+    for x in (1e-300, -3e-200, 5e-324, 2.0 ** -30):
+        assert evaluate1("asin", "f64", x)[0] == x
+        assert evaluate1("atan", "f64", x)[0] == x
+    assert evaluate1("acos", "f64", 5e-324)[0] == evaluate1("acos", "f64", 0.0)[0]
+    assert evaluate1("asin", "f64", 2.0 ** -26)[0] == 2.0 ** -26    # x^3/6 < ulp/2
+    with mpmath.workprec(400):
+        for x in (2.0 ** -20, 0.3, 0.5, 0.9999):
+            assert evaluate1("asin", "f64", x)[0] == float(mpmath.asin(mpmath.mpf(x)))
 
 
 def test_identities_on_balls():
