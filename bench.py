@@ -142,7 +142,7 @@ def valu_ops(fn, v, dt, a, ops):
         fin = get(pre + ("tanfin" if fn == "tan" else "sinfin") + ("35" if v == "u35" else ""))
         tot = red + fin
         return float(tot[0]), float(tot[1]), slow
-    tot = get(pre + fn)
+    tot = get(pre + fn + ("35" if v == "u35" else ""))
     return float(tot[0]), float(tot[1]), 0.0
 
 
@@ -318,6 +318,35 @@ def extra_share(lib, L, stream, calls, n_share, reps):
             "gelem_s": round(n_share * len(calls) / ms / 1e6, 2)}
 
 
+def extra_inverse_trig(lib, L, stream, n, reps, ops):
+    """asin, acos, atan (u10 and u35, binary64 and binary32) on 2^26
+    elements each: asin/acos on the unit-interval mixture, atan on the
+    mixture; per kernel the same roofline fractions as the step's."""
+    import torch
+    import workloads as W
+    sh = stream.cuda_stream
+    res = {}
+    for fn in ("asin", "acos", "atan"):
+        for dt in ("f64", "f32"):
+            a = W.function_mixture(fn, dt, n, 0)
+            ta = torch.from_numpy(a).cuda()
+            to = torch.empty_like(ta)
+            for v in ("u10", "u35"):
+                nm = L.entry_name(fn, v, dt)
+                ms = time_launches(stream, [checked(lib, nm, getattr(lib, nm), ta.data_ptr(),
+                                                    to.data_ptr(), n, sh)], reps)[0]
+                vo, v64, _ = valu_ops(fn, v, dt, a, ops)
+                slots = max(v64, vo / 2)
+                nb = ESIZE[dt] * 2
+                res["%s_%s_%s" % (fn, v, dt)] = {
+                    "ms": round(ms, 4), "gelem_s": round(n / ms / 1e6, 2),
+                    "valu_per_elem": vo, "valu_f64_per_elem": v64,
+                    "hbm_frac": round(nb * n / HBM_PEAK / (ms * 1e-3), 4),
+                    "alu_frac": round(slots * n / VALU_SLOTS / (ms * 1e-3), 4)}
+            del ta, to
+    return res
+
+
 def cpu_baseline(inputs, sample):
     """The oracle as it stands, on the first ``sample`` elements of every
     (function, dtype) input of the step, over a process pool on all cores."""
@@ -490,13 +519,16 @@ def main():
               "per_function": per}
     if tuned:
         result["tuned_launch_shapes"] = tuned
-    if not args.no_extras:
+    if not args.no_extras and not args.only:
         t_x = time.perf_counter()
         result["precision_forms"] = extra_precision_forms(lib, L, stream, dev, n, args.narrow_n,
                                                           args.reps)
         result["batch"] = extra_batch(lib, L, stream, args.reps)
         result["autograd"] = extra_autograd(lib, L, stream, args.reps)
         result["per_gpu_share"] = extra_share(lib, L, stream, calls, n // 8, args.reps)
+        with open(OPS_FILE) as fh:
+            result["inverse_trig"] = extra_inverse_trig(lib, L, stream, n, args.reps,
+                                                        json.load(fh))
         print("bench: extras in %.1f s" % (time.perf_counter() - t_x), file=sys.stderr,
               flush=True)
     if not args.no_cpu_baseline:

@@ -61,11 +61,14 @@ const char* libm_hip_version(void);
  * Unary functions, y[i] = f(x[i]).
  *
  * sin, cos, tan (Section 5, "sin and cos", "tan", "The Payne-Hanek Range
- * Reduction"): two Cody-Waite levels (|x| < 15, |x| < 1e14) and the
- * vectorised Payne-Hanek reduction for larger |x|; a sine polynomial on
+ * Reduction"): a Cody-Waite reduction for |x| < 1e14 (binary32: 65536) and
+ * the vectorised Payne-Hanek reduction above, chosen per element (the
+ * paper's bit-consistent arrangement, Section 3.3); a sine polynomial on
  * [-pi/2, pi/2]; tan through the double-angle formula on [-pi/8, pi/8].
- * exp (Section 5, "exp"), log (Section 5, "log").  exp2, log2, sinh, cosh
- * and tanh are not described in the paper and are built from the same
+ * exp (Section 5, "exp"), log (Section 5, "log").  asin, acos (Section 5,
+ * "asin and acos": reduction to [0, 0.5] through sqrt((1-x)/2)) and atan
+ * (Section 5, "atan": reduction to [0, 1] through 1/x).  exp2, log2, sinh,
+ * cosh and tanh are not described in the paper and are built from the same
  * reductions and double-double pieces.
  * ---------------------------------------------------------------------- */
 #define LIBM_HIP_DECL_UNARY(fn, var)                                                       \
@@ -94,6 +97,12 @@ LIBM_HIP_DECL_UNARY(log2, u10)
 LIBM_HIP_DECL_UNARY(sinh, u10)
 LIBM_HIP_DECL_UNARY(cosh, u10)
 LIBM_HIP_DECL_UNARY(tanh, u10)
+LIBM_HIP_DECL_UNARY(asin, u10)
+LIBM_HIP_DECL_UNARY(asin, u35)
+LIBM_HIP_DECL_UNARY(acos, u10)
+LIBM_HIP_DECL_UNARY(acos, u35)
+LIBM_HIP_DECL_UNARY(atan, u10)
+LIBM_HIP_DECL_UNARY(atan, u35)
 LIBM_HIP_DECL_UNARY_HALF(sin)
 LIBM_HIP_DECL_UNARY_HALF(cos)
 LIBM_HIP_DECL_UNARY_HALF(tan)
@@ -104,6 +113,9 @@ LIBM_HIP_DECL_UNARY_HALF(log2)
 LIBM_HIP_DECL_UNARY_HALF(sinh)
 LIBM_HIP_DECL_UNARY_HALF(cosh)
 LIBM_HIP_DECL_UNARY_HALF(tanh)
+LIBM_HIP_DECL_UNARY_HALF(asin)
+LIBM_HIP_DECL_UNARY_HALF(acos)
+LIBM_HIP_DECL_UNARY_HALF(atan)
 
 /* ------------------------------------------------------------------------
  * Binary functions, C argument order.
@@ -172,6 +184,7 @@ typedef enum {
   LIBM_HIP_SIN = 0, LIBM_HIP_COS, LIBM_HIP_TAN, LIBM_HIP_EXP, LIBM_HIP_EXP2,
   LIBM_HIP_LOG, LIBM_HIP_LOG2, LIBM_HIP_POW, LIBM_HIP_ATAN2, LIBM_HIP_SINH,
   LIBM_HIP_COSH, LIBM_HIP_TANH, LIBM_HIP_FMOD, LIBM_HIP_REMAINDER,
+  LIBM_HIP_ASIN, LIBM_HIP_ACOS, LIBM_HIP_ATAN,
   LIBM_HIP_NUM_FN
 } libm_hip_fn;
 typedef enum { LIBM_HIP_U10 = 0, LIBM_HIP_U35 = 1, LIBM_HIP_EXACT = 2 } libm_hip_variant;

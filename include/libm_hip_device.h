@@ -81,10 +81,17 @@ LIBM_HIP_DEVICE_UNARY(log2_u10, OpLog2U10)
 LIBM_HIP_DEVICE_UNARY(sinh_u10, OpSinhU10)
 LIBM_HIP_DEVICE_UNARY(cosh_u10, OpCoshU10)
 LIBM_HIP_DEVICE_UNARY(tanh_u10, OpTanhU10)
-/* 3.5-ULP trigonometric forms (binary64 and binary32) */
+/* asin, acos (Section 5, asin and acos), atan (Section 5, atan) */
+LIBM_HIP_DEVICE_UNARY(asin_u10, OpAsinU10)
+LIBM_HIP_DEVICE_UNARY(acos_u10, OpAcosU10)
+LIBM_HIP_DEVICE_UNARY(atan_u10, OpAtanU10)
+/* 3.5-ULP forms (binary64 and binary32) */
 LIBM_HIP_DEVICE_UNARY_WIDE(sin_u35, OpSinU35)
 LIBM_HIP_DEVICE_UNARY_WIDE(cos_u35, OpCosU35)
 LIBM_HIP_DEVICE_UNARY_WIDE(tan_u35, OpTanU35)
+LIBM_HIP_DEVICE_UNARY_WIDE(asin_u35, OpAsinU35)
+LIBM_HIP_DEVICE_UNARY_WIDE(acos_u35, OpAcosU35)
+LIBM_HIP_DEVICE_UNARY_WIDE(atan_u35, OpAtanU35)
 /* pow(x, y) (Section 5, pow) and atan2(y, x), C argument order */
 LIBM_HIP_DEVICE_BINARY(pow_u10, OpPowU10)
 LIBM_HIP_DEVICE_BINARY(atan2_u10, OpAtan2U10)

@@ -25,11 +25,13 @@ __all__ = ["load", "library_path", "UNARY", "BINARY", "VARIANTS", "entry_name",
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBNAME = "libm_hip.so"
 
-UNARY = ("sin", "cos", "tan", "exp", "exp2", "log", "log2", "sinh", "cosh", "tanh")
+UNARY = ("sin", "cos", "tan", "exp", "exp2", "log", "log2", "sinh", "cosh", "tanh",
+         "asin", "acos", "atan")
 BINARY = ("pow", "atan2", "fmod", "remainder")
 # accuracy variants served per function
 VARIANTS = {fn: ("u10",) for fn in UNARY + ("pow", "atan2")}
 VARIANTS.update({"sin": ("u10", "u35"), "cos": ("u10", "u35"), "tan": ("u10", "u35"),
+                 "asin": ("u10", "u35"), "acos": ("u10", "u35"), "atan": ("u10", "u35"),
                  "fmod": ("exact",), "remainder": ("exact",)})
 DTYPES = ("f64", "f32", "bf16", "f16", "f32_via_f64")
 
@@ -203,6 +205,7 @@ def _unary(fn):
 sin, cos, tan = _unary("sin"), _unary("cos"), _unary("tan")
 exp, exp2, log, log2 = _unary("exp"), _unary("exp2"), _unary("log"), _unary("log2")
 sinh, cosh, tanh = _unary("sinh"), _unary("cosh"), _unary("tanh")
+asin, acos, atan = _unary("asin"), _unary("acos"), _unary("atan")
 
 
 def pow(x, y, out=None, via_f64=False):
@@ -255,7 +258,7 @@ def backward(fn, inputs, gout, outs=None):
 # ---------------------------------------------------------------------------
 FN_CODES = {"sin": 0, "cos": 1, "tan": 2, "exp": 3, "exp2": 4, "log": 5, "log2": 6,
             "pow": 7, "atan2": 8, "sinh": 9, "cosh": 10, "tanh": 11, "fmod": 12,
-            "remainder": 13}
+            "remainder": 13, "asin": 14, "acos": 15, "atan": 16}
 VARIANT_CODES = {"u10": 0, "u35": 1, "exact": 2}
 DTYPE_CODES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "f32_via_f64": 4}
 

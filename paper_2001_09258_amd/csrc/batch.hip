@@ -77,14 +77,25 @@ struct Header {
   X(61, IoF64, OpAtan2U10, 2) X(62, IoF32, OpAtan2U10, 2) X(63, IoBF16, OpAtan2U10, 2) \
   X(64, IoF16, OpAtan2U10, 2) X(65, IoF32ViaF64, OpAtan2U10, 2)                 \
   X(66, IoF64, OpFmod, 2) X(67, IoF32, OpFmod, 2)                               \
-  X(68, IoF64, OpRemainder, 2) X(69, IoF32, OpRemainder, 2)
-constexpr int NUM_OPS = 70;
+  X(68, IoF64, OpRemainder, 2) X(69, IoF32, OpRemainder, 2)                     \
+  X(70, IoF64, OpAsinU10, 1) X(71, IoF32, OpAsinU10, 1) X(72, IoBF16, OpAsinU10, 1) \
+  X(73, IoF16, OpAsinU10, 1) X(74, IoF32ViaF64, OpAsinU10, 1)                   \
+  X(75, IoF64, OpAsinU35, 1) X(76, IoF32, OpAsinU35, 1)                         \
+  X(77, IoF64, OpAcosU10, 1) X(78, IoF32, OpAcosU10, 1) X(79, IoBF16, OpAcosU10, 1) \
+  X(80, IoF16, OpAcosU10, 1) X(81, IoF32ViaF64, OpAcosU10, 1)                   \
+  X(82, IoF64, OpAcosU35, 1) X(83, IoF32, OpAcosU35, 1)                         \
+  X(84, IoF64, OpAtanU10, 1) X(85, IoF32, OpAtanU10, 1) X(86, IoBF16, OpAtanU10, 1) \
+  X(87, IoF16, OpAtanU10, 1) X(88, IoF32ViaF64, OpAtanU10, 1)                   \
+  X(89, IoF64, OpAtanU35, 1) X(90, IoF32, OpAtanU35, 1)
+constexpr int NUM_OPS = 91;
 
 // host-side code of a (fn, variant, dtype) triple, or -1
 int op_code(int fn, int v, int t) {
   // dtype order in the table: f64, f32, bf16, f16, f32_via_f64
-  static const int u10_base[LIBM_HIP_NUM_FN] = {0, 7, 14, 21, 26, 31, 36, 56, 61, 41, 46, 51, -1, -1};
-  static const int u35_base[LIBM_HIP_NUM_FN] = {5, 12, 19, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
+  static const int u10_base[LIBM_HIP_NUM_FN] = {0, 7, 14, 21, 26, 31, 36, 56, 61, 41, 46, 51,
+                                                -1, -1, 70, 77, 84};
+  static const int u35_base[LIBM_HIP_NUM_FN] = {5, 12, 19, -1, -1, -1, -1, -1, -1, -1, -1, -1,
+                                                -1, -1, 75, 82, 89};
   if (fn < 0 || fn >= LIBM_HIP_NUM_FN || t < 0 || t > 4) return -1;
   if (fn == LIBM_HIP_FMOD || fn == LIBM_HIP_REMAINDER) {
     if (v != LIBM_HIP_EXACT || t > 1) return -1;
@@ -99,6 +110,7 @@ int op_code(int fn, int v, int t) {
 // (from the elementwise kernels' measured times: trig with Payne-Hanek and
 // the remainders are the most expensive, exp/log the cheapest)
 float op_cost(int code) {
+  if (code >= 70) return 0.6f;                 // asin, acos, atan
   if (code >= 66) return 1.5f;                 // fmod, remainder
   if (code <= 20) return 1.0f;                 // sin, cos, tan
   if (code >= 56) return 0.8f;                 // pow, atan2
@@ -106,7 +118,7 @@ float op_cost(int code) {
   return 0.35f;                                // exp, exp2, log, log2
 }
 
-size_t op_arity(int code) { return code >= 56 ? 2 : 1; }
+size_t op_arity(int code) { return code >= 56 && code <= 69 ? 2 : 1; }
 
 // ---- device side -------------------------------------------------------------
 // One tile of one request.  Kept out of line: each operation's tile loop is

@@ -373,6 +373,16 @@ LMH_INLINE float powf_u10(float x, float y) {
   return r;
 }
 
+// atan t for a pair 0 <= t <= 1 (binary32 form of atan_core)
+LMH_INLINE fff atanf_core(fff t) {
+  float z = t.hi * t.hi;
+  float a2 = poly_estrin(z, ATAN_A2_F32);
+  fff t3 = dd2_mul(dd2_squ(t), t);
+  fff c3 = dd2_mul(t3, mk(-THIRD_F_H, -THIRD_F_L));
+  float p5 = (t3.hi * z) * a2;
+  return dd2_add(dd2_add(t, c3), p5);
+}
+
 LMH_INLINE float atan2f_u10(float y, float x) {
   float ay = fabs_(y), ax = fabs_(x);
   bool both_inf = isinf_(ax) && isinf_(ay);
@@ -386,12 +396,7 @@ LMH_INLINE float atan2f_u10(float y, float x) {
   float nn = ldexp_(n, -de);
   fff t = dd2_div(mk(nn, 0.0f), mk(dn, 0.0f));
   t = isinf_(d) ? mk(0.0f, 0.0f) : t;
-  float z = t.hi * t.hi;
-  float a2 = poly_estrin(z, ATAN_A2_F32);
-  fff t3 = dd2_mul(dd2_squ(t), t);
-  fff c3 = dd2_mul(t3, mk(-THIRD_F_H, -THIRD_F_L));
-  float p5 = (t3.hi * z) * a2;
-  fff a = dd2_add(dd2_add(t, c3), p5);
+  fff a = atanf_core(t);
   if (t.hi < 0x1p-100f) {                           // see atan2_u10
     float q = n / d;
     float r = fma_(-ldexp_(q, 60), d, ldexp_(n, 60));
@@ -406,6 +411,83 @@ LMH_INLINE float atan2f_u10(float y, float x) {
   r = (isnan_(x) || isnan_(y)) ? __builtin_nanf("") : r;
   return r;
 }
+
+// ---------------------------------------------------------------------------
+// atan, asin, acos in binary32: the binary64 methods with float-float pairs
+// ---------------------------------------------------------------------------
+LMH_INLINE float atanf_u10(float x) {
+  float ax = fabs_(x);
+  bool big = ax > 1.0f;
+  fff t = big ? dd2_rec(mk(ax, 0.0f)) : mk(ax, 0.0f);
+  t = isinf_(ax) ? mk(0.0f, 0.0f) : t;
+  fff a = atanf_core(t);
+  if (big) a = dd2_add(mk(PIH2_F_H, PIH2_F_L), dd2_neg(a));
+  return copysign_(a.hi + a.lo, x);
+}
+
+LMH_INLINE float atanf_u35(float x) {
+  float ax = fabs_(x);
+  bool big = ax > 1.0f;
+  float t = big ? 1.0f / ax : ax;
+  float z = t * t;
+  float p = fma_(t * z, poly_estrin(z, ATAN_A_F32), t);
+  float r = big ? (PIH2_F_H - p) + PIH2_F_L : p;
+  return copysign_(r, x);
+}
+
+LMH_INLINE fff asinf_poly(fff s) {
+  float z = s.hi * s.hi;
+  float t = (s.hi * z) * poly_estrin(z, ASIN_S_F32);
+  return dd2_add(s, t);
+}
+
+LMH_INLINE fff asinf_reduce(float ax, bool exact_root) {
+  float z = (1.0f - ax) * 0.5f;
+  float sh = __builtin_sqrtf(z);
+  float e = fma_(-sh, sh, z);
+  float sl = (exact_root && z > 0.0f) ? e / (sh + sh) : 0.0f;
+  return mk(sh, sl);
+}
+
+template <bool U10>
+LMH_INLINE fff asinf_abs(float ax, bool& reduced) {
+  reduced = ax > 0.5f;
+  fff s = reduced ? asinf_reduce(ax, U10) : mk(ax, 0.0f);
+  return asinf_poly(s);
+}
+
+template <bool U10>
+LMH_INLINE float asinf_impl(float x) {
+  float ax = fabs_(x);
+  bool red;
+  fff a = asinf_abs<U10>(ax, red);
+  if (red) a = dd2_add(mk(PIH2_F_H, PIH2_F_L), dd2_scale(a, -2.0f));
+  float r = copysign_(a.hi + a.lo, x);
+  return ax > 1.0f ? __builtin_nanf("") : r;
+}
+
+template <bool U10>
+LMH_INLINE float acosf_impl(float x) {
+  float ax = fabs_(x);
+  bool red;
+  fff a = asinf_abs<U10>(ax, red);
+  bool neg = x < 0.0f;
+  fff r;
+  if (red) {
+    a = dd2_scale(a, 2.0f);
+    r = neg ? dd2_add(mk(PI2_F_H, PI2_F_L), dd2_neg(a)) : a;
+  } else {
+    a = neg ? dd2_neg(a) : a;
+    r = dd2_add(mk(PIH2_F_H, PIH2_F_L), dd2_neg(a));
+  }
+  float v = r.hi + r.lo;
+  return (ax > 1.0f || isnan_(x)) ? __builtin_nanf("") : v;
+}
+
+LMH_INLINE float asinf_u10(float x) { return asinf_impl<true>(x); }
+LMH_INLINE float asinf_u35(float x) { return asinf_impl<false>(x); }
+LMH_INLINE float acosf_u10(float x) { return acosf_impl<true>(x); }
+LMH_INLINE float acosf_u35(float x) { return acosf_impl<false>(x); }
 
 // ---------------------------------------------------------------------------
 // hyperbolic functions

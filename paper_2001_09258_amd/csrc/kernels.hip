@@ -240,6 +240,12 @@ LMH_DEF_UNARY(log2, u10, OpLog2U10, LOG2, U10)
 LMH_DEF_UNARY(sinh, u10, OpSinhU10, SINH, U10)
 LMH_DEF_UNARY(cosh, u10, OpCoshU10, COSH, U10)
 LMH_DEF_UNARY(tanh, u10, OpTanhU10, TANH, U10)
+LMH_DEF_UNARY(asin, u10, OpAsinU10, ASIN, U10)
+LMH_DEF_UNARY(asin, u35, OpAsinU35, ASIN, U35)
+LMH_DEF_UNARY(acos, u10, OpAcosU10, ACOS, U10)
+LMH_DEF_UNARY(acos, u35, OpAcosU35, ACOS, U35)
+LMH_DEF_UNARY(atan, u10, OpAtanU10, ATAN, U10)
+LMH_DEF_UNARY(atan, u35, OpAtanU35, ATAN, U35)
 LMH_DEF_UNARY_HALF(sin, OpSinU10, SIN)
 LMH_DEF_UNARY_HALF(cos, OpCosU10, COS)
 LMH_DEF_UNARY_HALF(tan, OpTanU10, TAN)
@@ -250,6 +256,9 @@ LMH_DEF_UNARY_HALF(log2, OpLog2U10, LOG2)
 LMH_DEF_UNARY_HALF(sinh, OpSinhU10, SINH)
 LMH_DEF_UNARY_HALF(cosh, OpCoshU10, COSH)
 LMH_DEF_UNARY_HALF(tanh, OpTanhU10, TANH)
+LMH_DEF_UNARY_HALF(asin, OpAsinU10, ASIN)
+LMH_DEF_UNARY_HALF(acos, OpAcosU10, ACOS)
+LMH_DEF_UNARY_HALF(atan, OpAtanU10, ATAN)
 
 #define LMH_DEF_BINARY(fn, var, Io, T, tag, Op, KEY)                                              \
   libm_hip_status libm_hip_##fn##var##_##tag(const T* a, const T* b, T* out, size_t n, void* s) { \
@@ -384,6 +393,18 @@ extern "C" libm_hip_status libm_hip_eval(libm_hip_fn fn, libm_hip_variant v, lib
     case LIBM_HIP_SINH: if (u10) return dispatch_unary<OpSinhU10>(t, a, out, n, s, false, key); break;
     case LIBM_HIP_COSH: if (u10) return dispatch_unary<OpCoshU10>(t, a, out, n, s, false, key); break;
     case LIBM_HIP_TANH: if (u10) return dispatch_unary<OpTanhU10>(t, a, out, n, s, false, key); break;
+    case LIBM_HIP_ASIN:
+      if (u10) return dispatch_unary<OpAsinU10>(t, a, out, n, s, false, key);
+      if (u35) return dispatch_unary<OpAsinU35>(t, a, out, n, s, true, key);
+      break;
+    case LIBM_HIP_ACOS:
+      if (u10) return dispatch_unary<OpAcosU10>(t, a, out, n, s, false, key);
+      if (u35) return dispatch_unary<OpAcosU35>(t, a, out, n, s, true, key);
+      break;
+    case LIBM_HIP_ATAN:
+      if (u10) return dispatch_unary<OpAtanU10>(t, a, out, n, s, false, key);
+      if (u35) return dispatch_unary<OpAtanU35>(t, a, out, n, s, true, key);
+      break;
     case LIBM_HIP_POW: if (u10) return dispatch_binary<OpPowU10>(t, a, b, out, n, s, true, key); break;
     case LIBM_HIP_ATAN2: if (u10) return dispatch_binary<OpAtan2U10>(t, a, b, out, n, s, true, key); break;
     case LIBM_HIP_FMOD:

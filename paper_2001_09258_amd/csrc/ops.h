@@ -101,6 +101,12 @@ LMH_OP1(OpLog2U10, log2_u10, log2f_u10)
 LMH_OP1(OpSinhU10, sinh_u10, sinhf_u10)
 LMH_OP1(OpCoshU10, cosh_u10, coshf_u10)
 LMH_OP1(OpTanhU10, tanh_u10, tanhf_u10)
+LMH_OP1(OpAsinU10, asin_u10, asinf_u10)
+LMH_OP1(OpAsinU35, asin_u35, asinf_u35)
+LMH_OP1(OpAcosU10, acos_u10, acosf_u10)
+LMH_OP1(OpAcosU35, acos_u35, acosf_u35)
+LMH_OP1(OpAtanU10, atan_u10, atanf_u10)
+LMH_OP1(OpAtanU35, atan_u35, atanf_u35)
 LMH_OP2(OpPowU10, pow_u10, powf_u10)
 LMH_OP2(OpAtan2U10, atan2_u10, atan2f_u10)
 LMH_OP2(OpFmod, fmod_f64, fmodf_f32)

@@ -112,6 +112,15 @@ def atan_a2():
     return f, w, mp.mpf(0), mp.mpf(1)
 
 
+def asin_s():
+    # asin x = x + x^3 S(x^2), |x| <= 1/2 (Section 5, asin/acos: the
+    # reduced argument lies in [0, 0.5])
+    f = _series_guard(lambda z: (mp.asin(mp.sqrt(z)) - mp.sqrt(z)) / z ** mp.mpf(1.5),
+                      lambda z: mp.mpf(1) / 6 + 3 * z / 40 + 15 * z ** 2 / 336)
+    w = lambda z: z ** mp.mpf(1.5) / mp.asin(mp.sqrt(z)) if z > 0 else mp.mpf(0)
+    return f, w, mp.mpf(0), mp.mpf(1) / 4 * mp.mpf("1.0001")
+
+
 def sinh_h():
     # sinh x = x + x^3 H(x^2), |x| <= 1
     f = _series_guard(lambda z: (mp.sinh(mp.sqrt(z)) - mp.sqrt(z)) / z ** mp.mpf(1.5),
@@ -140,6 +149,7 @@ SPECS = [
     ("ATAN_A_F64", atan_a, "f64", -58, 16),
     ("ATAN_A2_F64", atan_a2, "f64", -61, 16),
     ("SINH_H_F64", sinh_h, "f64", -62, 5),
+    ("ASIN_S_F64", asin_s, "f64", -58, 8),
     ("TANH_G_F64", tanh_g, "f64", -62, 9),
     ("EXP_P_F32", exp_p, "f32", -32, 4),
     ("LOG_Q_F32", log_q, "f32", -31, 2),
@@ -151,6 +161,7 @@ SPECS = [
     ("ATAN_A_F32", atan_a, "f32", -28, 6),
     ("ATAN_A2_F32", atan_a2, "f32", -31, 6),
     ("SINH_H_F32", sinh_h, "f32", -31, 2),
+    ("ASIN_S_F32", asin_s, "f32", -29, 3),
     ("TANH_G_F32", tanh_g, "f32", -31, 4),
 ]
 

@@ -22,6 +22,12 @@ K1(p64_log2, double, log2_u10(v))
 K1(p64_sinh, double, sinh_u10(v))
 K1(p64_cosh, double, cosh_u10(v))
 K1(p64_tanh, double, tanh_u10(v))
+K1(p64_asin, double, asin_u10(v))
+K1(p64_asin35, double, asin_u35(v))
+K1(p64_acos, double, acos_u10(v))
+K1(p64_acos35, double, acos_u35(v))
+K1(p64_atan, double, atan_u10(v))
+K1(p64_atan35, double, atan_u35(v))
 __global__ void p64_pow(const double* x, double* y) { int i = threadIdx.x; y[i] = pow_u10(x[i], x[i+64]); }
 __global__ void p64_atan2(const double* x, double* y) { int i = threadIdx.x; y[i] = atan2_u10(x[i], x[i+64]); }
 // binary32 pieces
@@ -38,5 +44,11 @@ K1(p32_log2, float, log2f_u10(v))
 K1(p32_sinh, float, sinhf_u10(v))
 K1(p32_cosh, float, coshf_u10(v))
 K1(p32_tanh, float, tanhf_u10(v))
+K1(p32_asin, float, asinf_u10(v))
+K1(p32_asin35, float, asinf_u35(v))
+K1(p32_acos, float, acosf_u10(v))
+K1(p32_acos35, float, acosf_u35(v))
+K1(p32_atan, float, atanf_u10(v))
+K1(p32_atan35, float, atanf_u35(v))
 __global__ void p32_pow(const float* x, float* y) { int i = threadIdx.x; y[i] = powf_u10(x[i], x[i+64]); }
 __global__ void p32_atan2(const float* x, float* y) { int i = threadIdx.x; y[i] = atan2f_u10(x[i], x[i+64]); }

@@ -83,6 +83,9 @@ extern "C" int device_api_eval(int fn, int variant, int dtype, const void* a, co
       case 0: U1W(sin_u35)
       case 1: U1W(cos_u35)
       case 2: U1W(tan_u35)
+      case 14: U1W(asin_u35)
+      case 15: U1W(acos_u35)
+      case 16: U1W(atan_u35)
     }
     return 2;
   }
@@ -101,6 +104,9 @@ extern "C" int device_api_eval(int fn, int variant, int dtype, const void* a, co
     case 11: U1(tanh_u10)
     case 12: B2W(fmod)
     case 13: B2W(remainder)
+    case 14: U1(asin_u10)
+    case 15: U1(acos_u10)
+    case 16: U1(atan_u10)
   }
   return 2;
 }

@@ -89,3 +89,23 @@ def test_batch_validation_errors():
         plan.run([("exp", "u10", "f64", y, None, y)] * 5)
     plan.run([])                                        # empty list: nothing to do
     plan.close()
+
+
+def test_batch_inverse_trig_requests():
+    """asin, acos, atan in every served variant and dtype through one plan."""
+    reqs = []
+    for i, (fn, v, dt) in enumerate([(f, v, d) for f in ("asin", "acos", "atan")
+                                     for v in ("u10", "u35")
+                                     for d in ("f64", "f32", "bf16", "f16", "f32_via_f64")
+                                     if v == "u10" or d in ("f64", "f32")]):
+        base = "f32" if dt == "f32_via_f64" else dt
+        a = W.function_mixture(fn, base, 5000 + 997 * i, 300 + i)
+        ta = to_device(a, dt)
+        reqs.append((fn, v, dt, ta, None, torch.empty_like(ta)))
+    ref = _reference(reqs)
+    plan = L.BatchPlan(64, use_graph=True)
+    plan.run(reqs)
+    torch.cuda.synchronize()
+    for (fn, v, dt, a, b, out), r in zip(reqs, ref):
+        assert _same(out, r), (fn, v, dt)
+    plan.close()

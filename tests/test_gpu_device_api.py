@@ -52,10 +52,7 @@ def _same(y0, y1):
 
 def _inputs(fn, dt, operand):
     base = "f32" if dt == "f32_via_f64" else dt
-    if base in ("bf16", "f16"):
-        a = W.narrow_mixture(fn, base, N, 60 + operand)
-    else:
-        a = W.mixture(fn, base, N, 60 + operand)
+    a = W.function_mixture(fn, base, N, 60 + operand)
     sp = W.specials(base)
     a[:sp.size] = sp
     return a

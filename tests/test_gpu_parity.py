@@ -30,9 +30,7 @@ BINARY = ("pow", "atan2", "fmod", "remainder")
 def _inputs(cfg, fn, dt, n, operand):
     base = "f32" if dt == "f32_via_f64" else dt
     if cfg == 2:
-        if base in ("bf16", "f16"):
-            return W.narrow_mixture(fn, base, n, operand)
-        return W.mixture(fn, base, n, operand)
+        return W.function_mixture(fn, base, n, operand)
     return W.large_args(fn, base, n, operand)
 
 
@@ -77,7 +75,9 @@ SPECIAL_F64 = [0.0, -0.0, math.inf, -math.inf, math.nan, 5e-324, -5e-324,
                2.2250738585072009e-308, -2.2250738585072009e-308, 2.2250738585072014e-308,
                1.0, -1.0, 0.5, -0.5, 2.0, -2.0, 3.0, -3.0, 1.7976931348623157e308,
                -1.7976931348623157e308, 709.782712893384, 709.7827128933841, -745.1332191019411,
-               -745.1332191019412, 710.4758600739439, 1e-300, 1e22, 1e300, 0.75, 1.5]
+               -745.1332191019412, 710.4758600739439, 1e-300, 1e22, 1e300, 0.75, 1.5,
+               0.9999999999999999, -0.9999999999999999, 0.5000000000000001,
+               -0.5000000000000001, 0.49999999999999994, 1.0000000000000002]
 
 
 def _special_inputs(dt, binary):

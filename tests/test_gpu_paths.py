@@ -24,8 +24,9 @@ N = 3 * 4096 + 37
 TRIG = [(fn, v, dt) for fn in ("sin", "cos", "tan") for v in ("u10", "u35")
         for dt in ("f64", "f32")] + [(fn, "u10", dt) for fn in ("sin", "cos", "tan")
                                      for dt in ("bf16", "f16", "f32_via_f64")]
-OTHERS = [(fn, "u10", dt) for fn in ("exp", "log", "pow", "atan2", "tanh")
-          for dt in ("f64", "f32")] + [("fmod", "exact", "f64"), ("remainder", "exact", "f32")]
+OTHERS = [(fn, "u10", dt) for fn in ("exp", "log", "pow", "atan2", "tanh", "asin", "acos")
+          for dt in ("f64", "f32")] + [("atan", "u35", "f64"), ("acos", "u35", "f32"),
+                                       ("fmod", "exact", "f64"), ("remainder", "exact", "f32")]
 BINARY = ("pow", "atan2", "fmod", "remainder")
 SLOW = {"f64": 1e14, "f32": 65536.0, "bf16": 65536.0, "f16": 65536.0, "f32_via_f64": 1e14}
 
@@ -39,9 +40,7 @@ def _gpu():
 
 def _inputs(fn, dt, operand):
     base = "f32" if dt == "f32_via_f64" else dt
-    if base in ("bf16", "f16"):
-        return W.narrow_mixture(fn, base, N, 40 + operand)
-    return W.mixture(fn, base, N, 40 + operand)
+    return W.function_mixture(fn, base, N, 40 + operand)
 
 
 def _run(fn, v, dt, a, b):

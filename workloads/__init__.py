@@ -19,12 +19,13 @@ import numpy as np
 
 __all__ = ["FN_IDS", "rng_for", "specials", "small_set", "mixture", "large_args",
            "narrow_mixture", "batch_requests", "autograd_inputs", "paper_domain",
+           "unit_mixture", "function_mixture",
            "PAPER_DOMAINS", "round_to_bf16", "to_bf16_bits",
            "from_bf16_bits", "np_dtype"]
 
 FN_IDS = {name: i for i, name in enumerate(
     ["sin", "cos", "tan", "exp", "exp2", "log", "log2", "pow", "atan2",
-     "sinh", "cosh", "tanh", "fmod", "remainder"])}
+     "sinh", "cosh", "tanh", "fmod", "remainder", "asin", "acos", "atan"])}
 
 DTYPE_MAX = {"f64": np.finfo(np.float64).max, "f32": float(np.finfo(np.float32).max),
              "f16": 65504.0, "bf16": 3.3895313892515355e38}
@@ -165,6 +166,41 @@ def narrow_mixture(fn, dt, n=1 << 28, operand=0):
     x = _mixture(rng, n, dt, lo, hi)
     with np.errstate(over="ignore"):
         return _cast(x, dt)
+
+
+def unit_mixture(fn, dt, n=1 << 26, operand=0):
+    """Arguments for asin/acos, whose domain is [-1, 1]: per element 45%
+    U[-1, 1], 25% sign * (1 - 10^U[-16, 0]) (binary32 and narrower: [-7, 0];
+    the region next to +-1 where the reduction matters), 20% sign *
+    10^U[lo, 0] (tiny arguments down to the format's subnormals), 9% outside
+    the domain (sign * 10^U[0, hi], NaN results), 1% the special set."""
+    rng = rng_for(8, fn, operand)
+    near = -16.0 if dt == "f64" else -7.0
+    lo = np.log10(DTYPE_MIN_SUB[dt])
+    hi = np.log10(DTYPE_MAX[dt])
+    cat = rng.random(n)
+    sign = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    x = rng.uniform(-1.0, 1.0, n)
+    m = (cat >= 0.45) & (cat < 0.70)
+    x[m] = sign[m] * (1.0 - np.exp(rng.uniform(near, 0.0, int(m.sum())) * np.log(10.0)))
+    m = (cat >= 0.70) & (cat < 0.90)
+    x[m] = sign[m] * np.exp(rng.uniform(lo, 0.0, int(m.sum())) * np.log(10.0))
+    m = (cat >= 0.90) & (cat < 0.99)
+    x[m] = sign[m] * np.exp(rng.uniform(0.0, hi, int(m.sum())) * np.log(10.0))
+    m = cat >= 0.99
+    x[m] = specials(dt)[rng.integers(0, 9, int(m.sum()))]
+    with np.errstate(over="ignore"):
+        return _cast(x, dt)
+
+
+def function_mixture(fn, dt, n=1 << 26, operand=0):
+    """The benchmark-style input of ``fn``: ``unit_mixture`` for asin and
+    acos, otherwise the mixture (bf16/f16: its narrow form)."""
+    if fn in ("asin", "acos"):
+        return unit_mixture(fn, dt, n, operand)
+    if dt in ("bf16", "f16"):
+        return narrow_mixture(fn, dt, n, operand)
+    return mixture(fn, dt, n, operand)
 
 
 # every (fn, variant) the library serves, used to draw batched requests
