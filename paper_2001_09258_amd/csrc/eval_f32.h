@@ -373,14 +373,25 @@ LMH_INLINE float powf_u10(float x, float y) {
   return r;
 }
 
-// atan t for a pair 0 <= t <= 1 (binary32 form of atan_core)
-LMH_INLINE fff atanf_core(fff t) {
-  float z = t.hi * t.hi;
-  float a2 = poly_estrin(z, ATAN_A2_F32);
-  fff t3 = dd2_mul(dd2_squ(t), t);
-  fff c3 = dd2_mul(t3, mk(-THIRD_F_H, -THIRD_F_L));
-  float p5 = (t3.hi * z) * a2;
-  return dd2_add(dd2_add(t, c3), p5);
+// binary32 forms of atan_poly / atan_ratio (the extra reduction above
+// tan(pi/8) through pi/4 + atan((n - d)/(n + d)))
+constexpr float TAN_PI8_F = 0x1.a82798p-2f;           // tan(pi/8), rounded down
+LMH_INLINE fff atanf_poly(fff v) {
+  float z = v.hi * v.hi;
+  float b2 = poly_estrin(z, ATAN_B2_F32);
+  fff v3 = dd2_mul(dd2_squ(v), v);
+  fff c3 = dd2_mul(v3, mk(-THIRD_F_H, -THIRD_F_L));
+  float p5 = (v3.hi * z) * b2;
+  return dd2_add(dd2_add(v, c3), p5);
+}
+
+LMH_INLINE fff atanf_ratio(float n, float d, fff& q, bool& red) {
+  red = n > TAN_PI8_F * d;
+  fff num = red ? dd2_add2(n, -d) : mk(n, 0.0f);
+  fff den = red ? dd2_add2(n, d) : mk(d, 0.0f);
+  q = dd2_div(num, den);
+  fff a = atanf_poly(red ? dd2_neg(q) : q);
+  return red ? dd2_add(mk(0.5f * PIH2_F_H, 0.5f * PIH2_F_L), dd2_neg(a)) : a;
 }
 
 LMH_INLINE float atan2f_u10(float y, float x) {
@@ -394,10 +405,12 @@ LMH_INLINE float atan2f_u10(float y, float x) {
   int de = frexp_exp_(d);
   float dn = ldexp_(d, -de);
   float nn = ldexp_(n, -de);
-  fff t = dd2_div(mk(nn, 0.0f), mk(dn, 0.0f));
+  fff t;
+  bool red;
+  fff a = atanf_ratio(nn, dn, t, red);
   t = isinf_(d) ? mk(0.0f, 0.0f) : t;
-  fff a = atanf_core(t);
-  if (t.hi < 0x1p-100f) {                           // see atan2_u10
+  a = isinf_(d) ? mk(0.0f, 0.0f) : a;
+  if (!red && t.hi < 0x1p-100f) {                           // see atan2_u10
     float q = n / d;
     float r = fma_(-ldexp_(q, 60), d, ldexp_(n, 60));
     bool tie_up = r < 0.0f && -r == ldexp_(d, -90);
@@ -418,9 +431,10 @@ LMH_INLINE float atan2f_u10(float y, float x) {
 LMH_INLINE float atanf_u10(float x) {
   float ax = fabs_(x);
   bool big = ax > 1.0f;
-  fff t = big ? dd2_rec(mk(ax, 0.0f)) : mk(ax, 0.0f);
-  t = isinf_(ax) ? mk(0.0f, 0.0f) : t;
-  fff a = atanf_core(t);
+  fff t;
+  bool red;
+  fff a = atanf_ratio(big ? 1.0f : ax, big ? ax : 1.0f, t, red);
+  a = isinf_(ax) ? mk(0.0f, 0.0f) : a;
   if (big) a = dd2_add(mk(PIH2_F_H, PIH2_F_L), dd2_neg(a));
   return copysign_(a.hi + a.lo, x);
 }

@@ -112,6 +112,16 @@ def atan_a2():
     return f, w, mp.mpf(0), mp.mpf(1)
 
 
+def atan_b2():
+    # atan v = v - v^3/3 + v^5 B2(v^2), 0 <= v <= tan(pi/8): the argument
+    # after atan t = pi/4 + atan((t - 1)/(t + 1)) for t > tan(pi/8)
+    f = _series_guard(lambda z: (mp.atan(mp.sqrt(z)) - mp.sqrt(z) + z ** mp.mpf(1.5) / 3)
+                      / z ** mp.mpf(2.5),
+                      lambda z: mp.mpf(1) / 5 - z / 7 + z ** 2 / 9)
+    w = lambda z: z ** mp.mpf(2.5) / mp.atan(mp.sqrt(z)) if z > 0 else mp.mpf(0)
+    return f, w, mp.mpf(0), mp.tan(mp.pi / 8) ** 2 * mp.mpf("1.001")
+
+
 def asin_s():
     # asin x = x + x^3 S(x^2), |x| <= 1/2 (Section 5, asin/acos: the
     # reduced argument lies in [0, 0.5])
@@ -148,6 +158,7 @@ SPECS = [
     ("TAN_T_F64", tan_t, "f64", -62, 8),
     ("ATAN_A_F64", atan_a, "f64", -58, 16),
     ("ATAN_A2_F64", atan_a2, "f64", -61, 16),
+    ("ATAN_B2_F64", atan_b2, "f64", -62, 6),
     ("SINH_H_F64", sinh_h, "f64", -62, 5),
     ("ASIN_S_F64", asin_s, "f64", -58, 8),
     ("TANH_G_F64", tanh_g, "f64", -62, 9),
@@ -160,6 +171,7 @@ SPECS = [
     ("TAN_T_F32", tan_t, "f32", -31, 3),
     ("ATAN_A_F32", atan_a, "f32", -28, 6),
     ("ATAN_A2_F32", atan_a2, "f32", -31, 6),
+    ("ATAN_B2_F32", atan_b2, "f32", -32, 2),
     ("SINH_H_F32", sinh_h, "f32", -31, 2),
     ("ASIN_S_F32", asin_s, "f32", -29, 3),
     ("TANH_G_F32", tanh_g, "f32", -31, 4),
