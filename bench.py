@@ -150,20 +150,31 @@ U10_SET = ["sin", "cos", "tan", "exp", "exp2", "log", "log2", "pow", "atan2", "s
            "cosh", "tanh"]
 
 
+_FLUSH = []
+
+
 def time_launches(stream, fn_calls, reps):
-    """Average ms of each zero-argument launcher, HIP events on ``stream``."""
+    """Average ms of each zero-argument launcher, HIP events on ``stream``
+    around every launch.  Before each timed launch a 512 MiB buffer is
+    overwritten (untimed) so that no launch finds its operands in the
+    256 MiB last-level cache left warm by the previous one."""
     import torch
+    if not _FLUSH:
+        _FLUSH.append(torch.empty(1 << 26, dtype=torch.float64, device="cuda"))
     out = []
     for f in fn_calls:
         f()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
+        total = 0.0
         for _ in range(reps):
+            _FLUSH[0].fill_(1.0)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
             f()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        out.append(e0.elapsed_time(e1) / reps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            total += e0.elapsed_time(e1)
+        out.append(total / reps)
     return out
 
 
@@ -491,15 +502,8 @@ def main():
     # same number of binary64 elements, 16 bytes per element
     src = dev[calls[0][0]][0]
     dst = torch.empty_like(src)
-    torch.neg(src, out=dst)
-    c0 = torch.cuda.Event(enable_timing=True)
-    c1 = torch.cuda.Event(enable_timing=True)
-    c0.record(stream)
-    for _ in range(args.reps):
-        torch.neg(src, out=dst)
-    c1.record(stream)
-    torch.cuda.synchronize()
-    copy_gbs = 16 * n / (c0.elapsed_time(c1) / args.reps * 1e-3) / 1e9
+    copy_ms = time_launches(stream, [lambda: torch.neg(src, out=dst)], args.reps)[0]
+    copy_gbs = 16 * n / (copy_ms * 1e-3) / 1e9
     del dst
 
     result = {"metric": "Gelem/s per function at <=1.0/3.5 ULP; % of HBM or VALU roofline",
