@@ -358,6 +358,32 @@ def extra_inverse_trig(lib, L, stream, n, reps, ops):
     return res
 
 
+def extra_sorted_paths(lib, L, stream, host, n, reps):
+    """Ablation: the trig kernels on the same inputs sorted so that
+    Cody-Waite and Payne-Hanek elements never share a wave, against the
+    mixed order of the step (the cost of path divergence)."""
+    import numpy as np
+    import torch
+    sh = stream.cuda_stream
+    res = {}
+    for fn in ("sin", "tan"):
+        for dt in ("f64", "f32"):
+            a = host[(fn, "u10", dt)][0]
+            order = np.argsort(~(np.abs(a) < SLOW_TRIG[dt]), kind="stable")
+            ts = torch.from_numpy(np.ascontiguousarray(a[order])).cuda()
+            tm = torch.from_numpy(a).cuda()
+            to = torch.empty_like(ts)
+            nm = L.entry_name(fn, "u10", dt)
+            f = getattr(lib, nm)
+            ms_m, ms_s = time_launches(stream, [
+                checked(lib, nm, f, tm.data_ptr(), to.data_ptr(), n, sh),
+                checked(lib, nm, f, ts.data_ptr(), to.data_ptr(), n, sh)], reps)
+            res["%s_u10_%s" % (fn, dt)] = {"mixed_ms": round(ms_m, 4), "sorted_ms": round(ms_s, 4),
+                                           "speedup_sorted": round(ms_m / ms_s, 3)}
+            del ts, tm, to
+    return res
+
+
 def cpu_baseline(inputs, sample):
     """The oracle as it stands, on the first ``sample`` elements of every
     (function, dtype) input of the step, over a process pool on all cores."""
@@ -533,6 +559,7 @@ def main():
         with open(OPS_FILE) as fh:
             result["inverse_trig"] = extra_inverse_trig(lib, L, stream, n, args.reps,
                                                         json.load(fh))
+        result["trig_sorted_by_path"] = extra_sorted_paths(lib, L, stream, host, n, args.reps)
         print("bench: extras in %.1f s" % (time.perf_counter() - t_x), file=sys.stderr,
               flush=True)
     if not args.no_cpu_baseline:

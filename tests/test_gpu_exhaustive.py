@@ -72,7 +72,9 @@ def test_binary32_sweep(fn, variant):
     bound = BOUND[variant]
     total = flagged = 0
     worst = 0.0
-    for start in range(0, 1 << 32, CHUNK * STRIDE):
+    for ci, start in enumerate(range(0, 1 << 32, CHUNK * STRIDE)):
+        if ci and ci % 32 == 0:
+            print("  sweep %s %s: %d patterns so far" % (fn, variant, total), flush=True)
         stop = min(start + CHUNK * STRIDE, 1 << 32)
         bits = np.arange(start, stop, STRIDE, dtype=np.uint64).astype(np.uint32)
         x32 = bits.view(np.float32)
