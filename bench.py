@@ -155,18 +155,19 @@ _FLUSH = []
 
 def time_launches(stream, fn_calls, reps):
     """Average ms of each zero-argument launcher, HIP events on ``stream``
-    around every launch.  Before each timed launch a 512 MiB buffer is
-    overwritten (untimed) so that no launch finds its operands in the
-    256 MiB last-level cache left warm by the previous one."""
+    around every launch.  Before each timed launch a 512 MiB buffer is read
+    (untimed) so that no launch finds its operands in the 256 MiB
+    last-level cache left warm by the previous one; a read leaves clean
+    lines, so the timed launch pays no write-back for it."""
     import torch
     if not _FLUSH:
-        _FLUSH.append(torch.empty(1 << 26, dtype=torch.float64, device="cuda"))
+        _FLUSH.append(torch.ones(1 << 26, dtype=torch.float64, device="cuda"))
     out = []
     for f in fn_calls:
         f()
         total = 0.0
         for _ in range(reps):
-            _FLUSH[0].fill_(1.0)
+            _FLUSH[0].sum()
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)

@@ -64,14 +64,16 @@ def _screen(y, ref, bound):
         flag = finite & ~(err <= bound - 1e-4)
         flag |= ~finite & ~same
         flag |= ((np.abs(rn) < tiny) | (np.abs(y) < tiny)) & ~same
-    return np.nonzero(flag)[0]
+        ok = finite & ~flag
+        est = float(err[ok].max()) if ok.any() else 0.0
+    return np.nonzero(flag)[0], est
 
 
 @pytest.mark.parametrize("fn,variant", SWEEP, ids=["-".join(c) for c in SWEEP])
 def test_binary32_sweep(fn, variant):
     bound = BOUND[variant]
     total = flagged = 0
-    worst = 0.0
+    worst = est_max = 0.0
     for ci, start in enumerate(range(0, 1 << 32, CHUNK * STRIDE)):
         if ci and ci % 32 == 0:
             print("  sweep %s %s: %d patterns so far" % (fn, variant, total), flush=True)
@@ -84,7 +86,8 @@ def test_binary32_sweep(fn, variant):
         y = yd.cpu().numpy().astype(np.float64)
         x64 = x32.astype(np.float64)
         ref = _host_ref(NP_F[fn], x64)
-        idx = _screen(y, ref, bound)
+        idx, est = _screen(y, ref, bound)
+        est_max = max(est_max, est)
         total += bits.size
         if idx.size:
             flagged += idx.size
@@ -97,8 +100,9 @@ def test_binary32_sweep(fn, variant):
                 "%s %s: x=%r y=%r want %r (max %.3f ulp)" % (
                     fn, variant, x64[idx][bad], y[idx][bad], rn[bad], res["max_ulp"])
             worst = max(worst, res["max_ulp"])
-    print("sweep %s %s f32: %d patterns (stride %d), %d decided by the oracle, worst of "
-          "those %.3f ulp" % (fn, variant, total, STRIDE, flagged, worst), flush=True)
+    print("sweep %s %s f32: %d patterns (stride %d), max error %.4f ulp (binary64 screen), "
+          "%d decided by the oracle, worst of those %.3f ulp"
+          % (fn, variant, total, STRIDE, est_max, flagged, worst), flush=True)
 
 
 NARROW_UNARY = ["sin", "cos", "tan", "exp", "exp2", "log", "log2", "sinh", "cosh", "tanh",
