@@ -18,6 +18,7 @@
   cosh^2 - sinh^2 = 1, exp(log x) = x.
 """
 import math
+import os
 import random
 import warnings
 
@@ -385,3 +386,35 @@ def test_identities_on_balls():
         back = exp_ball(L, 200)
         ratio = B.div(back, B.from_float(x), 200)
         assert _contains_one(ratio)
+
+
+def test_regression_inputs_are_valid_and_oracle_agrees_with_mpmath():
+    """tests/golden/regressions.txt: every value is exactly representable in
+    its dtype, and the oracle's binary64 result agrees with mpmath."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "regressions.txt")
+    conv = {"f64": np.float64, "f32": np.float32, "f16": np.float16}
+    n = 0
+    for line in open(path):
+        line = line.split("#", 1)[0].strip()
+        if not line:
+            continue
+        fn, v, dt, *vals = line.split()
+        xs = [float.fromhex(x) for x in vals]
+        for x in xs:
+            assert float(conv[dt](x)) == x or math.isnan(x), (line, x)
+        got = evaluate1(fn, "f64", *xs)[0]
+        v = _mp_f64(fn, *xs)
+        if v == 0 and len(xs) == 1:
+            # mpmath has no signed zero: the host libm gives the Annex F sign
+            assert same(got, float(NP_UNARY[fn](np.float64(xs[0])))), (line, got)
+        elif v == 0 or not mpmath.isfinite(v):
+            assert same(got, _to_f64(v)), (line, got, v)
+        else:
+            # nearest binary64 to the 400-bit value (mpmath's own float()
+            # rounds twice for subnormal results)
+            with mpmath.workprec(400):
+                d = [abs(mpmath.mpf(c) - v) for c in
+                     (got, math.nextafter(got, math.inf), math.nextafter(got, -math.inf))]
+            assert d[0] <= d[1] and d[0] <= d[2], (line, got)
+        n += 1
+    assert n >= 10
