@@ -331,19 +331,19 @@ def extra_share(lib, L, stream, calls, n_share, reps):
 
 
 def extra_inverse_trig(lib, L, stream, n, reps, ops):
-    """asin, acos, atan (u10 and u35, binary64 and binary32) on 2^26
-    elements each: asin/acos on the unit-interval mixture, atan on the
-    mixture; per kernel the same roofline fractions as the step's."""
+    """asin, acos, atan (u10 and u35) and log u35, binary64 and binary32, on
+    2^26 elements each: asin/acos on the unit-interval mixture, atan and log
+    on the mixture; per kernel the same roofline fractions as the step's."""
     import torch
     import workloads as W
     sh = stream.cuda_stream
     res = {}
-    for fn in ("asin", "acos", "atan"):
+    for fn in ("asin", "acos", "atan", "log"):
         for dt in ("f64", "f32"):
             a = W.function_mixture(fn, dt, n, 0)
             ta = torch.from_numpy(a).cuda()
             to = torch.empty_like(ta)
-            for v in ("u10", "u35"):
+            for v in (("u35",) if fn == "log" else ("u10", "u35")):
                 nm = L.entry_name(fn, v, dt)
                 ms = time_launches(stream, [checked(lib, nm, getattr(lib, nm), ta.data_ptr(),
                                                     to.data_ptr(), n, sh)], reps)[0]

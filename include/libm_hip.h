@@ -65,7 +65,7 @@ const char* libm_hip_version(void);
  * the vectorised Payne-Hanek reduction above, chosen per element (the
  * paper's bit-consistent arrangement, Section 3.3); a sine polynomial on
  * [-pi/2, pi/2]; tan through the double-angle formula on [-pi/8, pi/8].
- * exp (Section 5, "exp"), log (Section 5, "log").  asin, acos (Section 5,
+ * exp (Section 5, "exp"), log (Section 5, "log"; also a 3.5-ULP form).  asin, acos (Section 5,
  * "asin and acos": reduction to [0, 0.5] through sqrt((1-x)/2)) and atan
  * (Section 5, "atan": reduction to [0, 1] through 1/x).  exp2, log2, sinh,
  * cosh and tanh are not described in the paper and are built from the same
@@ -93,6 +93,7 @@ LIBM_HIP_DECL_UNARY(tan, u35)
 LIBM_HIP_DECL_UNARY(exp, u10)
 LIBM_HIP_DECL_UNARY(exp2, u10)
 LIBM_HIP_DECL_UNARY(log, u10)
+LIBM_HIP_DECL_UNARY(log, u35)
 LIBM_HIP_DECL_UNARY(log2, u10)
 LIBM_HIP_DECL_UNARY(sinh, u10)
 LIBM_HIP_DECL_UNARY(cosh, u10)

@@ -92,6 +92,7 @@ LIBM_HIP_DEVICE_UNARY_WIDE(tan_u35, OpTanU35)
 LIBM_HIP_DEVICE_UNARY_WIDE(asin_u35, OpAsinU35)
 LIBM_HIP_DEVICE_UNARY_WIDE(acos_u35, OpAcosU35)
 LIBM_HIP_DEVICE_UNARY_WIDE(atan_u35, OpAtanU35)
+LIBM_HIP_DEVICE_UNARY_WIDE(log_u35, OpLogU35)
 /* pow(x, y) (Section 5, pow) and atan2(y, x), C argument order */
 LIBM_HIP_DEVICE_BINARY(pow_u10, OpPowU10)
 LIBM_HIP_DEVICE_BINARY(atan2_u10, OpAtan2U10)

@@ -32,6 +32,7 @@ BINARY = ("pow", "atan2", "fmod", "remainder")
 VARIANTS = {fn: ("u10",) for fn in UNARY + ("pow", "atan2")}
 VARIANTS.update({"sin": ("u10", "u35"), "cos": ("u10", "u35"), "tan": ("u10", "u35"),
                  "asin": ("u10", "u35"), "acos": ("u10", "u35"), "atan": ("u10", "u35"),
+                 "log": ("u10", "u35"),
                  "fmod": ("exact",), "remainder": ("exact",)})
 DTYPES = ("f64", "f32", "bf16", "f16", "f32_via_f64")
 

@@ -86,15 +86,16 @@ struct Header {
   X(82, IoF64, OpAcosU35, 1) X(83, IoF32, OpAcosU35, 1)                         \
   X(84, IoF64, OpAtanU10, 1) X(85, IoF32, OpAtanU10, 1) X(86, IoBF16, OpAtanU10, 1) \
   X(87, IoF16, OpAtanU10, 1) X(88, IoF32ViaF64, OpAtanU10, 1)                   \
-  X(89, IoF64, OpAtanU35, 1) X(90, IoF32, OpAtanU35, 1)
-constexpr int NUM_OPS = 91;
+  X(89, IoF64, OpAtanU35, 1) X(90, IoF32, OpAtanU35, 1)                         \
+  X(91, IoF64, OpLogU35, 1) X(92, IoF32, OpLogU35, 1)
+constexpr int NUM_OPS = 93;
 
 // host-side code of a (fn, variant, dtype) triple, or -1
 int op_code(int fn, int v, int t) {
   // dtype order in the table: f64, f32, bf16, f16, f32_via_f64
   static const int u10_base[LIBM_HIP_NUM_FN] = {0, 7, 14, 21, 26, 31, 36, 56, 61, 41, 46, 51,
                                                 -1, -1, 70, 77, 84};
-  static const int u35_base[LIBM_HIP_NUM_FN] = {5, 12, 19, -1, -1, -1, -1, -1, -1, -1, -1, -1,
+  static const int u35_base[LIBM_HIP_NUM_FN] = {5, 12, 19, -1, -1, 91, -1, -1, -1, -1, -1, -1,
                                                 -1, -1, 75, 82, 89};
   if (fn < 0 || fn >= LIBM_HIP_NUM_FN || t < 0 || t > 4) return -1;
   if (fn == LIBM_HIP_FMOD || fn == LIBM_HIP_REMAINDER) {
@@ -110,6 +111,7 @@ int op_code(int fn, int v, int t) {
 // (from the elementwise kernels' measured times: trig with Payne-Hanek and
 // the remainders are the most expensive, exp/log the cheapest)
 float op_cost(int code) {
+  if (code >= 91) return 0.3f;                 // log u35
   if (code >= 70) return 0.6f;                 // asin, acos, atan
   if (code >= 66) return 1.5f;                 // fmod, remainder
   if (code <= 20) return 1.0f;                 // sin, cos, tan

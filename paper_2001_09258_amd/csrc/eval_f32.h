@@ -102,6 +102,22 @@ LMH_INLINE float logf_u10(float x) {
   return r;
 }
 
+LMH_INLINE float logf_u35(float x) {
+  float m = frexp_mant_(x);
+  int ie = frexp_exp_(x);
+  bool low = m < 0.75f;
+  m = low ? m + m : m;
+  float e = (float)(low ? ie - 1 : ie);
+  float t = (m - 1.0f) / (m + 1.0f);
+  float z = t * t;
+  float lm = fma_(t * z, poly_estrin(z, LOG_Q_F32), t + t);
+  float r = fma_(e, LN2_HI_F, fma_(e, LN2_LO_F, lm));
+  r = x == 0.0f ? -__builtin_inff() : r;
+  r = x < 0.0f ? __builtin_nanf("") : r;
+  r = (isinf_(x) && x > 0.0f) || isnan_(x) ? x : r;
+  return r;
+}
+
 LMH_INLINE float log2f_u10(float x) {
   float e;
   fff t = logf_t(x, e);

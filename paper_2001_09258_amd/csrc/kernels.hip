@@ -236,6 +236,7 @@ LMH_DEF_UNARY(tan, u35, OpTanU35, TAN, U35)
 LMH_DEF_UNARY(exp, u10, OpExpU10, EXP, U10)
 LMH_DEF_UNARY(exp2, u10, OpExp2U10, EXP2, U10)
 LMH_DEF_UNARY(log, u10, OpLogU10, LOG, U10)
+LMH_DEF_UNARY(log, u35, OpLogU35, LOG, U35)
 LMH_DEF_UNARY(log2, u10, OpLog2U10, LOG2, U10)
 LMH_DEF_UNARY(sinh, u10, OpSinhU10, SINH, U10)
 LMH_DEF_UNARY(cosh, u10, OpCoshU10, COSH, U10)
@@ -388,7 +389,10 @@ extern "C" libm_hip_status libm_hip_eval(libm_hip_fn fn, libm_hip_variant v, lib
       break;
     case LIBM_HIP_EXP: if (u10) return dispatch_unary<OpExpU10>(t, a, out, n, s, false, key); break;
     case LIBM_HIP_EXP2: if (u10) return dispatch_unary<OpExp2U10>(t, a, out, n, s, false, key); break;
-    case LIBM_HIP_LOG: if (u10) return dispatch_unary<OpLogU10>(t, a, out, n, s, false, key); break;
+    case LIBM_HIP_LOG:
+      if (u10) return dispatch_unary<OpLogU10>(t, a, out, n, s, false, key);
+      if (u35) return dispatch_unary<OpLogU35>(t, a, out, n, s, true, key);
+      break;
     case LIBM_HIP_LOG2: if (u10) return dispatch_unary<OpLog2U10>(t, a, out, n, s, false, key); break;
     case LIBM_HIP_SINH: if (u10) return dispatch_unary<OpSinhU10>(t, a, out, n, s, false, key); break;
     case LIBM_HIP_COSH: if (u10) return dispatch_unary<OpCoshU10>(t, a, out, n, s, false, key); break;

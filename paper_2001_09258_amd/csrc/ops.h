@@ -97,6 +97,7 @@ LMH_TRIG_OP(OpTanU35, tan_u35, tanf_u35, tan, tanf, LMH_NOARG, tan_finish_u35, t
 LMH_OP1(OpExpU10, exp_u10, expf_u10)
 LMH_OP1(OpExp2U10, exp2_u10, exp2f_u10)
 LMH_OP1(OpLogU10, log_u10, logf_u10)
+LMH_OP1(OpLogU35, log_u35, logf_u35)
 LMH_OP1(OpLog2U10, log2_u10, log2f_u10)
 LMH_OP1(OpSinhU10, sinh_u10, sinhf_u10)
 LMH_OP1(OpCoshU10, cosh_u10, coshf_u10)

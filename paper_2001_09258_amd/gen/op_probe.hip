@@ -22,6 +22,7 @@ K1(p64_log2, double, log2_u10(v))
 K1(p64_sinh, double, sinh_u10(v))
 K1(p64_cosh, double, cosh_u10(v))
 K1(p64_tanh, double, tanh_u10(v))
+K1(p64_log35, double, log_u35(v))
 K1(p64_asin, double, asin_u10(v))
 K1(p64_asin35, double, asin_u35(v))
 K1(p64_acos, double, acos_u10(v))
@@ -44,6 +45,7 @@ K1(p32_log2, float, log2f_u10(v))
 K1(p32_sinh, float, sinhf_u10(v))
 K1(p32_cosh, float, coshf_u10(v))
 K1(p32_tanh, float, tanhf_u10(v))
+K1(p32_log35, float, logf_u35(v))
 K1(p32_asin, float, asinf_u10(v))
 K1(p32_asin35, float, asinf_u35(v))
 K1(p32_acos, float, acosf_u10(v))

@@ -86,6 +86,7 @@ extern "C" int device_api_eval(int fn, int variant, int dtype, const void* a, co
       case 14: U1W(asin_u35)
       case 15: U1W(acos_u35)
       case 16: U1W(atan_u35)
+      case 5: U1W(log_u35)
     }
     return 2;
   }

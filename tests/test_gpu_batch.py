@@ -91,13 +91,15 @@ def test_batch_validation_errors():
     plan.close()
 
 
-def test_batch_inverse_trig_requests():
-    """asin, acos, atan in every served variant and dtype through one plan."""
+def test_batch_inverse_trig_and_log_u35_requests():
+    """asin, acos, atan in every served variant and dtype, and log u35,
+    through one plan."""
     reqs = []
-    for i, (fn, v, dt) in enumerate([(f, v, d) for f in ("asin", "acos", "atan")
-                                     for v in ("u10", "u35")
-                                     for d in ("f64", "f32", "bf16", "f16", "f32_via_f64")
-                                     if v == "u10" or d in ("f64", "f32")]):
+    kinds = [(f, v, d) for f in ("asin", "acos", "atan") for v in ("u10", "u35")
+             for d in ("f64", "f32", "bf16", "f16", "f32_via_f64")
+             if v == "u10" or d in ("f64", "f32")]
+    kinds += [("log", "u35", "f64"), ("log", "u35", "f32")]
+    for i, (fn, v, dt) in enumerate(kinds):
         base = "f32" if dt == "f32_via_f64" else dt
         a = W.function_mixture(fn, base, 5000 + 997 * i, 300 + i)
         ta = to_device(a, dt)
