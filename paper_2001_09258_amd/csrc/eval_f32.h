@@ -202,6 +202,8 @@ struct Trig32 {
 };
 
 LMH_INLINE bool trigf_slow(float x) { return !(fabs_(x) < CWF_LIMIT); }
+// |x| < 2^-12: sin x and tan x round to x, cos x to 1
+LMH_INLINE bool trigf_tiny(float x) { return fabs_(x) < 0x1p-12f; }
 
 LMH_INLINE Trig32 sincosf_fast(float x, bool is_cos) {
   float q, j;
@@ -257,20 +259,22 @@ LMH_INLINE float sinf_poly_u35(float r) {
 LMH_INLINE float sinf_finish_u10(float x, Trig32 s) {
   float v = sinf_poly_u10(s.r);
   v = is_odd_intf(s.j) ? -v : v;
-  return x == 0.0f ? x : v;
+  return trigf_tiny(x) ? x : v;
 }
 LMH_INLINE float cosf_finish_u10(float x, Trig32 s) {
   float v = sinf_poly_u10(s.r);
-  return is_odd_intf(s.j) ? -v : v;
+  v = is_odd_intf(s.j) ? -v : v;
+  return trigf_tiny(x) ? 1.0f : v;
 }
 LMH_INLINE float sinf_finish_u35(float x, Trig32 s) {
   float v = sinf_poly_u35(s.r.hi + s.r.lo);
   v = is_odd_intf(s.j) ? -v : v;
-  return x == 0.0f ? x : v;
+  return trigf_tiny(x) ? x : v;
 }
 LMH_INLINE float cosf_finish_u35(float x, Trig32 s) {
   float v = sinf_poly_u35(s.r.hi + s.r.lo);
-  return is_odd_intf(s.j) ? -v : v;
+  v = is_odd_intf(s.j) ? -v : v;
+  return trigf_tiny(x) ? 1.0f : v;
 }
 
 LMH_INLINE float sinf_u10(float x) { return sinf_finish_u10(x, sincosf_reduce(x, false)); }
@@ -320,7 +324,7 @@ LMH_INLINE fff tanf_ff(float x) { return tanf_ff_finish(x, tanf_reduce(x)); }
 
 LMH_INLINE float tanf_finish_u10(float x, Trig32 s) {
   fff q = tanf_ff_finish(x, s);
-  return fabs_(x) < 0x1p-12f ? x : q.hi + q.lo;
+  return trigf_tiny(x) ? x : q.hi + q.lo;
 }
 
 LMH_INLINE float tanf_finish_u35(float x, Trig32 s) {
@@ -333,7 +337,7 @@ LMH_INLINE float tanf_finish_u35(float x, Trig32 s) {
   float n2 = odd ? den : num;
   float d2 = odd ? -num : den;
   float res = n2 / d2;
-  return fabs_(x) < 0x1p-12f ? x : res;
+  return trigf_tiny(x) ? x : res;
 }
 
 LMH_INLINE float tanf_u10(float x) { return tanf_finish_u10(x, tanf_reduce(x)); }
