@@ -73,18 +73,13 @@ __global__ __launch_bounds__(MAX_BLOCK) void k_binary(const typename Io::S* __re
   }
 }
 
-// Trigonometric kernel that sorts each workgroup's elements by path.  Every
-// element is classified: tiny (the finisher returns x, or 1 for cos,
-// without a reduction), Cody-Waite (fast) or Payne-Hanek (slow, including
-// non-finite).  A workgroup without slow elements evaluates in place.
-// Otherwise the fast elements are appended to an LDS queue from the front
-// and the slow ones from the back (one LDS atomic per wave and class:
-// ballot, popcount, mbcnt); after a barrier all lanes walk the queue densely
-// -- fast items first, then slow -- and write every result into its
-// element's slot in LDS (tiny results go there directly); after a second
-// barrier each lane stores its own elements with one 16-byte store.  A wave
-// thus never runs the Cody-Waite path with most lanes masked off, nor the
-// Payne-Hanek path for one large argument.
+// Trigonometric kernel with the Payne-Hanek lanes gathered.  Each lane
+// classifies its elements; the Cody-Waite ones are reduced in place, the
+// others are appended to a workgroup queue in LDS (one LDS atomic per wave:
+// ballot, popcount, mbcnt) and reduced densely by all lanes after a barrier,
+// so a wave that holds a few large arguments no longer pays the whole
+// Payne-Hanek path.  The reduced states come back through LDS and every lane
+// finishes its own elements.
 __device__ __forceinline__ unsigned wave_reserve(bool pred, unsigned* counter) {
   unsigned long long m = __ballot(pred);
   unsigned pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
@@ -104,17 +99,15 @@ __global__ __launch_bounds__(BLOCK) void k_unary_split(const typename Io::S* __r
   typedef typename Io::S S;
   typedef typename Io::C C;
   typedef decltype(Op::fast(C())) St;
-  constexpr int CAP = BLOCK * EPT;
-  __shared__ C q_x[CAP];
-  __shared__ unsigned short q_slot[CAP];
-  __shared__ __align__(16) S q_out[CAP];
-  __shared__ unsigned cnt[3];                        // waves with slow elements, queue ends
-  if (threadIdx.x < 3) cnt[threadIdx.x] = 0;
+  __shared__ C q_x[BLOCK * EPT];
+  __shared__ unsigned short q_slot[BLOCK * EPT];
+  __shared__ St q_res[BLOCK * EPT];
+  __shared__ unsigned q_cnt;
+  if (threadIdx.x == 0) q_cnt = 0;
   size_t base = ((size_t)blockIdx.x * BLOCK + threadIdx.x) * EPT;
-  const bool full = VEC && base + EPT <= n;
   C xv[EPT];
   bool ok[EPT];
-  if (full) {
+  if (VEC && base + EPT <= n) {
     Pack<S, EPT> in = *reinterpret_cast<const Pack<S, EPT>*>(x + base);
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
@@ -128,65 +121,35 @@ __global__ __launch_bounds__(BLOCK) void k_unary_split(const typename Io::S* __r
       xv[i] = ok[i] ? Io::in(x[base + i]) : C(0);
     }
   }
-  int cls[EPT];                                      // 0 fast, 1 slow, 2 tiny or past the end
-  bool any_slow = false;
+  __syncthreads();                                   // q_cnt is initialised
+  St st[EPT];
+  bool slow[EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    cls[i] = !ok[i] || Op::is_tiny(xv[i]) ? 2 : (Op::is_slow(xv[i]) ? 1 : 0);
-    any_slow |= cls[i] == 1;
-  }
-  __syncthreads();                                   // cnt is initialised
-  if (__ballot(any_slow) != 0ull && (threadIdx.x & 63u) == 0u) atomicAdd(&cnt[0], 1u);
-  __syncthreads();
-  if (cnt[0] == 0u) {
-    // no Payne-Hanek element in this workgroup: evaluate in place
-    if (full) {
-      Pack<S, EPT> out;
-#pragma unroll
-      for (int i = 0; i < EPT; ++i) out.v[i] = Io::out(Op::finish(xv[i], Op::fast(xv[i])));
-      store_nt(out, y + base);
-    } else {
-#pragma unroll
-      for (int i = 0; i < EPT; ++i)
-        if (ok[i]) y[base + i] = Io::out(Op::finish(xv[i], Op::fast(xv[i])));
-    }
-    return;                                          // workgroup-uniform
-  }
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const unsigned short slot = (unsigned short)(threadIdx.x * EPT + i);
-    unsigned pf = wave_reserve(cls[i] == 0, &cnt[1]);
-    unsigned ps = wave_reserve(cls[i] == 1, &cnt[2]);
-    if (cls[i] == 0) {
-      q_x[pf] = xv[i];
-      q_slot[pf] = slot;
-    } else if (cls[i] == 1) {
-      q_x[CAP - 1 - ps] = xv[i];
-      q_slot[CAP - 1 - ps] = slot;
-    } else if (ok[i]) {
-      q_out[slot] = Io::out(Op::tiny(xv[i]));
+    slow[i] = ok[i] && Op::is_slow(xv[i]);
+    if (!slow[i]) st[i] = Op::fast(xv[i]);
+    unsigned pos = wave_reserve(slow[i], &q_cnt);
+    if (slow[i]) {
+      q_x[pos] = xv[i];
+      q_slot[pos] = (unsigned short)(threadIdx.x * EPT + i);
     }
   }
   __syncthreads();
-  const unsigned nf = cnt[1], ns = cnt[2];
-  for (unsigned p = threadIdx.x; p < nf + ns; p += BLOCK) {
-    const bool fast = p < nf;
-    const unsigned idx = fast ? p : CAP - 1 - (p - nf);
-    C xx = q_x[idx];
-    St st;
-    if (fast)
-      st = Op::fast(xx);
-    else
-      st = Op::slow(xx);
-    q_out[q_slot[idx]] = Io::out(Op::finish(xx, st));
-  }
+  const unsigned cnt = q_cnt;
+  for (unsigned p = threadIdx.x; p < cnt; p += BLOCK) q_res[q_slot[p]] = Op::slow(q_x[p]);
   __syncthreads();
-  if (full) {
-    store_nt(*reinterpret_cast<const Pack<S, EPT>*>(&q_out[threadIdx.x * EPT]), y + base);
+#pragma unroll
+  for (int i = 0; i < EPT; ++i)
+    if (slow[i]) st[i] = q_res[threadIdx.x * EPT + i];
+  if (VEC && base + EPT <= n) {
+    Pack<S, EPT> out;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) out.v[i] = Io::out(Op::finish(xv[i], st[i]));
+    store_nt(out, y + base);
   } else {
 #pragma unroll
     for (int i = 0; i < EPT; ++i)
-      if (ok[i]) y[base + i] = q_out[threadIdx.x * EPT + i];
+      if (ok[i]) y[base + i] = Io::out(Op::finish(xv[i], st[i]));
   }
 }
 

@@ -69,11 +69,12 @@ struct IoF16 {
     static __device__ __forceinline__ float f(float a, float b) { return lmh::F32FN(a, b); }    \
   };
 
-// Trigonometric tags also expose their reduction paths, so a kernel can sort
-// its elements by path and run each class densely: is_tiny(x) -> the
-// finisher's own shortcut value tiny(x) (x, or 1 for cos); is_slow(x);
-// fast(x) / slow(x) -> reduced state; finish(x, state) -> result.  Every
-// route gives the bits of f(x).
+// Trigonometric tags also expose their reduction paths, so a kernel can
+// gather the elements that need Payne-Hanek and run them densely:
+// is_slow(x), fast(x) / slow(x) -> reduced state, finish(x, state) ->
+// result; is_tiny(x) / tiny(x) give the finisher's own shortcut value (x, or
+// 1 for cos) for arguments that need no reduction.  Every route gives the
+// bits of f(x).
 #define LMH_TRIG_OP(NAME, F64FN, F32FN, RED64, RED32, ARG, FIN64, FIN32, TINYV)                 \
   struct NAME {                                                                                 \
     static constexpr bool kSplit = true;                                                        \
