@@ -104,18 +104,24 @@ def gen_inputs(plan, n):
 
 def kernel_source_hash():
     """sha256 over the device code of the elementwise kernels (kernels.h, the
-    evaluator headers and the generated tables); HBM traffic counters taken
-    for other device code are not reported.  Host-side files (launchers, the
-    C ABI, the tuner, the batch plan) do not enter it."""
+    evaluator headers and the generated tables), comments and blank lines
+    removed; HBM traffic counters taken for other device code are not
+    reported.  Host-side files (launchers, the C ABI, the tuner, the batch
+    plan) do not enter it."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for d, _, files in sorted(os.walk(CSRC)):
         for f in sorted(files):
             if f.endswith((".h", ".inc")):
                 path = os.path.join(d, f)
+                with open(path) as fh:
+                    text = fh.read()
+                text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+                text = re.sub(r"//[^\n]*", "", text)
+                code = "\n".join(ln.rstrip() for ln in text.splitlines() if ln.strip())
                 h.update(os.path.relpath(path, CSRC).encode())
-                with open(path, "rb") as fh:
-                    h.update(fh.read())
+                h.update(code.encode())
     return h.hexdigest()
 
 
