@@ -124,10 +124,17 @@ __global__ __launch_bounds__(BLOCK) void k_unary_split(const typename Io::S* __r
   __syncthreads();                                   // q_cnt is initialised
   St st[EPT];
   bool slow[EPT];
+  // Cody-Waite for every element, without a branch: nearly every wave holds
+  // Cody-Waite elements anyway, and straight-line code lets the compiler
+  // interleave the EPT independent reductions (the slow elements' states
+  // are replaced below)
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     slow[i] = ok[i] && Op::is_slow(xv[i]);
-    if (!slow[i]) st[i] = Op::fast(xv[i]);
+    st[i] = Op::fast(xv[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
     unsigned pos = wave_reserve(slow[i], &q_cnt);
     if (slow[i]) {
       q_x[pos] = xv[i];
