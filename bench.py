@@ -391,6 +391,38 @@ def extra_sorted_paths(lib, L, stream, host, n, reps):
     return res
 
 
+def extra_small_set(lib, L, stream, reps, ops):
+    """The binary64 small set (2^20 elements: sin, cos, exp on U[-10, 10],
+    log on (0, 1000]), 8 MiB per array: resident in the 256 MiB last-level
+    cache when timed back to back (warm), so the VALU fraction is the one to
+    read."""
+    import torch
+    import workloads as W
+    sh = stream.cuda_stream
+    res = {}
+    n = 1 << 20
+    for fn in ("sin", "cos", "exp", "log"):
+        a = W.small_set(fn, n)
+        ta = torch.from_numpy(a).cuda()
+        to = torch.empty_like(ta)
+        nm = L.entry_name(fn, "u10", "f64")
+        f = checked(lib, nm, getattr(lib, nm), ta.data_ptr(), to.data_ptr(), n, sh)
+        f()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(20 * reps):
+            f()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / (20 * reps)
+        vo, v64, _ = valu_ops(fn, "u10", "f64", a, ops)
+        slots = max(v64, vo / 2)
+        res[fn] = {"us": round(ms * 1e3, 2), "gelem_s": round(n / ms / 1e6, 2),
+                   "alu_frac": round(slots * n / VALU_SLOTS / (ms * 1e-3), 4)}
+    return res
+
+
 def cpu_baseline(inputs, sample):
     """The oracle as it stands, on the first ``sample`` elements of every
     (function, dtype) input of the step, over a process pool on all cores."""
@@ -403,8 +435,17 @@ def cpu_baseline(inputs, sample):
         oracle.evaluate(fn, dt, a[:sample], None if b is None else b[:sample], workers=workers)
         total += min(sample, a.shape[0])
     dt_s = time.perf_counter() - t0
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": total / dt_s / 1e9, "unit": "Gelem/s", "cores": workers,
-            "kind": "oracle",
+            "kind": "oracle", "host_cpu": cpu,
             "sample": "first %d elements of each of the %d (function, dtype) inputs of the "
                       "step (%d elements, %.1f s)" % (sample, len(inputs), total, dt_s)}
 
@@ -412,8 +453,8 @@ def cpu_baseline(inputs, sample):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the method is elementwise; "
-              "see the sharding notes in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py: measures one GPU only (every element is independent, so G GPUs "
+              "would each take 1/G of every array); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -567,6 +608,8 @@ def main():
             result["inverse_trig"] = extra_inverse_trig(lib, L, stream, n, args.reps,
                                                         json.load(fh))
         result["trig_sorted_by_path"] = extra_sorted_paths(lib, L, stream, host, n, args.reps)
+        with open(OPS_FILE) as fh:
+            result["small_set_f64_warm"] = extra_small_set(lib, L, stream, args.reps, json.load(fh))
         print("bench: extras in %.1f s" % (time.perf_counter() - t_x), file=sys.stderr,
               flush=True)
     if not args.no_cpu_baseline:

@@ -84,7 +84,7 @@ LMH_INLINE fff logf_t(float a, float& e) {
   bool low = m < 0.75f;
   m = low ? m + m : m;
   e = (float)(low ? ie - 1 : ie);
-  fff den = dd2_add2(m, 1.0f);
+  fff den = dd2_add(1.0f, m);                        // fast two-sum: m < 2
   return dd2_div(mk(m - 1.0f, 0.0f), den);
 }
 
