@@ -45,7 +45,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK = 8.0e12                       # bytes/s, MI355X HBM3E
 VALU_SLOTS = 256 * 4 * 16 * 2.4e9       # VALU lane-slots/s (one binary64 lane-op each)
 FP64_PEAK = 78.6e12                     # flop/s, dense vector FP64
-SLOW_TRIG = {"f64": 1e14, "f32": 65536.0}   # |x| at which trig switches to Payne-Hanek
+SLOW_TRIG = {"f64": 2.0 ** 14, "f32": 65536.0}   # |x| at which trig switches to Payne-Hanek
 OPS_FILE = os.path.join(ROOT, "paper_2001_09258_amd", "gen", "valu_per_element.json")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "elementwise_step_hbm_traffic.json")
 CSRC = os.path.join(ROOT, "paper_2001_09258_amd", "csrc")
@@ -144,7 +144,7 @@ def valu_ops(fn, v, dt, a, ops):
         return np.array([ops[key]["valu"], ops[key]["valu_f64"]], dtype=float)
     if fn in ("sin", "cos", "tan"):
         slow = float(np.mean(~(np.abs(a) < SLOW_TRIG[dt])))
-        red = (1 - slow) * get(pre + "cw") + slow * get(pre + "ph")
+        red = (1 - slow) * get(pre + fn + "cw") + slow * get(pre + fn + "ph")
         fin = get(pre + ("tanfin" if fn == "tan" else "sinfin") + ("35" if v == "u35" else ""))
         tot = red + fin
         return float(tot[0]), float(tot[1]), slow

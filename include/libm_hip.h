@@ -61,7 +61,7 @@ const char* libm_hip_version(void);
  * Unary functions, y[i] = f(x[i]).
  *
  * sin, cos, tan (Section 5, "sin and cos", "tan", "The Payne-Hanek Range
- * Reduction"): a Cody-Waite reduction for |x| < 1e14 (binary32: 65536) and
+ * Reduction"): a Cody-Waite reduction for |x| < 2^14 (binary32: 65536) and
  * the vectorised Payne-Hanek reduction above, chosen per element (the
  * paper's bit-consistent arrangement, Section 3.3); a sine polynomial on
  * [-pi/2, pi/2]; tan through the double-angle formula on [-pi/8, pi/8].

@@ -137,14 +137,20 @@ LMH_INLINE float log2f_u10(float x) {
 // ---------------------------------------------------------------------------
 // trigonometric reductions in binary32
 // ---------------------------------------------------------------------------
-// Cody-Waite with the period split in four floats; exact partial sums for
-// |q| < 2^17 by the same argument as in binary64.
-LMH_INLINE fff cwf_reduce(float x, float q, float c0, float c1, float c2, float c3) {
-  fff s = dd2_add2(mk(x, 0.0f), dd2_mul(q, -c0));
-  s = dd2_norm(s);
-  s = dd2_norm(dd2_add2(s, dd2_mul(q, -c1)));
-  s = dd2_norm(dd2_add2(s, dd2_mul(q, -c2)));
-  return dd2_add2(s, q * -c3);
+// Cody-Waite for |x| < 65536, carried out in binary64: a binary64 FMA costs
+// one issue slot on gfx950, a float-float step several.  x and q are exact
+// as doubles; C0 (37 bits, truncated) makes q*C0 exact for |q| < 2^16, and
+// x - q*C0 is exact (Sterbenz's lemma for q = rint(x/C); cos with q = +-1
+// and small x: exact for |x| >= 2^-29, and below 2^-12 the finisher returns
+// 1).  One more FMA with the nearest double to C - C0 leaves an error below
+// 2^-73, against a reduced argument of at least 2^-27.8 for |x| < 65536 (the
+// float nearest to 161 pi/2).  The result is split into a float pair
+// (hi + lo carries 48 bits).
+LMH_INLINE fff cwf_reduce(float x, float q, double c0, double c1) {
+  double qd = (double)q;
+  double r = fma_(qd, -c1, fma_(qd, -c0, (double)x));
+  float hi = (float)r;
+  return mk(hi, (float)(r - (double)hi));
 }
 
 // Payne-Hanek in binary32: |x| = m 2^(ex-23), m < 2^24 an integer; the
@@ -214,8 +220,7 @@ LMH_INLINE Trig32 sincosf_fast(float x, bool is_cos) {
     q = rint_(x * INV_PI_F);
     j = q;
   }
-  fff r = is_cos ? cwf_reduce(x, q, PIH_F_0, PIH_F_1, PIH_F_2, PIH_F_3)
-                 : cwf_reduce(x, q, PI_F_0, PI_F_1, PI_F_2, PI_F_3);
+  fff r = is_cos ? cwf_reduce(x, q, PIH_FD_0, PIH_FD_1) : cwf_reduce(x, q, PI_FD_0, PI_FD_1);
   return Trig32{r, j};
 }
 
@@ -284,7 +289,7 @@ LMH_INLINE float cosf_u35(float x) { return cosf_finish_u35(x, sincosf_reduce(x,
 
 LMH_INLINE Trig32 tanf_fast(float x) {
   float k = rint_(x * TWO_OVER_PI_F);
-  return Trig32{cwf_reduce(x, k, PIH_F_0, PIH_F_1, PIH_F_2, PIH_F_3), k};
+  return Trig32{cwf_reduce(x, k, PIH_FD_0, PIH_FD_1), k};
 }
 
 LMH_INLINE Trig32 tanf_slow(float x) {

@@ -73,37 +73,27 @@ __global__ __launch_bounds__(MAX_BLOCK) void k_binary(const typename Io::S* __re
   }
 }
 
-// Trigonometric kernel with the Payne-Hanek lanes gathered.  Each lane
-// classifies its elements; the Cody-Waite ones are reduced in place, the
-// others are appended to a workgroup queue in LDS (one LDS atomic per wave:
-// ballot, popcount, mbcnt) and reduced densely by all lanes after a barrier,
-// so a wave that holds a few large arguments no longer pays the whole
-// Payne-Hanek path.  The reduced states come back through LDS and every lane
-// finishes its own elements.
-__device__ __forceinline__ unsigned wave_reserve(bool pred, unsigned* counter) {
-  unsigned long long m = __ballot(pred);
-  unsigned pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                           __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-  unsigned base = 0;
-  if (m != 0ull) {
-    int leader = __ffsll((long long)m) - 1;
-    if (pred && pre == 0u) base = atomicAdd(counter, (unsigned)__popcll(m));
-    base = __shfl(base, leader);
-  }
-  return base + pre;
-}
-
+// Trigonometric kernel with the Payne-Hanek lanes gathered.  Every lane runs
+// the Cody-Waite reduction on its elements; the Payne-Hanek ones are also
+// written to a workgroup queue in LDS and reduced densely by all lanes after
+// a barrier, so a wave that holds a few large arguments no longer pays the
+// whole Payne-Hanek path.  Each wave owns a fixed region of the queue and
+// fills its front with ballot + mbcnt (no atomics); the dense pass maps its
+// index onto the filled fronts from the per-wave counts.  The reduced states
+// come back through LDS and every lane finishes its own elements.
 template <class Io, class Op, int EPT, bool VEC>
 __global__ __launch_bounds__(BLOCK) void k_unary_split(const typename Io::S* __restrict__ x,
                                                        typename Io::S* __restrict__ y, size_t n) {
   typedef typename Io::S S;
   typedef typename Io::C C;
   typedef decltype(Op::fast(C())) St;
+  constexpr int WAVES = BLOCK / 64;
+  constexpr unsigned REGION = 64 * EPT;
   __shared__ C q_x[BLOCK * EPT];
   __shared__ unsigned short q_slot[BLOCK * EPT];
   __shared__ St q_res[BLOCK * EPT];
-  __shared__ unsigned q_cnt;
-  if (threadIdx.x == 0) q_cnt = 0;
+  __shared__ unsigned q_cnt[WAVES];
+  const unsigned lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
   size_t base = ((size_t)blockIdx.x * BLOCK + threadIdx.x) * EPT;
   C xv[EPT];
   bool ok[EPT];
@@ -121,7 +111,6 @@ __global__ __launch_bounds__(BLOCK) void k_unary_split(const typename Io::S* __r
       xv[i] = ok[i] ? Io::in(x[base + i]) : C(0);
     }
   }
-  __syncthreads();                                   // q_cnt is initialised
   St st[EPT];
   bool slow[EPT];
   // Cody-Waite for every element, without a branch: nearly every wave holds
@@ -133,17 +122,37 @@ __global__ __launch_bounds__(BLOCK) void k_unary_split(const typename Io::S* __r
     slow[i] = ok[i] && Op::is_slow(xv[i]);
     st[i] = Op::fast(xv[i]);
   }
+  unsigned filled = 0;                               // wave-uniform
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    unsigned pos = wave_reserve(slow[i], &q_cnt);
+    unsigned long long m = __builtin_amdgcn_ballot_w64(slow[i]);
+    unsigned pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                             __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
     if (slow[i]) {
+      unsigned pos = wave * REGION + filled + pre;
       q_x[pos] = xv[i];
       q_slot[pos] = (unsigned short)(threadIdx.x * EPT + i);
     }
+    filled += (unsigned)__popcll(m);
   }
+  if (lane == 0) q_cnt[wave] = filled;
   __syncthreads();
-  const unsigned cnt = q_cnt;
-  for (unsigned p = threadIdx.x; p < cnt; p += BLOCK) q_res[q_slot[p]] = Op::slow(q_x[p]);
+  unsigned cnt[WAVES], first[WAVES];
+  unsigned total = 0;
+#pragma unroll
+  for (int w = 0; w < WAVES; ++w) {
+    cnt[w] = q_cnt[w];
+    first[w] = total;
+    total += cnt[w];
+  }
+  for (unsigned p = threadIdx.x; p < total; p += BLOCK) {
+    // dense index p -> slot in its wave's region, skipping the unfilled
+    // tails of the regions before it
+    unsigned pos = p;
+#pragma unroll
+    for (int w = 1; w < WAVES; ++w) pos += p >= first[w] ? REGION - cnt[w - 1] : 0u;
+    q_res[q_slot[pos]] = Op::slow(q_x[pos]);
+  }
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < EPT; ++i)

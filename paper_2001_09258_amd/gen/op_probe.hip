@@ -9,8 +9,12 @@ using namespace lmh;
 #define K1(NAME, T, EXPR) __global__ void NAME(const T* x, T* y) { int i = threadIdx.x; T v = x[i]; y[i] = (EXPR); }
 #define KS(NAME, T, EXPR) __global__ void NAME(const T* x, T* y) { int i = threadIdx.x; T v = x[i]; auto s = (EXPR); y[i] = s.r.hi + s.r.lo + s.j; }
 // binary64 pieces
-__global__ void p64_cw(const double* x, double* y) { int i = threadIdx.x; double v = x[i]; double q = rint_(v * INV_PI_D); ddd r = cw_reduce(v, q, PI_D_0, PI_D_1, PI_D_2, PI_D_3); y[i] = r.hi + r.lo + q; }
-KS(p64_ph, double, sincos_slow(v, false))
+KS(p64_sincw, double, sincos_fast(v, false))
+KS(p64_coscw, double, sincos_fast(v, true))
+KS(p64_tancw, double, tan_fast(v))
+KS(p64_sinph, double, sincos_slow(v, false))
+KS(p64_cosph, double, sincos_slow(v, true))
+KS(p64_tanph, double, tan_slow(v))
 __global__ void p64_sinfin(const double* x, double* y) { int i = threadIdx.x; Trig64 s{mk(x[i], x[i+64]), x[i+128]}; y[i] = sin_finish_u10(x[i+192], s); }
 __global__ void p64_sinfin35(const double* x, double* y) { int i = threadIdx.x; Trig64 s{mk(x[i], x[i+64]), x[i+128]}; y[i] = sin_finish_u35(x[i+192], s); }
 __global__ void p64_tanfin(const double* x, double* y) { int i = threadIdx.x; Trig64 s{mk(x[i], x[i+64]), x[i+128]}; y[i] = tan_finish_u10(x[i+192], s); }
@@ -32,8 +36,12 @@ K1(p64_atan35, double, atan_u35(v))
 __global__ void p64_pow(const double* x, double* y) { int i = threadIdx.x; y[i] = pow_u10(x[i], x[i+64]); }
 __global__ void p64_atan2(const double* x, double* y) { int i = threadIdx.x; y[i] = atan2_u10(x[i], x[i+64]); }
 // binary32 pieces
-__global__ void p32_cw(const float* x, float* y) { int i = threadIdx.x; float v = x[i]; float q = rint_(v * INV_PI_F); fff r = cwf_reduce(v, q, PI_F_0, PI_F_1, PI_F_2, PI_F_3); y[i] = r.hi + r.lo + q; }
-KS(p32_ph, float, sincosf_slow(v, false))
+KS(p32_sincw, float, sincosf_fast(v, false))
+KS(p32_coscw, float, sincosf_fast(v, true))
+KS(p32_tancw, float, tanf_fast(v))
+KS(p32_sinph, float, sincosf_slow(v, false))
+KS(p32_cosph, float, sincosf_slow(v, true))
+KS(p32_tanph, float, tanf_slow(v))
 __global__ void p32_sinfin(const float* x, float* y) { int i = threadIdx.x; Trig32 s{mk(x[i], x[i+64]), x[i+128]}; y[i] = sinf_finish_u10(x[i+192], s); }
 __global__ void p32_sinfin35(const float* x, float* y) { int i = threadIdx.x; Trig32 s{mk(x[i], x[i+64]), x[i+128]}; y[i] = sinf_finish_u35(x[i+192], s); }
 __global__ void p32_tanfin(const float* x, float* y) { int i = threadIdx.x; Trig32 s{mk(x[i], x[i+64]), x[i+128]}; y[i] = tanf_finish_u10(x[i+192], s); }

@@ -16,6 +16,7 @@ import pytest
 
 import workloads as W
 from tests.gpu_common import check, run_gpu, run_oracle, to_device, BOUND
+from tests.trig_hard_cases import mid_range, near_multiples
 
 pytestmark = pytest.mark.gpu
 
@@ -60,6 +61,24 @@ def test_parity_large_arguments(fn, variant, dt):
     b = _inputs(3, fn, dt, N_PAR, 1) if fn in BINARY else None
     print("parity large arguments", fn, variant, dt, flush=True)
     check(fn, variant, dt, a, b, label="large_args")
+
+
+HARD = [(fn, v, dt) for fn in ("sin", "cos", "tan") for v in ("u10", "u35")
+        for dt in ("f64", "f32")]
+
+
+@pytest.mark.parametrize("fn,variant,dt", HARD, ids=["-".join(c) for c in HARD])
+def test_trig_reduction_hard_cases(fn, variant, dt):
+    """Every float nearest to k pi/2 in the Cody-Waite range (binary64 below
+    2^14, binary32 below 65536) and its neighbours: the smallest reduced
+    arguments that range meets.  binary64 adds log-uniform arguments over
+    [2^14, 1e14] (the Payne-Hanek range whose table rows have leading
+    zeros)."""
+    a = near_multiples(dt)
+    if dt == "f64":
+        a = np.concatenate([a, mid_range(8192)])
+    print("trig hard cases", fn, variant, dt, a.size, flush=True)
+    check(fn, variant, dt, a, label="hard cases")
 
 
 @pytest.mark.parametrize("fn", ["sin", "cos", "exp", "log"])
