@@ -12,9 +12,10 @@ The cap is 16384 bits; hitting it raises instead of returning a guess.  Ziv's
 loop only stops when the exact value is not itself a rounding boundary
 (a representable number or a midpoint); the cases where it can be one are
 detected and computed exactly (exp2 and log2 at powers of two, pow when x^y is
-a dyadic rational).  exp, sin, cos, tan, log (x != 1), atan (x != 0) and the
-hyperbolic functions of a nonzero dyadic are transcendental, hence never a
-boundary.
+a dyadic rational, log10 at powers of ten, exp10 at nonnegative integers,
+cbrt at cubes and hypot when x^2 + y^2 is a square).  exp, sin, cos, tan,
+log (x != 1), atan (x != 0), expm1 and log1p (x != 0) and the hyperbolic
+functions of a nonzero dyadic are transcendental, hence never a boundary.
 
 Special inputs (zeros, infinities, NaN) follow C99 Annex F (F.9), which the
 paper adopts: "same results as libm, as specified in the ANSI C standard"
@@ -44,8 +45,9 @@ INF = float("inf")
 PREC_CAP = 16384
 
 UNARY = ("sin", "cos", "tan", "exp", "exp2", "log", "log2",
-         "sinh", "cosh", "tanh", "asin", "acos", "atan")
-BINARY = ("pow", "atan2", "fmod", "remainder")
+         "sinh", "cosh", "tanh", "asin", "acos", "atan",
+         "log10", "exp10", "expm1", "log1p", "cbrt")
+BINARY = ("pow", "atan2", "fmod", "remainder", "hypot")
 
 
 class OracleError(RuntimeError):
@@ -124,6 +126,37 @@ def _special_unary(fn, x):
     elif fn == "atan":
         if x == 0.0:
             return x
+    elif fn == "log10":
+        if x == 0.0:
+            return -INF
+        if x < 0:
+            return NAN
+        if math.isinf(x):
+            return INF
+        if x == 1.0:
+            return 0.0
+    elif fn == "exp10":
+        if x == 0.0:
+            return 1.0
+        if math.isinf(x):
+            return INF if x > 0 else 0.0
+    elif fn == "expm1":
+        if x == 0.0:
+            return x
+        if math.isinf(x):
+            return INF if x > 0 else -1.0
+    elif fn == "log1p":
+        if x == 0.0:
+            return x
+        if x == -1.0:
+            return -INF
+        if x < -1.0:
+            return NAN
+        if math.isinf(x):
+            return INF
+    elif fn == "cbrt":
+        if x == 0.0 or math.isinf(x):
+            return x
     return None
 
 
@@ -177,6 +210,15 @@ def _special_pow(x, y):
             return -INF if odd else INF
         return 0.0 if y < 0 else INF
     if x < 0 and not _is_int(y):
+        return NAN
+    return None
+
+
+def _special_hypot(x, y):
+    """Annex F: an infinite argument gives +inf even when the other is NaN."""
+    if math.isinf(x) or math.isinf(y):
+        return INF
+    if math.isnan(x) or math.isnan(y):
         return NAN
     return None
 
@@ -362,6 +404,67 @@ def _ball_acos(x, prec):
     return B.scale2(a, 1)
 
 
+def _ball_log10(x, prec):
+    m, e = _dyadic(x)
+    return div(log_ball(m, e, prec + 8), log_ball(5, 1, prec + 16), prec + 8)
+
+
+def _ball_exp10(x, prec):
+    wp = prec + 40
+    xb = mul(from_float(x), log_ball(5, 1, wp), wp)          # x ln 10
+    return exp_ball(_clamp_exp_arg(xb), prec)
+
+
+def _ball_expm1(x, prec):
+    """e^x - 1.  For |x| < 1 as 2 sinh(x/2) e^(x/2) (no cancellation); else
+    directly (|e^x - 1| >= 1 - 1/e)."""
+    if abs(x) < 1.0:
+        h = B.scale2(from_float(x), -1)
+        s, _ = sinh_cosh_small(h, prec + 8)
+        return B.scale2(mul(s, exp_ball(h, prec + 8), prec + 8), 1)
+    return sub(exp_ball(_clamp_exp_arg(from_float(x)), prec + 8), exact(1), prec + 8)
+
+
+def _one_plus(x):
+    """1 + x as an exact dyadic (M, E)."""
+    m, e = _dyadic(x)
+    if e >= 0:
+        return (m << e) + 1, 0
+    return m + (1 << -e), e
+
+
+def _ball_log1p(x, prec):
+    """log(1 + x) with 1 + x formed exactly; the logarithm's mantissa lies in
+    [sqrt(1/2), sqrt(2)) so the result is accurate relative to its own size
+    when 1 + x is near 1."""
+    M, E = _one_plus(x)
+    return log_ball(M, E, prec)
+
+
+def _ball_cbrt(x, prec):
+    """cbrt x = sign(x) exp(log|x| / 3)."""
+    m, e = _dyadic(abs(x))
+    wp = prec + 24
+    r = exp_ball(div(log_ball(m, e, wp), exact(3), wp), prec + 8)
+    return r if x > 0 else B.neg(r)
+
+
+def _sum_squares(x, y):
+    """x^2 + y^2 as an exact dyadic (S, E) with E even."""
+    terms = [_dyadic(abs(v)) for v in (x, y) if v != 0.0]
+    e = min(2 * ev for _, ev in terms)
+    S = sum((mv * mv) << (2 * ev - e) for mv, ev in terms)
+    if e & 1:
+        S <<= 1
+        e -= 1
+    return S, e
+
+
+def _ball_hypot(x, y, prec):
+    S, e = _sum_squares(x, y)
+    return B.sqrt(exact(S, e), prec + 8)
+
+
 def _ball_pow(x, y, prec):
     """|x|^y (sign handled by the caller) for finite nonzero x, y."""
     m, e = _dyadic(abs(x))
@@ -384,6 +487,16 @@ def _int_root(n, k):
         if c > 0 and c ** k == n:
             return c
     return None
+
+
+def _cbrt_exact(x):
+    """(m, e) with cbrt|x| = m 2^e when it is a dyadic, else None (then it is
+    irrational, hence no rounding boundary)."""
+    m, e = _dyadic(abs(x))
+    if e % 3 != 0:
+        return None
+    c = _int_root(m, 3)
+    return None if c is None else (c, e // 3)
 
 
 def _pow_exact(x, y):
@@ -446,7 +559,8 @@ _BALLS = {"sin": _ball_sin, "cos": _ball_cos, "tan": _ball_tan,
           "exp": _ball_exp, "exp2": _ball_exp2, "log": _ball_log,
           "log2": _ball_log2, "sinh": _ball_sinh, "cosh": _ball_cosh,
           "tanh": _ball_tanh, "asin": _ball_asin, "acos": _ball_acos,
-          "atan": _ball_atan}
+          "atan": _ball_atan, "log10": _ball_log10, "exp10": _ball_exp10,
+          "expm1": _ball_expm1, "log1p": _ball_log1p, "cbrt": _ball_cbrt}
 
 
 def _dd(b):
@@ -509,6 +623,19 @@ def evaluate1(fn, fmt_name, x, y=None):
         if fn == "acos" and x == -1.0:
             v = _round_const("pi", fmt)
             return v, v, 0.0
+        if fn == "log10":
+            m, e = _dyadic(x)
+            if e > 0 and m == 5 ** e:                 # x = 10^e
+                v = rn_dyadic(e, 0, fmt)
+                return v, v, 0.0
+        if fn == "exp10" and _is_int(x) and x > 0:
+            v = rn_dyadic(10 ** int(min(x, 400.0)), 0, fmt)
+            return v, v, 0.0
+        if fn == "cbrt":
+            ex = _cbrt_exact(x)
+            if ex is not None:
+                v = rn_dyadic(ex[0] if x > 0 else -ex[0], ex[1], fmt)
+                return v, v, 0.0
         return _ziv(_BALLS[fn], (x,), fmt, prec0)
     if fn == "atan2":
         sp = _special_atan2(x, y, fmt)       # atan2(x, y) in C order
@@ -529,6 +656,18 @@ def evaluate1(fn, fmt_name, x, y=None):
         if neg:
             return -v, -hi, -lo
         return v, hi, lo
+    if fn == "hypot":
+        sp = _special_hypot(x, y)
+        if sp is not None:
+            return sp, sp, 0.0
+        if x == 0.0 and y == 0.0:
+            return 0.0, 0.0, 0.0
+        S, e = _sum_squares(x, y)
+        r = math.isqrt(S)
+        if r * r == S:                                # also |x| when y = 0
+            v = rn_dyadic(r, e // 2, fmt)
+            return v, v, 0.0
+        return _ziv(_ball_hypot, (x, y), fmt, prec0)
     if fn in ("fmod", "remainder"):
         sp = _special_fmod(x, y)
         if sp is not None:

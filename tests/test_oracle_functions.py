@@ -39,7 +39,8 @@ SPECIALS = [0.0, -0.0, math.inf, -math.inf, math.nan, 1.0, -1.0, 0.5, -0.5,
 NP_UNARY = {"sin": np.sin, "cos": np.cos, "tan": np.tan, "exp": np.exp,
             "exp2": np.exp2, "log": np.log, "log2": np.log2, "sinh": np.sinh,
             "cosh": np.cosh, "tanh": np.tanh, "asin": np.arcsin, "acos": np.arccos,
-            "atan": np.arctan}
+            "atan": np.arctan, "log10": np.log10, "exp10": lambda x: np.power(10.0, x),
+            "expm1": np.expm1, "log1p": np.log1p, "cbrt": np.cbrt}
 
 
 def same(a, b):
@@ -112,7 +113,10 @@ MP = {"sin": mpmath.sin, "cos": mpmath.cos, "tan": mpmath.tan,
       "exp": mpmath.exp, "exp2": lambda x: mpmath.power(2, x),
       "log": mpmath.log, "log2": lambda x: mpmath.log(x, 2),
       "sinh": mpmath.sinh, "cosh": mpmath.cosh, "tanh": mpmath.tanh,
-      "asin": mpmath.asin, "acos": mpmath.acos, "atan": mpmath.atan}
+      "asin": mpmath.asin, "acos": mpmath.acos, "atan": mpmath.atan,
+      "log10": mpmath.log10, "exp10": lambda x: mpmath.power(10, x),
+      "expm1": mpmath.expm1, "log1p": mpmath.log1p,
+      "cbrt": lambda x: mpmath.sign(x) * mpmath.cbrt(abs(x))}   # the real root
 
 
 def _mp_f64(fn, x, y=None):
@@ -121,6 +125,8 @@ def _mp_f64(fn, x, y=None):
             v = mpmath.power(mpmath.mpf(x), mpmath.mpf(y))
         elif fn == "atan2":
             v = mpmath.atan2(mpmath.mpf(x), mpmath.mpf(y))
+        elif fn == "hypot":
+            v = mpmath.hypot(mpmath.mpf(x), mpmath.mpf(y))
         else:
             v = MP[fn](mpmath.mpf(x))
         return v
@@ -138,8 +144,19 @@ def _inputs(fn, rng, n):
     xs = []
     for _ in range(n):
         c = rng.random()
-        if fn in ("log", "log2"):
+        if fn in ("log", "log2", "log10"):
             xs.append(abs(_rand_bits(rng)) if c < 0.5 else rng.uniform(0, 1000))
+        elif fn == "log1p":
+            if c < 0.3:
+                xs.append(rng.uniform(-1, 1))
+            elif c < 0.6:
+                xs.append(math.copysign(10 ** rng.uniform(-310, 0), rng.random() - 0.5))
+            else:
+                xs.append(abs(_rand_bits(rng)))
+        elif fn in ("exp10", "expm1"):
+            lim = 330 if fn == "exp10" else 760
+            xs.append(rng.uniform(-lim, lim) if c < 0.5 else
+                      math.copysign(10 ** rng.uniform(-300, 3), rng.random() - 0.5))
         elif fn in ("asin", "acos"):
             if c < 0.4:
                 xs.append(rng.uniform(-1, 1))
@@ -239,7 +256,8 @@ def _midpoint_distance_in_dulps(d):
 
 
 @pytest.mark.parametrize("fn", ["sin", "cos", "tan", "exp", "log", "exp2", "log2",
-                                "sinh", "cosh", "tanh", "asin", "acos", "atan"])
+                                "sinh", "cosh", "tanh", "asin", "acos", "atan",
+                                "log10", "exp10", "expm1", "log1p", "cbrt"])
 def test_binary32_vs_glibc_double_rounded(fn):
     # a strided sweep over all positive and negative binary32 bit patterns
     stride = 1 << 16
@@ -418,3 +436,91 @@ def test_regression_inputs_are_valid_and_oracle_agrees_with_mpmath():
             assert d[0] <= d[1] and d[0] <= d[2], (line, got)
         n += 1
     assert n >= 10
+
+
+# --------------------------------------------------------------------------
+# log10, exp10, expm1, log1p, cbrt, hypot
+# --------------------------------------------------------------------------
+
+def test_log10_exp10_cbrt_exact_points():
+    """log10(10^n) = n, exp10(n) = RN(10^n) (Python's int -> float conversion
+    rounds half to even, an independent rounding of the exact integer;
+    10^23 is a midpoint), cbrt of exact cubes."""
+    for n in range(0, 23):
+        assert evaluate1("log10", "f64", float(10 ** n))[0] == float(n)
+    for n in range(0, 309):
+        assert evaluate1("exp10", "f64", float(n))[0] == float(10 ** n), n
+    assert evaluate1("exp10", "f64", 23.0)[0] == 1e23
+    assert evaluate1("exp10", "f64", 400.0)[0] == math.inf
+    for c in (1, 2, 3, 5, 7, 11, 12345, 2 ** 17 + 1):
+        for e in (-40, -3, 0, 3, 30):
+            x = math.ldexp(float(c ** 3), 3 * e)
+            assert evaluate1("cbrt", "f64", x)[0] == math.ldexp(float(c), e)
+            assert evaluate1("cbrt", "f64", -x)[0] == -math.ldexp(float(c), e)
+    # binary32: cbrt(27) = 3, log10(1e10) = 10 (1e10 is a binary32 value)
+    assert evaluate1("cbrt", "f32", 27.0)[0] == 3.0
+    assert evaluate1("log10", "f32", 1e10)[0] == 10.0
+
+
+def test_expm1_log1p_small_arguments_and_inverse():
+    """For |x| < 2^-54, expm1 x and log1p x round to x (x^2/2 is below half an
+    ulp); and log1p(expm1(x)) = x within the pair's accuracy (MP identity;
+    x > -1, where 1 + expm1 x is not tiny and the identity is well
+    conditioned)."""
+    for x in (1e-17, -1e-17, 5e-324, -5e-324, 2.0 ** -60, -(2.0 ** -1000)):
+        assert evaluate1("expm1", "f64", x)[0] == x
+        assert evaluate1("log1p", "f64", x)[0] == x
+    rng = random.Random(7)
+    for _ in range(60):
+        x = 10 ** rng.uniform(-20, 2) if rng.random() < 0.5 else -(10 ** rng.uniform(-20, 0))
+        _, h, l = evaluate1("expm1", "f64", x)
+        with mpmath.workprec(400):
+            y = mpmath.log1p(mpmath.mpf(h) + mpmath.mpf(l))
+            assert abs(y - x) <= abs(x) * mpmath.mpf(2) ** -100, x
+
+
+def test_cbrt_cube_identity():
+    rng = random.Random(8)
+    for _ in range(80):
+        x = _rand_bits(rng)
+        if not math.isfinite(x) or x == 0:
+            continue
+        _, h, l = evaluate1("cbrt", "f64", x)
+        with mpmath.workprec(400):
+            c = (mpmath.mpf(h) + mpmath.mpf(l)) ** 3
+            assert abs(c - x) <= abs(x) * mpmath.mpf(2) ** -100, x
+
+
+def test_hypot_exact_cases_specials_and_mpmath():
+    # Pythagorean triples, scaled; hypot(x, 0) = |x|; symmetric and even
+    # (m^2 - n^2, 2mn, m^2 + n^2) with m = 2^26 + 1, n = 2^25 - 1: 52- and 53-bit values
+    m, n = 2 ** 26 + 1, 2 ** 25 - 1
+    big = (m * m - n * n, 2 * m * n, m * m + n * n)
+    for a, b, c in ((3, 4, 5), (5, 12, 13), (20, 21, 29), (119, 120, 169), big):
+        if max(a, b, c).bit_length() > 53:
+            continue
+        for e in (-1070, -20, 0, 40, 900):
+            x, y, z = (math.ldexp(float(v), e) for v in (a, b, c))
+            if not all(math.isfinite(v) for v in (x, y, z)):
+                continue
+            for sx in (1, -1):
+                assert evaluate1("hypot", "f64", sx * x, y)[0] == z
+                assert evaluate1("hypot", "f64", y, sx * x)[0] == z
+    for x in (0.0, -0.0, 5e-324, -1.5, 1e308):
+        assert same(evaluate1("hypot", "f64", x, 0.0)[0], abs(x))
+    for x in (math.inf, -math.inf):
+        assert evaluate1("hypot", "f64", x, math.nan)[0] == math.inf
+        assert evaluate1("hypot", "f64", math.nan, x)[0] == math.inf
+    assert math.isnan(evaluate1("hypot", "f64", math.nan, 1.0)[0])
+    assert evaluate1("hypot", "f64", 1.5e308, 1.5e308)[0] == math.inf
+    assert evaluate1("hypot", "f64", 1e308, 1e308)[0] == math.hypot(1e308, 1e308)
+    rng = random.Random(9)
+    for _ in range(150):
+        x, y = _rand_bits(rng), _rand_bits(rng)
+        if rng.random() < 0.5:
+            y = x * 10 ** rng.uniform(-20, 0)
+        if not (math.isfinite(x) and math.isfinite(y)):
+            continue
+        got = evaluate1("hypot", "f64", x, y)[0]
+        assert same(got, _to_f64(_mp_f64("hypot", x, y))), (x, y)
+        assert same(got, math.hypot(x, y)) or abs(got - math.hypot(x, y)) <= math.ulp(got)
