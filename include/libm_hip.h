@@ -69,7 +69,14 @@ const char* libm_hip_version(void);
  * "asin and acos": reduction to [0, 0.5] through sqrt((1-x)/2)) and atan
  * (Section 5, "atan": reduction to [0, 1] through 1/x).  exp2, log2, sinh,
  * cosh and tanh are not described in the paper and are built from the same
- * reductions and double-double pieces.
+ * reductions and double-double pieces.  log10, log1p, exp10, expm1 and cbrt
+ * belong to the C99 set the paper's library provides (Section 1) but are
+ * not described either: log10 and log1p through the log reduction (log1p
+ * with 1 + x kept as an exact pair), exp10 and expm1 through the exp
+ * reduction (expm1 with e^r - 1 as a pair and 2^k - 1 as an exact pair),
+ * cbrt by Newton steps on x^(-1/3) from the hardware log2/exp2 estimates and
+ * one double-double residual correction.  All 1.0 ULP; the same Annex F
+ * special values as C99 (exp10 as exp: 10^+-0 = 1, 10^-inf = +0).
  * ---------------------------------------------------------------------- */
 #define LIBM_HIP_DECL_UNARY(fn, var)                                                       \
   libm_hip_status libm_hip_##fn##_##var##_f64(const double* x, double* y, size_t n,        \
@@ -117,6 +124,16 @@ LIBM_HIP_DECL_UNARY_HALF(tanh)
 LIBM_HIP_DECL_UNARY_HALF(asin)
 LIBM_HIP_DECL_UNARY_HALF(acos)
 LIBM_HIP_DECL_UNARY_HALF(atan)
+LIBM_HIP_DECL_UNARY(log10, u10)
+LIBM_HIP_DECL_UNARY(log1p, u10)
+LIBM_HIP_DECL_UNARY(exp10, u10)
+LIBM_HIP_DECL_UNARY(expm1, u10)
+LIBM_HIP_DECL_UNARY(cbrt, u10)
+LIBM_HIP_DECL_UNARY_HALF(log10)
+LIBM_HIP_DECL_UNARY_HALF(log1p)
+LIBM_HIP_DECL_UNARY_HALF(exp10)
+LIBM_HIP_DECL_UNARY_HALF(expm1)
+LIBM_HIP_DECL_UNARY_HALF(cbrt)
 
 /* ------------------------------------------------------------------------
  * Binary functions, C argument order.
@@ -124,6 +141,11 @@ LIBM_HIP_DECL_UNARY_HALF(atan)
  * pow(x, y) (Section 5, "pow": e^(y log x) in double-double), out = x^y.
  * atan2(y, x): quadrant logic around the atan polynomial on [0, 1]
  *   (Section 5, "atan"); out = atan2(y, x).
+ * hypot(x, y): sqrt(x^2 + y^2) without intermediate overflow or underflow
+ *   (C99; not described in the paper): the larger magnitude scaled into
+ *   [0.5, 1), the sum of squares as a double-double pair, a reciprocal
+ *   square root estimate refined by Newton steps and one residual
+ *   correction; 1.0 ULP; an infinite argument gives +inf even with a NaN.
  * fmod(x, y), remainder(x, y): exact; long division with floating-point
  *   digits (Section 5, "FP Remainder", Algorithm 1, Appendices B and C),
  *   extended to quotients beyond DBL_MAX.  remainder rounds the quotient to
@@ -142,6 +164,11 @@ LIBM_HIP_DECL_BINARY(atan2, _u10, float, f32)
 LIBM_HIP_DECL_BINARY(atan2, _u10, uint16_t, bf16)
 LIBM_HIP_DECL_BINARY(atan2, _u10, uint16_t, f16)
 LIBM_HIP_DECL_BINARY(atan2, _u10, float, f32_via_f64)
+LIBM_HIP_DECL_BINARY(hypot, _u10, double, f64)
+LIBM_HIP_DECL_BINARY(hypot, _u10, float, f32)
+LIBM_HIP_DECL_BINARY(hypot, _u10, uint16_t, bf16)
+LIBM_HIP_DECL_BINARY(hypot, _u10, uint16_t, f16)
+LIBM_HIP_DECL_BINARY(hypot, _u10, float, f32_via_f64)
 LIBM_HIP_DECL_BINARY(fmod, , double, f64)
 LIBM_HIP_DECL_BINARY(fmod, , float, f32)
 LIBM_HIP_DECL_BINARY(remainder, , double, f64)
@@ -186,6 +213,8 @@ typedef enum {
   LIBM_HIP_LOG, LIBM_HIP_LOG2, LIBM_HIP_POW, LIBM_HIP_ATAN2, LIBM_HIP_SINH,
   LIBM_HIP_COSH, LIBM_HIP_TANH, LIBM_HIP_FMOD, LIBM_HIP_REMAINDER,
   LIBM_HIP_ASIN, LIBM_HIP_ACOS, LIBM_HIP_ATAN,
+  LIBM_HIP_LOG10, LIBM_HIP_LOG1P, LIBM_HIP_EXP10, LIBM_HIP_EXPM1, LIBM_HIP_CBRT,
+  LIBM_HIP_HYPOT,
   LIBM_HIP_NUM_FN
 } libm_hip_fn;
 typedef enum { LIBM_HIP_U10 = 0, LIBM_HIP_U35 = 1, LIBM_HIP_EXACT = 2 } libm_hip_variant;

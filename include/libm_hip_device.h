@@ -85,6 +85,12 @@ LIBM_HIP_DEVICE_UNARY(tanh_u10, OpTanhU10)
 LIBM_HIP_DEVICE_UNARY(asin_u10, OpAsinU10)
 LIBM_HIP_DEVICE_UNARY(acos_u10, OpAcosU10)
 LIBM_HIP_DEVICE_UNARY(atan_u10, OpAtanU10)
+/* log10, log1p, exp10, expm1, cbrt (C99 functions of the paper's library) */
+LIBM_HIP_DEVICE_UNARY(log10_u10, OpLog10U10)
+LIBM_HIP_DEVICE_UNARY(log1p_u10, OpLog1pU10)
+LIBM_HIP_DEVICE_UNARY(exp10_u10, OpExp10U10)
+LIBM_HIP_DEVICE_UNARY(expm1_u10, OpExpm1U10)
+LIBM_HIP_DEVICE_UNARY(cbrt_u10, OpCbrtU10)
 /* 3.5-ULP forms (binary64 and binary32) */
 LIBM_HIP_DEVICE_UNARY_WIDE(sin_u35, OpSinU35)
 LIBM_HIP_DEVICE_UNARY_WIDE(cos_u35, OpCosU35)
@@ -96,6 +102,7 @@ LIBM_HIP_DEVICE_UNARY_WIDE(log_u35, OpLogU35)
 /* pow(x, y) (Section 5, pow) and atan2(y, x), C argument order */
 LIBM_HIP_DEVICE_BINARY(pow_u10, OpPowU10)
 LIBM_HIP_DEVICE_BINARY(atan2_u10, OpAtan2U10)
+LIBM_HIP_DEVICE_BINARY(hypot_u10, OpHypotU10)
 
 /* fmod(x, y) and remainder(x, y), exact (Section 5, FP remainder, Algorithm 1) */
 __device__ __forceinline__ double fmod(double x, double y) { return lmh_ops::OpFmod::f(x, y); }

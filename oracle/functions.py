@@ -576,6 +576,17 @@ def _dd(b):
     return hi, lo
 
 
+def _exact_result(m, e, fmt, zero_sign=1):
+    """An exactly known value m * 2**e: its rounding, and the binary64 pair of
+    the exact value (which may need more bits than the format has, e.g. a
+    midpoint) for the ULP metric."""
+    v = rn_dyadic(m, e, fmt, zero_sign=zero_sign)
+    if m == 0:
+        return v, v, 0.0
+    hi, lo = _dd(exact(m, e))
+    return v, hi, lo
+
+
 def _ziv(fn_ball, args, fmt, prec0):
     prec = prec0
     while prec <= PREC_CAP:
@@ -629,13 +640,11 @@ def evaluate1(fn, fmt_name, x, y=None):
                 v = rn_dyadic(e, 0, fmt)
                 return v, v, 0.0
         if fn == "exp10" and _is_int(x) and x > 0:
-            v = rn_dyadic(10 ** int(min(x, 400.0)), 0, fmt)
-            return v, v, 0.0
+            return _exact_result(10 ** int(min(x, 400.0)), 0, fmt)
         if fn == "cbrt":
             ex = _cbrt_exact(x)
             if ex is not None:
-                v = rn_dyadic(ex[0] if x > 0 else -ex[0], ex[1], fmt)
-                return v, v, 0.0
+                return _exact_result(ex[0] if x > 0 else -ex[0], ex[1], fmt)
         return _ziv(_BALLS[fn], (x,), fmt, prec0)
     if fn == "atan2":
         sp = _special_atan2(x, y, fmt)       # atan2(x, y) in C order
@@ -650,8 +659,7 @@ def evaluate1(fn, fmt_name, x, y=None):
         ex = _pow_exact(x, y)
         if ex is not None:
             m, e = ex
-            v = rn_dyadic(-m if neg else m, e, fmt, zero_sign=-1 if neg else 1)
-            return v, v, 0.0
+            return _exact_result(-m if neg else m, e, fmt, zero_sign=-1 if neg else 1)
         v, hi, lo = _ziv(_ball_pow, (x, y), fmt, prec0)
         if neg:
             return -v, -hi, -lo
@@ -665,8 +673,7 @@ def evaluate1(fn, fmt_name, x, y=None):
         S, e = _sum_squares(x, y)
         r = math.isqrt(S)
         if r * r == S:                                # also |x| when y = 0
-            v = rn_dyadic(r, e // 2, fmt)
-            return v, v, 0.0
+            return _exact_result(r, e // 2, fmt)
         return _ziv(_ball_hypot, (x, y), fmt, prec0)
     if fn in ("fmod", "remainder"):
         sp = _special_fmod(x, y)

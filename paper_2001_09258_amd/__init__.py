@@ -19,17 +19,18 @@ import os
 
 __all__ = ["load", "library_path", "UNARY", "BINARY", "VARIANTS", "entry_name",
            "call", "evaluate", "sin", "cos", "tan", "exp", "exp2", "log", "log2",
-           "sinh", "cosh", "tanh", "pow", "atan2", "fmod", "remainder",
+           "sinh", "cosh", "tanh", "asin", "acos", "atan", "log10", "log1p", "exp10",
+           "expm1", "cbrt", "pow", "atan2", "hypot", "fmod", "remainder",
            "LibmHipError"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBNAME = "libm_hip.so"
 
 UNARY = ("sin", "cos", "tan", "exp", "exp2", "log", "log2", "sinh", "cosh", "tanh",
-         "asin", "acos", "atan")
-BINARY = ("pow", "atan2", "fmod", "remainder")
+         "asin", "acos", "atan", "log10", "log1p", "exp10", "expm1", "cbrt")
+BINARY = ("pow", "atan2", "hypot", "fmod", "remainder")
 # accuracy variants served per function
-VARIANTS = {fn: ("u10",) for fn in UNARY + ("pow", "atan2")}
+VARIANTS = {fn: ("u10",) for fn in UNARY + ("pow", "atan2", "hypot")}
 VARIANTS.update({"sin": ("u10", "u35"), "cos": ("u10", "u35"), "tan": ("u10", "u35"),
                  "asin": ("u10", "u35"), "acos": ("u10", "u35"), "atan": ("u10", "u35"),
                  "log": ("u10", "u35"),
@@ -207,6 +208,8 @@ sin, cos, tan = _unary("sin"), _unary("cos"), _unary("tan")
 exp, exp2, log, log2 = _unary("exp"), _unary("exp2"), _unary("log"), _unary("log2")
 sinh, cosh, tanh = _unary("sinh"), _unary("cosh"), _unary("tanh")
 asin, acos, atan = _unary("asin"), _unary("acos"), _unary("atan")
+log10, log1p, exp10 = _unary("log10"), _unary("log1p"), _unary("exp10")
+expm1, cbrt = _unary("expm1"), _unary("cbrt")
 
 
 def pow(x, y, out=None, via_f64=False):
@@ -217,6 +220,11 @@ def pow(x, y, out=None, via_f64=False):
 def atan2(y, x, out=None, via_f64=False):
     """atan2(y, x) elementwise (C semantics, 1-ULP)."""
     return evaluate("atan2", y, x, "u10", out, via_f64)
+
+
+def hypot(x, y, out=None, via_f64=False):
+    """sqrt(x^2 + y^2) elementwise without spurious overflow (C semantics, 1-ULP)."""
+    return evaluate("hypot", x, y, "u10", out, via_f64)
 
 
 def fmod(x, y, out=None):
@@ -259,7 +267,8 @@ def backward(fn, inputs, gout, outs=None):
 # ---------------------------------------------------------------------------
 FN_CODES = {"sin": 0, "cos": 1, "tan": 2, "exp": 3, "exp2": 4, "log": 5, "log2": 6,
             "pow": 7, "atan2": 8, "sinh": 9, "cosh": 10, "tanh": 11, "fmod": 12,
-            "remainder": 13, "asin": 14, "acos": 15, "atan": 16}
+            "remainder": 13, "asin": 14, "acos": 15, "atan": 16, "log10": 17,
+            "log1p": 18, "exp10": 19, "expm1": 20, "cbrt": 21, "hypot": 22}
 VARIANT_CODES = {"u10": 0, "u35": 1, "exact": 2}
 DTYPE_CODES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "f32_via_f64": 4}
 

@@ -87,16 +87,29 @@ struct Header {
   X(84, IoF64, OpAtanU10, 1) X(85, IoF32, OpAtanU10, 1) X(86, IoBF16, OpAtanU10, 1) \
   X(87, IoF16, OpAtanU10, 1) X(88, IoF32ViaF64, OpAtanU10, 1)                   \
   X(89, IoF64, OpAtanU35, 1) X(90, IoF32, OpAtanU35, 1)                         \
-  X(91, IoF64, OpLogU35, 1) X(92, IoF32, OpLogU35, 1)
-constexpr int NUM_OPS = 93;
+  X(91, IoF64, OpLogU35, 1) X(92, IoF32, OpLogU35, 1)                           \
+  X(93, IoF64, OpLog10U10, 1) X(94, IoF32, OpLog10U10, 1) X(95, IoBF16, OpLog10U10, 1) \
+  X(96, IoF16, OpLog10U10, 1) X(97, IoF32ViaF64, OpLog10U10, 1)                 \
+  X(98, IoF64, OpLog1pU10, 1) X(99, IoF32, OpLog1pU10, 1) X(100, IoBF16, OpLog1pU10, 1) \
+  X(101, IoF16, OpLog1pU10, 1) X(102, IoF32ViaF64, OpLog1pU10, 1)               \
+  X(103, IoF64, OpExp10U10, 1) X(104, IoF32, OpExp10U10, 1) X(105, IoBF16, OpExp10U10, 1) \
+  X(106, IoF16, OpExp10U10, 1) X(107, IoF32ViaF64, OpExp10U10, 1)               \
+  X(108, IoF64, OpExpm1U10, 1) X(109, IoF32, OpExpm1U10, 1) X(110, IoBF16, OpExpm1U10, 1) \
+  X(111, IoF16, OpExpm1U10, 1) X(112, IoF32ViaF64, OpExpm1U10, 1)               \
+  X(113, IoF64, OpCbrtU10, 1) X(114, IoF32, OpCbrtU10, 1) X(115, IoBF16, OpCbrtU10, 1) \
+  X(116, IoF16, OpCbrtU10, 1) X(117, IoF32ViaF64, OpCbrtU10, 1)                 \
+  X(118, IoF64, OpHypotU10, 2) X(119, IoF32, OpHypotU10, 2) X(120, IoBF16, OpHypotU10, 2) \
+  X(121, IoF16, OpHypotU10, 2) X(122, IoF32ViaF64, OpHypotU10, 2)
+constexpr int NUM_OPS = 123;
 
 // host-side code of a (fn, variant, dtype) triple, or -1
 int op_code(int fn, int v, int t) {
   // dtype order in the table: f64, f32, bf16, f16, f32_via_f64
   static const int u10_base[LIBM_HIP_NUM_FN] = {0, 7, 14, 21, 26, 31, 36, 56, 61, 41, 46, 51,
-                                                -1, -1, 70, 77, 84};
+                                                -1, -1, 70, 77, 84, 93, 98, 103, 108, 113,
+                                                118};
   static const int u35_base[LIBM_HIP_NUM_FN] = {5, 12, 19, -1, -1, 91, -1, -1, -1, -1, -1, -1,
-                                                -1, -1, 75, 82, 89};
+                                                -1, -1, 75, 82, 89, -1, -1, -1, -1, -1, -1};
   if (fn < 0 || fn >= LIBM_HIP_NUM_FN || t < 0 || t > 4) return -1;
   if (fn == LIBM_HIP_FMOD || fn == LIBM_HIP_REMAINDER) {
     if (v != LIBM_HIP_EXACT || t > 1) return -1;
@@ -111,6 +124,8 @@ int op_code(int fn, int v, int t) {
 // (from the elementwise kernels' measured times: trig with Payne-Hanek and
 // the remainders are the most expensive, exp/log the cheapest)
 float op_cost(int code) {
+  if (code >= 113) return 0.45f;               // cbrt, hypot
+  if (code >= 93) return 0.4f;                 // log10, log1p, exp10, expm1
   if (code >= 91) return 0.3f;                 // log u35
   if (code >= 70) return 0.6f;                 // asin, acos, atan
   if (code >= 66) return 1.5f;                 // fmod, remainder
@@ -120,7 +135,7 @@ float op_cost(int code) {
   return 0.35f;                                // exp, exp2, log, log2
 }
 
-size_t op_arity(int code) { return code >= 56 && code <= 69 ? 2 : 1; }
+size_t op_arity(int code) { return (code >= 56 && code <= 69) || code >= 118 ? 2 : 1; }
 
 // ---- device side -------------------------------------------------------------
 // One tile of one request.  Kept out of line: each operation's tile loop is

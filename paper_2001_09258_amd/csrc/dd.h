@@ -194,6 +194,16 @@ LMH_INLINE T poly_estrin(T z, const T (&c)[N]) {
   return v[0];
 }
 
+// Estrin over the tail c[OFF..N-1] of a table: the polynomial (P(z) - the
+// first OFF terms) / z^OFF
+template <int OFF, class T, int N>
+LMH_INLINE T poly_estrin_tail(T z, const T (&c)[N]) {
+  T t[N - OFF];
+#pragma unroll
+  for (int i = 0; i < N - OFF; ++i) t[i] = c[OFF + i];
+  return poly_estrin(z, t);
+}
+
 }  // namespace lmh
 
 #pragma STDC FP_CONTRACT DEFAULT

@@ -1,8 +1,10 @@
 // Binary32 evaluators.  The paper covers binary64 only; these follow the same
 // reduction / polynomial / reconstruction structure in binary32, with
 // float-float pairs only where the 1-ULP bound needs them (the reduced
-// argument, the lowest polynomial terms, the reconstructions).  No binary64
-// arithmetic is used.
+// argument, the lowest polynomial terms, the reconstructions).  Binary64
+// arithmetic appears only where a few binary64 instructions replace a longer
+// float-float sequence (one binary64 instruction costs one issue slot on
+// gfx950): the trig Cody-Waite reduction and cbrt.
 #pragma once
 #include "dd.h"
 #include "generated/consts.inc"
@@ -588,6 +590,113 @@ LMH_INLINE float tanhf_u10(float x) {
   }
   r = fabs_(x) < 0x1p-12f ? x : r;
   return isnan_(x) ? x : r;
+}
+
+// ---------------------------------------------------------------------------
+// log10, log1p, exp10, expm1, cbrt, hypot in binary32 (the binary64 forms'
+// structure)
+// ---------------------------------------------------------------------------
+LMH_INLINE fff logf_pair(fff t, float e) {
+  float z = t.hi * t.hi;
+  float t3q = (t.hi * z) * poly_estrin(z, LOG_Q_F32);
+  fff lm = dd2_add(t.hi + t.hi, (t.lo + t.lo) + t3q);
+  fff s = dd2_add2(e * LN2_HI_F, lm.hi);            // e*LN2_HI is exact
+  return mk(s.hi, s.lo + (lm.lo + e * LN2_LO_F));
+}
+
+LMH_INLINE float logf_specials(float x, float r) {
+  r = x == 0.0f ? -__builtin_inff() : r;
+  r = x < 0.0f ? __builtin_nanf("") : r;
+  return (isinf_(x) && x > 0.0f) || isnan_(x) ? x : r;
+}
+
+LMH_INLINE float log10f_u10(float x) {
+  float e;
+  fff t = logf_t(x, e);
+  fff l = dd2_mul(dd2_norm(logf_pair(t, e)), mk(INVLN10_F_H, INVLN10_F_L));
+  return logf_specials(x, l.hi + l.lo);
+}
+
+LMH_INLINE float log1pf_u10(float x) {
+  fff a = dd2_add2(1.0f, x);
+  float m = frexp_mant_(a.hi);
+  int ie = frexp_exp_(a.hi);
+  ie = m < 0.75f ? ie - 1 : ie;
+  float mh = ldexp_(a.hi, -ie), ml = ldexp_(a.lo, -ie);
+  fff num = dd2_add2(mh - 1.0f, ml);
+  fff den = dd2_add(dd2_add(1.0f, mh), ml);
+  fff l = logf_pair(dd2_div(num, den), (float)ie);
+  float r = l.hi + l.lo;
+  r = x == -1.0f ? -__builtin_inff() : r;
+  r = x < -1.0f ? __builtin_nanf("") : r;
+  r = (isinf_(x) && x > 0.0f) || isnan_(x) ? x : r;
+  return fabs_(x) < 0x1p-25f ? x : r;               // rounds to x; keeps +-0
+}
+
+// |x| <= 50 covers every finite, nonzero binary32 result; |k| <= 167 keeps
+// k * LN2_HI (16 bits) exact
+LMH_INLINE float exp10f_u10(float x) {
+  float xc = x > 50.0f ? 50.0f : (x < -50.0f ? -50.0f : x);
+  float k = rint_(xc * LOG2_10_F);
+  fff a = dd2_mul(xc, LN10_F_H);
+  float s = fma_(k, -LN2_HI_F, a.hi);
+  float t = fma_(xc, LN10_F_L, a.lo) + k * -LN2_LO_F;
+  fff r = dd2_add2(s, t);
+  float v = ff_ldexp(expf_core(r.hi, r.lo), (int)k);
+  return isnan_(x) ? x : v;
+}
+
+// below -18, e^x is under half an ulp of 1 (2^-25) and the result is -1
+LMH_INLINE float expm1f_u10(float x) {
+  float xc = x > 89.0f ? 89.0f : (x < -18.0f ? -18.0f : x);
+  float k = rint_(xc * LOG2E_F);
+  float s0 = fma_(k, -LN2_HI_F, xc);
+  float t0 = k * -LN2_LO_F;
+  float rh = s0 + t0;
+  float rl = (s0 - rh) + t0;
+  fff h = dd2_mul(rh, rh);
+  fff em = dd2_add(rh, mk(0.5f * h.hi, 0.5f * h.lo));
+  em.lo += fma_(rh * h.hi, poly_estrin_tail<1>(rh, EXP_P_F32), fma_(rh, rl, rl));
+  int kh = (int)k - 1;
+  fff t = mk(ldexp_(em.hi, kh), ldexp_(em.lo, kh));
+  fff d = dd2_add2(ldexp_(1.0f, kh), -0.5f);
+  fff sum = dd2_add2(t, d);
+  float r = 2.0f * (sum.hi + sum.lo);
+  r = x < -18.0f ? -1.0f : r;
+  r = isnan_(x) ? x : r;
+  return fabs_(x) < 0x1p-25f ? x : r;
+}
+
+// cbrt in binary64: a = m 2^i in [0.5, 4) as for binary64, one Newton step
+// on the hardware estimate (~2^-43), y = a z^2 rounded once to binary32
+LMH_INLINE float cbrtf_u10(float x) {
+  double ax = fabs_((double)x);
+  double m = frexp_mant_(ax);
+  int e = frexp_exp_(ax);
+  int q = (e + 1200) / 3 - 400;
+  double a = ldexp_(m, e - 3 * q);
+  double z = (double)exp2_est_(log2_est_((float)a) * (-1.0f / 3.0f));
+  z = fma_(z * THIRD_D_H, fma_(-a, z * z * z, 1.0), z);
+  float r = (float)ldexp_(a * (z * z), q);
+  r = copysign_(r, x);
+  return (x == 0.0f || !isfinite_(x)) ? x : r;
+}
+
+// hypot in binary64: the squares of binary32 values are exact there and
+// their sum is rounded once; sqrt from the reciprocal square root estimate
+// and two Newton steps (~2^-50), rounded once to binary32
+LMH_INLINE float hypotf_u10(float x, float y) {
+  double a = (double)x, b = (double)y;
+  double S = fma_(a, a, b * b);
+  double g = rsq_(S);
+  double h = 0.5 * g;
+  double r = S * g;
+  r = fma_(h, fma_(-r, r, S), r);
+  r = fma_(h, fma_(-r, r, S), r);
+  float v = (float)r;
+  v = S == 0.0 ? 0.0f : v;
+  v = isnan_(x) || isnan_(y) ? __builtin_nanf("") : v;
+  return isinf_(x) || isinf_(y) ? __builtin_inff() : v;
 }
 
 // ---------------------------------------------------------------------------

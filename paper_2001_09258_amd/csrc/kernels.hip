@@ -247,6 +247,11 @@ LMH_DEF_UNARY(acos, u10, OpAcosU10, ACOS, U10)
 LMH_DEF_UNARY(acos, u35, OpAcosU35, ACOS, U35)
 LMH_DEF_UNARY(atan, u10, OpAtanU10, ATAN, U10)
 LMH_DEF_UNARY(atan, u35, OpAtanU35, ATAN, U35)
+LMH_DEF_UNARY(log10, u10, OpLog10U10, LOG10, U10)
+LMH_DEF_UNARY(log1p, u10, OpLog1pU10, LOG1P, U10)
+LMH_DEF_UNARY(exp10, u10, OpExp10U10, EXP10, U10)
+LMH_DEF_UNARY(expm1, u10, OpExpm1U10, EXPM1, U10)
+LMH_DEF_UNARY(cbrt, u10, OpCbrtU10, CBRT, U10)
 LMH_DEF_UNARY_HALF(sin, OpSinU10, SIN)
 LMH_DEF_UNARY_HALF(cos, OpCosU10, COS)
 LMH_DEF_UNARY_HALF(tan, OpTanU10, TAN)
@@ -260,6 +265,11 @@ LMH_DEF_UNARY_HALF(tanh, OpTanhU10, TANH)
 LMH_DEF_UNARY_HALF(asin, OpAsinU10, ASIN)
 LMH_DEF_UNARY_HALF(acos, OpAcosU10, ACOS)
 LMH_DEF_UNARY_HALF(atan, OpAtanU10, ATAN)
+LMH_DEF_UNARY_HALF(log10, OpLog10U10, LOG10)
+LMH_DEF_UNARY_HALF(log1p, OpLog1pU10, LOG1P)
+LMH_DEF_UNARY_HALF(exp10, OpExp10U10, EXP10)
+LMH_DEF_UNARY_HALF(expm1, OpExpm1U10, EXPM1)
+LMH_DEF_UNARY_HALF(cbrt, OpCbrtU10, CBRT)
 
 #define LMH_DEF_BINARY(fn, var, Io, T, tag, Op, KEY)                                              \
   libm_hip_status libm_hip_##fn##var##_##tag(const T* a, const T* b, T* out, size_t n, void* s) { \
@@ -276,6 +286,11 @@ LMH_DEF_BINARY(atan2, _u10, IoF32, float, f32, OpAtan2U10, LMH_KEY(ATAN2, U10, F
 LMH_DEF_BINARY(atan2, _u10, IoBF16, uint16_t, bf16, OpAtan2U10, LMH_KEY(ATAN2, U10, BF16))
 LMH_DEF_BINARY(atan2, _u10, IoF16, uint16_t, f16, OpAtan2U10, LMH_KEY(ATAN2, U10, F16))
 LMH_DEF_BINARY(atan2, _u10, IoF32ViaF64, float, f32_via_f64, OpAtan2U10, LMH_KEY(ATAN2, U10, F32_VIA_F64))
+LMH_DEF_BINARY(hypot, _u10, IoF64, double, f64, OpHypotU10, LMH_KEY(HYPOT, U10, F64))
+LMH_DEF_BINARY(hypot, _u10, IoF32, float, f32, OpHypotU10, LMH_KEY(HYPOT, U10, F32))
+LMH_DEF_BINARY(hypot, _u10, IoBF16, uint16_t, bf16, OpHypotU10, LMH_KEY(HYPOT, U10, BF16))
+LMH_DEF_BINARY(hypot, _u10, IoF16, uint16_t, f16, OpHypotU10, LMH_KEY(HYPOT, U10, F16))
+LMH_DEF_BINARY(hypot, _u10, IoF32ViaF64, float, f32_via_f64, OpHypotU10, LMH_KEY(HYPOT, U10, F32_VIA_F64))
 LMH_DEF_BINARY(fmod, , IoF64, double, f64, OpFmod, LMH_KEY(FMOD, EXACT, F64))
 LMH_DEF_BINARY(fmod, , IoF32, float, f32, OpFmod, LMH_KEY(FMOD, EXACT, F32))
 LMH_DEF_BINARY(remainder, , IoF64, double, f64, OpRemainder, LMH_KEY(REMAINDER, EXACT, F64))
@@ -409,6 +424,12 @@ extern "C" libm_hip_status libm_hip_eval(libm_hip_fn fn, libm_hip_variant v, lib
       if (u10) return dispatch_unary<OpAtanU10>(t, a, out, n, s, false, key);
       if (u35) return dispatch_unary<OpAtanU35>(t, a, out, n, s, true, key);
       break;
+    case LIBM_HIP_LOG10: if (u10) return dispatch_unary<OpLog10U10>(t, a, out, n, s, false, key); break;
+    case LIBM_HIP_LOG1P: if (u10) return dispatch_unary<OpLog1pU10>(t, a, out, n, s, false, key); break;
+    case LIBM_HIP_EXP10: if (u10) return dispatch_unary<OpExp10U10>(t, a, out, n, s, false, key); break;
+    case LIBM_HIP_EXPM1: if (u10) return dispatch_unary<OpExpm1U10>(t, a, out, n, s, false, key); break;
+    case LIBM_HIP_CBRT: if (u10) return dispatch_unary<OpCbrtU10>(t, a, out, n, s, false, key); break;
+    case LIBM_HIP_HYPOT: if (u10) return dispatch_binary<OpHypotU10>(t, a, b, out, n, s, true, key); break;
     case LIBM_HIP_POW: if (u10) return dispatch_binary<OpPowU10>(t, a, b, out, n, s, true, key); break;
     case LIBM_HIP_ATAN2: if (u10) return dispatch_binary<OpAtan2U10>(t, a, b, out, n, s, true, key); break;
     case LIBM_HIP_FMOD:

@@ -115,6 +115,12 @@ LMH_OP1(OpAcosU10, acos_u10, acosf_u10)
 LMH_OP1(OpAcosU35, acos_u35, acosf_u35)
 LMH_OP1(OpAtanU10, atan_u10, atanf_u10)
 LMH_OP1(OpAtanU35, atan_u35, atanf_u35)
+LMH_OP1(OpLog10U10, log10_u10, log10f_u10)
+LMH_OP1(OpLog1pU10, log1p_u10, log1pf_u10)
+LMH_OP1(OpExp10U10, exp10_u10, exp10f_u10)
+LMH_OP1(OpExpm1U10, expm1_u10, expm1f_u10)
+LMH_OP1(OpCbrtU10, cbrt_u10, cbrtf_u10)
+LMH_OP2(OpHypotU10, hypot_u10, hypotf_u10)
 LMH_OP2(OpPowU10, pow_u10, powf_u10)
 LMH_OP2(OpAtan2U10, atan2_u10, atan2f_u10)
 LMH_OP2(OpFmod, fmod_f64, fmodf_f32)

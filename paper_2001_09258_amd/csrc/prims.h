@@ -41,6 +41,12 @@ LMH_INLINE int frexp_exp_(float x) { return __builtin_amdgcn_frexp_expf(x); }
 // hardware reciprocal estimate (refined by the callers with Newton steps)
 LMH_INLINE double rcp_(double x) { return __builtin_amdgcn_rcp(x); }
 LMH_INLINE float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+// hardware reciprocal square root estimate (refined by Newton steps)
+LMH_INLINE double rsq_(double x) { return __builtin_amdgcn_rsq(x); }
+// hardware base-2 logarithm and exponential estimates (v_log_f32, v_exp_f32,
+// about 22 correct bits): only ever the starting point of Newton steps
+LMH_INLINE float log2_est_(float x) { return __builtin_amdgcn_logf(x); }
+LMH_INLINE float exp2_est_(float x) { return __builtin_amdgcn_exp2f(x); }
 LMH_INLINE bool isnan_(double x) { return __builtin_isnan(x); }
 LMH_INLINE bool isnan_(float x) { return __builtin_isnan(x); }
 LMH_INLINE bool isinf_(double x) { return __builtin_isinf(x); }

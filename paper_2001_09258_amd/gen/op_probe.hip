@@ -35,6 +35,12 @@ K1(p64_atan, double, atan_u10(v))
 K1(p64_atan35, double, atan_u35(v))
 __global__ void p64_pow(const double* x, double* y) { int i = threadIdx.x; y[i] = pow_u10(x[i], x[i+64]); }
 __global__ void p64_atan2(const double* x, double* y) { int i = threadIdx.x; y[i] = atan2_u10(x[i], x[i+64]); }
+__global__ void p64_hypot(const double* x, double* y) { int i = threadIdx.x; y[i] = hypot_u10(x[i], x[i+64]); }
+K1(p64_log10, double, log10_u10(v))
+K1(p64_log1p, double, log1p_u10(v))
+K1(p64_exp10, double, exp10_u10(v))
+K1(p64_expm1, double, expm1_u10(v))
+K1(p64_cbrt, double, cbrt_u10(v))
 // binary32 pieces
 KS(p32_sincw, float, sincosf_fast(v, false))
 KS(p32_coscw, float, sincosf_fast(v, true))
@@ -62,3 +68,9 @@ K1(p32_atan, float, atanf_u10(v))
 K1(p32_atan35, float, atanf_u35(v))
 __global__ void p32_pow(const float* x, float* y) { int i = threadIdx.x; y[i] = powf_u10(x[i], x[i+64]); }
 __global__ void p32_atan2(const float* x, float* y) { int i = threadIdx.x; y[i] = atan2f_u10(x[i], x[i+64]); }
+__global__ void p32_hypot(const float* x, float* y) { int i = threadIdx.x; y[i] = hypotf_u10(x[i], x[i+64]); }
+K1(p32_log10, float, log10f_u10(v))
+K1(p32_log1p, float, log1pf_u10(v))
+K1(p32_exp10, float, exp10f_u10(v))
+K1(p32_expm1, float, expm1f_u10(v))
+K1(p32_cbrt, float, cbrtf_u10(v))

@@ -108,6 +108,12 @@ extern "C" int device_api_eval(int fn, int variant, int dtype, const void* a, co
     case 14: U1(asin_u10)
     case 15: U1(acos_u10)
     case 16: U1(atan_u10)
+    case 17: U1(log10_u10)
+    case 18: U1(log1p_u10)
+    case 19: U1(exp10_u10)
+    case 20: U1(expm1_u10)
+    case 21: U1(cbrt_u10)
+    case 22: B2(hypot_u10)
   }
   return 2;
 }

@@ -111,3 +111,26 @@ def test_batch_inverse_trig_and_log_u35_requests():
     for (fn, v, dt, a, b, out), r in zip(reqs, ref):
         assert _same(out, r), (fn, v, dt)
     plan.close()
+
+
+def test_batch_c99_function_requests():
+    """log10, log1p, exp10, expm1, cbrt and hypot in every dtype through one
+    plan (hypot binary), against the per-function entry points."""
+    reqs = []
+    kinds = [(f, d) for f in ("log10", "log1p", "exp10", "expm1", "cbrt", "hypot")
+             for d in ("f64", "f32", "bf16", "f16", "f32_via_f64")]
+    for i, (fn, dt) in enumerate(kinds):
+        base = "f32" if dt == "f32_via_f64" else dt
+        a = W.function_mixture(fn, base, 4000 + 991 * i, 400 + i)
+        ta = to_device(a, dt)
+        tb = None
+        if fn == "hypot":
+            tb = to_device(W.function_mixture(fn, base, a.size, 450 + i), dt)
+        reqs.append((fn, "u10", dt, ta, tb, torch.empty_like(ta)))
+    ref = _reference(reqs)
+    plan = L.BatchPlan(64, use_graph=True)
+    plan.run(reqs)
+    torch.cuda.synchronize()
+    for (fn, v, dt, a, b, out), r in zip(reqs, ref):
+        assert _same(out, r), (fn, v, dt)
+    plan.close()

@@ -3,8 +3,8 @@ patterns and regular grids, Section 6; a GPU can afford every pattern).
 
 * binary32: every STRIDE-th bit pattern (default stride 61, an odd step so
   every residue of the low mantissa bits is visited; LIBM_HIP_SWEEP_STRIDE=1
-  sweeps all 2^32) for sin u10/u35, cos, tan, exp, log u10/u35, asin u10/u35, acos
-  and atan u10/u35.  The host's
+  sweeps all 2^32) for sin u10/u35, cos, tan, exp, log u10/u35, asin u10/u35, acos,
+  atan u10/u35, log10, log1p, exp10, expm1 and cbrt.  The host's
   binary64 functions screen the results (their error, at most a few binary64
   ulps, is below 1e-7 binary32 ulp); every element the screen cannot clear
   (estimated error within 1e-4 of the bound, a special-class difference, or a
@@ -30,10 +30,13 @@ import paper_2001_09258_amd as L  # noqa: E402
 STRIDE = int(os.environ.get("LIBM_HIP_SWEEP_STRIDE", "61"))
 CHUNK = 1 << 24
 NP_F = {"sin": np.sin, "cos": np.cos, "tan": np.tan, "exp": np.exp, "log": np.log,
-        "asin": np.arcsin, "acos": np.arccos, "atan": np.arctan}
+        "asin": np.arcsin, "acos": np.arccos, "atan": np.arctan, "log10": np.log10,
+        "log1p": np.log1p, "exp10": lambda x: np.power(10.0, x), "expm1": np.expm1,
+        "cbrt": np.cbrt}
 SWEEP = [("sin", "u10"), ("sin", "u35"), ("cos", "u10"), ("tan", "u10"), ("exp", "u10"),
          ("log", "u10"), ("log", "u35"), ("asin", "u10"), ("asin", "u35"), ("acos", "u10"),
-         ("atan", "u10"), ("atan", "u35")]
+         ("atan", "u10"), ("atan", "u35"), ("log10", "u10"), ("log1p", "u10"),
+         ("exp10", "u10"), ("expm1", "u10"), ("cbrt", "u10")]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -106,7 +109,7 @@ def test_binary32_sweep(fn, variant):
 
 
 NARROW_UNARY = ["sin", "cos", "tan", "exp", "exp2", "log", "log2", "sinh", "cosh", "tanh",
-                "asin", "acos", "atan"]
+                "asin", "acos", "atan", "log10", "log1p", "exp10", "expm1", "cbrt"]
 
 
 @pytest.mark.parametrize("dt", ["bf16", "f16"])

@@ -26,9 +26,12 @@ TRIG = [(fn, v, dt) for fn in ("sin", "cos", "tan") for v in ("u10", "u35")
                                      for dt in ("bf16", "f16", "f32_via_f64")]
 OTHERS = [(fn, "u10", dt) for fn in ("exp", "log", "pow", "atan2", "tanh", "asin", "acos")
           for dt in ("f64", "f32")] + [("atan", "u35", "f64"), ("acos", "u35", "f32"),
-                                       ("log", "u35", "f64"),
+                                       ("log", "u35", "f64"), ("log10", "u10", "f32"),
+                                       ("log1p", "u10", "f64"), ("exp10", "u10", "f32"),
+                                       ("expm1", "u10", "f64"), ("cbrt", "u10", "f64"),
+                                       ("hypot", "u10", "f64"), ("hypot", "u10", "f32"),
                                        ("fmod", "exact", "f64"), ("remainder", "exact", "f32")]
-BINARY = ("pow", "atan2", "fmod", "remainder")
+BINARY = ("pow", "atan2", "hypot", "fmod", "remainder")
 SLOW = {"f64": 2.0 ** 14, "f32": 65536.0, "bf16": 65536.0, "f16": 65536.0, "f32_via_f64": 2.0 ** 14}
 
 

@@ -25,7 +25,8 @@ __all__ = ["FN_IDS", "rng_for", "specials", "small_set", "mixture", "large_args"
 
 FN_IDS = {name: i for i, name in enumerate(
     ["sin", "cos", "tan", "exp", "exp2", "log", "log2", "pow", "atan2",
-     "sinh", "cosh", "tanh", "fmod", "remainder", "asin", "acos", "atan"])}
+     "sinh", "cosh", "tanh", "fmod", "remainder", "asin", "acos", "atan",
+     "log10", "log1p", "exp10", "expm1", "cbrt", "hypot"])}
 
 DTYPE_MAX = {"f64": np.finfo(np.float64).max, "f32": float(np.finfo(np.float32).max),
              "f16": 65504.0, "bf16": 3.3895313892515355e38}
@@ -195,12 +196,23 @@ def unit_mixture(fn, dt, n=1 << 26, operand=0):
 
 def function_mixture(fn, dt, n=1 << 26, operand=0):
     """The benchmark-style input of ``fn``: ``unit_mixture`` for asin and
-    acos, otherwise the mixture (bf16/f16: its narrow form)."""
+    acos, otherwise the mixture (bf16/f16: its narrow form).  For log1p a
+    fifth of the elements, drawn per element, are -(1 - 10^U[near, 0]) with
+    near = -16 (binary64), -7 (binary32, bf16) or -3 (f16): next to -1, where
+    1 + x cancels."""
     if fn in ("asin", "acos"):
         return unit_mixture(fn, dt, n, operand)
     if dt in ("bf16", "f16"):
-        return narrow_mixture(fn, dt, n, operand)
-    return mixture(fn, dt, n, operand)
+        x = narrow_mixture(fn, dt, n, operand)
+    else:
+        x = mixture(fn, dt, n, operand)
+    if fn == "log1p":
+        rng = rng_for(9, fn, operand)
+        m = rng.random(n) < 0.2
+        near = {"f64": -16.0, "f16": -3.0}.get(dt, -7.0)
+        v = -(1.0 - np.exp(rng.uniform(near, 0.0, int(m.sum())) * np.log(10.0)))
+        x[m] = _cast(v, dt)
+    return x
 
 
 # every (fn, variant) the library serves, used to draw batched requests
