@@ -365,31 +365,36 @@ def extra_inverse_trig(lib, L, stream, n, reps, ops):
     return res
 
 
-def extra_c99(lib, L, stream, n, reps, ops):
-    """log10, log1p, exp10, expm1, cbrt (unary) and hypot (binary), binary64
-    and binary32, on 2^26 elements of each function's mixture; per kernel the
-    same roofline fractions as the step's."""
+C99_EXTRA = [(fn, "u10") for fn in ("log10", "log1p", "exp10", "expm1", "cbrt", "hypot")]
+U35_EXTRA = [(fn, "u35") for fn in ("atan2", "sinh", "cosh", "tanh")]
+
+
+def extra_functions(lib, L, stream, n, reps, ops, kinds):
+    """Further function-variants, binary64 and binary32, on 2^26 elements of
+    each function's mixture (two operands for binary functions); per kernel
+    the same roofline fractions as the step's."""
     import torch
     import workloads as W
     sh = stream.cuda_stream
     res = {}
-    for fn in ("log10", "log1p", "exp10", "expm1", "cbrt", "hypot"):
+    for fn, var in kinds:
+        binary = fn in L.BINARY
         for dt in ("f64", "f32"):
             a = W.function_mixture(fn, dt, n, 0)
             ta = torch.from_numpy(a).cuda()
             to = torch.empty_like(ta)
-            nm = L.entry_name(fn, "u10", dt)
-            if fn == "hypot":
+            nm = L.entry_name(fn, var, dt)
+            if binary:
                 tb = torch.from_numpy(W.function_mixture(fn, dt, n, 1)).cuda()
                 args = (ta.data_ptr(), tb.data_ptr(), to.data_ptr(), n, sh)
             else:
                 tb = None
                 args = (ta.data_ptr(), to.data_ptr(), n, sh)
             ms = time_launches(stream, [checked(lib, nm, getattr(lib, nm), *args)], reps)[0]
-            vo, v64, _ = valu_ops(fn, "u10", dt, a, ops)
+            vo, v64, _ = valu_ops(fn, var, dt, a, ops)
             slots = max(v64, vo / 2)
-            nb = ESIZE[dt] * (3 if fn == "hypot" else 2)
-            res["%s_u10_%s" % (fn, dt)] = {
+            nb = ESIZE[dt] * (3 if binary else 2)
+            res["%s_%s_%s" % (fn, var, dt)] = {
                 "ms": round(ms, 4), "gelem_s": round(n / ms / 1e6, 2),
                 "valu_per_elem": vo, "valu_f64_per_elem": v64,
                 "hbm_frac": round(nb * n / HBM_PEAK / (ms * 1e-3), 4),
@@ -641,7 +646,9 @@ def main():
             result["inverse_trig"] = extra_inverse_trig(lib, L, stream, n, args.reps,
                                                         json.load(fh))
         with open(OPS_FILE) as fh:
-            result["c99_functions"] = extra_c99(lib, L, stream, n, args.reps, json.load(fh))
+            ops = json.load(fh)
+        result["c99_functions"] = extra_functions(lib, L, stream, n, args.reps, ops, C99_EXTRA)
+        result["u35_forms"] = extra_functions(lib, L, stream, n, args.reps, ops, U35_EXTRA)
         result["trig_sorted_by_path"] = extra_sorted_paths(lib, L, stream, host, n, args.reps)
         with open(OPS_FILE) as fh:
             result["small_set_f64_warm"] = extra_small_set(lib, L, stream, args.reps, json.load(fh))

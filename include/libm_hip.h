@@ -69,7 +69,9 @@ const char* libm_hip_version(void);
  * "asin and acos": reduction to [0, 0.5] through sqrt((1-x)/2)) and atan
  * (Section 5, "atan": reduction to [0, 1] through 1/x).  exp2, log2, sinh,
  * cosh and tanh are not described in the paper and are built from the same
- * reductions and double-double pieces.  log10, log1p, exp10, expm1 and cbrt
+ * reductions and double-double pieces; their 3.5-ULP forms (binary64 and
+ * binary32) drop the double-double: e^|x|/2 in working precision and one
+ * IEEE division.  log10, log1p, exp10, expm1 and cbrt
  * belong to the C99 set the paper's library provides (Section 1) but are
  * not described either: log10 and log1p through the log reduction (log1p
  * with 1 + x kept as an exact pair), exp10 and expm1 through the exp
@@ -105,6 +107,9 @@ LIBM_HIP_DECL_UNARY(log2, u10)
 LIBM_HIP_DECL_UNARY(sinh, u10)
 LIBM_HIP_DECL_UNARY(cosh, u10)
 LIBM_HIP_DECL_UNARY(tanh, u10)
+LIBM_HIP_DECL_UNARY(sinh, u35)
+LIBM_HIP_DECL_UNARY(cosh, u35)
+LIBM_HIP_DECL_UNARY(tanh, u35)
 LIBM_HIP_DECL_UNARY(asin, u10)
 LIBM_HIP_DECL_UNARY(asin, u35)
 LIBM_HIP_DECL_UNARY(acos, u10)
@@ -140,7 +145,9 @@ LIBM_HIP_DECL_UNARY_HALF(cbrt)
  *
  * pow(x, y) (Section 5, "pow": e^(y log x) in double-double), out = x^y.
  * atan2(y, x): quadrant logic around the atan polynomial on [0, 1]
- *   (Section 5, "atan"); out = atan2(y, x).
+ *   (Section 5, "atan"); out = atan2(y, x).  The 3.5-ULP form (binary64 and
+ *   binary32) takes the ratio by one IEEE division and evaluates the
+ *   polynomial and the pi/2, pi reconstructions in working precision.
  * hypot(x, y): sqrt(x^2 + y^2) without intermediate overflow or underflow
  *   (C99; not described in the paper): the larger magnitude scaled into
  *   [0.5, 1), the sum of squares as a double-double pair, a reciprocal
@@ -164,6 +171,8 @@ LIBM_HIP_DECL_BINARY(atan2, _u10, float, f32)
 LIBM_HIP_DECL_BINARY(atan2, _u10, uint16_t, bf16)
 LIBM_HIP_DECL_BINARY(atan2, _u10, uint16_t, f16)
 LIBM_HIP_DECL_BINARY(atan2, _u10, float, f32_via_f64)
+LIBM_HIP_DECL_BINARY(atan2, _u35, double, f64)
+LIBM_HIP_DECL_BINARY(atan2, _u35, float, f32)
 LIBM_HIP_DECL_BINARY(hypot, _u10, double, f64)
 LIBM_HIP_DECL_BINARY(hypot, _u10, float, f32)
 LIBM_HIP_DECL_BINARY(hypot, _u10, uint16_t, bf16)

@@ -55,6 +55,10 @@ namespace libm_hip_device {
   __device__ __forceinline__ double NAME(double x) { return lmh_ops::OP::f(x); }            \
   __device__ __forceinline__ float NAME(float x) { return lmh_ops::OP::f(x); }
 
+#define LIBM_HIP_DEVICE_BINARY_WIDE(NAME, OP)                                             \
+  __device__ __forceinline__ double NAME(double a, double b) { return lmh_ops::OP::f(a, b); } \
+  __device__ __forceinline__ float NAME(float a, float b) { return lmh_ops::OP::f(a, b); }
+
 #define LIBM_HIP_DEVICE_BINARY(NAME, OP)                                                  \
   __device__ __forceinline__ double NAME(double a, double b) { return lmh_ops::OP::f(a, b); } \
   __device__ __forceinline__ float NAME(float a, float b) { return lmh_ops::OP::f(a, b); }    \
@@ -99,10 +103,14 @@ LIBM_HIP_DEVICE_UNARY_WIDE(asin_u35, OpAsinU35)
 LIBM_HIP_DEVICE_UNARY_WIDE(acos_u35, OpAcosU35)
 LIBM_HIP_DEVICE_UNARY_WIDE(atan_u35, OpAtanU35)
 LIBM_HIP_DEVICE_UNARY_WIDE(log_u35, OpLogU35)
+LIBM_HIP_DEVICE_UNARY_WIDE(sinh_u35, OpSinhU35)
+LIBM_HIP_DEVICE_UNARY_WIDE(cosh_u35, OpCoshU35)
+LIBM_HIP_DEVICE_UNARY_WIDE(tanh_u35, OpTanhU35)
 /* pow(x, y) (Section 5, pow) and atan2(y, x), C argument order */
 LIBM_HIP_DEVICE_BINARY(pow_u10, OpPowU10)
 LIBM_HIP_DEVICE_BINARY(atan2_u10, OpAtan2U10)
 LIBM_HIP_DEVICE_BINARY(hypot_u10, OpHypotU10)
+LIBM_HIP_DEVICE_BINARY_WIDE(atan2_u35, OpAtan2U35)
 
 /* fmod(x, y) and remainder(x, y), exact (Section 5, FP remainder, Algorithm 1) */
 __device__ __forceinline__ double fmod(double x, double y) { return lmh_ops::OpFmod::f(x, y); }
@@ -151,6 +159,7 @@ __device__ __forceinline__ T masked(bool active, T x, F f) {
 #undef LIBM_HIP_DEVICE_UNARY
 #undef LIBM_HIP_DEVICE_UNARY_WIDE
 #undef LIBM_HIP_DEVICE_BINARY
+#undef LIBM_HIP_DEVICE_BINARY_WIDE
 #undef LIBM_HIP_DEVICE_BWD
 
 }  // namespace libm_hip_device

@@ -33,7 +33,8 @@ BINARY = ("pow", "atan2", "hypot", "fmod", "remainder")
 VARIANTS = {fn: ("u10",) for fn in UNARY + ("pow", "atan2", "hypot")}
 VARIANTS.update({"sin": ("u10", "u35"), "cos": ("u10", "u35"), "tan": ("u10", "u35"),
                  "asin": ("u10", "u35"), "acos": ("u10", "u35"), "atan": ("u10", "u35"),
-                 "log": ("u10", "u35"),
+                 "log": ("u10", "u35"), "atan2": ("u10", "u35"), "sinh": ("u10", "u35"),
+                 "cosh": ("u10", "u35"), "tanh": ("u10", "u35"),
                  "fmod": ("exact",), "remainder": ("exact",)})
 DTYPES = ("f64", "f32", "bf16", "f16", "f32_via_f64")
 
@@ -217,9 +218,9 @@ def pow(x, y, out=None, via_f64=False):
     return evaluate("pow", x, y, "u10", out, via_f64)
 
 
-def atan2(y, x, out=None, via_f64=False):
-    """atan2(y, x) elementwise (C semantics, 1-ULP)."""
-    return evaluate("atan2", y, x, "u10", out, via_f64)
+def atan2(y, x, variant="u10", out=None, via_f64=False):
+    """atan2(y, x) elementwise (C semantics; variant 'u10' or 'u35')."""
+    return evaluate("atan2", y, x, variant, out, via_f64)
 
 
 def hypot(x, y, out=None, via_f64=False):

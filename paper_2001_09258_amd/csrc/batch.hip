@@ -99,8 +99,12 @@ struct Header {
   X(113, IoF64, OpCbrtU10, 1) X(114, IoF32, OpCbrtU10, 1) X(115, IoBF16, OpCbrtU10, 1) \
   X(116, IoF16, OpCbrtU10, 1) X(117, IoF32ViaF64, OpCbrtU10, 1)                 \
   X(118, IoF64, OpHypotU10, 2) X(119, IoF32, OpHypotU10, 2) X(120, IoBF16, OpHypotU10, 2) \
-  X(121, IoF16, OpHypotU10, 2) X(122, IoF32ViaF64, OpHypotU10, 2)
-constexpr int NUM_OPS = 123;
+  X(121, IoF16, OpHypotU10, 2) X(122, IoF32ViaF64, OpHypotU10, 2)             \
+  X(123, IoF64, OpAtan2U35, 2) X(124, IoF32, OpAtan2U35, 2)                     \
+  X(125, IoF64, OpSinhU35, 1) X(126, IoF32, OpSinhU35, 1)                       \
+  X(127, IoF64, OpCoshU35, 1) X(128, IoF32, OpCoshU35, 1)                       \
+  X(129, IoF64, OpTanhU35, 1) X(130, IoF32, OpTanhU35, 1)
+constexpr int NUM_OPS = 131;
 
 // host-side code of a (fn, variant, dtype) triple, or -1
 int op_code(int fn, int v, int t) {
@@ -108,8 +112,9 @@ int op_code(int fn, int v, int t) {
   static const int u10_base[LIBM_HIP_NUM_FN] = {0, 7, 14, 21, 26, 31, 36, 56, 61, 41, 46, 51,
                                                 -1, -1, 70, 77, 84, 93, 98, 103, 108, 113,
                                                 118};
-  static const int u35_base[LIBM_HIP_NUM_FN] = {5, 12, 19, -1, -1, 91, -1, -1, -1, -1, -1, -1,
-                                                -1, -1, 75, 82, 89, -1, -1, -1, -1, -1, -1};
+  static const int u35_base[LIBM_HIP_NUM_FN] = {5, 12, 19, -1, -1, 91, -1, -1, 123, 125, 127,
+                                                129, -1, -1, 75, 82, 89, -1, -1, -1, -1, -1,
+                                                -1};
   if (fn < 0 || fn >= LIBM_HIP_NUM_FN || t < 0 || t > 4) return -1;
   if (fn == LIBM_HIP_FMOD || fn == LIBM_HIP_REMAINDER) {
     if (v != LIBM_HIP_EXACT || t > 1) return -1;
@@ -124,6 +129,8 @@ int op_code(int fn, int v, int t) {
 // (from the elementwise kernels' measured times: trig with Payne-Hanek and
 // the remainders are the most expensive, exp/log the cheapest)
 float op_cost(int code) {
+  if (code >= 125) return 0.35f;               // sinh, cosh, tanh u35
+  if (code >= 123) return 0.5f;                // atan2 u35
   if (code >= 113) return 0.45f;               // cbrt, hypot
   if (code >= 93) return 0.4f;                 // log10, log1p, exp10, expm1
   if (code >= 91) return 0.3f;                 // log u35
@@ -135,7 +142,9 @@ float op_cost(int code) {
   return 0.35f;                                // exp, exp2, log, log2
 }
 
-size_t op_arity(int code) { return (code >= 56 && code <= 69) || code >= 118 ? 2 : 1; }
+size_t op_arity(int code) {
+  return (code >= 56 && code <= 69) || (code >= 118 && code <= 124) ? 2 : 1;
+}
 
 // ---- device side -------------------------------------------------------------
 // One tile of one request.  Kept out of line: each operation's tile loop is

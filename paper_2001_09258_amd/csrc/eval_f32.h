@@ -593,6 +593,71 @@ LMH_INLINE float tanhf_u10(float x) {
 }
 
 // ---------------------------------------------------------------------------
+// 3.5-ULP atan2, sinh, cosh, tanh in binary32 (the binary64 forms' structure)
+// ---------------------------------------------------------------------------
+LMH_INLINE float atan2f_u35(float y, float x) {
+  float ay = fabs_(y), ax = fabs_(x);
+  bool both_inf = isinf_(ax) && isinf_(ay);
+  ay = both_inf ? 1.0f : ay;
+  ax = both_inf ? 1.0f : ax;
+  bool swap = ay > ax;
+  float t = (swap ? ax : ay) / (swap ? ay : ax);
+  float z = t * t;
+  float a = fma_(t * z, poly_estrin(z, ATAN_A_F32), t);
+  a = swap ? (PIH2_F_H - a) + PIH2_F_L : a;
+  bool xneg = __builtin_signbit(x);
+  a = xneg ? (PI2_F_H - a) + PI2_F_L : a;
+  float r = copysign_(a, y);
+  if (y == 0.0f) r = xneg ? copysign_(PI2_F_H, y) : copysign_(0.0f, y);
+  return (isnan_(x) || isnan_(y)) ? __builtin_nanf("") : r;
+}
+
+// e^a 2^-s in working precision (|a| <= 104 keeps k * LN2_HI exact)
+LMH_INLINE float expf_ws(float a, int s) {
+  float k = rint_(a * LOG2E_F);
+  float s0 = fma_(k, -LN2_HI_F, a);
+  float t = k * -LN2_LO_F;
+  float rh = s0 + t;
+  float rl = (s0 - rh) + t;
+  fff e = expf_core(rh, rl);
+  return ldexp_(e.hi + e.lo, (int)k - s);
+}
+
+LMH_INLINE float sinhf_u35(float x) {
+  float ax = fabs_(x);
+  float r;
+  if (ax < 1.0f) {
+    float z = x * x;
+    r = fma_(x * z, poly_estrin(z, SINH_H_F32), x);
+  } else {
+    float e = expf_ws(ax > 90.0f ? 90.0f : ax, 1);
+    r = copysign_(e - 0.25f / e, x);
+  }
+  return isnan_(x) ? x : r;
+}
+
+LMH_INLINE float coshf_u35(float x) {
+  float ax = fabs_(x);
+  float e = expf_ws(ax > 90.0f ? 90.0f : ax, 1);
+  float r = e + 0.25f / e;
+  return isnan_(x) ? x : r;
+}
+
+LMH_INLINE float tanhf_u35(float x) {
+  float ax = fabs_(x);
+  float r;
+  if (ax < 0.625f) {
+    float z = x * x;
+    r = fma_(x * z, poly_estrin(z, TANH_G_F32), x);
+  } else {
+    float e2 = expf_ws(ax > 20.0f ? 40.0f : ax + ax, 0);
+    r = copysign_(1.0f - 2.0f / (e2 + 1.0f), x);
+  }
+  r = ax < 0x1p-12f ? x : r;                       // keeps tanh(-0) = -0
+  return isnan_(x) ? x : r;
+}
+
+// ---------------------------------------------------------------------------
 // log10, log1p, exp10, expm1, cbrt, hypot in binary32 (the binary64 forms'
 // structure)
 // ---------------------------------------------------------------------------

@@ -241,6 +241,9 @@ LMH_DEF_UNARY(log2, u10, OpLog2U10, LOG2, U10)
 LMH_DEF_UNARY(sinh, u10, OpSinhU10, SINH, U10)
 LMH_DEF_UNARY(cosh, u10, OpCoshU10, COSH, U10)
 LMH_DEF_UNARY(tanh, u10, OpTanhU10, TANH, U10)
+LMH_DEF_UNARY(sinh, u35, OpSinhU35, SINH, U35)
+LMH_DEF_UNARY(cosh, u35, OpCoshU35, COSH, U35)
+LMH_DEF_UNARY(tanh, u35, OpTanhU35, TANH, U35)
 LMH_DEF_UNARY(asin, u10, OpAsinU10, ASIN, U10)
 LMH_DEF_UNARY(asin, u35, OpAsinU35, ASIN, U35)
 LMH_DEF_UNARY(acos, u10, OpAcosU10, ACOS, U10)
@@ -286,6 +289,8 @@ LMH_DEF_BINARY(atan2, _u10, IoF32, float, f32, OpAtan2U10, LMH_KEY(ATAN2, U10, F
 LMH_DEF_BINARY(atan2, _u10, IoBF16, uint16_t, bf16, OpAtan2U10, LMH_KEY(ATAN2, U10, BF16))
 LMH_DEF_BINARY(atan2, _u10, IoF16, uint16_t, f16, OpAtan2U10, LMH_KEY(ATAN2, U10, F16))
 LMH_DEF_BINARY(atan2, _u10, IoF32ViaF64, float, f32_via_f64, OpAtan2U10, LMH_KEY(ATAN2, U10, F32_VIA_F64))
+LMH_DEF_BINARY(atan2, _u35, IoF64, double, f64, OpAtan2U35, LMH_KEY(ATAN2, U35, F64))
+LMH_DEF_BINARY(atan2, _u35, IoF32, float, f32, OpAtan2U35, LMH_KEY(ATAN2, U35, F32))
 LMH_DEF_BINARY(hypot, _u10, IoF64, double, f64, OpHypotU10, LMH_KEY(HYPOT, U10, F64))
 LMH_DEF_BINARY(hypot, _u10, IoF32, float, f32, OpHypotU10, LMH_KEY(HYPOT, U10, F32))
 LMH_DEF_BINARY(hypot, _u10, IoBF16, uint16_t, bf16, OpHypotU10, LMH_KEY(HYPOT, U10, BF16))
@@ -409,9 +414,18 @@ extern "C" libm_hip_status libm_hip_eval(libm_hip_fn fn, libm_hip_variant v, lib
       if (u35) return dispatch_unary<OpLogU35>(t, a, out, n, s, true, key);
       break;
     case LIBM_HIP_LOG2: if (u10) return dispatch_unary<OpLog2U10>(t, a, out, n, s, false, key); break;
-    case LIBM_HIP_SINH: if (u10) return dispatch_unary<OpSinhU10>(t, a, out, n, s, false, key); break;
-    case LIBM_HIP_COSH: if (u10) return dispatch_unary<OpCoshU10>(t, a, out, n, s, false, key); break;
-    case LIBM_HIP_TANH: if (u10) return dispatch_unary<OpTanhU10>(t, a, out, n, s, false, key); break;
+    case LIBM_HIP_SINH:
+      if (u10) return dispatch_unary<OpSinhU10>(t, a, out, n, s, false, key);
+      if (u35) return dispatch_unary<OpSinhU35>(t, a, out, n, s, true, key);
+      break;
+    case LIBM_HIP_COSH:
+      if (u10) return dispatch_unary<OpCoshU10>(t, a, out, n, s, false, key);
+      if (u35) return dispatch_unary<OpCoshU35>(t, a, out, n, s, true, key);
+      break;
+    case LIBM_HIP_TANH:
+      if (u10) return dispatch_unary<OpTanhU10>(t, a, out, n, s, false, key);
+      if (u35) return dispatch_unary<OpTanhU35>(t, a, out, n, s, true, key);
+      break;
     case LIBM_HIP_ASIN:
       if (u10) return dispatch_unary<OpAsinU10>(t, a, out, n, s, false, key);
       if (u35) return dispatch_unary<OpAsinU35>(t, a, out, n, s, true, key);
@@ -431,7 +445,10 @@ extern "C" libm_hip_status libm_hip_eval(libm_hip_fn fn, libm_hip_variant v, lib
     case LIBM_HIP_CBRT: if (u10) return dispatch_unary<OpCbrtU10>(t, a, out, n, s, false, key); break;
     case LIBM_HIP_HYPOT: if (u10) return dispatch_binary<OpHypotU10>(t, a, b, out, n, s, true, key); break;
     case LIBM_HIP_POW: if (u10) return dispatch_binary<OpPowU10>(t, a, b, out, n, s, true, key); break;
-    case LIBM_HIP_ATAN2: if (u10) return dispatch_binary<OpAtan2U10>(t, a, b, out, n, s, true, key); break;
+    case LIBM_HIP_ATAN2:
+      if (u10) return dispatch_binary<OpAtan2U10>(t, a, b, out, n, s, true, key);
+      if (u35) return dispatch_binary<OpAtan2U35>(t, a, b, out, n, s, false, key);
+      break;
     case LIBM_HIP_FMOD:
       if (v == LIBM_HIP_EXACT) return dispatch_binary<OpFmod>(t, a, b, out, n, s, false, key);
       break;

@@ -121,6 +121,10 @@ LMH_OP1(OpExp10U10, exp10_u10, exp10f_u10)
 LMH_OP1(OpExpm1U10, expm1_u10, expm1f_u10)
 LMH_OP1(OpCbrtU10, cbrt_u10, cbrtf_u10)
 LMH_OP2(OpHypotU10, hypot_u10, hypotf_u10)
+LMH_OP1(OpSinhU35, sinh_u35, sinhf_u35)
+LMH_OP1(OpCoshU35, cosh_u35, coshf_u35)
+LMH_OP1(OpTanhU35, tanh_u35, tanhf_u35)
+LMH_OP2(OpAtan2U35, atan2_u35, atan2f_u35)
 LMH_OP2(OpPowU10, pow_u10, powf_u10)
 LMH_OP2(OpAtan2U10, atan2_u10, atan2f_u10)
 LMH_OP2(OpFmod, fmod_f64, fmodf_f32)

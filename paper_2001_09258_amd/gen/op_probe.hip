@@ -36,6 +36,10 @@ K1(p64_atan35, double, atan_u35(v))
 __global__ void p64_pow(const double* x, double* y) { int i = threadIdx.x; y[i] = pow_u10(x[i], x[i+64]); }
 __global__ void p64_atan2(const double* x, double* y) { int i = threadIdx.x; y[i] = atan2_u10(x[i], x[i+64]); }
 __global__ void p64_hypot(const double* x, double* y) { int i = threadIdx.x; y[i] = hypot_u10(x[i], x[i+64]); }
+__global__ void p64_atan235(const double* x, double* y) { int i = threadIdx.x; y[i] = atan2_u35(x[i], x[i+64]); }
+K1(p64_sinh35, double, sinh_u35(v))
+K1(p64_cosh35, double, cosh_u35(v))
+K1(p64_tanh35, double, tanh_u35(v))
 K1(p64_log10, double, log10_u10(v))
 K1(p64_log1p, double, log1p_u10(v))
 K1(p64_exp10, double, exp10_u10(v))
@@ -69,6 +73,10 @@ K1(p32_atan35, float, atanf_u35(v))
 __global__ void p32_pow(const float* x, float* y) { int i = threadIdx.x; y[i] = powf_u10(x[i], x[i+64]); }
 __global__ void p32_atan2(const float* x, float* y) { int i = threadIdx.x; y[i] = atan2f_u10(x[i], x[i+64]); }
 __global__ void p32_hypot(const float* x, float* y) { int i = threadIdx.x; y[i] = hypotf_u10(x[i], x[i+64]); }
+__global__ void p32_atan235(const float* x, float* y) { int i = threadIdx.x; y[i] = atan2f_u35(x[i], x[i+64]); }
+K1(p32_sinh35, float, sinhf_u35(v))
+K1(p32_cosh35, float, coshf_u35(v))
+K1(p32_tanh35, float, tanhf_u35(v))
 K1(p32_log10, float, log10f_u10(v))
 K1(p32_log1p, float, log1pf_u10(v))
 K1(p32_exp10, float, exp10f_u10(v))

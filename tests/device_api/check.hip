@@ -87,6 +87,10 @@ extern "C" int device_api_eval(int fn, int variant, int dtype, const void* a, co
       case 15: U1W(acos_u35)
       case 16: U1W(atan_u35)
       case 5: U1W(log_u35)
+      case 8: B2W(atan2_u35)
+      case 9: U1W(sinh_u35)
+      case 10: U1W(cosh_u35)
+      case 11: U1W(tanh_u35)
     }
     return 2;
   }

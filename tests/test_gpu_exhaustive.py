@@ -4,7 +4,8 @@ patterns and regular grids, Section 6; a GPU can afford every pattern).
 * binary32: every STRIDE-th bit pattern (default stride 61, an odd step so
   every residue of the low mantissa bits is visited; LIBM_HIP_SWEEP_STRIDE=1
   sweeps all 2^32) for sin u10/u35, cos, tan, exp, log u10/u35, asin u10/u35, acos,
-  atan u10/u35, log10, log1p, exp10, expm1 and cbrt.  The host's
+  atan u10/u35, log10, log1p, exp10, expm1, cbrt, and sinh, cosh, tanh u35.
+  The host's
   binary64 functions screen the results (their error, at most a few binary64
   ulps, is below 1e-7 binary32 ulp); every element the screen cannot clear
   (estimated error within 1e-4 of the bound, a special-class difference, or a
@@ -32,11 +33,12 @@ CHUNK = 1 << 24
 NP_F = {"sin": np.sin, "cos": np.cos, "tan": np.tan, "exp": np.exp, "log": np.log,
         "asin": np.arcsin, "acos": np.arccos, "atan": np.arctan, "log10": np.log10,
         "log1p": np.log1p, "exp10": lambda x: np.power(10.0, x), "expm1": np.expm1,
-        "cbrt": np.cbrt}
+        "cbrt": np.cbrt, "sinh": np.sinh, "cosh": np.cosh, "tanh": np.tanh}
 SWEEP = [("sin", "u10"), ("sin", "u35"), ("cos", "u10"), ("tan", "u10"), ("exp", "u10"),
          ("log", "u10"), ("log", "u35"), ("asin", "u10"), ("asin", "u35"), ("acos", "u10"),
          ("atan", "u10"), ("atan", "u35"), ("log10", "u10"), ("log1p", "u10"),
-         ("exp10", "u10"), ("expm1", "u10"), ("cbrt", "u10")]
+         ("exp10", "u10"), ("expm1", "u10"), ("cbrt", "u10"), ("sinh", "u35"),
+         ("cosh", "u35"), ("tanh", "u35")]
 
 
 @pytest.fixture(scope="module", autouse=True)
