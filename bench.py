@@ -403,6 +403,33 @@ def extra_functions(lib, L, stream, n, reps, ops, kinds):
     return res
 
 
+def extra_sincos(lib, L, stream, n, reps):
+    """sincos u10 (one pass, two outputs) against sin u10 and cos u10 launched
+    separately, on the same 2^26-element mixture (binary64, binary32)."""
+    import torch
+    import workloads as W
+    sh = stream.cuda_stream
+    res = {}
+    for dt in ("f64", "f32"):
+        ta = torch.from_numpy(W.function_mixture("sin", dt, n, 0)).cuda()
+        ts, tc = torch.empty_like(ta), torch.empty_like(ta)
+        nm = "libm_hip_sincos_u10_%s" % dt
+        one = checked(lib, nm, getattr(lib, nm), ta.data_ptr(), ts.data_ptr(), tc.data_ptr(), n, sh)
+        calls = [checked(lib, L.entry_name(fn, "u10", dt), getattr(lib, L.entry_name(fn, "u10", dt)),
+                         ta.data_ptr(), out.data_ptr(), n, sh)
+                 for fn, out in (("sin", ts), ("cos", tc))]
+
+        def both():
+            for g in calls:
+                g()
+        ms_one, ms_two = time_launches(stream, [one, both], reps)
+        res[dt] = {"sincos_ms": round(ms_one, 4), "sin_plus_cos_ms": round(ms_two, 4),
+                   "gelem_s": round(n / ms_one / 1e6, 2),
+                   "speedup": round(ms_two / ms_one, 3)}
+        del ta, ts, tc
+    return res
+
+
 def extra_sorted_paths(lib, L, stream, host, n, reps):
     """Ablation: the trig kernels on the same inputs sorted so that
     Cody-Waite and Payne-Hanek elements never share a wave, against the
@@ -649,6 +676,7 @@ def main():
             ops = json.load(fh)
         result["c99_functions"] = extra_functions(lib, L, stream, n, args.reps, ops, C99_EXTRA)
         result["u35_forms"] = extra_functions(lib, L, stream, n, args.reps, ops, U35_EXTRA)
+        result["sincos"] = extra_sincos(lib, L, stream, n, args.reps)
         result["trig_sorted_by_path"] = extra_sorted_paths(lib, L, stream, host, n, args.reps)
         with open(OPS_FILE) as fh:
             result["small_set_f64_warm"] = extra_small_set(lib, L, stream, args.reps, json.load(fh))

@@ -141,6 +141,26 @@ LIBM_HIP_DECL_UNARY_HALF(expm1)
 LIBM_HIP_DECL_UNARY_HALF(cbrt)
 
 /* ------------------------------------------------------------------------
+ * sincos: s[i] = sin(x[i]) and c[i] = cos(x[i]) in one pass (the paper's
+ * library provides sincos, Section 1).  Each result is bit-identical to the
+ * sin and cos entry points of the same variant and type: the Cody-Waite
+ * elements take sin's and cos's own reductions, a Payne-Hanek element is
+ * reduced once and mapped to both.  u10: f64, f32, bf16, f16, f32_via_f64;
+ * u35: f64, f32.  s and c are distinct outputs; either may be x itself
+ * (in-place); NULL x, s or c with n > 0 -> LIBM_HIP_ERR_INVALID.
+ * ---------------------------------------------------------------------- */
+#define LIBM_HIP_DECL_SINCOS(var, T, tag)                                                  \
+  libm_hip_status libm_hip_sincos_##var##_##tag(const T* x, T* s, T* c, size_t n,          \
+                                                void* stream);
+LIBM_HIP_DECL_SINCOS(u10, double, f64)
+LIBM_HIP_DECL_SINCOS(u10, float, f32)
+LIBM_HIP_DECL_SINCOS(u10, uint16_t, bf16)
+LIBM_HIP_DECL_SINCOS(u10, uint16_t, f16)
+LIBM_HIP_DECL_SINCOS(u10, float, f32_via_f64)
+LIBM_HIP_DECL_SINCOS(u35, double, f64)
+LIBM_HIP_DECL_SINCOS(u35, float, f32)
+
+/* ------------------------------------------------------------------------
  * Binary functions, C argument order.
  *
  * pow(x, y) (Section 5, "pow": e^(y log x) in double-double), out = x^y.

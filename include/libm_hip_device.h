@@ -112,6 +112,39 @@ LIBM_HIP_DEVICE_BINARY(atan2_u10, OpAtan2U10)
 LIBM_HIP_DEVICE_BINARY(hypot_u10, OpHypotU10)
 LIBM_HIP_DEVICE_BINARY_WIDE(atan2_u35, OpAtan2U35)
 
+/* sincos: *s = sin x, *c = cos x, bit-identical to sin_* and cos_* of the
+   same variant and type */
+__device__ __forceinline__ void sincos_u10(double x, double* s, double* c) {
+  lmh_ops::OpSinCosU10::f(x, *s, *c);
+}
+__device__ __forceinline__ void sincos_u10(float x, float* s, float* c) {
+  lmh_ops::OpSinCosU10::f(x, *s, *c);
+}
+__device__ __forceinline__ void sincos_u35(double x, double* s, double* c) {
+  lmh_ops::OpSinCosU35::f(x, *s, *c);
+}
+__device__ __forceinline__ void sincos_u35(float x, float* s, float* c) {
+  lmh_ops::OpSinCosU35::f(x, *s, *c);
+}
+__device__ __forceinline__ void sincos_u10_via_f64(float x, float* s, float* c) {
+  double sd, cd;
+  lmh_ops::OpSinCosU10::f(lmh_ops::IoF32ViaF64::in(x), sd, cd);
+  *s = lmh_ops::IoF32ViaF64::out(sd);
+  *c = lmh_ops::IoF32ViaF64::out(cd);
+}
+__device__ __forceinline__ void sincos_u10_bf16(uint16_t x, uint16_t* s, uint16_t* c) {
+  float sf, cf;
+  lmh_ops::OpSinCosU10::f(lmh_ops::IoBF16::in(x), sf, cf);
+  *s = lmh_ops::IoBF16::out(sf);
+  *c = lmh_ops::IoBF16::out(cf);
+}
+__device__ __forceinline__ void sincos_u10_f16(uint16_t x, uint16_t* s, uint16_t* c) {
+  float sf, cf;
+  lmh_ops::OpSinCosU10::f(lmh_ops::IoF16::in(x), sf, cf);
+  *s = lmh_ops::IoF16::out(sf);
+  *c = lmh_ops::IoF16::out(cf);
+}
+
 /* fmod(x, y) and remainder(x, y), exact (Section 5, FP remainder, Algorithm 1) */
 __device__ __forceinline__ double fmod(double x, double y) { return lmh_ops::OpFmod::f(x, y); }
 __device__ __forceinline__ float fmod(float x, float y) { return lmh_ops::OpFmod::f(x, y); }

@@ -20,7 +20,7 @@ import os
 __all__ = ["load", "library_path", "UNARY", "BINARY", "VARIANTS", "entry_name",
            "call", "evaluate", "sin", "cos", "tan", "exp", "exp2", "log", "log2",
            "sinh", "cosh", "tanh", "asin", "acos", "atan", "log10", "log1p", "exp10",
-           "expm1", "cbrt", "pow", "atan2", "hypot", "fmod", "remainder",
+           "expm1", "cbrt", "sincos", "pow", "atan2", "hypot", "fmod", "remainder",
            "LibmHipError"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -74,6 +74,12 @@ def bwd_entry_points():
             for fn in BWD_UNARY + BWD_BINARY for dt in ("f64", "f32")]
 
 
+def sincos_entry_points():
+    """(variant, dtype, symbol) of every sincos entry point."""
+    return [(v, dt, "libm_hip_sincos_%s_%s" % (v, dt))
+            for v in ("u10", "u35") for dt in DTYPES if served("sin", v, dt)]
+
+
 def all_entry_points():
     out = []
     for fn in UNARY + BINARY:
@@ -107,6 +113,10 @@ def load():
             f.argtypes = [vp, vp, sz, vp]
         else:
             f.argtypes = [vp, vp, vp, sz, vp]
+    for v, dt, name in sincos_entry_points():
+        f = getattr(lib, name)
+        f.restype = ctypes.c_int
+        f.argtypes = [vp, vp, vp, sz, vp]
     for fn, dt, name in bwd_entry_points():
         f = getattr(lib, name)
         f.restype = ctypes.c_int
@@ -211,6 +221,23 @@ sinh, cosh, tanh = _unary("sinh"), _unary("cosh"), _unary("tanh")
 asin, acos, atan = _unary("asin"), _unary("acos"), _unary("atan")
 log10, log1p, exp10 = _unary("log10"), _unary("log1p"), _unary("exp10")
 expm1, cbrt = _unary("expm1"), _unary("cbrt")
+
+
+def sincos(x, variant="u10", outs=None, via_f64=False):
+    """(sin x, cos x) elementwise in one pass, each bit-identical to sin and
+    cos of the same variant."""
+    import torch
+    if x.device.type != "cuda" or not x.is_contiguous():
+        raise LibmHipError("sincos: expected a contiguous HIP tensor")
+    tag = _dtype_tag(x, via_f64)
+    if not served("sin", variant, tag):
+        raise LibmHipError("sincos: %s %s is not served" % (variant, tag))
+    s, c = (torch.empty_like(x), torch.empty_like(x)) if outs is None else outs
+    name = "libm_hip_sincos_%s_%s" % (variant, tag)
+    lib = load()
+    _check(getattr(lib, name)(x.data_ptr(), s.data_ptr(), c.data_ptr(), x.numel(),
+                              _stream_handle()), name)
+    return s, c
 
 
 def pow(x, y, out=None, via_f64=False):

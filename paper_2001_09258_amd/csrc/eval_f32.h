@@ -284,6 +284,36 @@ LMH_INLINE float cosf_finish_u35(float x, Trig32 s) {
   return trigf_tiny(x) ? 1.0f : v;
 }
 
+// sincos in binary32: as the binary64 form
+struct SinCos32 {
+  Trig32 s, c;
+};
+LMH_INLINE SinCos32 sincosf2_fast(float x) {
+  return SinCos32{sincosf_fast(x, false), sincosf_fast(x, true)};
+}
+LMH_INLINE Trig32 sincosf_raw(float x) {
+  float k;
+  fff r = phf_reduce_signed(x, k);
+  return Trig32{r, k};
+}
+LMH_INLINE SinCos32 sincosf_lift(float x, Trig32 raw) {
+  float js, jc;
+  fff rs = quadrant_to_half_periodf(raw.r, raw.j, js);
+  fff rc = quadrant_to_half_periodf(raw.r, raw.j + 1.0f, jc);
+  bool fin = isfinite_(x);
+  rs.hi = fin ? rs.hi : __builtin_nanf("");
+  rc.hi = fin ? rc.hi : __builtin_nanf("");
+  return SinCos32{Trig32{rs, js}, Trig32{rc, jc}};
+}
+LMH_INLINE SinCos32 sincosf2_reduce(float x) {
+  SinCos32 s;
+  if (trigf_slow(x))
+    s = sincosf_lift(x, sincosf_raw(x));
+  else
+    s = sincosf2_fast(x);
+  return s;
+}
+
 LMH_INLINE float sinf_u10(float x) { return sinf_finish_u10(x, sincosf_reduce(x, false)); }
 LMH_INLINE float cosf_u10(float x) { return cosf_finish_u10(x, sincosf_reduce(x, true)); }
 LMH_INLINE float sinf_u35(float x) { return sinf_finish_u35(x, sincosf_reduce(x, false)); }

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(MAX_BLOCK) void k_binary(const typename Io::S* __re
   }
 }
 
-// Trigonometric kernel with the Payne-Hanek lanes gathered.  Every lane runs
+// Trigonometric kernels with the Payne-Hanek lanes gathered.  Every lane runs
 // the Cody-Waite reduction on its elements; the Payne-Hanek ones are also
 // written to a workgroup queue in LDS and reduced densely by all lanes after
 // a barrier, so a wave that holds a few large arguments no longer pays the
@@ -81,22 +81,60 @@ __global__ __launch_bounds__(MAX_BLOCK) void k_binary(const typename Io::S* __re
 // fills its front with ballot + mbcnt (no atomics); the dense pass maps its
 // index onto the filled fronts from the per-wave counts.  The reduced states
 // come back through LDS and every lane finishes its own elements.
-template <class Io, class Op, int EPT, bool VEC>
-__global__ __launch_bounds__(BLOCK) void k_unary_split(const typename Io::S* __restrict__ x,
-                                                       typename Io::S* __restrict__ y, size_t n) {
+constexpr int SPLIT_WAVES = BLOCK / 64;
+
+// Append this lane's slow elements to its wave's region (all lanes of the
+// workgroup must call it); the wave's count goes to q_cnt[wave].
+template <int EPT, class C>
+__device__ __forceinline__ void queue_slow(const C (&xv)[EPT], const bool (&slow)[EPT], C* q_x,
+                                           unsigned short* q_slot, unsigned* q_cnt) {
+  const unsigned lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  unsigned filled = 0;                               // wave-uniform
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    unsigned long long m = __builtin_amdgcn_ballot_w64(slow[i]);
+    unsigned pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                             __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+    if (slow[i]) {
+      unsigned pos = wave * (64u * EPT) + filled + pre;
+      q_x[pos] = xv[i];
+      q_slot[pos] = (unsigned short)(threadIdx.x * EPT + i);
+    }
+    filled += (unsigned)__popcll(m);
+  }
+  if (lane == 0) q_cnt[wave] = filled;
+}
+
+// After a barrier: every queued element reduced once, by the workgroup's
+// lanes in dense order, its state stored at its slot.
+template <int EPT, class C, class R, class F>
+__device__ __forceinline__ void reduce_queue(const C* q_x, const unsigned short* q_slot,
+                                             const unsigned* q_cnt, R* q_res, F reduce) {
+  unsigned cnt[SPLIT_WAVES], first[SPLIT_WAVES];
+  unsigned total = 0;
+#pragma unroll
+  for (int w = 0; w < SPLIT_WAVES; ++w) {
+    cnt[w] = q_cnt[w];
+    first[w] = total;
+    total += cnt[w];
+  }
+  for (unsigned p = threadIdx.x; p < total; p += BLOCK) {
+    // dense index p -> slot in its wave's region, skipping the unfilled
+    // tails of the regions before it
+    unsigned pos = p;
+#pragma unroll
+    for (int w = 1; w < SPLIT_WAVES; ++w) pos += p >= first[w] ? 64u * EPT - cnt[w - 1] : 0u;
+    q_res[q_slot[pos]] = reduce(q_x[pos]);
+  }
+}
+
+// EPT elements of this lane: a 16-byte pack or masked scalar loads
+template <class Io, int EPT, bool VEC>
+__device__ __forceinline__ void load_lane(const typename Io::S* __restrict__ x, size_t n,
+                                          size_t base, typename Io::C (&xv)[EPT],
+                                          bool (&ok)[EPT]) {
   typedef typename Io::S S;
   typedef typename Io::C C;
-  typedef decltype(Op::fast(C())) St;
-  constexpr int WAVES = BLOCK / 64;
-  constexpr unsigned REGION = 64 * EPT;
-  __shared__ C q_x[BLOCK * EPT];
-  __shared__ unsigned short q_slot[BLOCK * EPT];
-  __shared__ St q_res[BLOCK * EPT];
-  __shared__ unsigned q_cnt[WAVES];
-  const unsigned lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-  size_t base = ((size_t)blockIdx.x * BLOCK + threadIdx.x) * EPT;
-  C xv[EPT];
-  bool ok[EPT];
   if (VEC && base + EPT <= n) {
     Pack<S, EPT> in = *reinterpret_cast<const Pack<S, EPT>*>(x + base);
 #pragma unroll
@@ -111,6 +149,22 @@ __global__ __launch_bounds__(BLOCK) void k_unary_split(const typename Io::S* __r
       xv[i] = ok[i] ? Io::in(x[base + i]) : C(0);
     }
   }
+}
+
+template <class Io, class Op, int EPT, bool VEC>
+__global__ __launch_bounds__(BLOCK) void k_unary_split(const typename Io::S* __restrict__ x,
+                                                       typename Io::S* __restrict__ y, size_t n) {
+  typedef typename Io::S S;
+  typedef typename Io::C C;
+  typedef decltype(Op::fast(C())) St;
+  __shared__ C q_x[BLOCK * EPT];
+  __shared__ unsigned short q_slot[BLOCK * EPT];
+  __shared__ St q_res[BLOCK * EPT];
+  __shared__ unsigned q_cnt[SPLIT_WAVES];
+  size_t base = ((size_t)blockIdx.x * BLOCK + threadIdx.x) * EPT;
+  C xv[EPT];
+  bool ok[EPT];
+  load_lane<Io, EPT, VEC>(x, n, base, xv, ok);
   St st[EPT];
   bool slow[EPT];
   // Cody-Waite for every element, without a branch: nearly every wave holds
@@ -122,37 +176,9 @@ __global__ __launch_bounds__(BLOCK) void k_unary_split(const typename Io::S* __r
     slow[i] = ok[i] && Op::is_slow(xv[i]);
     st[i] = Op::fast(xv[i]);
   }
-  unsigned filled = 0;                               // wave-uniform
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    unsigned long long m = __builtin_amdgcn_ballot_w64(slow[i]);
-    unsigned pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                             __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-    if (slow[i]) {
-      unsigned pos = wave * REGION + filled + pre;
-      q_x[pos] = xv[i];
-      q_slot[pos] = (unsigned short)(threadIdx.x * EPT + i);
-    }
-    filled += (unsigned)__popcll(m);
-  }
-  if (lane == 0) q_cnt[wave] = filled;
+  queue_slow<EPT>(xv, slow, q_x, q_slot, q_cnt);
   __syncthreads();
-  unsigned cnt[WAVES], first[WAVES];
-  unsigned total = 0;
-#pragma unroll
-  for (int w = 0; w < WAVES; ++w) {
-    cnt[w] = q_cnt[w];
-    first[w] = total;
-    total += cnt[w];
-  }
-  for (unsigned p = threadIdx.x; p < total; p += BLOCK) {
-    // dense index p -> slot in its wave's region, skipping the unfilled
-    // tails of the regions before it
-    unsigned pos = p;
-#pragma unroll
-    for (int w = 1; w < WAVES; ++w) pos += p >= first[w] ? REGION - cnt[w - 1] : 0u;
-    q_res[q_slot[pos]] = Op::slow(q_x[pos]);
-  }
+  reduce_queue<EPT>(q_x, q_slot, q_cnt, q_res, [](C v) { return Op::slow(v); });
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < EPT; ++i)
@@ -166,6 +192,60 @@ __global__ __launch_bounds__(BLOCK) void k_unary_split(const typename Io::S* __r
 #pragma unroll
     for (int i = 0; i < EPT; ++i)
       if (ok[i]) y[base + i] = Io::out(Op::finish(xv[i], st[i]));
+  }
+}
+
+// sin and cos of each element in one pass: the Payne-Hanek elements are
+// reduced once in the queue (the raw pair and quadrant, the smallest state)
+// and mapped to both half-period states afterwards.
+template <class Io, class Op, int EPT, bool VEC>
+__global__ __launch_bounds__(BLOCK) void k_sincos_split(const typename Io::S* __restrict__ x,
+                                                        typename Io::S* __restrict__ ys,
+                                                        typename Io::S* __restrict__ yc,
+                                                        size_t n) {
+  typedef typename Io::S S;
+  typedef typename Io::C C;
+  typedef decltype(Op::fast(C())) St;
+  typedef decltype(Op::slow(C())) Raw;
+  __shared__ C q_x[BLOCK * EPT];
+  __shared__ unsigned short q_slot[BLOCK * EPT];
+  __shared__ Raw q_res[BLOCK * EPT];
+  __shared__ unsigned q_cnt[SPLIT_WAVES];
+  size_t base = ((size_t)blockIdx.x * BLOCK + threadIdx.x) * EPT;
+  C xv[EPT];
+  bool ok[EPT];
+  load_lane<Io, EPT, VEC>(x, n, base, xv, ok);
+  St st[EPT];
+  bool slow[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    slow[i] = ok[i] && Op::is_slow(xv[i]);
+    st[i] = Op::fast(xv[i]);
+  }
+  queue_slow<EPT>(xv, slow, q_x, q_slot, q_cnt);
+  __syncthreads();
+  reduce_queue<EPT>(q_x, q_slot, q_cnt, q_res, [](C v) { return Op::slow(v); });
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < EPT; ++i)
+    if (slow[i]) st[i] = Op::lift(xv[i], q_res[threadIdx.x * EPT + i]);
+  if (VEC && base + EPT <= n) {
+    Pack<S, EPT> os, oc;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      os.v[i] = Io::out(Op::finish_sin(xv[i], st[i]));
+      oc.v[i] = Io::out(Op::finish_cos(xv[i], st[i]));
+    }
+    store_nt(os, ys + base);
+    store_nt(oc, yc + base);
+  } else {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      if (ok[i]) {
+        ys[base + i] = Io::out(Op::finish_sin(xv[i], st[i]));
+        yc[base + i] = Io::out(Op::finish_cos(xv[i], st[i]));
+      }
+    }
   }
 }
 

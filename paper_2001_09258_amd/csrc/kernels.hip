@@ -137,6 +137,30 @@ libm_hip_status launch_unary(const void* x, void* y, size_t n, void* stream, con
 }
 
 template <class Io, class Op>
+libm_hip_status launch_sincos(const void* x, void* ys, void* yc, size_t n, void* stream,
+                              const char* name) {
+  if (n == 0) return LIBM_HIP_OK;
+  if (!x || !ys || !yc) {
+    set_error("libm_hip: NULL pointer with n > 0");
+    return LIBM_HIP_ERR_INVALID;
+  }
+  typedef typename Io::S S;
+  constexpr int EPT = ept_for<S>();
+  hipStream_t s = (hipStream_t)stream;
+  bool vec = aligned16(x) && aligned16(ys) && aligned16(yc);
+  unsigned blocks;
+  if (!grid_for(n, EPT, Cfg{BLOCK, 1}, blocks)) return LIBM_HIP_ERR_INVALID;
+  const S* xs = (const S*)x;
+  if (vec)
+    hipLaunchKernelGGL((k_sincos_split<Io, Op, EPT, true>), dim3(blocks), dim3(BLOCK), 0, s, xs,
+                       (S*)ys, (S*)yc, n);
+  else
+    hipLaunchKernelGGL((k_sincos_split<Io, Op, EPT, false>), dim3(blocks), dim3(BLOCK), 0, s, xs,
+                       (S*)ys, (S*)yc, n);
+  return launch_error(name);
+}
+
+template <class Io, class Op>
 libm_hip_status launch_binary(const void* a, const void* b, void* y, size_t n, void* stream,
                               const char* name, int key) {
   if (n == 0) return LIBM_HIP_OK;
@@ -273,6 +297,18 @@ LMH_DEF_UNARY_HALF(log1p, OpLog1pU10, LOG1P)
 LMH_DEF_UNARY_HALF(exp10, OpExp10U10, EXP10)
 LMH_DEF_UNARY_HALF(expm1, OpExpm1U10, EXPM1)
 LMH_DEF_UNARY_HALF(cbrt, OpCbrtU10, CBRT)
+
+#define LMH_DEF_SINCOS(var, Io, T, tag, Op)                                                        \
+  libm_hip_status libm_hip_sincos_##var##_##tag(const T* x, T* s, T* c, size_t n, void* stream) {  \
+    return launch_sincos<Io, Op>(x, s, c, n, stream, "sincos_" #var "_" #tag);                      \
+  }
+LMH_DEF_SINCOS(u10, IoF64, double, f64, OpSinCosU10)
+LMH_DEF_SINCOS(u10, IoF32, float, f32, OpSinCosU10)
+LMH_DEF_SINCOS(u10, IoBF16, uint16_t, bf16, OpSinCosU10)
+LMH_DEF_SINCOS(u10, IoF16, uint16_t, f16, OpSinCosU10)
+LMH_DEF_SINCOS(u10, IoF32ViaF64, float, f32_via_f64, OpSinCosU10)
+LMH_DEF_SINCOS(u35, IoF64, double, f64, OpSinCosU35)
+LMH_DEF_SINCOS(u35, IoF32, float, f32, OpSinCosU35)
 
 #define LMH_DEF_BINARY(fn, var, Io, T, tag, Op, KEY)                                              \
   libm_hip_status libm_hip_##fn##var##_##tag(const T* a, const T* b, T* out, size_t n, void* s) { \

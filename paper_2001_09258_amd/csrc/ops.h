@@ -93,6 +93,49 @@ struct IoF16 {
     static __device__ __forceinline__ double finish(double x, lmh::Trig64 s) { return lmh::FIN64(x, s); } \
     static __device__ __forceinline__ float finish(float x, lmh::Trig32 s) { return lmh::FIN32(x, s); }   \
   };
+// sincos: fast(x) -> both reduction states, slow(x) -> the raw Payne-Hanek
+// pair and quadrant, lift(x, raw) -> both states, finish_sin / finish_cos
+#define LMH_SINCOS_OP(NAME, SFIN64, CFIN64, SFIN32, CFIN32)                                      \
+  struct NAME {                                                                                 \
+    static __device__ __forceinline__ bool is_slow(double x) { return lmh::trig_slow(x); }      \
+    static __device__ __forceinline__ bool is_slow(float x) { return lmh::trigf_slow(x); }      \
+    static __device__ __forceinline__ lmh::SinCos64 fast(double x) { return lmh::sincos2_fast(x); } \
+    static __device__ __forceinline__ lmh::SinCos32 fast(float x) { return lmh::sincosf2_fast(x); } \
+    static __device__ __forceinline__ lmh::Trig64 slow(double x) { return lmh::sincos_raw(x); }  \
+    static __device__ __forceinline__ lmh::Trig32 slow(float x) { return lmh::sincosf_raw(x); }  \
+    static __device__ __forceinline__ lmh::SinCos64 lift(double x, lmh::Trig64 r) {             \
+      return lmh::sincos_lift(x, r);                                                            \
+    }                                                                                           \
+    static __device__ __forceinline__ lmh::SinCos32 lift(float x, lmh::Trig32 r) {              \
+      return lmh::sincosf_lift(x, r);                                                           \
+    }                                                                                           \
+    static __device__ __forceinline__ double finish_sin(double x, lmh::SinCos64 s) {            \
+      return lmh::SFIN64(x, s.s);                                                               \
+    }                                                                                           \
+    static __device__ __forceinline__ double finish_cos(double x, lmh::SinCos64 s) {            \
+      return lmh::CFIN64(x, s.c);                                                               \
+    }                                                                                           \
+    static __device__ __forceinline__ float finish_sin(float x, lmh::SinCos32 s) {              \
+      return lmh::SFIN32(x, s.s);                                                               \
+    }                                                                                           \
+    static __device__ __forceinline__ float finish_cos(float x, lmh::SinCos32 s) {              \
+      return lmh::CFIN32(x, s.c);                                                               \
+    }                                                                                           \
+    /* one-call form (device API): both under the execution mask */                             \
+    static __device__ __forceinline__ void f(double x, double& s, double& c) {                  \
+      lmh::SinCos64 st = lmh::sincos2_reduce(x);                                                \
+      s = lmh::SFIN64(x, st.s);                                                                 \
+      c = lmh::CFIN64(x, st.c);                                                                 \
+    }                                                                                           \
+    static __device__ __forceinline__ void f(float x, float& s, float& c) {                     \
+      lmh::SinCos32 st = lmh::sincosf2_reduce(x);                                               \
+      s = lmh::SFIN32(x, st.s);                                                                 \
+      c = lmh::CFIN32(x, st.c);                                                                 \
+    }                                                                                           \
+  };
+LMH_SINCOS_OP(OpSinCosU10, sin_finish_u10, cos_finish_u10, sinf_finish_u10, cosf_finish_u10)
+LMH_SINCOS_OP(OpSinCosU35, sin_finish_u35, cos_finish_u35, sinf_finish_u35, cosf_finish_u35)
+
 #define LMH_NOARG
 #define LMH_COMMA ,
 LMH_TRIG_OP(OpSinU10, sin_u10, sinf_u10, sincos, sincosf, LMH_COMMA false, sin_finish_u10, sinf_finish_u10, x)

@@ -130,3 +130,37 @@ extern "C" int device_api_masked_sin(const double* a, double* y, size_t n, void*
   hipLaunchKernelGGL((km<double, decltype(f)>), dim3(g), dim3(256), 0, (hipStream_t)s, a, y, n, f);
   return hipGetLastError() == hipSuccess ? 0 : 3;
 }
+
+// sincos through the device API: s and c outputs
+template <class S, class F>
+__global__ void ksc(const S* a, S* ys, S* yc, size_t n, F f) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) f(a[i], &ys[i], &yc[i]);
+}
+template <class S, class F>
+int launch_sc(const void* a, void* ys, void* yc, size_t n, void* s, F f) {
+  unsigned g = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL((ksc<S, F>), dim3(g), dim3(256), 0, (hipStream_t)s, (const S*)a, (S*)ys,
+                     (S*)yc, n, f);
+  return hipGetLastError() == hipSuccess ? 0 : 3;
+}
+
+extern "C" int device_api_sincos(int variant, int dtype, const void* a, void* ys, void* yc,
+                                 size_t n, void* s) {
+  if (n == 0) return 0;
+  if (variant == 1) {
+    switch (dtype) {
+      case 0: return launch_sc<double>(a, ys, yc, n, s, [] __device__(double x, double* p, double* q) { D::sincos_u35(x, p, q); });
+      case 1: return launch_sc<float>(a, ys, yc, n, s, [] __device__(float x, float* p, float* q) { D::sincos_u35(x, p, q); });
+    }
+    return 2;
+  }
+  switch (dtype) {
+    case 0: return launch_sc<double>(a, ys, yc, n, s, [] __device__(double x, double* p, double* q) { D::sincos_u10(x, p, q); });
+    case 1: return launch_sc<float>(a, ys, yc, n, s, [] __device__(float x, float* p, float* q) { D::sincos_u10(x, p, q); });
+    case 2: return launch_sc<uint16_t>(a, ys, yc, n, s, [] __device__(uint16_t x, uint16_t* p, uint16_t* q) { D::sincos_u10_bf16(x, p, q); });
+    case 3: return launch_sc<uint16_t>(a, ys, yc, n, s, [] __device__(uint16_t x, uint16_t* p, uint16_t* q) { D::sincos_u10_f16(x, p, q); });
+    case 4: return launch_sc<float>(a, ys, yc, n, s, [] __device__(float x, float* p, float* q) { D::sincos_u10_via_f64(x, p, q); });
+  }
+  return 2;
+}
