@@ -32,7 +32,11 @@
  * Element types: f64 = double, f32 = float, bf16 and f16 = uint16_t bit
  * patterns of bfloat16 / IEEE binary16 (evaluated in binary32 and rounded to
  * nearest-even once).  "f32_via_f64" variants take and return float but
- * evaluate the binary64 u10 function and round once.
+ * evaluate in binary64 and round once.  These forms run the wider type's
+ * 3.5-ULP evaluator where the function has one (sin, cos, tan, sincos, log,
+ * asin, acos, atan, atan2, sinh, cosh, tanh), else its 1.0-ULP one: the
+ * wider type carries at least 13 more bits, so the result is within
+ * 0.5 + 3.5 * 2^-13 ULP of the exact value in the narrow format.
  */
 #ifndef LIBM_HIP_H
 #define LIBM_HIP_H
@@ -77,8 +81,12 @@ const char* libm_hip_version(void);
  * with 1 + x kept as an exact pair), exp10 and expm1 through the exp
  * reduction (expm1 with e^r - 1 as a pair and 2^k - 1 as an exact pair),
  * cbrt by Newton steps on x^(-1/3) from the hardware log2/exp2 estimates and
- * one double-double residual correction.  All 1.0 ULP; the same Annex F
- * special values as C99 (exp10 as exp: 10^+-0 = 1, 10^-inf = +0).
+ * one double-double residual correction.  asinh, acosh and atanh (C99, not
+ * described in the paper either) as log1p of an argument formed without
+ * cancellation: |x| + x^2/(1 + sqrt(1 + x^2)), (x - 1) + sqrt((x - 1)(x + 1))
+ * and 2|x|/(1 - |x|) (halved), in double-double (binary32: in binary64
+ * working precision).  All 1.0 ULP; the same Annex F special values as C99
+ * (exp10 as exp: 10^+-0 = 1, 10^-inf = +0).
  * ---------------------------------------------------------------------- */
 #define LIBM_HIP_DECL_UNARY(fn, var)                                                       \
   libm_hip_status libm_hip_##fn##_##var##_f64(const double* x, double* y, size_t n,        \
@@ -139,6 +147,12 @@ LIBM_HIP_DECL_UNARY_HALF(log1p)
 LIBM_HIP_DECL_UNARY_HALF(exp10)
 LIBM_HIP_DECL_UNARY_HALF(expm1)
 LIBM_HIP_DECL_UNARY_HALF(cbrt)
+LIBM_HIP_DECL_UNARY(asinh, u10)
+LIBM_HIP_DECL_UNARY(acosh, u10)
+LIBM_HIP_DECL_UNARY(atanh, u10)
+LIBM_HIP_DECL_UNARY_HALF(asinh)
+LIBM_HIP_DECL_UNARY_HALF(acosh)
+LIBM_HIP_DECL_UNARY_HALF(atanh)
 
 /* ------------------------------------------------------------------------
  * sincos: s[i] = sin(x[i]) and c[i] = cos(x[i]) in one pass (the paper's
@@ -243,7 +257,7 @@ typedef enum {
   LIBM_HIP_COSH, LIBM_HIP_TANH, LIBM_HIP_FMOD, LIBM_HIP_REMAINDER,
   LIBM_HIP_ASIN, LIBM_HIP_ACOS, LIBM_HIP_ATAN,
   LIBM_HIP_LOG10, LIBM_HIP_LOG1P, LIBM_HIP_EXP10, LIBM_HIP_EXPM1, LIBM_HIP_CBRT,
-  LIBM_HIP_HYPOT,
+  LIBM_HIP_HYPOT, LIBM_HIP_ASINH, LIBM_HIP_ACOSH, LIBM_HIP_ATANH,
   LIBM_HIP_NUM_FN
 } libm_hip_fn;
 typedef enum { LIBM_HIP_U10 = 0, LIBM_HIP_U35 = 1, LIBM_HIP_EXACT = 2 } libm_hip_variant;

@@ -25,7 +25,10 @@
  * Every function is a pure function of its arguments: no memory, no state,
  * no errno or flags; special values follow C99 Annex F as the entry points
  * do.  Accuracy: *_u10 within 1.0 ULP, *_u35 within 3.5 ULP, fmod and
- * remainder exact; bf16/f16 forms evaluate in binary32 and round once.
+ * remainder exact; bf16/f16 forms evaluate in binary32 and _via_f64 forms in
+ * binary64 (with the 3.5-ULP evaluator where one exists, which the extra
+ * bits of the wider type keep within 0.5 + 3.5 * 2^-13 ULP of the narrow
+ * result) and round once.
  * The *_bwd functions return the vector-Jacobian product g * f'(x) (two
  * partials for pow and atan2) as the backward entry points do.
  */
@@ -38,17 +41,19 @@
 
 namespace libm_hip_device {
 
+#define LIBM_HIP_DEVICE_EVAL(IO, OP) lmh_ops::EvalOp<lmh_ops::IO, lmh_ops::OP>::type
 #define LIBM_HIP_DEVICE_UNARY(NAME, OP)                                                   \
   __device__ __forceinline__ double NAME(double x) { return lmh_ops::OP::f(x); }            \
   __device__ __forceinline__ float NAME(float x) { return lmh_ops::OP::f(x); }              \
   __device__ __forceinline__ float NAME##_via_f64(float x) {                                \
-    return lmh_ops::IoF32ViaF64::out(lmh_ops::OP::f(lmh_ops::IoF32ViaF64::in(x)));          \
+    return lmh_ops::IoF32ViaF64::out(                                                       \
+        LIBM_HIP_DEVICE_EVAL(IoF32ViaF64, OP)::f(lmh_ops::IoF32ViaF64::in(x)));              \
   }                                                                                       \
   __device__ __forceinline__ uint16_t NAME##_bf16(uint16_t x) {                             \
-    return lmh_ops::IoBF16::out(lmh_ops::OP::f(lmh_ops::IoBF16::in(x)));                    \
+    return lmh_ops::IoBF16::out(LIBM_HIP_DEVICE_EVAL(IoBF16, OP)::f(lmh_ops::IoBF16::in(x))); \
   }                                                                                       \
   __device__ __forceinline__ uint16_t NAME##_f16(uint16_t x) {                              \
-    return lmh_ops::IoF16::out(lmh_ops::OP::f(lmh_ops::IoF16::in(x)));                      \
+    return lmh_ops::IoF16::out(LIBM_HIP_DEVICE_EVAL(IoF16, OP)::f(lmh_ops::IoF16::in(x)));    \
   }
 
 #define LIBM_HIP_DEVICE_UNARY_WIDE(NAME, OP)                                              \
@@ -63,14 +68,16 @@ namespace libm_hip_device {
   __device__ __forceinline__ double NAME(double a, double b) { return lmh_ops::OP::f(a, b); } \
   __device__ __forceinline__ float NAME(float a, float b) { return lmh_ops::OP::f(a, b); }    \
   __device__ __forceinline__ float NAME##_via_f64(float a, float b) {                       \
-    return lmh_ops::IoF32ViaF64::out(                                                       \
-        lmh_ops::OP::f(lmh_ops::IoF32ViaF64::in(a), lmh_ops::IoF32ViaF64::in(b)));           \
+    return lmh_ops::IoF32ViaF64::out(LIBM_HIP_DEVICE_EVAL(IoF32ViaF64, OP)::f(               \
+        lmh_ops::IoF32ViaF64::in(a), lmh_ops::IoF32ViaF64::in(b)));                          \
   }                                                                                       \
   __device__ __forceinline__ uint16_t NAME##_bf16(uint16_t a, uint16_t b) {                 \
-    return lmh_ops::IoBF16::out(lmh_ops::OP::f(lmh_ops::IoBF16::in(a), lmh_ops::IoBF16::in(b))); \
+    return lmh_ops::IoBF16::out(                                                            \
+        LIBM_HIP_DEVICE_EVAL(IoBF16, OP)::f(lmh_ops::IoBF16::in(a), lmh_ops::IoBF16::in(b))); \
   }                                                                                       \
   __device__ __forceinline__ uint16_t NAME##_f16(uint16_t a, uint16_t b) {                  \
-    return lmh_ops::IoF16::out(lmh_ops::OP::f(lmh_ops::IoF16::in(a), lmh_ops::IoF16::in(b)));   \
+    return lmh_ops::IoF16::out(                                                             \
+        LIBM_HIP_DEVICE_EVAL(IoF16, OP)::f(lmh_ops::IoF16::in(a), lmh_ops::IoF16::in(b)));    \
   }
 
 /* sin, cos, tan (Section 5, sin/cos and tan), exp, log (Section 5, exp and
@@ -95,6 +102,9 @@ LIBM_HIP_DEVICE_UNARY(log1p_u10, OpLog1pU10)
 LIBM_HIP_DEVICE_UNARY(exp10_u10, OpExp10U10)
 LIBM_HIP_DEVICE_UNARY(expm1_u10, OpExpm1U10)
 LIBM_HIP_DEVICE_UNARY(cbrt_u10, OpCbrtU10)
+LIBM_HIP_DEVICE_UNARY(asinh_u10, OpAsinhU10)
+LIBM_HIP_DEVICE_UNARY(acosh_u10, OpAcoshU10)
+LIBM_HIP_DEVICE_UNARY(atanh_u10, OpAtanhU10)
 /* 3.5-ULP forms (binary64 and binary32) */
 LIBM_HIP_DEVICE_UNARY_WIDE(sin_u35, OpSinU35)
 LIBM_HIP_DEVICE_UNARY_WIDE(cos_u35, OpCosU35)
@@ -128,19 +138,19 @@ __device__ __forceinline__ void sincos_u35(float x, float* s, float* c) {
 }
 __device__ __forceinline__ void sincos_u10_via_f64(float x, float* s, float* c) {
   double sd, cd;
-  lmh_ops::OpSinCosU10::f(lmh_ops::IoF32ViaF64::in(x), sd, cd);
+  LIBM_HIP_DEVICE_EVAL(IoF32ViaF64, OpSinCosU10)::f(lmh_ops::IoF32ViaF64::in(x), sd, cd);
   *s = lmh_ops::IoF32ViaF64::out(sd);
   *c = lmh_ops::IoF32ViaF64::out(cd);
 }
 __device__ __forceinline__ void sincos_u10_bf16(uint16_t x, uint16_t* s, uint16_t* c) {
   float sf, cf;
-  lmh_ops::OpSinCosU10::f(lmh_ops::IoBF16::in(x), sf, cf);
+  LIBM_HIP_DEVICE_EVAL(IoBF16, OpSinCosU10)::f(lmh_ops::IoBF16::in(x), sf, cf);
   *s = lmh_ops::IoBF16::out(sf);
   *c = lmh_ops::IoBF16::out(cf);
 }
 __device__ __forceinline__ void sincos_u10_f16(uint16_t x, uint16_t* s, uint16_t* c) {
   float sf, cf;
-  lmh_ops::OpSinCosU10::f(lmh_ops::IoF16::in(x), sf, cf);
+  LIBM_HIP_DEVICE_EVAL(IoF16, OpSinCosU10)::f(lmh_ops::IoF16::in(x), sf, cf);
   *s = lmh_ops::IoF16::out(sf);
   *c = lmh_ops::IoF16::out(cf);
 }
@@ -190,6 +200,7 @@ __device__ __forceinline__ T masked(bool active, T x, F f) {
 }
 
 #undef LIBM_HIP_DEVICE_UNARY
+#undef LIBM_HIP_DEVICE_EVAL
 #undef LIBM_HIP_DEVICE_UNARY_WIDE
 #undef LIBM_HIP_DEVICE_BINARY
 #undef LIBM_HIP_DEVICE_BINARY_WIDE

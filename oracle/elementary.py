@@ -6,7 +6,9 @@ These are textbook definitions chosen to be easy to check by eye and
 deliberately different from the methods the GPU kernels use:
 
 * exp:   x = k ln2 + r, exp(r / 2^s) by Taylor series, squared s times.
-* log:   x = m 2^E with m in [sqrt(1/2), sqrt 2), log m = 2 atanh((m-1)/(m+1)).
+* log:   x = m 2^E with m in [sqrt(1/2), sqrt 2), log m = 2 atanh((m-1)/(m+1));
+         the same series for balls (log_of_ball) and for log(1 + u) with small
+         u (log1p_ball, through u / (2 + u)).
 * sin/cos: the exact argument times 2/pi (as many bits as its exponent needs),
          nearest integer k and fraction f, r = f pi/2, Taylor series for
          sin r and cos r, quadrant from k mod 4.
@@ -20,8 +22,8 @@ from . import ball as B
 from .ball import Ball, exact, add, sub, mul, div, approx, mag_log2
 from .consts import pi, ln2, two_over_pi, half_pi
 
-__all__ = ["exp_ball", "log_ball", "sincos_reduced", "sin_cos_ball",
-           "atan_ball", "sinh_cosh_small", "tail_ball"]
+__all__ = ["exp_ball", "log_ball", "log_of_ball", "log1p_ball", "sincos_reduced",
+           "sin_cos_ball", "atan_ball", "sinh_cosh_small", "tail_ball"]
 
 
 def tail_ball(b, bound_log2):
@@ -96,6 +98,51 @@ def log_ball(m, e, prec):
         wpe = wp + abs(E).bit_length()
         res = add(res, mul(exact(E), ln2(wpe + 8), wpe), wp)
     return res
+
+
+def _atanh_series2(t, wp):
+    """2 atanh(t) = 2 (t + t^3/3 + t^5/5 + ...) for a ball |t| <= 1/3."""
+    if t.m == 0 and t.r == 0:
+        return exact(0)
+    t2 = mul(t, t, wp)
+    term = t
+    s = t
+    k = 1
+    while True:
+        term = mul(term, t2, wp)
+        s = add(s, div(term, exact(2 * k + 1), wp), wp)
+        if mag_log2(term) < mag_log2(t) - wp - 8:
+            s = tail_ball(s, mag_log2(term) - 3)
+            break
+        k += 1
+    return B.scale2(s, 1)
+
+
+def log_of_ball(y, prec):
+    """log y for a ball y > 0: y = y' 2^E with the midpoint's exponent, so
+    y' is near [1/2, 2); log y' = 2 atanh((y' - 1)/(y' + 1))."""
+    lo, hi, e = y.lo_hi()
+    if lo <= 0:
+        raise B.PrecisionError("log of a ball that reaches zero")
+    E = e + y.m.bit_length() - 1
+    yp = B.scale2(y, -E)                   # midpoint in [1, 2)
+    wp = prec + 16
+    one = exact(1)
+    res = _atanh_series2(div(sub(yp, one, wp), add(yp, one, wp), wp), wp)
+    if E != 0:
+        wpe = wp + abs(E).bit_length()
+        res = add(res, mul(exact(E), ln2(wpe + 8), wpe), wp)
+    return res
+
+
+def log1p_ball(u, prec):
+    """log(1 + u) for a ball u >= 0: 2 atanh(u / (2 + u)) while u < 1 (the
+    quotient is below 1/3, and small u keeps its relative accuracy), else
+    log(1 + u)."""
+    wp = prec + 16
+    if approx(u) < 1.0:
+        return _atanh_series2(div(u, add(exact(2), u, wp), wp), wp)
+    return log_of_ball(add(exact(1), u, wp), prec)
 
 
 def sincos_reduced(m, e, prec):

@@ -14,8 +14,9 @@ loop only stops when the exact value is not itself a rounding boundary
 detected and computed exactly (exp2 and log2 at powers of two, pow when x^y is
 a dyadic rational, log10 at powers of ten, exp10 at nonnegative integers,
 cbrt at cubes and hypot when x^2 + y^2 is a square).  exp, sin, cos, tan,
-log (x != 1), atan (x != 0), expm1 and log1p (x != 0) and the hyperbolic
-functions of a nonzero dyadic are transcendental, hence never a boundary.
+log (x != 1), atan (x != 0), expm1 and log1p (x != 0), the hyperbolic
+functions and their inverses (asinh, atanh at x != 0, acosh at x != 1) of a
+nonzero dyadic are transcendental, hence never a boundary.
 
 Special inputs (zeros, infinities, NaN) follow C99 Annex F (F.9), which the
 paper adopts: "same results as libm, as specified in the ANSI C standard"
@@ -34,7 +35,7 @@ import math
 from . import ball as B
 from .ball import Ball, exact, from_float, add, sub, mul, div, PrecisionError
 from .consts import pi, ln2
-from .elementary import (exp_ball, log_ball, sincos_reduced, sin_cos_ball,
+from .elementary import (exp_ball, log_ball, log1p_ball, sincos_reduced, sin_cos_ball,
                          atan_ball, sinh_cosh_small)
 from .rounding import FORMATS, rn_dyadic, rn_ball
 
@@ -46,7 +47,7 @@ PREC_CAP = 16384
 
 UNARY = ("sin", "cos", "tan", "exp", "exp2", "log", "log2",
          "sinh", "cosh", "tanh", "asin", "acos", "atan",
-         "log10", "exp10", "expm1", "log1p", "cbrt")
+         "log10", "exp10", "expm1", "log1p", "cbrt", "asinh", "acosh", "atanh")
 BINARY = ("pow", "atan2", "fmod", "remainder", "hypot")
 
 
@@ -157,6 +158,23 @@ def _special_unary(fn, x):
     elif fn == "cbrt":
         if x == 0.0 or math.isinf(x):
             return x
+    elif fn == "asinh":
+        if x == 0.0 or math.isinf(x):
+            return x
+    elif fn == "acosh":
+        if x < 1.0:                      # including -inf
+            return NAN
+        if x == 1.0:
+            return 0.0
+        if math.isinf(x):
+            return INF
+    elif fn == "atanh":
+        if abs(x) > 1.0:                 # including +-inf
+            return NAN
+        if x == 0.0:
+            return x
+        if abs(x) == 1.0:
+            return math.copysign(INF, x)
     return None
 
 
@@ -449,6 +467,37 @@ def _ball_cbrt(x, prec):
     return r if x > 0 else B.neg(r)
 
 
+def _ball_asinh(x, prec):
+    """asinh|x| = log1p(u), u = |x| + x^2 / (1 + sqrt(1 + x^2)) (no
+    cancellation); odd."""
+    wp = prec + 24
+    X = from_float(abs(x))
+    x2 = mul(X, X, wp)
+    one = exact(1)
+    u = add(X, div(x2, add(one, B.sqrt(add(one, x2, wp), wp), wp), wp), wp)
+    r = log1p_ball(u, prec + 8)
+    return r if x > 0 else B.neg(r)
+
+
+def _ball_acosh(x, prec):
+    """acosh x = log1p(u), u = (x - 1) + sqrt((x - 1)(x + 1)), x > 1."""
+    wp = prec + 24
+    X = from_float(x)
+    one = exact(1)
+    d = sub(X, one, wp)                                  # exact for a dyadic
+    u = add(d, B.sqrt(mul(d, add(X, one, wp), wp), wp), wp)
+    return log1p_ball(u, prec + 8)
+
+
+def _ball_atanh(x, prec):
+    """atanh|x| = log1p(2|x| / (1 - |x|)) / 2, |x| < 1; odd."""
+    wp = prec + 24
+    X = from_float(abs(x))
+    u = div(B.scale2(X, 1), sub(exact(1), X, wp), wp)
+    r = B.scale2(log1p_ball(u, prec + 8), -1)
+    return r if x > 0 else B.neg(r)
+
+
 def _sum_squares(x, y):
     """x^2 + y^2 as an exact dyadic (S, E) with E even."""
     terms = [_dyadic(abs(v)) for v in (x, y) if v != 0.0]
@@ -560,7 +609,8 @@ _BALLS = {"sin": _ball_sin, "cos": _ball_cos, "tan": _ball_tan,
           "log2": _ball_log2, "sinh": _ball_sinh, "cosh": _ball_cosh,
           "tanh": _ball_tanh, "asin": _ball_asin, "acos": _ball_acos,
           "atan": _ball_atan, "log10": _ball_log10, "exp10": _ball_exp10,
-          "expm1": _ball_expm1, "log1p": _ball_log1p, "cbrt": _ball_cbrt}
+          "expm1": _ball_expm1, "log1p": _ball_log1p, "cbrt": _ball_cbrt,
+          "asinh": _ball_asinh, "acosh": _ball_acosh, "atanh": _ball_atanh}
 
 
 def _dd(b):

@@ -103,18 +103,24 @@ struct Header {
   X(123, IoF64, OpAtan2U35, 2) X(124, IoF32, OpAtan2U35, 2)                     \
   X(125, IoF64, OpSinhU35, 1) X(126, IoF32, OpSinhU35, 1)                       \
   X(127, IoF64, OpCoshU35, 1) X(128, IoF32, OpCoshU35, 1)                       \
-  X(129, IoF64, OpTanhU35, 1) X(130, IoF32, OpTanhU35, 1)
-constexpr int NUM_OPS = 131;
+  X(129, IoF64, OpTanhU35, 1) X(130, IoF32, OpTanhU35, 1)                       \
+  X(131, IoF64, OpAsinhU10, 1) X(132, IoF32, OpAsinhU10, 1) X(133, IoBF16, OpAsinhU10, 1) \
+  X(134, IoF16, OpAsinhU10, 1) X(135, IoF32ViaF64, OpAsinhU10, 1)               \
+  X(136, IoF64, OpAcoshU10, 1) X(137, IoF32, OpAcoshU10, 1) X(138, IoBF16, OpAcoshU10, 1) \
+  X(139, IoF16, OpAcoshU10, 1) X(140, IoF32ViaF64, OpAcoshU10, 1)               \
+  X(141, IoF64, OpAtanhU10, 1) X(142, IoF32, OpAtanhU10, 1) X(143, IoBF16, OpAtanhU10, 1) \
+  X(144, IoF16, OpAtanhU10, 1) X(145, IoF32ViaF64, OpAtanhU10, 1)
+constexpr int NUM_OPS = 146;
 
 // host-side code of a (fn, variant, dtype) triple, or -1
 int op_code(int fn, int v, int t) {
   // dtype order in the table: f64, f32, bf16, f16, f32_via_f64
   static const int u10_base[LIBM_HIP_NUM_FN] = {0, 7, 14, 21, 26, 31, 36, 56, 61, 41, 46, 51,
                                                 -1, -1, 70, 77, 84, 93, 98, 103, 108, 113,
-                                                118};
+                                                118, 131, 136, 141};
   static const int u35_base[LIBM_HIP_NUM_FN] = {5, 12, 19, -1, -1, 91, -1, -1, 123, 125, 127,
                                                 129, -1, -1, 75, 82, 89, -1, -1, -1, -1, -1,
-                                                -1};
+                                                -1, -1, -1, -1};
   if (fn < 0 || fn >= LIBM_HIP_NUM_FN || t < 0 || t > 4) return -1;
   if (fn == LIBM_HIP_FMOD || fn == LIBM_HIP_REMAINDER) {
     if (v != LIBM_HIP_EXACT || t > 1) return -1;
@@ -129,6 +135,7 @@ int op_code(int fn, int v, int t) {
 // (from the elementwise kernels' measured times: trig with Payne-Hanek and
 // the remainders are the most expensive, exp/log the cheapest)
 float op_cost(int code) {
+  if (code >= 131) return 0.55f;               // asinh, acosh, atanh
   if (code >= 125) return 0.35f;               // sinh, cosh, tanh u35
   if (code >= 123) return 0.5f;                // atan2 u35
   if (code >= 113) return 0.45f;               // cbrt, hypot
@@ -216,7 +223,7 @@ void k_batch(const Desc* __restrict__ descs,
     unsigned long long start = (t - d.tile_begin) * (unsigned long long)TILE;
     switch (d.op) {
 #define LMH_CASE(code, Io, Op, ar) \
-  case code: run_tile<Io, Op, ar>(d.a, d.b, d.out, d.n, start); break;
+  case code: run_tile<Io, typename EvalOp<Io, Op>::type, ar>(d.a, d.b, d.out, d.n, start); break;
       LMH_BATCH_OPS(LMH_CASE)
 #undef LMH_CASE
       default: break;

@@ -4,12 +4,14 @@
 // argument, the lowest polynomial terms, the reconstructions).  Binary64
 // arithmetic appears only where a few binary64 instructions replace a longer
 // float-float sequence (one binary64 instruction costs one issue slot on
-// gfx950): the trig Cody-Waite reduction and cbrt.
+// gfx950): the trig Cody-Waite reduction, cbrt, hypot and the inverse
+// hyperbolic functions.
 #pragma once
 #include "dd.h"
 #include "generated/consts.inc"
 #include "generated/poly_coeffs.inc"
 #include "generated/ph_table_f32.inc"
+#include "eval_f64.h"                          // binary64 pieces used in working precision
 #pragma STDC FP_CONTRACT OFF
 
 namespace lmh {
@@ -760,6 +762,50 @@ LMH_INLINE float expm1f_u10(float x) {
   r = x < -18.0f ? -1.0f : r;
   r = isnan_(x) ? x : r;
   return fabs_(x) < 0x1p-25f ? x : r;
+}
+
+// asinh, acosh, atanh in binary64 working precision: for binary32 x the
+// squares and x +- 1 are exact doubles, the square root comes from the
+// reciprocal square root estimate and two Newton steps, and log1p(u) is
+// log(1 + u) with the rounding error of 1 + u added back (/ (1 + u)); each
+// stage is good to a few binary64 ulps, far inside binary32's half ulp
+LMH_INLINE double sqrt_ws(double p) {
+  double g = rsq_(p);
+  double h = 0.5 * g;
+  double r = p * g;
+  r = fma_(h, fma_(-r, r, p), r);
+  return fma_(h, fma_(-r, r, p), r);
+}
+
+LMH_INLINE double log1p_ws(double u) {            // finite u >= 0
+  double a = 1.0 + u;
+  return log_ws(a) + (u - (a - 1.0)) / a;
+}
+
+LMH_INLINE float asinhf_u10(float x) {
+  double a = fabs_((double)x);
+  double x2 = a * a;
+  double r = log1p_ws(a + x2 / (1.0 + sqrt_ws(1.0 + x2)));
+  float v = copysign_((float)r, x);
+  return fabs_(x) < 0x1p-12f || !isfinite_(x) ? x : v;
+}
+
+LMH_INLINE float acoshf_u10(float x) {
+  double xd = (double)x;
+  double d = xd - 1.0;
+  float v = (float)log1p_ws(d + sqrt_ws(d * (xd + 1.0)));
+  v = x == 1.0f ? 0.0f : v;
+  v = x < 1.0f ? __builtin_nanf("") : v;
+  return isinf_(x) && x > 0.0f ? x : (isnan_(x) ? x : v);
+}
+
+LMH_INLINE float atanhf_u10(float x) {
+  double a = fabs_((double)x);
+  float v = copysign_((float)(0.5 * log1p_ws(2.0 * a / (1.0 - a))), x);
+  v = a == 1.0 ? copysign_(__builtin_inff(), x) : v;
+  v = a > 1.0 ? __builtin_nanf("") : v;
+  v = fabs_(x) < 0x1p-12f ? x : v;
+  return isnan_(x) ? x : v;
 }
 
 // cbrt in binary64: a = m 2^i in [0.5, 4) as for binary64, one Newton step

@@ -97,9 +97,10 @@ inline bool grid_for(size_t n, int ept, Cfg c, unsigned& blocks) {
   return true;
 }
 
-template <class Io, class Op>
+template <class Io, class OpF>
 libm_hip_status launch_unary(const void* x, void* y, size_t n, void* stream, const char* name,
                              int key) {
+  typedef typename EvalOp<Io, OpF>::type Op;
   if (n == 0) return LIBM_HIP_OK;
   if (!x || !y) {
     set_error("libm_hip: NULL pointer with n > 0");
@@ -136,9 +137,10 @@ libm_hip_status launch_unary(const void* x, void* y, size_t n, void* stream, con
   return launch_error(name);
 }
 
-template <class Io, class Op>
+template <class Io, class OpF>
 libm_hip_status launch_sincos(const void* x, void* ys, void* yc, size_t n, void* stream,
                               const char* name) {
+  typedef typename EvalOp<Io, OpF>::type Op;
   if (n == 0) return LIBM_HIP_OK;
   if (!x || !ys || !yc) {
     set_error("libm_hip: NULL pointer with n > 0");
@@ -160,9 +162,10 @@ libm_hip_status launch_sincos(const void* x, void* ys, void* yc, size_t n, void*
   return launch_error(name);
 }
 
-template <class Io, class Op>
+template <class Io, class OpF>
 libm_hip_status launch_binary(const void* a, const void* b, void* y, size_t n, void* stream,
                               const char* name, int key) {
+  typedef typename EvalOp<Io, OpF>::type Op;
   if (n == 0) return LIBM_HIP_OK;
   if (!a || !b || !y) {
     set_error("libm_hip: NULL pointer with n > 0");
@@ -279,6 +282,9 @@ LMH_DEF_UNARY(log1p, u10, OpLog1pU10, LOG1P, U10)
 LMH_DEF_UNARY(exp10, u10, OpExp10U10, EXP10, U10)
 LMH_DEF_UNARY(expm1, u10, OpExpm1U10, EXPM1, U10)
 LMH_DEF_UNARY(cbrt, u10, OpCbrtU10, CBRT, U10)
+LMH_DEF_UNARY(asinh, u10, OpAsinhU10, ASINH, U10)
+LMH_DEF_UNARY(acosh, u10, OpAcoshU10, ACOSH, U10)
+LMH_DEF_UNARY(atanh, u10, OpAtanhU10, ATANH, U10)
 LMH_DEF_UNARY_HALF(sin, OpSinU10, SIN)
 LMH_DEF_UNARY_HALF(cos, OpCosU10, COS)
 LMH_DEF_UNARY_HALF(tan, OpTanU10, TAN)
@@ -297,6 +303,9 @@ LMH_DEF_UNARY_HALF(log1p, OpLog1pU10, LOG1P)
 LMH_DEF_UNARY_HALF(exp10, OpExp10U10, EXP10)
 LMH_DEF_UNARY_HALF(expm1, OpExpm1U10, EXPM1)
 LMH_DEF_UNARY_HALF(cbrt, OpCbrtU10, CBRT)
+LMH_DEF_UNARY_HALF(asinh, OpAsinhU10, ASINH)
+LMH_DEF_UNARY_HALF(acosh, OpAcoshU10, ACOSH)
+LMH_DEF_UNARY_HALF(atanh, OpAtanhU10, ATANH)
 
 #define LMH_DEF_SINCOS(var, Io, T, tag, Op)                                                        \
   libm_hip_status libm_hip_sincos_##var##_##tag(const T* x, T* s, T* c, size_t n, void* stream) {  \
@@ -479,6 +488,9 @@ extern "C" libm_hip_status libm_hip_eval(libm_hip_fn fn, libm_hip_variant v, lib
     case LIBM_HIP_EXP10: if (u10) return dispatch_unary<OpExp10U10>(t, a, out, n, s, false, key); break;
     case LIBM_HIP_EXPM1: if (u10) return dispatch_unary<OpExpm1U10>(t, a, out, n, s, false, key); break;
     case LIBM_HIP_CBRT: if (u10) return dispatch_unary<OpCbrtU10>(t, a, out, n, s, false, key); break;
+    case LIBM_HIP_ASINH: if (u10) return dispatch_unary<OpAsinhU10>(t, a, out, n, s, false, key); break;
+    case LIBM_HIP_ACOSH: if (u10) return dispatch_unary<OpAcoshU10>(t, a, out, n, s, false, key); break;
+    case LIBM_HIP_ATANH: if (u10) return dispatch_unary<OpAtanhU10>(t, a, out, n, s, false, key); break;
     case LIBM_HIP_HYPOT: if (u10) return dispatch_binary<OpHypotU10>(t, a, b, out, n, s, true, key); break;
     case LIBM_HIP_POW: if (u10) return dispatch_binary<OpPowU10>(t, a, b, out, n, s, true, key); break;
     case LIBM_HIP_ATAN2:

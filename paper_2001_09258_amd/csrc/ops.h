@@ -163,6 +163,9 @@ LMH_OP1(OpLog1pU10, log1p_u10, log1pf_u10)
 LMH_OP1(OpExp10U10, exp10_u10, exp10f_u10)
 LMH_OP1(OpExpm1U10, expm1_u10, expm1f_u10)
 LMH_OP1(OpCbrtU10, cbrt_u10, cbrtf_u10)
+LMH_OP1(OpAsinhU10, asinh_u10, asinhf_u10)
+LMH_OP1(OpAcoshU10, acosh_u10, acoshf_u10)
+LMH_OP1(OpAtanhU10, atanh_u10, atanhf_u10)
 LMH_OP2(OpHypotU10, hypot_u10, hypotf_u10)
 LMH_OP1(OpSinhU35, sinh_u35, sinhf_u35)
 LMH_OP1(OpCoshU35, cosh_u35, coshf_u35)
@@ -212,6 +215,44 @@ __device__ __forceinline__ void store_nt(const P& v, void* dst) {
 // elements per lane and pack: 16 bytes of storage per lane and operand
 template <class S>
 constexpr int ept_for() { return 16 / (int)sizeof(S); }
+
+// The evaluator an (element type, function) pair runs.  bf16 and f16 go
+// through binary32 and f32_via_f64 through binary64: the wider type carries
+// at least 13 more bits (bf16: 16, f16: 13, binary32 from binary64: 29), so
+// its 3.5-ULP evaluator, rounded once, is within 0.5 + 3.5 * 2^-13 ULP of the
+// exact result in the narrow format, inside the 1.0-ULP bound; it is used
+// wherever it exists.  Every path (entry points, dispatcher, batched kernel,
+// device API) maps through this, so they agree bit for bit.
+template <class Io, class Op>
+struct EvalOp {
+  typedef Op type;
+};
+#define LMH_NARROW_EVAL(OP10, OP35)                   \
+  template <>                                         \
+  struct EvalOp<IoBF16, OP10> {                       \
+    typedef OP35 type;                                \
+  };                                                  \
+  template <>                                         \
+  struct EvalOp<IoF16, OP10> {                        \
+    typedef OP35 type;                                \
+  };                                                  \
+  template <>                                         \
+  struct EvalOp<IoF32ViaF64, OP10> {                  \
+    typedef OP35 type;                                \
+  };
+LMH_NARROW_EVAL(OpSinU10, OpSinU35)
+LMH_NARROW_EVAL(OpCosU10, OpCosU35)
+LMH_NARROW_EVAL(OpTanU10, OpTanU35)
+LMH_NARROW_EVAL(OpSinCosU10, OpSinCosU35)
+LMH_NARROW_EVAL(OpLogU10, OpLogU35)
+LMH_NARROW_EVAL(OpAsinU10, OpAsinU35)
+LMH_NARROW_EVAL(OpAcosU10, OpAcosU35)
+LMH_NARROW_EVAL(OpAtanU10, OpAtanU35)
+LMH_NARROW_EVAL(OpSinhU10, OpSinhU35)
+LMH_NARROW_EVAL(OpCoshU10, OpCoshU35)
+LMH_NARROW_EVAL(OpTanhU10, OpTanhU35)
+LMH_NARROW_EVAL(OpAtan2U10, OpAtan2U35)
+#undef LMH_NARROW_EVAL
 
 }  // namespace lmh_ops
 

@@ -45,6 +45,9 @@ K1(p64_log1p, double, log1p_u10(v))
 K1(p64_exp10, double, exp10_u10(v))
 K1(p64_expm1, double, expm1_u10(v))
 K1(p64_cbrt, double, cbrt_u10(v))
+K1(p64_asinh, double, asinh_u10(v))
+K1(p64_acosh, double, acosh_u10(v))
+K1(p64_atanh, double, atanh_u10(v))
 // binary32 pieces
 KS(p32_sincw, float, sincosf_fast(v, false))
 KS(p32_coscw, float, sincosf_fast(v, true))
@@ -82,3 +85,6 @@ K1(p32_log1p, float, log1pf_u10(v))
 K1(p32_exp10, float, exp10f_u10(v))
 K1(p32_expm1, float, expm1f_u10(v))
 K1(p32_cbrt, float, cbrtf_u10(v))
+K1(p32_asinh, float, asinhf_u10(v))
+K1(p32_acosh, float, acoshf_u10(v))
+K1(p32_atanh, float, atanhf_u10(v))

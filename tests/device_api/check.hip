@@ -118,6 +118,9 @@ extern "C" int device_api_eval(int fn, int variant, int dtype, const void* a, co
     case 20: U1(expm1_u10)
     case 21: U1(cbrt_u10)
     case 22: B2(hypot_u10)
+    case 23: U1(asinh_u10)
+    case 24: U1(acosh_u10)
+    case 25: U1(atanh_u10)
   }
   return 2;
 }

@@ -40,7 +40,8 @@ NP_UNARY = {"sin": np.sin, "cos": np.cos, "tan": np.tan, "exp": np.exp,
             "exp2": np.exp2, "log": np.log, "log2": np.log2, "sinh": np.sinh,
             "cosh": np.cosh, "tanh": np.tanh, "asin": np.arcsin, "acos": np.arccos,
             "atan": np.arctan, "log10": np.log10, "exp10": lambda x: np.power(10.0, x),
-            "expm1": np.expm1, "log1p": np.log1p, "cbrt": np.cbrt}
+            "expm1": np.expm1, "log1p": np.log1p, "cbrt": np.cbrt, "asinh": np.arcsinh,
+            "acosh": np.arccosh, "atanh": np.arctanh}
 
 
 def same(a, b):
@@ -116,7 +117,8 @@ MP = {"sin": mpmath.sin, "cos": mpmath.cos, "tan": mpmath.tan,
       "asin": mpmath.asin, "acos": mpmath.acos, "atan": mpmath.atan,
       "log10": mpmath.log10, "exp10": lambda x: mpmath.power(10, x),
       "expm1": mpmath.expm1, "log1p": mpmath.log1p,
-      "cbrt": lambda x: mpmath.sign(x) * mpmath.cbrt(abs(x))}   # the real root
+      "cbrt": lambda x: mpmath.sign(x) * mpmath.cbrt(abs(x)),   # the real root
+      "asinh": mpmath.asinh, "acosh": mpmath.acosh, "atanh": mpmath.atanh}
 
 
 def _mp_f64(fn, x, y=None):
@@ -153,6 +155,11 @@ def _inputs(fn, rng, n):
                 xs.append(math.copysign(10 ** rng.uniform(-310, 0), rng.random() - 0.5))
             else:
                 xs.append(abs(_rand_bits(rng)))
+        elif fn == "acosh":
+            xs.append(1 + 10 ** rng.uniform(-16, 0) if c < 0.4 else abs(_rand_bits(rng)) + 1.0)
+        elif fn == "atanh":
+            xs.append(math.copysign(1 - 10 ** rng.uniform(-16, 0), rng.random() - 0.5) if c < 0.4
+                      else math.copysign(10 ** rng.uniform(-310, 0), rng.random() - 0.5))
         elif fn in ("exp10", "expm1"):
             lim = 330 if fn == "exp10" else 760
             xs.append(rng.uniform(-lim, lim) if c < 0.5 else
@@ -257,7 +264,8 @@ def _midpoint_distance_in_dulps(d):
 
 @pytest.mark.parametrize("fn", ["sin", "cos", "tan", "exp", "log", "exp2", "log2",
                                 "sinh", "cosh", "tanh", "asin", "acos", "atan",
-                                "log10", "exp10", "expm1", "log1p", "cbrt"])
+                                "log10", "exp10", "expm1", "log1p", "cbrt", "asinh",
+                                "acosh", "atanh"])
 def test_binary32_vs_glibc_double_rounded(fn):
     # a strided sweep over all positive and negative binary32 bit patterns
     stride = 1 << 16
@@ -524,3 +532,50 @@ def test_hypot_exact_cases_specials_and_mpmath():
         got = evaluate1("hypot", "f64", x, y)[0]
         assert same(got, _to_f64(_mp_f64("hypot", x, y))), (x, y)
         assert same(got, math.hypot(x, y)) or abs(got - math.hypot(x, y)) <= math.ulp(got)
+
+
+def test_inverse_hyperbolics_identities_and_small_arguments():
+    """sinh(asinh x) = x, cosh(acosh x) = x and tanh(atanh x) = x on the
+    reference pairs (MP identities); asinh x and atanh x round to x for
+    |x| < 2^-27 (x^3/6 and x^3/3 are below half an ulp); acosh near 1
+    against sqrt(2d) (1 - d/12 + 3d^2/160), d = x - 1."""
+    rng = random.Random(10)
+    for _ in range(60):
+        x = math.copysign(10 ** rng.uniform(-20, 300), rng.random() - 0.5)
+        _, h, l = evaluate1("asinh", "f64", x)
+        with mpmath.workprec(400):
+            assert abs(mpmath.sinh(mpmath.mpf(h) + mpmath.mpf(l)) - x) <= abs(x) * mpmath.mpf(2) ** -98
+        a = 1 + 10 ** rng.uniform(-15, 3)
+        _, h, l = evaluate1("acosh", "f64", a)
+        with mpmath.workprec(400):
+            assert abs(mpmath.cosh(mpmath.mpf(h) + mpmath.mpf(l)) - a) <= a * mpmath.mpf(2) ** -98
+        t = math.copysign(10 ** rng.uniform(-20, -0.01), rng.random() - 0.5)
+        _, h, l = evaluate1("atanh", "f64", t)
+        with mpmath.workprec(400):
+            assert abs(mpmath.tanh(mpmath.mpf(h) + mpmath.mpf(l)) - t) <= abs(t) * mpmath.mpf(2) ** -98
+    for x in (1e-10, -3e-9, 5e-324, -(2.0 ** -40)):
+        assert evaluate1("asinh", "f64", x)[0] == x
+        assert evaluate1("atanh", "f64", x)[0] == x
+    for k in (30, 40, 50):
+        d = 2.0 ** -k
+        want = math.sqrt(2 * d) * (1 - d / 12 + 3 * d * d / 160)   # to O(d^3)
+        got = evaluate1("acosh", "f64", 1 + d)[0]
+        assert abs(got - want) <= 2 * math.ulp(want)
+
+
+def test_log_series_on_balls_agree_with_exact_log():
+    """log_of_ball and log1p_ball (used for the inverse hyperbolics) against
+    log_ball on exact dyadics."""
+    from oracle.elementary import log_of_ball, log1p_ball
+    rng = random.Random(11)
+    for _ in range(40):
+        m = rng.getrandbits(53) | 1
+        e = rng.randint(-1100, 900)
+        a = log_ball(m, e, 200)
+        b = log_of_ball(B.exact(m, e), 200)
+        assert abs(B.approx(a) - B.approx(b)) <= abs(B.approx(a)) * 2.0 ** -150 + 2.0 ** -190
+        u_m, u_e = rng.getrandbits(53) | 1, rng.randint(-200, 0)
+        c = log1p_ball(B.exact(u_m, u_e), 200)
+        # 1 + u = (2^-u_e + u_m) 2^u_e exactly
+        d = log_ball((1 << -u_e) + u_m, u_e, 200)
+        assert abs(B.approx(c) - B.approx(d)) <= abs(B.approx(d)) * 2.0 ** -150

@@ -26,7 +26,7 @@ __all__ = ["FN_IDS", "rng_for", "specials", "small_set", "mixture", "large_args"
 FN_IDS = {name: i for i, name in enumerate(
     ["sin", "cos", "tan", "exp", "exp2", "log", "log2", "pow", "atan2",
      "sinh", "cosh", "tanh", "fmod", "remainder", "asin", "acos", "atan",
-     "log10", "log1p", "exp10", "expm1", "cbrt", "hypot"])}
+     "log10", "log1p", "exp10", "expm1", "cbrt", "hypot", "asinh", "acosh", "atanh"])}
 
 DTYPE_MAX = {"f64": np.finfo(np.float64).max, "f32": float(np.finfo(np.float32).max),
              "f16": 65504.0, "bf16": 3.3895313892515355e38}
@@ -196,11 +196,12 @@ def unit_mixture(fn, dt, n=1 << 26, operand=0):
 
 def function_mixture(fn, dt, n=1 << 26, operand=0):
     """The benchmark-style input of ``fn``: ``unit_mixture`` for asin and
-    acos, otherwise the mixture (bf16/f16: its narrow form).  For log1p a
+    acos and atanh, otherwise the mixture (bf16/f16: its narrow form); for
+    acosh 60% of the elements become |x| + 1 and 30% 1 + 10^U[near, 0].  For log1p a
     fifth of the elements, drawn per element, are -(1 - 10^U[near, 0]) with
     near = -16 (binary64), -7 (binary32, bf16) or -3 (f16): next to -1, where
     1 + x cancels."""
-    if fn in ("asin", "acos"):
+    if fn in ("asin", "acos", "atanh"):
         return unit_mixture(fn, dt, n, operand)
     if dt in ("bf16", "f16"):
         x = narrow_mixture(fn, dt, n, operand)
@@ -212,6 +213,16 @@ def function_mixture(fn, dt, n=1 << 26, operand=0):
         near = {"f64": -16.0, "f16": -3.0}.get(dt, -7.0)
         v = -(1.0 - np.exp(rng.uniform(near, 0.0, int(m.sum())) * np.log(10.0)))
         x[m] = _cast(v, dt)
+    if fn == "acosh":
+        # the domain is [1, inf): |x| + 1 for 60% of the elements and
+        # 1 + 10^U[near, 0] for 30%, the rest as drawn
+        rng = rng_for(10, fn, operand)
+        c = rng.random(n)
+        near = {"f64": -16.0, "f16": -3.0}.get(dt, -7.0)
+        with np.errstate(over="ignore"):
+            shifted = _cast(np.abs(x.astype(np.float64)) + 1.0, dt)
+            close = _cast(1.0 + np.exp(rng.uniform(near, 0.0, n) * np.log(10.0)), dt)
+        x = np.where(c < 0.6, shifted, np.where(c < 0.9, close, x))
     return x
 
 
