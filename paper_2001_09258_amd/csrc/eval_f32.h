@@ -73,9 +73,10 @@ LMH_INLINE float exp2f_u10(float x) {
 
 LMH_INLINE fff expf_ff(fff w, float& k) {
   float wh = w.hi > 104.0f ? 104.0f : (w.hi < -104.0f ? -104.0f : w.hi);
+  float wl = wh == w.hi ? w.lo : 0.0f;              // the tail goes with a clamp
   k = rint_(wh * LOG2E_F);
   float s = fma_(k, -LN2_HI_F, wh);
-  fff r = dd2_add2(s, w.lo + k * -LN2_LO_F);
+  fff r = dd2_add2(s, wl + k * -LN2_LO_F);
   return dd2_norm(expf_core(r.hi, r.lo));
 }
 
@@ -407,29 +408,19 @@ LMH_INLINE float powf_u10(float x, float y) {
   fff w = dd2_mul(lg, y);
   float k;
   fff e = expf_ff(w, k);
-  float r = ff_ldexp(e, (int)k);
-  r = w.hi > 89.0f ? __builtin_inff() : r;
-  r = w.hi < -104.0f ? 0.0f : r;
+  float r = ff_ldexp(e, (int)k);                   // overflows / underflows itself
+  // Annex F as in the binary64 form
   bool yint = rint_(y) == y;
-  bool yodd = yint && fabs_(y) < 0x1p24f && is_odd_intf(y);
-  r = (x < 0.0f && yodd) ? -r : r;
-  r = (x < 0.0f && !yint && isfinite_(x) && isfinite_(y)) ? __builtin_nanf("") : r;
-  if (isinf_(x)) {
-    bool neg = x < 0.0f;
-    float mag = y < 0.0f ? 0.0f : __builtin_inff();
-    r = (neg && yodd) ? -mag : mag;
-  }
-  if (isinf_(y)) {
-    float mag = (ax < 1.0f) == (y < 0.0f) ? __builtin_inff() : 0.0f;
-    r = ax == 1.0f ? 1.0f : mag;
-  }
-  if (x == 0.0f) {
-    float mag = y < 0.0f ? __builtin_inff() : 0.0f;
-    r = yodd ? copysign_(mag, x) : mag;
-  }
+  bool yodd = fabs_(fma_(-2.0f, rint_(0.5f * y), y)) == 1.0f;
+  bool xneg = __builtin_signbit(x);
+  r = (xneg && yodd) ? -r : r;
+  r = (x < 0.0f && !yint) ? __builtin_nanf("") : r;
+  float mag = (ax == 0.0f) == (y < 0.0f) ? __builtin_inff() : 0.0f;
+  r = (ax == 0.0f || isinf_(x)) ? ((xneg && yodd) ? -mag : mag) : r;
+  float ymag = (ax < 1.0f) == (y < 0.0f) ? __builtin_inff() : 0.0f;
+  r = isinf_(y) ? (ax == 1.0f ? 1.0f : ymag) : r;
   r = (isnan_(x) || isnan_(y)) ? __builtin_nanf("") : r;
-  r = (y == 0.0f || x == 1.0f) ? 1.0f : r;
-  return r;
+  return (y == 0.0f || x == 1.0f) ? 1.0f : r;
 }
 
 // binary32 forms of atan_poly / atan_ratio (the extra reduction above

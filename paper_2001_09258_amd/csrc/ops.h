@@ -72,18 +72,12 @@ struct IoF16 {
 // Trigonometric tags also expose their reduction paths, so a kernel can
 // gather the elements that need Payne-Hanek and run them densely:
 // is_slow(x), fast(x) / slow(x) -> reduced state, finish(x, state) ->
-// result; is_tiny(x) / tiny(x) give the finisher's own shortcut value (x, or
-// 1 for cos) for arguments that need no reduction.  Every route gives the
-// bits of f(x).
-#define LMH_TRIG_OP(NAME, F64FN, F32FN, RED64, RED32, ARG, FIN64, FIN32, TINYV)                 \
+// result.  Every route gives the bits of f(x).
+#define LMH_TRIG_OP(NAME, F64FN, F32FN, RED64, RED32, ARG, FIN64, FIN32)                        \
   struct NAME {                                                                                 \
     static constexpr bool kSplit = true;                                                        \
     static __device__ __forceinline__ double f(double x) { return lmh::F64FN(x); }              \
     static __device__ __forceinline__ float f(float x) { return lmh::F32FN(x); }                \
-    static __device__ __forceinline__ bool is_tiny(double x) { return lmh::trig_tiny(x); }      \
-    static __device__ __forceinline__ bool is_tiny(float x) { return lmh::trigf_tiny(x); }      \
-    static __device__ __forceinline__ double tiny(double x) { return TINYV; }                    \
-    static __device__ __forceinline__ float tiny(float x) { return TINYV; }                      \
     static __device__ __forceinline__ bool is_slow(double x) { return lmh::trig_slow(x); }      \
     static __device__ __forceinline__ bool is_slow(float x) { return lmh::trigf_slow(x); }      \
     static __device__ __forceinline__ lmh::Trig64 fast(double x) { return lmh::RED64##_fast(x ARG); } \
@@ -138,12 +132,12 @@ LMH_SINCOS_OP(OpSinCosU35, sin_finish_u35, cos_finish_u35, sinf_finish_u35, cosf
 
 #define LMH_NOARG
 #define LMH_COMMA ,
-LMH_TRIG_OP(OpSinU10, sin_u10, sinf_u10, sincos, sincosf, LMH_COMMA false, sin_finish_u10, sinf_finish_u10, x)
-LMH_TRIG_OP(OpSinU35, sin_u35, sinf_u35, sincos, sincosf, LMH_COMMA false, sin_finish_u35, sinf_finish_u35, x)
-LMH_TRIG_OP(OpCosU10, cos_u10, cosf_u10, sincos, sincosf, LMH_COMMA true, cos_finish_u10, cosf_finish_u10, 1)
-LMH_TRIG_OP(OpCosU35, cos_u35, cosf_u35, sincos, sincosf, LMH_COMMA true, cos_finish_u35, cosf_finish_u35, 1)
-LMH_TRIG_OP(OpTanU10, tan_u10, tanf_u10, tan, tanf, LMH_NOARG, tan_finish_u10, tanf_finish_u10, x)
-LMH_TRIG_OP(OpTanU35, tan_u35, tanf_u35, tan, tanf, LMH_NOARG, tan_finish_u35, tanf_finish_u35, x)
+LMH_TRIG_OP(OpSinU10, sin_u10, sinf_u10, sincos, sincosf, LMH_COMMA false, sin_finish_u10, sinf_finish_u10)
+LMH_TRIG_OP(OpSinU35, sin_u35, sinf_u35, sincos, sincosf, LMH_COMMA false, sin_finish_u35, sinf_finish_u35)
+LMH_TRIG_OP(OpCosU10, cos_u10, cosf_u10, sincos, sincosf, LMH_COMMA true, cos_finish_u10, cosf_finish_u10)
+LMH_TRIG_OP(OpCosU35, cos_u35, cosf_u35, sincos, sincosf, LMH_COMMA true, cos_finish_u35, cosf_finish_u35)
+LMH_TRIG_OP(OpTanU10, tan_u10, tanf_u10, tan, tanf, LMH_NOARG, tan_finish_u10, tanf_finish_u10)
+LMH_TRIG_OP(OpTanU35, tan_u35, tanf_u35, tan, tanf, LMH_NOARG, tan_finish_u35, tanf_finish_u35)
 LMH_OP1(OpExpU10, exp_u10, expf_u10)
 LMH_OP1(OpExp2U10, exp2_u10, exp2f_u10)
 LMH_OP1(OpLogU10, log_u10, logf_u10)
