@@ -366,7 +366,7 @@ def extra_inverse_trig(lib, L, stream, n, reps, ops):
 
 
 C99_EXTRA = [(fn, "u10") for fn in ("log10", "log1p", "exp10", "expm1", "cbrt", "hypot", "asinh",
-                                    "acosh", "atanh")]
+                                    "acosh", "atanh", "erf", "erfc")]
 U35_EXTRA = [(fn, "u35") for fn in ("atan2", "sinh", "cosh", "tanh")]
 
 

@@ -85,8 +85,15 @@ const char* libm_hip_version(void);
  * described in the paper either) as log1p of an argument formed without
  * cancellation: |x| + x^2/(1 + sqrt(1 + x^2)), (x - 1) + sqrt((x - 1)(x + 1))
  * and 2|x|/(1 - |x|) (halved), in double-double (binary32: in binary64
- * working precision).  All 1.0 ULP; the same Annex F special values as C99
- * (exp10 as exp: 10^+-0 = 1, 10^-inf = +0).
+ * working precision).  erf and erfc (C99, not described in the paper):
+ * erf x = c0 x + c1 x^3 + x^5 P(x^2) below |x| = 0.75 (c0, c1 as pairs);
+ * above, erfc |x| = e^(-x^2) g(|x|) with g from a six-row table of
+ * polynomials (in |x|, or in 1/|x| from 2.25 on) and e^(-x^2) from the
+ * double-double exp of the exact square; erf = 1 - erfc there, erfc(-|x|) =
+ * 2 - erfc |x| (binary32: the same in binary64 working precision).  All 1.0
+ * ULP; the same Annex F special values as C99 (exp10 as exp: 10^+-0 = 1,
+ * 10^-inf = +0; erf(+-0) = +-0, erf(+-inf) = +-1, erfc(-inf) = 2,
+ * erfc(+inf) = +0).
  * ---------------------------------------------------------------------- */
 #define LIBM_HIP_DECL_UNARY(fn, var)                                                       \
   libm_hip_status libm_hip_##fn##_##var##_f64(const double* x, double* y, size_t n,        \
@@ -150,9 +157,13 @@ LIBM_HIP_DECL_UNARY_HALF(cbrt)
 LIBM_HIP_DECL_UNARY(asinh, u10)
 LIBM_HIP_DECL_UNARY(acosh, u10)
 LIBM_HIP_DECL_UNARY(atanh, u10)
+LIBM_HIP_DECL_UNARY(erf, u10)
+LIBM_HIP_DECL_UNARY(erfc, u10)
 LIBM_HIP_DECL_UNARY_HALF(asinh)
 LIBM_HIP_DECL_UNARY_HALF(acosh)
 LIBM_HIP_DECL_UNARY_HALF(atanh)
+LIBM_HIP_DECL_UNARY_HALF(erf)
+LIBM_HIP_DECL_UNARY_HALF(erfc)
 
 /* ------------------------------------------------------------------------
  * sincos: s[i] = sin(x[i]) and c[i] = cos(x[i]) in one pass (the paper's
@@ -258,6 +269,7 @@ typedef enum {
   LIBM_HIP_ASIN, LIBM_HIP_ACOS, LIBM_HIP_ATAN,
   LIBM_HIP_LOG10, LIBM_HIP_LOG1P, LIBM_HIP_EXP10, LIBM_HIP_EXPM1, LIBM_HIP_CBRT,
   LIBM_HIP_HYPOT, LIBM_HIP_ASINH, LIBM_HIP_ACOSH, LIBM_HIP_ATANH,
+  LIBM_HIP_ERF, LIBM_HIP_ERFC,
   LIBM_HIP_NUM_FN
 } libm_hip_fn;
 typedef enum { LIBM_HIP_U10 = 0, LIBM_HIP_U35 = 1, LIBM_HIP_EXACT = 2 } libm_hip_variant;

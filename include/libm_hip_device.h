@@ -96,7 +96,8 @@ LIBM_HIP_DEVICE_UNARY(tanh_u10, OpTanhU10)
 LIBM_HIP_DEVICE_UNARY(asin_u10, OpAsinU10)
 LIBM_HIP_DEVICE_UNARY(acos_u10, OpAcosU10)
 LIBM_HIP_DEVICE_UNARY(atan_u10, OpAtanU10)
-/* log10, log1p, exp10, expm1, cbrt (C99 functions of the paper's library) */
+/* log10, log1p, exp10, expm1, cbrt, asinh, acosh, atanh, erf, erfc (C99
+   functions of the paper's library) */
 LIBM_HIP_DEVICE_UNARY(log10_u10, OpLog10U10)
 LIBM_HIP_DEVICE_UNARY(log1p_u10, OpLog1pU10)
 LIBM_HIP_DEVICE_UNARY(exp10_u10, OpExp10U10)
@@ -105,6 +106,8 @@ LIBM_HIP_DEVICE_UNARY(cbrt_u10, OpCbrtU10)
 LIBM_HIP_DEVICE_UNARY(asinh_u10, OpAsinhU10)
 LIBM_HIP_DEVICE_UNARY(acosh_u10, OpAcoshU10)
 LIBM_HIP_DEVICE_UNARY(atanh_u10, OpAtanhU10)
+LIBM_HIP_DEVICE_UNARY(erf_u10, OpErfU10)
+LIBM_HIP_DEVICE_UNARY(erfc_u10, OpErfcU10)
 /* 3.5-ULP forms (binary64 and binary32) */
 LIBM_HIP_DEVICE_UNARY_WIDE(sin_u35, OpSinU35)
 LIBM_HIP_DEVICE_UNARY_WIDE(cos_u35, OpCosU35)

@@ -15,6 +15,7 @@ deliberately different from the methods the GPU kernels use:
 * atan:  two argument halvings atan t = 2 atan(t / (1 + sqrt(1 + t^2))), then
          the Taylor series.
 * sinh/cosh: Taylor series for |x| < 1, (E -+ 1/E)/2 with E = exp|x| otherwise.
+* erf:   (2/sqrt(pi)) e^(-x^2) times the positive series sum 2^n x^(2n+1)/(2n+1)!!.
 
 Every series adds a bound on its truncated tail to the ball radius.
 """
@@ -23,7 +24,7 @@ from .ball import Ball, exact, add, sub, mul, div, approx, mag_log2
 from .consts import pi, ln2, two_over_pi, half_pi
 
 __all__ = ["exp_ball", "log_ball", "log_of_ball", "log1p_ball", "sincos_reduced",
-           "sin_cos_ball", "atan_ball", "sinh_cosh_small", "tail_ball"]
+           "sin_cos_ball", "atan_ball", "sinh_cosh_small", "erf_ball", "tail_ball"]
 
 
 def tail_ball(b, bound_log2):
@@ -215,6 +216,28 @@ def atan_ball(t, prec):
             break
         k += 1
     return B.scale2(s, halvings)
+
+
+def erf_ball(x, prec):
+    """erf x for an exact x > 0: (2/sqrt(pi)) e^(-x^2) sum_n 2^n x^(2n+1) /
+    (1 3 5 ... (2n+1)), a series of positive terms (no cancellation).  Once
+    the term ratio r = 2x^2/(2n+3) is below 1/2 the tail is below the last
+    term."""
+    wp = prec + 24
+    x2 = mul(x, x, wp)
+    twox2 = B.scale2(x2, 1)
+    term = x
+    s = x
+    n = 0
+    while True:
+        n += 1
+        term = div(mul(term, twox2, wp), exact(2 * n + 1), wp)
+        s = add(s, term, wp)
+        if approx(twox2) < (2 * n + 3) / 2 and mag_log2(term) < mag_log2(s) - wp - 8:
+            s = tail_ball(s, mag_log2(term) + 1)
+            break
+    c = div(exact(2), B.sqrt(pi(wp + 8), wp), wp)
+    return mul(mul(c, exp_ball(B.neg(x2), wp), wp), s, wp)
 
 
 def sinh_cosh_small(x, prec):

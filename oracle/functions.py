@@ -15,8 +15,8 @@ detected and computed exactly (exp2 and log2 at powers of two, pow when x^y is
 a dyadic rational, log10 at powers of ten, exp10 at nonnegative integers,
 cbrt at cubes and hypot when x^2 + y^2 is a square).  exp, sin, cos, tan,
 log (x != 1), atan (x != 0), expm1 and log1p (x != 0), the hyperbolic
-functions and their inverses (asinh, atanh at x != 0, acosh at x != 1) of a
-nonzero dyadic are transcendental, hence never a boundary.
+functions and their inverses (asinh, atanh at x != 0, acosh at x != 1) and
+erf, erfc of a nonzero dyadic are transcendental, hence never a boundary.
 
 Special inputs (zeros, infinities, NaN) follow C99 Annex F (F.9), which the
 paper adopts: "same results as libm, as specified in the ANSI C standard"
@@ -36,7 +36,7 @@ from . import ball as B
 from .ball import Ball, exact, from_float, add, sub, mul, div, PrecisionError
 from .consts import pi, ln2
 from .elementary import (exp_ball, log_ball, log1p_ball, sincos_reduced, sin_cos_ball,
-                         atan_ball, sinh_cosh_small)
+                         atan_ball, sinh_cosh_small, erf_ball)
 from .rounding import FORMATS, rn_dyadic, rn_ball
 
 __all__ = ["UNARY", "BINARY", "evaluate1", "OracleError"]
@@ -47,7 +47,8 @@ PREC_CAP = 16384
 
 UNARY = ("sin", "cos", "tan", "exp", "exp2", "log", "log2",
          "sinh", "cosh", "tanh", "asin", "acos", "atan",
-         "log10", "exp10", "expm1", "log1p", "cbrt", "asinh", "acosh", "atanh")
+         "log10", "exp10", "expm1", "log1p", "cbrt", "asinh", "acosh", "atanh",
+         "erf", "erfc")
 BINARY = ("pow", "atan2", "fmod", "remainder", "hypot")
 
 
@@ -175,6 +176,16 @@ def _special_unary(fn, x):
             return x
         if abs(x) == 1.0:
             return math.copysign(INF, x)
+    elif fn == "erf":
+        if x == 0.0:
+            return x
+        if math.isinf(x):
+            return math.copysign(1.0, x)
+    elif fn == "erfc":
+        if x == 0.0:
+            return 1.0
+        if math.isinf(x):
+            return 0.0 if x > 0 else 2.0
     return None
 
 
@@ -498,6 +509,19 @@ def _ball_atanh(x, prec):
     return r if x > 0 else B.neg(r)
 
 
+def _ball_erf(x, prec):
+    r = erf_ball(from_float(abs(x)), prec + 8)
+    return r if x > 0 else B.neg(r)
+
+
+def _ball_erfc(x, prec):
+    """1 - erf x; for x > 0 the subtraction cancels about x^2 log2(e) bits,
+    which the working precision adds."""
+    extra = int(1.45 * x * x) + 16 if x > 0 else 8
+    e = erf_ball(from_float(abs(x)), prec + extra)
+    return sub(exact(1), e, prec + 8) if x > 0 else add(exact(1), e, prec + 8)
+
+
 def _sum_squares(x, y):
     """x^2 + y^2 as an exact dyadic (S, E) with E even."""
     terms = [_dyadic(abs(v)) for v in (x, y) if v != 0.0]
@@ -610,7 +634,8 @@ _BALLS = {"sin": _ball_sin, "cos": _ball_cos, "tan": _ball_tan,
           "tanh": _ball_tanh, "asin": _ball_asin, "acos": _ball_acos,
           "atan": _ball_atan, "log10": _ball_log10, "exp10": _ball_exp10,
           "expm1": _ball_expm1, "log1p": _ball_log1p, "cbrt": _ball_cbrt,
-          "asinh": _ball_asinh, "acosh": _ball_acosh, "atanh": _ball_atanh}
+          "asinh": _ball_asinh, "acosh": _ball_acosh, "atanh": _ball_atanh,
+          "erf": _ball_erf, "erfc": _ball_erfc}
 
 
 def _dd(b):
@@ -691,6 +716,15 @@ def evaluate1(fn, fmt_name, x, y=None):
                 return v, v, 0.0
         if fn == "exp10" and _is_int(x) and x > 0:
             return _exact_result(10 ** int(min(x, 400.0)), 0, fmt)
+        if fn == "erf" and abs(x) > 27.0:
+            # 1 - erf|x| < 2^-1050: the result is +-1 in every format, and
+            # so is the exact value to far below any ulp
+            v = math.copysign(1.0, x)
+            return v, v, 0.0
+        if fn == "erfc" and abs(x) > 28.0:
+            # erfc x < 2^-1135 (x > 28) or 2 - that: +0 or 2 in every format
+            v = 0.0 if x > 0 else 2.0
+            return v, v, 0.0
         if fn == "cbrt":
             ex = _cbrt_exact(x)
             if ex is not None:

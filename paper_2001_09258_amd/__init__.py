@@ -20,7 +20,7 @@ import os
 __all__ = ["load", "library_path", "UNARY", "BINARY", "VARIANTS", "entry_name",
            "call", "evaluate", "sin", "cos", "tan", "exp", "exp2", "log", "log2",
            "sinh", "cosh", "tanh", "asin", "acos", "atan", "log10", "log1p", "exp10",
-           "expm1", "cbrt", "asinh", "acosh", "atanh", "sincos", "pow", "atan2", "hypot", "fmod", "remainder",
+           "expm1", "cbrt", "asinh", "acosh", "atanh", "erf", "erfc", "sincos", "pow", "atan2", "hypot", "fmod", "remainder",
            "LibmHipError"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -28,7 +28,7 @@ _LIBNAME = "libm_hip.so"
 
 UNARY = ("sin", "cos", "tan", "exp", "exp2", "log", "log2", "sinh", "cosh", "tanh",
          "asin", "acos", "atan", "log10", "log1p", "exp10", "expm1", "cbrt", "asinh",
-         "acosh", "atanh")
+         "acosh", "atanh", "erf", "erfc")
 BINARY = ("pow", "atan2", "hypot", "fmod", "remainder")
 # accuracy variants served per function
 VARIANTS = {fn: ("u10",) for fn in UNARY + ("pow", "atan2", "hypot")}
@@ -223,6 +223,7 @@ asin, acos, atan = _unary("asin"), _unary("acos"), _unary("atan")
 log10, log1p, exp10 = _unary("log10"), _unary("log1p"), _unary("exp10")
 expm1, cbrt = _unary("expm1"), _unary("cbrt")
 asinh, acosh, atanh = _unary("asinh"), _unary("acosh"), _unary("atanh")
+erf, erfc = _unary("erf"), _unary("erfc")
 
 
 def sincos(x, variant="u10", outs=None, via_f64=False):
@@ -299,7 +300,7 @@ FN_CODES = {"sin": 0, "cos": 1, "tan": 2, "exp": 3, "exp2": 4, "log": 5, "log2":
             "pow": 7, "atan2": 8, "sinh": 9, "cosh": 10, "tanh": 11, "fmod": 12,
             "remainder": 13, "asin": 14, "acos": 15, "atan": 16, "log10": 17,
             "log1p": 18, "exp10": 19, "expm1": 20, "cbrt": 21, "hypot": 22, "asinh": 23,
-            "acosh": 24, "atanh": 25}
+            "acosh": 24, "atanh": 25, "erf": 26, "erfc": 27}
 VARIANT_CODES = {"u10": 0, "u35": 1, "exact": 2}
 DTYPE_CODES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "f32_via_f64": 4}
 

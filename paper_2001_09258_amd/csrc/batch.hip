@@ -109,18 +109,22 @@ struct Header {
   X(136, IoF64, OpAcoshU10, 1) X(137, IoF32, OpAcoshU10, 1) X(138, IoBF16, OpAcoshU10, 1) \
   X(139, IoF16, OpAcoshU10, 1) X(140, IoF32ViaF64, OpAcoshU10, 1)               \
   X(141, IoF64, OpAtanhU10, 1) X(142, IoF32, OpAtanhU10, 1) X(143, IoBF16, OpAtanhU10, 1) \
-  X(144, IoF16, OpAtanhU10, 1) X(145, IoF32ViaF64, OpAtanhU10, 1)
-constexpr int NUM_OPS = 146;
+  X(144, IoF16, OpAtanhU10, 1) X(145, IoF32ViaF64, OpAtanhU10, 1)               \
+  X(146, IoF64, OpErfU10, 1) X(147, IoF32, OpErfU10, 1) X(148, IoBF16, OpErfU10, 1) \
+  X(149, IoF16, OpErfU10, 1) X(150, IoF32ViaF64, OpErfU10, 1)                   \
+  X(151, IoF64, OpErfcU10, 1) X(152, IoF32, OpErfcU10, 1) X(153, IoBF16, OpErfcU10, 1) \
+  X(154, IoF16, OpErfcU10, 1) X(155, IoF32ViaF64, OpErfcU10, 1)
+constexpr int NUM_OPS = 156;
 
 // host-side code of a (fn, variant, dtype) triple, or -1
 int op_code(int fn, int v, int t) {
   // dtype order in the table: f64, f32, bf16, f16, f32_via_f64
   static const int u10_base[LIBM_HIP_NUM_FN] = {0, 7, 14, 21, 26, 31, 36, 56, 61, 41, 46, 51,
                                                 -1, -1, 70, 77, 84, 93, 98, 103, 108, 113,
-                                                118, 131, 136, 141};
+                                                118, 131, 136, 141, 146, 151};
   static const int u35_base[LIBM_HIP_NUM_FN] = {5, 12, 19, -1, -1, 91, -1, -1, 123, 125, 127,
                                                 129, -1, -1, 75, 82, 89, -1, -1, -1, -1, -1,
-                                                -1, -1, -1, -1};
+                                                -1, -1, -1, -1, -1, -1};
   if (fn < 0 || fn >= LIBM_HIP_NUM_FN || t < 0 || t > 4) return -1;
   if (fn == LIBM_HIP_FMOD || fn == LIBM_HIP_REMAINDER) {
     if (v != LIBM_HIP_EXACT || t > 1) return -1;
@@ -135,6 +139,7 @@ int op_code(int fn, int v, int t) {
 // (from the elementwise kernels' measured times: trig with Payne-Hanek and
 // the remainders are the most expensive, exp/log the cheapest)
 float op_cost(int code) {
+  if (code >= 146) return 0.5f;                // erf, erfc
   if (code >= 131) return 0.55f;               // asinh, acosh, atanh
   if (code >= 125) return 0.35f;               // sinh, cosh, tanh u35
   if (code >= 123) return 0.5f;                // atan2 u35

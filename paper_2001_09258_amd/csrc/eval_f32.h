@@ -4,8 +4,8 @@
 // argument, the lowest polynomial terms, the reconstructions).  Binary64
 // arithmetic appears only where a few binary64 instructions replace a longer
 // float-float sequence (one binary64 instruction costs one issue slot on
-// gfx950): the trig Cody-Waite reduction, cbrt, hypot and the inverse
-// hyperbolic functions.
+// gfx950): the trig Cody-Waite reduction, cbrt, hypot, the inverse
+// hyperbolic functions, erf and erfc.
 #pragma once
 #include "dd.h"
 #include "generated/consts.inc"
@@ -796,6 +796,45 @@ LMH_INLINE float atanhf_u10(float x) {
   v = a == 1.0 ? copysign_(__builtin_inff(), x) : v;
   v = a > 1.0 ? __builtin_nanf("") : v;
   v = fabs_(x) < 0x1p-12f ? x : v;
+  return isnan_(x) ? x : v;
+}
+
+// erf, erfc in binary64 working precision with the binary64 polynomials:
+// x (2/sqrt(pi) + z P(z)) below 1, e^(-x^2) g from the table above (e^(-x^2)
+// from the working-precision exp of the rounded square: relative error
+// below x^2 2^-52, 2^-45 for the |x| < 10.1 that binary32 reaches)
+LMH_INLINE double erf_ws_small(double x) {          // |x| < 0.75
+  double z = x * x;
+  return x * fma_(z, fma_(z, poly_estrin(z, ERF_P_F64), ERF_C1_D_H), TWO_OVER_SQRTPI_D_H);
+}
+LMH_INLINE double erfc_ws_big(double a) {            // 0.75 <= a <= 10.1
+  bool inv;
+  ddd g = erfc_poly(a, inv);
+  double v = exp_ws(-(a * a), 0) * (g.hi + g.lo);
+  return inv ? v / a : v;
+}
+
+LMH_INLINE float erff_u10(float x) {
+  double a = fabs_((double)x);
+  double r = erf_ws_small((double)x);
+  bool mid = a >= ERF_SMALL && a < 4.0;              // above 4 erf rounds to +-1
+  if (any_lane(mid)) r = mid ? copysign_(1.0 - erfc_ws_big(mid ? a : 1.0), (double)x) : r;
+  float v = (float)r;
+  v = a >= 4.0 ? copysign_(1.0f, x) : v;
+  return isnan_(x) ? x : v;
+}
+
+LMH_INLINE float erfcf_u10(float x) {
+  double xd = (double)x, a = fabs_(xd);
+  double r = 1.0 - erf_ws_small(a < ERF_SMALL ? xd : 0.0);
+  bool tab = a >= ERF_SMALL && a < 10.1;             // erfc(10.1) < 2^-150
+  if (any_lane(tab)) {
+    double e = erfc_ws_big(tab ? a : 1.0);
+    r = tab ? (xd > 0.0 ? e : 2.0 - e) : r;
+  }
+  float v = (float)r;
+  v = x >= 10.1f ? 0.0f : v;
+  v = x <= -10.1f ? 2.0f : v;
   return isnan_(x) ? x : v;
 }
 

@@ -285,6 +285,8 @@ LMH_DEF_UNARY(cbrt, u10, OpCbrtU10, CBRT, U10)
 LMH_DEF_UNARY(asinh, u10, OpAsinhU10, ASINH, U10)
 LMH_DEF_UNARY(acosh, u10, OpAcoshU10, ACOSH, U10)
 LMH_DEF_UNARY(atanh, u10, OpAtanhU10, ATANH, U10)
+LMH_DEF_UNARY(erf, u10, OpErfU10, ERF, U10)
+LMH_DEF_UNARY(erfc, u10, OpErfcU10, ERFC, U10)
 LMH_DEF_UNARY_HALF(sin, OpSinU10, SIN)
 LMH_DEF_UNARY_HALF(cos, OpCosU10, COS)
 LMH_DEF_UNARY_HALF(tan, OpTanU10, TAN)
@@ -306,6 +308,8 @@ LMH_DEF_UNARY_HALF(cbrt, OpCbrtU10, CBRT)
 LMH_DEF_UNARY_HALF(asinh, OpAsinhU10, ASINH)
 LMH_DEF_UNARY_HALF(acosh, OpAcoshU10, ACOSH)
 LMH_DEF_UNARY_HALF(atanh, OpAtanhU10, ATANH)
+LMH_DEF_UNARY_HALF(erf, OpErfU10, ERF)
+LMH_DEF_UNARY_HALF(erfc, OpErfcU10, ERFC)
 
 #define LMH_DEF_SINCOS(var, Io, T, tag, Op)                                                        \
   libm_hip_status libm_hip_sincos_##var##_##tag(const T* x, T* s, T* c, size_t n, void* stream) {  \
@@ -491,6 +495,8 @@ extern "C" libm_hip_status libm_hip_eval(libm_hip_fn fn, libm_hip_variant v, lib
     case LIBM_HIP_ASINH: if (u10) return dispatch_unary<OpAsinhU10>(t, a, out, n, s, false, key); break;
     case LIBM_HIP_ACOSH: if (u10) return dispatch_unary<OpAcoshU10>(t, a, out, n, s, false, key); break;
     case LIBM_HIP_ATANH: if (u10) return dispatch_unary<OpAtanhU10>(t, a, out, n, s, false, key); break;
+    case LIBM_HIP_ERF: if (u10) return dispatch_unary<OpErfU10>(t, a, out, n, s, false, key); break;
+    case LIBM_HIP_ERFC: if (u10) return dispatch_unary<OpErfcU10>(t, a, out, n, s, false, key); break;
     case LIBM_HIP_HYPOT: if (u10) return dispatch_binary<OpHypotU10>(t, a, b, out, n, s, true, key); break;
     case LIBM_HIP_POW: if (u10) return dispatch_binary<OpPowU10>(t, a, b, out, n, s, true, key); break;
     case LIBM_HIP_ATAN2:

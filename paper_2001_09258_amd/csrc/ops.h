@@ -160,6 +160,8 @@ LMH_OP1(OpCbrtU10, cbrt_u10, cbrtf_u10)
 LMH_OP1(OpAsinhU10, asinh_u10, asinhf_u10)
 LMH_OP1(OpAcoshU10, acosh_u10, acoshf_u10)
 LMH_OP1(OpAtanhU10, atanh_u10, atanhf_u10)
+LMH_OP1(OpErfU10, erf_u10, erff_u10)
+LMH_OP1(OpErfcU10, erfc_u10, erfcf_u10)
 LMH_OP2(OpHypotU10, hypot_u10, hypotf_u10)
 LMH_OP1(OpSinhU35, sinh_u35, sinhf_u35)
 LMH_OP1(OpCoshU35, cosh_u35, coshf_u35)

@@ -147,6 +147,17 @@ def tanh_g():
     return f, w, mp.mpf(0), mp.mpf("0.625") ** 2 * mp.mpf("1.0001")
 
 
+def erf_p():
+    # erf x = c0 x + c1 x^3 + x^5 P(z), z = x^2 <= 0.75^2, c0 = 2/sqrt(pi),
+    # c1 = -c0/3 (both kept as pairs in the kernel)
+    c0 = 2 / mp.sqrt(mp.pi)
+    c1 = -c0 / 3
+    f = _series_guard(lambda z: ((mp.erf(mp.sqrt(z)) / mp.sqrt(z) - c0) / z - c1) / z,
+                      lambda z: c0 * (mp.mpf(1) / 10 - z / 42 + z ** 2 / 216))
+    w = lambda z: z ** 2 * mp.sqrt(z) / mp.erf(mp.sqrt(z)) if z > 0 else mp.mpf(0)
+    return f, w, mp.mpf(0), mp.mpf("0.5626")
+
+
 # name, target builder, format, error goal (log2), first degree tried
 SPECS = [
     ("EXP_P_F64", exp_p, "f64", -63, 10),
@@ -162,6 +173,7 @@ SPECS = [
     ("SINH_H_F64", sinh_h, "f64", -62, 5),
     ("ASIN_S_F64", asin_s, "f64", -58, 8),
     ("TANH_G_F64", tanh_g, "f64", -62, 9),
+    ("ERF_P_F64", erf_p, "f64", -60, 5),
     ("EXP_P_F32", exp_p, "f32", -32, 4),
     ("LOG_Q_F32", log_q, "f32", -31, 2),
     ("LOG_R_F32", log_r, "f32", -36, 2),

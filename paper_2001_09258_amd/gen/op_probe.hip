@@ -48,6 +48,8 @@ K1(p64_cbrt, double, cbrt_u10(v))
 K1(p64_asinh, double, asinh_u10(v))
 K1(p64_acosh, double, acosh_u10(v))
 K1(p64_atanh, double, atanh_u10(v))
+K1(p64_erf, double, erf_u10(v))
+K1(p64_erfc, double, erfc_u10(v))
 // binary32 pieces
 KS(p32_sincw, float, sincosf_fast(v, false))
 KS(p32_coscw, float, sincosf_fast(v, true))
@@ -88,3 +90,5 @@ K1(p32_cbrt, float, cbrtf_u10(v))
 K1(p32_asinh, float, asinhf_u10(v))
 K1(p32_acosh, float, acoshf_u10(v))
 K1(p32_atanh, float, atanhf_u10(v))
+K1(p32_erf, float, erff_u10(v))
+K1(p32_erfc, float, erfcf_u10(v))

@@ -121,6 +121,8 @@ extern "C" int device_api_eval(int fn, int variant, int dtype, const void* a, co
     case 23: U1(asinh_u10)
     case 24: U1(acosh_u10)
     case 25: U1(atanh_u10)
+    case 26: U1(erf_u10)
+    case 27: U1(erfc_u10)
   }
   return 2;
 }

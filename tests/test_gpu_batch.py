@@ -114,12 +114,12 @@ def test_batch_inverse_trig_and_log_u35_requests():
 
 
 def test_batch_c99_function_requests():
-    """log10, log1p, exp10, expm1, cbrt, hypot, asinh, acosh and atanh in
-    every dtype through one plan (hypot binary), against the per-function
+    """log10, log1p, exp10, expm1, cbrt, hypot, asinh, acosh, atanh, erf and
+    erfc in every dtype through one plan (hypot binary), against the per-function
     entry points."""
     reqs = []
     kinds = [(f, d) for f in ("log10", "log1p", "exp10", "expm1", "cbrt", "hypot", "asinh",
-                              "acosh", "atanh")
+                              "acosh", "atanh", "erf", "erfc")
              for d in ("f64", "f32", "bf16", "f16", "f32_via_f64")]
     for i, (fn, dt) in enumerate(kinds):
         base = "f32" if dt == "f32_via_f64" else dt

@@ -4,8 +4,8 @@ patterns and regular grids, Section 6; a GPU can afford every pattern).
 * binary32: every STRIDE-th bit pattern (default stride 61, an odd step so
   every residue of the low mantissa bits is visited; LIBM_HIP_SWEEP_STRIDE=1
   sweeps all 2^32) for sin u10/u35, cos, tan, exp, log u10/u35, asin u10/u35, acos,
-  atan u10/u35, log10, log1p, exp10, expm1, cbrt, asinh, acosh, atanh, and
-  sinh, cosh, tanh u35.
+  atan u10/u35, log10, log1p, exp10, expm1, cbrt, asinh, acosh, atanh, erf,
+  erfc, and sinh, cosh, tanh u35.
   The host's
   binary64 functions screen the results (their error, at most a few binary64
   ulps, is below 1e-7 binary32 ulp); every element the screen cannot clear
@@ -20,6 +20,7 @@ import os
 
 import numpy as np
 import pytest
+import scipy.special as sps
 
 from tests.gpu_common import run_gpu, run_oracle, BOUND
 from tests.ulp import compare
@@ -35,13 +36,14 @@ NP_F = {"sin": np.sin, "cos": np.cos, "tan": np.tan, "exp": np.exp, "log": np.lo
         "asin": np.arcsin, "acos": np.arccos, "atan": np.arctan, "log10": np.log10,
         "log1p": np.log1p, "exp10": lambda x: np.power(10.0, x), "expm1": np.expm1,
         "cbrt": np.cbrt, "sinh": np.sinh, "cosh": np.cosh, "tanh": np.tanh,
-        "asinh": np.arcsinh, "acosh": np.arccosh, "atanh": np.arctanh}
+        "asinh": np.arcsinh, "acosh": np.arccosh, "atanh": np.arctanh, "erf": sps.erf,
+        "erfc": sps.erfc}
 SWEEP = [("sin", "u10"), ("sin", "u35"), ("cos", "u10"), ("tan", "u10"), ("exp", "u10"),
          ("log", "u10"), ("log", "u35"), ("asin", "u10"), ("asin", "u35"), ("acos", "u10"),
          ("atan", "u10"), ("atan", "u35"), ("log10", "u10"), ("log1p", "u10"),
          ("exp10", "u10"), ("expm1", "u10"), ("cbrt", "u10"), ("sinh", "u35"),
          ("cosh", "u35"), ("tanh", "u35"), ("asinh", "u10"), ("acosh", "u10"),
-         ("atanh", "u10")]
+         ("atanh", "u10"), ("erf", "u10"), ("erfc", "u10")]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -115,7 +117,7 @@ def test_binary32_sweep(fn, variant):
 
 NARROW_UNARY = ["sin", "cos", "tan", "exp", "exp2", "log", "log2", "sinh", "cosh", "tanh",
                 "asin", "acos", "atan", "log10", "log1p", "exp10", "expm1", "cbrt", "asinh",
-                "acosh", "atanh"]
+                "acosh", "atanh", "erf", "erfc"]
 
 
 @pytest.mark.parametrize("dt", ["bf16", "f16"])

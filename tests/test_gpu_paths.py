@@ -33,6 +33,8 @@ OTHERS = [(fn, "u10", dt) for fn in ("exp", "log", "pow", "atan2", "tanh", "asin
                                        ("atan2", "u35", "f64"), ("sinh", "u35", "f32"),
                                        ("tanh", "u35", "f64"), ("asinh", "u10", "f64"),
                                        ("acosh", "u10", "f32"), ("atanh", "u10", "f64"),
+                                       ("erf", "u10", "f64"), ("erfc", "u10", "f32"),
+                                       ("erfc", "u10", "f64"),
                                        ("fmod", "exact", "f64"), ("remainder", "exact", "f32")]
 BINARY = ("pow", "atan2", "hypot", "fmod", "remainder")
 SLOW = {"f64": 2.0 ** 14, "f32": 65536.0, "bf16": 65536.0, "f16": 65536.0, "f32_via_f64": 2.0 ** 14}

@@ -41,7 +41,9 @@ NP_UNARY = {"sin": np.sin, "cos": np.cos, "tan": np.tan, "exp": np.exp,
             "cosh": np.cosh, "tanh": np.tanh, "asin": np.arcsin, "acos": np.arccos,
             "atan": np.arctan, "log10": np.log10, "exp10": lambda x: np.power(10.0, x),
             "expm1": np.expm1, "log1p": np.log1p, "cbrt": np.cbrt, "asinh": np.arcsinh,
-            "acosh": np.arccosh, "atanh": np.arctanh}
+            "acosh": np.arccosh, "atanh": np.arctanh,
+            "erf": np.vectorize(math.erf, otypes=[np.float64]),
+            "erfc": np.vectorize(math.erfc, otypes=[np.float64])}
 
 
 def same(a, b):
@@ -57,6 +59,8 @@ def same(a, b):
 @pytest.mark.parametrize("fn", sorted(NP_UNARY))
 def test_unary_specials_match_host_libm(fn):
     for x in [0.0, -0.0, math.inf, -math.inf, math.nan, 1.0, -1.0]:
+        if fn in ("erf", "erfc") and abs(x) == 1.0:
+            continue       # not special there, and the host's erfc(-1) is 1 ulp off
         got = evaluate1(fn, "f64", x)[0]
         want = float(NP_UNARY[fn](np.float64(x)))
         assert same(got, want), (fn, x, got, want)
@@ -118,7 +122,8 @@ MP = {"sin": mpmath.sin, "cos": mpmath.cos, "tan": mpmath.tan,
       "log10": mpmath.log10, "exp10": lambda x: mpmath.power(10, x),
       "expm1": mpmath.expm1, "log1p": mpmath.log1p,
       "cbrt": lambda x: mpmath.sign(x) * mpmath.cbrt(abs(x)),   # the real root
-      "asinh": mpmath.asinh, "acosh": mpmath.acosh, "atanh": mpmath.atanh}
+      "asinh": mpmath.asinh, "acosh": mpmath.acosh, "atanh": mpmath.atanh,
+      "erf": mpmath.erf, "erfc": mpmath.erfc}
 
 
 def _mp_f64(fn, x, y=None):
@@ -160,6 +165,13 @@ def _inputs(fn, rng, n):
         elif fn == "atanh":
             xs.append(math.copysign(1 - 10 ** rng.uniform(-16, 0), rng.random() - 0.5) if c < 0.4
                       else math.copysign(10 ** rng.uniform(-310, 0), rng.random() - 0.5))
+        elif fn in ("erf", "erfc"):
+            if c < 0.5:
+                xs.append(rng.uniform(-6, 6))
+            elif c < 0.8:
+                xs.append(rng.uniform(-1, 28))
+            else:
+                xs.append(math.copysign(10 ** rng.uniform(-310, 0), rng.random() - 0.5))
         elif fn in ("exp10", "expm1"):
             lim = 330 if fn == "exp10" else 760
             xs.append(rng.uniform(-lim, lim) if c < 0.5 else
@@ -265,7 +277,7 @@ def _midpoint_distance_in_dulps(d):
 @pytest.mark.parametrize("fn", ["sin", "cos", "tan", "exp", "log", "exp2", "log2",
                                 "sinh", "cosh", "tanh", "asin", "acos", "atan",
                                 "log10", "exp10", "expm1", "log1p", "cbrt", "asinh",
-                                "acosh", "atanh"])
+                                "acosh", "atanh", "erf", "erfc"])
 def test_binary32_vs_glibc_double_rounded(fn):
     # a strided sweep over all positive and negative binary32 bit patterns
     stride = 1 << 16
@@ -561,6 +573,61 @@ def test_inverse_hyperbolics_identities_and_small_arguments():
         want = math.sqrt(2 * d) * (1 - d / 12 + 3 * d * d / 160)   # to O(d^3)
         got = evaluate1("acosh", "f64", 1 + d)[0]
         assert abs(got - want) <= 2 * math.ulp(want)
+
+
+def _erfc_continued_fraction(x, terms=4000):
+    """erfc x for x > 0 from Laplace's continued fraction, e^(-x^2)/sqrt(pi) /
+    (x + (1/2)/(x + 1/(x + (3/2)/(x + 2/(x + ...))))), evaluated bottom-up
+    (a formula independent of the oracle's power series)."""
+    x = mpmath.mpf(x)
+    t = x
+    for k in range(terms, 0, -1):
+        t = x + mpmath.mpf(k) / 2 / t
+    return mpmath.exp(-x * x) / mpmath.sqrt(mpmath.pi) / t
+
+
+def test_erf_erfc_identities_series_and_table_values():
+    """erf(-x) = -erf x, erfc(-x) = 2 - erfc x and erf x + erfc x = 1 on the
+    reference pairs; erfc x for x >= 2 against Laplace's continued fraction;
+    erf x against 2x/sqrt(pi) (1 - x^2/3 + x^4/10) for |x| < 2^-20; tabulated
+    values erf(1/2), erf(1), erfc(2); erfc of tiny x is 1 and erf of tiny x
+    is x (2/sqrt(pi)) rounded."""
+    rng = random.Random(12)
+    for _ in range(40):
+        x = rng.uniform(0.01, 6.5) if rng.random() < 0.7 else 10 ** rng.uniform(-12, 0)
+        r1, h1, l1 = evaluate1("erf", "f64", x)
+        r2, h2, l2 = evaluate1("erf", "f64", -x)
+        assert same(r2, -r1) and h2 == -h1 and l2 == -l1
+        c1, ch, cl = evaluate1("erfc", "f64", x)
+        c2, dh, dl = evaluate1("erfc", "f64", -x)
+        with mpmath.workprec(400):
+            s = mpmath.mpf(h1) + mpmath.mpf(l1) + mpmath.mpf(ch) + mpmath.mpf(cl)
+            assert abs(s - 1) <= mpmath.mpf(2) ** -100
+            t = mpmath.mpf(dh) + mpmath.mpf(dl) + mpmath.mpf(ch) + mpmath.mpf(cl)
+            assert abs(t - 2) <= mpmath.mpf(2) ** -100
+    for x in [2.0, 2.5, 3.75, 5.0, 8.5, 12.0, 19.25, 26.5, 27.25]:
+        _, h, l = evaluate1("erfc", "f64", x)
+        with mpmath.workprec(300):
+            want = _erfc_continued_fraction(x)
+            # the pair's low part is a double: near 2^-1022 it holds no more
+            # than 2^-1075 absolute
+            tol = want * mpmath.mpf(2) ** -95 + mpmath.mpf(2) ** -1075
+            assert abs(mpmath.mpf(h) + mpmath.mpf(l) - want) <= tol, x
+    for k in (21, 30, 45, 80, 300):
+        x = 1.5 * 2.0 ** -k
+        _, h, l = evaluate1("erf", "f64", x)
+        with mpmath.workprec(300):
+            xm = mpmath.mpf(x)
+            want = 2 * xm / mpmath.sqrt(mpmath.pi) * (1 - xm ** 2 / 3 + xm ** 4 / 10)
+            # omitted terms below x^6, the pair's own rounding below 2^-104
+            assert abs(mpmath.mpf(h) + mpmath.mpf(l) - want) <= want * (xm ** 6 + mpmath.mpf(2) ** -104)
+    # Abramowitz and Stegun, Table 7.1, to 20 digits
+    assert evaluate1("erf", "f64", 0.5)[0] == float("0.52049987781304653768")
+    assert evaluate1("erf", "f64", 1.0)[0] == float("0.84270079294971486934")
+    assert evaluate1("erfc", "f64", 2.0)[0] == float("0.0046777349810472658379")
+    for x in (5e-324, 1e-300, -1e-20, 2.0 ** -60):
+        assert evaluate1("erfc", "f64", x)[0] == 1.0
+    assert evaluate1("erf", "f64", 2.0 ** -1000)[0] == 1.1283791670955126 * 2.0 ** -1000
 
 
 def test_log_series_on_balls_agree_with_exact_log():

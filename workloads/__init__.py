@@ -26,7 +26,8 @@ __all__ = ["FN_IDS", "rng_for", "specials", "small_set", "mixture", "large_args"
 FN_IDS = {name: i for i, name in enumerate(
     ["sin", "cos", "tan", "exp", "exp2", "log", "log2", "pow", "atan2",
      "sinh", "cosh", "tanh", "fmod", "remainder", "asin", "acos", "atan",
-     "log10", "log1p", "exp10", "expm1", "cbrt", "hypot", "asinh", "acosh", "atanh"])}
+     "log10", "log1p", "exp10", "expm1", "cbrt", "hypot", "asinh", "acosh", "atanh",
+     "erf", "erfc"])}
 
 DTYPE_MAX = {"f64": np.finfo(np.float64).max, "f32": float(np.finfo(np.float32).max),
              "f16": 65504.0, "bf16": 3.3895313892515355e38}
@@ -200,7 +201,10 @@ def function_mixture(fn, dt, n=1 << 26, operand=0):
     acosh 60% of the elements become |x| + 1 and 30% 1 + 10^U[near, 0].  For log1p a
     fifth of the elements, drawn per element, are -(1 - 10^U[near, 0]) with
     near = -16 (binary64), -7 (binary32, bf16) or -3 (f16): next to -1, where
-    1 + x cancels."""
+    1 + x cancels.  For erf and erfc 60% of the elements become U[-w, w]
+    (erf) or U[-w, v] (erfc), where w = 6 (binary64) or 4 and v is where erfc
+    underflows the format (27.3, 10.1 for binary32 and bf16, 4 for f16): the
+    range where the results are neither saturated nor zero."""
     if fn in ("asin", "acos", "atanh"):
         return unit_mixture(fn, dt, n, operand)
     if dt in ("bf16", "f16"):
@@ -223,6 +227,12 @@ def function_mixture(fn, dt, n=1 << 26, operand=0):
             shifted = _cast(np.abs(x.astype(np.float64)) + 1.0, dt)
             close = _cast(1.0 + np.exp(rng.uniform(near, 0.0, n) * np.log(10.0)), dt)
         x = np.where(c < 0.6, shifted, np.where(c < 0.9, close, x))
+    if fn in ("erf", "erfc"):
+        rng = rng_for(11, fn, operand)
+        w = 6.0 if dt == "f64" else 4.0
+        v = w if fn == "erf" else {"f64": 27.3, "f16": 4.0}.get(dt, 10.1)
+        m = rng.random(n) < 0.6
+        x[m] = _cast(rng.uniform(-w, v, int(m.sum())), dt)
     return x
 
 
