@@ -283,6 +283,25 @@ libm_hip_status libm_hip_eval(libm_hip_fn fn, libm_hip_variant v, libm_hip_dtype
                               void* stream);
 
 /* ------------------------------------------------------------------------
+ * Bit-consistent form (the paper's bit-wise consistent functions, Section
+ * 3.3): the same evaluators with every primitive an IEEE operation with a
+ * defined result (correctly rounded division and square root in place of
+ * the hardware reciprocal, reciprocal square root and log2/exp2 estimates;
+ * a seed for x^(-1/3) from fused multiply-adds only) and every element on
+ * its own path.  Its results equal, bit for bit, those of the host build of
+ * the same source, libm_hip_host_eval (libm_hip_host.h), so a CPU can
+ * reproduce them.  Arguments and status as for libm_hip_eval, with t
+ * LIBM_HIP_F64 or LIBM_HIP_F32 only (others: LIBM_HIP_ERR_UNSUPPORTED);
+ * every (fn, v) of the library is served.  Same accuracy bounds and special
+ * values as the default entry points, which may differ from it in the last
+ * bit of some results; one plain kernel (an element per lane), slower than
+ * the default entry points.
+ * ---------------------------------------------------------------------- */
+libm_hip_status libm_hip_consistent_eval(libm_hip_fn fn, libm_hip_variant v, libm_hip_dtype t,
+                                         const void* a, const void* b, void* out, size_t n,
+                                         void* stream);
+
+/* ------------------------------------------------------------------------
  * Launch-shape autotuner (not part of the paper).  Every entry point except
  * the trigonometric ones (whose kernel gathers Payne-Hanek lanes through a
  * queue sized to a 256-lane workgroup) launches with a (workgroup size,

@@ -21,7 +21,7 @@ __all__ = ["load", "library_path", "UNARY", "BINARY", "VARIANTS", "entry_name",
            "call", "evaluate", "sin", "cos", "tan", "exp", "exp2", "log", "log2",
            "sinh", "cosh", "tanh", "asin", "acos", "atan", "log10", "log1p", "exp10",
            "expm1", "cbrt", "asinh", "acosh", "atanh", "erf", "erfc", "sincos", "pow", "atan2", "hypot", "fmod", "remainder",
-           "LibmHipError"]
+           "consistent", "host_consistent", "LibmHipError"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBNAME = "libm_hip.so"
@@ -123,6 +123,9 @@ def load():
         f.restype = ctypes.c_int
         f.argtypes = [vp, vp, vp, sz, vp] if fn in BWD_UNARY else [vp, vp, vp, vp, vp, sz, vp]
     lib.libm_hip_eval.restype = ctypes.c_int
+    lib.libm_hip_consistent_eval.restype = ctypes.c_int
+    lib.libm_hip_consistent_eval.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp,
+                                             vp, sz, vp]
     lib.libm_hip_eval.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp, sz, vp]
     _lib = lib
     return lib
@@ -419,3 +422,90 @@ def tune_load(path):
 
 def tune_reset():
     _tune_lib().libm_hip_tune_reset()
+
+
+# ---------------------------------------------------------------------------
+# bit-consistent form: libm_hip_consistent_eval on the GPU and the host build
+# of the same evaluators (libm_hip_host.so), whose results are bit-identical
+# ---------------------------------------------------------------------------
+_HOSTLIB = "libm_hip_host.so"
+_host = None
+
+
+def host_library_path():
+    return os.path.join(_HERE, _HOSTLIB)
+
+
+def load_host():
+    """Load libm_hip_host.so (raises if it has not been built)."""
+    global _host
+    if _host is not None:
+        return _host
+    path = host_library_path()
+    if not os.path.exists(path):
+        raise LibmHipError("libm_hip_host.so not found at %s; run "
+                           "python -m paper_2001_09258_amd.build" % path)
+    lib = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    lib.libm_hip_host_eval.restype = ctypes.c_int
+    lib.libm_hip_host_eval.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp,
+                                       ctypes.c_size_t]
+    _host = lib
+    return lib
+
+
+def _consistent_args(fn, variant):
+    if fn not in FN_CODES or fn in ("sincos",):
+        raise ValueError("unknown function %s" % fn)
+    if variant is None:
+        variant = VARIANTS[fn][0]
+    if variant not in VARIANTS[fn]:
+        raise ValueError("%s has no variant %s" % (fn, variant))
+    return FN_CODES[fn], VARIANT_CODES[variant]
+
+
+def consistent(fn, a, b=None, variant=None, out=None):
+    """fn over float64/float32 device tensors in the bit-consistent form (the
+    same bits as ``host_consistent`` on the host)."""
+    import torch
+    lib = load()
+    f, v = _consistent_args(fn, variant)
+    if not a.is_cuda:
+        raise ValueError("libm_hip evaluates device tensors only")
+    tag = {torch.float64: "f64", torch.float32: "f32"}.get(a.dtype)
+    if tag is None:
+        raise TypeError("the bit-consistent form takes float64 or float32")
+    a = a.contiguous()
+    if fn in BINARY:
+        if b is None or b.shape != a.shape or b.dtype != a.dtype or b.device != a.device:
+            raise ValueError("binary functions need two tensors of equal shape, dtype, device")
+        b = b.contiguous()
+    out = torch.empty_like(a) if out is None else out
+    with torch.cuda.device(a.device):
+        st = lib.libm_hip_consistent_eval(f, v, DTYPE_CODES[tag], a.data_ptr(),
+                                          None if b is None else b.data_ptr(), out.data_ptr(),
+                                          a.numel(), _stream_handle())
+    _check(st, "libm_hip_consistent_eval")
+    return out
+
+
+def host_consistent(fn, a, b=None, variant=None):
+    """fn over float64/float32 numpy arrays on the host, bit-identical to
+    ``consistent`` on the GPU (the host build of the same evaluators)."""
+    import numpy as np
+    lib = load_host()
+    f, v = _consistent_args(fn, variant)
+    a = np.ascontiguousarray(a)
+    tag = {np.dtype(np.float64): "f64", np.dtype(np.float32): "f32"}.get(a.dtype)
+    if tag is None:
+        raise TypeError("the bit-consistent form takes float64 or float32")
+    if fn in BINARY:
+        b = np.ascontiguousarray(b, dtype=a.dtype)
+        if b.shape != a.shape:
+            raise ValueError("binary functions need two arrays of equal shape")
+    out = np.empty_like(a)
+    st = lib.libm_hip_host_eval(f, v, DTYPE_CODES[tag], a.ctypes.data,
+                                None if b is None else b.ctypes.data, out.ctypes.data, a.size)
+    if st != 0:
+        raise LibmHipError("libm_hip_host_eval failed with status %d" % st)
+    return out

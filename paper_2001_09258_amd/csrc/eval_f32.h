@@ -839,14 +839,14 @@ LMH_INLINE float erfcf_u10(float x) {
 }
 
 // cbrt in binary64: a = m 2^i in [0.5, 4) as for binary64, one Newton step
-// on the hardware estimate (~2^-43), y = a z^2 rounded once to binary32
+// on rcbrt_seed (~2^-43 or better), y = a z^2 rounded once to binary32
 LMH_INLINE float cbrtf_u10(float x) {
   double ax = fabs_((double)x);
   double m = frexp_mant_(ax);
   int e = frexp_exp_(ax);
   int q = (e + 1200) / 3 - 400;
   double a = ldexp_(m, e - 3 * q);
-  double z = (double)exp2_est_(log2_est_((float)a) * (-1.0f / 3.0f));
+  double z = rcbrt_seed(a);
   z = fma_(z * THIRD_D_H, fma_(-a, z * z * z, 1.0), z);
   float r = (float)ldexp_(a * (z * z), q);
   r = copysign_(r, x);

@@ -10,19 +10,23 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include "abi_util.h"
 #include "kernels.h"
 #include "../../include/libm_hip.h"
 
-namespace {
-using namespace lmh_ops;
-using namespace lmh_kernels;
-
+namespace lmh_abi {
 thread_local char g_last_error[256] = "";
 
 void set_error(const char* msg) {
   strncpy(g_last_error, msg, sizeof(g_last_error) - 1);
   g_last_error[sizeof(g_last_error) - 1] = 0;
 }
+}  // namespace lmh_abi
+
+namespace {
+using namespace lmh_ops;
+using namespace lmh_kernels;
+using lmh_abi::set_error;
 
 // ---------------------------------------------------------------------------
 // launch configurations (autotuned)
@@ -231,7 +235,7 @@ libm_hip_status launch_ternary2(const void* a, const void* b, const void* c, voi
 // ---------------------------------------------------------------------------
 extern "C" {
 
-const char* libm_hip_last_error(void) { return g_last_error; }
+const char* libm_hip_last_error(void) { return lmh_abi::g_last_error; }
 const char* libm_hip_version(void) { return "libm_hip 0.1 (gfx950)"; }
 
 #define LMH_KEY(FN, V, T) tune_key(LIBM_HIP_##FN, LIBM_HIP_##V, LIBM_HIP_##T)

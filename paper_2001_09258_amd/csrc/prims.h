@@ -7,6 +7,15 @@
 // the same small set -- FMA, round-to-integer, mantissa/exponent extraction
 // and conditional moves (Section 3.1, sub-features) -- so the evaluators stay
 // branch-free except where a wave may skip a whole path no lane needs.
+//
+// Two builds share the evaluators.  The default one uses the hardware
+// reciprocal, reciprocal square root and log2/exp2 estimates as the starting
+// points of Newton steps.  With LMH_BITWISE_CONSISTENT defined, every
+// primitive is an IEEE operation with one defined result (division and square
+// root correctly rounded, a seed for x^(-1/3) from FMAs only), so the same
+// evaluator source gives the same bits wherever it is compiled: on the GPU
+// and, with LMH_HOST_SCALAR also defined, as a plain C++ build for the host
+// (the paper's bit-consistent functions, Section 3.3).
 #pragma once
 #include <stdint.h>
 
@@ -15,6 +24,10 @@
 // (honoured under the default -ffp-contract; an explicit
 // -ffp-contract=fast overrides it and changes results).
 #pragma STDC FP_CONTRACT OFF
+
+#ifdef LMH_HOST_SCALAR
+#include "prims_host.h"
+#else
 
 #define LMH_INLINE __device__ __forceinline__
 
@@ -38,15 +51,6 @@ LMH_INLINE double frexp_mant_(double x) { return __builtin_amdgcn_frexp_mant(x);
 LMH_INLINE float frexp_mant_(float x) { return __builtin_amdgcn_frexp_mantf(x); }
 LMH_INLINE int frexp_exp_(double x) { return __builtin_amdgcn_frexp_exp(x); }
 LMH_INLINE int frexp_exp_(float x) { return __builtin_amdgcn_frexp_expf(x); }
-// hardware reciprocal estimate (refined by the callers with Newton steps)
-LMH_INLINE double rcp_(double x) { return __builtin_amdgcn_rcp(x); }
-LMH_INLINE float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
-// hardware reciprocal square root estimate (refined by Newton steps)
-LMH_INLINE double rsq_(double x) { return __builtin_amdgcn_rsq(x); }
-// hardware base-2 logarithm and exponential estimates (v_log_f32, v_exp_f32,
-// about 22 correct bits): only ever the starting point of Newton steps
-LMH_INLINE float log2_est_(float x) { return __builtin_amdgcn_logf(x); }
-LMH_INLINE float exp2_est_(float x) { return __builtin_amdgcn_exp2f(x); }
 LMH_INLINE bool isnan_(double x) { return __builtin_isnan(x); }
 LMH_INLINE bool isnan_(float x) { return __builtin_isnan(x); }
 LMH_INLINE bool isinf_(double x) { return __builtin_isinf(x); }
@@ -63,9 +67,46 @@ LMH_INLINE float as_f32(int32_t x) { return __builtin_bit_cast(float, x); }
 // to end a loop once every lane is done; the loop body stays exec-masked)
 LMH_INLINE bool any_lane(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
 
+}  // namespace lmh
+#endif  // LMH_HOST_SCALAR
+
+namespace lmh {
+
 // the neighbour of a positive finite x towards zero (x > 0, not subnormal 0)
 LMH_INLINE double pred_(double x) { return as_f64(as_i64(x) - 1); }
 LMH_INLINE float pred_(float x) { return as_f32(as_i32(x) - 1); }
+
+#ifdef LMH_BITWISE_CONSISTENT
+// 1/x and 1/sqrt(x) as correctly rounded IEEE operations (the callers' Newton
+// steps then leave them unchanged or move them by the same defined amount)
+LMH_INLINE double rcp_(double x) { return 1.0 / x; }
+LMH_INLINE float rcp_(float x) { return 1.0f / x; }
+LMH_INLINE double rsq_(double x) { return 1.0 / __builtin_sqrt(x); }
+// a^(-1/3) for a in [0.5, 4) to about 2^-43: a = m 2^i with m in [0.5, 1)
+// and i in {0, 1, 2}; (1.49978 - 0.513 m) is within 1.33 % of m^(-1/3),
+// times 2^(-i/3), then three Newton steps z += z (1 - a z^3)/3 (each squares
+// the relative error and doubles it)
+LMH_INLINE double rcbrt_seed(double a) {
+  double m = frexp_mant_(a);
+  int i = frexp_exp_(a);
+  double k = i == 0 ? 1.0 : (i == 1 ? 0x1.965fea53d6e3dp-1 : 0x1.428a2f98d728bp-1);
+  double z = fma_(m, -0.513, 1.499777789099392) * k;
+  for (int it = 0; it < 3; ++it) z = fma_(z * (1.0 / 3.0), fma_(-a, z * z * z, 1.0), z);
+  return z;
+}
+#else
+// hardware reciprocal estimate (refined by the callers with Newton steps)
+LMH_INLINE double rcp_(double x) { return __builtin_amdgcn_rcp(x); }
+LMH_INLINE float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+// hardware reciprocal square root estimate (refined by Newton steps)
+LMH_INLINE double rsq_(double x) { return __builtin_amdgcn_rsq(x); }
+// a^(-1/3) for a in [0.5, 4) from the hardware base-2 logarithm and
+// exponential estimates (v_log_f32, v_exp_f32; about 22 correct bits), the
+// starting point of the callers' Newton steps
+LMH_INLINE double rcbrt_seed(double a) {
+  return (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf((float)a) * (-1.0f / 3.0f));
+}
+#endif
 
 }  // namespace lmh
 

@@ -10,13 +10,13 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
+def _declared(only=None):
     """Functions declared by the C-ABI headers (those with an extern "C"
     block; libm_hip_device.h holds device functions only and exports
-    nothing)."""
+    nothing), optionally of one header only."""
     names = set()
     for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
-        if not h.endswith(".h"):
+        if not h.endswith(".h") or (only is not None and h != only):
             continue
         with open(os.path.join(ROOT, "include", h)) as fh:
             if 'extern "C"' not in fh.read():
@@ -25,6 +25,11 @@ def _declared():
                              check=True, capture_output=True, text=True).stdout
         names |= set(re.findall(r"\b(libm_hip_\w+)\s*\(", out))
     return names
+
+
+# libm_hip_host.h declares the host library's entry point (and includes
+# libm_hip.h, whose names the GPU library exports)
+HOST_ONLY = {"libm_hip_host_eval"}
 
 
 def test_header_declares_the_expected_surface():
@@ -41,8 +46,24 @@ def test_library_exports_every_declared_symbol():
     if not os.path.exists(path):
         pytest.fail("libm_hip.so is not built (run __graft_entry__.build())")
     lib = ctypes.CDLL(path)
-    missing = [n for n in sorted(_declared()) if not hasattr(lib, n)]
+    assert _declared("libm_hip_host.h") - _declared("libm_hip.h") == HOST_ONLY
+    missing = [n for n in sorted(_declared() - HOST_ONLY) if not hasattr(lib, n)]
     assert not missing, missing
+
+
+def test_host_library_exports_its_entry_point_and_validates():
+    import paper_2001_09258_amd as L
+    path = L.host_library_path()
+    if not os.path.exists(path):
+        pytest.fail("libm_hip_host.so is not built (run __graft_entry__.build())")
+    lib = L.load_host()
+    assert all(hasattr(lib, n) for n in HOST_ONLY)
+    f = lib.libm_hip_host_eval
+    assert f(L.FN_CODES["exp"], 0, 0, None, None, None, 0) == 0        # n == 0
+    assert f(L.FN_CODES["exp"], 0, 0, None, None, None, 5) == 1        # NULL, n > 0
+    assert f(L.FN_CODES["exp"], 0, 2, None, None, None, 5) == 2        # bf16: unsupported
+    assert f(L.FN_CODES["exp"], 1, 0, None, None, None, 5) == 2        # exp u35: not served
+    assert f(99, 0, 0, None, None, None, 5) == 2
 
 
 def test_binding_mirrors_entry_points():

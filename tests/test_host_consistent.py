@@ -1,0 +1,60 @@
+"""The host build of the bit-consistent evaluators (libm_hip_host.so) meets
+the same bounds as the GPU entry points against the oracle: 1.0 ULP (u10),
+3.5 ULP (u35), exact fmod/remainder, Annex F special values bit-exact.  It
+runs on the CPU; the GPU half of the bit-identity check is
+test_gpu_consistent.py.  This also pins the bit-consistent primitives
+(IEEE division and square root in place of the hardware estimates, the
+FMA-only x^(-1/3) seed of cbrt)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests.ulp import compare
+
+import paper_2001_09258_amd as L
+
+N = 400
+KINDS = [(fn, v, dt) for fn in L.UNARY + L.BINARY for v in L.VARIANTS[fn]
+         for dt in ("f64", "f32")]
+BOUND = {"u10": 1.0, "u35": 3.5, "exact": 0.0}
+
+
+def _inputs(fn, dt, operand):
+    a = W.function_mixture(fn, dt, N, 500 + operand)
+    sp = W.specials(dt)
+    a[:sp.size] = sp
+    return a
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    try:
+        L.load_host()
+    except L.LibmHipError as e:
+        pytest.fail(str(e))
+
+
+@pytest.mark.parametrize("fn,v,dt", KINDS, ids=["-".join(k) for k in KINDS])
+def test_host_consistent_within_bound(fn, v, dt):
+    npdt = np.float64 if dt == "f64" else np.float32
+    a = _inputs(fn, dt, 0)
+    b = _inputs(fn, dt, 1)[::-1].copy() if fn in L.BINARY else None
+    y = L.host_consistent(fn, a.astype(npdt), None if b is None else b.astype(npdt), v)
+    rn, hi, lo = oracle.evaluate(fn, dt, a, b)
+    r = compare(y.astype(np.float64), rn, hi, lo, dt, BOUND[v])
+    bad = r["bad_idx"][:4]
+    assert r["violations"] == 0 and r["special_mismatch"] == 0, \
+        "%s %s %s: x=%r y=%r want %r (max %.3f ulp)" % (fn, v, dt, a[bad], y[bad], rn[bad],
+                                                       r["max_ulp"])
+
+
+def test_cbrt_consistent_seed_over_the_reduced_range():
+    """cbrt on a dense grid of the reduced argument range [0.5, 4) and its
+    scalings, where the FMA-only seed and its Newton steps run."""
+    m = np.linspace(0.5, 4.0, 3001)[:-1]
+    x = np.concatenate([m, m * 2.0 ** 300, m * 2.0 ** -1050, -m * 2.0 ** -600])
+    y = L.host_consistent("cbrt", x)
+    rn, hi, lo = oracle.evaluate("cbrt", "f64", x)
+    r = compare(y, rn, hi, lo, "f64", 1.0)
+    assert r["violations"] == 0 and r["special_mismatch"] == 0, r["max_ulp"]
