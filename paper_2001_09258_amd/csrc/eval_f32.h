@@ -402,14 +402,9 @@ LMH_INLINE fff logf_ff(float a) {
   return dd2_add2(el, l);
 }
 
-LMH_INLINE float powf_u10(float x, float y) {
+// the Annex F values of pow around r = |x|^y (as in the binary64 form)
+LMH_INLINE float powf_annexf(float x, float y, float r) {
   float ax = fabs_(x);
-  fff lg = logf_ff(ax);
-  fff w = dd2_mul(lg, y);
-  float k;
-  fff e = expf_ff(w, k);
-  float r = ff_ldexp(e, (int)k);                   // overflows / underflows itself
-  // Annex F as in the binary64 form
   bool yint = rint_(y) == y;
   bool yodd = fabs_(fma_(-2.0f, rint_(0.5f * y), y)) == 1.0f;
   bool xneg = __builtin_signbit(x);
@@ -421,6 +416,16 @@ LMH_INLINE float powf_u10(float x, float y) {
   r = isinf_(y) ? (ax == 1.0f ? 1.0f : ymag) : r;
   r = (isnan_(x) || isnan_(y)) ? __builtin_nanf("") : r;
   return (y == 0.0f || x == 1.0f) ? 1.0f : r;
+}
+
+LMH_INLINE float powf_u10(float x, float y) {
+  float ax = fabs_(x);
+  fff lg = logf_ff(ax);
+  fff w = dd2_mul(lg, y);
+  float k;
+  fff e = expf_ff(w, k);
+  float r = ff_ldexp(e, (int)k);                   // overflows / underflows itself
+  return powf_annexf(x, y, r);
 }
 
 // binary32 forms of atan_poly / atan_ratio (the extra reduction above

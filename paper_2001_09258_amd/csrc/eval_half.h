@@ -1,0 +1,203 @@
+// Evaluators for data stored as bf16 or f16 (not in the paper, which covers
+// binary64 and binary32): the input widened exactly to binary32, arithmetic
+// in binary32 sized for the narrow formats, one rounding to the format at the
+// end (by the storage type).  A bf16 or f16 result within 1.0 ULP needs the
+// binary32 value within about 2^-12 relative (half an f16 ulp, with the
+// final rounding's half ulp on top); every evaluator here stays below 2^-17,
+// so the short polynomials and the binary32 transcendental unit (v_exp_f32,
+// v_log_f32, v_rcp_f32, each within about one binary32 ulp) suffice where the
+// binary32 evaluators spend double-length arithmetic.  Both formats have
+// 65536 bit patterns; every one is checked against the oracle.
+//
+//   exp, exp2, log, log2, sinh, cosh, tanh: for bf16 and f16 (any binary32
+//     value of those formats, bf16 subnormals included);
+//   pow: for bf16 and f16, 2^(y log2|x|) with the binary32 Annex F selects;
+//   sin, cos, tan, sincos: one Cody-Waite reduction by pi/2 below |x| =
+//     65536 (every finite f16), the binary32 kernels' Payne-Hanek reduction
+//     above (bf16 only), the same short polynomials after either.
+#pragma once
+#include "eval_f32.h"
+
+#pragma STDC FP_CONTRACT OFF
+
+namespace lmh {
+
+// 2^t: v_exp_f32, with results below the binary32 normal range formed as
+// 2^(t + 64) 2^-64 (one rounding into the subnormal range, 16 bits finer
+// than bf16's)
+LMH_INLINE float nexp2_core(float t) {
+  bool lo = t < -125.0f;
+  float y = exp2_hw(lo ? t + 64.0f : t);
+  return lo ? ldexp_(y, -64) : y;
+}
+
+// e^x = 2^(x log2 e): the product's rounding moves the result by at most
+// ln2 |t| 2^-24 relative (2^-17.2 at the bf16 underflow, t = -134)
+LMH_INLINE float nexp(float x) { return nexp2_core(x * INVLN2_F_H); }
+
+// 2^x; for an integer x the exact power of two, so that the results which
+// are ties of the narrow formats' rounding (2^-25 in f16, 2^-134 in bf16)
+// never hang on the last bit of v_exp_f32
+LMH_INLINE float nexp2(float x) {
+  float k = rint_(x);
+  float c = k < -160.0f ? -160.0f : (k > 160.0f ? 160.0f : k);
+  float y = nexp2_core(x);
+  return x == k ? ldexp_(1.0f, (int)c) : y;
+}
+
+// log2 x from v_log_f32; binary32 subnormals (bf16 subnormals) of either
+// sign are scaled by 2^64 first (v_log_f32 reads a subnormal as a zero of its
+// sign, which would make log of a negative subnormal -inf instead of NaN).
+// 0 -> -inf, negative -> NaN, inf -> inf.
+LMH_INLINE float nlog2_core(float x) {
+  bool sub = x != 0.0f && fabs_(x) < 0x1p-126f;
+  float l = log2_hw(sub ? x * 0x1p64f : x);
+  return sub ? l - 64.0f : l;
+}
+
+// log(1 + s) for |s| < 1/16 (s = x - 1 is exact there): Taylor to s^6, the
+// omitted terms below s^6/7 < 2^-27 relative.  Near 1 the logarithm is small
+// and an absolute error of v_log_f32 would be a large relative one.
+LMH_INLINE float nlog1p_small(float s) {
+  float p = fma_(s, fma_(s, fma_(s, fma_(s, -1.0f / 6.0f, 0.2f), -0.25f), 1.0f / 3.0f), -0.5f);
+  return fma_(s * s, p, s);
+}
+
+LMH_INLINE float nlog(float x) {
+  float s = x - 1.0f;
+  float l = nlog2_core(x) * LN2_F_H;
+  return fabs_(s) < 0.0625f ? nlog1p_small(s) : l;
+}
+
+LMH_INLINE float nlog2(float x) {
+  float s = x - 1.0f;
+  float l = nlog2_core(x);
+  return fabs_(s) < 0.0625f ? nlog1p_small(s) * INVLN2_F_H : l;
+}
+
+// pow: t = y log2|x| with log2 within about 2^-21 relative (nlog2: the
+// transcendental unit, or the series next to 1), so t is off by at most
+// |t| 2^-20.9; a finite nonzero bf16 result has |t| < 134, an f16 one
+// |t| < 25, so 2^t is within 2^-12.3 (bf16) and 2^-14.8 (f16) relative.
+// Zeros, infinities, NaN, negative bases and the exact cases of Annex F come
+// from the binary32 form's selects.
+LMH_INLINE float npow(float x, float y) {
+  float t = y * nlog2(fabs_(x));
+  return powf_annexf(x, y, nexp2_core(t));
+}
+
+// e^a / 2 for a >= 0 (inf from a = 89.42 up)
+LMH_INLINE float nexp_half(float a) { return exp2_hw(fma_(a, INVLN2_F_H, -1.0f)); }
+
+// cosh x = e^|x|/2 + (1/4) / (e^|x|/2): a sum of positive terms
+LMH_INLINE float ncosh(float x) {
+  float e = nexp_half(fabs_(x));
+  return e + 0.25f * rcp_hw(e);
+}
+
+// sinh: below |x| = 1/2 the Taylor series to x^5 (omitted terms below
+// 2^-18.4 relative), above e^|x|/2 - (1/4) / (e^|x|/2), which cancels by at
+// most a factor 1.6
+LMH_INLINE float nsinh(float x) {
+  float a = fabs_(x);
+  float z = a * a;
+  float p = fma_(a * z, fma_(z, 1.0f / 120.0f, 1.0f / 6.0f), a);
+  float e = nexp_half(a);
+  float big = e - 0.25f * rcp_hw(e);
+  return copysign_(a < 0.5f ? p : big, x);
+}
+
+// tanh: below |x| = 0.55 the Taylor series to x^11 (omitted terms below
+// 2^-18 relative); above 1 - 2 / (e^(2|x|) + 1), which does not cancel there
+// (tanh 0.55 > 1/2) and reaches 1 once 2 / (e^(2|x|) + 1) is below half an ulp
+LMH_INLINE float ntanh(float x) {
+  float a = fabs_(x);
+  float z = a * a;
+  float p = fma_(z, fma_(z, fma_(z, fma_(z, -1382.0f / 155925.0f, 62.0f / 2835.0f),
+                                  -17.0f / 315.0f), 2.0f / 15.0f), -1.0f / 3.0f);
+  float small = fma_(a * z, p, a);
+  float u = exp2_hw(a * (2.0f * INVLN2_F_H));
+  float big = 1.0f - 2.0f * rcp_hw(u + 1.0f);
+  return copysign_(a < 0.55f ? small : big, x);
+}
+
+// ---- f16 trigonometry ----------------------------------------------------
+// k = rint(x 2/pi), r = x - k pi/2 by the binary32 kernels' Cody-Waite
+// reduction in binary64 (valid for |x| < 65536, which holds every finite
+// f16): r is within 2^-24 relative of the exact reduced argument, whose
+// magnitude over all f16 arguments is at least 2^-16 (x = 177.5).  inf and
+// NaN give a NaN r.
+LMH_INLINE Trig32 hsincos_reduce(float x) {
+  float k = rint_(x * TWO_OVER_PI_F);
+  return Trig32{cwf_reduce(x, k, PIH_FD_0, PIH_FD_1), k};
+}
+
+// sin r and cos r for |r| <= pi/4 (a little more after k's rounding): Taylor
+// to r^7 and to r^8 (omitted terms below 2^-20.9 and 2^-24 relative)
+LMH_INLINE float hsin_poly(float r) {
+  float z = r * r;
+  return fma_(r * z, fma_(z, fma_(z, -1.0f / 5040.0f, 1.0f / 120.0f), -1.0f / 6.0f), r);
+}
+LMH_INLINE float hcos_poly(float r) {
+  float z = r * r;
+  return fma_(z, fma_(z, fma_(z, fma_(z, 1.0f / 40320.0f, -1.0f / 720.0f), 1.0f / 24.0f), -0.5f),
+              1.0f);
+}
+
+// m = j mod 4 from q = j - 4 rint(j/4) in {-2, -1, 0, 1, 2} (exact: |j| is
+// below 2^16); odd m takes the other polynomial, m in {2, 3} the sign
+LMH_INLINE float hsin_finish(Trig32 s) {
+  float r = s.r.hi;
+  float q = s.j - 4.0f * rint_(s.j * 0.25f);
+  bool odd = fabs_(q) == 1.0f;
+  bool neg = fabs_(q) == 2.0f || q == -1.0f;
+  float v = odd ? hcos_poly(r) : hsin_poly(r);
+  return neg ? -v : v;
+}
+
+// tan: sin r / cos r (m even) or -cos r / sin r (m odd), each through the
+// reciprocal unit (r = 0 only with m = 0)
+LMH_INLINE float htan_finish(Trig32 s) {
+  float r = s.r.hi;
+  float q = s.j - 4.0f * rint_(s.j * 0.25f);
+  bool odd = fabs_(q) == 1.0f;
+  float sn = hsin_poly(r), cs = hcos_poly(r);
+  return odd ? -cs * rcp_hw(sn) : sn * rcp_hw(cs);
+}
+
+// sin x = sin(r + m pi/2), cos x = sin(r + (m + 1) pi/2); sin(+-0) and
+// tan(+-0) keep the sign of zero.  The state is either reduction's.
+LMH_INLINE float nsin_fin(float x, Trig32 s) {
+  float v = hsin_finish(s);
+  return x == 0.0f ? x : v;
+}
+LMH_INLINE float ncos_fin(float, Trig32 s) {
+  s.j += 1.0f;
+  return hsin_finish(s);
+}
+LMH_INLINE float ntan_fin(float x, Trig32 s) {
+  float v = htan_finish(s);
+  return x == 0.0f ? x : v;
+}
+
+// f16: every finite argument is below 65536
+LMH_INLINE float hsin(float x) { return nsin_fin(x, hsincos_reduce(x)); }
+LMH_INLINE float hcos(float x) { return ncos_fin(x, hsincos_reduce(x)); }
+LMH_INLINE float htan(float x) { return ntan_fin(x, hsincos_reduce(x)); }
+
+// bf16: from 65536 up (and for inf and NaN) the binary32 Payne-Hanek
+// reduction, whose state (r = x - k pi/2 as a pair, k mod 4, NaN r for a
+// non-finite x) has the same meaning
+LMH_INLINE bool nbtrig_slow(float x) { return !(fabs_(x) < 65536.0f); }
+LMH_INLINE Trig32 nbtrig_reduce(float x) {
+  Trig32 s;
+  if (nbtrig_slow(x))
+    s = tanf_slow(x);
+  else
+    s = hsincos_reduce(x);
+  return s;
+}
+
+}  // namespace lmh
+
+#pragma STDC FP_CONTRACT DEFAULT

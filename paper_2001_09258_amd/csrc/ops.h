@@ -6,6 +6,7 @@
 
 #include "eval_f64.h"
 #include "eval_f32.h"
+#include "eval_half.h"
 #include "eval_grad.h"
 #pragma STDC FP_CONTRACT OFF
 
@@ -212,43 +213,123 @@ __device__ __forceinline__ void store_nt(const P& v, void* dst) {
 template <class S>
 constexpr int ept_for() { return 16 / (int)sizeof(S); }
 
-// The evaluator an (element type, function) pair runs.  bf16 and f16 go
-// through binary32 and f32_via_f64 through binary64: the wider type carries
-// at least 13 more bits (bf16: 16, f16: 13, binary32 from binary64: 29), so
-// its 3.5-ULP evaluator, rounded once, is within 0.5 + 3.5 * 2^-13 ULP of the
+// Evaluators of the narrow formats (eval_half.h): binary32 only
+#define LMH_OPN(NAME, FN)                                                            \
+  struct NAME {                                                                    \
+    static constexpr bool kSplit = false;                                          \
+    static __device__ __forceinline__ float f(float x) { return lmh::FN(x); }      \
+  };
+LMH_OPN(OpNExp, nexp)
+LMH_OPN(OpNExp2, nexp2)
+LMH_OPN(OpNLog, nlog)
+LMH_OPN(OpNLog2, nlog2)
+LMH_OPN(OpNSinh, nsinh)
+LMH_OPN(OpNCosh, ncosh)
+LMH_OPN(OpNTanh, ntanh)
+LMH_OPN(OpHSin, hsin)
+LMH_OPN(OpHCos, hcos)
+LMH_OPN(OpHTan, htan)
+#undef LMH_OPN
+struct OpNPow {
+  static __device__ __forceinline__ float f(float x, float y) { return lmh::npow(x, y); }
+};
+// bf16 trig in the split kernel's interface (Payne-Hanek lanes gathered)
+#define LMH_NTRIG_OP(NAME, FIN)                                                                  \
+  struct NAME {                                                                                \
+    static constexpr bool kSplit = true;                                                       \
+    static __device__ __forceinline__ float f(float x) { return lmh::FIN(x, lmh::nbtrig_reduce(x)); } \
+    static __device__ __forceinline__ bool is_slow(float x) { return lmh::nbtrig_slow(x); }     \
+    static __device__ __forceinline__ lmh::Trig32 fast(float x) { return lmh::hsincos_reduce(x); } \
+    static __device__ __forceinline__ lmh::Trig32 slow(float x) { return lmh::tanf_slow(x); }   \
+    static __device__ __forceinline__ float finish(float x, lmh::Trig32 s) { return lmh::FIN(x, s); } \
+  };
+LMH_NTRIG_OP(OpNSin, nsin_fin)
+LMH_NTRIG_OP(OpNCos, ncos_fin)
+LMH_NTRIG_OP(OpNTan, ntan_fin)
+#undef LMH_NTRIG_OP
+// sincos of the narrow formats in the split kernel's interface: the state of
+// cos is sin's with the quadrant advanced by one inside ncos_fin, so the
+// results are the bits of the sin and cos evaluators.  SLOW: whether the
+// Payne-Hanek reduction is ever needed (bf16) or never (f16).
+template <bool SLOW>
+struct OpNSinCos {
+  static __device__ __forceinline__ bool is_slow(float x) { return SLOW && lmh::nbtrig_slow(x); }
+  static __device__ __forceinline__ lmh::SinCos32 fast(float x) {
+    lmh::Trig32 s = lmh::hsincos_reduce(x);
+    return lmh::SinCos32{s, s};
+  }
+  static __device__ __forceinline__ lmh::Trig32 slow(float x) { return lmh::tanf_slow(x); }
+  static __device__ __forceinline__ lmh::SinCos32 lift(float, lmh::Trig32 s) {
+    return lmh::SinCos32{s, s};
+  }
+  static __device__ __forceinline__ float finish_sin(float x, lmh::SinCos32 s) {
+    return lmh::nsin_fin(x, s.s);
+  }
+  static __device__ __forceinline__ float finish_cos(float x, lmh::SinCos32 s) {
+    return lmh::ncos_fin(x, s.c);
+  }
+  static __device__ __forceinline__ void f(float x, float& s, float& c) {
+    lmh::Trig32 st = SLOW ? lmh::nbtrig_reduce(x) : lmh::hsincos_reduce(x);
+    s = lmh::nsin_fin(x, st);
+    c = lmh::ncos_fin(x, st);
+  }
+};
+
+// The evaluator an (element type, function) pair runs.  f32_via_f64 goes
+// through binary64, bf16 and f16 through binary32: the wider type carries at
+// least 13 more bits (bf16: 16, f16: 13, binary32 from binary64: 29), so its
+// 3.5-ULP evaluator, rounded once, is within 0.5 + 3.5 * 2^-13 ULP of the
 // exact result in the narrow format, inside the 1.0-ULP bound; it is used
-// wherever it exists.  Every path (entry points, dispatcher, batched kernel,
-// device API) maps through this, so they agree bit for bit.
+// wherever it exists.  Where a narrow-format evaluator exists (eval_half.h),
+// bf16 and f16 run that instead.  Every path (entry points, dispatcher,
+// batched kernel, device API) maps through this, so they agree bit for bit.
 template <class Io, class Op>
 struct EvalOp {
   typedef Op type;
 };
-#define LMH_NARROW_EVAL(OP10, OP35)                   \
+#define LMH_EVAL_AS(IO, OP, AS)                       \
   template <>                                         \
-  struct EvalOp<IoBF16, OP10> {                       \
-    typedef OP35 type;                                \
-  };                                                  \
-  template <>                                         \
-  struct EvalOp<IoF16, OP10> {                        \
-    typedef OP35 type;                                \
-  };                                                  \
-  template <>                                         \
-  struct EvalOp<IoF32ViaF64, OP10> {                  \
-    typedef OP35 type;                                \
+  struct EvalOp<IO, OP> {                             \
+    typedef AS type;                                  \
   };
-LMH_NARROW_EVAL(OpSinU10, OpSinU35)
-LMH_NARROW_EVAL(OpCosU10, OpCosU35)
-LMH_NARROW_EVAL(OpTanU10, OpTanU35)
-LMH_NARROW_EVAL(OpSinCosU10, OpSinCosU35)
-LMH_NARROW_EVAL(OpLogU10, OpLogU35)
+#define LMH_NARROW_EVAL(OP10, OP35)                   \
+  LMH_EVAL_AS(IoBF16, OP10, OP35)                     \
+  LMH_EVAL_AS(IoF16, OP10, OP35)                      \
+  LMH_EVAL_AS(IoF32ViaF64, OP10, OP35)
+#define LMH_WIDE_AND_HALF(OP10, OP35, OPN)            \
+  LMH_EVAL_AS(IoBF16, OP10, OPN)                      \
+  LMH_EVAL_AS(IoF16, OP10, OPN)                       \
+  LMH_EVAL_AS(IoF32ViaF64, OP10, OP35)
+#define LMH_HALF_ONLY(OP10, OPN)                      \
+  LMH_EVAL_AS(IoBF16, OP10, OPN)                      \
+  LMH_EVAL_AS(IoF16, OP10, OPN)
+// trig: f16 in a plain kernel (no element needs Payne-Hanek), bf16 in the
+// split kernel
+#define LMH_TRIG_EVAL(OP10, OP35, OPB, OPH)           \
+  LMH_EVAL_AS(IoBF16, OP10, OPB)                      \
+  LMH_EVAL_AS(IoF16, OP10, OPH)                       \
+  LMH_EVAL_AS(IoF32ViaF64, OP10, OP35)
+LMH_TRIG_EVAL(OpSinU10, OpSinU35, OpNSin, OpHSin)
+LMH_TRIG_EVAL(OpCosU10, OpCosU35, OpNCos, OpHCos)
+LMH_TRIG_EVAL(OpTanU10, OpTanU35, OpNTan, OpHTan)
+LMH_TRIG_EVAL(OpSinCosU10, OpSinCosU35, OpNSinCos<true>, OpNSinCos<false>)
+LMH_WIDE_AND_HALF(OpLogU10, OpLogU35, OpNLog)
+LMH_WIDE_AND_HALF(OpSinhU10, OpSinhU35, OpNSinh)
+LMH_WIDE_AND_HALF(OpCoshU10, OpCoshU35, OpNCosh)
+LMH_WIDE_AND_HALF(OpTanhU10, OpTanhU35, OpNTanh)
+LMH_HALF_ONLY(OpExpU10, OpNExp)
+LMH_HALF_ONLY(OpExp2U10, OpNExp2)
+LMH_HALF_ONLY(OpLog2U10, OpNLog2)
+LMH_HALF_ONLY(OpPowU10, OpNPow)
 LMH_NARROW_EVAL(OpAsinU10, OpAsinU35)
 LMH_NARROW_EVAL(OpAcosU10, OpAcosU35)
 LMH_NARROW_EVAL(OpAtanU10, OpAtanU35)
-LMH_NARROW_EVAL(OpSinhU10, OpSinhU35)
-LMH_NARROW_EVAL(OpCoshU10, OpCoshU35)
-LMH_NARROW_EVAL(OpTanhU10, OpTanhU35)
 LMH_NARROW_EVAL(OpAtan2U10, OpAtan2U35)
 #undef LMH_NARROW_EVAL
+#undef LMH_WIDE_AND_HALF
+#undef LMH_HALF_ONLY
+#undef LMH_TRIG_EVAL
+#undef LMH_EVAL_AS
 
 }  // namespace lmh_ops
 

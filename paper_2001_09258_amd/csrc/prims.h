@@ -63,6 +63,14 @@ LMH_INLINE double as_f64(int64_t x) { return __builtin_bit_cast(double, x); }
 LMH_INLINE int32_t as_i32(float x) { return __builtin_bit_cast(int32_t, x); }
 LMH_INLINE float as_f32(int32_t x) { return __builtin_bit_cast(float, x); }
 
+// the transcendental unit in binary32: v_exp_f32 (2^x), v_log_f32 (log2 x)
+// and v_rcp_f32 (1/x), each within about one binary32 ulp.  Only the
+// narrow-format evaluators use them as results (their error is far below a
+// bf16 or f16 ulp, and every bf16 and f16 input is tested); the GPU build only
+LMH_INLINE float exp2_hw(float x) { return __builtin_amdgcn_exp2f(x); }
+LMH_INLINE float log2_hw(float x) { return __builtin_amdgcn_logf(x); }
+LMH_INLINE float rcp_hw(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // true if the predicate holds on any active lane of the wavefront (used only
 // to end a loop once every lane is done; the loop body stays exec-masked)
 LMH_INLINE bool any_lane(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }

@@ -22,7 +22,7 @@ import numpy as np
 import pytest
 import scipy.special as sps
 
-from tests.gpu_common import run_gpu, run_oracle, BOUND
+from tests.gpu_common import run_gpu, run_oracle, to_device, to_host, BOUND
 from tests.ulp import compare
 
 pytestmark = pytest.mark.gpu
@@ -136,3 +136,32 @@ def test_narrow_all_patterns(fn, dt):
         "%s %s: x=%r y=%r want %r (max %.3f ulp)" % (fn, dt, x[bad], y[bad], rn[bad],
                                                     res["max_ulp"])
     print("all %s patterns %s: max %.3f ulp" % (dt, fn, res["max_ulp"]), flush=True)
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+def test_narrow_pow_pairs(dt):
+    """pow on 2^18 pairs of the format: half random bit patterns for both
+    operands, half bases within 20 % of 1 with exponents U[-40, 40] rounded
+    to 0.1 (the region where y log2 x stays finite and is most sensitive to
+    the logarithm's accuracy), against the oracle."""
+    n = 1 << 18
+    rng = np.random.default_rng(17)
+    bits = rng.integers(0, 1 << 16, size=(2, n)).astype(np.uint32)
+    if dt == "bf16":
+        pat = (bits << 16).view(np.float32).astype(np.float64)
+    else:
+        pat = bits.astype(np.uint16).view(np.float16).astype(np.float64)
+    near = rng.random(n) < 0.5
+    x = np.where(near, 1.0 + rng.uniform(-0.2, 0.2, n), pat[0])
+    y = np.where(near, np.round(rng.uniform(-40.0, 40.0, n), 1), pat[1])
+    base = {"bf16": "bf16", "f16": "f16"}[dt]
+    x = to_host(to_device(x, base))          # exact values of the format
+    y = to_host(to_device(y, base))
+    r = run_gpu("pow", "u10", dt, x, y)
+    rn, hi, lo = run_oracle("pow", dt, x, y)
+    res = compare(r, rn, hi, lo, dt, 1.0)
+    bad = res["bad_idx"][:4]
+    assert res["violations"] == 0 and res["special_mismatch"] == 0, \
+        "pow %s: x=%r y=%r got %r want %r (max %.3f ulp)" % (dt, x[bad], y[bad], r[bad], rn[bad],
+                                                           res["max_ulp"])
+    print("pow %s pairs: max %.3f ulp" % (dt, res["max_ulp"]), flush=True)
