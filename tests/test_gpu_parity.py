@@ -207,3 +207,22 @@ def test_full_size_sampled(fn, variant, dt):
     rn, hi, lo = run_oracle(fn, dt, a[idx], None if b is None else b[idx])
     res = compare(y[idx], rn, hi, lo, dt, BOUND[variant])
     assert res["violations"] == 0 and res["special_mismatch"] == 0, res
+
+
+FULL_NARROW = [("sin", "f16"), ("exp", "bf16"), ("tan", "bf16")]
+
+
+@pytest.mark.parametrize("fn,dt", FULL_NARROW, ids=["-".join(c) for c in FULL_NARROW])
+def test_full_size_sampled_narrow(fn, dt):
+    """2^28 bf16/f16 elements (the narrow formats' benchmark size) through the
+    narrow-format evaluators; 4096 sampled outputs checked against the
+    oracle one by one."""
+    n = 1 << 28
+    a = W.narrow_mixture(fn, dt, n, 0)
+    print("full size", fn, dt, flush=True)
+    y = run_gpu(fn, "u10", dt, a)
+    idx = np.concatenate([np.random.default_rng(6).integers(0, n, 4096), [0, n - 1]])
+    from tests.ulp import compare
+    rn, hi, lo = run_oracle(fn, dt, a[idx])
+    res = compare(y[idx], rn, hi, lo, dt, 1.0)
+    assert res["violations"] == 0 and res["special_mismatch"] == 0, res
