@@ -32,11 +32,15 @@
  * Element types: f64 = double, f32 = float, bf16 and f16 = uint16_t bit
  * patterns of bfloat16 / IEEE binary16 (evaluated in binary32 and rounded to
  * nearest-even once).  "f32_via_f64" variants take and return float but
- * evaluate in binary64 and round once.  These forms run the wider type's
- * 3.5-ULP evaluator where the function has one (sin, cos, tan, sincos, log,
- * asin, acos, atan, atan2, sinh, cosh, tanh), else its 1.0-ULP one: the
- * wider type carries at least 13 more bits, so the result is within
- * 0.5 + 3.5 * 2^-13 ULP of the exact value in the narrow format.
+ * evaluate in binary64 and round once.  bf16 and f16 run evaluators sized
+ * for those formats where they exist (exp, exp2, log, log2, pow, sinh, cosh,
+ * tanh; sin, cos, tan and sincos: binary32 arithmetic with short series and
+ * the transcendental unit, every one of the 65536 inputs of each format
+ * within 1.0 ULP); otherwise these forms run the wider type's 3.5-ULP
+ * evaluator where the function has one (asin, acos, atan, atan2, and for
+ * f32_via_f64 also sin, cos, tan, sincos, log, sinh, cosh, tanh), else its
+ * 1.0-ULP one: the wider type carries at least 13 more bits, so the result
+ * is within 0.5 + 3.5 * 2^-13 ULP of the exact value in the narrow format.
  */
 #ifndef LIBM_HIP_H
 #define LIBM_HIP_H
