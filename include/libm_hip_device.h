@@ -25,10 +25,12 @@
  * Every function is a pure function of its arguments: no memory, no state,
  * no errno or flags; special values follow C99 Annex F as the entry points
  * do.  Accuracy: *_u10 within 1.0 ULP, *_u35 within 3.5 ULP, fmod and
- * remainder exact; bf16/f16 forms evaluate in binary32 and _via_f64 forms in
- * binary64 (with the 3.5-ULP evaluator where one exists, which the extra
- * bits of the wider type keep within 0.5 + 3.5 * 2^-13 ULP of the narrow
- * result) and round once.
+ * remainder exact; bf16/f16 forms evaluate in binary32 (with the evaluators
+ * sized for those formats where they exist, else the 3.5-ULP binary32 one
+ * where it exists) and _via_f64 forms in binary64 (with the 3.5-ULP
+ * evaluator where one exists, which the extra bits of the wider type keep
+ * within 0.5 + 3.5 * 2^-13 ULP of the narrow result), and round once; each
+ * gives the bits of the corresponding entry point.
  * The *_bwd functions return the vector-Jacobian product g * f'(x) (two
  * partials for pow and atan2) as the backward entry points do.
  */
