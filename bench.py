@@ -404,6 +404,48 @@ def extra_functions(lib, L, stream, n, reps, ops, kinds):
     return res
 
 
+def extra_large_args(lib, L, stream, n, reps, ops):
+    """The large-argument workload on 2^26 elements: sin, cos, tan (u10,
+    u35) on half sign * 10^U[5, log10 max] and half near multiples of pi/2
+    (almost every element takes Payne-Hanek), fmod and remainder on operands
+    log-uniform over the whole range (long quotient loops); binary64 and
+    binary32.  Trig kernels get the step's roofline fractions; the remainder
+    loops' work depends on the operands, so they get time and HBM only."""
+    import numpy as np
+    import torch
+    import workloads as W
+    sh = stream.cuda_stream
+    res = {}
+    kinds = [(fn, v) for fn in ("sin", "cos", "tan") for v in ("u10", "u35")]
+    kinds += [("fmod", "exact"), ("remainder", "exact")]
+    for fn, var in kinds:
+        binary = fn in L.BINARY
+        for dt in ("f64", "f32"):
+            a = W.large_args(fn, dt, n, 0)
+            ta = torch.from_numpy(a).cuda()
+            to = torch.empty_like(ta)
+            nm = L.entry_name(fn, var, dt)
+            if binary:
+                tb = torch.from_numpy(W.large_args(fn, dt, n, 1)).cuda()
+                args = (ta.data_ptr(), tb.data_ptr(), to.data_ptr(), n, sh)
+            else:
+                tb = None
+                args = (ta.data_ptr(), to.data_ptr(), n, sh)
+            ms = time_launches(stream, [checked(lib, nm, getattr(lib, nm), *args)], reps)[0]
+            nb = ESIZE[dt] * (3 if binary else 2)
+            r = {"ms": round(ms, 4), "gelem_s": round(n / ms / 1e6, 2),
+                 "hbm_frac": round(nb * n / HBM_PEAK / (ms * 1e-3), 4)}
+            if not binary:
+                vo, v64, slow = valu_ops(fn, var, dt, a, ops)
+                slots = max(v64, vo / 2)
+                r.update({"payne_hanek_share": round(float(slow), 4), "valu_per_elem": vo,
+                          "valu_f64_per_elem": v64,
+                          "alu_frac": round(slots * n / VALU_SLOTS / (ms * 1e-3), 4)})
+            res["%s_%s_%s" % (fn, var, dt)] = r
+            del ta, tb, to
+    return res
+
+
 def extra_sincos(lib, L, stream, n, reps):
     """sincos u10 (one pass, two outputs) against sin u10 and cos u10 launched
     separately, on the same 2^26-element mixture (binary64, binary32)."""
@@ -678,6 +720,7 @@ def main():
         result["c99_functions"] = extra_functions(lib, L, stream, n, args.reps, ops, C99_EXTRA)
         result["u35_forms"] = extra_functions(lib, L, stream, n, args.reps, ops, U35_EXTRA)
         result["sincos"] = extra_sincos(lib, L, stream, n, args.reps)
+        result["large_args"] = extra_large_args(lib, L, stream, n, args.reps, ops)
         result["trig_sorted_by_path"] = extra_sorted_paths(lib, L, stream, host, n, args.reps)
         with open(OPS_FILE) as fh:
             result["small_set_f64_warm"] = extra_small_set(lib, L, stream, args.reps, json.load(fh))
