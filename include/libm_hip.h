@@ -206,6 +206,11 @@ LIBM_HIP_DECL_SINCOS(u35, float, f32)
  *   digits (Section 5, "FP Remainder", Algorithm 1, Appendices B and C),
  *   extended to quotients beyond DBL_MAX.  remainder rounds the quotient to
  *   nearest-even (IEEE 754).
+ * fdim(x, y), fmax(x, y), fmin(x, y): exact (C99 F.9.9; the paper shows
+ *   fdim as a masking example, Section 2): fdim is x - y rounded once when
+ *   x > y, else +0, NaN if either argument is NaN; fmax / fmin return the
+ *   larger / smaller argument, the other one when one is NaN, NaN when both
+ *   are; -0 counts as smaller than +0 (C99 leaves that order open).
  * ---------------------------------------------------------------------- */
 #define LIBM_HIP_DECL_BINARY(fn, var, T, tag)                                              \
   libm_hip_status libm_hip_##fn##var##_##tag(const T* a, const T* b, T* out, size_t n,     \
@@ -231,6 +236,12 @@ LIBM_HIP_DECL_BINARY(fmod, , double, f64)
 LIBM_HIP_DECL_BINARY(fmod, , float, f32)
 LIBM_HIP_DECL_BINARY(remainder, , double, f64)
 LIBM_HIP_DECL_BINARY(remainder, , float, f32)
+LIBM_HIP_DECL_BINARY(fdim, , double, f64)
+LIBM_HIP_DECL_BINARY(fdim, , float, f32)
+LIBM_HIP_DECL_BINARY(fmax, , double, f64)
+LIBM_HIP_DECL_BINARY(fmax, , float, f32)
+LIBM_HIP_DECL_BINARY(fmin, , double, f64)
+LIBM_HIP_DECL_BINARY(fmin, , float, f32)
 
 /* ------------------------------------------------------------------------
  * Backward (vector-Jacobian products) for autograd; not part of the paper.
@@ -273,7 +284,7 @@ typedef enum {
   LIBM_HIP_ASIN, LIBM_HIP_ACOS, LIBM_HIP_ATAN,
   LIBM_HIP_LOG10, LIBM_HIP_LOG1P, LIBM_HIP_EXP10, LIBM_HIP_EXPM1, LIBM_HIP_CBRT,
   LIBM_HIP_HYPOT, LIBM_HIP_ASINH, LIBM_HIP_ACOSH, LIBM_HIP_ATANH,
-  LIBM_HIP_ERF, LIBM_HIP_ERFC,
+  LIBM_HIP_ERF, LIBM_HIP_ERFC, LIBM_HIP_FDIM, LIBM_HIP_FMAX, LIBM_HIP_FMIN,
   LIBM_HIP_NUM_FN
 } libm_hip_fn;
 typedef enum { LIBM_HIP_U10 = 0, LIBM_HIP_U35 = 1, LIBM_HIP_EXACT = 2 } libm_hip_variant;

@@ -169,6 +169,13 @@ __device__ __forceinline__ double remainder(double x, double y) {
 __device__ __forceinline__ float remainder(float x, float y) {
   return lmh_ops::OpRemainder::f(x, y);
 }
+/* fdim, fmax, fmin (C99 F.9.9), exact; -0 ordered below +0 */
+__device__ __forceinline__ double fdim(double x, double y) { return lmh_ops::OpFdim::f(x, y); }
+__device__ __forceinline__ float fdim(float x, float y) { return lmh_ops::OpFdim::f(x, y); }
+__device__ __forceinline__ double fmax(double x, double y) { return lmh_ops::OpFmax::f(x, y); }
+__device__ __forceinline__ float fmax(float x, float y) { return lmh_ops::OpFmax::f(x, y); }
+__device__ __forceinline__ double fmin(double x, double y) { return lmh_ops::OpFmin::f(x, y); }
+__device__ __forceinline__ float fmin(float x, float y) { return lmh_ops::OpFmin::f(x, y); }
 
 /* backward: g * f'(x) */
 #define LIBM_HIP_DEVICE_BWD(NAME, FN)                                                     \

@@ -26,6 +26,12 @@ fmod is n - d*trunc(n/d) and remainder is n - d*rint_even(n/d); both results
 are exactly representable, so the oracle computes them with exact integer
 arithmetic (Section 5, "FP Remainder", Algorithm 1's postcondition).
 
+fdim, fmax, fmin are C99 functions of the library's set (Section 1) that the
+paper only shows as a masking example: fdim(x, y) is x - y rounded when
+x > y, else +0; fmax/fmin return the larger/smaller argument, the other one
+if one is NaN, NaN if both are (F.9.9).  C99 leaves the order of -0 and +0
+open; here -0 < +0 (fmax(-0, +0) = +0, fmin(-0, +0) = -0).
+
 Besides the rounded value the oracle returns a high-precision approximation of
 the exact value as a pair of binary64 numbers (hi, lo), from which the tests
 compute ULP errors.
@@ -49,7 +55,7 @@ UNARY = ("sin", "cos", "tan", "exp", "exp2", "log", "log2",
          "sinh", "cosh", "tanh", "asin", "acos", "atan",
          "log10", "exp10", "expm1", "log1p", "cbrt", "asinh", "acosh", "atanh",
          "erf", "erfc")
-BINARY = ("pow", "atan2", "fmod", "remainder", "hypot")
+BINARY = ("pow", "atan2", "fmod", "remainder", "hypot", "fdim", "fmax", "fmin")
 
 
 class OracleError(RuntimeError):
@@ -759,6 +765,28 @@ def evaluate1(fn, fmt_name, x, y=None):
         if r * r == S:                                # also |x| when y = 0
             return _exact_result(r, e // 2, fmt)
         return _ziv(_ball_hypot, (x, y), fmt, prec0)
+    if fn == "fdim":
+        if math.isnan(x) or math.isnan(y):
+            return NAN, NAN, 0.0
+        if not x > y:
+            return 0.0, 0.0, 0.0
+        if math.isinf(x) or math.isinf(y):            # x = +inf or y = -inf
+            return INF, INF, 0.0
+        (nx, dx), (ny, dy) = x.as_integer_ratio(), y.as_integer_ratio()
+        d = max(dx, dy)                               # powers of two
+        num = nx * (d // dx) - ny * (d // dy)
+        v = rn_dyadic(num, -(d.bit_length() - 1), fmt)
+        return v, v, 0.0
+    if fn in ("fmax", "fmin"):
+        if math.isnan(x):
+            return y, y, 0.0
+        if math.isnan(y):
+            return x, x, 0.0
+        # order: -0 before +0; otherwise the numeric order
+        kx = (x, math.copysign(1.0, x))
+        ky = (y, math.copysign(1.0, y))
+        v = (x if kx >= ky else y) if fn == "fmax" else (x if kx <= ky else y)
+        return v, v, 0.0
     if fn in ("fmod", "remainder"):
         sp = _special_fmod(x, y)
         if sp is not None:

@@ -20,7 +20,8 @@ import os
 __all__ = ["load", "library_path", "UNARY", "BINARY", "VARIANTS", "entry_name",
            "call", "evaluate", "sin", "cos", "tan", "exp", "exp2", "log", "log2",
            "sinh", "cosh", "tanh", "asin", "acos", "atan", "log10", "log1p", "exp10",
-           "expm1", "cbrt", "asinh", "acosh", "atanh", "erf", "erfc", "sincos", "pow", "atan2", "hypot", "fmod", "remainder",
+           "expm1", "cbrt", "asinh", "acosh", "atanh", "erf", "erfc", "sincos", "pow", "atan2",
+           "hypot", "fmod", "remainder", "fdim", "fmax", "fmin",
            "consistent", "host_consistent", "LibmHipError"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -29,14 +30,16 @@ _LIBNAME = "libm_hip.so"
 UNARY = ("sin", "cos", "tan", "exp", "exp2", "log", "log2", "sinh", "cosh", "tanh",
          "asin", "acos", "atan", "log10", "log1p", "exp10", "expm1", "cbrt", "asinh",
          "acosh", "atanh", "erf", "erfc")
-BINARY = ("pow", "atan2", "hypot", "fmod", "remainder")
+BINARY = ("pow", "atan2", "hypot", "fmod", "remainder", "fdim", "fmax", "fmin")
+EXACT = ("fmod", "remainder", "fdim", "fmax", "fmin")
 # accuracy variants served per function
 VARIANTS = {fn: ("u10",) for fn in UNARY + ("pow", "atan2", "hypot")}
 VARIANTS.update({"sin": ("u10", "u35"), "cos": ("u10", "u35"), "tan": ("u10", "u35"),
                  "asin": ("u10", "u35"), "acos": ("u10", "u35"), "atan": ("u10", "u35"),
                  "log": ("u10", "u35"), "atan2": ("u10", "u35"), "sinh": ("u10", "u35"),
                  "cosh": ("u10", "u35"), "tanh": ("u10", "u35"),
-                 "fmod": ("exact",), "remainder": ("exact",)})
+                 "fmod": ("exact",), "remainder": ("exact",), "fdim": ("exact",),
+                 "fmax": ("exact",), "fmin": ("exact",)})
 DTYPES = ("f64", "f32", "bf16", "f16", "f32_via_f64")
 
 
@@ -49,7 +52,7 @@ def library_path():
 
 
 def entry_name(fn, variant, dtype):
-    if fn in ("fmod", "remainder"):
+    if fn in EXACT:
         return "libm_hip_%s_%s" % (fn, dtype)
     return "libm_hip_%s_%s_%s" % (fn, variant, dtype)
 
@@ -58,7 +61,7 @@ def served(fn, variant, dtype):
     """True if the library exports this combination."""
     if variant not in VARIANTS.get(fn, ()):
         return False
-    if fn in ("fmod", "remainder"):
+    if fn in EXACT:
         return dtype in ("f64", "f32")
     if variant == "u35":
         return dtype in ("f64", "f32")
@@ -271,6 +274,21 @@ def remainder(x, y, out=None):
     return evaluate("remainder", x, y, "exact", out)
 
 
+def fdim(x, y, out=None):
+    """C fdim(x, y) elementwise: x - y if x > y, else +0."""
+    return evaluate("fdim", x, y, "exact", out)
+
+
+def fmax(x, y, out=None):
+    """C fmax(x, y) elementwise (NaN-ignoring; -0 below +0)."""
+    return evaluate("fmax", x, y, "exact", out)
+
+
+def fmin(x, y, out=None):
+    """C fmin(x, y) elementwise (NaN-ignoring; -0 below +0)."""
+    return evaluate("fmin", x, y, "exact", out)
+
+
 def backward(fn, inputs, gout, outs=None):
     """Raw backward call: ``inputs`` are the saved forward inputs (C order),
     ``gout`` the upstream gradient; returns the input gradient(s)."""
@@ -303,7 +321,8 @@ FN_CODES = {"sin": 0, "cos": 1, "tan": 2, "exp": 3, "exp2": 4, "log": 5, "log2":
             "pow": 7, "atan2": 8, "sinh": 9, "cosh": 10, "tanh": 11, "fmod": 12,
             "remainder": 13, "asin": 14, "acos": 15, "atan": 16, "log10": 17,
             "log1p": 18, "exp10": 19, "expm1": 20, "cbrt": 21, "hypot": 22, "asinh": 23,
-            "acosh": 24, "atanh": 25, "erf": 26, "erfc": 27}
+            "acosh": 24, "atanh": 25, "erf": 26, "erfc": 27, "fdim": 28, "fmax": 29,
+            "fmin": 30}
 VARIANT_CODES = {"u10": 0, "u35": 1, "exact": 2}
 DTYPE_CODES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "f32_via_f64": 4}
 

@@ -931,6 +931,25 @@ LMH_INLINE float remainderf_f32(float x, float y) {
   return r;
 }
 
+// fdim, fmax, fmin (C99 functions of the paper's set, Section 1, shown there
+// only as a masking example): fdim(x, y) = x - y (one rounding) when x > y,
+// else +0, NaN if either is NaN; fmax / fmin pick the larger / smaller
+// argument, the other one when one is NaN, with -0 ordered below +0
+LMH_INLINE float fdimf_f32(float x, float y) {
+  float d = x > y ? x - y : 0.0f;
+  return (isnan_(x) || isnan_(y)) ? __builtin_nanf("") : d;
+}
+LMH_INLINE float fmaxf_f32(float x, float y) {
+  bool zeros = x == 0.0f && y == 0.0f;
+  float r = (x > y || isnan_(y)) ? x : y;
+  return zeros ? (__builtin_signbit(x) ? y : x) : r;
+}
+LMH_INLINE float fminf_f32(float x, float y) {
+  bool zeros = x == 0.0f && y == 0.0f;
+  float r = (x < y || isnan_(y)) ? x : y;
+  return zeros ? (__builtin_signbit(x) ? x : y) : r;
+}
+
 }  // namespace lmh
 
 #pragma STDC FP_CONTRACT DEFAULT

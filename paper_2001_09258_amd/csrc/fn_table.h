@@ -29,4 +29,6 @@
   X(POW, U10, pow_u10, powf_u10)                                                      \
   X(ATAN2, U10, atan2_u10, atan2f_u10) X(ATAN2, U35, atan2_u35, atan2f_u35)           \
   X(HYPOT, U10, hypot_u10, hypotf_u10)                                                \
-  X(FMOD, EXACT, fmod_f64, fmodf_f32) X(REMAINDER, EXACT, remainder_f64, remainderf_f32)
+  X(FMOD, EXACT, fmod_f64, fmodf_f32) X(REMAINDER, EXACT, remainder_f64, remainderf_f32)     \
+  X(FDIM, EXACT, fdim_f64, fdimf_f32) X(FMAX, EXACT, fmax_f64, fmaxf_f32)                     \
+  X(FMIN, EXACT, fmin_f64, fminf_f32)

@@ -351,6 +351,12 @@ LMH_DEF_BINARY(hypot, _u10, IoF16, uint16_t, f16, OpHypotU10, LMH_KEY(HYPOT, U10
 LMH_DEF_BINARY(hypot, _u10, IoF32ViaF64, float, f32_via_f64, OpHypotU10, LMH_KEY(HYPOT, U10, F32_VIA_F64))
 LMH_DEF_BINARY(fmod, , IoF64, double, f64, OpFmod, LMH_KEY(FMOD, EXACT, F64))
 LMH_DEF_BINARY(fmod, , IoF32, float, f32, OpFmod, LMH_KEY(FMOD, EXACT, F32))
+LMH_DEF_BINARY(fdim, , IoF64, double, f64, OpFdim, LMH_KEY(FDIM, EXACT, F64))
+LMH_DEF_BINARY(fdim, , IoF32, float, f32, OpFdim, LMH_KEY(FDIM, EXACT, F32))
+LMH_DEF_BINARY(fmax, , IoF64, double, f64, OpFmax, LMH_KEY(FMAX, EXACT, F64))
+LMH_DEF_BINARY(fmax, , IoF32, float, f32, OpFmax, LMH_KEY(FMAX, EXACT, F32))
+LMH_DEF_BINARY(fmin, , IoF64, double, f64, OpFmin, LMH_KEY(FMIN, EXACT, F64))
+LMH_DEF_BINARY(fmin, , IoF32, float, f32, OpFmin, LMH_KEY(FMIN, EXACT, F32))
 LMH_DEF_BINARY(remainder, , IoF64, double, f64, OpRemainder, LMH_KEY(REMAINDER, EXACT, F64))
 LMH_DEF_BINARY(remainder, , IoF32, float, f32, OpRemainder, LMH_KEY(REMAINDER, EXACT, F32))
 
@@ -512,6 +518,15 @@ extern "C" libm_hip_status libm_hip_eval(libm_hip_fn fn, libm_hip_variant v, lib
       break;
     case LIBM_HIP_REMAINDER:
       if (v == LIBM_HIP_EXACT) return dispatch_binary<OpRemainder>(t, a, b, out, n, s, false, key);
+      break;
+    case LIBM_HIP_FDIM:
+      if (v == LIBM_HIP_EXACT) return dispatch_binary<OpFdim>(t, a, b, out, n, s, false, key);
+      break;
+    case LIBM_HIP_FMAX:
+      if (v == LIBM_HIP_EXACT) return dispatch_binary<OpFmax>(t, a, b, out, n, s, false, key);
+      break;
+    case LIBM_HIP_FMIN:
+      if (v == LIBM_HIP_EXACT) return dispatch_binary<OpFmin>(t, a, b, out, n, s, false, key);
       break;
     default: break;
   }

@@ -172,6 +172,9 @@ LMH_OP2(OpPowU10, pow_u10, powf_u10)
 LMH_OP2(OpAtan2U10, atan2_u10, atan2f_u10)
 LMH_OP2(OpFmod, fmod_f64, fmodf_f32)
 LMH_OP2(OpRemainder, remainder_f64, remainderf_f32)
+LMH_OP2(OpFdim, fdim_f64, fdimf_f32)
+LMH_OP2(OpFmax, fmax_f64, fmaxf_f32)
+LMH_OP2(OpFmin, fmin_f64, fminf_f32)
 
 // backward tags: (x, g) -> g f'(x); (a, b, g) -> two partials
 #define LMH_OPB(NAME, FN)                                                                   \

@@ -123,6 +123,9 @@ extern "C" int device_api_eval(int fn, int variant, int dtype, const void* a, co
     case 25: U1(atanh_u10)
     case 26: U1(erf_u10)
     case 27: U1(erfc_u10)
+    case 28: B2W(fdim)
+    case 29: B2W(fmax)
+    case 30: B2W(fmin)
   }
   return 2;
 }

@@ -136,3 +136,22 @@ def test_batch_c99_function_requests():
     for (fn, v, dt, a, b, out), r in zip(reqs, ref):
         assert _same(out, r), (fn, v, dt)
     plan.close()
+
+
+def test_batch_exact_function_requests():
+    """fmod, remainder, fdim, fmax and fmin (exact, binary64 and binary32)
+    through one plan, against the per-function entry points."""
+    reqs = []
+    kinds = [(f, d) for f in ("fmod", "remainder", "fdim", "fmax", "fmin") for d in ("f64", "f32")]
+    for i, (fn, dt) in enumerate(kinds):
+        a = W.function_mixture(fn, dt, 3000 + 977 * i, 500 + i)
+        b = W.function_mixture(fn, dt, a.size, 550 + i)
+        ta, tb = to_device(a, dt), to_device(b, dt)
+        reqs.append((fn, "exact", dt, ta, tb, torch.empty_like(ta)))
+    ref = _reference(reqs)
+    plan = L.BatchPlan(64, use_graph=True)
+    plan.run(reqs)
+    torch.cuda.synchronize()
+    for (fn, v, dt, a, b, out), r in zip(reqs, ref):
+        assert _same(out, r), (fn, v, dt)
+    plan.close()

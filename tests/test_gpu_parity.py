@@ -25,7 +25,7 @@ import paper_2001_09258_amd as L  # noqa: E402
 
 N_PAR = 3 * 4096 + 37            # 24+ tiles of 512 f64 elements, ragged tail
 CASES = [(fn, v, dt) for fn, v, dt, _ in L.all_entry_points()]
-BINARY = ("pow", "atan2", "hypot", "fmod", "remainder")
+BINARY = L.BINARY
 
 
 def _inputs(cfg, fn, dt, n, operand):

@@ -35,8 +35,9 @@ OTHERS = [(fn, "u10", dt) for fn in ("exp", "log", "pow", "atan2", "tanh", "asin
                                        ("acosh", "u10", "f32"), ("atanh", "u10", "f64"),
                                        ("erf", "u10", "f64"), ("erfc", "u10", "f32"),
                                        ("erfc", "u10", "f64"),
-                                       ("fmod", "exact", "f64"), ("remainder", "exact", "f32")]
-BINARY = ("pow", "atan2", "hypot", "fmod", "remainder")
+                                       ("fmod", "exact", "f64"), ("remainder", "exact", "f32"),
+                                       ("fdim", "exact", "f64"), ("fmax", "exact", "f32")]
+BINARY = L.BINARY
 SLOW = {"f64": 2.0 ** 14, "f32": 65536.0, "bf16": 65536.0, "f16": 65536.0, "f32_via_f64": 2.0 ** 14}
 
 

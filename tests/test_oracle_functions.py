@@ -646,3 +646,32 @@ def test_log_series_on_balls_agree_with_exact_log():
         # 1 + u = (2^-u_e + u_m) 2^u_e exactly
         d = log_ball((1 << -u_e) + u_m, u_e, 200)
         assert abs(B.approx(c) - B.approx(d)) <= abs(B.approx(d)) * 2.0 ** -150
+
+
+def test_fdim_fmax_fmin_against_ieee_operations():
+    """fdim against the host's IEEE subtraction (binary64 and binary32),
+    fmax/fmin against numpy's NaN-ignoring fmax/fmin, and the signed-zero
+    order (-0 below +0) on all zero pairs."""
+    rng = random.Random(13)
+    vals = [0.0, -0.0, math.inf, -math.inf, math.nan, 1.0, -1.0, 5e-324, 1e308, -1e308]
+    vals += [_rand_bits(rng) for _ in range(300)] + [rng.uniform(-10, 10) for _ in range(100)]
+    vals = [v for v in vals]
+    pairs = [(a, b) for a in vals[:60] for b in vals[:60]] + \
+        [(rng.choice(vals), rng.choice(vals)) for _ in range(2000)]
+    for a, b in pairs:
+        got = evaluate1("fdim", "f64", a, b)[0]
+        want = math.nan if (math.isnan(a) or math.isnan(b)) else (a - b if a > b else 0.0)
+        assert same(got, want), ("fdim", a, b, got, want)
+        fa, fb = np.float32(a), np.float32(b)
+        got32 = evaluate1("fdim", "f32", float(fa), float(fb))[0]
+        with np.errstate(all="ignore"):
+            w32 = np.float32("nan") if (np.isnan(fa) or np.isnan(fb)) else \
+                (fa - fb if fa > fb else np.float32(0.0))
+        assert same(got32, float(w32)), ("fdim f32", fa, fb, got32, w32)
+        if a == 0.0 and b == 0.0:
+            neg_a, neg_b = math.copysign(1, a) < 0, math.copysign(1, b) < 0
+            assert same(evaluate1("fmax", "f64", a, b)[0], -0.0 if (neg_a and neg_b) else 0.0)
+            assert same(evaluate1("fmin", "f64", a, b)[0], 0.0 if not (neg_a or neg_b) else -0.0)
+            continue
+        assert same(evaluate1("fmax", "f64", a, b)[0], float(np.fmax(a, b))), ("fmax", a, b)
+        assert same(evaluate1("fmin", "f64", a, b)[0], float(np.fmin(a, b))), ("fmin", a, b)
