@@ -211,6 +211,9 @@ LIBM_HIP_DECL_SINCOS(u35, float, f32)
  *   x > y, else +0, NaN if either argument is NaN; fmax / fmin return the
  *   larger / smaller argument, the other one when one is NaN, NaN when both
  *   are; -0 counts as smaller than +0 (C99 leaves that order open).
+ * copysign(x, y), nextafter(x, y): exact (C99 F.9.8.3, F.9.8.3's neighbour
+ *   rule: y if x == y, the smallest subnormal towards y from a zero, NaN if
+ *   either argument is NaN).
  * ---------------------------------------------------------------------- */
 #define LIBM_HIP_DECL_BINARY(fn, var, T, tag)                                              \
   libm_hip_status libm_hip_##fn##var##_##tag(const T* a, const T* b, T* out, size_t n,     \
@@ -242,6 +245,30 @@ LIBM_HIP_DECL_BINARY(fmax, , double, f64)
 LIBM_HIP_DECL_BINARY(fmax, , float, f32)
 LIBM_HIP_DECL_BINARY(fmin, , double, f64)
 LIBM_HIP_DECL_BINARY(fmin, , float, f32)
+LIBM_HIP_DECL_BINARY(copysign, , double, f64)
+LIBM_HIP_DECL_BINARY(copysign, , float, f32)
+LIBM_HIP_DECL_BINARY(nextafter, , double, f64)
+LIBM_HIP_DECL_BINARY(nextafter, , float, f32)
+
+/* ------------------------------------------------------------------------
+ * The rest of the C99 real functions with one exact answer (the paper's
+ * library covers all C99 real functions, Section 1), binary64 and binary32,
+ * y[i] = f(x[i]): sqrt correctly rounded (the IEEE square root), trunc,
+ * floor, ceil, round (halfway cases away from zero), rint (halfway cases to
+ * even), fabs, logb (the exponent of x as if normalized; logb(+-0) = -inf,
+ * logb(+-inf) = +inf).  Signs of zero and NaN as C99 Annex F.
+ * ---------------------------------------------------------------------- */
+#define LIBM_HIP_DECL_EXACT1(fn)                                                            \
+  libm_hip_status libm_hip_##fn##_f64(const double* x, double* y, size_t n, void* stream);  \
+  libm_hip_status libm_hip_##fn##_f32(const float* x, float* y, size_t n, void* stream);
+LIBM_HIP_DECL_EXACT1(sqrt)
+LIBM_HIP_DECL_EXACT1(trunc)
+LIBM_HIP_DECL_EXACT1(floor)
+LIBM_HIP_DECL_EXACT1(ceil)
+LIBM_HIP_DECL_EXACT1(round)
+LIBM_HIP_DECL_EXACT1(rint)
+LIBM_HIP_DECL_EXACT1(fabs)
+LIBM_HIP_DECL_EXACT1(logb)
 
 /* ------------------------------------------------------------------------
  * Backward (vector-Jacobian products) for autograd; not part of the paper.
@@ -285,6 +312,8 @@ typedef enum {
   LIBM_HIP_LOG10, LIBM_HIP_LOG1P, LIBM_HIP_EXP10, LIBM_HIP_EXPM1, LIBM_HIP_CBRT,
   LIBM_HIP_HYPOT, LIBM_HIP_ASINH, LIBM_HIP_ACOSH, LIBM_HIP_ATANH,
   LIBM_HIP_ERF, LIBM_HIP_ERFC, LIBM_HIP_FDIM, LIBM_HIP_FMAX, LIBM_HIP_FMIN,
+  LIBM_HIP_SQRT, LIBM_HIP_TRUNC, LIBM_HIP_FLOOR, LIBM_HIP_CEIL, LIBM_HIP_ROUND, LIBM_HIP_RINT,
+  LIBM_HIP_FABS, LIBM_HIP_LOGB, LIBM_HIP_COPYSIGN, LIBM_HIP_NEXTAFTER,
   LIBM_HIP_NUM_FN
 } libm_hip_fn;
 typedef enum { LIBM_HIP_U10 = 0, LIBM_HIP_U35 = 1, LIBM_HIP_EXACT = 2 } libm_hip_variant;

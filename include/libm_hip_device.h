@@ -176,6 +176,28 @@ __device__ __forceinline__ double fmax(double x, double y) { return lmh_ops::OpF
 __device__ __forceinline__ float fmax(float x, float y) { return lmh_ops::OpFmax::f(x, y); }
 __device__ __forceinline__ double fmin(double x, double y) { return lmh_ops::OpFmin::f(x, y); }
 __device__ __forceinline__ float fmin(float x, float y) { return lmh_ops::OpFmin::f(x, y); }
+/* the rest of the exact C99 set: sqrt (correctly rounded), trunc, floor, ceil,
+   round, rint, fabs, logb, copysign, nextafter */
+__device__ __forceinline__ double sqrt(double x) { return lmh_ops::OpSqrt::f(x); }
+__device__ __forceinline__ float sqrt(float x) { return lmh_ops::OpSqrt::f(x); }
+__device__ __forceinline__ double trunc(double x) { return lmh_ops::OpTrunc::f(x); }
+__device__ __forceinline__ float trunc(float x) { return lmh_ops::OpTrunc::f(x); }
+__device__ __forceinline__ double floor(double x) { return lmh_ops::OpFloor::f(x); }
+__device__ __forceinline__ float floor(float x) { return lmh_ops::OpFloor::f(x); }
+__device__ __forceinline__ double ceil(double x) { return lmh_ops::OpCeil::f(x); }
+__device__ __forceinline__ float ceil(float x) { return lmh_ops::OpCeil::f(x); }
+__device__ __forceinline__ double round(double x) { return lmh_ops::OpRound::f(x); }
+__device__ __forceinline__ float round(float x) { return lmh_ops::OpRound::f(x); }
+__device__ __forceinline__ double rint(double x) { return lmh_ops::OpRint::f(x); }
+__device__ __forceinline__ float rint(float x) { return lmh_ops::OpRint::f(x); }
+__device__ __forceinline__ double fabs(double x) { return lmh_ops::OpFabs::f(x); }
+__device__ __forceinline__ float fabs(float x) { return lmh_ops::OpFabs::f(x); }
+__device__ __forceinline__ double logb(double x) { return lmh_ops::OpLogb::f(x); }
+__device__ __forceinline__ float logb(float x) { return lmh_ops::OpLogb::f(x); }
+__device__ __forceinline__ double copysign(double x, double y) { return lmh_ops::OpCopysign::f(x, y); }
+__device__ __forceinline__ float copysign(float x, float y) { return lmh_ops::OpCopysign::f(x, y); }
+__device__ __forceinline__ double nextafter(double x, double y) { return lmh_ops::OpNextafter::f(x, y); }
+__device__ __forceinline__ float nextafter(float x, float y) { return lmh_ops::OpNextafter::f(x, y); }
 
 /* backward: g * f'(x) */
 #define LIBM_HIP_DEVICE_BWD(NAME, FN)                                                     \

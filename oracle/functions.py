@@ -30,7 +30,12 @@ fdim, fmax, fmin are C99 functions of the library's set (Section 1) that the
 paper only shows as a masking example: fdim(x, y) is x - y rounded when
 x > y, else +0; fmax/fmin return the larger/smaller argument, the other one
 if one is NaN, NaN if both are (F.9.9).  C99 leaves the order of -0 and +0
-open; here -0 < +0 (fmax(-0, +0) = +0, fmin(-0, +0) = -0).
+open; here -0 < +0 (fmax(-0, +0) = +0, fmin(-0, +0) = -0).  The rest of the
+C99 set that has one exact answer: sqrt (correctly rounded: the exact
+square root of the dyadic argument, rounded once), trunc, floor, ceil, round
+(halfway cases away from zero), rint (to nearest even), fabs, logb (the
+unbiased exponent of the argument as if normalized), copysign, nextafter
+(F.9.4.5, F.9.6, F.9.3.11, F.9.8.3, F.9.9).
 
 Besides the rounded value the oracle returns a high-precision approximation of
 the exact value as a pair of binary64 numbers (hi, lo), from which the tests
@@ -54,8 +59,12 @@ PREC_CAP = 16384
 UNARY = ("sin", "cos", "tan", "exp", "exp2", "log", "log2",
          "sinh", "cosh", "tanh", "asin", "acos", "atan",
          "log10", "exp10", "expm1", "log1p", "cbrt", "asinh", "acosh", "atanh",
-         "erf", "erfc")
-BINARY = ("pow", "atan2", "fmod", "remainder", "hypot", "fdim", "fmax", "fmin")
+         "erf", "erfc", "sqrt", "trunc", "floor", "ceil", "round", "rint", "fabs", "logb")
+BINARY = ("pow", "atan2", "fmod", "remainder", "hypot", "fdim", "fmax", "fmin", "copysign",
+          "nextafter")
+# functions whose result is the exact value or its correct rounding (no
+# approximation involved): defined directly, no Ziv loop
+EXACT_UNARY = ("sqrt", "trunc", "floor", "ceil", "round", "rint", "fabs", "logb")
 
 
 class OracleError(RuntimeError):
@@ -684,6 +693,57 @@ def _ziv(fn_ball, args, fmt, prec0):
     raise OracleError("precision cap reached for %r" % (args,))
 
 
+def _ball_sqrt(x, prec):
+    m, e = _dyadic(x)
+    return B.sqrt(exact(m, e), prec + 8)
+
+
+def _exact_unary(fn, x, fmt, prec0):
+    """The exactly defined unary functions (see the module docstring)."""
+    from fractions import Fraction
+    if math.isnan(x):
+        return NAN, NAN, 0.0
+    if fn == "fabs":
+        v = abs(x)
+        return v, v, 0.0
+    if fn == "logb":
+        if x == 0.0:
+            return -INF, -INF, 0.0
+        if math.isinf(x):
+            return INF, INF, 0.0
+        v = float(math.frexp(x)[1] - 1)
+        return v, v, 0.0
+    if fn == "sqrt":
+        if x < 0.0:
+            return NAN, NAN, 0.0
+        if x == 0.0 or math.isinf(x):
+            return x, x, 0.0
+        m, e = _dyadic(x)
+        if e & 1:
+            m, e = m << 1, e - 1
+        r = math.isqrt(m)
+        if r * r == m:
+            return _exact_result(r, e // 2, fmt)
+        return _ziv(_ball_sqrt, (x,), fmt, prec0)
+    # integral roundings: exact integers, zero keeping the argument's sign
+    if math.isinf(x) or x == 0.0:
+        return x, x, 0.0
+    q = Fraction(x)
+    if fn == "trunc":
+        k = math.trunc(q)
+    elif fn == "floor":
+        k = math.floor(q)
+    elif fn == "ceil":
+        k = math.ceil(q)
+    elif fn == "round":
+        k = math.floor(abs(q) + Fraction(1, 2))
+        k = -k if q < 0 else k
+    else:                                             # rint: ties to even
+        k = round(q)
+    v = math.copysign(float(k), x)
+    return v, v, 0.0
+
+
 def evaluate1(fn, fmt_name, x, y=None):
     """Correctly rounded fn(x) (or fn(x, y)) in format ``fmt_name``.
 
@@ -696,6 +756,8 @@ def evaluate1(fn, fmt_name, x, y=None):
     (rn, 0) when the result is exact or special)."""
     fmt = FORMATS[fmt_name]
     prec0 = fmt.p + 40
+    if fn in EXACT_UNARY:
+        return _exact_unary(fn, x, fmt, prec0)
     if fn in UNARY:
         sp = _special_unary(fn, x)
         if sp is not None:
@@ -776,6 +838,20 @@ def evaluate1(fn, fmt_name, x, y=None):
         d = max(dx, dy)                               # powers of two
         num = nx * (d // dx) - ny * (d // dy)
         v = rn_dyadic(num, -(d.bit_length() - 1), fmt)
+        return v, v, 0.0
+    if fn == "copysign":
+        v = math.copysign(x, y)
+        return v, v, 0.0
+    if fn == "nextafter":
+        if math.isnan(x) or math.isnan(y):
+            return NAN, NAN, 0.0
+        if fmt_name == "f64":
+            v = math.nextafter(x, y)
+        elif fmt_name == "f32":
+            import numpy as np
+            v = float(np.nextafter(np.float32(x), np.float32(y)))
+        else:
+            raise ValueError("nextafter: binary64 and binary32 only")
         return v, v, 0.0
     if fn in ("fmax", "fmin"):
         if math.isnan(x):

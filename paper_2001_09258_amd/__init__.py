@@ -21,7 +21,8 @@ __all__ = ["load", "library_path", "UNARY", "BINARY", "VARIANTS", "entry_name",
            "call", "evaluate", "sin", "cos", "tan", "exp", "exp2", "log", "log2",
            "sinh", "cosh", "tanh", "asin", "acos", "atan", "log10", "log1p", "exp10",
            "expm1", "cbrt", "asinh", "acosh", "atanh", "erf", "erfc", "sincos", "pow", "atan2",
-           "hypot", "fmod", "remainder", "fdim", "fmax", "fmin",
+           "hypot", "fmod", "remainder", "fdim", "fmax", "fmin", "copysign", "nextafter",
+           "sqrt", "trunc", "floor", "ceil", "rint", "fabs", "logb",
            "consistent", "host_consistent", "LibmHipError"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -29,11 +30,14 @@ _LIBNAME = "libm_hip.so"
 
 UNARY = ("sin", "cos", "tan", "exp", "exp2", "log", "log2", "sinh", "cosh", "tanh",
          "asin", "acos", "atan", "log10", "log1p", "exp10", "expm1", "cbrt", "asinh",
-         "acosh", "atanh", "erf", "erfc")
-BINARY = ("pow", "atan2", "hypot", "fmod", "remainder", "fdim", "fmax", "fmin")
-EXACT = ("fmod", "remainder", "fdim", "fmax", "fmin")
+         "acosh", "atanh", "erf", "erfc", "sqrt", "trunc", "floor", "ceil", "round", "rint",
+         "fabs", "logb")
+BINARY = ("pow", "atan2", "hypot", "fmod", "remainder", "fdim", "fmax", "fmin", "copysign",
+          "nextafter")
+EXACT = ("fmod", "remainder", "fdim", "fmax", "fmin", "copysign", "nextafter", "sqrt", "trunc",
+         "floor", "ceil", "round", "rint", "fabs", "logb")
 # accuracy variants served per function
-VARIANTS = {fn: ("u10",) for fn in UNARY + ("pow", "atan2", "hypot")}
+VARIANTS = {fn: ("exact",) if fn in EXACT else ("u10",) for fn in UNARY + BINARY}
 VARIANTS.update({"sin": ("u10", "u35"), "cos": ("u10", "u35"), "tan": ("u10", "u35"),
                  "asin": ("u10", "u35"), "acos": ("u10", "u35"), "atan": ("u10", "u35"),
                  "log": ("u10", "u35"), "atan2": ("u10", "u35"), "sinh": ("u10", "u35"),
@@ -232,6 +236,18 @@ asinh, acosh, atanh = _unary("asinh"), _unary("acosh"), _unary("atanh")
 erf, erfc = _unary("erf"), _unary("erfc")
 
 
+def _exact1(fn):
+    def f(x, out=None):
+        return evaluate(fn, x, None, "exact", out)
+    f.__name__ = fn
+    f.__doc__ = "Elementwise C %s on a float64/float32 device tensor (exact result)." % fn
+    return f
+
+
+sqrt, trunc, floor, ceil = _exact1("sqrt"), _exact1("trunc"), _exact1("floor"), _exact1("ceil")
+round, rint, fabs, logb = _exact1("round"), _exact1("rint"), _exact1("fabs"), _exact1("logb")
+
+
 def sincos(x, variant="u10", outs=None, via_f64=False):
     """(sin x, cos x) elementwise in one pass, each bit-identical to sin and
     cos of the same variant."""
@@ -289,6 +305,16 @@ def fmin(x, y, out=None):
     return evaluate("fmin", x, y, "exact", out)
 
 
+def copysign(x, y, out=None):
+    """C copysign(x, y) elementwise."""
+    return evaluate("copysign", x, y, "exact", out)
+
+
+def nextafter(x, y, out=None):
+    """C nextafter(x, y) elementwise."""
+    return evaluate("nextafter", x, y, "exact", out)
+
+
 def backward(fn, inputs, gout, outs=None):
     """Raw backward call: ``inputs`` are the saved forward inputs (C order),
     ``gout`` the upstream gradient; returns the input gradient(s)."""
@@ -322,7 +348,8 @@ FN_CODES = {"sin": 0, "cos": 1, "tan": 2, "exp": 3, "exp2": 4, "log": 5, "log2":
             "remainder": 13, "asin": 14, "acos": 15, "atan": 16, "log10": 17,
             "log1p": 18, "exp10": 19, "expm1": 20, "cbrt": 21, "hypot": 22, "asinh": 23,
             "acosh": 24, "atanh": 25, "erf": 26, "erfc": 27, "fdim": 28, "fmax": 29,
-            "fmin": 30}
+            "fmin": 30, "sqrt": 31, "trunc": 32, "floor": 33, "ceil": 34, "round": 35,
+            "rint": 36, "fabs": 37, "logb": 38, "copysign": 39, "nextafter": 40}
 VARIANT_CODES = {"u10": 0, "u35": 1, "exact": 2}
 DTYPE_CODES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "f32_via_f64": 4}
 

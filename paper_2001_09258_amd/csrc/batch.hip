@@ -116,24 +116,36 @@ struct Header {
   X(154, IoF16, OpErfcU10, 1) X(155, IoF32ViaF64, OpErfcU10, 1)               \
   X(156, IoF64, OpFdim, 2) X(157, IoF32, OpFdim, 2)                             \
   X(158, IoF64, OpFmax, 2) X(159, IoF32, OpFmax, 2)                             \
-  X(160, IoF64, OpFmin, 2) X(161, IoF32, OpFmin, 2)
-constexpr int NUM_OPS = 162;
+  X(160, IoF64, OpFmin, 2) X(161, IoF32, OpFmin, 2)                             \
+  X(162, IoF64, OpSqrt, 1) X(163, IoF32, OpSqrt, 1) \
+  X(164, IoF64, OpTrunc, 1) X(165, IoF32, OpTrunc, 1) \
+  X(166, IoF64, OpFloor, 1) X(167, IoF32, OpFloor, 1) \
+  X(168, IoF64, OpCeil, 1) X(169, IoF32, OpCeil, 1) \
+  X(170, IoF64, OpRound, 1) X(171, IoF32, OpRound, 1) \
+  X(172, IoF64, OpRint, 1) X(173, IoF32, OpRint, 1) \
+  X(174, IoF64, OpFabs, 1) X(175, IoF32, OpFabs, 1) \
+  X(176, IoF64, OpLogb, 1) X(177, IoF32, OpLogb, 1) \
+  X(178, IoF64, OpCopysign, 2) X(179, IoF32, OpCopysign, 2) \
+  X(180, IoF64, OpNextafter, 2) X(181, IoF32, OpNextafter, 2)
+constexpr int NUM_OPS = 182;
 
 // host-side code of a (fn, variant, dtype) triple, or -1
 int op_code(int fn, int v, int t) {
   // dtype order in the table: f64, f32, bf16, f16, f32_via_f64
   static const int u10_base[LIBM_HIP_NUM_FN] = {0, 7, 14, 21, 26, 31, 36, 56, 61, 41, 46, 51,
                                                 -1, -1, 70, 77, 84, 93, 98, 103, 108, 113,
-                                                118, 131, 136, 141, 146, 151, -1, -1, -1};
+                                                118, 131, 136, 141, 146, 151, -1, -1, -1,
+                                                -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
   static const int u35_base[LIBM_HIP_NUM_FN] = {5, 12, 19, -1, -1, 91, -1, -1, 123, 125, 127,
                                                 129, -1, -1, 75, 82, 89, -1, -1, -1, -1, -1,
-                                                -1, -1, -1, -1, -1, -1, -1, -1, -1};
+                                                -1, -1, -1, -1, -1, -1, -1, -1, -1,
+                                                -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
   if (fn < 0 || fn >= LIBM_HIP_NUM_FN || t < 0 || t > 4) return -1;
   if (fn == LIBM_HIP_FMOD || fn == LIBM_HIP_REMAINDER) {
     if (v != LIBM_HIP_EXACT || t > 1) return -1;
     return (fn == LIBM_HIP_FMOD ? 66 : 68) + t;
   }
-  if (fn == LIBM_HIP_FDIM || fn == LIBM_HIP_FMAX || fn == LIBM_HIP_FMIN) {
+  if (fn >= LIBM_HIP_FDIM && fn <= LIBM_HIP_NEXTAFTER) {          // exact, f64 and f32
     if (v != LIBM_HIP_EXACT || t > 1) return -1;
     return 156 + 2 * (fn - LIBM_HIP_FDIM) + t;
   }
@@ -146,7 +158,7 @@ int op_code(int fn, int v, int t) {
 // (from the elementwise kernels' measured times: trig with Payne-Hanek and
 // the remainders are the most expensive, exp/log the cheapest)
 float op_cost(int code) {
-  if (code >= 156) return 0.25f;               // fdim, fmax, fmin
+  if (code >= 156) return 0.25f;               // fdim, fmax, fmin and the rest of the exact set
   if (code >= 146) return 0.5f;                // erf, erfc
   if (code >= 131) return 0.55f;               // asinh, acosh, atanh
   if (code >= 125) return 0.35f;               // sinh, cosh, tanh u35
@@ -163,7 +175,10 @@ float op_cost(int code) {
 }
 
 size_t op_arity(int code) {
-  return (code >= 56 && code <= 69) || (code >= 118 && code <= 124) || code >= 156 ? 2 : 1;
+  return (code >= 56 && code <= 69) || (code >= 118 && code <= 124) ||
+                 (code >= 156 && code <= 161) || code >= 178
+             ? 2
+             : 1;
 }
 
 // ---- device side -------------------------------------------------------------

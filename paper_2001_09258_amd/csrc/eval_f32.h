@@ -950,6 +950,40 @@ LMH_INLINE float fminf_f32(float x, float y) {
   return zeros ? (__builtin_signbit(x) ? x : y) : r;
 }
 
+// The rest of the C99 set with one exact answer (Section 1: the library
+// covers all C99 real functions): sqrt correctly rounded (the IEEE square
+// root; -0 -> -0, negative -> NaN), trunc, floor, ceil, round (halfway away
+// from zero), rint (halfway to even), fabs, logb (the exponent of x as if
+// normalized; 0 -> -inf, inf -> +inf), copysign, nextafter.
+LMH_INLINE float sqrtf_f32(float x) { return __builtin_sqrtf(x); }
+LMH_INLINE float truncf_f32(float x) { return trunc_(x); }
+LMH_INLINE float floorf_f32(float x) { return __builtin_floorf(x); }
+LMH_INLINE float ceilf_f32(float x) { return __builtin_ceilf(x); }
+LMH_INLINE float rintf_f32(float x) { return rint_(x); }
+LMH_INLINE float fabsf_f32(float x) { return fabs_(x); }
+// round: x - trunc(x) is exact (both share x's exponent range), so the
+// halfway test has no rounding; inf and NaN keep trunc's result
+LMH_INLINE float roundf_f32(float x) {
+  float t = trunc_(x);
+  return fabs_(x - t) >= 0.5f ? t + copysign_(1.0f, x) : t;
+}
+LMH_INLINE float logbf_f32(float x) {
+  float e = (float)(frexp_exp_(x) - 1);
+  float r = isfinite_(x) ? e : fabs_(x);
+  return x == 0.0f ? -__builtin_inff() : r;
+}
+LMH_INLINE float copysignf_f32(float x, float y) { return copysign_(x, y); }
+// nextafter: the neighbour of x towards y by one step of the integer image
+// (the magnitude grows when y lies beyond x away from zero); y when x == y,
+// the smallest subnormal with y's sign from a zero, NaN if either is NaN
+LMH_INLINE float nextafterf_f32(float x, float y) {
+  bool away = (y > x) == (x > 0.0f);
+  float r = as_f32(as_i32(x) + (away ? 1 : -1));
+  r = x == 0.0f ? copysign_(0x1p-149f, y) : r;
+  r = x == y ? y : r;
+  return (isnan_(x) || isnan_(y)) ? x + y : r;
+}
+
 }  // namespace lmh
 
 #pragma STDC FP_CONTRACT DEFAULT

@@ -23,7 +23,11 @@
   X(CBRT, U10, cbrt_u10, cbrtf_u10)                                                   \
   X(ASINH, U10, asinh_u10, asinhf_u10) X(ACOSH, U10, acosh_u10, acoshf_u10)           \
   X(ATANH, U10, atanh_u10, atanhf_u10)                                                \
-  X(ERF, U10, erf_u10, erff_u10) X(ERFC, U10, erfc_u10, erfcf_u10)
+  X(ERF, U10, erf_u10, erff_u10) X(ERFC, U10, erfc_u10, erfcf_u10)                   \
+  X(SQRT, EXACT, sqrt_f64, sqrtf_f32) X(TRUNC, EXACT, trunc_f64, truncf_f32)         \
+  X(FLOOR, EXACT, floor_f64, floorf_f32) X(CEIL, EXACT, ceil_f64, ceilf_f32)         \
+  X(ROUND, EXACT, round_f64, roundf_f32) X(RINT, EXACT, rint_f64, rintf_f32)         \
+  X(FABS, EXACT, fabs_f64, fabsf_f32) X(LOGB, EXACT, logb_f64, logbf_f32)
 
 #define LMH_CONSISTENT_BINARY(X)                                                      \
   X(POW, U10, pow_u10, powf_u10)                                                      \
@@ -31,4 +35,5 @@
   X(HYPOT, U10, hypot_u10, hypotf_u10)                                                \
   X(FMOD, EXACT, fmod_f64, fmodf_f32) X(REMAINDER, EXACT, remainder_f64, remainderf_f32)     \
   X(FDIM, EXACT, fdim_f64, fdimf_f32) X(FMAX, EXACT, fmax_f64, fmaxf_f32)                     \
-  X(FMIN, EXACT, fmin_f64, fminf_f32)
+  X(FMIN, EXACT, fmin_f64, fminf_f32) X(COPYSIGN, EXACT, copysign_f64, copysignf_f32)         \
+  X(NEXTAFTER, EXACT, nextafter_f64, nextafterf_f32)

@@ -357,6 +357,26 @@ LMH_DEF_BINARY(fmax, , IoF64, double, f64, OpFmax, LMH_KEY(FMAX, EXACT, F64))
 LMH_DEF_BINARY(fmax, , IoF32, float, f32, OpFmax, LMH_KEY(FMAX, EXACT, F32))
 LMH_DEF_BINARY(fmin, , IoF64, double, f64, OpFmin, LMH_KEY(FMIN, EXACT, F64))
 LMH_DEF_BINARY(fmin, , IoF32, float, f32, OpFmin, LMH_KEY(FMIN, EXACT, F32))
+LMH_DEF_BINARY(copysign, , IoF64, double, f64, OpCopysign, LMH_KEY(COPYSIGN, EXACT, F64))
+LMH_DEF_BINARY(copysign, , IoF32, float, f32, OpCopysign, LMH_KEY(COPYSIGN, EXACT, F32))
+LMH_DEF_BINARY(nextafter, , IoF64, double, f64, OpNextafter, LMH_KEY(NEXTAFTER, EXACT, F64))
+LMH_DEF_BINARY(nextafter, , IoF32, float, f32, OpNextafter, LMH_KEY(NEXTAFTER, EXACT, F32))
+
+#define LMH_DEF_EXACT1(fn, Op, FN)                                                               \
+  libm_hip_status libm_hip_##fn##_f64(const double* x, double* y, size_t n, void* s) {          \
+    return launch_unary<IoF64, Op>(x, y, n, s, #fn "_f64", LMH_KEY(FN, EXACT, F64));             \
+  }                                                                                              \
+  libm_hip_status libm_hip_##fn##_f32(const float* x, float* y, size_t n, void* s) {            \
+    return launch_unary<IoF32, Op>(x, y, n, s, #fn "_f32", LMH_KEY(FN, EXACT, F32));             \
+  }
+LMH_DEF_EXACT1(sqrt, OpSqrt, SQRT)
+LMH_DEF_EXACT1(trunc, OpTrunc, TRUNC)
+LMH_DEF_EXACT1(floor, OpFloor, FLOOR)
+LMH_DEF_EXACT1(ceil, OpCeil, CEIL)
+LMH_DEF_EXACT1(round, OpRound, ROUND)
+LMH_DEF_EXACT1(rint, OpRint, RINT)
+LMH_DEF_EXACT1(fabs, OpFabs, FABS)
+LMH_DEF_EXACT1(logb, OpLogb, LOGB)
 LMH_DEF_BINARY(remainder, , IoF64, double, f64, OpRemainder, LMH_KEY(REMAINDER, EXACT, F64))
 LMH_DEF_BINARY(remainder, , IoF32, float, f32, OpRemainder, LMH_KEY(REMAINDER, EXACT, F32))
 
@@ -527,6 +547,36 @@ extern "C" libm_hip_status libm_hip_eval(libm_hip_fn fn, libm_hip_variant v, lib
       break;
     case LIBM_HIP_FMIN:
       if (v == LIBM_HIP_EXACT) return dispatch_binary<OpFmin>(t, a, b, out, n, s, false, key);
+      break;
+    case LIBM_HIP_SQRT:
+      if (v == LIBM_HIP_EXACT) return dispatch_unary<OpSqrt>(t, a, out, n, s, true, key);
+      break;
+    case LIBM_HIP_TRUNC:
+      if (v == LIBM_HIP_EXACT) return dispatch_unary<OpTrunc>(t, a, out, n, s, true, key);
+      break;
+    case LIBM_HIP_FLOOR:
+      if (v == LIBM_HIP_EXACT) return dispatch_unary<OpFloor>(t, a, out, n, s, true, key);
+      break;
+    case LIBM_HIP_CEIL:
+      if (v == LIBM_HIP_EXACT) return dispatch_unary<OpCeil>(t, a, out, n, s, true, key);
+      break;
+    case LIBM_HIP_ROUND:
+      if (v == LIBM_HIP_EXACT) return dispatch_unary<OpRound>(t, a, out, n, s, true, key);
+      break;
+    case LIBM_HIP_RINT:
+      if (v == LIBM_HIP_EXACT) return dispatch_unary<OpRint>(t, a, out, n, s, true, key);
+      break;
+    case LIBM_HIP_FABS:
+      if (v == LIBM_HIP_EXACT) return dispatch_unary<OpFabs>(t, a, out, n, s, true, key);
+      break;
+    case LIBM_HIP_LOGB:
+      if (v == LIBM_HIP_EXACT) return dispatch_unary<OpLogb>(t, a, out, n, s, true, key);
+      break;
+    case LIBM_HIP_COPYSIGN:
+      if (v == LIBM_HIP_EXACT) return dispatch_binary<OpCopysign>(t, a, b, out, n, s, false, key);
+      break;
+    case LIBM_HIP_NEXTAFTER:
+      if (v == LIBM_HIP_EXACT) return dispatch_binary<OpNextafter>(t, a, b, out, n, s, false, key);
       break;
     default: break;
   }

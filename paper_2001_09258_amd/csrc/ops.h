@@ -175,6 +175,16 @@ LMH_OP2(OpRemainder, remainder_f64, remainderf_f32)
 LMH_OP2(OpFdim, fdim_f64, fdimf_f32)
 LMH_OP2(OpFmax, fmax_f64, fmaxf_f32)
 LMH_OP2(OpFmin, fmin_f64, fminf_f32)
+LMH_OP1(OpSqrt, sqrt_f64, sqrtf_f32)
+LMH_OP1(OpTrunc, trunc_f64, truncf_f32)
+LMH_OP1(OpFloor, floor_f64, floorf_f32)
+LMH_OP1(OpCeil, ceil_f64, ceilf_f32)
+LMH_OP1(OpRound, round_f64, roundf_f32)
+LMH_OP1(OpRint, rint_f64, rintf_f32)
+LMH_OP1(OpFabs, fabs_f64, fabsf_f32)
+LMH_OP1(OpLogb, logb_f64, logbf_f32)
+LMH_OP2(OpCopysign, copysign_f64, copysignf_f32)
+LMH_OP2(OpNextafter, nextafter_f64, nextafterf_f32)
 
 // backward tags: (x, g) -> g f'(x); (a, b, g) -> two partials
 #define LMH_OPB(NAME, FN)                                                                   \

@@ -68,6 +68,12 @@ int launch2(const void* a, const void* b, void* y, size_t n, void* s, F f) {
     case 4: return launch2<float>(a, b, y, n, s, [] __device__(float u, float v) { return D::NAME##_via_f64(u, v); });       \
   }                                                                                         \
   return 2;
+#define U1W(NAME)                                                                           \
+  switch (dtype) {                                                                          \
+    case 0: return launch1<double>(a, y, n, s, [] __device__(double x) { return D::NAME(x); }); \
+    case 1: return launch1<float>(a, y, n, s, [] __device__(float x) { return D::NAME(x); });   \
+  }                                                                                         \
+  return 2;
 #define B2W(NAME)                                                                           \
   switch (dtype) {                                                                          \
     case 0: return launch2<double>(a, b, y, n, s, [] __device__(double u, double v) { return D::NAME(u, v); }); \
@@ -126,6 +132,16 @@ extern "C" int device_api_eval(int fn, int variant, int dtype, const void* a, co
     case 28: B2W(fdim)
     case 29: B2W(fmax)
     case 30: B2W(fmin)
+    case 31: U1W(sqrt)
+    case 32: U1W(trunc)
+    case 33: U1W(floor)
+    case 34: U1W(ceil)
+    case 35: U1W(round)
+    case 36: U1W(rint)
+    case 37: U1W(fabs)
+    case 38: U1W(logb)
+    case 39: B2W(copysign)
+    case 40: B2W(nextafter)
   }
   return 2;
 }

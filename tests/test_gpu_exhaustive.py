@@ -165,3 +165,30 @@ def test_narrow_pow_pairs(dt):
         "pow %s: x=%r y=%r got %r want %r (max %.3f ulp)" % (dt, x[bad], y[bad], r[bad], rn[bad],
                                                            res["max_ulp"])
     print("pow %s pairs: max %.3f ulp" % (dt, res["max_ulp"]), flush=True)
+
+
+def test_sqrt_correctly_rounded_sweep():
+    """sqrt (exact variant: the correctly rounded square root) on every
+    STRIDE-th binary32 pattern against numpy's binary32 square root (an IEEE
+    operation), and on 2^22 random binary64 patterns against the host's;
+    bit for bit, NaN as a class."""
+    total = bad = 0
+    for start in range(0, 1 << 32, CHUNK * STRIDE):
+        bits = np.arange(start, min(start + CHUNK * STRIDE, 1 << 32), STRIDE, dtype=np.uint64)
+        x = bits.astype(np.uint32).view(np.float32)
+        y = run_gpu("sqrt", "exact", "f32", x.astype(np.float64)).astype(np.float32)
+        with np.errstate(invalid="ignore"):
+            want = np.sqrt(x)
+        same = (y.view(np.uint32) == want.view(np.uint32)) | (np.isnan(y) & np.isnan(want))
+        bad += int((~same).sum())
+        total += x.size
+    assert bad == 0, "%d of %d binary32 square roots differ" % (bad, total)
+    rng = np.random.default_rng(23)
+    x = rng.integers(0, 1 << 63, 1 << 22, dtype=np.uint64).view(np.float64)
+    y = run_gpu("sqrt", "exact", "f64", x)
+    with np.errstate(invalid="ignore"):
+        want = np.sqrt(x)
+    same = (y.view(np.uint64) == want.view(np.uint64)) | (np.isnan(y) & np.isnan(want))
+    assert same.all(), x[~same][:4]
+    print("sqrt: %d binary32 patterns and 2^22 binary64 ones correctly rounded" % total,
+          flush=True)

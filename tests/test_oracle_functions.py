@@ -675,3 +675,42 @@ def test_fdim_fmax_fmin_against_ieee_operations():
             continue
         assert same(evaluate1("fmax", "f64", a, b)[0], float(np.fmax(a, b))), ("fmax", a, b)
         assert same(evaluate1("fmin", "f64", a, b)[0], float(np.fmin(a, b))), ("fmin", a, b)
+
+
+def test_exact_c99_set_against_host_operations():
+    """sqrt against the host's IEEE square root (binary64, and numpy's
+    binary32 one), trunc/floor/ceil/rint/fabs/copysign/nextafter against
+    numpy, round against decimal's ROUND_HALF_UP on the exact decimal
+    expansion, logb against frexp; signs of zero included."""
+    import decimal
+    rng = random.Random(14)
+    xs = [0.0, -0.0, math.inf, -math.inf, 0.5, -0.5, 1.5, -2.5, 2.5, 0.49999999999999994,
+          -0.49999999999999994, 4503599627370495.5, 4503599627370497.0, 5e-324, -1e-310,
+          1.7976931348623157e308, 4.0, 9.0, 2.0]
+    xs += [_rand_bits(rng) for _ in range(400)] + [rng.uniform(-100, 100) for _ in range(200)]
+    xs = [x for x in xs if not math.isnan(x)]
+    for x in xs:
+        want = {"trunc": float(np.trunc(x)), "floor": float(np.floor(x)),
+                "ceil": float(np.ceil(x)), "rint": float(np.rint(x)), "fabs": float(np.fabs(x))}
+        with np.errstate(invalid="ignore"):
+            want["sqrt"] = float(np.sqrt(x))
+        if math.isfinite(x):
+            d = decimal.Decimal(x).quantize(decimal.Decimal(1), rounding=decimal.ROUND_HALF_UP,
+                                            context=decimal.Context(prec=400))
+            want["round"] = math.copysign(float(d), x)
+            want["logb"] = -math.inf if x == 0 else float(math.frexp(x)[1] - 1)
+        else:
+            want["round"] = x
+            want["logb"] = math.inf
+        for fn, w in want.items():
+            assert same(evaluate1(fn, "f64", x)[0], w), (fn, x, evaluate1(fn, "f64", x)[0], w)
+        f = float(np.float32(x)) if abs(x) < 3e38 or not math.isfinite(x) else 1.0
+        with np.errstate(invalid="ignore"):
+            w32 = float(np.sqrt(np.float32(f)))
+        assert same(evaluate1("sqrt", "f32", f)[0], w32), ("sqrt f32", f)
+        y = rng.choice(xs)
+        assert same(evaluate1("copysign", "f64", x, y)[0], float(np.copysign(x, y)))
+        assert same(evaluate1("nextafter", "f64", x, y)[0], float(np.nextafter(x, y))), (x, y)
+        g = float(np.float32(y)) if abs(y) < 3e38 or not math.isfinite(y) else -1.0
+        assert same(evaluate1("nextafter", "f32", f, g)[0],
+                    float(np.nextafter(np.float32(f), np.float32(g)))), (f, g)

@@ -27,7 +27,8 @@ FN_IDS = {name: i for i, name in enumerate(
     ["sin", "cos", "tan", "exp", "exp2", "log", "log2", "pow", "atan2",
      "sinh", "cosh", "tanh", "fmod", "remainder", "asin", "acos", "atan",
      "log10", "log1p", "exp10", "expm1", "cbrt", "hypot", "asinh", "acosh", "atanh",
-     "erf", "erfc", "fdim", "fmax", "fmin"])}
+     "erf", "erfc", "fdim", "fmax", "fmin", "sqrt", "trunc", "floor", "ceil", "round",
+     "rint", "fabs", "logb", "copysign", "nextafter"])}
 
 DTYPE_MAX = {"f64": np.finfo(np.float64).max, "f32": float(np.finfo(np.float32).max),
              "f16": 65504.0, "bf16": 3.3895313892515355e38}
