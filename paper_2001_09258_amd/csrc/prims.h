@@ -66,7 +66,8 @@ LMH_INLINE float as_f32(int32_t x) { return __builtin_bit_cast(float, x); }
 // the transcendental unit in binary32: v_exp_f32 (2^x), v_log_f32 (log2 x)
 // and v_rcp_f32 (1/x), each within about one binary32 ulp.  Only the
 // narrow-format evaluators use them as results (their error is far below a
-// bf16 or f16 ulp, and every bf16 and f16 input is tested); the GPU build only
+// bf16 or f16 ulp, and every bf16 and f16 input is tested).  GPU build only:
+// the host build of the evaluators never includes those evaluators.
 LMH_INLINE float exp2_hw(float x) { return __builtin_amdgcn_exp2f(x); }
 LMH_INLINE float log2_hw(float x) { return __builtin_amdgcn_logf(x); }
 LMH_INLINE float rcp_hw(float x) { return __builtin_amdgcn_rcpf(x); }
