@@ -271,6 +271,32 @@ LIBM_HIP_DECL_EXACT1(fabs)
 LIBM_HIP_DECL_EXACT1(logb)
 
 /* ------------------------------------------------------------------------
+ * C99 functions with integer operands or results (7.12.6; the paper's
+ * library covers all C99 real functions, Section 1), binary64 and binary32,
+ * one element per index, integer arrays of int32_t:
+ *   ldexp:  y[i] = x[i] * 2^e[i] rounded once (scalbn is the same function
+ *           for binary formats); exponents beyond +-2200 (binary32: +-400)
+ *           act as those bounds, where every finite nonzero x already
+ *           overflows or underflows.
+ *   ilogb:  e[i] = the exponent of x[i] as if normalized; INT_MIN for +-0
+ *           and NaN (FP_ILOGB0 = FP_ILOGBNAN), INT_MAX for +-inf.
+ *   frexp:  m[i] in [0.5, 1) with x[i] = m[i] * 2^e[i]; +-0, +-inf and NaN
+ *           give m[i] = x[i], e[i] = 0.
+ * Exact.  Any alignment; not served by libm_hip_eval or the batch API
+ * (their requests carry floating-point operands only).
+ * ---------------------------------------------------------------------- */
+libm_hip_status libm_hip_ldexp_f64(const double* x, const int32_t* e, double* y, size_t n,
+                                   void* stream);
+libm_hip_status libm_hip_ldexp_f32(const float* x, const int32_t* e, float* y, size_t n,
+                                   void* stream);
+libm_hip_status libm_hip_ilogb_f64(const double* x, int32_t* e, size_t n, void* stream);
+libm_hip_status libm_hip_ilogb_f32(const float* x, int32_t* e, size_t n, void* stream);
+libm_hip_status libm_hip_frexp_f64(const double* x, double* m, int32_t* e, size_t n,
+                                   void* stream);
+libm_hip_status libm_hip_frexp_f32(const float* x, float* m, int32_t* e, size_t n,
+                                   void* stream);
+
+/* ------------------------------------------------------------------------
  * Backward (vector-Jacobian products) for autograd; not part of the paper.
  * gx[i] = gy[i] * f'(x[i]) for sin, cos, tan, exp, log, tanh, evaluated from
  * the u10 forward pieces (tanh' as 1/cosh^2, never 1 - tanh^2).  Binary:

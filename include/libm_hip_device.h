@@ -176,6 +176,19 @@ __device__ __forceinline__ double fmax(double x, double y) { return lmh_ops::OpF
 __device__ __forceinline__ float fmax(float x, float y) { return lmh_ops::OpFmax::f(x, y); }
 __device__ __forceinline__ double fmin(double x, double y) { return lmh_ops::OpFmin::f(x, y); }
 __device__ __forceinline__ float fmin(float x, float y) { return lmh_ops::OpFmin::f(x, y); }
+/* ldexp, ilogb, frexp (C99 7.12.6): as the entry points of libm_hip.h */
+__device__ __forceinline__ double ldexp(double x, int n) { return lmh_ops::OpIntFns::ldexp(x, n); }
+__device__ __forceinline__ float ldexp(float x, int n) { return lmh_ops::OpIntFns::ldexp(x, n); }
+__device__ __forceinline__ int ilogb(double x) { return lmh_ops::OpIntFns::ilogb(x); }
+__device__ __forceinline__ int ilogb(float x) { return lmh_ops::OpIntFns::ilogb(x); }
+__device__ __forceinline__ double frexp(double x, int* e) {
+  *e = lmh_ops::OpIntFns::frexp_exp(x);
+  return lmh_ops::OpIntFns::frexp_mant(x);
+}
+__device__ __forceinline__ float frexp(float x, int* e) {
+  *e = lmh_ops::OpIntFns::frexp_exp(x);
+  return lmh_ops::OpIntFns::frexp_mant(x);
+}
 /* the rest of the exact C99 set: sqrt (correctly rounded), trunc, floor, ceil,
    round, rint, fabs, logb, copysign, nextafter */
 __device__ __forceinline__ double sqrt(double x) { return lmh_ops::OpSqrt::f(x); }

@@ -130,6 +130,13 @@ def load():
         f.restype = ctypes.c_int
         f.argtypes = [vp, vp, vp, sz, vp] if fn in BWD_UNARY else [vp, vp, vp, vp, vp, sz, vp]
     lib.libm_hip_eval.restype = ctypes.c_int
+    for nm in ("libm_hip_ldexp_f64", "libm_hip_ldexp_f32", "libm_hip_frexp_f64",
+               "libm_hip_frexp_f32"):
+        getattr(lib, nm).restype = ctypes.c_int
+        getattr(lib, nm).argtypes = [vp, vp, vp, sz, vp]
+    for nm in ("libm_hip_ilogb_f64", "libm_hip_ilogb_f32"):
+        getattr(lib, nm).restype = ctypes.c_int
+        getattr(lib, nm).argtypes = [vp, vp, sz, vp]
     lib.libm_hip_consistent_eval.restype = ctypes.c_int
     lib.libm_hip_consistent_eval.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp,
                                              vp, sz, vp]
@@ -555,3 +562,60 @@ def host_consistent(fn, a, b=None, variant=None):
     if st != 0:
         raise LibmHipError("libm_hip_host_eval failed with status %d" % st)
     return out
+
+
+# ---------------------------------------------------------------------------
+# integer-operand functions (C99 7.12.6): ldexp, ilogb, frexp
+# ---------------------------------------------------------------------------
+def _fp_tag(a):
+    import torch
+    tag = {torch.float64: "f64", torch.float32: "f32"}.get(a.dtype)
+    if tag is None or not a.is_cuda:
+        raise TypeError("expects a float64 or float32 device tensor")
+    return tag
+
+
+def ldexp(x, e, out=None):
+    """x * 2^e elementwise (e an int32 device tensor of x's shape)."""
+    import torch
+    lib = load()
+    tag = _fp_tag(x)
+    x = x.contiguous()
+    e = e.to(torch.int32).contiguous()
+    if e.shape != x.shape or e.device != x.device:
+        raise ValueError("e must be an int32 tensor of x's shape on its device")
+    out = torch.empty_like(x) if out is None else out
+    with torch.cuda.device(x.device):
+        st = getattr(lib, "libm_hip_ldexp_" + tag)(x.data_ptr(), e.data_ptr(), out.data_ptr(),
+                                                   x.numel(), _stream_handle())
+    _check(st, "libm_hip_ldexp_" + tag)
+    return out
+
+
+def ilogb(x):
+    """The exponent of x as if normalized, as an int32 tensor."""
+    import torch
+    lib = load()
+    tag = _fp_tag(x)
+    x = x.contiguous()
+    e = torch.empty(x.shape, dtype=torch.int32, device=x.device)
+    with torch.cuda.device(x.device):
+        st = getattr(lib, "libm_hip_ilogb_" + tag)(x.data_ptr(), e.data_ptr(), x.numel(),
+                                                   _stream_handle())
+    _check(st, "libm_hip_ilogb_" + tag)
+    return e
+
+
+def frexp(x):
+    """(m, e): m in [0.5, 1) of x's dtype and e int32 with x = m * 2^e."""
+    import torch
+    lib = load()
+    tag = _fp_tag(x)
+    x = x.contiguous()
+    m = torch.empty_like(x)
+    e = torch.empty(x.shape, dtype=torch.int32, device=x.device)
+    with torch.cuda.device(x.device):
+        st = getattr(lib, "libm_hip_frexp_" + tag)(x.data_ptr(), m.data_ptr(), e.data_ptr(),
+                                                   x.numel(), _stream_handle())
+    _check(st, "libm_hip_frexp_" + tag)
+    return m, e

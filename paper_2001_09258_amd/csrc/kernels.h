@@ -292,4 +292,30 @@ __global__ __launch_bounds__(MAX_BLOCK) void k_ternary2(const typename Io::S* __
 }
 
 
+// Elementwise kernels of the integer-operand functions (ldexp, ilogb,
+// frexp): one element per lane, grid-stride, any alignment.  T is the
+// floating-point type, F a tag with the element function.
+constexpr int MAP_BLOCK = 256;
+template <class T, class F>
+__global__ __launch_bounds__(MAP_BLOCK) void k_ldexp(const T* x, const int* e, T* y, size_t n) {
+  size_t stride = (size_t)gridDim.x * MAP_BLOCK;
+  for (size_t i = (size_t)blockIdx.x * MAP_BLOCK + threadIdx.x; i < n; i += stride)
+    y[i] = F::ldexp(x[i], e[i]);
+}
+template <class T, class F>
+__global__ __launch_bounds__(MAP_BLOCK) void k_ilogb(const T* x, int* e, size_t n) {
+  size_t stride = (size_t)gridDim.x * MAP_BLOCK;
+  for (size_t i = (size_t)blockIdx.x * MAP_BLOCK + threadIdx.x; i < n; i += stride)
+    e[i] = F::ilogb(x[i]);
+}
+template <class T, class F>
+__global__ __launch_bounds__(MAP_BLOCK) void k_frexp(const T* x, T* m, int* e, size_t n) {
+  size_t stride = (size_t)gridDim.x * MAP_BLOCK;
+  for (size_t i = (size_t)blockIdx.x * MAP_BLOCK + threadIdx.x; i < n; i += stride) {
+    T v = x[i];
+    m[i] = F::frexp_mant(v);
+    e[i] = F::frexp_exp(v);
+  }
+}
+
 }  // namespace lmh_kernels

@@ -468,6 +468,70 @@ libm_hip_status dispatch_binary(libm_hip_dtype t, const void* a, const void* b, 
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// integer-operand functions: ldexp, ilogb, frexp (binary64, binary32)
+// ---------------------------------------------------------------------------
+namespace {
+inline unsigned map_grid(size_t n) {
+  size_t b = (n + MAP_BLOCK - 1) / MAP_BLOCK;
+  return (unsigned)(b < 65536 ? b : 65536);
+}
+template <class T>
+libm_hip_status run_ldexp(const T* x, const int32_t* e, T* y, size_t n, void* s, const char* nm) {
+  if (n == 0) return LIBM_HIP_OK;
+  if (!x || !e || !y) {
+    set_error("libm_hip: NULL pointer with n > 0");
+    return LIBM_HIP_ERR_INVALID;
+  }
+  hipLaunchKernelGGL((k_ldexp<T, OpIntFns>), dim3(map_grid(n)), dim3(MAP_BLOCK), 0,
+                     (hipStream_t)s, x, (const int*)e, y, n);
+  return launch_error(nm);
+}
+template <class T>
+libm_hip_status run_ilogb(const T* x, int32_t* e, size_t n, void* s, const char* nm) {
+  if (n == 0) return LIBM_HIP_OK;
+  if (!x || !e) {
+    set_error("libm_hip: NULL pointer with n > 0");
+    return LIBM_HIP_ERR_INVALID;
+  }
+  hipLaunchKernelGGL((k_ilogb<T, OpIntFns>), dim3(map_grid(n)), dim3(MAP_BLOCK), 0,
+                     (hipStream_t)s, x, (int*)e, n);
+  return launch_error(nm);
+}
+template <class T>
+libm_hip_status run_frexp(const T* x, T* m, int32_t* e, size_t n, void* s, const char* nm) {
+  if (n == 0) return LIBM_HIP_OK;
+  if (!x || !m || !e) {
+    set_error("libm_hip: NULL pointer with n > 0");
+    return LIBM_HIP_ERR_INVALID;
+  }
+  hipLaunchKernelGGL((k_frexp<T, OpIntFns>), dim3(map_grid(n)), dim3(MAP_BLOCK), 0,
+                     (hipStream_t)s, x, m, (int*)e, n);
+  return launch_error(nm);
+}
+}  // namespace
+
+extern "C" {
+libm_hip_status libm_hip_ldexp_f64(const double* x, const int32_t* e, double* y, size_t n, void* s) {
+  return run_ldexp(x, e, y, n, s, "ldexp_f64");
+}
+libm_hip_status libm_hip_ldexp_f32(const float* x, const int32_t* e, float* y, size_t n, void* s) {
+  return run_ldexp(x, e, y, n, s, "ldexp_f32");
+}
+libm_hip_status libm_hip_ilogb_f64(const double* x, int32_t* e, size_t n, void* s) {
+  return run_ilogb(x, e, n, s, "ilogb_f64");
+}
+libm_hip_status libm_hip_ilogb_f32(const float* x, int32_t* e, size_t n, void* s) {
+  return run_ilogb(x, e, n, s, "ilogb_f32");
+}
+libm_hip_status libm_hip_frexp_f64(const double* x, double* m, int32_t* e, size_t n, void* s) {
+  return run_frexp(x, m, e, n, s, "frexp_f64");
+}
+libm_hip_status libm_hip_frexp_f32(const float* x, float* m, int32_t* e, size_t n, void* s) {
+  return run_frexp(x, m, e, n, s, "frexp_f32");
+}
+}  // extern "C"
+
 extern "C" libm_hip_status libm_hip_eval(libm_hip_fn fn, libm_hip_variant v, libm_hip_dtype t,
                                          const void* a, const void* b, void* out, size_t n,
                                          void* s) {

@@ -185,6 +185,17 @@ LMH_OP1(OpFabs, fabs_f64, fabsf_f32)
 LMH_OP1(OpLogb, logb_f64, logbf_f32)
 LMH_OP2(OpCopysign, copysign_f64, copysignf_f32)
 LMH_OP2(OpNextafter, nextafter_f64, nextafterf_f32)
+// the integer-operand functions
+struct OpIntFns {
+  static __device__ __forceinline__ double ldexp(double x, int n) { return lmh::ldexp_f64(x, n); }
+  static __device__ __forceinline__ float ldexp(float x, int n) { return lmh::ldexpf_f32(x, n); }
+  static __device__ __forceinline__ int ilogb(double x) { return lmh::ilogb_f64(x); }
+  static __device__ __forceinline__ int ilogb(float x) { return lmh::ilogbf_f32(x); }
+  static __device__ __forceinline__ double frexp_mant(double x) { return lmh::frexp_mant_f64(x); }
+  static __device__ __forceinline__ float frexp_mant(float x) { return lmh::frexp_mantf_f32(x); }
+  static __device__ __forceinline__ int frexp_exp(double x) { return lmh::frexp_exp_f64(x); }
+  static __device__ __forceinline__ int frexp_exp(float x) { return lmh::frexp_expf_f32(x); }
+};
 
 // backward tags: (x, g) -> g f'(x); (a, b, g) -> two partials
 #define LMH_OPB(NAME, FN)                                                                   \

@@ -1,0 +1,74 @@
+"""ldexp, ilogb and frexp (C99 7.12.6) on the GPU against the oracle,
+element by element and bit for bit, binary64 and binary32: the benchmark
+mixture plus the special set, exponents uniform over the whole range and
+near the overflow and subnormal edges, and a ragged length."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import intfuncs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2001_09258_amd as L  # noqa: E402
+
+N = 3 * 4096 + 37
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L.load()
+
+
+def _x(dt, seed):
+    a = W.mixture("exp", dt, N, seed)
+    sp = W.specials(dt)
+    a[:sp.size] = sp
+    return a
+
+
+def _same(got, want):
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    eq = (got == want) & (np.signbit(got) == np.signbit(want))
+    return eq | (np.isnan(got) & np.isnan(want))
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_ldexp(dt):
+    a = _x(dt, 31)
+    lim = 2200 if dt == "f64" else 400
+    rng = np.random.default_rng(32)
+    e = rng.integers(-lim - 100, lim + 100, N).astype(np.int32)
+    edge = 1024 if dt == "f64" else 128
+    e[::3] = rng.integers(-edge - 60, edge + 5, e[::3].size)
+    ta = torch.from_numpy(a).cuda()
+    y = L.ldexp(ta, torch.from_numpy(e).cuda()).cpu().numpy()
+    want = np.array([I.ldexp(float(v), int(k), dt) for v, k in zip(a, e)])
+    bad = ~_same(y, want)
+    assert not bad.any(), (a[bad][:3], e[bad][:3], y[bad][:3], want[bad][:3])
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_ilogb_frexp(dt):
+    a = _x(dt, 33)
+    ta = torch.from_numpy(a).cuda()
+    e = L.ilogb(ta).cpu().numpy()
+    m, fe = L.frexp(ta)
+    m, fe = m.cpu().numpy(), fe.cpu().numpy()
+    want_e = np.array([I.ilogb(float(v)) for v in a])
+    assert (e == want_e).all(), a[e != want_e][:3]
+    fr = [I.frexp(float(v)) for v in a]
+    assert _same(m, [f[0] for f in fr]).all()
+    assert (fe == np.array([f[1] for f in fr])).all()
+
+
+def test_null_and_zero_length():
+    lib = L.load()
+    assert lib.libm_hip_ldexp_f64(None, None, None, 0, None) == 0
+    assert lib.libm_hip_ldexp_f64(None, None, None, 3, None) == 1
+    assert lib.libm_hip_ilogb_f32(None, None, 3, None) == 1
+    assert lib.libm_hip_frexp_f64(None, None, None, 3, None) == 1

@@ -714,3 +714,29 @@ def test_exact_c99_set_against_host_operations():
         g = float(np.float32(y)) if abs(y) < 3e38 or not math.isfinite(y) else -1.0
         assert same(evaluate1("nextafter", "f32", f, g)[0],
                     float(np.nextafter(np.float32(f), np.float32(g)))), (f, g)
+
+
+def test_ldexp_ilogb_frexp_against_numpy():
+    """The integer-operand functions against numpy's ldexp and frexp (host
+    C library), binary64 and binary32, over random patterns, subnormals,
+    zeros, infinities and exponents across the whole range."""
+    from oracle import intfuncs as I
+    rng = random.Random(15)
+    xs = [0.0, -0.0, math.inf, -math.inf, 5e-324, -5e-324, 1.0, 0.75, 1.7976931348623157e308]
+    xs += [_rand_bits(rng) for _ in range(500)]
+    for x in xs:
+        if math.isnan(x):
+            assert I.ilogb(x) == I.INT_MIN and math.isnan(I.frexp(x)[0])
+            continue
+        m, e = np.frexp(x)
+        assert I.frexp(x) == (float(m), int(e) if math.isfinite(x) else 0) or \
+            (not math.isfinite(x) and I.frexp(x)[0] == x)
+        want = I.INT_MIN if x == 0 else (I.INT_MAX if math.isinf(x) else int(np.frexp(x)[1]) - 1)
+        assert I.ilogb(x) == want, x
+        for n in (rng.randint(-2200, 2200), rng.randint(-60, 60), -1074, 1023, 2100):
+            assert same(I.ldexp(x, n, "f64"), float(np.ldexp(x, n))), (x, n)
+            f = np.float32(x) if abs(x) < 3e38 or not math.isfinite(x) else np.float32(1.5)
+            n32 = max(-400, min(400, n))
+            with np.errstate(over="ignore", under="ignore"):
+                w = float(np.ldexp(f, n32))
+            assert same(I.ldexp(float(f), n32, "f32"), w), (float(f), n32)
