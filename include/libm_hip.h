@@ -282,9 +282,23 @@ LIBM_HIP_DECL_EXACT1(logb)
  *           and NaN (FP_ILOGB0 = FP_ILOGBNAN), INT_MAX for +-inf.
  *   frexp:  m[i] in [0.5, 1) with x[i] = m[i] * 2^e[i]; +-0, +-inf and NaN
  *           give m[i] = x[i], e[i] = 0.
+ *   modf:   f[i] = x[i] - trunc(x[i]), ip[i] = trunc(x[i]), both with the
+ *           sign of x[i]; +-inf gives (+-0, +-inf), NaN (NaN, NaN).
+ *   fma:    y[i] = a[i] * b[i] + c[i] rounded once (IEEE fused multiply-add).
+ *   lrint, lround: the nearest integer of x[i] as int64_t (halfway cases to
+ *           even / away from zero); INT64_MIN where it does not fit in
+ *           int64_t and for NaN (C99 leaves those unspecified).
  * Exact.  Any alignment; not served by libm_hip_eval or the batch API
- * (their requests carry floating-point operands only).
+ * (their requests carry one or two floating-point operands and one result).
  * ---------------------------------------------------------------------- */
+#define LIBM_HIP_DECL_MAPS(T, tag)                                                           \
+  libm_hip_status libm_hip_modf_##tag(const T* x, T* f, T* ip, size_t n, void* stream);    \
+  libm_hip_status libm_hip_fma_##tag(const T* a, const T* b, const T* c, T* y, size_t n,   \
+                                     void* stream);                                         \
+  libm_hip_status libm_hip_lrint_##tag(const T* x, int64_t* y, size_t n, void* stream);    \
+  libm_hip_status libm_hip_lround_##tag(const T* x, int64_t* y, size_t n, void* stream);
+LIBM_HIP_DECL_MAPS(double, f64)
+LIBM_HIP_DECL_MAPS(float, f32)
 libm_hip_status libm_hip_ldexp_f64(const double* x, const int32_t* e, double* y, size_t n,
                                    void* stream);
 libm_hip_status libm_hip_ldexp_f32(const float* x, const int32_t* e, float* y, size_t n,

@@ -189,6 +189,21 @@ __device__ __forceinline__ float frexp(float x, int* e) {
   *e = lmh_ops::OpIntFns::frexp_exp(x);
   return lmh_ops::OpIntFns::frexp_mant(x);
 }
+/* modf, fma, lrint, lround (C99): as the entry points of libm_hip.h */
+__device__ __forceinline__ double modf(double x, double* ip) {
+  *ip = lmh_ops::OpIntFns::modf_int(x);
+  return lmh_ops::OpIntFns::modf_frac(x);
+}
+__device__ __forceinline__ float modf(float x, float* ip) {
+  *ip = lmh_ops::OpIntFns::modf_int(x);
+  return lmh_ops::OpIntFns::modf_frac(x);
+}
+__device__ __forceinline__ double fma(double x, double y, double z) { return lmh_ops::OpIntFns::fma(x, y, z); }
+__device__ __forceinline__ float fma(float x, float y, float z) { return lmh_ops::OpIntFns::fma(x, y, z); }
+__device__ __forceinline__ long long lrint(double x) { return lmh_ops::OpIntFns::lrint(x); }
+__device__ __forceinline__ long long lrint(float x) { return lmh_ops::OpIntFns::lrint(x); }
+__device__ __forceinline__ long long lround(double x) { return lmh_ops::OpIntFns::lround(x); }
+__device__ __forceinline__ long long lround(float x) { return lmh_ops::OpIntFns::lround(x); }
 /* the rest of the exact C99 set: sqrt (correctly rounded), trunc, floor, ceil,
    round, rint, fabs, logb, copysign, nextafter */
 __device__ __forceinline__ double sqrt(double x) { return lmh_ops::OpSqrt::f(x); }

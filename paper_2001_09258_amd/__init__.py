@@ -619,3 +619,60 @@ def frexp(x):
                                                    x.numel(), _stream_handle())
     _check(st, "libm_hip_frexp_" + tag)
     return m, e
+
+
+def modf(x):
+    """(fraction, integral part) of x elementwise, both with x's sign."""
+    import torch
+    lib = load()
+    tag = _fp_tag(x)
+    x = x.contiguous()
+    f, ip = torch.empty_like(x), torch.empty_like(x)
+    nm = "libm_hip_modf_" + tag
+    with torch.cuda.device(x.device):
+        st = getattr(lib, nm)(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(f.data_ptr()),
+                              ctypes.c_void_p(ip.data_ptr()), ctypes.c_size_t(x.numel()),
+                              ctypes.c_void_p(_stream_handle()))
+    _check(st, nm)
+    return f, ip
+
+
+def fma(a, b, c):
+    """a * b + c rounded once, elementwise."""
+    import torch
+    lib = load()
+    tag = _fp_tag(a)
+    a, b, c = a.contiguous(), b.contiguous(), c.contiguous()
+    if not (a.shape == b.shape == c.shape and a.dtype == b.dtype == c.dtype):
+        raise ValueError("fma needs three tensors of equal shape and dtype")
+    y = torch.empty_like(a)
+    nm = "libm_hip_fma_" + tag
+    with torch.cuda.device(a.device):
+        st = getattr(lib, nm)(*[ctypes.c_void_p(t.data_ptr()) for t in (a, b, c, y)],
+                              ctypes.c_size_t(a.numel()), ctypes.c_void_p(_stream_handle()))
+    _check(st, nm)
+    return y
+
+
+def _to_int64(kind, x):
+    import torch
+    lib = load()
+    tag = _fp_tag(x)
+    x = x.contiguous()
+    y = torch.empty(x.shape, dtype=torch.int64, device=x.device)
+    nm = "libm_hip_%s_%s" % (kind, tag)
+    with torch.cuda.device(x.device):
+        st = getattr(lib, nm)(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                              ctypes.c_size_t(x.numel()), ctypes.c_void_p(_stream_handle()))
+    _check(st, nm)
+    return y
+
+
+def lrint(x):
+    """Nearest integer (ties to even) as int64; INT64_MIN where it does not fit."""
+    return _to_int64("lrint", x)
+
+
+def lround(x):
+    """Nearest integer (ties away from zero) as int64; INT64_MIN where it does not fit."""
+    return _to_int64("lround", x)

@@ -1000,6 +1000,23 @@ LMH_INLINE int ilogbf_f32(float x) {
 LMH_INLINE float frexp_mantf_f32(float x) { return frexp_mant_(x); }
 LMH_INLINE int frexp_expf_f32(float x) { return isfinite_(x) ? frexp_exp_(x) : 0; }
 
+// modf: the integral part trunc(x) and the fraction x - trunc(x) (exact),
+// both with the sign of x; inf -> (+-0, +-inf), NaN -> (NaN, NaN).  fma: one
+// IEEE fused multiply-add.  lrint / lround: rint(x) / round(x) as int64,
+// INT64_MIN where it does not fit (and for NaN), as the x86-64 conversion.
+LMH_INLINE float modf_fracf_f32(float x) {
+  float f = x - trunc_(x);
+  return copysign_(isinf_(x) ? 0.0f : f, x);
+}
+LMH_INLINE float modf_intf_f32(float x) { return trunc_(x); }
+LMH_INLINE float fmaf_f32(float x, float y, float z) { return fma_(x, y, z); }
+LMH_INLINE long long to_i64f_f32(float v) {
+  bool fits = v >= -0x1p63f && v < 0x1p63f;               // false for NaN
+  return fits ? (long long)v : (-9223372036854775807LL - 1);
+}
+LMH_INLINE long long lrintf_f32(float x) { return to_i64f_f32(rint_(x)); }
+LMH_INLINE long long lroundf_f32(float x) { return to_i64f_f32(roundf_f32(x)); }
+
 }  // namespace lmh
 
 #pragma STDC FP_CONTRACT DEFAULT

@@ -309,6 +309,28 @@ __global__ __launch_bounds__(MAP_BLOCK) void k_ilogb(const T* x, int* e, size_t 
     e[i] = F::ilogb(x[i]);
 }
 template <class T, class F>
+__global__ __launch_bounds__(MAP_BLOCK) void k_modf(const T* x, T* f, T* ip, size_t n) {
+  size_t stride = (size_t)gridDim.x * MAP_BLOCK;
+  for (size_t i = (size_t)blockIdx.x * MAP_BLOCK + threadIdx.x; i < n; i += stride) {
+    T v = x[i];
+    f[i] = F::modf_frac(v);
+    ip[i] = F::modf_int(v);
+  }
+}
+template <class T, class F>
+__global__ __launch_bounds__(MAP_BLOCK) void k_fma(const T* a, const T* b, const T* c, T* y,
+                                                   size_t n) {
+  size_t stride = (size_t)gridDim.x * MAP_BLOCK;
+  for (size_t i = (size_t)blockIdx.x * MAP_BLOCK + threadIdx.x; i < n; i += stride)
+    y[i] = F::fma(a[i], b[i], c[i]);
+}
+template <class T, class F, bool ROUND>
+__global__ __launch_bounds__(MAP_BLOCK) void k_lrint(const T* x, long long* y, size_t n) {
+  size_t stride = (size_t)gridDim.x * MAP_BLOCK;
+  for (size_t i = (size_t)blockIdx.x * MAP_BLOCK + threadIdx.x; i < n; i += stride)
+    y[i] = ROUND ? F::lround(x[i]) : F::lrint(x[i]);
+}
+template <class T, class F>
 __global__ __launch_bounds__(MAP_BLOCK) void k_frexp(const T* x, T* m, int* e, size_t n) {
   size_t stride = (size_t)gridDim.x * MAP_BLOCK;
   for (size_t i = (size_t)blockIdx.x * MAP_BLOCK + threadIdx.x; i < n; i += stride) {

@@ -509,9 +509,55 @@ libm_hip_status run_frexp(const T* x, T* m, int32_t* e, size_t n, void* s, const
                      (hipStream_t)s, x, m, (int*)e, n);
   return launch_error(nm);
 }
+#define LMH_MAP_CHECK(...)                                                                  \
+  if (n == 0) return LIBM_HIP_OK;                                                           \
+  if (__VA_ARGS__) {                                                                        \
+    set_error("libm_hip: NULL pointer with n > 0");                                         \
+    return LIBM_HIP_ERR_INVALID;                                                            \
+  }
+template <class T>
+libm_hip_status run_modf(const T* x, T* f, T* ip, size_t n, void* s, const char* nm) {
+  LMH_MAP_CHECK(!x || !f || !ip)
+  hipLaunchKernelGGL((k_modf<T, OpIntFns>), dim3(map_grid(n)), dim3(MAP_BLOCK), 0,
+                     (hipStream_t)s, x, f, ip, n);
+  return launch_error(nm);
+}
+template <class T>
+libm_hip_status run_fma(const T* a, const T* b, const T* c, T* y, size_t n, void* s,
+                        const char* nm) {
+  LMH_MAP_CHECK(!a || !b || !c || !y)
+  hipLaunchKernelGGL((k_fma<T, OpIntFns>), dim3(map_grid(n)), dim3(MAP_BLOCK), 0,
+                     (hipStream_t)s, a, b, c, y, n);
+  return launch_error(nm);
+}
+template <class T, bool ROUND>
+libm_hip_status run_lrint(const T* x, int64_t* y, size_t n, void* s, const char* nm) {
+  LMH_MAP_CHECK(!x || !y)
+  hipLaunchKernelGGL((k_lrint<T, OpIntFns, ROUND>), dim3(map_grid(n)), dim3(MAP_BLOCK), 0,
+                     (hipStream_t)s, x, (long long*)y, n);
+  return launch_error(nm);
+}
+#undef LMH_MAP_CHECK
 }  // namespace
 
 extern "C" {
+#define LMH_DEF_MAPS(T, tag)                                                                     \
+  libm_hip_status libm_hip_modf_##tag(const T* x, T* f, T* ip, size_t n, void* s) {            \
+    return run_modf(x, f, ip, n, s, "modf_" #tag);                                              \
+  }                                                                                              \
+  libm_hip_status libm_hip_fma_##tag(const T* a, const T* b, const T* c, T* y, size_t n,       \
+                                     void* s) {                                                  \
+    return run_fma(a, b, c, y, n, s, "fma_" #tag);                                              \
+  }                                                                                              \
+  libm_hip_status libm_hip_lrint_##tag(const T* x, int64_t* y, size_t n, void* s) {            \
+    return run_lrint<T, false>(x, y, n, s, "lrint_" #tag);                                      \
+  }                                                                                              \
+  libm_hip_status libm_hip_lround_##tag(const T* x, int64_t* y, size_t n, void* s) {           \
+    return run_lrint<T, true>(x, y, n, s, "lround_" #tag);                                      \
+  }
+LMH_DEF_MAPS(double, f64)
+LMH_DEF_MAPS(float, f32)
+#undef LMH_DEF_MAPS
 libm_hip_status libm_hip_ldexp_f64(const double* x, const int32_t* e, double* y, size_t n, void* s) {
   return run_ldexp(x, e, y, n, s, "ldexp_f64");
 }

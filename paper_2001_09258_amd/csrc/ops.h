@@ -195,6 +195,16 @@ struct OpIntFns {
   static __device__ __forceinline__ float frexp_mant(float x) { return lmh::frexp_mantf_f32(x); }
   static __device__ __forceinline__ int frexp_exp(double x) { return lmh::frexp_exp_f64(x); }
   static __device__ __forceinline__ int frexp_exp(float x) { return lmh::frexp_expf_f32(x); }
+  static __device__ __forceinline__ double modf_frac(double x) { return lmh::modf_frac_f64(x); }
+  static __device__ __forceinline__ float modf_frac(float x) { return lmh::modf_fracf_f32(x); }
+  static __device__ __forceinline__ double modf_int(double x) { return lmh::modf_int_f64(x); }
+  static __device__ __forceinline__ float modf_int(float x) { return lmh::modf_intf_f32(x); }
+  static __device__ __forceinline__ double fma(double x, double y, double z) { return lmh::fma_f64(x, y, z); }
+  static __device__ __forceinline__ float fma(float x, float y, float z) { return lmh::fmaf_f32(x, y, z); }
+  static __device__ __forceinline__ long long lrint(double x) { return lmh::lrint_f64(x); }
+  static __device__ __forceinline__ long long lrint(float x) { return lmh::lrintf_f32(x); }
+  static __device__ __forceinline__ long long lround(double x) { return lmh::lround_f64(x); }
+  static __device__ __forceinline__ long long lround(float x) { return lmh::lroundf_f32(x); }
 };
 
 // backward tags: (x, g) -> g f'(x); (a, b, g) -> two partials

@@ -72,3 +72,36 @@ def test_null_and_zero_length():
     assert lib.libm_hip_ldexp_f64(None, None, None, 3, None) == 1
     assert lib.libm_hip_ilogb_f32(None, None, 3, None) == 1
     assert lib.libm_hip_frexp_f64(None, None, None, 3, None) == 1
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_modf_lrint_lround(dt):
+    a = _x(dt, 34)
+    a[-64:] = np.array([0.5, -0.5, 1.5, -1.5, 2.5, -2.5, 1e19, -1e19, 9.2e18, -9.2e18] * 6 +
+                       [0.49999997, -0.49999997, 4.5, 3.0], dtype=a.dtype)
+    ta = torch.from_numpy(a).cuda()
+    f, ip = L.modf(ta)
+    want = [I.modf(float(v)) for v in a]
+    assert _same(f.cpu().numpy(), [w[0] for w in want]).all()
+    assert _same(ip.cpu().numpy(), [w[1] for w in want]).all()
+    r = L.lrint(ta).cpu().numpy()
+    assert (r == np.array([I.lrint(float(v)) for v in a], dtype=np.int64)).all()
+    r = L.lround(ta).cpu().numpy()
+    assert (r == np.array([I.lround(float(v)) for v in a], dtype=np.int64)).all()
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_fma(dt):
+    rng = np.random.default_rng(35)
+    a, b, c = _x(dt, 36), _x(dt, 37)[::-1].copy(), _x(dt, 38)
+    c[::4] = -(a[::4].astype(np.float64) * b[::4].astype(np.float64)).astype(a.dtype)  # cancellation
+    sp = W.specials(dt)
+    trip = np.array([(x, y, z) for x in sp for y in sp for z in sp], dtype=a.dtype)
+    a = np.concatenate([a, trip[:, 0]])
+    b = np.concatenate([b, trip[:, 1]])
+    c = np.concatenate([c, trip[:, 2]])
+    ta, tb, tc = (torch.from_numpy(np.ascontiguousarray(v)).cuda() for v in (a, b, c))
+    y = L.fma(ta, tb, tc).cpu().numpy()
+    want = np.array([I.fma(float(x), float(yv), float(z), dt) for x, yv, z in zip(a, b, c)])
+    bad = ~_same(y, want)
+    assert not bad.any(), (a[bad][:3], b[bad][:3], c[bad][:3], y[bad][:3], want[bad][:3])

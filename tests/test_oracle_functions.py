@@ -740,3 +740,33 @@ def test_ldexp_ilogb_frexp_against_numpy():
             with np.errstate(over="ignore", under="ignore"):
                 w = float(np.ldexp(f, n32))
             assert same(I.ldexp(float(f), n32, "f32"), w), (float(f), n32)
+
+
+def test_modf_fma_lrint_lround_against_host():
+    """modf against Python's math.modf, fma against the host C library's
+    fma, lrint against numpy's rint, lround against decimal's half-up
+    rounding (binary64)."""
+    import ctypes
+    import decimal
+    from oracle import intfuncs as I
+    libm = ctypes.CDLL("libm.so.6")
+    libm.fma.restype = ctypes.c_double
+    libm.fma.argtypes = [ctypes.c_double] * 3
+    rng = random.Random(16)
+    vals = [0.0, -0.0, math.inf, -math.inf, 0.5, -0.5, 2.5, -2.5, 1e19, -1e19, 5e-324]
+    vals += [_rand_bits(rng) for _ in range(300)] + [rng.uniform(-1e3, 1e3) for _ in range(200)]
+    vals = [v for v in vals if not math.isnan(v)]
+    for x in vals:
+        f, ip = I.modf(x)
+        wf, wip = math.modf(x)
+        assert same(f, wf) and same(ip, wip), x
+        if math.isfinite(x) and abs(x) < 9.2e18:
+            assert I.lrint(x) == int(np.rint(x)), x
+            d = decimal.Decimal(x).quantize(decimal.Decimal(1), rounding=decimal.ROUND_HALF_UP,
+                                            context=decimal.Context(prec=400))
+            assert I.lround(x) == int(d), x
+        else:
+            assert I.lrint(x) == I.INT64_MIN and I.lround(x) == I.INT64_MIN
+    for _ in range(3000):
+        a, b, c = (rng.choice(vals) for _ in range(3))
+        assert same(I.fma(a, b, c, "f64"), libm.fma(a, b, c)), (a, b, c)
