@@ -285,6 +285,10 @@ LIBM_HIP_DECL_EXACT1(logb)
  *   modf:   f[i] = x[i] - trunc(x[i]), ip[i] = trunc(x[i]), both with the
  *           sign of x[i]; +-inf gives (+-0, +-inf), NaN (NaN, NaN).
  *   fma:    y[i] = a[i] * b[i] + c[i] rounded once (IEEE fused multiply-add).
+ *   remquo: r[i] = remainder(x[i], y[i]) (bit-identical to the remainder
+ *           entry point), q[i] with the sign of x/y and the low three bits
+ *           of the magnitude of the quotient rounded to nearest-even; q = 0
+ *           where the remainder is NaN or y is infinite.
  *   lrint, lround: the nearest integer of x[i] as int64_t (halfway cases to
  *           even / away from zero); INT64_MIN where it does not fit in
  *           int64_t and for NaN (C99 leaves those unspecified).
@@ -296,7 +300,9 @@ LIBM_HIP_DECL_EXACT1(logb)
   libm_hip_status libm_hip_fma_##tag(const T* a, const T* b, const T* c, T* y, size_t n,   \
                                      void* stream);                                         \
   libm_hip_status libm_hip_lrint_##tag(const T* x, int64_t* y, size_t n, void* stream);    \
-  libm_hip_status libm_hip_lround_##tag(const T* x, int64_t* y, size_t n, void* stream);
+  libm_hip_status libm_hip_lround_##tag(const T* x, int64_t* y, size_t n, void* stream);   \
+  libm_hip_status libm_hip_remquo_##tag(const T* x, const T* y, T* r, int32_t* q, size_t n, \
+                                        void* stream);
 LIBM_HIP_DECL_MAPS(double, f64)
 LIBM_HIP_DECL_MAPS(float, f32)
 libm_hip_status libm_hip_ldexp_f64(const double* x, const int32_t* e, double* y, size_t n,

@@ -189,7 +189,15 @@ __device__ __forceinline__ float frexp(float x, int* e) {
   *e = lmh_ops::OpIntFns::frexp_exp(x);
   return lmh_ops::OpIntFns::frexp_mant(x);
 }
-/* modf, fma, lrint, lround (C99): as the entry points of libm_hip.h */
+/* remquo, modf, fma, lrint, lround (C99): as the entry points of libm_hip.h */
+__device__ __forceinline__ double remquo(double x, double y, int* q) {
+  *q = lmh_ops::OpIntFns::remquo_quo(x, y);
+  return lmh_ops::OpIntFns::remquo_rem(x, y);
+}
+__device__ __forceinline__ float remquo(float x, float y, int* q) {
+  *q = lmh_ops::OpIntFns::remquo_quo(x, y);
+  return lmh_ops::OpIntFns::remquo_rem(x, y);
+}
 __device__ __forceinline__ double modf(double x, double* ip) {
   *ip = lmh_ops::OpIntFns::modf_int(x);
   return lmh_ops::OpIntFns::modf_frac(x);

@@ -14,7 +14,7 @@ import math
 from .functions import _dyadic
 from .rounding import FORMATS, rn_dyadic
 
-__all__ = ["ldexp", "ilogb", "frexp", "modf", "fma", "lrint", "lround", "INT_MIN", "INT_MAX",
+__all__ = ["ldexp", "ilogb", "frexp", "modf", "fma", "lrint", "lround", "remquo", "INT_MIN", "INT_MAX",
            "INT64_MIN"]
 
 INT_MIN = -2 ** 31
@@ -112,3 +112,21 @@ def lround(x):
     k = math.floor(abs(q) + Fraction(1, 2))
     k = -k if q < 0 else k
     return k if -2 ** 63 <= k < 2 ** 63 else INT64_MIN
+
+
+def remquo(x, y):
+    """(remainder(x, y), quo): quo has the sign of x/y and the low three
+    bits of the magnitude of the quotient rounded to nearest-even (C99
+    7.12.10.3); NaN remainder and quo 0 for y = 0, infinite x or NaN; x and
+    quo 0 for infinite y."""
+    from fractions import Fraction
+    if math.isnan(x) or math.isnan(y) or math.isinf(x) or y == 0.0:
+        return math.nan, 0
+    if math.isinf(y):
+        return x, 0
+    q = round(Fraction(x) / Fraction(y))            # ties to even
+    r = Fraction(x) - q * Fraction(y)                # exact, representable
+    rv = float(r) if r != 0 else math.copysign(0.0, x)
+    neg = (math.copysign(1.0, x) < 0) != (math.copysign(1.0, y) < 0)
+    mag = abs(q) & 7
+    return rv, (-mag if neg else mag)

@@ -676,3 +676,22 @@ def lrint(x):
 def lround(x):
     """Nearest integer (ties away from zero) as int64; INT64_MIN where it does not fit."""
     return _to_int64("lround", x)
+
+
+def remquo(x, y):
+    """(remainder(x, y), quo) elementwise; quo int32 with the sign of x/y and
+    the quotient's low three bits."""
+    import torch
+    lib = load()
+    tag = _fp_tag(x)
+    x, y = x.contiguous(), y.contiguous()
+    if x.shape != y.shape or x.dtype != y.dtype:
+        raise ValueError("remquo needs two tensors of equal shape and dtype")
+    r = torch.empty_like(x)
+    q = torch.empty(x.shape, dtype=torch.int32, device=x.device)
+    nm = "libm_hip_remquo_" + tag
+    with torch.cuda.device(x.device):
+        st = getattr(lib, nm)(*[ctypes.c_void_p(t.data_ptr()) for t in (x, y, r, q)],
+                              ctypes.c_size_t(x.numel()), ctypes.c_void_p(_stream_handle()))
+    _check(st, nm)
+    return r, q

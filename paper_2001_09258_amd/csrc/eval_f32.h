@@ -1017,6 +1017,29 @@ LMH_INLINE long long to_i64f_f32(float v) {
 LMH_INLINE long long lrintf_f32(float x) { return to_i64f_f32(rint_(x)); }
 LMH_INLINE long long lroundf_f32(float x) { return to_i64f_f32(roundf_f32(x)); }
 
+// remquo: the remainder is remainder(x, y); quo carries the sign of x / y
+// and the low three bits of the quotient's magnitude rounded to nearest-even:
+// r8 = |x| mod 8|y| exactly (|x| itself where 8|y| overflows), its quotient
+// by |y| in [0, 7] from the exact signs of fma(-k, |y|, r8), then the same
+// halfway rule as the remainder.  quo = 0 for the NaN cases and infinite y.
+LMH_INLINE int remquo_quof_f32(float x, float y) {
+  float n = fabs_(x), d = fabs_(y);
+  float d8 = d * 8;                                   // exact or inf
+  bool special = !isfinite_(x) || !isfinite_(d) || d == 0.0f;
+  bool small = !(n >= d8);
+  float r8 = fmodf_core(special || small ? 0.0f : n, special || small ? 1.0f : d8);
+  r8 = small ? n : r8;
+  int q = 0;
+#pragma unroll
+  for (int k = 1; k < 8; ++k) q += fma_(-(float)k, d, r8) >= 0.0f ? 1 : 0;
+  float r = fma_(-(float)q, d, r8);                   // exact: r8 mod d
+  float twice = r + r;
+  q += (twice > d || (twice == d && (q & 1))) ? 1 : 0;
+  q &= 7;
+  q = (__builtin_signbit(x) != __builtin_signbit(y)) ? -q : q;
+  return special ? 0 : q;
+}
+
 }  // namespace lmh
 
 #pragma STDC FP_CONTRACT DEFAULT

@@ -309,6 +309,16 @@ __global__ __launch_bounds__(MAP_BLOCK) void k_ilogb(const T* x, int* e, size_t 
     e[i] = F::ilogb(x[i]);
 }
 template <class T, class F>
+__global__ __launch_bounds__(MAP_BLOCK) void k_remquo(const T* x, const T* y, T* r, int* q,
+                                                      size_t n) {
+  size_t stride = (size_t)gridDim.x * MAP_BLOCK;
+  for (size_t i = (size_t)blockIdx.x * MAP_BLOCK + threadIdx.x; i < n; i += stride) {
+    T a = x[i], b = y[i];
+    r[i] = F::remquo_rem(a, b);
+    q[i] = F::remquo_quo(a, b);
+  }
+}
+template <class T, class F>
 __global__ __launch_bounds__(MAP_BLOCK) void k_modf(const T* x, T* f, T* ip, size_t n) {
   size_t stride = (size_t)gridDim.x * MAP_BLOCK;
   for (size_t i = (size_t)blockIdx.x * MAP_BLOCK + threadIdx.x; i < n; i += stride) {

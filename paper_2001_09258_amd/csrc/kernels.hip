@@ -537,6 +537,14 @@ libm_hip_status run_lrint(const T* x, int64_t* y, size_t n, void* s, const char*
                      (hipStream_t)s, x, (long long*)y, n);
   return launch_error(nm);
 }
+template <class T>
+libm_hip_status run_remquo(const T* x, const T* y, T* r, int32_t* q, size_t n, void* s,
+                           const char* nm) {
+  LMH_MAP_CHECK(!x || !y || !r || !q)
+  hipLaunchKernelGGL((k_remquo<T, OpIntFns>), dim3(map_grid(n)), dim3(MAP_BLOCK), 0,
+                     (hipStream_t)s, x, y, r, (int*)q, n);
+  return launch_error(nm);
+}
 #undef LMH_MAP_CHECK
 }  // namespace
 
@@ -554,6 +562,10 @@ extern "C" {
   }                                                                                              \
   libm_hip_status libm_hip_lround_##tag(const T* x, int64_t* y, size_t n, void* s) {           \
     return run_lrint<T, true>(x, y, n, s, "lround_" #tag);                                      \
+  }                                                                                              \
+  libm_hip_status libm_hip_remquo_##tag(const T* x, const T* y, T* r, int32_t* q, size_t n,    \
+                                        void* s) {                                               \
+    return run_remquo(x, y, r, q, n, s, "remquo_" #tag);                                        \
   }
 LMH_DEF_MAPS(double, f64)
 LMH_DEF_MAPS(float, f32)

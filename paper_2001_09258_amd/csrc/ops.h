@@ -205,6 +205,10 @@ struct OpIntFns {
   static __device__ __forceinline__ long long lrint(float x) { return lmh::lrintf_f32(x); }
   static __device__ __forceinline__ long long lround(double x) { return lmh::lround_f64(x); }
   static __device__ __forceinline__ long long lround(float x) { return lmh::lroundf_f32(x); }
+  static __device__ __forceinline__ double remquo_rem(double x, double y) { return lmh::remainder_f64(x, y); }
+  static __device__ __forceinline__ float remquo_rem(float x, float y) { return lmh::remainderf_f32(x, y); }
+  static __device__ __forceinline__ int remquo_quo(double x, double y) { return lmh::remquo_quo_f64(x, y); }
+  static __device__ __forceinline__ int remquo_quo(float x, float y) { return lmh::remquo_quof_f32(x, y); }
 };
 
 // backward tags: (x, g) -> g f'(x); (a, b, g) -> two partials

@@ -105,3 +105,20 @@ def test_fma(dt):
     want = np.array([I.fma(float(x), float(yv), float(z), dt) for x, yv, z in zip(a, b, c)])
     bad = ~_same(y, want)
     assert not bad.any(), (a[bad][:3], b[bad][:3], c[bad][:3], y[bad][:3], want[bad][:3])
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_remquo(dt):
+    """remquo against the oracle: the remainder bit for bit (and equal to
+    the remainder entry point), the quotient's sign and low three bits."""
+    a = np.concatenate([W.large_args("fmod", dt, N, 40), _x(dt, 41)])
+    b = np.concatenate([W.large_args("fmod", dt, N, 42), _x(dt, 43)[::-1]])
+    ta, tb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    r, q = L.remquo(ta, tb)
+    r, q = r.cpu().numpy(), q.cpu().numpy()
+    want = [I.remquo(float(u), float(v)) for u, v in zip(a, b)]
+    assert _same(r, [w[0] for w in want]).all()
+    assert _same(r, L.remainder(ta, tb).cpu().numpy()).all()
+    wq = np.array([w[1] for w in want], dtype=np.int32)
+    bad = q != wq
+    assert not bad.any(), (a[bad][:3], b[bad][:3], q[bad][:3], wq[bad][:3])

@@ -770,3 +770,25 @@ def test_modf_fma_lrint_lround_against_host():
     for _ in range(3000):
         a, b, c = (rng.choice(vals) for _ in range(3))
         assert same(I.fma(a, b, c, "f64"), libm.fma(a, b, c)), (a, b, c)
+
+
+def test_remquo_against_host_libm():
+    """remquo against the host C library's remquo (binary64): the remainder
+    bit for bit and the quotient's sign and low three bits."""
+    import ctypes
+    from oracle import intfuncs as I
+    libm = ctypes.CDLL("libm.so.6")
+    libm.remquo.restype = ctypes.c_double
+    libm.remquo.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_int)]
+    rng = random.Random(17)
+    vals = [0.0, -0.0, math.inf, -math.inf, 1.0, -1.0, 0.75, 3.0, 2.5, 5e-324, 1e308]
+    vals += [_rand_bits(rng) for _ in range(300)] + [rng.uniform(-50, 50) for _ in range(200)]
+    vals = [v for v in vals if not math.isnan(v)]
+    for _ in range(4000):
+        x, y = rng.choice(vals), rng.choice(vals)
+        q = ctypes.c_int(0)
+        w = libm.remquo(x, y, ctypes.byref(q))
+        r, qq = I.remquo(x, y)
+        assert same(r, w), (x, y, r, w)
+        if math.isfinite(w) and math.isfinite(y):
+            assert qq % 8 == q.value % 8 and (qq == 0 or (qq < 0) == (q.value < 0)), (x, y, qq, q.value)
