@@ -7,11 +7,14 @@ cosh, tanh (u10), in binary64 and binary32, 2^26 elements each (30 kernel
 launches; the mixture of 49% U[-1e4, 1e4], 50% log-uniform magnitudes, 1%
 special values).  Inputs are resident in HBM before timing starts.
 
-Prints one JSON line: whole-step throughput in Gelem/s, the roofline of the
-dominant kernel (its own average duration, measured with HIP events recorded
-on the launch stream around every launch of the timed steps), per-function
-throughput with both roofline fractions, and the CPU oracle's rate on a
-bounded sample of the same inputs.
+Prints one compact JSON line on stdout (a few KB): whole-step throughput in
+Gelem/s, the roofline of the dominant kernel (its own average duration,
+measured with HIP events recorded on the launch stream around every launch
+of the timed steps), per-kernel throughput with both roofline fractions, and
+the CPU oracle's rate on a bounded sample of the same inputs.  The further
+measurements (precision forms, batch, autograd, large arguments, ...) go to
+stderr as they complete and, with the per-kernel details, to the file named
+by ``--out``.
 
 Rooflines.  HBM: algorithmic bytes per element (inputs read once, output
 written once) against 8 TB/s.  VALU: the evaluator's vector-ALU instructions
@@ -75,6 +78,8 @@ def parse():
                    help="skip the bf16/f16/via-f64, batched and autograd measurements")
     p.add_argument("--narrow-n", type=int, default=1 << 28,
                    help="elements per bf16/f16 function")
+    p.add_argument("--out", default=os.path.join("gpurun_out", "bench_full.json"),
+                   help="file for the full result (every extra); '' to skip")
     return p.parse_args()
 
 
@@ -531,18 +536,8 @@ def extra_small_set(lib, L, stream, reps, ops):
     return res
 
 
-def cpu_baseline(inputs, sample):
-    """The oracle as it stands, on the first ``sample`` elements of every
-    (function, dtype) input of the step, over a process pool on all cores."""
-    import oracle
-    from oracle.batch import default_workers
-    workers = default_workers()
-    total = 0
-    t0 = time.perf_counter()
-    for (fn, v, dt), (a, b) in inputs.items():
-        oracle.evaluate(fn, dt, a[:sample], None if b is None else b[:sample], workers=workers)
-        total += min(sample, a.shape[0])
-    dt_s = time.perf_counter() - t0
+def host_cpu_info():
+    """CPU model name and the number of CPUs this process may use."""
     cpu = "unknown"
     try:
         with open("/proc/cpuinfo") as fh:
@@ -552,10 +547,38 @@ def cpu_baseline(inputs, sample):
                     break
     except OSError:
         pass
-    return {"value": total / dt_s / 1e9, "unit": "Gelem/s", "cores": workers,
-            "kind": "oracle", "host_cpu": cpu,
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        nproc = os.cpu_count() or 1
+    return cpu, nproc
+
+
+def cpu_baseline(inputs, sample):
+    """The oracle as it stands, on the first ``sample`` elements of every
+    (function, dtype) input of the step, over a process pool on the host's
+    cores; the pool is terminated and joined before returning."""
+    import oracle
+    from oracle.batch import default_workers, shutdown
+    workers = default_workers()
+    total = 0
+    t0 = time.perf_counter()
+    try:
+        for (fn, v, dt), (a, b) in inputs.items():
+            oracle.evaluate(fn, dt, a[:sample], None if b is None else b[:sample],
+                            workers=workers)
+            total += min(sample, a.shape[0])
+    finally:
+        shutdown()
+    dt_s = time.perf_counter() - t0
+    cpu, nproc = host_cpu_info()
+    rate = total / dt_s
+    return {"value": round(rate / 1e9, 7), "unit": "Gelem/s", "cores": workers,
+            "nproc": nproc, "kind": "oracle", "host_cpu": cpu,
+            "per_core_Melem_s": round(rate / workers / 1e6, 4),
             "sample": "first %d elements of each of the %d (function, dtype) inputs of the "
-                      "step (%d elements, %.1f s)" % (sample, len(inputs), total, dt_s)}
+                      "step (%d elements, %.1f s, %d worker processes)"
+                      % (sample, len(inputs), total, dt_s, workers)}
 
 
 def main():
@@ -705,30 +728,59 @@ def main():
               "per_function": per}
     if tuned:
         result["tuned_launch_shapes"] = tuned
+    extras = {}
     if not args.no_extras and not args.only:
         t_x = time.perf_counter()
-        result["precision_forms"] = extra_precision_forms(lib, L, stream, dev, n, args.narrow_n,
-                                                          args.reps)
-        result["batch"] = extra_batch(lib, L, stream, args.reps)
-        result["autograd"] = extra_autograd(lib, L, stream, args.reps)
-        result["per_gpu_share"] = extra_share(lib, L, stream, calls, n // 8, args.reps)
-        with open(OPS_FILE) as fh:
-            result["inverse_trig"] = extra_inverse_trig(lib, L, stream, n, args.reps,
-                                                        json.load(fh))
+
+        def extra(name, f, *fa):
+            extras[name] = f(*fa)
+            # every extra goes to stderr as it completes (and to the full file)
+            print("bench-extra %s %s" % (name, json.dumps(extras[name])), file=sys.stderr,
+                  flush=True)
         with open(OPS_FILE) as fh:
             ops = json.load(fh)
-        result["c99_functions"] = extra_functions(lib, L, stream, n, args.reps, ops, C99_EXTRA)
-        result["u35_forms"] = extra_functions(lib, L, stream, n, args.reps, ops, U35_EXTRA)
-        result["sincos"] = extra_sincos(lib, L, stream, n, args.reps)
-        result["large_args"] = extra_large_args(lib, L, stream, n, args.reps, ops)
-        result["trig_sorted_by_path"] = extra_sorted_paths(lib, L, stream, host, n, args.reps)
-        with open(OPS_FILE) as fh:
-            result["small_set_f64_warm"] = extra_small_set(lib, L, stream, args.reps, json.load(fh))
+        extra("precision_forms", extra_precision_forms, lib, L, stream, dev, n, args.narrow_n,
+              args.reps)
+        extra("batch", extra_batch, lib, L, stream, args.reps)
+        extra("autograd", extra_autograd, lib, L, stream, args.reps)
+        extra("per_gpu_share", extra_share, lib, L, stream, calls, n // 8, args.reps)
+        extra("inverse_trig", extra_inverse_trig, lib, L, stream, n, args.reps, ops)
+        extra("c99_functions", extra_functions, lib, L, stream, n, args.reps, ops, C99_EXTRA)
+        extra("u35_forms", extra_functions, lib, L, stream, n, args.reps, ops, U35_EXTRA)
+        extra("sincos", extra_sincos, lib, L, stream, n, args.reps)
+        extra("large_args", extra_large_args, lib, L, stream, n, args.reps, ops)
+        extra("trig_sorted_by_path", extra_sorted_paths, lib, L, stream, host, n, args.reps)
+        extra("small_set_f64_warm", extra_small_set, lib, L, stream, args.reps, ops)
         print("bench: extras in %.1f s" % (time.perf_counter() - t_x), file=sys.stderr,
               flush=True)
+    result.update(extras)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(host, args.cpu_sample)
-    print(json.dumps(result))
+    if args.out:
+        d = os.path.dirname(os.path.abspath(args.out))
+        os.makedirs(d, exist_ok=True)
+        with open(args.out, "w") as fh:
+            json.dump(result, fh, indent=1)
+    print(json.dumps(compact(result, args.out)))
+
+
+def compact(result, full_path):
+    """The one stdout line: the contract's keys, the roofline object, the
+    CPU baseline and per kernel (Gelem/s, HBM fraction, VALU fraction); the
+    extras stay in the full file."""
+    keep = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+            "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config",
+            "roofline")
+    out = {k: result[k] for k in keep}
+    if "cpu_baseline" in result:
+        out["cpu_baseline"] = result["cpu_baseline"]
+    out["copy_ceiling_frac"] = result["copy_ceiling"]["frac_of_peak"]
+    out["per_function"] = {"columns": ["gelem_s", "hbm_frac", "alu_frac"]}
+    for k, r in result["per_function"].items():
+        out["per_function"][k] = [r["gelem_s"], round(r["hbm_frac"], 3), round(r["alu_frac"], 3)]
+    if full_path:
+        out["full_results"] = full_path
+    return out
 
 
 if __name__ == "__main__":

@@ -12,15 +12,29 @@ import numpy as np
 
 from .functions import evaluate1
 
-__all__ = ["evaluate", "default_workers"]
+__all__ = ["evaluate", "default_workers", "shutdown"]
 
 _pool = None
 _pool_size = 0
 
 
 def default_workers():
-    n = os.cpu_count() or 1
+    """Worker processes: the CPUs this process may run on, at most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
     return max(1, min(16, n))
+
+
+def shutdown():
+    """Terminate and join the worker pool (if one was started)."""
+    global _pool, _pool_size
+    if _pool is not None:
+        _pool.terminate()
+        _pool.join()
+    _pool = None
+    _pool_size = 0
 
 
 def _chunk(args):

@@ -199,26 +199,59 @@ def _stream_handle():
     return torch.cuda.current_stream().cuda_stream
 
 
+def _operand(t, ref, what, dtype=None):
+    """Check that ``t`` is a device tensor on ``ref``'s device with ``ref``'s
+    shape and the given dtype (``ref``'s by default); returns it contiguous.
+    Raises before anything reaches a kernel."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a tensor" % what)
+    if not t.is_cuda or t.device != ref.device:
+        raise ValueError("%s must be a device tensor on %s" % (what, ref.device))
+    if t.shape != ref.shape:
+        raise ValueError("%s has shape %s, expected %s" % (what, tuple(t.shape),
+                                                            tuple(ref.shape)))
+    want = ref.dtype if dtype is None else dtype
+    if t.dtype != want:
+        raise ValueError("%s has dtype %s, expected %s" % (what, t.dtype, want))
+    return t.contiguous()
+
+
+def _output(t, ref, what, dtype=None):
+    """As ``_operand`` for a caller-supplied output, which must already be
+    contiguous (a copy would not be written back); None allocates one."""
+    import torch
+    if t is None:
+        return torch.empty(ref.shape, dtype=ref.dtype if dtype is None else dtype,
+                           device=ref.device)
+    _operand(t, ref, what, dtype)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    return t
+
+
+def _device_input(a):
+    import torch
+    if not isinstance(a, torch.Tensor) or not a.is_cuda:
+        raise ValueError("libm_hip evaluates device tensors only")
+    return a.contiguous()
+
+
 def evaluate(fn, a, b=None, variant=None, out=None, via_f64=False):
     """fn over device tensors (C argument order for binary functions)."""
     import torch
     load()
     if variant is None:
         variant = VARIANTS[fn][0]
-    if not a.is_cuda:
-        raise ValueError("libm_hip evaluates device tensors only")
-    a = a.contiguous()
+    a = _device_input(a)
     if fn in BINARY:
-        if b is None or b.shape != a.shape or b.dtype != a.dtype or b.device != a.device:
-            raise ValueError("binary functions need two tensors of equal shape, dtype, device")
-        b = b.contiguous()
+        if b is None:
+            raise ValueError("%s needs two tensors" % fn)
+        b = _operand(b, a, "second operand")
     tag = _dtype_tag(a, via_f64)
     if not served(fn, variant, tag):
         raise ValueError("%s %s is not served for %s" % (fn, variant, tag))
-    if out is None:
-        out = torch.empty_like(a)
-    elif out.shape != a.shape or out.dtype != a.dtype or not out.is_contiguous():
-        raise ValueError("out must be a contiguous tensor like the input")
+    out = _output(out, a, "out")
     with torch.cuda.device(a.device):
         call(fn, variant, tag, a.data_ptr(), 0 if b is None else b.data_ptr(),
              out.data_ptr(), a.numel(), _stream_handle())
@@ -259,16 +292,17 @@ def sincos(x, variant="u10", outs=None, via_f64=False):
     """(sin x, cos x) elementwise in one pass, each bit-identical to sin and
     cos of the same variant."""
     import torch
-    if x.device.type != "cuda" or not x.is_contiguous():
-        raise LibmHipError("sincos: expected a contiguous HIP tensor")
+    x = _device_input(x)
     tag = _dtype_tag(x, via_f64)
     if not served("sin", variant, tag):
         raise LibmHipError("sincos: %s %s is not served" % (variant, tag))
-    s, c = (torch.empty_like(x), torch.empty_like(x)) if outs is None else outs
+    s, c = (None, None) if outs is None else outs
+    s, c = _output(s, x, "sin output"), _output(c, x, "cos output")
     name = "libm_hip_sincos_%s_%s" % (variant, tag)
     lib = load()
-    _check(getattr(lib, name)(x.data_ptr(), s.data_ptr(), c.data_ptr(), x.numel(),
-                              _stream_handle()), name)
+    with torch.cuda.device(x.device):
+        _check(getattr(lib, name)(x.data_ptr(), s.data_ptr(), c.data_ptr(), x.numel(),
+                                  _stream_handle()), name)
     return s, c
 
 
@@ -327,21 +361,28 @@ def backward(fn, inputs, gout, outs=None):
     ``gout`` the upstream gradient; returns the input gradient(s)."""
     import torch
     load()
-    tag = _dtype_tag(inputs[0], False)
+    x0 = _device_input(inputs[0])
+    tag = _dtype_tag(x0, False)
     if tag not in ("f64", "f32"):
         raise TypeError("backward kernels take float64 or float32")
     name = "libm_hip_%s_u10_%s_bwd" % (fn, tag)
     f = getattr(load(), name)
-    ins = [t.contiguous() for t in inputs]
-    g = gout.contiguous()
+    k = 1 if fn in BWD_UNARY else 2
+    if len(inputs) != k:
+        raise ValueError("%s backward takes %d saved input(s)" % (fn, k))
+    ins = [x0] + [_operand(t, x0, "saved input %d" % i) for i, t in enumerate(inputs[1:], 1)]
+    g = _operand(gout, x0, "upstream gradient")
     n = ins[0].numel()
+    outs = (None,) * k if outs is None else tuple(outs)
+    if len(outs) != k:
+        raise ValueError("%s backward writes %d gradient(s)" % (fn, k))
     with torch.cuda.device(ins[0].device):
         if fn in BWD_UNARY:
-            gx = torch.empty_like(ins[0]) if outs is None else outs[0]
+            gx = _output(outs[0], x0, "gradient output")
             _check(f(ins[0].data_ptr(), g.data_ptr(), gx.data_ptr(), n, _stream_handle()), name)
             return (gx,)
-        g0 = torch.empty_like(ins[0]) if outs is None else outs[0]
-        g1 = torch.empty_like(ins[0]) if outs is None else outs[1]
+        g0 = _output(outs[0], x0, "gradient output 0")
+        g1 = _output(outs[1], x0, "gradient output 1")
         _check(f(ins[0].data_ptr(), ins[1].data_ptr(), g.data_ptr(), g0.data_ptr(),
                  g1.data_ptr(), n, _stream_handle()), name)
         return (g0, g1)
@@ -455,8 +496,13 @@ def tune(fn, a, b=None, variant=None, out=None, via_f64=False):
     import torch
     lib = _tune_lib()
     variant = variant or VARIANTS[fn][0]
+    a = _device_input(a)
+    if fn in BINARY:
+        if b is None:
+            raise ValueError("%s needs two tensors" % fn)
+        b = _operand(b, a, "second operand")
     tag = _dtype_tag(a, via_f64)
-    out = torch.empty_like(a) if out is None else out
+    out = _output(out, a, "out")
     blk, pk = ctypes.c_int(0), ctypes.c_int(0)
     st = lib.libm_hip_tune(FN_CODES[fn], VARIANT_CODES[variant], DTYPE_CODES[tag], a.data_ptr(),
                            None if b is None else b.data_ptr(), out.data_ptr(), a.numel(),
@@ -523,17 +569,15 @@ def consistent(fn, a, b=None, variant=None, out=None):
     import torch
     lib = load()
     f, v = _consistent_args(fn, variant)
-    if not a.is_cuda:
-        raise ValueError("libm_hip evaluates device tensors only")
+    a = _device_input(a)
     tag = {torch.float64: "f64", torch.float32: "f32"}.get(a.dtype)
     if tag is None:
         raise TypeError("the bit-consistent form takes float64 or float32")
-    a = a.contiguous()
     if fn in BINARY:
-        if b is None or b.shape != a.shape or b.dtype != a.dtype or b.device != a.device:
-            raise ValueError("binary functions need two tensors of equal shape, dtype, device")
-        b = b.contiguous()
-    out = torch.empty_like(a) if out is None else out
+        if b is None:
+            raise ValueError("%s needs two tensors" % fn)
+        b = _operand(b, a, "second operand")
+    out = _output(out, a, "out")
     with torch.cuda.device(a.device):
         st = lib.libm_hip_consistent_eval(f, v, DTYPE_CODES[tag], a.data_ptr(),
                                           None if b is None else b.data_ptr(), out.data_ptr(),
@@ -569,8 +613,10 @@ def host_consistent(fn, a, b=None, variant=None):
 # ---------------------------------------------------------------------------
 def _fp_tag(a):
     import torch
+    if not isinstance(a, torch.Tensor) or not a.is_cuda:
+        raise ValueError("expects a float64 or float32 device tensor")
     tag = {torch.float64: "f64", torch.float32: "f32"}.get(a.dtype)
-    if tag is None or not a.is_cuda:
+    if tag is None:
         raise TypeError("expects a float64 or float32 device tensor")
     return tag
 
@@ -581,10 +627,8 @@ def ldexp(x, e, out=None):
     lib = load()
     tag = _fp_tag(x)
     x = x.contiguous()
-    e = e.to(torch.int32).contiguous()
-    if e.shape != x.shape or e.device != x.device:
-        raise ValueError("e must be an int32 tensor of x's shape on its device")
-    out = torch.empty_like(x) if out is None else out
+    e = _operand(e, x, "exponent tensor", torch.int32)
+    out = _output(out, x, "out")
     with torch.cuda.device(x.device):
         st = getattr(lib, "libm_hip_ldexp_" + tag)(x.data_ptr(), e.data_ptr(), out.data_ptr(),
                                                    x.numel(), _stream_handle())
@@ -642,9 +686,8 @@ def fma(a, b, c):
     import torch
     lib = load()
     tag = _fp_tag(a)
-    a, b, c = a.contiguous(), b.contiguous(), c.contiguous()
-    if not (a.shape == b.shape == c.shape and a.dtype == b.dtype == c.dtype):
-        raise ValueError("fma needs three tensors of equal shape and dtype")
+    a = a.contiguous()
+    b, c = _operand(b, a, "second operand"), _operand(c, a, "third operand")
     y = torch.empty_like(a)
     nm = "libm_hip_fma_" + tag
     with torch.cuda.device(a.device):
@@ -684,9 +727,8 @@ def remquo(x, y):
     import torch
     lib = load()
     tag = _fp_tag(x)
-    x, y = x.contiguous(), y.contiguous()
-    if x.shape != y.shape or x.dtype != y.dtype:
-        raise ValueError("remquo needs two tensors of equal shape and dtype")
+    x = x.contiguous()
+    y = _operand(y, x, "second operand")
     r = torch.empty_like(x)
     q = torch.empty(x.shape, dtype=torch.int32, device=x.device)
     nm = "libm_hip_remquo_" + tag
