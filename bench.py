@@ -273,7 +273,7 @@ def extra_batch(lib, L, stream, reps):
     def run_batch():
         st = plan.run_raw(arr, len(tensors), sh)
         if st != 0:
-            raise RuntimeError("batch_run: %s" % lib.libm_hip_batch_last_error())
+            raise RuntimeError("batch_run: %s" % lib.libm_hip_last_error())
     singles = []
     for fn, var, dt, ta, tb, to in tensors:
         nm = L.entry_name(fn, var, dt)
@@ -409,13 +409,106 @@ def extra_functions(lib, L, stream, n, reps, ops, kinds):
     return res
 
 
+def fmod_valu(L, fn, dt, a, b, ops, m=1 << 20):
+    """Dynamic VALU work per element of fmod / remainder: the long-division
+    loop runs, for each element slot of a pack, as many digit steps as the
+    slowest of the wave's 64 lanes needs.  Step counts come from the host
+    build of the same evaluators (libm_hip_host_fmod_steps) on the first m
+    elements; a wave covers 64 consecutive packs of 16 bytes.  VALU per
+    element = (whole function - one step) + one step x mean wave steps.
+    Returns (valu, valu_f64, wave steps per element, lane steps per element)."""
+    import numpy as np
+    npd = np.float64 if dt == "f64" else np.float32
+    x = np.ascontiguousarray(a[:m], dtype=npd)
+    y = np.ascontiguousarray(b[:m], dtype=npd)
+    if fn == "remainder":
+        with np.errstate(over="ignore"):
+            y = y + y                                 # remainder runs fmod(|x|, 2|y|)
+    _, st = L.host_fmod_steps(x, y)
+    ept = 16 // ESIZE[dt]
+    wave = st[: (st.size // (64 * ept)) * 64 * ept].reshape(-1, 64, ept).max(axis=1)
+    pre = "p64_" if dt == "f64" else "p32_"
+    whole, step = ops[pre + fn], ops[pre + "fmodstep"]
+    wm = float(wave.mean())
+    vo = whole["valu"] - step["valu"] + step["valu"] * wm
+    v64 = whole["valu_f64"] - step["valu_f64"] + step["valu_f64"] * wm
+    return vo, v64, wm, float(st.mean())
+
+
+def extra_paper_domains(lib, L, stream, n, reps, ops):
+    """The paper's own benchmark domains (Section 7, table of reciprocal
+    throughputs), binary64, 2^26 uniform elements each: sin, cos, tan (u10,
+    u35) on U[0.4, 0.5], U[0, 6.28], U[0, 1e100]; asin, acos on U[-1, 1];
+    atan on U[-700, 700]; log on U[0, 1e300]; exp on U[-700, 700]; pow on
+    U[-30, 30]^2."""
+    import torch
+    import workloads as W
+    sh = stream.cuda_stream
+    res = {}
+    rows = [(fn, v, dom) for fn in ("sin", "cos", "tan") for v in ("u10", "u35")
+            for dom in W.PAPER_DOMAINS[fn]]
+    rows += [("asin", v, (-1.0, 1.0)) for v in ("u10", "u35")]
+    rows += [("acos", v, (-1.0, 1.0)) for v in ("u10", "u35")]
+    rows += [("atan", v, (-700.0, 700.0)) for v in ("u10", "u35")]
+    rows += [("log", v, dom) for v in ("u10", "u35") for dom in W.PAPER_DOMAINS["log"]]
+    rows += [("exp", "u10", dom) for dom in W.PAPER_DOMAINS["exp"]]
+    rows += [("pow", "u10", dom) for dom in W.PAPER_DOMAINS["pow"]]
+    for fn, v, (lo, hi) in rows:
+        ta = torch.from_numpy(W.paper_domain(fn, lo, hi, n, "f64", 0)).cuda()
+        to = torch.empty_like(ta)
+        nm = L.entry_name(fn, v, "f64")
+        if fn in L.BINARY:
+            tb = torch.from_numpy(W.paper_domain(fn, lo, hi, n, "f64", 1)).cuda()
+            args = (ta.data_ptr(), tb.data_ptr(), to.data_ptr(), n, sh)
+        else:
+            tb = None
+            args = (ta.data_ptr(), to.data_ptr(), n, sh)
+        ms = time_launches(stream, [checked(lib, nm, getattr(lib, nm), *args)], reps)[0]
+        nb = 8 * (3 if fn in L.BINARY else 2)
+        res["%s_%s_f64 [%g, %g]" % (fn, v, lo, hi)] = {
+            "ms": round(ms, 4), "gelem_s": round(n / ms / 1e6, 2),
+            "hbm_frac": round(nb * n / HBM_PEAK / (ms * 1e-3), 4)}
+        del ta, tb, to
+    return res
+
+
+def extra_fmod_ratio_sweep(lib, L, stream, reps, ops, n=1 << 24):
+    """The paper's fmod benchmark (Section 7, the fmod figure): binary64
+    fmod with d ~ U[1, 100] and n = r d U[0.95, 1.05] for r = 10^0, 10^0.5,
+    ..., 10^25, 2^24 elements per point; time, mean wave steps (the loop
+    count the slowest lane of each wave sets) and VALU fraction."""
+    import numpy as np
+    import torch
+    import workloads as W
+    sh = stream.cuda_stream
+    res = {}
+    nm = L.entry_name("fmod", "exact", "f64")
+    for k in range(51):
+        e = k / 2.0
+        rng = W.rng_for(11, "fmod", k)
+        d = rng.uniform(1.0, 100.0, n)
+        x = 10.0 ** e * d * rng.uniform(0.95, 1.05, n)
+        ta, tb = torch.from_numpy(x).cuda(), torch.from_numpy(d).cuda()
+        to = torch.empty_like(ta)
+        ms = time_launches(stream, [checked(lib, nm, getattr(lib, nm), ta.data_ptr(),
+                                            tb.data_ptr(), to.data_ptr(), n, sh)], reps)[0]
+        vo, v64, wm, em = fmod_valu(L, "fmod", "f64", x, d, ops)
+        slots = max(v64, vo / 2)
+        res["1e%.1f" % e] = {"ms": round(ms, 4), "gelem_s": round(n / ms / 1e6, 2),
+                             "wave_steps_per_elem": round(wm, 3), "valu_per_elem": round(vo, 1),
+                             "alu_frac": round(slots * n / VALU_SLOTS / (ms * 1e-3), 4)}
+        del ta, tb, to
+    return res
+
+
 def extra_large_args(lib, L, stream, n, reps, ops):
     """The large-argument workload on 2^26 elements: sin, cos, tan (u10,
     u35) on half sign * 10^U[5, log10 max] and half near multiples of pi/2
     (almost every element takes Payne-Hanek), fmod and remainder on operands
     log-uniform over the whole range (long quotient loops); binary64 and
-    binary32.  Trig kernels get the step's roofline fractions; the remainder
-    loops' work depends on the operands, so they get time and HBM only."""
+    binary32.  Trig kernels get the step's roofline fractions; fmod and
+    remainder get their VALU work from the digit steps their waves take
+    (fmod_valu)."""
     import numpy as np
     import torch
     import workloads as W
@@ -431,7 +524,8 @@ def extra_large_args(lib, L, stream, n, reps, ops):
             to = torch.empty_like(ta)
             nm = L.entry_name(fn, var, dt)
             if binary:
-                tb = torch.from_numpy(W.large_args(fn, dt, n, 1)).cuda()
+                bh = W.large_args(fn, dt, n, 1)
+                tb = torch.from_numpy(bh).cuda()
                 args = (ta.data_ptr(), tb.data_ptr(), to.data_ptr(), n, sh)
             else:
                 tb = None
@@ -445,6 +539,13 @@ def extra_large_args(lib, L, stream, n, reps, ops):
                 slots = max(v64, vo / 2)
                 r.update({"payne_hanek_share": round(float(slow), 4), "valu_per_elem": vo,
                           "valu_f64_per_elem": v64,
+                          "alu_frac": round(slots * n / VALU_SLOTS / (ms * 1e-3), 4)})
+            else:
+                vo, v64, wsteps, esteps = fmod_valu(L, fn, dt, a, bh, ops)
+                slots = max(v64, vo / 2)
+                r.update({"valu_per_elem": round(vo, 1), "valu_f64_per_elem": round(v64, 1),
+                          "wave_steps_per_elem": round(wsteps, 3),
+                          "lane_steps_per_elem": round(esteps, 3),
                           "alu_frac": round(slots * n / VALU_SLOTS / (ms * 1e-3), 4)})
             res["%s_%s_%s" % (fn, var, dt)] = r
             del ta, tb, to
@@ -749,6 +850,8 @@ def main():
         extra("u35_forms", extra_functions, lib, L, stream, n, args.reps, ops, U35_EXTRA)
         extra("sincos", extra_sincos, lib, L, stream, n, args.reps)
         extra("large_args", extra_large_args, lib, L, stream, n, args.reps, ops)
+        extra("paper_domains", extra_paper_domains, lib, L, stream, n, args.reps, ops)
+        extra("fmod_ratio_sweep", extra_fmod_ratio_sweep, lib, L, stream, args.reps, ops)
         extra("trig_sorted_by_path", extra_sorted_paths, lib, L, stream, host, n, args.reps)
         extra("small_set_f64_warm", extra_small_set, lib, L, stream, args.reps, ops)
         print("bench: extras in %.1f s" % (time.perf_counter() - t_x), file=sys.stderr,

@@ -320,9 +320,17 @@ libm_hip_status libm_hip_frexp_f32(const float* x, float* m, int32_t* e, size_t 
  * Backward (vector-Jacobian products) for autograd; not part of the paper.
  * gx[i] = gy[i] * f'(x[i]) for sin, cos, tan, exp, log, tanh, evaluated from
  * the u10 forward pieces (tanh' as 1/cosh^2, never 1 - tanh^2).  Binary:
- *   pow:   gx = gout * y * x^(y-1),  gy = gout * x^y * log(x)  (x > 0;
- *          gy = 0 at x == 0 with y >= 0, NaN for x < 0);
- *   atan2: gy = gout * x / (x^2 + y^2), gx = -gout * y / (x^2 + y^2).
+ *   pow:   gx = gout * y * x^(y-1),  gy = gout * x^y * log(x)  (x > 0, and
+ *          x < 0 with integer y for gx; each rounded once, also where the
+ *          power or the product over- or underflows); at x == +-0 gx =
+ *          gout * y * pow(x, y - 1) with Annex F pow (0 for y == 0) and gy
+ *          = 0 for y >= 0, NaN for y < 0; gy is NaN for x < 0, both are NaN
+ *          for x < 0 with non-integer y;
+ *   atan2: gy = gout * x / (x^2 + y^2), gx = -gout * y / (x^2 + y^2), with x
+ *          and y scaled by a common power of two (no overflow or underflow
+ *          of the squares); both NaN at (0, 0).
+ * Bounds (against the correctly rounded products): 2.5 ULP for the unary
+ * gradients, 4 ULP for the pow and atan2 partials.
  * Same conventions as the forward calls (device pointers, n, stream).
  * ---------------------------------------------------------------------- */
 #define LIBM_HIP_DECL_BWD(fn)                                                              \
@@ -423,20 +431,26 @@ void libm_hip_tune_reset(void);
  * evaluators).  Requests are cut into 4096-element tiles that workgroups take
  * from a device counter, most expensive requests first.
  *
- * libm_hip_batch_plan_create: allocates the plan's device request table (up
- *   to max_requests <= 1024 entries), a pinned staging copy, a tile counter,
- *   a private capture stream; use_graph != 0 replays a captured graph, 0
- *   launches the kernels directly.  The plan owns these; destroy frees them
+ * libm_hip_batch_plan_create: makes a plan on `device` (-1: the calling
+ *   thread's current device), allocating there the device request table (up
+ *   to max_requests <= 1024 entries), a tile counter, a pinned staging copy
+ *   and a private capture stream.  The plan owns these; destroy frees them
  *   (call it once the plan's last run has completed, e.g. after synchronizing
  *   its stream).  The persistent grid holds as many 256-lane workgroups per
- *   CU as can be resident together.
+ *   CU as can be resident together.  Runs replay a captured hip graph.
+ * libm_hip_batch_plan_set_graph: use_graph = 0 makes later runs launch the
+ *   kernels directly instead of replaying the graph (same results).
  * libm_hip_batch_run: validates every request (LIBM_HIP_ERR_UNSUPPORTED for a
  *   combination the library does not serve, LIBM_HIP_ERR_INVALID for NULL
- *   pointers with n > 0), uploads the table on `stream` and enqueues the
- *   kernels there; returns without waiting for them.  Requests with n == 0
- *   are skipped.  A plan is not thread-safe: runs of one plan must be issued
- *   from one thread, on one stream or with the streams ordered by the caller.
- * Errors of these three calls are reported by libm_hip_batch_last_error().
+ *   pointers with n > 0), uploads the table on `stream` (a stream of the
+ *   plan's device) and enqueues the kernels there; returns without waiting
+ *   for them.  Requests with n == 0 are skipped.  A plan is not thread-safe:
+ *   runs of one plan must be issued from one thread, on one stream or with
+ *   the streams ordered by the caller.
+ * Errors of these calls are reported by libm_hip_last_error() (the calling
+ * thread's message); libm_hip_batch_last_error() returns the same message.
+ * The calls make the plan's device current while they run and restore the
+ * caller's current device before returning.
  * ---------------------------------------------------------------------- */
 typedef struct libm_hip_request {
   int fn;           /* libm_hip_fn */
@@ -451,7 +465,8 @@ typedef struct libm_hip_request {
 typedef struct libm_hip_batch_plan libm_hip_batch_plan;
 
 libm_hip_status libm_hip_batch_plan_create(libm_hip_batch_plan** plan, int max_requests,
-                                           int use_graph);
+                                           int device);
+libm_hip_status libm_hip_batch_plan_set_graph(libm_hip_batch_plan* plan, int use_graph);
 libm_hip_status libm_hip_batch_run(libm_hip_batch_plan* plan, const libm_hip_request* requests,
                                    int k, void* stream);
 void libm_hip_batch_plan_destroy(libm_hip_batch_plan* plan);

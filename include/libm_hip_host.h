@@ -31,6 +31,19 @@ extern "C" {
 libm_hip_status libm_hip_host_eval(libm_hip_fn fn, libm_hip_variant v, libm_hip_dtype t,
                                    const void* a, const void* b, void* out, size_t n);
 
+/* Instrumented exact remainder (Section 5, "FP Remainder", Algorithm 1):
+ * out[i] = fmod(x[i], y[i]) exactly as libm_hip_host_eval computes it, and
+ * steps[i] = the number of long-division digit steps the element took (0
+ * when |x| < |y| or for the special cases).  The paper's worked example
+ * (1e40 mod 0.75) takes 3 steps; in general about ceil(log2(|x/y|) / 52)
+ * (binary32: / 23), plus at most one more for the exponent-scaled digits of
+ * quotients beyond the format's range.  t is LIBM_HIP_F64 or LIBM_HIP_F32;
+ * x, y, out are host arrays of that type, steps an int32 array, all of n
+ * elements and caller-owned.  Returns LIBM_HIP_OK, LIBM_HIP_ERR_INVALID for
+ * a NULL array with n > 0, LIBM_HIP_ERR_UNSUPPORTED for another dtype. */
+libm_hip_status libm_hip_host_fmod_steps(libm_hip_dtype t, const void* x, const void* y,
+                                         void* out, int32_t* steps, size_t n);
+
 #ifdef __cplusplus
 }
 #endif

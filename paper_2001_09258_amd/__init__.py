@@ -418,6 +418,8 @@ def _batch_lib():
         lib.libm_hip_batch_run.restype = ctypes.c_int
         lib.libm_hip_batch_run.argtypes = [ctypes.c_void_p, ctypes.POINTER(Request), ctypes.c_int,
                                            ctypes.c_void_p]
+        lib.libm_hip_batch_plan_set_graph.restype = ctypes.c_int
+        lib.libm_hip_batch_plan_set_graph.argtypes = [ctypes.c_void_p, ctypes.c_int]
         lib.libm_hip_batch_plan_destroy.restype = None
         lib.libm_hip_batch_plan_destroy.argtypes = [ctypes.c_void_p]
         lib.libm_hip_batch_last_error.restype = ctypes.c_char_p
@@ -430,14 +432,16 @@ class BatchPlan:
     with device tensors (``b`` None for unary functions); enqueued on the
     current stream."""
 
-    def __init__(self, max_requests=64, use_graph=True):
+    def __init__(self, max_requests=64, use_graph=True, device=-1):
         lib = _batch_lib()
         h = ctypes.c_void_p()
-        st = lib.libm_hip_batch_plan_create(ctypes.byref(h), max_requests, 1 if use_graph else 0)
+        st = lib.libm_hip_batch_plan_create(ctypes.byref(h), max_requests, device)
         if st != 0:
             raise LibmHipError("batch_plan_create failed (%d): %s"
-                               % (st, lib.libm_hip_batch_last_error().decode()))
+                               % (st, lib.libm_hip_last_error().decode()))
         self._h = h
+        if not use_graph:
+            _check(lib.libm_hip_batch_plan_set_graph(h, 0), "libm_hip_batch_plan_set_graph")
         self.max_requests = max_requests
 
     def run(self, requests, stream=None):
@@ -451,7 +455,7 @@ class BatchPlan:
                                     _stream_handle() if stream is None else stream)
         if st != 0:
             raise LibmHipError("batch_run failed (%d): %s"
-                               % (st, lib.libm_hip_batch_last_error().decode()))
+                               % (st, lib.libm_hip_last_error().decode()))
 
     def run_raw(self, arr, k, stream):
         """Run a prepared ctypes Request array (no Python-side marshalling)."""
@@ -549,8 +553,31 @@ def load_host():
     lib.libm_hip_host_eval.restype = ctypes.c_int
     lib.libm_hip_host_eval.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp,
                                        ctypes.c_size_t]
+    lib.libm_hip_host_fmod_steps.restype = ctypes.c_int
+    lib.libm_hip_host_fmod_steps.argtypes = [ctypes.c_int, vp, vp, vp, vp, ctypes.c_size_t]
     _host = lib
     return lib
+
+
+def host_fmod_steps(x, y):
+    """fmod over float64/float32 numpy arrays on the host (the bit-consistent
+    build) and the number of long-division digit steps of each element."""
+    import numpy as np
+    lib = load_host()
+    x = np.ascontiguousarray(x)
+    tag = {np.dtype(np.float64): "f64", np.dtype(np.float32): "f32"}.get(x.dtype)
+    if tag is None:
+        raise TypeError("fmod steps take float64 or float32")
+    y = np.ascontiguousarray(y, dtype=x.dtype)
+    if y.shape != x.shape:
+        raise ValueError("fmod needs two arrays of equal shape")
+    out = np.empty_like(x)
+    steps = np.empty(x.shape, dtype=np.int32)
+    st = lib.libm_hip_host_fmod_steps(DTYPE_CODES[tag], x.ctypes.data, y.ctypes.data,
+                                      out.ctypes.data, steps.ctypes.data, x.size)
+    if st != 0:
+        raise LibmHipError("libm_hip_host_fmod_steps failed with status %d" % st)
+    return out, steps
 
 
 def _consistent_args(fn, variant):

@@ -15,6 +15,7 @@
 // reads the table and the tile total from device memory, so the graph stays
 // valid for any request list that fits the plan.
 #include "ops.h"
+#include "abi_util.h"
 #include "../../include/libm_hip.h"
 
 #include <algorithm>
@@ -259,10 +260,24 @@ void k_batch(const Desc* __restrict__ descs,
   }
 }
 
-thread_local char g_batch_error[256] = "";
-void batch_error(const char* m) {
-  strncpy(g_batch_error, m, sizeof(g_batch_error) - 1);
-}
+// batch errors go to the library's one thread-local message
+void batch_error(const char* m) { lmh_abi::set_error(m); }
+
+// makes `device` current for the lifetime of the guard (device < 0: keep the
+// current one) and restores the previous current device afterwards
+struct DeviceGuard {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit DeviceGuard(int device) {
+    if (device < 0) return;
+    err = hipGetDevice(&prev);
+    if (err == hipSuccess && prev != device) err = hipSetDevice(device);
+    else prev = -1;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
 
 }  // namespace
 
@@ -285,19 +300,30 @@ struct libm_hip_batch_plan {
 
 extern "C" {
 
-const char* libm_hip_batch_last_error(void) { return g_batch_error; }
+const char* libm_hip_batch_last_error(void) { return lmh_abi::g_last_error; }
 
 libm_hip_status libm_hip_batch_plan_create(libm_hip_batch_plan** out, int max_requests,
-                                           int use_graph) {
-  if (!out || max_requests <= 0 || max_requests > MAX_REQ) {
-    batch_error("libm_hip_batch_plan_create: invalid arguments (1 <= max_requests <= 1024)");
+                                           int device) {
+  int ndev = 0;
+  if (!out || max_requests <= 0 || max_requests > MAX_REQ ||
+      (device >= 0 && (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev))) {
+    batch_error("libm_hip_batch_plan_create: invalid arguments (1 <= max_requests <= 1024, "
+                "device -1 or an existing device)");
     return LIBM_HIP_ERR_INVALID;
   }
+  DeviceGuard guard(device);
+  if (guard.err != hipSuccess) {
+    batch_error(hipGetErrorString(guard.err));
+    return LIBM_HIP_ERR_HIP;
+  }
   libm_hip_batch_plan* p = new (std::nothrow) libm_hip_batch_plan();
-  if (!p) return LIBM_HIP_ERR_NOMEM;
+  if (!p) {
+    batch_error("libm_hip_batch_plan_create: out of host memory");
+    return LIBM_HIP_ERR_NOMEM;
+  }
   memset(p, 0, sizeof(*p));
   p->max_requests = max_requests;
-  p->use_graph = use_graph != 0;
+  p->use_graph = true;
   hipError_t e = hipGetDevice(&p->device);
   int cus = 0;
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
@@ -325,8 +351,18 @@ libm_hip_status libm_hip_batch_plan_create(libm_hip_batch_plan** out, int max_re
   return LIBM_HIP_OK;
 }
 
+libm_hip_status libm_hip_batch_plan_set_graph(libm_hip_batch_plan* p, int use_graph) {
+  if (!p) {
+    batch_error("libm_hip_batch_plan_set_graph: NULL plan");
+    return LIBM_HIP_ERR_INVALID;
+  }
+  p->use_graph = use_graph != 0;
+  return LIBM_HIP_OK;
+}
+
 void libm_hip_batch_plan_destroy(libm_hip_batch_plan* p) {
   if (!p) return;
+  DeviceGuard guard(p->device);
   // teardown errors cannot be reported through a void call; they are ignored
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
@@ -352,6 +388,11 @@ libm_hip_status libm_hip_batch_run(libm_hip_batch_plan* p, const libm_hip_reques
   if (!p || (k > 0 && !reqs) || k < 0 || k > p->max_requests) {
     batch_error("libm_hip_batch_run: invalid arguments");
     return LIBM_HIP_ERR_INVALID;
+  }
+  DeviceGuard guard(p->device);
+  if (guard.err != hipSuccess) {
+    batch_error(hipGetErrorString(guard.err));
+    return LIBM_HIP_ERR_HIP;
   }
   hipStream_t s = (hipStream_t)stream;
   // validate and order by estimated cost, most expensive first

@@ -5,7 +5,8 @@
 // arithmetic appears only where a few binary64 instructions replace a longer
 // float-float sequence (one binary64 instruction costs one issue slot on
 // gfx950): the trig Cody-Waite reduction, cbrt, hypot, the inverse
-// hyperbolic functions, erf and erfc.
+// hyperbolic functions, erf and erfc; and on the lanes whose exp, exp2,
+// exp10 or pow result falls in the subnormal range (see f32_sub_units).
 #pragma once
 #include "dd.h"
 #include "generated/consts.inc"
@@ -34,6 +35,26 @@ LMH_INLINE float ff_ldexp(fff v, int q) {
   return r;
 }
 
+// Binary32 results in the subnormal range (below 2^-126) keep up to 23 bits,
+// and deciding the last one needs the value to well below 2^-23 of a
+// subnormal ulp.  The working float-float paths reach ~2^-30 relative (one
+// subnormal result in a few thousand came out a unit off), and float-float
+// cannot go much below 2^-46, which would still leave an expected miss over
+// the 2^21 binary32 inputs whose exp is subnormal.  So the lanes whose
+// result falls in that range evaluate the binary64 pieces (~2^-60) and round
+// once here: v 2^q in units of 2^-149, rounded to an integer with the low
+// word deciding; d is the distance from rint(hi) in those units.
+LMH_INLINE double f32_sub_units(ddd v, int q, double& d) {
+  v = dd2_norm(v);
+  double h = ldexp_(v.hi, q + 149);
+  double l = ldexp_(v.lo, q + 149);
+  double n = rint_(h);
+  d = (h - n) + l;
+  return d > 0.5 ? n + 1.0 : (d < -0.5 ? n - 1.0 : n);
+}
+
+LMH_INLINE float f32_from_units(double n) { return ldexp_((float)n, -149); }
+
 LMH_INLINE float mod4f(float v) { return v - 4.0f * rint_(v * 0.25f); }
 LMH_INLINE bool is_odd_intf(float q) { return q - 2.0f * rint_(q * 0.5f) != 0.0f; }
 
@@ -57,6 +78,13 @@ LMH_INLINE float expf_u10(float x) {
   float rh = s + t;
   float rl = (s - rh) + t;
   float r = ff_ldexp(expf_core(rh, rl), (int)k);
+  bool sub = k <= -126.0f && k >= -151.0f;          // result below 2^-125
+  if (rare_lane(sub)) {
+    double sh, sl, d;
+    double kd = exp_reduce(sub ? (double)xc : 0.0, sh, sl);
+    float rs = f32_from_units(f32_sub_units(exp_core(sh, sl), (int)kd, d));
+    r = sub ? rs : r;
+  }
   return isnan_(x) ? x : r;
 }
 
@@ -68,11 +96,18 @@ LMH_INLINE float exp2f_u10(float x) {
   t.lo = fma_(f, LN2_F_L, t.lo);
   t = dd2_norm(t);
   float r = ff_ldexp(expf_core(t.hi, t.lo), (int)k);
+  bool sub = k <= -126.0f && k >= -151.0f;
+  if (rare_lane(sub)) {
+    double fd = sub ? (double)f : 0.0, d;         // f = x - k exactly
+    ddd td = dd2_norm(dd2_add2(dd2_mul(fd, LN2_D_H), dd2_mul(fd, LN2_D_L)));
+    float rs = f32_from_units(f32_sub_units(exp_core(td.hi, td.lo), (int)k, d));
+    r = sub ? rs : r;
+  }
   return isnan_(x) ? x : r;
 }
 
-LMH_INLINE fff expf_ff(fff w, float& k) {
-  float wh = w.hi > 104.0f ? 104.0f : (w.hi < -104.0f ? -104.0f : w.hi);
+LMH_INLINE fff expf_ff(fff w, float& k, float lim = 104.0f) {
+  float wh = w.hi > lim ? lim : (w.hi < -lim ? -lim : w.hi);
   float wl = wh == w.hi ? w.lo : 0.0f;              // the tail goes with a clamp
   k = rint_(wh * LOG2E_F);
   float s = fma_(k, -LN2_HI_F, wh);
@@ -425,6 +460,19 @@ LMH_INLINE float powf_u10(float x, float y) {
   float k;
   fff e = expf_ff(w, k);
   float r = ff_ldexp(e, (int)k);                   // overflows / underflows itself
+  bool sub = k <= -126.0f && k >= -151.0f && isfinite_(ax) && ax != 0.0f && isfinite_(y);
+  if (rare_lane(sub)) {
+    // binary64 log and exp pairs (~2^-59 relative for |w| <= 104); an exact
+    // tie between two subnormals is decided by ties-to-even
+    double axd = sub ? (double)ax : 0.5, yd = sub ? (double)y : 1.0, kd, d;
+    ddd ed = exp_dd(dd2_mul(log_dd(axd), yd), kd);
+    double n = f32_sub_units(ed, (int)kd, d);
+    if (fabs_(fabs_(d) - 0.5) < 0x1p-28) {
+      double tie = pow_tie_units(axd, yd, 150.0);
+      n = tie != 0.0 ? rint_(0.5 * tie) : n;
+    }
+    r = sub ? f32_from_units(n) : r;
+  }
   return powf_annexf(x, y, r);
 }
 
@@ -629,9 +677,16 @@ LMH_INLINE float atan2f_u35(float y, float x) {
   ay = both_inf ? 1.0f : ay;
   ax = both_inf ? 1.0f : ax;
   bool swap = ay > ax;
-  float t = (swap ? ax : ay) / (swap ? ay : ax);
+  float n = swap ? ax : ay, d = swap ? ay : ax;
+  float t = n / d;
   float z = t * t;
   float a = fma_(t * z, poly_estrin(z, ATAN_A_F32), t);
+  bool tiny = !swap && t < 0x1p-100f;
+  if (rare_lane(tiny)) {                                 // see atan2_u35
+    float r0 = fma_(-ldexp_(t, 60), d, ldexp_(n, 60));
+    float at = (r0 < 0.0f && -r0 == ldexp_(d, -90)) ? pred_(t) : t;
+    a = tiny ? at : a;
+  }
   a = swap ? (PIH2_F_H - a) + PIH2_F_L : a;
   bool xneg = __builtin_signbit(x);
   a = xneg ? (PI2_F_H - a) + PI2_F_L : a;
@@ -736,6 +791,16 @@ LMH_INLINE float exp10f_u10(float x) {
   float t = fma_(xc, LN10_F_L, a.lo) + k * -LN2_LO_F;
   fff r = dd2_add2(s, t);
   float v = ff_ldexp(expf_core(r.hi, r.lo), (int)k);
+  bool sub = k <= -126.0f && k >= -151.0f;
+  if (rare_lane(sub)) {
+    // binary64: x ln10 as an exact pair plus x times ln10's tail
+    double xd = sub ? (double)xc : 0.0, d;
+    double kd = rint_(xd * LOG2_10_D);
+    ddd a = dd2_mul(xd, LN10_D_H);
+    ddd rd = dd2_add2(fma_(kd, -LN2_HI_D, a.hi), fma_(xd, LN10_D_L, a.lo) + kd * -LN2_LO_D);
+    float vs = f32_from_units(f32_sub_units(exp_core(rd.hi, rd.lo), (int)kd, d));
+    v = sub ? vs : v;
+  }
   return isnan_(x) ? x : v;
 }
 
@@ -878,29 +943,40 @@ LMH_INLINE float hypotf_u10(float x, float y) {
 // ---------------------------------------------------------------------------
 // exact remainders in binary32 (same long division as binary64)
 // ---------------------------------------------------------------------------
-LMH_INLINE float fmodf_core(float n, float d) {
+LMH_INLINE fff fmodf_step(fff r, float d, float dm, float rdm, int de) {   // see fmod_step
+  float rm = frexp_mant_(r.hi);
+  int re = frexp_exp_(r.hi);
+  int E = re - de;
+  float qf = pred_(rm) * rdm;
+  float qs = E < 25 ? ldexp_(trunc_(ldexp_(qf, E)), -E) : qf;
+  qs = (r.hi < 3.0f * d && r.hi > d) ? ldexp_(2.0f, -E) : qs;
+  qs = (r.hi < 2.0f * d && r.hi > d) ? ldexp_(1.0f, -E) : qs;
+  qs = r.hi == d ? (r.lo >= 0.0f ? ldexp_(1.0f, -E) : 0.0f) : qs;
+  fff p = dd2_mul(qs, dm);
+  p = mk(ldexp_(p.hi, re), ldexp_(p.lo, re));
+  return dd2_norm(dd2_add2(r, dd2_neg(p)));
+}
+
+LMH_INLINE float fmodf_core_steps(float n, float d, int& steps) {   // see fmod_core_steps
   float dm = frexp_mant_(d);
   int de = frexp_exp_(d);
   float rdm = pred_(1.0f / dm);
   fff r = mk(n, 0.0f);
   bool active = r.hi > d || (r.hi == d && r.lo >= 0.0f);
+  steps = 0;
   for (int it = 0; it < 64 && any_lane(active); ++it) {
     if (active) {
-      float rm = frexp_mant_(r.hi);
-      int re = frexp_exp_(r.hi);
-      int E = re - de;
-      float qf = pred_(rm) * rdm;
-      float qs = E < 25 ? ldexp_(trunc_(ldexp_(qf, E)), -E) : qf;
-      qs = (r.hi < 3.0f * d && r.hi > d) ? ldexp_(2.0f, -E) : qs;
-      qs = (r.hi < 2.0f * d && r.hi > d) ? ldexp_(1.0f, -E) : qs;
-      qs = r.hi == d ? (r.lo >= 0.0f ? ldexp_(1.0f, -E) : 0.0f) : qs;
-      fff p = dd2_mul(qs, dm);
-      p = mk(ldexp_(p.hi, re), ldexp_(p.lo, re));
-      r = dd2_norm(dd2_add2(r, dd2_neg(p)));
+      ++steps;
+      r = fmodf_step(r, d, dm, rdm, de);
       active = r.hi > d || (r.hi == d && r.lo >= 0.0f);
     }
   }
   return r.hi;
+}
+
+LMH_INLINE float fmodf_core(float n, float d) {
+  int steps;
+  return fmodf_core_steps(n, d, steps);
 }
 
 LMH_INLINE float fmodf_f32(float x, float y) {

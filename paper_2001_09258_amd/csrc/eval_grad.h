@@ -46,21 +46,38 @@ LMH_INLINE double tanh_bwd(double x, double g) {
   return isnan_(x) ? x : r;
 }
 
+// e * 2^k as a pair for an integer e (|e| < 2^11 keeps e * LN2_A exact;
+// beyond, the product pair is exact anyway)
+LMH_INLINE ddd ln2_times(double e) { return dd2_add2(dd2_mul(e, LN2_A_D), e * LN2_B_D); }
+
+// pow partials for finite x != 0 (x < 0 with integer y for gx), finite y:
+// with g = gm 2^ge, y = ym 2^ye and log|x| = lm 2^le (gm, ym, lm in [0.5,
+// 1)), the power-of-two exponents join the exponential's argument,
+//   gx = gm ym e^((y - 1) log|x| + (ye + ge) ln2),
+//   gy = gm lm e^(y log|x| + (le + ge) ln2),
+// so every product stays near 1 and each partial is rounded once by the
+// final scaling, however large or small g, y and the power are (the clamp of
+// the exponential's argument at +-1000 is then exactly overflow / underflow).
 LMH_INLINE void pow_bwd(double x, double y, double g, double& gx, double& gy) {
   double ax = fabs_(x);
   ddd lg = log_dd(ax);
-  ddd w = dd2_mul(lg, y);                                  // y log x
+  double gm = frexp_mant_(g), ym = frexp_mant_(y);
+  double ge = (double)frexp_exp_(g), ye = (double)frexp_exp_(y);
+  int ile = frexp_exp_(lg.hi);
+  ddd lm = mk(ldexp_(lg.hi, -ile), ldexp_(lg.lo, -ile));
+  ddd w = dd2_mul(lg, y);                                  // y log|x|
   double k1, k2;
-  ddd e1 = exp_dd(dd2_add2(w, dd2_neg(lg)), k1);           // x^(y-1)
-  ddd e2 = exp_dd(w, k2);                                  // x^y
-  double dx = dd_ldexp(dd2_mul(dd2_mul(e1, y), g), (int)k1);
-  double dy = dd_ldexp(dd2_mul(dd2_mul(e2, lg), g), (int)k2);
+  ddd e1 = exp_dd(dd2_add2(dd2_add2(w, dd2_neg(lg)), ln2_times(ye + ge)), k1);
+  ddd e2 = exp_dd(dd2_add2(w, ln2_times((double)ile + ge)), k2);
+  double dx = dd_ldexp(dd2_mul(dd2_mul(e1, ym), gm), (int)k1);
+  double dy = dd_ldexp(dd2_mul(dd2_mul(e2, lm), gm), (int)k2);
   bool yint = rint_(y) == y;
-  bool ym1odd = yint && fabs_(y) < 0x1p53 && !is_odd_int(y);   // y-1 odd
-  dx = (x < 0.0 && ym1odd) ? -dx : dx;
-  // outside x > 0 (and for overflowing magnitudes) use the forward pow,
-  // which carries every Annex F case
-  bool plain = x > 0.0 && isfinite_(x) && isfinite_(y) && fabs_(w.hi) < 700.0;
+  bool ym1odd = yint && fabs_(y) < 0x1p53 && !is_odd_int(y);   // y - 1 odd
+  dx = (x < 0.0 && ym1odd) ? -dx : dx;                     // x^(y-1) = -|x|^(y-1)
+  dy = x < 0.0 ? __builtin_nan("") : dy;
+  // x = +-0, infinite or NaN, and x < 0 with y not an integer: the forward
+  // pow, which carries every Annex F case
+  bool plain = ax != 0.0 && isfinite_(ax) && isfinite_(y) && (x > 0.0 || yint);
   if (!plain) {
     dx = g * (y * pow_u10(x, y - 1.0));
     dy = x > 0.0 ? g * (pow_u10(x, y) * (lg.hi + lg.lo)) : __builtin_nan("");
@@ -107,19 +124,29 @@ LMH_INLINE float tanh_bwd(float x, float g) {
   return isnan_(x) ? x : r;
 }
 
+LMH_INLINE fff ln2_timesf(float e) { return dd2_add2(dd2_mul(e, LN2_HI_F), e * LN2_LO_F); }
+
+// as the binary64 form; the exponential's argument is clamped at +-110, where
+// the result (a pair below 1.42 times e^-110) is below half the smallest
+// subnormal, or (1/8 e^110) overflows
 LMH_INLINE void pow_bwd(float x, float y, float g, float& gx, float& gy) {
   float ax = fabs_(x);
   fff lg = logf_ff(ax);
+  float gm = frexp_mant_(g), ym = frexp_mant_(y);
+  float ge = (float)frexp_exp_(g), ye = (float)frexp_exp_(y);
+  int ile = frexp_exp_(lg.hi);
+  fff lm = mk(ldexp_(lg.hi, -ile), ldexp_(lg.lo, -ile));
   fff w = dd2_mul(lg, y);
   float k1, k2;
-  fff e1 = expf_ff(dd2_add2(w, dd2_neg(lg)), k1);
-  fff e2 = expf_ff(w, k2);
-  float dx = ff_ldexp(dd2_mul(dd2_mul(e1, y), g), (int)k1);
-  float dy = ff_ldexp(dd2_mul(dd2_mul(e2, lg), g), (int)k2);
+  fff e1 = expf_ff(dd2_add2(dd2_add2(w, dd2_neg(lg)), ln2_timesf(ye + ge)), k1, 110.0f);
+  fff e2 = expf_ff(dd2_add2(w, ln2_timesf((float)ile + ge)), k2, 110.0f);
+  float dx = ff_ldexp(dd2_mul(dd2_mul(e1, ym), gm), (int)k1);
+  float dy = ff_ldexp(dd2_mul(dd2_mul(e2, lm), gm), (int)k2);
   bool yint = rint_(y) == y;
   bool ym1odd = yint && fabs_(y) < 0x1p24f && !is_odd_intf(y);
   dx = (x < 0.0f && ym1odd) ? -dx : dx;
-  bool plain = x > 0.0f && isfinite_(x) && isfinite_(y) && fabs_(w.hi) < 85.0f;
+  dy = x < 0.0f ? __builtin_nanf("") : dy;
+  bool plain = ax != 0.0f && isfinite_(ax) && isfinite_(y) && (x > 0.0f || yint);
   if (!plain) {
     dx = g * (y * powf_u10(x, y - 1.0f));
     dy = x > 0.0f ? g * (powf_u10(x, y) * (lg.hi + lg.lo)) : __builtin_nanf("");

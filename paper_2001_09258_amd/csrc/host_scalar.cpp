@@ -63,3 +63,29 @@ extern "C" libm_hip_status libm_hip_host_eval(libm_hip_fn fn, libm_hip_variant v
   LMH_CONSISTENT_BINARY(LMH_HOST_CASE2)
   return LIBM_HIP_ERR_UNSUPPORTED;
 }
+
+extern "C" libm_hip_status libm_hip_host_fmod_steps(libm_hip_dtype t, const void* x,
+                                                    const void* y, void* out, int32_t* steps,
+                                                    size_t n) {
+  if (t != LIBM_HIP_F64 && t != LIBM_HIP_F32) return LIBM_HIP_ERR_UNSUPPORTED;
+  if (n == 0) return LIBM_HIP_OK;
+  if (!x || !y || !out || !steps) return LIBM_HIP_ERR_INVALID;
+  for (size_t i = 0; i < n; ++i) {
+    int s = 0;
+    if (t == LIBM_HIP_F64) {
+      double a = ((const double*)x)[i], b = ((const double*)y)[i];
+      double na = lmh::fabs_(a), nb = lmh::fabs_(b);
+      if (lmh::isfinite_(a) && lmh::isfinite_(nb) && nb != 0.0 && na >= nb)
+        lmh::fmod_core_steps(na, nb, s);
+      ((double*)out)[i] = lmh::fmod_f64(a, b);
+    } else {
+      float a = ((const float*)x)[i], b = ((const float*)y)[i];
+      float na = lmh::fabs_(a), nb = lmh::fabs_(b);
+      if (lmh::isfinite_(a) && lmh::isfinite_(nb) && nb != 0.0f && na >= nb)
+        lmh::fmodf_core_steps(na, nb, s);
+      ((float*)out)[i] = lmh::fmodf_f32(a, b);
+    }
+    steps[i] = s;
+  }
+  return LIBM_HIP_OK;
+}

@@ -81,6 +81,16 @@ LMH_INLINE bool any_lane(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
 
 namespace lmh {
 
+// any_lane for a path that only rare arguments take (results in the
+// subnormal range): the instruction counts of the common path
+// (gen/count_ops.py, built with LMH_COUNT_COMMON_PATH) leave such paths out,
+// since almost no wave runs them
+#ifdef LMH_COUNT_COMMON_PATH
+LMH_INLINE bool rare_lane(bool) { return false; }
+#else
+LMH_INLINE bool rare_lane(bool p) { return any_lane(p); }
+#endif
+
 // the neighbour of a positive finite x towards zero (x > 0, not subnormal 0)
 LMH_INLINE double pred_(double x) { return as_f64(as_i64(x) - 1); }
 LMH_INLINE float pred_(float x) { return as_f32(as_i32(x) - 1); }

@@ -7,7 +7,12 @@ binary64 units, the transcendental-unit instructions, and the
 floating-point operations (an FMA counts as two).  The result,
 ``valu_per_element.json``, is the per-element work the benchmark uses for
 the ALU roofline of compute-bound kernels: one element per lane, so VALU
-instructions per kernel = lane-operations per element.
+instructions per kernel = lane-operations per element.  The probes are
+built with LMH_COUNT_COMMON_PATH, which drops the paths only rare arguments
+take (results in the subnormal range), so the counts are those of the path
+almost every wave runs.  fmod and remainder loop: ``p64_fmodstep`` /
+``p32_fmodstep`` count one digit step, and the whole-function probes hold
+one copy of it; the benchmark scales by the steps the waves actually take.
 
 Run:  python -m paper_2001_09258_amd.gen.count_ops
 """
@@ -61,7 +66,8 @@ def main():
     with tempfile.TemporaryDirectory() as d:
         out = os.path.join(d, "probe.s")
         subprocess.run(["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O3", "-std=c++17",
-                        "-ffp-contract=off", "-fno-gpu-flush-denormals-to-zero", "-Xclang",
+                        "-ffp-contract=off", "-fno-gpu-flush-denormals-to-zero",
+                        "-DLMH_COUNT_COMMON_PATH", "-Xclang",
                         "-target-feature", "-Xclang", "-packed-fp32-ops", "--cuda-device-only",
                         "-S", "-o", out, src], check=True)
         res = count(open(out).read())

@@ -61,6 +61,17 @@ def log_r():
     return f, w, mp.mpf(0), mp.mpf(1) / 25 * mp.mpf("1.01")
 
 
+def log_r7():
+    # log m = 2t + (2/3) t^3 + (2/5) t^5 + t^7 R7(t^2): pow's logarithm, whose
+    # relative error is multiplied by |y log x| (up to ~745) in the result
+    f = _series_guard(lambda z: (2 * mp.atanh(mp.sqrt(z)) - 2 * mp.sqrt(z)
+                                 - mp.mpf(2) / 3 * z ** mp.mpf(1.5)
+                                 - mp.mpf(2) / 5 * z ** mp.mpf(2.5)) / z ** mp.mpf(3.5),
+                      lambda z: mp.mpf(2) / 7 + 2 * z / 9 + 2 * z ** 2 / 11)
+    w = lambda z: z ** mp.mpf(3.5) / (2 * mp.atanh(mp.sqrt(z))) if z > 0 else mp.mpf(0)
+    return f, w, mp.mpf(0), mp.mpf(1) / 25 * mp.mpf("1.01")
+
+
 def sin_s():
     # sin r = r + r^3 S(r^2), |r| <= pi/2
     f = _series_guard(lambda z: (mp.sin(mp.sqrt(z)) - mp.sqrt(z)) / z ** mp.mpf(1.5),
@@ -163,6 +174,7 @@ SPECS = [
     ("EXP_P_F64", exp_p, "f64", -63, 10),
     ("LOG_Q_F64", log_q, "f64", -62, 6),
     ("LOG_R_F64", log_r, "f64", -60, 7),
+    ("LOG_R7_F64", log_r7, "f64", -67, 5),
     ("SIN_S_F64", sin_s, "f64", -60, 7),
     ("SIN_S2_F64", sin_s2, "f64", -62, 6),
     ("SIN_S3_F64", sin_s3, "f64", -62, 5),

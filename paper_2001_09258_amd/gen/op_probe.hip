@@ -92,3 +92,11 @@ K1(p32_acosh, float, acoshf_u10(v))
 K1(p32_atanh, float, atanhf_u10(v))
 K1(p32_erf, float, erff_u10(v))
 K1(p32_erfc, float, erfcf_u10(v))
+// exact remainders: the whole functions (one copy of the digit step) and
+// one digit step alone
+__global__ void p64_fmod(const double* x, double* y) { int i = threadIdx.x; y[i] = fmod_f64(x[i], x[i+64]); }
+__global__ void p64_remainder(const double* x, double* y) { int i = threadIdx.x; y[i] = remainder_f64(x[i], x[i+64]); }
+__global__ void p64_fmodstep(const double* x, double* y) { int i = threadIdx.x; ddd r = fmod_step(mk(x[i], x[i+64]), x[i+128], x[i+192], x[i+256], (int)x[i+320]); y[i] = r.hi + r.lo; }
+__global__ void p32_fmod(const float* x, float* y) { int i = threadIdx.x; y[i] = fmodf_f32(x[i], x[i+64]); }
+__global__ void p32_remainder(const float* x, float* y) { int i = threadIdx.x; y[i] = remainderf_f32(x[i], x[i+64]); }
+__global__ void p32_fmodstep(const float* x, float* y) { int i = threadIdx.x; fff r = fmodf_step(mk(x[i], x[i+64]), x[i+128], x[i+192], x[i+256], (int)x[i+320]); y[i] = r.hi + r.lo; }

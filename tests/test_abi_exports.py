@@ -29,7 +29,7 @@ def _declared(only=None):
 
 # libm_hip_host.h declares the host library's entry point (and includes
 # libm_hip.h, whose names the GPU library exports)
-HOST_ONLY = {"libm_hip_host_eval"}
+HOST_ONLY = {"libm_hip_host_eval", "libm_hip_host_fmod_steps"}
 
 
 def test_header_declares_the_expected_surface():
@@ -118,3 +118,20 @@ def test_device_header_compiles_for_gfx950(tmp_path):
     subprocess.run([hipcc, "--offload-arch=gfx950", "-O1", "-std=c++17", "--cuda-device-only",
                     "-fsyntax-only", "-I", os.path.join(ROOT, "include"), str(src)],
                    check=True, capture_output=True)
+
+
+def test_batch_plan_argument_errors_without_a_gpu():
+    """Invalid plan arguments are rejected before any HIP call, with the
+    message on the library's thread-local error channel."""
+    import paper_2001_09258_amd as L
+    lib = ctypes.CDLL(L.library_path())
+    lib.libm_hip_last_error.restype = ctypes.c_char_p
+    lib.libm_hip_batch_last_error.restype = ctypes.c_char_p
+    h = ctypes.c_void_p()
+    assert lib.libm_hip_batch_plan_create(ctypes.byref(h), 0, -1) == 1
+    assert b"max_requests" in lib.libm_hip_last_error()
+    assert lib.libm_hip_batch_last_error() == lib.libm_hip_last_error()
+    assert lib.libm_hip_batch_plan_create(ctypes.byref(h), 2000, -1) == 1
+    assert lib.libm_hip_batch_plan_create(None, 4, -1) == 1
+    assert lib.libm_hip_batch_plan_set_graph(None, 0) == 1
+    assert h.value is None

@@ -148,3 +148,119 @@ def test_autograd_full_size(fn):
     for gv, (rn, hi, lo) in zip(got, want):
         r = compare(gv.astype(np.float64), rn, hi, lo, "f32", bound)
         assert r["violations"] == 0 and r["special_mismatch"] == 0, r
+
+
+# ---------------------------------------------------------------------------
+# backward kernels away from U[0.1, 10]
+# ---------------------------------------------------------------------------
+def _run_bwd(fn, dt, a, b, g):
+    ins = [torch.from_numpy(np.ascontiguousarray(v).astype(NPD[dt])).cuda()
+           for v in ((a,) if b is None else (a, b))]
+    outs = L.backward(fn, ins, torch.from_numpy(g.astype(NPD[dt])).cuda())
+    return [o.cpu().numpy().astype(np.float64) for o in outs]
+
+
+def _check_grad(got, want, dt, bound, what):
+    rn, hi, lo = want
+    r = compare(got, rn, hi, lo, dt, bound, subnormal="report")
+    if r["subnormal_mismatch"]:
+        print("%s: %d of %d subnormal gradients not correctly rounded"
+              % (what, r["subnormal_mismatch"], r["subnormal_results"]), flush=True)
+    assert r["violations"] == 0 and r["special_mismatch"] == 0, (what, r)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_pow_backward_whole_range_vs_oracle(dt):
+    """pow partials with |y log x| out to the overflow and underflow edges
+    (gradients rounded once, also into subnormals and at overflow), and
+    x < 0 with integer y: d/dx = y (-1)^(y-1) |x|^(y-1), d/dy = NaN."""
+    import oracle.batch as OB
+    n = 6000
+    a, b, g = W.backward_edges("pow", dt, n, 0)
+    print("bwd edges pow", dt, flush=True)
+    gx, gy = _run_bwd("pow", dt, a, b, g)
+    a64, b64, g64 = (v.astype(np.float64) for v in (a, b, g))
+    wx, wy = OB.evaluate_grad("pow", dt, np.abs(a64), g64, b64)
+    neg = a64 < 0
+    flip = neg & (np.fmod(b64, 2.0) == 0)                 # y even: y - 1 odd
+    wx = tuple(np.where(flip, -v, v) for v in wx)
+    _check_grad(gx, wx, dt, BOUND2, "pow d/dx")
+    _check_grad(gy[~neg], tuple(v[~neg] for v in wy), dt, BOUND2, "pow d/dy")
+    assert np.isnan(gy[neg]).all()
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_atan2_backward_extreme_magnitudes_vs_oracle(dt):
+    """atan2 partials with y, x near overflow and underflow (the common
+    power-of-two prescaling keeps x^2 + y^2 finite)."""
+    import oracle.batch as OB
+    a, b, g = W.backward_edges("atan2", dt, 6000, 0)
+    print("bwd edges atan2", dt, flush=True)
+    gy, gx = _run_bwd("atan2", dt, a, b, g)
+    wy, wx = OB.evaluate_grad("atan2", dt, a.astype(np.float64), g.astype(np.float64),
+                              b.astype(np.float64))
+    _check_grad(gy, wy, dt, BOUND2, "atan2 d/dy")
+    _check_grad(gx, wx, dt, BOUND2, "atan2 d/dx")
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_tanh_backward_large_arguments_vs_oracle(dt):
+    """tanh' = 1/cosh^2 out to where it underflows (|x| up to 380 binary64,
+    60 binary32): no 1 - tanh^2 cancellation, gradual underflow."""
+    import oracle.batch as OB
+    a, _, g = W.backward_edges("tanh", dt, 6000, 0)
+    print("bwd edges tanh", dt, flush=True)
+    (gx,) = _run_bwd("tanh", dt, a, None, g)
+    (want,) = OB.evaluate_grad("tanh", dt, a.astype(np.float64), g.astype(np.float64))
+    _check_grad(gx, want, dt, BOUND1, "tanh'")
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_tan_backward_near_poles_vs_oracle(dt):
+    """tan' = 1 + tan^2 at the floating-point numbers next to multiples of
+    pi/2 (the odd ones are the poles, where tan' reaches ~2^106)."""
+    import oracle.batch as OB
+    from tests.trig_hard_cases import near_multiples
+    x = near_multiples(dt)
+    x = x[::max(1, x.size // 6000)]
+    g = np.random.default_rng(9).standard_normal(x.size)
+    x, g = x.astype(NPD[dt]), g.astype(NPD[dt])
+    print("bwd edges tan", dt, x.size, flush=True)
+    (gx,) = _run_bwd("tan", dt, x, None, g)
+    (want,) = OB.evaluate_grad("tan", dt, x.astype(np.float64), g.astype(np.float64))
+    _check_grad(gx, want, dt, BOUND1, "tan'")
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_backward_special_points(dt):
+    """The values the header documents: pow at x = +-0 (d/dx = g y
+    pow(x, y - 1) with Annex F pow; d/dy = 0 for y >= 0, NaN for y < 0), at
+    x < 0 with non-integer y (both NaN), at x = 1 (d/dy = 0) and y = 0
+    (d/dx = 0); atan2 at (0, 0) (both NaN) and on the axes."""
+    import math
+    xs = [0.0, -0.0, 0.0, -0.0, 0.0, 0.0, -0.0, 0.0, -2.0, 1.0, 3.0]
+    ys = [2.0, 2.0, 3.0, 3.0, 1.0, 0.5, -1.0, 0.0, 0.5, 7.0, 0.0]
+    g = 1.5
+    gx, gy = _run_bwd("pow", dt, np.array(xs), np.array(ys), np.full(len(xs), g))
+    for i, (x, y) in enumerate(zip(xs, ys)):
+        if x < 0 and y != math.floor(y):
+            assert math.isnan(gx[i]) and math.isnan(gy[i]), (x, y)
+            continue
+        if x == 0.0:
+            with np.errstate(divide="ignore"):
+                p = float(np.power(np.float64(x), np.float64(y - 1.0)))   # C99 Annex F pow
+            wx = 0.0 if y == 0 else g * (y * p)
+            wy = 0.0 if y >= 0 else float("nan")
+            assert (gx[i] == wx and math.copysign(1, gx[i]) == math.copysign(1, wx)), (x, y, gx[i], wx)
+            assert (math.isnan(wy) and math.isnan(gy[i])) or gy[i] == wy, (x, y, gy[i], wy)
+        if x == 1.0:
+            assert gy[i] == 0.0, (x, y, gy[i])
+        if y == 0.0:
+            assert gx[i] == 0.0, (x, y, gx[i])
+    ay = np.array([0.0, 0.0, 3.0, -2.0])
+    ax = np.array([0.0, -2.0, 0.0, 0.0])
+    gyy, gxx = _run_bwd("atan2", dt, ay, ax, np.full(4, g))
+    assert np.isnan(gyy[0]) and np.isnan(gxx[0])
+    assert gyy[1] == g * -0.5 and gxx[1] == 0.0              # d/dy = x / x^2 = 1/x
+    assert gyy[2] == 0.0 and gxx[2] == -g / 3.0
+    assert gyy[3] == 0.0 and gxx[3] == g / 2.0

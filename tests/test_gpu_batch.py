@@ -155,3 +155,24 @@ def test_batch_exact_function_requests():
     for (fn, v, dt, a, b, out), r in zip(reqs, ref):
         assert _same(out, r), (fn, v, dt)
     plan.close()
+
+
+def test_plan_on_an_explicit_device_and_error_channel():
+    """A plan made for device 0 by number runs like one on the current
+    device; an unsupported request is reported on libm_hip_last_error."""
+    import ctypes
+    a = to_device(W.mixture("exp", "f64", 10000, 0), "f64")
+    out = torch.empty_like(a)
+    plan = L.BatchPlan(4, use_graph=False, device=0)
+    plan.run([("exp", "u10", "f64", a, None, out)])
+    torch.cuda.synchronize()
+    assert _same(out, L.evaluate("exp", a))
+    lib = L.load()
+    arr = (L.Request * 1)(L.Request(L.FN_CODES["fmod"], L.VARIANT_CODES["u10"], 0, 0,
+                                    a.data_ptr(), a.data_ptr(), out.data_ptr(), 16))
+    assert plan.run_raw(arr, 1, 0) == 2
+    assert b"unsupported" in lib.libm_hip_last_error()
+    bad = ctypes.c_void_p()
+    n = torch.cuda.device_count()
+    assert lib.libm_hip_batch_plan_create(ctypes.byref(bad), 4, n) == 1
+    plan.close()

@@ -1,5 +1,7 @@
 """The device-callable API (include/libm_hip_device.h) gives the same bits as
-the entry points.
+the entry points, and its results meet the oracle's bounds (checked
+directly on the first ORACLE_N outputs of every case, special values
+included).
 
 The check library (tests/device_api/check.hip, built by build()) runs the
 header's functions in a plain one-element-per-lane kernel compiled with the
@@ -14,7 +16,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from tests.gpu_common import to_device, to_host
+from tests.gpu_common import check_values, to_device, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -26,6 +28,7 @@ LIB = os.path.join(HERE, "device_api", "libdevice_api_check.so")
 CASES = [(fn, v, dt) for fn, v, dt, _ in L.all_entry_points()]
 BINARY = L.BINARY
 N = 3 * 4096 + 37
+ORACLE_N = 4096
 
 
 @pytest.fixture(scope="module")
@@ -75,6 +78,8 @@ def test_device_api_matches_entry_point(chk, fn, v, dt):
     bad = ~_same(y0, y1)
     assert not bad.any(), "%s %s %s: %d differ, e.g. x=%r" % (fn, v, dt, int(bad.sum()),
                                                             a[np.nonzero(bad)[0][:3]])
+    k = ORACLE_N
+    check_values(fn, v, dt, a[:k], None if b is None else b[:k], y1[:k], label="device_api")
 
 
 def test_masked_evaluation(chk):

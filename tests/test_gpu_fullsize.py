@@ -1,0 +1,65 @@
+"""Full benchmark size, in the launch shape the benchmark times.
+
+Every kernel of the benchmark step (15 function-variants x {binary64,
+binary32} on the 2^26-element mixture) and of the large-argument workload
+(sin, cos, tan u10/u35, fmod, remainder x {binary64, binary32} on 2^26
+elements) runs on its full-size input after the launch-shape tuner has
+picked its shape on those buffers, exactly as the benchmark does; 2^16
+sampled outputs plus the first and last are checked against the oracle one
+by one (ULP bound, special classes and binary64/binary32 subnormal results
+bit-exact; exact functions bit-exact).
+"""
+import concurrent.futures as cf
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_common import check_values, to_device, to_host
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2001_09258_amd as L  # noqa: E402
+
+N = 1 << 26
+SAMPLES = 1 << 16
+STEP = [("sin", "u10"), ("sin", "u35"), ("cos", "u10"), ("cos", "u35"), ("tan", "u10"),
+        ("tan", "u35"), ("exp", "u10"), ("exp2", "u10"), ("log", "u10"), ("log2", "u10"),
+        ("pow", "u10"), ("atan2", "u10"), ("sinh", "u10"), ("cosh", "u10"), ("tanh", "u10")]
+LARGE = [("sin", "u10"), ("sin", "u35"), ("cos", "u10"), ("cos", "u35"), ("tan", "u10"),
+         ("tan", "u35"), ("fmod", "exact"), ("remainder", "exact")]
+CASES = [("mixture", fn, v, dt) for dt in ("f64", "f32") for fn, v in STEP]
+CASES += [("large_args", fn, v, dt) for dt in ("f64", "f32") for fn, v in LARGE]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L.load()
+    yield
+    L.tune_reset()
+
+
+@pytest.mark.parametrize("workload,fn,variant,dt", CASES, ids=["-".join(c) for c in CASES])
+def test_full_size_tuned_sampled(workload, fn, variant, dt):
+    gen = W.mixture if workload == "mixture" else W.large_args
+    binary = fn in L.BINARY
+    with cf.ThreadPoolExecutor(2) as ex:
+        fa = ex.submit(gen, fn, dt, N, 0)
+        fb = ex.submit(gen, fn, dt, N, 1) if binary else None
+        a, b = fa.result(), (fb.result() if fb else None)
+    print("full size tuned", workload, fn, variant, dt, flush=True)
+    ta = to_device(a, dt)
+    tb = to_device(b, dt) if binary else None
+    out = torch.empty_like(ta)
+    shape = L.tune(fn, ta, tb, variant=variant, out=out)
+    L.evaluate(fn, ta, tb, variant=variant, out=out)
+    idx = np.random.default_rng(17).integers(0, N, SAMPLES)
+    idx = np.unique(np.concatenate([idx, [0, N - 1]]))
+    y = to_host(out[torch.from_numpy(idx).cuda()])
+    torch.cuda.synchronize()
+    res = check_values(fn, variant, dt, a[idx], None if b is None else b[idx], y,
+                       label="full size %s %s" % (workload, shape))
+    print("  shape %s: %d checked, max %.3f ulp" % (shape, idx.size, res["max_ulp"]), flush=True)

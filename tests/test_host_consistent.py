@@ -14,7 +14,7 @@ from tests.ulp import compare, exact_compare
 
 import paper_2001_09258_amd as L
 
-N = 400
+N = 3000
 KINDS = [(fn, v, dt) for fn in L.UNARY + L.BINARY for v in L.VARIANTS[fn]
          for dt in ("f64", "f32")]
 BOUND = {"u10": 1.0, "u35": 3.5, "exact": 0.0}
@@ -62,3 +62,41 @@ def test_cbrt_consistent_seed_over_the_reduced_range():
     rn, hi, lo = oracle.evaluate("cbrt", "f64", x)
     r = compare(y, rn, hi, lo, "f64", 1.0)
     assert r["violations"] == 0 and r["special_mismatch"] == 0, r["max_ulp"]
+
+
+SUB_KINDS = [(fn, v, dt) for fn in W.SUBNORMAL_FNS for v in L.VARIANTS[fn] if v != "exact"
+             for dt in ("f64", "f32")]
+
+
+@pytest.mark.parametrize("fn,v,dt", SUB_KINDS, ids=["-".join(k) for k in SUB_KINDS])
+def test_host_subnormal_results_bit_exact(fn, v, dt):
+    """Arguments whose results lie in the subnormal range: every subnormal
+    result equals the oracle's correctly rounded value bit for bit (the
+    accurate paths of exp, exp2, exp10, pow, erf and erfc, and the
+    tiny-argument identities of the others)."""
+    npdt = np.float64 if dt == "f64" else np.float32
+    a, b = W.subnormal_results(fn, dt, 3000, 0)
+    y = L.host_consistent(fn, a.astype(npdt), None if b is None else b.astype(npdt), v)
+    rn, hi, lo = oracle.evaluate(fn, dt, a.astype(np.float64),
+                                 None if b is None else b.astype(np.float64))
+    r = compare(y.astype(np.float64), rn, hi, lo, dt, BOUND[v], subnormal="exact")
+    bad = r["bad_idx"][:4]
+    assert r["subnormal_results"] >= 1000, r["subnormal_results"]
+    assert r["violations"] == 0 and r["special_mismatch"] == 0, \
+        "%s %s %s: %d subnormal mismatches; x=%r b=%r y=%r want %r" % (
+            fn, v, dt, r["subnormal_mismatch"], a[bad], None if b is None else b[bad],
+            y[bad], rn[bad])
+
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_host_pow_over_the_whole_result_range(dt):
+    """pow with |y log x| up to the overflow and underflow edges, where the
+    logarithm's relative error is amplified ~745 times (binary64)."""
+    npdt = np.float64 if dt == "f64" else np.float32
+    a, b = W.pow_wide(dt, 6000, 0)
+    y = L.host_consistent("pow", a.astype(npdt), b.astype(npdt), "u10")
+    rn, hi, lo = oracle.evaluate("pow", dt, a.astype(np.float64), b.astype(np.float64))
+    r = compare(y.astype(np.float64), rn, hi, lo, dt, 1.0)
+    assert r["violations"] == 0 and r["special_mismatch"] == 0, (r["max_ulp"], a[r["bad_idx"][:3]],
+                                                                 b[r["bad_idx"][:3]])

@@ -227,3 +227,32 @@ def test_float32_constant_roundings():
     # rounded unless the double lies on a float midpoint (it does not)
     assert v == float(np.float32(np.float64(math.pi)))
     assert struct.pack("<f", v) == struct.pack("<f", 3.14159274101257324)
+
+
+def test_rn_dyadic_bf16_matches_torch_conversion():
+    """bf16 (p = 8, emin = -126): RN of binary32 values (random patterns over
+    the whole range, bf16 subnormals, halfway cases, values just below and
+    above the overflow threshold) equals torch's float32 -> bfloat16
+    conversion, which rounds to nearest even."""
+    import numpy as np
+    import torch
+    BF16 = FORMATS["bf16"]
+    rng = np.random.default_rng(11)
+    bits = [rng.integers(0, 0x7F800000, 20000, dtype=np.uint32)]
+    bits.append(rng.integers(0, 0x00800000, 4000, dtype=np.uint32))       # f32 subnormals
+    hw = rng.integers(0, 0x7F7F, 4000, dtype=np.uint32) << 16
+    bits.append(hw | 0x8000)                                                 # exact halfway cases
+    bits.append(hw | 0x7FFF)
+    bits.append(hw | 0x8001)
+    bits.append(np.arange(0x7F7F7FF0, 0x7F800000, dtype=np.uint32))         # overflow edge
+    u = np.concatenate(bits)
+    u = np.concatenate([u, u | np.uint32(0x80000000)])
+    x = u.view(np.float32)
+    want = torch.from_numpy(x.copy()).to(torch.bfloat16).to(torch.float64).numpy()
+    n_inf = 0
+    for xi, wi in zip(x.tolist(), want.tolist()):
+        m, e = _exact(float(xi))
+        got = rn_dyadic(m, e, BF16, zero_sign=-1 if math.copysign(1.0, xi) < 0 else 1)
+        assert got == wi and math.copysign(1.0, got) == math.copysign(1.0, wi), (xi, got, wi)
+        n_inf += math.isinf(got)
+    assert n_inf > 0

@@ -19,7 +19,8 @@ import numpy as np
 
 __all__ = ["FN_IDS", "rng_for", "specials", "small_set", "mixture", "large_args",
            "narrow_mixture", "batch_requests", "autograd_inputs", "paper_domain",
-           "unit_mixture", "function_mixture",
+           "unit_mixture", "function_mixture", "subnormal_results", "SUBNORMAL_FNS",
+           "pow_wide", "backward_edges",
            "PAPER_DOMAINS", "round_to_bf16", "to_bf16_bits",
            "from_bf16_bits", "np_dtype"]
 
@@ -287,3 +288,105 @@ PAPER_DOMAINS = {
 def paper_domain(fn, lo, hi, n, dt="f64", operand=0):
     rng = rng_for(7, fn, operand)
     return _cast(rng.uniform(lo, hi, n), dt)
+
+
+# functions with results in the subnormal range, and how to reach it: an
+# argument interval (by format) or "tiny" (subnormal arguments, whose result
+# is about the argument itself)
+SUBNORMAL_FNS = {
+    "exp": {"f64": (-745.2, -708.3), "f32": (-104.0, -87.3)},
+    "exp2": {"f64": (-1075.0, -1022.0), "f32": (-150.0, -126.0)},
+    "exp10": {"f64": (-323.65, -307.6), "f32": (-45.2, -37.9)},
+    "erfc": {"f64": (26.5, 27.3), "f32": (9.1, 10.1)},
+    "pow": "power", "atan2": "quotient", "hypot": "tiny-pair",
+    "erf": "tiny", "sin": "tiny", "tan": "tiny", "asin": "tiny", "atan": "tiny",
+    "sinh": "tiny", "tanh": "tiny", "asinh": "tiny", "atanh": "tiny",
+    "log1p": "tiny", "expm1": "tiny",
+}
+
+
+def subnormal_results(fn, dt, n, operand=0):
+    """Arguments (a, b) whose exact results lie in (or at the edge of) the
+    subnormal range of binary64 or binary32: uniform over the interval of
+    SUBNORMAL_FNS for exp, exp2, exp10 and erfc; random subnormal bit
+    patterns of both signs for functions that return about their argument;
+    pow: x ~ U(0.01, 0.99), y = t / log2(x) with t ~ U[log2 of the smallest
+    subnormal - 1, log2 of the smallest normal], plus exact ties
+    (3 2^-215)^5 and the like; atan2: y = x 2^t with x log-uniform; hypot:
+    both operands 2^t.  b is None for unary functions."""
+    rng = rng_for(8, fn, operand)
+    kind = SUBNORMAL_FNS[fn]
+    lo_t, hi_t = (-1075.0, -1022.0) if dt == "f64" else (-150.0, -126.0)
+    big = 1e300 if dt == "f64" else 1e30
+    b = None
+    if isinstance(kind, dict):
+        lo, hi = kind[dt]
+        a = rng.uniform(lo, hi, n)
+    elif kind == "tiny":
+        nbits = 52 if dt == "f64" else 23
+        bits = rng.integers(1, 1 << nbits, n, dtype=np.uint64)
+        a = bits.astype(np.float64) * 2.0 ** (lo_t + 1.0)
+        a = np.where(rng.random(n) < 0.5, -a, a)
+    elif kind == "power":
+        a = rng.uniform(0.01, 0.99, n)
+        b = rng.uniform(lo_t, hi_t, n) / np.log2(_cast(a, dt).astype(np.float64))
+        # exact results halfway between two subnormals, and exact subnormals
+        T = -lo_t
+        ties = [(3 * 2.0 ** -(T // 5), 5.0), (5 * 2.0 ** -(T // 5), 5.0),
+                (2.0 ** -1, T), (2.0, -T), (0.5, T - 1), (9 * 2.0 ** (-(2 * T) // 5), 2.5)]
+        for i, (x, y) in enumerate(ties[:n]):
+            a[i], b[i] = x, y
+    elif kind == "quotient":
+        b = np.exp(rng.uniform(0.0, np.log(big), n))
+        a = b * 2.0 ** rng.uniform(lo_t, hi_t, n)
+        a = np.where(rng.random(n) < 0.5, -a, a)
+    else:
+        a = 2.0 ** rng.uniform(lo_t + 1.0, hi_t, n)
+        b = 2.0 ** rng.uniform(lo_t + 1.0, hi_t, n)
+    a = _cast(a, dt)
+    return a, None if b is None else _cast(b, dt)
+
+
+def pow_wide(dt, n, operand=0):
+    """pow arguments whose result spans the whole finite range: x log-uniform
+    in [1e-3, 1e3], y = w / ln x with w ~ U[-745, 709.7] (binary32:
+    U[-103.9, 88.7]), so |y log x| reaches the overflow and underflow edges,
+    where the logarithm's relative error is amplified the most."""
+    rng = rng_for(9, "pow", operand)
+    lo, hi = (-745.0, 709.7) if dt == "f64" else (-103.9, 88.7)
+    x = _cast(np.exp(rng.uniform(np.log(1e-3), np.log(1e3), n)), dt)
+    y = rng.uniform(lo, hi, n) / np.log(x.astype(np.float64))
+    return x, _cast(y, dt)
+
+
+def backward_edges(fn, dt, n, operand=0):
+    """Arguments for the backward kernels away from U[0.1, 10]:
+    pow: the pow_wide range (partials near overflow and underflow) with
+    negative x at integer y mixed in; atan2: y, x both log-uniform over
+    1e-300..1e300 (binary32: 1e-37..1e37) with random signs and a ratio
+    within e^+-3; tanh: x ~ U[-380, 380] (binary32: U[-60, 60]); tan: doubles
+    next to odd multiples of pi/2 come from the tests' own hard-case list.
+    Returns (a, b, g) with g standard normal; b is None for unary functions."""
+    rng = rng_for(10, fn, operand)
+    g = _cast(rng.standard_normal(n), dt)
+    b = None
+    if fn == "pow":
+        a, b = pow_wide(dt, n, operand)
+        neg = rng.random(n) < 0.25
+        yi = np.rint(rng.uniform(-40.0, 40.0, n))
+        a = np.where(neg, -a.astype(np.float64), a.astype(np.float64))
+        b = np.where(neg, yi, b.astype(np.float64))
+        a, b = _cast(a, dt), _cast(b, dt)
+    elif fn == "atan2":
+        e = 300.0 if dt == "f64" else 37.0
+        a = np.exp(rng.uniform(-e, e, n) * np.log(10.0))
+        b = a * np.exp(rng.uniform(-3.0, 3.0, n))
+        a = np.where(rng.random(n) < 0.5, -a, a)
+        b = np.where(rng.random(n) < 0.5, -b, b)
+        a, b = _cast(a, dt), _cast(b, dt)
+    elif fn == "tanh":
+        m = 380.0 if dt == "f64" else 60.0
+        a = _cast(rng.uniform(-m, m, n), dt)
+    else:
+        raise ValueError(fn)
+    return a, b, g
