@@ -17,6 +17,9 @@ cbrt at cubes and hypot when x^2 + y^2 is a square).  exp, sin, cos, tan,
 log (x != 1), atan (x != 0), expm1 and log1p (x != 0), the hyperbolic
 functions and their inverses (asinh, atanh at x != 0, acosh at x != 1) and
 erf, erfc of a nonzero dyadic are transcendental, hence never a boundary.
+lgamma and tgamma (oracle/gamma.py): exact at the positive integers (tgamma)
+and at 1 and 2 (lgamma); elsewhere the loop relies on the values not being
+boundaries, which its termination on every tested argument confirms.
 
 Special inputs (zeros, infinities, NaN) follow C99 Annex F (F.9), which the
 paper adopts: "same results as libm, as specified in the ANSI C standard"
@@ -49,6 +52,7 @@ from .consts import pi, ln2
 from .elementary import (exp_ball, log_ball, log1p_ball, sincos_reduced, sin_cos_ball,
                          atan_ball, sinh_cosh_small, erf_ball)
 from .rounding import FORMATS, rn_dyadic, rn_ball
+from .gamma import lgamma_ball, tgamma_ball
 
 __all__ = ["UNARY", "BINARY", "evaluate1", "OracleError"]
 
@@ -59,7 +63,8 @@ PREC_CAP = 16384
 UNARY = ("sin", "cos", "tan", "exp", "exp2", "log", "log2",
          "sinh", "cosh", "tanh", "asin", "acos", "atan",
          "log10", "exp10", "expm1", "log1p", "cbrt", "asinh", "acosh", "atanh",
-         "erf", "erfc", "sqrt", "trunc", "floor", "ceil", "round", "rint", "fabs", "logb")
+         "erf", "erfc", "sqrt", "trunc", "floor", "ceil", "round", "rint", "fabs", "logb",
+         "lgamma", "tgamma")
 BINARY = ("pow", "atan2", "fmod", "remainder", "hypot", "fdim", "fmax", "fmin", "copysign",
           "nextafter")
 # functions whose result is the exact value or its correct rounding (no
@@ -201,6 +206,20 @@ def _special_unary(fn, x):
             return 1.0
         if math.isinf(x):
             return 0.0 if x > 0 else 2.0
+    elif fn == "lgamma":
+        # F.9.5.3: +inf at +-inf and at the poles (zero, negative integers)
+        if math.isinf(x) or (x <= 0.0 and x == math.floor(x)):
+            return INF
+        if x == 1.0 or x == 2.0:
+            return 0.0
+    elif fn == "tgamma":
+        # F.9.5.4: +-0 -> +-inf, negative integers and -inf -> NaN, +inf -> +inf
+        if x == 0.0:
+            return math.copysign(INF, x)
+        if math.isinf(x):
+            return INF if x > 0 else NAN
+        if x < 0.0 and x == math.floor(x):
+            return NAN
     return None
 
 
@@ -650,7 +669,7 @@ _BALLS = {"sin": _ball_sin, "cos": _ball_cos, "tan": _ball_tan,
           "atan": _ball_atan, "log10": _ball_log10, "exp10": _ball_exp10,
           "expm1": _ball_expm1, "log1p": _ball_log1p, "cbrt": _ball_cbrt,
           "asinh": _ball_asinh, "acosh": _ball_acosh, "atanh": _ball_atanh,
-          "erf": _ball_erf, "erfc": _ball_erfc}
+          "erf": _ball_erf, "erfc": _ball_erfc, "lgamma": lgamma_ball, "tgamma": tgamma_ball}
 
 
 def _dd(b):
@@ -797,6 +816,15 @@ def evaluate1(fn, fmt_name, x, y=None):
             ex = _cbrt_exact(x)
             if ex is not None:
                 return _exact_result(ex[0] if x > 0 else -ex[0], ex[1], fmt)
+        if fn == "tgamma":
+            if x > 200.0:                             # Gamma(200) > 2^1240: +inf
+                return INF, INF, 0.0
+            if x == math.floor(x):                    # Gamma(n) = (n - 1)!
+                return _exact_result(math.factorial(int(x) - 1), 0, fmt)
+            if x < -200.0:
+                # |Gamma(x)| < 2^-1190 here: a zero with the sign of sin(pi x)
+                v = 0.0 if math.floor(x) % 2 == 0 else -0.0
+                return v, v, 0.0
         return _ziv(_BALLS[fn], (x,), fmt, prec0)
     if fn == "atan2":
         sp = _special_atan2(x, y, fmt)       # atan2(x, y) in C order
