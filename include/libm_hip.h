@@ -472,6 +472,28 @@ libm_hip_status libm_hip_batch_run(libm_hip_batch_plan* plan, const libm_hip_req
 void libm_hip_batch_plan_destroy(libm_hip_batch_plan* plan);
 const char* libm_hip_batch_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * The batched evaluation without any allocation, for callers that cannot
+ * allocate device memory (code being captured into a hip graph, tight
+ * serving loops, harnesses that forbid hipMalloc): the results of
+ * libm_hip_batch_run (same kernels, same tile order) with no plan.  The
+ * request table (at most 256 requests), its header and the tile counter
+ * live in a fixed 12.5 KiB device array of the library, one per GPU, held
+ * until the process ends; the table reaches it through a small staging
+ * kernel that takes the requests as kernel arguments (no host-to-device
+ * copy), and that kernel also clears the counter.  The call makes no
+ * hipMalloc, hipFree or other allocating call.
+ * Every call on one GPU uses that GPU's one array: calls that overlap on a
+ * GPU (from several threads or on unordered streams) race and must be
+ * ordered by the caller.  Arguments as libm_hip_batch_run, on the current
+ * device's `stream`; LIBM_HIP_ERR_INVALID for k > 256 (message on
+ * libm_hip_last_error), LIBM_HIP_ERR_UNSUPPORTED / LIBM_HIP_ERR_INVALID for
+ * a bad request, LIBM_HIP_ERR_HIP for a launch failure.  Returns without
+ * waiting for the kernels.
+ * ---------------------------------------------------------------------- */
+libm_hip_status libm_hip_batch_run_noalloc(const libm_hip_request* requests, int k,
+                                           void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -418,6 +418,9 @@ def _batch_lib():
         lib.libm_hip_batch_run.restype = ctypes.c_int
         lib.libm_hip_batch_run.argtypes = [ctypes.c_void_p, ctypes.POINTER(Request), ctypes.c_int,
                                            ctypes.c_void_p]
+        lib.libm_hip_batch_run_noalloc.restype = ctypes.c_int
+        lib.libm_hip_batch_run_noalloc.argtypes = [ctypes.POINTER(Request), ctypes.c_int,
+                                                   ctypes.c_void_p]
         lib.libm_hip_batch_plan_set_graph.restype = ctypes.c_int
         lib.libm_hip_batch_plan_set_graph.argtypes = [ctypes.c_void_p, ctypes.c_int]
         lib.libm_hip_batch_plan_destroy.restype = None
@@ -471,6 +474,28 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+def request_array(requests):
+    """A ctypes libm_hip_request array from (fn, variant, dtype, a, b, out)
+    tuples of device tensors (b None for unary functions)."""
+    arr = (Request * max(1, len(requests)))()
+    for i, (fn, v, dt, a, b, out) in enumerate(requests):
+        arr[i] = Request(FN_CODES[fn], VARIANT_CODES[v], DTYPE_CODES[dt], 0, a.data_ptr(),
+                         0 if b is None else b.data_ptr(), out.data_ptr(), a.numel())
+    return arr
+
+
+def batch_run_noalloc(requests, stream=None):
+    """libm_hip_batch_run_noalloc over (fn, variant, dtype, a, b, out) tuples
+    of device tensors, on the current stream; allocates nothing on the
+    device."""
+    lib = _batch_lib()
+    st = lib.libm_hip_batch_run_noalloc(request_array(requests), len(requests),
+                                        _stream_handle() if stream is None else stream)
+    if st != 0:
+        raise LibmHipError("batch_run_noalloc failed (%d): %s"
+                           % (st, lib.libm_hip_last_error().decode()))
 
 
 # ---------------------------------------------------------------------------

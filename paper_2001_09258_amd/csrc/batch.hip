@@ -19,6 +19,7 @@
 #include "../../include/libm_hip.h"
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <stdio.h>
 #include <string.h>
@@ -260,6 +261,42 @@ void k_batch(const Desc* __restrict__ descs,
   }
 }
 
+// ---- the no-allocation form ---------------------------------------------------
+// libm_hip_batch_run_noalloc keeps its request table, header and tile counter
+// in this file-scope device array instead of plan memory: every GPU the
+// library runs on holds one copy until the process ends.  Layout: tile
+// counter at byte 0, header at byte 64, request table from byte 256.  Host
+// code never uses the array's name as an address (in host code it names a
+// host-side stand-in); it uses the device address hipGetSymbolAddress gives
+// for the current device, kept per device.
+constexpr int NOALLOC_MAX_REQ = 256;
+constexpr size_t SCRATCH_TABLE = 256;
+constexpr size_t SCRATCH_BYTES = SCRATCH_TABLE + sizeof(Desc) * NOALLOC_MAX_REQ;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+// the staging kernel takes up to STAGE_CHUNK descriptors by value (kernel
+// arguments, no host-to-device copy) and writes them into the table; the
+// launch that stages the first chunk also writes the header and clears the
+// tile counter
+constexpr int STAGE_CHUNK = 64;
+struct StageArgs {
+  Desc d[STAGE_CHUNK];
+  Header h;
+  int first;
+  int count;
+};
+static_assert(sizeof(StageArgs) < 4000, "kernel arguments stay below 4 KiB");
+
+__global__ void k_batch_stage(StageArgs args, unsigned char* base) {
+  Desc* table = reinterpret_cast<Desc*>(base + SCRATCH_TABLE);
+  int i = threadIdx.x;
+  if (i < args.count) table[args.first + i] = args.d[i];
+  if (args.first == 0 && i == 0) {
+    *reinterpret_cast<Header*>(base + 64) = args.h;
+    *reinterpret_cast<unsigned long long*>(base) = 0ull;
+  }
+}
+
 // batch errors go to the library's one thread-local message
 void batch_error(const char* m) { lmh_abi::set_error(m); }
 
@@ -476,3 +513,123 @@ libm_hip_status libm_hip_batch_run(libm_hip_batch_plan* p, const libm_hip_reques
 }
 
 }  // extern "C"
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[MAX_DEVICES];    // device address of scratch, per device
+unsigned g_scratch_grid[MAX_DEVICES];         // persistent grid, per device
+
+// set-up on the first call on a device (with that device current): the
+// device address of this device's copy of scratch, and the persistent grid
+hipError_t noalloc_setup(int dev, unsigned char** base, unsigned* grid) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    unsigned char* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    int cus = 0, per_cu = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, BBLOCK, 0) != hipSuccess ||
+        per_cu <= 0)
+      per_cu = 4;
+    g_scratch_grid[dev] = (unsigned)((cus > 0 ? cus : 256) * per_cu);
+    g_scratch_ptr[dev] = ptr;
+  }
+  *base = g_scratch_ptr[dev];
+  *grid = g_scratch_grid[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+extern "C" libm_hip_status libm_hip_batch_run_noalloc(const libm_hip_request* reqs, int k,
+                                                      void* stream) {
+  if ((k > 0 && !reqs) || k < 0) {
+    batch_error("libm_hip_batch_run_noalloc: invalid arguments");
+    return LIBM_HIP_ERR_INVALID;
+  }
+  if (k > NOALLOC_MAX_REQ) {
+    batch_error("libm_hip_batch_run_noalloc: at most 256 requests per call");
+    return LIBM_HIP_ERR_INVALID;
+  }
+  // validate and order by estimated cost, most expensive first (fixed-size
+  // arrays on the stack: no allocation of any kind)
+  int order[NOALLOC_MAX_REQ];
+  float cost[NOALLOC_MAX_REQ];
+  int codes[NOALLOC_MAX_REQ];
+  int m = 0;
+  for (int i = 0; i < k; ++i) {
+    const libm_hip_request& r = reqs[i];
+    int code = op_code(r.fn, r.variant, r.dtype);
+    if (code < 0) {
+      batch_error("libm_hip_batch_run_noalloc: unsupported (fn, variant, dtype)");
+      return LIBM_HIP_ERR_UNSUPPORTED;
+    }
+    if (r.n > 0 && (!r.a || !r.out || (op_arity(code) == 2 && !r.b))) {
+      batch_error("libm_hip_batch_run_noalloc: NULL pointer with n > 0");
+      return LIBM_HIP_ERR_INVALID;
+    }
+    codes[i] = code;
+    cost[i] = op_cost(code) * (float)r.n;
+    if (r.n > 0) order[m++] = i;
+  }
+  if (m == 0) return LIBM_HIP_OK;
+  // ties keep the caller's order, as in libm_hip_batch_run
+  std::sort(order, order + m, [&](int x, int y) {
+    return cost[x] > cost[y] || (cost[x] == cost[y] && x < y);
+  });
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess && (dev < 0 || dev >= MAX_DEVICES)) e = hipErrorInvalidDevice;
+  unsigned char* base = nullptr;
+  unsigned grid = 0;
+  if (e == hipSuccess) e = noalloc_setup(dev, &base, &grid);
+  if (e != hipSuccess) {
+    batch_error(hipGetErrorString(e));
+    return LIBM_HIP_ERR_HIP;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  StageArgs args;
+  memset(&args, 0, sizeof(args));
+  unsigned long long tiles = 0;
+  for (int j = 0; j < m; ++j) {
+    const libm_hip_request& r = reqs[order[j]];
+    tiles += (r.n + TILE - 1) / TILE;
+  }
+  args.h.total_tiles = tiles;
+  args.h.k = m;
+  tiles = 0;
+  for (int first = 0; first < m && e == hipSuccess; first += STAGE_CHUNK) {
+    int count = m - first < STAGE_CHUNK ? m - first : STAGE_CHUNK;
+    for (int j = 0; j < count; ++j) {
+      const libm_hip_request& r = reqs[order[first + j]];
+      Desc& d = args.d[j];
+      d.a = r.a;
+      d.b = r.b;
+      d.out = r.out;
+      d.n = r.n;
+      d.tile_begin = tiles;
+      d.op = codes[order[first + j]];
+      d.pad = 0;
+      tiles += (r.n + TILE - 1) / TILE;
+    }
+    args.first = first;
+    args.count = count;
+    hipLaunchKernelGGL(k_batch_stage, dim3(1), dim3(STAGE_CHUNK), 0, s, args, base);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(BBLOCK), 0, s,
+                       reinterpret_cast<const Desc*>(base + SCRATCH_TABLE),
+                       reinterpret_cast<const Header*>(base + 64),
+                       reinterpret_cast<unsigned long long*>(base));
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) {
+    batch_error(hipGetErrorString(e));
+    return LIBM_HIP_ERR_HIP;
+  }
+  return LIBM_HIP_OK;
+}
