@@ -169,6 +169,24 @@ LIBM_HIP_DECL_UNARY_HALF(atanh)
 LIBM_HIP_DECL_UNARY_HALF(erf)
 LIBM_HIP_DECL_UNARY_HALF(erfc)
 
+/* lgamma and tgamma (C99 functions of the paper's set, Section 1; not
+ * described in the paper).  log Gamma(a) for a > 0 as a double-double pair:
+ * minimax expansions around the zeros at 1 and 2 (|a - 1|, |a - 2| <= 1/16),
+ * Stirling's series with ten Bernoulli terms from a >= 10, and below that
+ * the recurrence up to a + n >= 10 with the product a (a + 1) ... (a + n - 1)
+ * in double-double; lgamma(x) = log Gamma(1 + x) - log|x| for |x| < 1/16 and
+ * the reflection formula for x <= -1/16; tgamma = sign e^lgamma, the
+ * exponential of the pair rounded once.  1.0 ULP, except next to the zeros
+ * of lgamma on the negative axis (where the reflection's subtraction
+ * cancels; the error there is about 2^-100 absolute).  binary32: the binary64
+ * pairs rounded once.  Annex F: lgamma(+-0) = lgamma(-n) = lgamma(+-inf) =
+ * +inf, lgamma(1) = lgamma(2) = +0; tgamma(+-0) = +-inf, tgamma(-n) =
+ * tgamma(-inf) = NaN, tgamma(+inf) = +inf; NaN gives NaN. */
+LIBM_HIP_DECL_UNARY(lgamma, u10)
+LIBM_HIP_DECL_UNARY(tgamma, u10)
+LIBM_HIP_DECL_UNARY_HALF(lgamma)
+LIBM_HIP_DECL_UNARY_HALF(tgamma)
+
 /* ------------------------------------------------------------------------
  * sincos: s[i] = sin(x[i]) and c[i] = cos(x[i]) in one pass (the paper's
  * library provides sincos, Section 1).  Each result is bit-identical to the
@@ -230,6 +248,8 @@ LIBM_HIP_DECL_BINARY(atan2, _u10, uint16_t, f16)
 LIBM_HIP_DECL_BINARY(atan2, _u10, float, f32_via_f64)
 LIBM_HIP_DECL_BINARY(atan2, _u35, double, f64)
 LIBM_HIP_DECL_BINARY(atan2, _u35, float, f32)
+LIBM_HIP_DECL_BINARY(pow, _u35, double, f64)
+LIBM_HIP_DECL_BINARY(pow, _u35, float, f32)
 LIBM_HIP_DECL_BINARY(hypot, _u10, double, f64)
 LIBM_HIP_DECL_BINARY(hypot, _u10, float, f32)
 LIBM_HIP_DECL_BINARY(hypot, _u10, uint16_t, bf16)
@@ -368,6 +388,7 @@ typedef enum {
   LIBM_HIP_ERF, LIBM_HIP_ERFC, LIBM_HIP_FDIM, LIBM_HIP_FMAX, LIBM_HIP_FMIN,
   LIBM_HIP_SQRT, LIBM_HIP_TRUNC, LIBM_HIP_FLOOR, LIBM_HIP_CEIL, LIBM_HIP_ROUND, LIBM_HIP_RINT,
   LIBM_HIP_FABS, LIBM_HIP_LOGB, LIBM_HIP_COPYSIGN, LIBM_HIP_NEXTAFTER,
+  LIBM_HIP_LGAMMA, LIBM_HIP_TGAMMA,
   LIBM_HIP_NUM_FN
 } libm_hip_fn;
 typedef enum { LIBM_HIP_U10 = 0, LIBM_HIP_U35 = 1, LIBM_HIP_EXACT = 2 } libm_hip_variant;

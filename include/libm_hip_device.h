@@ -110,6 +110,8 @@ LIBM_HIP_DEVICE_UNARY(acosh_u10, OpAcoshU10)
 LIBM_HIP_DEVICE_UNARY(atanh_u10, OpAtanhU10)
 LIBM_HIP_DEVICE_UNARY(erf_u10, OpErfU10)
 LIBM_HIP_DEVICE_UNARY(erfc_u10, OpErfcU10)
+LIBM_HIP_DEVICE_UNARY(lgamma_u10, OpLgammaU10)
+LIBM_HIP_DEVICE_UNARY(tgamma_u10, OpTgammaU10)
 /* 3.5-ULP forms (binary64 and binary32) */
 LIBM_HIP_DEVICE_UNARY_WIDE(sin_u35, OpSinU35)
 LIBM_HIP_DEVICE_UNARY_WIDE(cos_u35, OpCosU35)
@@ -126,6 +128,7 @@ LIBM_HIP_DEVICE_BINARY(pow_u10, OpPowU10)
 LIBM_HIP_DEVICE_BINARY(atan2_u10, OpAtan2U10)
 LIBM_HIP_DEVICE_BINARY(hypot_u10, OpHypotU10)
 LIBM_HIP_DEVICE_BINARY_WIDE(atan2_u35, OpAtan2U35)
+LIBM_HIP_DEVICE_BINARY_WIDE(pow_u35, OpPowU35)
 
 /* sincos: *s = sin x, *c = cos x, bit-identical to sin_* and cos_* of the
    same variant and type */

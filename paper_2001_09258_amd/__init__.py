@@ -20,7 +20,8 @@ import os
 __all__ = ["load", "library_path", "UNARY", "BINARY", "VARIANTS", "entry_name",
            "call", "evaluate", "sin", "cos", "tan", "exp", "exp2", "log", "log2",
            "sinh", "cosh", "tanh", "asin", "acos", "atan", "log10", "log1p", "exp10",
-           "expm1", "cbrt", "asinh", "acosh", "atanh", "erf", "erfc", "sincos", "pow", "atan2",
+           "expm1", "cbrt", "asinh", "acosh", "atanh", "erf", "erfc", "lgamma", "tgamma",
+           "sincos", "pow", "atan2",
            "hypot", "fmod", "remainder", "fdim", "fmax", "fmin", "copysign", "nextafter",
            "sqrt", "trunc", "floor", "ceil", "rint", "fabs", "logb",
            "consistent", "host_consistent", "LibmHipError"]
@@ -30,7 +31,8 @@ _LIBNAME = "libm_hip.so"
 
 UNARY = ("sin", "cos", "tan", "exp", "exp2", "log", "log2", "sinh", "cosh", "tanh",
          "asin", "acos", "atan", "log10", "log1p", "exp10", "expm1", "cbrt", "asinh",
-         "acosh", "atanh", "erf", "erfc", "sqrt", "trunc", "floor", "ceil", "round", "rint",
+         "acosh", "atanh", "erf", "erfc", "lgamma", "tgamma", "sqrt", "trunc", "floor", "ceil",
+         "round", "rint",
          "fabs", "logb")
 BINARY = ("pow", "atan2", "hypot", "fmod", "remainder", "fdim", "fmax", "fmin", "copysign",
           "nextafter")
@@ -41,6 +43,7 @@ VARIANTS = {fn: ("exact",) if fn in EXACT else ("u10",) for fn in UNARY + BINARY
 VARIANTS.update({"sin": ("u10", "u35"), "cos": ("u10", "u35"), "tan": ("u10", "u35"),
                  "asin": ("u10", "u35"), "acos": ("u10", "u35"), "atan": ("u10", "u35"),
                  "log": ("u10", "u35"), "atan2": ("u10", "u35"), "sinh": ("u10", "u35"),
+                 "pow": ("u10", "u35"),
                  "cosh": ("u10", "u35"), "tanh": ("u10", "u35"),
                  "fmod": ("exact",), "remainder": ("exact",), "fdim": ("exact",),
                  "fmax": ("exact",), "fmin": ("exact",)})
@@ -274,6 +277,7 @@ log10, log1p, exp10 = _unary("log10"), _unary("log1p"), _unary("exp10")
 expm1, cbrt = _unary("expm1"), _unary("cbrt")
 asinh, acosh, atanh = _unary("asinh"), _unary("acosh"), _unary("atanh")
 erf, erfc = _unary("erf"), _unary("erfc")
+lgamma, tgamma = _unary("lgamma"), _unary("tgamma")
 
 
 def _exact1(fn):
@@ -397,7 +401,8 @@ FN_CODES = {"sin": 0, "cos": 1, "tan": 2, "exp": 3, "exp2": 4, "log": 5, "log2":
             "log1p": 18, "exp10": 19, "expm1": 20, "cbrt": 21, "hypot": 22, "asinh": 23,
             "acosh": 24, "atanh": 25, "erf": 26, "erfc": 27, "fdim": 28, "fmax": 29,
             "fmin": 30, "sqrt": 31, "trunc": 32, "floor": 33, "ceil": 34, "round": 35,
-            "rint": 36, "fabs": 37, "logb": 38, "copysign": 39, "nextafter": 40}
+            "rint": 36, "fabs": 37, "logb": 38, "copysign": 39, "nextafter": 40,
+            "lgamma": 41, "tgamma": 42}
 VARIANT_CODES = {"u10": 0, "u35": 1, "exact": 2}
 DTYPE_CODES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "f32_via_f64": 4}
 

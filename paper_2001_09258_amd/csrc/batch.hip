@@ -128,8 +128,13 @@ struct Header {
   X(174, IoF64, OpFabs, 1) X(175, IoF32, OpFabs, 1) \
   X(176, IoF64, OpLogb, 1) X(177, IoF32, OpLogb, 1) \
   X(178, IoF64, OpCopysign, 2) X(179, IoF32, OpCopysign, 2) \
-  X(180, IoF64, OpNextafter, 2) X(181, IoF32, OpNextafter, 2)
-constexpr int NUM_OPS = 182;
+  X(180, IoF64, OpNextafter, 2) X(181, IoF32, OpNextafter, 2) \
+  X(182, IoF64, OpPowU35, 2) X(183, IoF32, OpPowU35, 2) \
+  X(184, IoF64, OpLgammaU10, 1) X(185, IoF32, OpLgammaU10, 1) X(186, IoBF16, OpLgammaU10, 1) \
+  X(187, IoF16, OpLgammaU10, 1) X(188, IoF32ViaF64, OpLgammaU10, 1)               \
+  X(189, IoF64, OpTgammaU10, 1) X(190, IoF32, OpTgammaU10, 1) X(191, IoBF16, OpTgammaU10, 1) \
+  X(192, IoF16, OpTgammaU10, 1) X(193, IoF32ViaF64, OpTgammaU10, 1)
+constexpr int NUM_OPS = 194;
 
 // host-side code of a (fn, variant, dtype) triple, or -1
 int op_code(int fn, int v, int t) {
@@ -137,11 +142,13 @@ int op_code(int fn, int v, int t) {
   static const int u10_base[LIBM_HIP_NUM_FN] = {0, 7, 14, 21, 26, 31, 36, 56, 61, 41, 46, 51,
                                                 -1, -1, 70, 77, 84, 93, 98, 103, 108, 113,
                                                 118, 131, 136, 141, 146, 151, -1, -1, -1,
-                                                -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
-  static const int u35_base[LIBM_HIP_NUM_FN] = {5, 12, 19, -1, -1, 91, -1, -1, 123, 125, 127,
+                                                -1, -1, -1, -1, -1, -1, -1, -1, -1, -1,
+                                                184, 189};
+  static const int u35_base[LIBM_HIP_NUM_FN] = {5, 12, 19, -1, -1, 91, -1, 182, 123, 125, 127,
                                                 129, -1, -1, 75, 82, 89, -1, -1, -1, -1, -1,
                                                 -1, -1, -1, -1, -1, -1, -1, -1, -1,
-                                                -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
+                                                -1, -1, -1, -1, -1, -1, -1, -1, -1, -1,
+                                                -1, -1};
   if (fn < 0 || fn >= LIBM_HIP_NUM_FN || t < 0 || t > 4) return -1;
   if (fn == LIBM_HIP_FMOD || fn == LIBM_HIP_REMAINDER) {
     if (v != LIBM_HIP_EXACT || t > 1) return -1;
@@ -160,6 +167,8 @@ int op_code(int fn, int v, int t) {
 // (from the elementwise kernels' measured times: trig with Payne-Hanek and
 // the remainders are the most expensive, exp/log the cheapest)
 float op_cost(int code) {
+  if (code >= 184) return 1.5f;                // lgamma, tgamma
+  if (code >= 182) return 0.75f;               // pow u35
   if (code >= 156) return 0.25f;               // fdim, fmax, fmin and the rest of the exact set
   if (code >= 146) return 0.5f;                // erf, erfc
   if (code >= 131) return 0.55f;               // asinh, acosh, atanh
@@ -178,7 +187,7 @@ float op_cost(int code) {
 
 size_t op_arity(int code) {
   return (code >= 56 && code <= 69) || (code >= 118 && code <= 124) ||
-                 (code >= 156 && code <= 161) || code >= 178
+                 (code >= 156 && code <= 161) || (code >= 178 && code <= 183)
              ? 2
              : 1;
 }

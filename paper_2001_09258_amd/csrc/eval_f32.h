@@ -68,7 +68,9 @@ LMH_INLINE fff expf_core(float rh, float rl) {
   return mk(s.hi, s.lo + w);
 }
 
-LMH_INLINE float expf_u10(float x) {
+// (F_main / F_rare / F as in eval_f64.h: the rare path decides results in
+// the subnormal range)
+LMH_INLINE float expf_u10_main(float x, bool& rare) {
   // beyond +-104 the result overflows / rounds to zero; the clamp keeps
   // k * LN2_HI exact (|k| <= 150)
   float xc = x > 104.0f ? 104.0f : (x < -104.0f ? -104.0f : x);
@@ -77,33 +79,59 @@ LMH_INLINE float expf_u10(float x) {
   float t = k * -LN2_LO_F;
   float rh = s + t;
   float rl = (s - rh) + t;
-  float r = ff_ldexp(expf_core(rh, rl), (int)k);
-  bool sub = k <= -126.0f && k >= -151.0f;          // result below 2^-125
-  if (rare_lane(sub)) {
-    double sh, sl, d;
-    double kd = exp_reduce(sub ? (double)xc : 0.0, sh, sl);
-    float rs = f32_from_units(f32_sub_units(exp_core(sh, sl), (int)kd, d));
-    r = sub ? rs : r;
-  }
+  fff e = expf_core(rh, rl);
+  // results below 2^-125 (the pair is in [0.7, 1.42]); a clamped argument
+  // (x < -104, e^x < 2^-150) rounds to zero on this path
+  rare = k <= -126.0f && x >= -104.0f;
+  float r = ldexp_(e.hi + e.lo, (int)k);
   return isnan_(x) ? x : r;
 }
 
-LMH_INLINE float exp2f_u10(float x) {
+LMH_INLINE float expf_u10_rare(float x) {          // -104 <= x < -87
+  double sh, sl, d;
+  double kd = exp_reduce((double)x, sh, sl);
+  return f32_from_units(f32_sub_units(exp_core(sh, sl), (int)kd, d));
+}
+
+LMH_INLINE float expf_u10(float x) {
+  bool rare;
+  float r = expf_u10_main(x, rare);
+  if (rare_lane(rare)) {
+    float rs = expf_u10_rare(rare ? x : -95.0f);
+    r = rare ? rs : r;
+  }
+  return r;
+}
+
+LMH_INLINE float exp2f_u10_main(float x, bool& rare) {
   float xc = x > 150.0f ? 150.0f : (x < -150.0f ? -150.0f : x);
   float k = rint_(xc);
   float f = xc - k;
   fff t = dd2_mul(f, LN2_F_H);
   t.lo = fma_(f, LN2_F_L, t.lo);
   t = dd2_norm(t);
-  float r = ff_ldexp(expf_core(t.hi, t.lo), (int)k);
-  bool sub = k <= -126.0f && k >= -151.0f;
-  if (rare_lane(sub)) {
-    double fd = sub ? (double)f : 0.0, d;         // f = x - k exactly
-    ddd td = dd2_norm(dd2_add2(dd2_mul(fd, LN2_D_H), dd2_mul(fd, LN2_D_L)));
-    float rs = f32_from_units(f32_sub_units(exp_core(td.hi, td.lo), (int)k, d));
-    r = sub ? rs : r;
-  }
+  fff e = expf_core(t.hi, t.lo);
+  // x <= -150 gives 2^-150 or less: zero (the tie at -150 to even)
+  rare = k <= -126.0f && x > -150.0f;
+  float r = ldexp_(e.hi + e.lo, (int)k);
   return isnan_(x) ? x : r;
+}
+
+LMH_INLINE float exp2f_u10_rare(float x) {         // -150 < x < -125.5
+  float k = rint_(x);
+  double fd = (double)(x - k), d;                   // exact
+  ddd td = dd2_norm(dd2_add2(dd2_mul(fd, LN2_D_H), dd2_mul(fd, LN2_D_L)));
+  return f32_from_units(f32_sub_units(exp_core(td.hi, td.lo), (int)k, d));
+}
+
+LMH_INLINE float exp2f_u10(float x) {
+  bool rare;
+  float r = exp2f_u10_main(x, rare);
+  if (rare_lane(rare)) {
+    float rs = exp2f_u10_rare(rare ? x : -140.0f);
+    r = rare ? rs : r;
+  }
+  return r;
 }
 
 LMH_INLINE fff expf_ff(fff w, float& k, float lim = 104.0f) {
@@ -453,28 +481,66 @@ LMH_INLINE float powf_annexf(float x, float y, float r) {
   return (y == 0.0f || x == 1.0f) ? 1.0f : r;
 }
 
-LMH_INLINE float powf_u10(float x, float y) {
+// 3.5-ULP powf: the same float-float logarithm and product (the logarithm's
+// relative error is multiplied by |y log x|, up to ~104), then the
+// exponential in working precision: the reduced argument keeps the tail of
+// the pair w, e^r = 1 + r + r^2 P(r) in binary32 (~1.3 ULP in all)
+LMH_INLINE float expf_pair_ws(fff w, float& k) {
+  float wh = w.hi > 104.0f ? 104.0f : (w.hi < -104.0f ? -104.0f : w.hi);
+  float wl = wh == w.hi ? w.lo : 0.0f;
+  k = rint_(wh * LOG2E_F);
+  float r = fma_(k, -LN2_HI_F, wh) + (wl + k * -LN2_LO_F);
+  return fma_(r * r, poly_estrin(r, EXP_P_F32), r) + 1.0f;
+}
+
+template <bool U10>
+LMH_INLINE float powf_main(float x, float y, bool& rare) {
   float ax = fabs_(x);
   fff lg = logf_ff(ax);
   fff w = dd2_mul(lg, y);
-  float k;
-  fff e = expf_ff(w, k);
-  float r = ff_ldexp(e, (int)k);                   // overflows / underflows itself
-  bool sub = k <= -126.0f && k >= -151.0f && isfinite_(ax) && ax != 0.0f && isfinite_(y);
-  if (rare_lane(sub)) {
-    // binary64 log and exp pairs (~2^-59 relative for |w| <= 104); an exact
-    // tie between two subnormals is decided by ties-to-even
-    double axd = sub ? (double)ax : 0.5, yd = sub ? (double)y : 1.0, kd, d;
-    ddd ed = exp_dd(dd2_mul(log_dd(axd), yd), kd);
-    double n = f32_sub_units(ed, (int)kd, d);
-    if (fabs_(fabs_(d) - 0.5) < 0x1p-28) {
-      double tie = pow_tie_units(axd, yd, 150.0);
-      n = tie != 0.0 ? rint_(0.5 * tie) : n;
-    }
-    r = sub ? f32_from_units(n) : r;
+  float k, r;
+  if (U10) {
+    fff e = expf_ff(w, k);
+    r = ldexp_(e.hi + e.lo, (int)k);
+  } else {
+    float p = expf_pair_ws(w, k);
+    r = ldexp_(p, (int)k);
   }
+  // results below 2^-125; w clamped at -104 (e^w < 2^-150) rounds to zero
+  rare = k <= -126.0f && w.hi >= -104.0f && isfinite_(ax) && ax != 0.0f && isfinite_(y);
   return powf_annexf(x, y, r);
 }
+
+// binary64 log and exp pairs (~2^-59 relative for |w| <= 104), one rounding
+// at 2^-149; an exact tie between two subnormals is decided by ties-to-even
+LMH_INLINE float powf_rare(float x, float y) {
+  double axd = fabs_((double)x), yd = (double)y, kd, d;
+  ddd ed = exp_dd(dd2_mul(log_dd(axd), yd), kd);
+  double n = f32_sub_units(ed, (int)kd, d);
+  if (fabs_(fabs_(d) - 0.5) < 0x1p-28) {
+    double tie = pow_tie_units(axd, yd, 150.0);
+    n = tie != 0.0 ? rint_(0.5 * tie) : n;
+  }
+  return powf_annexf(x, y, f32_from_units(n));
+}
+
+template <bool U10>
+LMH_INLINE float powf_impl(float x, float y) {
+  bool rare;
+  float r = powf_main<U10>(x, y, rare);
+  if (rare_lane(rare)) {
+    float rs = powf_rare(rare ? x : 0.5f, rare ? y : 140.0f);
+    r = rare ? rs : r;
+  }
+  return r;
+}
+
+LMH_INLINE float powf_u10(float x, float y) { return powf_impl<true>(x, y); }
+LMH_INLINE float powf_u35(float x, float y) { return powf_impl<false>(x, y); }
+LMH_INLINE float powf_u10_main(float x, float y, bool& rare) { return powf_main<true>(x, y, rare); }
+LMH_INLINE float powf_u35_main(float x, float y, bool& rare) { return powf_main<false>(x, y, rare); }
+LMH_INLINE float powf_u10_rare(float x, float y) { return powf_rare(x, y); }
+LMH_INLINE float powf_u35_rare(float x, float y) { return powf_rare(x, y); }
 
 // binary32 forms of atan_poly / atan_ratio (the extra reduction above
 // tan(pi/8) through pi/4 + atan((n - d)/(n + d)))
@@ -671,28 +737,44 @@ LMH_INLINE float tanhf_u10(float x) {
 // ---------------------------------------------------------------------------
 // 3.5-ULP atan2, sinh, cosh, tanh in binary32 (the binary64 forms' structure)
 // ---------------------------------------------------------------------------
-LMH_INLINE float atan2f_u35(float y, float x) {
-  float ay = fabs_(y), ax = fabs_(x);
-  bool both_inf = isinf_(ax) && isinf_(ay);
-  ay = both_inf ? 1.0f : ay;
-  ax = both_inf ? 1.0f : ax;
-  bool swap = ay > ax;
-  float n = swap ? ax : ay, d = swap ? ay : ax;
-  float t = n / d;
-  float z = t * t;
-  float a = fma_(t * z, poly_estrin(z, ATAN_A_F32), t);
-  bool tiny = !swap && t < 0x1p-100f;
-  if (rare_lane(tiny)) {                                 // see atan2_u35
-    float r0 = fma_(-ldexp_(t, 60), d, ldexp_(n, 60));
-    float at = (r0 < 0.0f && -r0 == ldexp_(d, -90)) ? pred_(t) : t;
-    a = tiny ? at : a;
-  }
+LMH_INLINE float atan2f_u35_finish(float y, float x, float a, bool swap) {
   a = swap ? (PIH2_F_H - a) + PIH2_F_L : a;
   bool xneg = __builtin_signbit(x);
   a = xneg ? (PI2_F_H - a) + PI2_F_L : a;
   float r = copysign_(a, y);
   if (y == 0.0f) r = xneg ? copysign_(PI2_F_H, y) : copysign_(0.0f, y);
   return (isnan_(x) || isnan_(y)) ? __builtin_nanf("") : r;
+}
+
+LMH_INLINE float atan2f_u35_main(float y, float x, bool& rare) {
+  float ay = fabs_(y), ax = fabs_(x);
+  bool both_inf = isinf_(ax) && isinf_(ay);
+  ay = both_inf ? 1.0f : ay;
+  ax = both_inf ? 1.0f : ax;
+  bool swap = ay > ax;
+  float t = (swap ? ax : ay) / (swap ? ay : ax);
+  float z = t * t;
+  float a = fma_(t * z, poly_estrin(z, ATAN_A_F32), t);
+  rare = !swap && t < 0x1p-100f && t != 0.0f;
+  return atan2f_u35_finish(y, x, a, swap);
+}
+
+LMH_INLINE float atan2f_u35_rare(float y, float x) {   // see atan2_u35_rare
+  float n = fabs_(y), d = fabs_(x);
+  float t = n / d;
+  float r0 = fma_(-ldexp_(t, 60), d, ldexp_(n, 60));
+  float a = (r0 < 0.0f && -r0 == ldexp_(d, -90)) ? pred_(t) : t;
+  return atan2f_u35_finish(y, x, a, false);
+}
+
+LMH_INLINE float atan2f_u35(float y, float x) {
+  bool rare;
+  float r = atan2f_u35_main(y, x, rare);
+  if (rare_lane(rare)) {
+    float rs = atan2f_u35_rare(rare ? y : 1.0f, rare ? x : 2.0f);
+    r = rare ? rs : r;
+  }
+  return r;
 }
 
 // e^a 2^-s in working precision (|a| <= 104 keeps k * LN2_HI exact)
@@ -783,25 +865,36 @@ LMH_INLINE float log1pf_u10(float x) {
 
 // |x| <= 50 covers every finite, nonzero binary32 result; |k| <= 167 keeps
 // k * LN2_HI (16 bits) exact
-LMH_INLINE float exp10f_u10(float x) {
+LMH_INLINE float exp10f_u10_main(float x, bool& rare) {
   float xc = x > 50.0f ? 50.0f : (x < -50.0f ? -50.0f : x);
   float k = rint_(xc * LOG2_10_F);
   fff a = dd2_mul(xc, LN10_F_H);
   float s = fma_(k, -LN2_HI_F, a.hi);
   float t = fma_(xc, LN10_F_L, a.lo) + k * -LN2_LO_F;
   fff r = dd2_add2(s, t);
-  float v = ff_ldexp(expf_core(r.hi, r.lo), (int)k);
-  bool sub = k <= -126.0f && k >= -151.0f;
-  if (rare_lane(sub)) {
-    // binary64: x ln10 as an exact pair plus x times ln10's tail
-    double xd = sub ? (double)xc : 0.0, d;
-    double kd = rint_(xd * LOG2_10_D);
-    ddd a = dd2_mul(xd, LN10_D_H);
-    ddd rd = dd2_add2(fma_(kd, -LN2_HI_D, a.hi), fma_(xd, LN10_D_L, a.lo) + kd * -LN2_LO_D);
-    float vs = f32_from_units(f32_sub_units(exp_core(rd.hi, rd.lo), (int)kd, d));
-    v = sub ? vs : v;
-  }
+  fff e = expf_core(r.hi, r.lo);
+  rare = k <= -126.0f && k >= -151.0f;              // the clamp gives k = -166
+  float v = ldexp_(e.hi + e.lo, (int)k);
   return isnan_(x) ? x : v;
+}
+
+// binary64: x ln10 as an exact pair plus x times ln10's tail
+LMH_INLINE float exp10f_u10_rare(float x) {        // -45.5 < x < -37.7
+  double xd = (double)x, d;
+  double kd = rint_(xd * LOG2_10_D);
+  ddd a = dd2_mul(xd, LN10_D_H);
+  ddd rd = dd2_add2(fma_(kd, -LN2_HI_D, a.hi), fma_(xd, LN10_D_L, a.lo) + kd * -LN2_LO_D);
+  return f32_from_units(f32_sub_units(exp_core(rd.hi, rd.lo), (int)kd, d));
+}
+
+LMH_INLINE float exp10f_u10(float x) {
+  bool rare;
+  float r = exp10f_u10_main(x, rare);
+  if (rare_lane(rare)) {
+    float rs = exp10f_u10_rare(rare ? x : -40.0f);
+    r = rare ? rs : r;
+  }
+  return r;
 }
 
 // below -18, e^x is under half an ulp of 1 (2^-25) and the result is -1
@@ -943,6 +1036,47 @@ LMH_INLINE float hypotf_u10(float x, float y) {
 // ---------------------------------------------------------------------------
 // exact remainders in binary32 (same long division as binary64)
 // ---------------------------------------------------------------------------
+// binary32 erf and erfc have no rare path (their binary64 working precision
+// rounds subnormal results correctly): the split form reports no rare lane
+LMH_INLINE float erff_u10_main(float x, bool& rare) { rare = false; return erff_u10(x); }
+LMH_INLINE float erff_u10_rare(float x) { return erff_u10(x); }
+LMH_INLINE float erfcf_u10_main(float x, bool& rare) { rare = false; return erfcf_u10(x); }
+LMH_INLINE float erfcf_u10_rare(float x) { return erfcf_u10(x); }
+
+// lgamma and tgamma in binary32: the binary64 evaluators' pairs rounded once
+// into binary32 (lgamma never has a binary32 subnormal result; tgamma's
+// subnormal results are rounded from the exponential's pair at 2^-149).
+LMH_INLINE float lgammaf_u10(float x) {
+  double r = lgamma_u10((double)x);
+  return (float)r;
+}
+
+LMH_INLINE float tgammaf_u10_main(float x, bool& rare) {
+  bool rare64;                       // binary64 subnormal results: zero in binary32
+  float r = (float)tgamma_u10_main((double)x, rare64);
+  rare = fabs_(r) < 0x1p-125f && isfinite_(x) && x < 0.0f && rint_(x) != x && x > -60.0f;
+  return r;
+}
+
+LMH_INLINE float tgammaf_u10_rare(float x) {       // results below 2^-125
+  double xd = (double)x, k, d;
+  bool ovf;
+  ddd l = lgamma_dd<false>(xd, ovf);
+  ddd e = exp_dd(l, k);
+  float v = f32_from_units(f32_sub_units(e, (int)k, d));
+  return floor_is_odd(xd) ? -v : v;
+}
+
+LMH_INLINE float tgammaf_u10(float x) {
+  bool rare;
+  float r = tgammaf_u10_main(x, rare);
+  if (rare_lane(rare)) {
+    float rs = tgammaf_u10_rare(rare ? x : -40.5f);
+    r = rare ? rs : r;
+  }
+  return r;
+}
+
 LMH_INLINE fff fmodf_step(fff r, float d, float dm, float rdm, int de) {   // see fmod_step
   float rm = frexp_mant_(r.hi);
   int re = frexp_exp_(r.hi);

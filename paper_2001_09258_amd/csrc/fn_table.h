@@ -24,13 +24,14 @@
   X(ASINH, U10, asinh_u10, asinhf_u10) X(ACOSH, U10, acosh_u10, acoshf_u10)           \
   X(ATANH, U10, atanh_u10, atanhf_u10)                                                \
   X(ERF, U10, erf_u10, erff_u10) X(ERFC, U10, erfc_u10, erfcf_u10)                   \
+  X(LGAMMA, U10, lgamma_u10, lgammaf_u10) X(TGAMMA, U10, tgamma_u10, tgammaf_u10)    \
   X(SQRT, EXACT, sqrt_f64, sqrtf_f32) X(TRUNC, EXACT, trunc_f64, truncf_f32)         \
   X(FLOOR, EXACT, floor_f64, floorf_f32) X(CEIL, EXACT, ceil_f64, ceilf_f32)         \
   X(ROUND, EXACT, round_f64, roundf_f32) X(RINT, EXACT, rint_f64, rintf_f32)         \
   X(FABS, EXACT, fabs_f64, fabsf_f32) X(LOGB, EXACT, logb_f64, logbf_f32)
 
 #define LMH_CONSISTENT_BINARY(X)                                                      \
-  X(POW, U10, pow_u10, powf_u10)                                                      \
+  X(POW, U10, pow_u10, powf_u10) X(POW, U35, pow_u35, powf_u35)                       \
   X(ATAN2, U10, atan2_u10, atan2f_u10) X(ATAN2, U35, atan2_u35, atan2f_u35)           \
   X(HYPOT, U10, hypot_u10, hypotf_u10)                                                \
   X(FMOD, EXACT, fmod_f64, fmodf_f32) X(REMAINDER, EXACT, remainder_f64, remainderf_f32)     \

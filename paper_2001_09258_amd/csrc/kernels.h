@@ -10,6 +10,7 @@
 // become exec-masked selects.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include "ops.h"
 
@@ -18,6 +19,62 @@ using namespace lmh_ops;
 
 constexpr int BLOCK = 256;          // workgroup of the gathered-trig kernels
 constexpr int MAX_BLOCK = 1024;
+
+// Operations with a rare accurate path (a static member kRare) are evaluated
+// in two steps over a pack: the common path for every element, then, if any
+// lane of the wave flagged an element, the rare path for the flagged ones.
+// The pack's evaluations stay one stretch of code the compiler interleaves.
+template <class Op, class = void>
+struct HasRare {
+  static constexpr bool value = false;
+};
+template <class Op>
+struct HasRare<Op, std::void_t<decltype(Op::kRare)>> {
+  static constexpr bool value = Op::kRare;
+};
+
+template <class Io, class Op, int EPT, class S>
+__device__ __forceinline__ void eval_pack1(const Pack<S, EPT>& in, Pack<S, EPT>& out) {
+  if constexpr (HasRare<Op>::value) {
+    bool rare[EPT];
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      out.v[i] = Io::out(Op::main(Io::in(in.v[i]), rare[i]));
+      any = any || rare[i];
+    }
+    if (lmh::rare_lane(any)) {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i)
+        if (rare[i]) out.v[i] = Io::out(Op::rare(Io::in(in.v[i])));
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) out.v[i] = Io::out(Op::f(Io::in(in.v[i])));
+  }
+}
+
+template <class Io, class Op, int EPT, class S>
+__device__ __forceinline__ void eval_pack2(const Pack<S, EPT>& ia, const Pack<S, EPT>& ib,
+                                           Pack<S, EPT>& out) {
+  if constexpr (HasRare<Op>::value) {
+    bool rare[EPT];
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      out.v[i] = Io::out(Op::main(Io::in(ia.v[i]), Io::in(ib.v[i]), rare[i]));
+      any = any || rare[i];
+    }
+    if (lmh::rare_lane(any)) {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i)
+        if (rare[i]) out.v[i] = Io::out(Op::rare(Io::in(ia.v[i]), Io::in(ib.v[i])));
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) out.v[i] = Io::out(Op::f(Io::in(ia.v[i]), Io::in(ib.v[i])));
+  }
+}
 
 // Each workgroup covers blockDim.x * PACKS packs; pack u of a lane is
 // (block_base + u * blockDim.x + lane), so every iteration is one fully
@@ -34,8 +91,7 @@ __global__ __launch_bounds__(MAX_BLOCK) void k_unary(const typename Io::S* __res
     if (VEC && base + EPT <= n) {
       Pack<S, EPT> in = *reinterpret_cast<const Pack<S, EPT>*>(x + base);
       Pack<S, EPT> out;
-#pragma unroll
-      for (int i = 0; i < EPT; ++i) out.v[i] = Io::out(Op::f(Io::in(in.v[i])));
+      eval_pack1<Io, Op, EPT>(in, out);
       store_nt(out, y + base);
     } else {
 #pragma unroll
@@ -60,9 +116,7 @@ __global__ __launch_bounds__(MAX_BLOCK) void k_binary(const typename Io::S* __re
       Pack<S, EPT> ia = *reinterpret_cast<const Pack<S, EPT>*>(a + base);
       Pack<S, EPT> ib = *reinterpret_cast<const Pack<S, EPT>*>(b + base);
       Pack<S, EPT> out;
-#pragma unroll
-      for (int i = 0; i < EPT; ++i)
-        out.v[i] = Io::out(Op::f(Io::in(ia.v[i]), Io::in(ib.v[i])));
+      eval_pack2<Io, Op, EPT>(ia, ib, out);
       store_nt(out, y + base);
     } else {
 #pragma unroll

@@ -291,6 +291,8 @@ LMH_DEF_UNARY(acosh, u10, OpAcoshU10, ACOSH, U10)
 LMH_DEF_UNARY(atanh, u10, OpAtanhU10, ATANH, U10)
 LMH_DEF_UNARY(erf, u10, OpErfU10, ERF, U10)
 LMH_DEF_UNARY(erfc, u10, OpErfcU10, ERFC, U10)
+LMH_DEF_UNARY(lgamma, u10, OpLgammaU10, LGAMMA, U10)
+LMH_DEF_UNARY(tgamma, u10, OpTgammaU10, TGAMMA, U10)
 LMH_DEF_UNARY_HALF(sin, OpSinU10, SIN)
 LMH_DEF_UNARY_HALF(cos, OpCosU10, COS)
 LMH_DEF_UNARY_HALF(tan, OpTanU10, TAN)
@@ -314,6 +316,8 @@ LMH_DEF_UNARY_HALF(acosh, OpAcoshU10, ACOSH)
 LMH_DEF_UNARY_HALF(atanh, OpAtanhU10, ATANH)
 LMH_DEF_UNARY_HALF(erf, OpErfU10, ERF)
 LMH_DEF_UNARY_HALF(erfc, OpErfcU10, ERFC)
+LMH_DEF_UNARY_HALF(lgamma, OpLgammaU10, LGAMMA)
+LMH_DEF_UNARY_HALF(tgamma, OpTgammaU10, TGAMMA)
 
 #define LMH_DEF_SINCOS(var, Io, T, tag, Op)                                                        \
   libm_hip_status libm_hip_sincos_##var##_##tag(const T* x, T* s, T* c, size_t n, void* stream) {  \
@@ -343,6 +347,8 @@ LMH_DEF_BINARY(atan2, _u10, IoBF16, uint16_t, bf16, OpAtan2U10, LMH_KEY(ATAN2, U
 LMH_DEF_BINARY(atan2, _u10, IoF16, uint16_t, f16, OpAtan2U10, LMH_KEY(ATAN2, U10, F16))
 LMH_DEF_BINARY(atan2, _u10, IoF32ViaF64, float, f32_via_f64, OpAtan2U10, LMH_KEY(ATAN2, U10, F32_VIA_F64))
 LMH_DEF_BINARY(atan2, _u35, IoF64, double, f64, OpAtan2U35, LMH_KEY(ATAN2, U35, F64))
+LMH_DEF_BINARY(pow, _u35, IoF64, double, f64, OpPowU35, LMH_KEY(POW, U35, F64))
+LMH_DEF_BINARY(pow, _u35, IoF32, float, f32, OpPowU35, LMH_KEY(POW, U35, F32))
 LMH_DEF_BINARY(atan2, _u35, IoF32, float, f32, OpAtan2U35, LMH_KEY(ATAN2, U35, F32))
 LMH_DEF_BINARY(hypot, _u10, IoF64, double, f64, OpHypotU10, LMH_KEY(HYPOT, U10, F64))
 LMH_DEF_BINARY(hypot, _u10, IoF32, float, f32, OpHypotU10, LMH_KEY(HYPOT, U10, F32))
@@ -648,9 +654,14 @@ extern "C" libm_hip_status libm_hip_eval(libm_hip_fn fn, libm_hip_variant v, lib
     case LIBM_HIP_ACOSH: if (u10) return dispatch_unary<OpAcoshU10>(t, a, out, n, s, false, key); break;
     case LIBM_HIP_ATANH: if (u10) return dispatch_unary<OpAtanhU10>(t, a, out, n, s, false, key); break;
     case LIBM_HIP_ERF: if (u10) return dispatch_unary<OpErfU10>(t, a, out, n, s, false, key); break;
+    case LIBM_HIP_LGAMMA: if (u10) return dispatch_unary<OpLgammaU10>(t, a, out, n, s, false, key); break;
+    case LIBM_HIP_TGAMMA: if (u10) return dispatch_unary<OpTgammaU10>(t, a, out, n, s, false, key); break;
     case LIBM_HIP_ERFC: if (u10) return dispatch_unary<OpErfcU10>(t, a, out, n, s, false, key); break;
     case LIBM_HIP_HYPOT: if (u10) return dispatch_binary<OpHypotU10>(t, a, b, out, n, s, true, key); break;
-    case LIBM_HIP_POW: if (u10) return dispatch_binary<OpPowU10>(t, a, b, out, n, s, true, key); break;
+    case LIBM_HIP_POW:
+      if (u10) return dispatch_binary<OpPowU10>(t, a, b, out, n, s, true, key);
+      if (u35) return dispatch_binary<OpPowU35>(t, a, b, out, n, s, false, key);
+      break;
     case LIBM_HIP_ATAN2:
       if (u10) return dispatch_binary<OpAtan2U10>(t, a, b, out, n, s, true, key);
       if (u35) return dispatch_binary<OpAtan2U35>(t, a, b, out, n, s, false, key);

@@ -64,6 +64,35 @@ struct IoF16 {
     static __device__ __forceinline__ double f(double x) { return lmh::F64FN(x); } \
     static __device__ __forceinline__ float f(float x) { return lmh::F32FN(x); }   \
   };
+// tags of evaluators with a rare accurate path (results in the subnormal
+// range): main(x, rare) is the common path and flags the lanes that need
+// rare(x); f(x) does both.  The elementwise kernels evaluate main for a whole
+// pack and then rare once for the flagged elements.
+#define LMH_OP1R(NAME, F64FN, F32FN)                                                         \
+  struct NAME {                                                                            \
+    static constexpr bool kSplit = false;                                                  \
+    static constexpr bool kRare = true;                                                    \
+    static __device__ __forceinline__ double f(double x) { return lmh::F64FN(x); }         \
+    static __device__ __forceinline__ float f(float x) { return lmh::F32FN(x); }           \
+    static __device__ __forceinline__ double main(double x, bool& r) { return lmh::F64FN##_main(x, r); } \
+    static __device__ __forceinline__ float main(float x, bool& r) { return lmh::F32FN##_main(x, r); }   \
+    static __device__ __forceinline__ double rare(double x) { return lmh::F64FN##_rare(x); }  \
+    static __device__ __forceinline__ float rare(float x) { return lmh::F32FN##_rare(x); }    \
+  };
+#define LMH_OP2R(NAME, F64FN, F32FN)                                                         \
+  struct NAME {                                                                            \
+    static constexpr bool kRare = true;                                                    \
+    static __device__ __forceinline__ double f(double a, double b) { return lmh::F64FN(a, b); } \
+    static __device__ __forceinline__ float f(float a, float b) { return lmh::F32FN(a, b); }    \
+    static __device__ __forceinline__ double main(double a, double b, bool& r) {           \
+      return lmh::F64FN##_main(a, b, r);                                                   \
+    }                                                                                      \
+    static __device__ __forceinline__ float main(float a, float b, bool& r) {              \
+      return lmh::F32FN##_main(a, b, r);                                                   \
+    }                                                                                      \
+    static __device__ __forceinline__ double rare(double a, double b) { return lmh::F64FN##_rare(a, b); } \
+    static __device__ __forceinline__ float rare(float a, float b) { return lmh::F32FN##_rare(a, b); }    \
+  };
 #define LMH_OP2(NAME, F64FN, F32FN)                                                        \
   struct NAME {                                                                          \
     static __device__ __forceinline__ double f(double a, double b) { return lmh::F64FN(a, b); } \
@@ -139,8 +168,8 @@ LMH_TRIG_OP(OpCosU10, cos_u10, cosf_u10, sincos, sincosf, LMH_COMMA true, cos_fi
 LMH_TRIG_OP(OpCosU35, cos_u35, cosf_u35, sincos, sincosf, LMH_COMMA true, cos_finish_u35, cosf_finish_u35)
 LMH_TRIG_OP(OpTanU10, tan_u10, tanf_u10, tan, tanf, LMH_NOARG, tan_finish_u10, tanf_finish_u10)
 LMH_TRIG_OP(OpTanU35, tan_u35, tanf_u35, tan, tanf, LMH_NOARG, tan_finish_u35, tanf_finish_u35)
-LMH_OP1(OpExpU10, exp_u10, expf_u10)
-LMH_OP1(OpExp2U10, exp2_u10, exp2f_u10)
+LMH_OP1R(OpExpU10, exp_u10, expf_u10)
+LMH_OP1R(OpExp2U10, exp2_u10, exp2f_u10)
 LMH_OP1(OpLogU10, log_u10, logf_u10)
 LMH_OP1(OpLogU35, log_u35, logf_u35)
 LMH_OP1(OpLog2U10, log2_u10, log2f_u10)
@@ -155,20 +184,23 @@ LMH_OP1(OpAtanU10, atan_u10, atanf_u10)
 LMH_OP1(OpAtanU35, atan_u35, atanf_u35)
 LMH_OP1(OpLog10U10, log10_u10, log10f_u10)
 LMH_OP1(OpLog1pU10, log1p_u10, log1pf_u10)
-LMH_OP1(OpExp10U10, exp10_u10, exp10f_u10)
+LMH_OP1R(OpExp10U10, exp10_u10, exp10f_u10)
 LMH_OP1(OpExpm1U10, expm1_u10, expm1f_u10)
 LMH_OP1(OpCbrtU10, cbrt_u10, cbrtf_u10)
 LMH_OP1(OpAsinhU10, asinh_u10, asinhf_u10)
 LMH_OP1(OpAcoshU10, acosh_u10, acoshf_u10)
 LMH_OP1(OpAtanhU10, atanh_u10, atanhf_u10)
-LMH_OP1(OpErfU10, erf_u10, erff_u10)
-LMH_OP1(OpErfcU10, erfc_u10, erfcf_u10)
+LMH_OP1R(OpErfU10, erf_u10, erff_u10)
+LMH_OP1R(OpErfcU10, erfc_u10, erfcf_u10)
+LMH_OP1(OpLgammaU10, lgamma_u10, lgammaf_u10)
+LMH_OP1R(OpTgammaU10, tgamma_u10, tgammaf_u10)
 LMH_OP2(OpHypotU10, hypot_u10, hypotf_u10)
 LMH_OP1(OpSinhU35, sinh_u35, sinhf_u35)
 LMH_OP1(OpCoshU35, cosh_u35, coshf_u35)
 LMH_OP1(OpTanhU35, tanh_u35, tanhf_u35)
-LMH_OP2(OpAtan2U35, atan2_u35, atan2f_u35)
-LMH_OP2(OpPowU10, pow_u10, powf_u10)
+LMH_OP2R(OpAtan2U35, atan2_u35, atan2f_u35)
+LMH_OP2R(OpPowU10, pow_u10, powf_u10)
+LMH_OP2R(OpPowU35, pow_u35, powf_u35)
 LMH_OP2(OpAtan2U10, atan2_u10, atan2f_u10)
 LMH_OP2(OpFmod, fmod_f64, fmodf_f32)
 LMH_OP2(OpRemainder, remainder_f64, remainderf_f32)

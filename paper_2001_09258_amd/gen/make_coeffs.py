@@ -72,6 +72,27 @@ def log_r7():
     return f, w, mp.mpf(0), mp.mpf(1) / 25 * mp.mpf("1.01")
 
 
+LGAM_T = mp.mpf("0.0625")
+
+
+def lgam1():
+    # log Gamma(1 + t) = -gamma t + t^2 L1(t), |t| <= 1/16
+    f = _series_guard(lambda t: (mp.loggamma(1 + t) + mp.euler * t) / t ** 2,
+                      lambda t: mp.zeta(2) / 2 - mp.zeta(3) / 3 * t + mp.zeta(4) / 4 * t ** 2)
+    # relative weight t^2 / |log Gamma(1 + t)| = |t| / |-gamma + t L1(t)|
+    w = lambda t: abs(t) / abs(-mp.euler + t * f(t))
+    return f, w, -LGAM_T * mp.mpf("1.001"), LGAM_T * mp.mpf("1.001")
+
+
+def lgam2():
+    # log Gamma(2 + t) = (1 - gamma) t + t^2 L2(t), |t| <= 1/16
+    f = _series_guard(lambda t: (mp.loggamma(2 + t) - (1 - mp.euler) * t) / t ** 2,
+                      lambda t: (mp.zeta(2) - 1) / 2 - (mp.zeta(3) - 1) / 3 * t
+                      + (mp.zeta(4) - 1) / 4 * t ** 2)
+    w = lambda t: abs(t) / abs((1 - mp.euler) + t * f(t))
+    return f, w, -LGAM_T * mp.mpf("1.001"), LGAM_T * mp.mpf("1.001")
+
+
 def sin_s():
     # sin r = r + r^3 S(r^2), |r| <= pi/2
     f = _series_guard(lambda z: (mp.sin(mp.sqrt(z)) - mp.sqrt(z)) / z ** mp.mpf(1.5),
@@ -175,6 +196,8 @@ SPECS = [
     ("LOG_Q_F64", log_q, "f64", -62, 6),
     ("LOG_R_F64", log_r, "f64", -60, 7),
     ("LOG_R7_F64", log_r7, "f64", -67, 5),
+    ("LGAM1_F64", lgam1, "f64", -60, 8),
+    ("LGAM2_F64", lgam2, "f64", -60, 8),
     ("SIN_S_F64", sin_s, "f64", -60, 7),
     ("SIN_S2_F64", sin_s2, "f64", -62, 6),
     ("SIN_S3_F64", sin_s3, "f64", -62, 5),

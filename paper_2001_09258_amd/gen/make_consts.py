@@ -109,6 +109,39 @@ def accurate_path_constants(lines, ln2, head):
     table("ERFC_ASYM_D", asym)
 
 
+def gamma_constants(lines):
+    """lgamma/tgamma: Euler's gamma, 1 - gamma, log(2 pi)/2 and log pi as
+    pairs; Stirling's coefficients B_2k / (2k (2k - 1)), k = 1..10, from
+    exact Bernoulli numbers."""
+    from fractions import Fraction
+    P = "__device__ constexpr double "
+    for name, v in (("EULER", mp.euler), ("ONE_M_EULER", 1 - mp.euler),
+                    ("HALF_LN2PI", mp.log(2 * mp.pi) / 2), ("LNPI", mp.log(mp.pi))):
+        h, l = split(v, 2, "f64")
+        lines.append(P + "%s_D_H = %s;" % (name, hx(h, "f64")))
+        lines.append(P + "%s_D_L = %s;" % (name, hx(l, "f64")))
+    bern = [Fraction(1)]
+    for m in range(1, 22):
+        acc, c = Fraction(0), 1
+        for j in range(m):
+            acc += c * bern[j]
+            c = c * (m + 1 - j) // (j + 1)
+        bern.append(-acc / (m + 1))
+    coef = [bern[2 * k] / (2 * k * (2 * k - 1)) for k in range(1, 11)]
+    lines.append(P + "LGAM_STIRLING_D[10] = {%s};" % ", ".join(
+        hx(rnd(mp.mpf(c.numerator) / c.denominator, "f64"), "f64") for c in coef))
+    lines.append(P + "LGAM_STIRLING_TAIL_D[9] = {%s};" % ", ".join(
+        hx(rnd(mp.mpf(c.numerator) / c.denominator, "f64"), "f64") for c in coef[1:]))
+    # sine's Taylor series for the accurate reflection: 1/7! and 1/9! as
+    # pairs, the terms from r^11 on as doubles
+    for name, n in (("INV5040", 7), ("INV362880", 9)):
+        h, l = split(mp.mpf(1) / mp.factorial(n), 2, "f64")
+        lines.append(P + "%s_D_H = %s;" % (name, hx(h, "f64")))
+        lines.append(P + "%s_D_L = %s;" % (name, hx(l, "f64")))
+    tail = [(-1) ** (k + 1) / mp.factorial(11 + 2 * k) for k in range(8)]
+    lines.append(P + "SIN_TAYLOR11_D[8] = {%s};" % ", ".join(hx(rnd(v, "f64"), "f64") for v in tail))
+
+
 def hx(v, fmt):
     return float(v).hex() + ("f" if fmt == "f32" else "")
 
@@ -140,6 +173,7 @@ def main():
             lines.append(P + "%s_%s_L = %s;" % (name, sfx, hx(l, fmt)))
         if fmt == "f64":
             accurate_path_constants(lines, ln2, head)
+            gamma_constants(lines)
         for name, v in (("LOG2E", 1 / mp.log(2)), ("INV_PI", 1 / mp.pi),
                         ("TWO_OVER_PI", 2 / mp.pi), ("LOG2_10", mp.log(10, 2))):
             lines.append(P + "%s_%s = %s;" % (name, sfx, hx(rnd(v, fmt), fmt)))

@@ -37,6 +37,7 @@ __global__ void p64_pow(const double* x, double* y) { int i = threadIdx.x; y[i] 
 __global__ void p64_atan2(const double* x, double* y) { int i = threadIdx.x; y[i] = atan2_u10(x[i], x[i+64]); }
 __global__ void p64_hypot(const double* x, double* y) { int i = threadIdx.x; y[i] = hypot_u10(x[i], x[i+64]); }
 __global__ void p64_atan235(const double* x, double* y) { int i = threadIdx.x; y[i] = atan2_u35(x[i], x[i+64]); }
+__global__ void p64_pow35(const double* x, double* y) { int i = threadIdx.x; y[i] = pow_u35(x[i], x[i+64]); }
 K1(p64_sinh35, double, sinh_u35(v))
 K1(p64_cosh35, double, cosh_u35(v))
 K1(p64_tanh35, double, tanh_u35(v))
@@ -79,6 +80,7 @@ __global__ void p32_pow(const float* x, float* y) { int i = threadIdx.x; y[i] = 
 __global__ void p32_atan2(const float* x, float* y) { int i = threadIdx.x; y[i] = atan2f_u10(x[i], x[i+64]); }
 __global__ void p32_hypot(const float* x, float* y) { int i = threadIdx.x; y[i] = hypotf_u10(x[i], x[i+64]); }
 __global__ void p32_atan235(const float* x, float* y) { int i = threadIdx.x; y[i] = atan2f_u35(x[i], x[i+64]); }
+__global__ void p32_pow35(const float* x, float* y) { int i = threadIdx.x; y[i] = powf_u35(x[i], x[i+64]); }
 K1(p32_sinh35, float, sinhf_u35(v))
 K1(p32_cosh35, float, coshf_u35(v))
 K1(p32_tanh35, float, tanhf_u35(v))

@@ -94,6 +94,7 @@ extern "C" int device_api_eval(int fn, int variant, int dtype, const void* a, co
       case 16: U1W(atan_u35)
       case 5: U1W(log_u35)
       case 8: B2W(atan2_u35)
+      case 7: B2W(pow_u35)
       case 9: U1W(sinh_u35)
       case 10: U1W(cosh_u35)
       case 11: U1W(tanh_u35)
@@ -129,6 +130,8 @@ extern "C" int device_api_eval(int fn, int variant, int dtype, const void* a, co
     case 25: U1(atanh_u10)
     case 26: U1(erf_u10)
     case 27: U1(erfc_u10)
+    case 41: U1(lgamma_u10)
+    case 42: U1(tgamma_u10)
     case 28: B2W(fdim)
     case 29: B2W(fmax)
     case 30: B2W(fmin)

@@ -29,7 +29,7 @@ FN_IDS = {name: i for i, name in enumerate(
      "sinh", "cosh", "tanh", "fmod", "remainder", "asin", "acos", "atan",
      "log10", "log1p", "exp10", "expm1", "cbrt", "hypot", "asinh", "acosh", "atanh",
      "erf", "erfc", "fdim", "fmax", "fmin", "sqrt", "trunc", "floor", "ceil", "round",
-     "rint", "fabs", "logb", "copysign", "nextafter"])}
+     "rint", "fabs", "logb", "copysign", "nextafter", "lgamma", "tgamma"])}
 
 DTYPE_MAX = {"f64": np.finfo(np.float64).max, "f32": float(np.finfo(np.float32).max),
              "f16": 65504.0, "bf16": 3.3895313892515355e38}
@@ -206,7 +206,9 @@ def function_mixture(fn, dt, n=1 << 26, operand=0):
     1 + x cancels.  For erf and erfc 60% of the elements become U[-w, w]
     (erf) or U[-w, v] (erfc), where w = 6 (binary64) or 4 and v is where erfc
     underflows the format (27.3, 10.1 for binary32 and bf16, 4 for f16): the
-    range where the results are neither saturated nor zero."""
+    range where the results are neither saturated nor zero.  lgamma and
+    tgamma: 40% U[-10, 10], and for tgamma 30% over the range where its
+    results are finite and nonzero (binary64 U[-190, 175])."""
     if fn in ("asin", "acos", "atanh"):
         return unit_mixture(fn, dt, n, operand)
     if dt in ("bf16", "f16"):
@@ -229,6 +231,19 @@ def function_mixture(fn, dt, n=1 << 26, operand=0):
             shifted = _cast(np.abs(x.astype(np.float64)) + 1.0, dt)
             close = _cast(1.0 + np.exp(rng.uniform(near, 0.0, n) * np.log(10.0)), dt)
         x = np.where(c < 0.6, shifted, np.where(c < 0.9, close, x))
+    if fn in ("lgamma", "tgamma"):
+        # 40% U[-10, 10] (both signs, the zeros of lgamma at 1 and 2, the
+        # poles), and for tgamma 30% U[-190, 175] (results across the whole
+        # range, subnormal ones near -180)
+        rng = rng_for(12, fn, operand)
+        c = rng.random(n)
+        m = c < 0.4
+        x[m] = _cast(rng.uniform(-10.0, 10.0, int(m.sum())), dt)
+        if fn == "tgamma":
+            hi = {"f64": 175.0, "f32": 36.0, "bf16": 36.0, "f16": 9.0}[dt]
+            lo = {"f64": -190.0, "f32": -46.0, "bf16": -46.0, "f16": -12.0}[dt]
+            m = (c >= 0.4) & (c < 0.7)
+            x[m] = _cast(rng.uniform(lo, hi, int(m.sum())), dt)
     if fn in ("erf", "erfc"):
         rng = rng_for(11, fn, operand)
         w = 6.0 if dt == "f64" else 4.0
@@ -298,6 +313,7 @@ SUBNORMAL_FNS = {
     "exp2": {"f64": (-1075.0, -1022.0), "f32": (-150.0, -126.0)},
     "exp10": {"f64": (-323.65, -307.6), "f32": (-45.2, -37.9)},
     "erfc": {"f64": (26.5, 27.3), "f32": (9.1, 10.1)},
+    "tgamma": {"f64": (-177.5, -171.5), "f32": (-38.8, -34.3)},
     "pow": "power", "atan2": "quotient", "hypot": "tiny-pair",
     "erf": "tiny", "sin": "tiny", "tan": "tiny", "asin": "tiny", "atan": "tiny",
     "sinh": "tiny", "tanh": "tiny", "asinh": "tiny", "atanh": "tiny",
