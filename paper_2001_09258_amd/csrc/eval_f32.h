@@ -55,7 +55,6 @@ LMH_INLINE double f32_sub_units(ddd v, int q, double& d) {
 
 LMH_INLINE float f32_from_units(double n) { return ldexp_((float)n, -149); }
 
-LMH_INLINE float mod4f(float v) { return v - 4.0f * rint_(v * 0.25f); }
 LMH_INLINE bool is_odd_intf(float q) { return q - 2.0f * rint_(q * 0.5f) != 0.0f; }
 
 // ---------------------------------------------------------------------------
@@ -205,67 +204,69 @@ LMH_INLINE float log2f_u10(float x) {
 // ---------------------------------------------------------------------------
 // trigonometric reductions in binary32
 // ---------------------------------------------------------------------------
-// Cody-Waite for |x| < 65536, carried out in binary64: a binary64 FMA costs
-// one issue slot on gfx950, a float-float step several.  x and q are exact
-// as doubles; C0 (37 bits, truncated) makes q*C0 exact for |q| < 2^16, and
-// x - q*C0 is exact (Sterbenz's lemma for q = rint(x/C); cos with q = +-1
-// and small x: exact for |x| >= 2^-29, and below 2^-12 the finisher returns
-// 1).  One more FMA with the nearest double to C - C0 leaves an error below
-// 2^-73, against a reduced argument of at least 2^-27.8 for |x| < 65536 (the
-// float nearest to 161 pi/2).  The result is split into a float pair
-// (hi + lo carries 48 bits).
-LMH_INLINE fff cwf_reduce(float x, float q, double c0, double c1) {
-  double qd = (double)q;
-  double r = fma_(qd, -c1, fma_(qd, -c0, (double)x));
-  float hi = (float)r;
-  return mk(hi, (float)(r - (double)hi));
-}
-
-// Payne-Hanek in binary32: |x| = m 2^(ex-23), m < 2^24 an integer; the
-// table row holds (2^(ex-23) 2/pi) mod 4 in four 23-bit fixed-position limbs.
-LMH_INLINE fff phf_reduce(float ax, float& k) {
-  int ex = frexp_exp_(ax) - 1;
-  ex = ex < 0 ? 0 : (ex > 127 ? 127 : ex);
-  float m = ldexp_(frexp_mant_(ax), 24);
-  const float* W = PH_TABLE_F32 + 4 * ex;
-  float w0 = W[0], w1 = W[1], w2 = W[2], w3 = W[3];
-  fff p = dd2_mul(m, w0);
-  float i0 = rint_(p.hi), j0 = rint_(p.lo);
-  float x0 = (p.hi - i0) + (p.lo - j0);
-  float k0 = rint_(x0);
-  x0 -= k0;
-  float q = mod4f(i0) + mod4f(j0) + k0;
-  fff s = mk(x0, 0.0f);
-  s = dd2_add2(s, dd2_mul(m, w1));
-  float k1 = rint_(s.hi);
-  s = dd2_norm(mk(s.hi - k1, s.lo));
-  s = dd2_add2(s, dd2_mul(m, w2));
-  float k2 = rint_(s.hi);
-  s = dd2_norm(mk(s.hi - k2, s.lo));
-  s = dd2_add2(s, dd2_mul(m, w3));
-  float k3 = rint_(s.hi);
-  s = dd2_norm(mk(s.hi - k3, s.lo));
-  k = mod4f(q + k1 + k2 + k3);
-  return dd2_mul(s, mk(PIH2_F_H, PIH2_F_L));
-}
-
-LMH_INLINE fff phf_reduce_signed(float x, float& k) {
-  fff r = phf_reduce(fabs_(x), k);
-  if (x < 0.0f) {
-    r = dd2_neg(r);
-    k = -k;
+// Cody-Waite for |x| < 65536 in float-float (binary32 arithmetic only):
+// r = x - q C with C = c0 + c1 + c2 + c3 (c0 the nearest float, c1 the rest
+// to 8 significant bits, c2 and c3 nearest floats; together within 2^-78
+// of C), |q| < 2^16.
+// * x - q c0 is exact, so one FMA forms it: both are multiples of the last
+//   place of c0 or of x (|x| >= 1/2 wherever q != 0), and the difference is
+//   below 2 (C = pi) or 1 (C = pi/2) in magnitude, 24 bits.  cos's q = +-1
+//   meets |x| < 1, where the difference is not exact: ODD_HEAD adds the
+//   two-sum error there (q c0 = +-c0 is exact).
+// * q c1 is exact (at most 16 + 8 bits) and r0 - q c1 is a two-sum; q c2,
+//   below 2^-17, is an exact FMA pair whose head is a second two-sum.
+// * The low words left are added rounded.  Where r is small, s is within
+//   2^-17 of r, so every low word is below 2^-40 and the error about 2^-64
+//   absolute, against a reduced argument of at least 2^-27.8 for
+//   |x| < 65536 (the float nearest to 161 pi/2); elsewhere the low words are
+//   below 2^-24 |r| and the error below 2^-47 |r|.
+template <bool ODD_HEAD>
+LMH_INLINE fff cwf_reduce(float x, float q, float c0, float c1, float c2, float c3) {
+  float r0 = fma_(q, -c0, x);
+  float e0 = 0.0f;
+  if (ODD_HEAD) {
+    float qc = q * -c0;                           // exact for q = +-1
+    float v = r0 - x;
+    e0 = fabs_(x) < 1.0f ? (x - (r0 - v)) + (qc - v) : 0.0f;
   }
-  return r;
+  fff s = dd2_add2(r0, q * -c1);
+  fff p2 = dd2_mul(q, -c2);
+  fff t = dd2_add2(s.hi, p2.hi);
+  float lo = ((s.lo + t.lo) + e0) + fma_(q, -c3, p2.lo);
+  return dd2_add(t.hi, lo);
 }
 
-LMH_INLINE fff quadrant_to_half_periodf(fff r, float k, float& j) {
-  if (is_odd_intf(k)) {
-    float sg = r.hi >= 0.0f ? 1.0f : -1.0f;
-    r = dd2_add2(r, mk(-sg * PIH2_F_H, -sg * PIH2_F_L));
-    k += sg;
-  }
-  j = k * 0.5f;
-  return r;
+// Payne-Hanek in binary32, the binary64 core's steps in float-float:
+// |x| = m 2^(ex-23), m < 2^24 an integer; row e of the table holds
+// (2^(e-23) 2/pi) mod 4 in four 23-bit fixed-position limbs (limb i: the
+// weights 2^(1-23i) .. 2^(-21-23i)), row ex for 2|x|/pi, row ex-1 for
+// |x|/pi.  Returns f = rfrac(m W + h) as a pair, |f| <= 1/2 + 2^-19, and j
+// congruent modulo 4 to the integer removed.  Exactness, with the binary64
+// argument's numbers scaled: m w0 is a multiple of 2^-21 below 2^26 and
+// m w1 one of 2^-44 below 8 (exact pairs), x0 and t - rint t are exact, e + p1
+// is a multiple of 2^-44 below 2^-20 (exact), and the normalising fast
+// two-sum is exact (where the low part is the larger, every difference it
+// forms is a multiple of 2^-44 below 2^-20); m w2 < 2^-20 is an exact pair
+// and m w3 < 2^-43 is rounded once (2^-67, the size of the table's
+// truncation times m, 2^-66).
+LMH_INLINE fff phf_core(float a, int row_shift, float h, float& j) {
+  int ex = frexp_exp_(a) - 1;
+  int row = ex - row_shift;
+  row = row < 0 ? 0 : (row > 127 ? 127 : row);
+  float m = ldexp_(frexp_mant_(a), 24);
+  const float* W = PH_TABLE_F32 + 4 * row;
+  fff p0 = dd2_mul(m, W[0]);
+  float i0 = rint_(p0.hi), j0 = rint_(p0.lo);
+  float x0 = ((p0.hi - i0) + (p0.lo - j0)) + h;
+  fff p1 = dd2_mul(m, W[1]);
+  fff t = dd2_add2(x0, p1.hi);
+  float k1 = rint_(t.hi);
+  fff s = dd2_add(t.hi - k1, t.lo + p1.lo);
+  fff p2 = dd2_mul(m, W[2]);
+  fff c = dd2_add2(s.hi, p2.hi);
+  float lo = c.lo + (s.lo + (p2.lo + m * W[3]));
+  j = (i0 - 4.0f * rint_(0.25f * i0)) + j0 + k1;
+  return dd2_add(c.hi, lo);
 }
 
 constexpr float CWF_LIMIT = 65536.0f;
@@ -288,15 +289,17 @@ LMH_INLINE Trig32 sincosf_fast(float x, bool is_cos) {
     q = rint_(x * INV_PI_F);
     j = q;
   }
-  fff r = is_cos ? cwf_reduce(x, q, PIH_FD_0, PIH_FD_1) : cwf_reduce(x, q, PI_FD_0, PI_FD_1);
+  fff r = is_cos ? cwf_reduce<true>(x, q, PIH_F_C0, PIH_F_C1, PIH_F_C2, PIH_F_C3)
+                 : cwf_reduce<false>(x, q, PI_F_C0, PI_F_C1, PI_F_C2, PI_F_C3);
   return Trig32{r, j};
 }
 
 LMH_INLINE Trig32 sincosf_slow(float x, bool is_cos) {
-  float k, j;
-  fff r = phf_reduce_signed(x, k);
-  if (is_cos) k += 1.0f;
-  r = quadrant_to_half_periodf(r, k, j);
+  // |x|/pi (+ 1/2 for cos) = j + f, as in the binary64 form
+  float j;
+  fff f = phf_core(fabs_(x), 1, is_cos ? 0.5f : 0.0f, j);
+  fff r = dd2_mul(f, mk(2.0f * PIH2_F_H, 2.0f * PIH2_F_L));
+  if (!is_cos && x < 0.0f) r = dd2_neg(r);
   r.hi = isfinite_(x) ? r.hi : __builtin_nanf("");
   return Trig32{r, j};
 }
@@ -357,19 +360,9 @@ struct SinCos32 {
 LMH_INLINE SinCos32 sincosf2_fast(float x) {
   return SinCos32{sincosf_fast(x, false), sincosf_fast(x, true)};
 }
-LMH_INLINE Trig32 sincosf_raw(float x) {
-  float k;
-  fff r = phf_reduce_signed(x, k);
-  return Trig32{r, k};
-}
+LMH_INLINE Trig32 sincosf_raw(float x) { return sincosf_slow(x, false); }
 LMH_INLINE SinCos32 sincosf_lift(float x, Trig32 raw) {
-  float js, jc;
-  fff rs = quadrant_to_half_periodf(raw.r, raw.j, js);
-  fff rc = quadrant_to_half_periodf(raw.r, raw.j + 1.0f, jc);
-  bool fin = isfinite_(x);
-  rs.hi = fin ? rs.hi : __builtin_nanf("");
-  rc.hi = fin ? rc.hi : __builtin_nanf("");
-  return SinCos32{Trig32{rs, js}, Trig32{rc, jc}};
+  return SinCos32{raw, sincosf_slow(x, true)};
 }
 LMH_INLINE SinCos32 sincosf2_reduce(float x) {
   SinCos32 s;
@@ -387,14 +380,20 @@ LMH_INLINE float cosf_u35(float x) { return cosf_finish_u35(x, sincosf_reduce(x,
 
 LMH_INLINE Trig32 tanf_fast(float x) {
   float k = rint_(x * TWO_OVER_PI_F);
-  return Trig32{cwf_reduce(x, k, PIH_FD_0, PIH_FD_1), k};
+  return Trig32{cwf_reduce<false>(x, k, PIH_F_C0, PIH_F_C1, PIH_F_C2, PIH_F_C3), k};
 }
 
 LMH_INLINE Trig32 tanf_slow(float x) {
-  float k;
-  fff r = phf_reduce_signed(x, k);
+  // x = j pi/2 + r with j modulo 4 (the bf16 finishers read the quadrant)
+  float j;
+  fff f = phf_core(fabs_(x), 0, 0.0f, j);
+  fff r = dd2_mul(f, mk(PIH2_F_H, PIH2_F_L));
+  if (x < 0.0f) {
+    r = dd2_neg(r);
+    j = -j;
+  }
   r.hi = isfinite_(x) ? r.hi : __builtin_nanf("");
-  return Trig32{r, k};
+  return Trig32{r, j};
 }
 
 LMH_INLINE Trig32 tanf_reduce(float x) {

@@ -122,14 +122,14 @@ LMH_INLINE float ntanh(float x) {
 }
 
 // ---- f16 trigonometry ----------------------------------------------------
-// k = rint(x 2/pi), r = x - k pi/2 by the binary32 kernels' Cody-Waite
-// reduction in binary64 (valid for |x| < 65536, which holds every finite
-// f16): r is within 2^-24 relative of the exact reduced argument, whose
+// k = rint(x 2/pi), r = x - k pi/2 by the binary32 kernels' float-float
+// Cody-Waite reduction (valid for |x| < 65536, which holds every finite
+// f16): r is within 2^-34 relative of the exact reduced argument, whose
 // magnitude over all f16 arguments is at least 2^-16 (x = 177.5).  inf and
 // NaN give a NaN r.
 LMH_INLINE Trig32 hsincos_reduce(float x) {
   float k = rint_(x * TWO_OVER_PI_F);
-  return Trig32{cwf_reduce(x, k, PIH_FD_0, PIH_FD_1), k};
+  return Trig32{cwf_reduce<false>(x, k, PIH_F_C0, PIH_F_C1, PIH_F_C2, PIH_F_C3), k};
 }
 
 // sin r and cos r for |r| <= pi/4 (a little more after k's rounding): Taylor

@@ -249,6 +249,92 @@ __global__ __launch_bounds__(BLOCK) void k_unary_split(const typename Io::S* __r
   }
 }
 
+// The same gathering for the binary64 evaluators, done per wave instead of
+// per workgroup: a wave takes WPACKS 16-byte packs per lane, compacts its
+// Cody-Waite elements at the front of its own LDS region and its
+// Payne-Hanek elements at the back, and then evaluates the region densely,
+// 64 elements per step, reduction and finish together; only the one step
+// where the two kinds meet runs both reductions.  Each result overwrites its
+// input's position (that position is read and written by one lane in one
+// step), and the lanes read their results back from the positions they
+// wrote.  A wave only reads LDS that its own lanes wrote, so no workgroup
+// barrier is needed: wave_lds_sync keeps the compiler from moving LDS
+// accesses across it, and one wave's LDS accesses complete in order.
+constexpr int WPACKS = 4;
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <class Io, class Op, int EPT, bool VEC>
+__global__ __launch_bounds__(BLOCK) void k_unary_wsplit(const typename Io::S* __restrict__ x,
+                                                        typename Io::S* __restrict__ y, size_t n) {
+  typedef typename Io::S S;
+  typedef typename Io::C C;
+  typedef decltype(Op::fast(C())) St;
+  constexpr int PW = 64 * EPT * WPACKS;               // elements per wave
+  static_assert(PW <= 65536, "positions are 16-bit");
+  __shared__ C q[SPLIT_WAVES * PW];
+  const unsigned lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  C* qw = q + wave * PW;
+  const size_t wbase = ((size_t)blockIdx.x * SPLIT_WAVES + wave) * PW;
+  unsigned nfast = 0, nslow = 0;                       // wave-uniform
+  unsigned short pos[WPACKS][EPT];
+  bool ok[WPACKS][EPT];
+#pragma unroll
+  for (int u = 0; u < WPACKS; ++u) {
+    C xv[EPT];
+    load_lane<Io, EPT, VEC>(x, n, wbase + (size_t)(u * 64 + lane) * EPT, xv, ok[u]);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      bool slow = ok[u][i] && Op::is_slow(xv[i]);
+      bool fast = ok[u][i] && !slow;
+      unsigned long long mf = __builtin_amdgcn_ballot_w64(fast);
+      unsigned long long ms = __builtin_amdgcn_ballot_w64(slow);
+      unsigned rf = __builtin_amdgcn_mbcnt_hi((unsigned)(mf >> 32),
+                                              __builtin_amdgcn_mbcnt_lo((unsigned)mf, 0u));
+      unsigned rs = __builtin_amdgcn_mbcnt_hi((unsigned)(ms >> 32),
+                                              __builtin_amdgcn_mbcnt_lo((unsigned)ms, 0u));
+      unsigned p = fast ? nfast + rf : PW - 1 - (nslow + rs);
+      pos[u][i] = (unsigned short)p;
+      if (ok[u][i]) qw[p] = xv[i];
+      nfast += (unsigned)__popcll(mf);
+      nslow += (unsigned)__popcll(ms);
+    }
+  }
+  wave_lds_sync();
+  // dense index d: Cody-Waite elements are d < nfast at position d, the
+  // Payne-Hanek ones follow from the back of the region
+  for (unsigned d = lane; d < nfast + nslow; d += 64) {
+    bool fast = d < nfast;
+    unsigned p = fast ? d : PW - 1 - (d - nfast);
+    C v = qw[p];
+    St st;
+    if (fast)
+      st = Op::fast(v);
+    else
+      st = Op::slow(v);
+    qw[p] = Op::finish(v, st);
+  }
+  wave_lds_sync();
+#pragma unroll
+  for (int u = 0; u < WPACKS; ++u) {
+    size_t base = wbase + (size_t)(u * 64 + lane) * EPT;
+    if (VEC && base + EPT <= n) {
+      Pack<S, EPT> out;
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) out.v[i] = Io::out(qw[pos[u][i]]);
+      store_nt(out, y + base);
+    } else {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i)
+        if (ok[u][i]) y[base + i] = Io::out(qw[pos[u][i]]);
+    }
+  }
+}
+
 // sin and cos of each element in one pass: the Payne-Hanek elements are
 // reduced once in the queue (the raw pair and quadrant, the smallest state)
 // and mapped to both half-period states afterwards.

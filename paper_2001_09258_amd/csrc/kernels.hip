@@ -117,8 +117,15 @@ libm_hip_status launch_unary(const void* x, void* y, size_t n, void* stream, con
   S* ys = (S*)y;
   bool vec = aligned16(x) && aligned16(y);
   unsigned blocks;
-  if constexpr (Op::kSplit) {
-    // the gathering kernel sizes its LDS queue to a 256-lane workgroup
+  if constexpr (Op::kSplit && sizeof(typename Io::C) == 8) {
+    // binary64 evaluators: the per-wave gathering kernel, WPACKS packs per lane
+    if (!grid_for(n, EPT, Cfg{BLOCK, WPACKS}, blocks)) return LIBM_HIP_ERR_INVALID;
+    if (vec)
+      hipLaunchKernelGGL((k_unary_wsplit<Io, Op, EPT, true>), dim3(blocks), dim3(BLOCK), 0, s, xs, ys, n);
+    else
+      hipLaunchKernelGGL((k_unary_wsplit<Io, Op, EPT, false>), dim3(blocks), dim3(BLOCK), 0, s, xs, ys, n);
+  } else if constexpr (Op::kSplit) {
+    // the workgroup-gathering kernel sizes its LDS queue to a 256-lane workgroup
     if (!grid_for(n, EPT, Cfg{BLOCK, 1}, blocks)) return LIBM_HIP_ERR_INVALID;
     if (vec)
       hipLaunchKernelGGL((k_unary_split<Io, Op, EPT, true>), dim3(blocks), dim3(BLOCK), 0, s, xs, ys, n);

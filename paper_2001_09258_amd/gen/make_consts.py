@@ -67,6 +67,21 @@ def trailing_zero_head(v, bits):
     return mp.nint(v * scale) / scale
 
 
+def cw_float_pieces(v):
+    """Four binary32 pieces of v for the float-float Cody-Waite reduction:
+    c0 the nearest float, c1 the rest rounded to 8 significant bits (q*c1
+    exact for |q| < 2^16), c2 and c3 the nearest floats to what is left."""
+    c0 = rnd(v, "f32")
+    c1 = trailing_zero_head(v - c0, 8)
+    c2 = rnd(v - c0 - c1, "f32")
+    c3 = rnd(v - c0 - c1 - c2, "f32")
+    out = [c0, c1, c2, c3]
+    for c in out:
+        assert mp.mpf(float(np.float32(float(c)))) == c
+    assert abs(v - sum(out)) < abs(v) * mp.mpf(2) ** -78
+    return out
+
+
 def accurate_path_constants(lines, ln2, head):
     """Constants of the binary64 accurate path (results in the subnormal
     range, where the last bit needs about 2^-100 relative accuracy):
@@ -154,11 +169,12 @@ def main():
         for name, v in (("PIH", mp.pi / 2), ("PI", mp.pi)):
             if fmt == "f64":
                 parts, tag = short_pieces(v, 39, 4), "D"
+                for i, p in enumerate(parts):
+                    lines.append("__device__ constexpr double %s_%s_%d = %s;"
+                                 % (name, tag, i, hx(p, "f64")))
             else:
-                parts, tag = short_pieces(v, 37, 2), "FD"
-            for i, p in enumerate(parts):
-                lines.append("__device__ constexpr double %s_%s_%d = %s;"
-                             % (name, tag, i, hx(p, "f64")))
+                for i, p in enumerate(cw_float_pieces(v)):
+                    lines.append(P + "%s_F_C%d = %s;" % (name, i, hx(p, "f32")))
         ln2 = mp.log(2)
         head = trailing_zero_head(ln2, hbits)
         lines.append(P + "LN2_HI_%s = %s;  // %d significant bits" % (sfx, hx(head, fmt), hbits))
