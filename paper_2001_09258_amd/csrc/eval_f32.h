@@ -2,11 +2,11 @@
 // reduction / polynomial / reconstruction structure in binary32, with
 // float-float pairs only where the 1-ULP bound needs them (the reduced
 // argument, the lowest polynomial terms, the reconstructions).  Binary64
-// arithmetic appears only where a few binary64 instructions replace a longer
-// float-float sequence (one binary64 instruction costs one issue slot on
-// gfx950): the trig Cody-Waite reduction, cbrt, hypot, the inverse
-// hyperbolic functions, erf and erfc; and on the lanes whose exp, exp2,
-// exp10 or pow result falls in the subnormal range (see f32_sub_units).
+// arithmetic appears only on lanes whose result is subnormal, where
+// float-float cannot decide the one rounding (exp, exp2, exp10, pow: see
+// f32_sub_units; hypot: see hypotf_u10_main), and in four C99 additions that
+// evaluate in binary64 working precision and round once: erf, erfc, lgamma
+// and tgamma.
 #pragma once
 #include "dd.h"
 #include "generated/consts.inc"
@@ -917,48 +917,72 @@ LMH_INLINE float expm1f_u10(float x) {
   return fabs_(x) < 0x1p-25f ? x : r;
 }
 
-// asinh, acosh, atanh in binary64 working precision: for binary32 x the
-// squares and x +- 1 are exact doubles, the square root comes from the
-// reciprocal square root estimate and two Newton steps, and log1p(u) is
-// log(1 + u) with the rounding error of 1 + u added back (/ (1 + u)); each
-// stage is good to a few binary64 ulps, far inside binary32's half ulp
-LMH_INLINE double sqrt_ws(double p) {
-  double g = rsq_(p);
-  double h = 0.5 * g;
-  double r = p * g;
-  r = fma_(h, fma_(-r, r, p), r);
-  return fma_(h, fma_(-r, r, p), r);
+// asinh, acosh, atanh in float-float, the binary64 forms' structure:
+// log1p of an argument formed without cancellation, sqrt from the
+// reciprocal square root estimate, one Newton step and the pair's residual,
+// log1p(u) = log((1 + u) 2^-e) + e ln2 from the float-float log pair.
+// Above 2^60 (where x^2 would near binary32's range) asinh and acosh take
+// log1p(|x|) + ln2 (the omitted 1/(4 x^2) is below 2^-120).
+LMH_INLINE fff sqrtf_ff(fff p) {
+  float g = rsq_(p.hi);
+  float h = 0.5f * g;
+  float r = p.hi * g;
+  r = fma_(h, fma_(-r, r, p.hi), r);
+  fff q = dd2_mul(r, r);
+  float res = ((p.hi - q.hi) - q.lo) + p.lo;
+  return dd2_add(r, res * h);
 }
 
-LMH_INLINE double log1p_ws(double u) {            // finite u >= 0
-  double a = 1.0 + u;
-  return log_ws(a) + (u - (a - 1.0)) / a;
+LMH_INLINE fff log1pf_ff(fff u) {                   // u > -1
+  fff a = dd2_add2(1.0f, u.hi);
+  a.lo += u.lo;
+  float m = frexp_mant_(a.hi);
+  int ie = frexp_exp_(a.hi);
+  ie = m < 0.75f ? ie - 1 : ie;
+  float mh = ldexp_(a.hi, -ie), ml = ldexp_(a.lo, -ie);
+  fff num = dd2_add2(mh - 1.0f, ml);                 // mh - 1 is exact
+  fff den = dd2_add(dd2_add(1.0f, mh), ml);
+  return logf_pair(dd2_div(num, den), (float)ie);
 }
+
+constexpr float INVHYP_BIG_F = 0x1p60f;
 
 LMH_INLINE float asinhf_u10(float x) {
-  double a = fabs_((double)x);
-  double x2 = a * a;
-  double r = log1p_ws(a + x2 / (1.0 + sqrt_ws(1.0 + x2)));
-  float v = copysign_((float)r, x);
-  return fabs_(x) < 0x1p-12f || !isfinite_(x) ? x : v;
+  float ax = fabs_(x);
+  bool big = ax > INVHYP_BIG_F;
+  float a = big ? 1.0f : ax;
+  fff x2 = dd2_mul(a, a);
+  fff den = dd2_add(sqrtf_ff(dd2_add2(x2, 1.0f)), 1.0f);
+  fff u = dd2_add(a, dd2_div(x2, den));
+  fff l = log1pf_ff(big ? mk(ax, 0.0f) : u);
+  l = dd2_add(l, big ? mk(LN2_F_H, LN2_F_L) : mk(0.0f, 0.0f));
+  float r = copysign_(l.hi + l.lo, x);
+  r = ax < 0x1p-12f || isinf_(x) ? x : r;            // asinh x rounds to x; +-inf
+  return isnan_(x) ? x : r;
 }
 
 LMH_INLINE float acoshf_u10(float x) {
-  double xd = (double)x;
-  double d = xd - 1.0;
-  float v = (float)log1p_ws(d + sqrt_ws(d * (xd + 1.0)));
-  v = x == 1.0f ? 0.0f : v;
-  v = x < 1.0f ? __builtin_nanf("") : v;
-  return isinf_(x) && x > 0.0f ? x : (isnan_(x) ? x : v);
+  bool big = x > INVHYP_BIG_F;
+  float a = big ? 2.0f : x;
+  fff d = dd2_add2(a, -1.0f);
+  fff u = dd2_add(sqrtf_ff(dd2_mul(d, dd2_add2(a, 1.0f))), d);
+  fff l = log1pf_ff(big ? mk(x, 0.0f) : u);
+  l = dd2_add(l, big ? mk(LN2_F_H, LN2_F_L) : mk(0.0f, 0.0f));
+  float r = l.hi + l.lo;
+  r = x == 1.0f ? 0.0f : r;
+  r = x < 1.0f ? __builtin_nanf("") : r;
+  return isinf_(x) && x > 0.0f ? x : (isnan_(x) ? x : r);
 }
 
 LMH_INLINE float atanhf_u10(float x) {
-  double a = fabs_((double)x);
-  float v = copysign_((float)(0.5 * log1p_ws(2.0 * a / (1.0 - a))), x);
-  v = a == 1.0 ? copysign_(__builtin_inff(), x) : v;
-  v = a > 1.0 ? __builtin_nanf("") : v;
-  v = fabs_(x) < 0x1p-12f ? x : v;
-  return isnan_(x) ? x : v;
+  float ax = fabs_(x);
+  fff u = dd2_div(mk(2.0f * ax, 0.0f), dd2_add2(1.0f, -ax));
+  fff l = log1pf_ff(u);
+  float r = copysign_(0.5f * (l.hi + l.lo), x);
+  r = ax == 1.0f ? copysign_(__builtin_inff(), x) : r;
+  r = ax > 1.0f ? __builtin_nanf("") : r;
+  r = ax < 0x1p-12f ? x : r;                         // atanh x rounds to x
+  return isnan_(x) ? x : r;
 }
 
 // erf, erfc in binary64 working precision with the binary64 polynomials:
@@ -1000,36 +1024,70 @@ LMH_INLINE float erfcf_u10(float x) {
   return isnan_(x) ? x : v;
 }
 
-// cbrt in binary64: a = m 2^i in [0.5, 4) as for binary64, one Newton step
-// on rcbrt_seed (~2^-43 or better), y = a z^2 rounded once to binary32
+// cbrt in float-float: |x| = a 2^(3q) with a = m 2^i in [0.5, 4); y0 = a z^2
+// from the seed z ~ a^(-1/3) (about 2^-21), then one Newton step on
+// y^3 = a with the residual a - y0^3 from exact products (y0^2 = P + p,
+// y0 P = T + t; a - T is exact, T being within a factor two of a) and
+// 1/(3 y0^2) taken as z^2 / 3: about 2^-42 before the one rounding in the
+// last FMA.  A binary32 cube root is never a midpoint (its cube would need
+// 73 bits) nor subnormal (|x| >= 2^-149 gives at least 2^-49.7).
 LMH_INLINE float cbrtf_u10(float x) {
-  double ax = fabs_((double)x);
-  double m = frexp_mant_(ax);
+  float ax = fabs_(x);
+  float m = frexp_mant_(ax);
   int e = frexp_exp_(ax);
-  int q = (e + 1200) / 3 - 400;
-  double a = ldexp_(m, e - 3 * q);
-  double z = rcbrt_seed(a);
-  z = fma_(z * THIRD_D_H, fma_(-a, z * z * z, 1.0), z);
-  float r = (float)ldexp_(a * (z * z), q);
+  int q = (e + 300) / 3 - 100;                       // floor(e / 3)
+  float a = ldexp_(m, e - 3 * q);
+  float z = rcbrt_seed(a);
+  float z2 = z * z;
+  float y0 = a * z2;
+  fff p = dd2_mul(y0, y0);
+  fff t = dd2_mul(y0, p.hi);
+  float d = ((a - t.hi) - t.lo) - y0 * p.lo;
+  float r = ldexp_(fma_(d * (1.0f / 3.0f), z2, y0), q);
   r = copysign_(r, x);
   return (x == 0.0f || !isfinite_(x)) ? x : r;
 }
 
-// hypot in binary64: the squares of binary32 values are exact there and
-// their sum is rounded once; sqrt from the reciprocal square root estimate
-// and two Newton steps (~2^-50), rounded once to binary32
-LMH_INLINE float hypotf_u10(float x, float y) {
-  double a = (double)x, b = (double)y;
-  double S = fma_(a, a, b * b);
-  double g = rsq_(S);
-  double h = 0.5 * g;
-  double r = S * g;
-  r = fma_(h, fma_(-r, r, S), r);
-  r = fma_(h, fma_(-r, r, S), r);
-  float v = (float)r;
-  v = S == 0.0 ? 0.0f : v;
+// hypot: |x|, |y| scaled by 2^-s (s the larger one's exponent), the sum of
+// squares as a float-float pair (exact products, one fast two-sum), its
+// square root from the reciprocal square root estimate, one Newton step
+// and a correction by the pair's residual (about 2^-46), rounded once.
+// Subnormal results (s <= -125) need more: sqrt(N) 2^-149 for an integer
+// N < 2^48 comes within 2^-26.5 units of a rounding midpoint, which 2^-46
+// relative does not resolve, so those lanes take the rare path, where N is
+// exact in binary64 and its correctly rounded square root decides.
+LMH_INLINE float hypotf_u10_main(float x, float y, bool& rare) {
+  float ax = fabs_(x), ay = fabs_(y);
+  float n = ax > ay ? ax : ay, d = ax > ay ? ay : ax;
+  int s = frexp_exp_(n);
+  float ns = ldexp_(n, -s), ds = ldexp_(d, -s);
+  fff S = dd2_add(dd2_mul(ns, ns), dd2_mul(ds, ds));
+  float g = rsq_(S.hi);
+  float h = 0.5f * g;
+  float r = S.hi * g;
+  r = fma_(h, fma_(-r, r, S.hi), r);
+  fff p = dd2_mul(r, r);
+  float res = ((S.hi - p.hi) - p.lo) + S.lo;
+  float v = ldexp_(fma_(res, h, r), s);
+  rare = s <= -125 && n != 0.0f;
+  v = n == 0.0f ? 0.0f : v;
   v = isnan_(x) || isnan_(y) ? __builtin_nanf("") : v;
   return isinf_(x) || isinf_(y) ? __builtin_inff() : v;
+}
+
+LMH_INLINE float hypotf_u10_rare(float x, float y) {     // |x|, |y| < 2^-125
+  double a = (double)x, b = (double)y;
+  return (float)__builtin_sqrt(fma_(a, a, b * b));
+}
+
+LMH_INLINE float hypotf_u10(float x, float y) {
+  bool rare;
+  float r = hypotf_u10_main(x, y, rare);
+  if (rare_lane(rare)) {
+    float rs = hypotf_u10_rare(rare ? x : 0.0f, rare ? y : 0.0f);
+    r = rare ? rs : r;
+  }
+  return r;
 }
 
 // ---------------------------------------------------------------------------

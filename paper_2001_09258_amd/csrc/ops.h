@@ -194,7 +194,7 @@ LMH_OP1R(OpErfU10, erf_u10, erff_u10)
 LMH_OP1R(OpErfcU10, erfc_u10, erfcf_u10)
 LMH_OP1(OpLgammaU10, lgamma_u10, lgammaf_u10)
 LMH_OP1R(OpTgammaU10, tgamma_u10, tgammaf_u10)
-LMH_OP2(OpHypotU10, hypot_u10, hypotf_u10)
+LMH_OP2R(OpHypotU10, hypot_u10, hypotf_u10)
 LMH_OP1(OpSinhU35, sinh_u35, sinhf_u35)
 LMH_OP1(OpCoshU35, cosh_u35, coshf_u35)
 LMH_OP1(OpTanhU35, tanh_u35, tanhf_u35)

@@ -101,6 +101,7 @@ LMH_INLINE float pred_(float x) { return as_f32(as_i32(x) - 1); }
 LMH_INLINE double rcp_(double x) { return 1.0 / x; }
 LMH_INLINE float rcp_(float x) { return 1.0f / x; }
 LMH_INLINE double rsq_(double x) { return 1.0 / __builtin_sqrt(x); }
+LMH_INLINE float rsq_(float x) { return 1.0f / __builtin_sqrtf(x); }
 // a^(-1/3) for a in [0.5, 4) to about 2^-43: a = m 2^i with m in [0.5, 1)
 // and i in {0, 1, 2}; (1.49978 - 0.513 m) is within 1.33 % of m^(-1/3),
 // times 2^(-i/3), then three Newton steps z += z (1 - a z^3)/3 (each squares
@@ -113,18 +114,29 @@ LMH_INLINE double rcbrt_seed(double a) {
   for (int it = 0; it < 3; ++it) z = fma_(z * (1.0 / 3.0), fma_(-a, z * z * z, 1.0), z);
   return z;
 }
+// binary32: the same seed and two Newton steps (about 2^-21)
+LMH_INLINE float rcbrt_seed(float a) {
+  float m = frexp_mant_(a);
+  int i = frexp_exp_(a);
+  float k = i == 0 ? 1.0f : (i == 1 ? 0x1.965feap-1f : 0x1.428a30p-1f);
+  float z = fma_(m, -0.513f, 1.4997778f) * k;
+  for (int it = 0; it < 2; ++it) z = fma_(z * (1.0f / 3.0f), fma_(-a, z * z * z, 1.0f), z);
+  return z;
+}
 #else
 // hardware reciprocal estimate (refined by the callers with Newton steps)
 LMH_INLINE double rcp_(double x) { return __builtin_amdgcn_rcp(x); }
 LMH_INLINE float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
 // hardware reciprocal square root estimate (refined by Newton steps)
 LMH_INLINE double rsq_(double x) { return __builtin_amdgcn_rsq(x); }
+LMH_INLINE float rsq_(float x) { return __builtin_amdgcn_rsqf(x); }
 // a^(-1/3) for a in [0.5, 4) from the hardware base-2 logarithm and
 // exponential estimates (v_log_f32, v_exp_f32; about 22 correct bits), the
 // starting point of the callers' Newton steps
-LMH_INLINE double rcbrt_seed(double a) {
-  return (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf((float)a) * (-1.0f / 3.0f));
+LMH_INLINE float rcbrt_seed(float a) {
+  return __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(a) * (-1.0f / 3.0f));
 }
+LMH_INLINE double rcbrt_seed(double a) { return (double)rcbrt_seed((float)a); }
 #endif
 
 }  // namespace lmh
