@@ -11,6 +11,10 @@ binary64 pair approximating the exact value (see ``functions.evaluate1``).
 
 Parity status of every function is listed in the module docstring of
 ``functions``; the pins live in ``tests/test_oracle_*.py``.
+
+``fast32`` is a first stage in C for binary32 sin, exp and log over every
+binary32 input (double-double within 2^-90, the ball code for what that
+cannot decide), pinned against mpmath, the ball oracle and the host libm.
 """
 from .functions import UNARY, BINARY, evaluate1, OracleError
 from .batch import evaluate

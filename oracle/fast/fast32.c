@@ -1,0 +1,519 @@
+/* Fast first stage of the oracle for binary32 sin, exp and log.
+ *
+ * TEST INFRASTRUCTURE ONLY: used by tests/ to sweep every binary32 input;
+ * the GPU library never links or calls it, and it shares no code, header,
+ * table or constant generator with the library (its constants come from
+ * oracle.consts through oracle/fast/make_tables.py).
+ *
+ * Each function returns the exact value as a double-double v = hi + lo with
+ * |v - f(x)| <= 2^-90 |f(x)| (the claimed bound, checked in
+ * tests/test_oracle_fast.py against the ball oracle), and the correctly
+ * rounded binary32 result when that bound decides it; otherwise it reports
+ * the input as undecided and the caller asks the ball oracle.
+ *
+ *  sin: 2|x|/pi = k + f (|f| <= 1/2) from an integer product of the 24-bit
+ *       mantissa with 256 bits of 2/pi (the Payne-Hanek idea of the paper's
+ *       Section 5 done in exact integer arithmetic), r = f pi/2 in
+ *       double-double, then the Taylor series of sin r or cos r
+ *       (|r| <= pi/4) by quadrant.
+ *  exp: x = k ln2 + r, |r| <= ln2/2, ln 2 as three doubles (k ln2_0 exact),
+ *       e^r by its Taylor series in double-double, times 2^k.
+ *  log: x = m 2^e, m in [1/sqrt 2, sqrt 2); log m = 2 atanh t,
+ *       t = (m - 1)/(m + 1), by its series in double-double, plus e ln 2.
+ *
+ * Error budget (relative): the double-double operations of a series of
+ * n <= 40 terms contribute below n 2^-104; the reductions are exact or below
+ * 2^-97 (sin: the 128 fraction bits kept, 2^-128 absolute, against the
+ * smallest reduced argument of a binary32 input, about 2^-31); the constants
+ * are within 2^-150.  2^-90 leaves a factor of 2^5 to spare.
+ *
+ * Built with -ffp-contract=off so that the error-free transformations stay
+ * exact (the exact product's error term by C99 fma(), which -mfma makes the
+ * host's fused multiply-add instruction).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "tables.h"
+
+typedef struct {
+  double hi, lo;
+} dd;
+
+static inline dd two_sum(double a, double b) {
+  double s = a + b;
+  double v = s - a;
+  dd r = {s, (a - (s - v)) + (b - v)};
+  return r;
+}
+
+static inline dd fast_two_sum(double a, double b) { /* |a| >= |b| or a == 0 */
+  double s = a + b;
+  dd r = {s, b - (s - a)};
+  return r;
+}
+
+static inline dd two_prod(double a, double b) {
+  double p = a * b;
+  dd r = {p, fma(a, b, -p)};
+  return r;
+}
+
+static inline dd dd_add(dd a, dd b) {
+  dd s = two_sum(a.hi, b.hi);
+  dd t = two_sum(a.lo, b.lo);
+  s.lo += t.hi;
+  s = fast_two_sum(s.hi, s.lo);
+  s.lo += t.lo;
+  return fast_two_sum(s.hi, s.lo);
+}
+
+static inline dd dd_neg(dd a) {
+  dd r = {-a.hi, -a.lo};
+  return r;
+}
+
+static inline dd dd_mul(dd a, dd b) {
+  dd p = two_prod(a.hi, b.hi);
+  p.lo += a.hi * b.lo + a.lo * b.hi;
+  return fast_two_sum(p.hi, p.lo);
+}
+
+static inline dd dd_mul_d(dd a, double b) {
+  dd p = two_prod(a.hi, b);
+  p.lo += a.lo * b;
+  return fast_two_sum(p.hi, p.lo);
+}
+
+static inline dd dd_div(dd a, dd b) {
+  double q1 = a.hi / b.hi;
+  dd r = dd_add(a, dd_neg(dd_mul_d(b, q1)));
+  double q2 = r.hi / b.hi;
+  r = dd_add(r, dd_neg(dd_mul_d(b, q2)));
+  double q3 = r.hi / b.hi;
+  dd q = fast_two_sum(q1, q2);
+  return dd_add(q, (dd){q3, 0.0});
+}
+
+static inline dd dd_from(double a) {
+  dd r = {a, 0.0};
+  return r;
+}
+
+/* ---- the series ------------------------------------------------------- */
+
+/* Taylor coefficients as pairs, formed once when the library is loaded:
+   1/n! by repeated pair division, 1/(2k + 1) likewise (each within 2^-104) */
+#define NFACT 32
+#define NODD 24
+static dd INV_FACT[NFACT];
+static dd INV_ODD[NODD];
+
+__attribute__((constructor)) static void init_coefficients(void) {
+  INV_FACT[0] = dd_from(1.0);
+  for (int n = 1; n < NFACT; ++n) INV_FACT[n] = dd_div(INV_FACT[n - 1], dd_from((double)n));
+  for (int k = 0; k < NODD; ++k) INV_ODD[k] = dd_div(dd_from(1.0), dd_from((double)(2 * k + 1)));
+}
+
+/* Horner's rule for a polynomial in z whose coefficients from index LO up
+   contribute less than 2^-57 of the sum: those in binary64, the rest in
+   pairs.  One polynomial evaluation, coefficient k of c at c[k * stride +
+   off]. */
+static dd horner(dd z, const dd* c, int stride, int off, int top, int lo) {
+  double t = c[top * stride + off].hi;
+  for (int k = top - 1; k >= lo; --k) t = t * z.hi + c[k * stride + off].hi;
+  dd s = dd_from(t);
+  for (int k = lo - 1; k >= 0; --k) s = dd_add(dd_mul(s, z), c[k * stride + off]);
+  return s;
+}
+
+/* sin r = r sum_{n<=13} (-r^2)^n / (2n+1)!  and cos r = sum_{n<=14} (-r^2)^n
+   / (2n)! for |r| <= pi/4 (+ 2^-40): the first omitted terms are below
+   2^-112 |sin r| and 2^-117; the terms from n = 9 on are below 2^-63 and
+   summed in binary64 */
+static dd sin_series(dd r) {
+  dd z = dd_neg(dd_mul(r, r));
+  return dd_mul(horner(z, INV_FACT, 2, 1, 13, 9), r);
+}
+
+static dd cos_series(dd r) {
+  dd z = dd_neg(dd_mul(r, r));
+  return horner(z, INV_FACT, 2, 0, 14, 10);
+}
+
+/* e^r = sum_{n<=23} r^n / n! for |r| <= 0.35: the first omitted term is
+   below 2^-115; the terms from n = 14 on are below 2^-57 */
+static dd exp_series(dd r) { return horner(r, INV_FACT, 1, 0, 23, 14); }
+
+/* 2 atanh t = 2 t sum_{k<=21} t^(2k) / (2k+1) for |t| <= 0.172: the first
+   omitted term is below 2^-112 of the sum; the terms from k = 12 on are
+   below 2^-60 */
+static dd atanh2_series(dd t) {
+  dd s = dd_mul(horner(dd_mul(t, t), INV_ODD, 1, 0, 21, 12), t);
+  s.hi *= 2.0;
+  s.lo *= 2.0;
+  return s;
+}
+
+/* ---- reductions --------------------------------------------------------- */
+
+/* 32 bits of 2/pi's fraction starting at bit position p (0-based: bit 0
+   has weight 1/2); bits past the table are zero */
+static uint32_t tbits32(int p) {
+  int w = p / 32, o = p % 32;
+  uint32_t a = w < 16 ? TWO_OVER_PI_W[w] : 0u;
+  uint32_t b = w + 1 < 16 ? TWO_OVER_PI_W[w + 1] : 0u;
+  return o ? (a << o) | (b >> (32 - o)) : a;
+}
+
+/* bits [lowbit, lowbit + 63] of the 320-bit little-endian number Q */
+static uint64_t get64(const uint64_t Q[5], int lowbit) {
+  if (lowbit < 0) return get64(Q, 0) << -lowbit;
+  int w = lowbit / 64, o = lowbit % 64;
+  uint64_t a = w < 5 ? Q[w] : 0u;
+  uint64_t b = w + 1 < 5 ? Q[w + 1] : 0u;
+  return o ? (a >> o) | (b << (64 - o)) : a;
+}
+
+/* |x| = m 2^E (m < 2^24 an integer): 2|x|/pi = q + f with q an integer taken
+   modulo 4 and |f| <= 1/2, f as a pair (absolute error below 2^-127) */
+static dd reduce_2_over_pi(uint32_t m, int E, int* quadrant) {
+  /* bits of 2/pi of weight 2^-i with i <= E - 2 contribute multiples of 4:
+     start the 256-bit window W at weight 2^-s */
+  int s = E - 1 > 1 ? E - 1 : 1;
+  uint32_t w[8];
+  for (int i = 0; i < 8; ++i) w[i] = tbits32(s - 1 + 32 * i);
+  /* P = m W (288 bits) as little-endian 64-bit words; value = P 2^(E - s - 255) */
+  uint64_t Q[5] = {0, 0, 0, 0, 0};
+  uint64_t carry = 0;
+  for (int i = 7; i >= 0; --i) { /* 32-bit limb 7 - i from the bottom */
+    uint64_t t = (uint64_t)w[i] * m + carry;
+    int limb = 7 - i;
+    Q[limb / 2] |= (uint64_t)(uint32_t)t << (32 * (limb % 2));
+    carry = t >> 32;
+  }
+  Q[4] = carry;
+  int F = 255 - E + s; /* bits >= F form the integer part */
+  int q = (int)(get64(Q, F) & 3u);
+  unsigned __int128 fr = ((unsigned __int128)get64(Q, F - 64) << 64) | get64(Q, F - 128);
+  __int128 sf;
+  if (fr >> 127) { /* f >= 1/2: take f - 1 and the next integer */
+    sf = (__int128)(fr - ((unsigned __int128)1 << 127)) - ((__int128)1 << 127);
+    q += 1;
+  } else {
+    sf = (__int128)fr;
+  }
+  *quadrant = q & 3;
+  double hi = (double)sf;
+  double lo = (double)(sf - (__int128)hi);
+  return fast_two_sum(ldexp(hi, -128), ldexp(lo, -128));
+}
+
+/* ---- the functions: pair values ---------------------------------------- */
+
+/* returns 0 and a pair for finite results that need rounding; 1 with *rn
+   set for exact or special results */
+static int sin_value(float x, dd* v, float* rn) {
+  if (isnan(x) || isinf(x)) {
+    *rn = NAN;
+    return 1;
+  }
+  if (x == 0.0f) {
+    *rn = x;
+    return 1;
+  }
+  double ax = fabs((double)x);
+  dd r;
+  int k;
+  if (ax < 0.78539816339744830) { /* below pi/4 */
+    r = dd_from(ax);
+    k = 0;
+  } else {
+    int e;
+    double mant = frexp(ax, &e); /* ax = mant 2^e, mant in [0.5, 1) */
+    uint32_t m = (uint32_t)ldexp(mant, 24);
+    dd f = reduce_2_over_pi(m, e - 24, &k);
+    r = dd_mul(f, (dd){PIO2_D[0], PIO2_D[1]});
+  }
+  dd s = (k & 1) ? cos_series(r) : sin_series(r);
+  if (k & 2) s = dd_neg(s);
+  if (x < 0.0f) s = dd_neg(s);
+  *v = s;
+  return 0;
+}
+
+static int exp_value(float x, dd* v, float* rn) {
+  if (isnan(x)) {
+    *rn = x;
+    return 1;
+  }
+  if (x == 0.0f) {
+    *rn = 1.0f;
+    return 1;
+  }
+  if (x > 89.0f) { /* e^89 > 2^128 */
+    *rn = INFINITY;
+    return 1;
+  }
+  if (x < -104.0f) { /* e^-104 < 2^-150: rounds to +0 */
+    *rn = 0.0f;
+    return 1;
+  }
+  double xd = (double)x;
+  double k = nearbyint(xd / LN2_D[0]);
+  /* r = x - k (l0 + l1 + l2): k l0 is not exact in general; use the pair
+     products and exact sums */
+  dd p0 = two_prod(k, LN2_D[0]);
+  dd p1 = two_prod(k, LN2_D[1]);
+  dd r = dd_add(dd_from(xd), dd_neg(p0));
+  r = dd_add(r, dd_neg(p1));
+  r = dd_add(r, dd_from(-k * LN2_D[2]));
+  dd e = exp_series(r);
+  e.hi = ldexp(e.hi, (int)k);
+  e.lo = ldexp(e.lo, (int)k);
+  *v = e;
+  return 0;
+}
+
+static int log_value(float x, dd* v, float* rn) {
+  if (isnan(x)) {
+    *rn = x;
+    return 1;
+  }
+  if (x < 0.0f) {
+    *rn = NAN;
+    return 1;
+  }
+  if (x == 0.0f) {
+    *rn = -INFINITY;
+    return 1;
+  }
+  if (isinf(x)) {
+    *rn = x;
+    return 1;
+  }
+  if (x == 1.0f) {
+    *rn = 0.0f;
+    return 1;
+  }
+  int e;
+  double m = frexp((double)x, &e); /* [0.5, 1) */
+  if (m < 0.70710678118654752) {
+    m *= 2.0;
+    e -= 1;
+  }
+  /* t = (m - 1)/(m + 1): m - 1 and m + 1 are exact (m has 24 bits) */
+  dd t = dd_div(dd_from(m - 1.0), dd_from(m + 1.0));
+  dd l = atanh2_series(t);
+  dd el = dd_add(two_prod((double)e, LN2_D[0]), two_prod((double)e, LN2_D[1]));
+  el = dd_add(el, dd_from((double)e * LN2_D[2]));
+  *v = dd_add(el, l);
+  return 0;
+}
+
+/* ---- rounding to binary32 ----------------------------------------------- */
+
+/* distance |v - c| for a float candidate c (c = 2^128 stands for +inf) */
+static double dist(dd v, double c) {
+  dd d = two_sum(v.hi, -c);
+  return fabs(d.hi + (d.lo + v.lo));
+}
+
+/* correctly rounded binary32 value of v, given |v - exact| <= rel |exact|;
+   returns 1 if the bound does not decide it */
+static int round_f32(dd v, double rel, float* out) {
+  double a = fabs(v.hi);
+  double tol = rel * a * 1.01 + 0x1p-300;
+  float f = (float)v.hi;
+  double cands[3];
+  float fl[3];
+  if (isinf(f)) {
+    fl[0] = copysignf(INFINITY, f);
+    cands[0] = copysign(0x1p128, v.hi);
+    fl[1] = copysignf(0x1.fffffep127f, f);
+    cands[1] = (double)fl[1];
+    fl[2] = fl[1];
+    cands[2] = cands[1];
+  } else {
+    fl[0] = f;
+    fl[1] = nextafterf(f, -INFINITY);
+    fl[2] = nextafterf(f, INFINITY);
+    for (int i = 0; i < 3; ++i) cands[i] = isinf(fl[i]) ? copysign(0x1p128, (double)fl[i]) : (double)fl[i];
+  }
+  double d[3];
+  for (int i = 0; i < 3; ++i) d[i] = dist(v, cands[i]);
+  int best = 0;
+  for (int i = 1; i < 3; ++i)
+    if (d[i] < d[best]) best = i;
+  double second = INFINITY;
+  for (int i = 0; i < 3; ++i)
+    if (i != best && fl[i] != fl[best] && d[i] < second) second = d[i];
+  *out = fl[best];
+  /* undecided when the two nearest candidates are within the error of
+     being equally near */
+  return second - d[best] <= 2.0 * tol;
+}
+
+/* ---- exported entry points ---------------------------------------------- */
+
+enum { FN_SIN = 0, FN_EXP = 1, FN_LOG = 2 };
+
+static int value(int fn, float x, dd* v, float* rn) {
+  switch (fn) {
+    case FN_SIN: return sin_value(x, v, rn);
+    case FN_EXP: return exp_value(x, v, rn);
+    default: return log_value(x, v, rn);
+  }
+}
+
+static const double REL = 0x1p-90;
+
+/* n inputs: hi/lo the pair (NaN for special results), rn the rounded value,
+   undecided[i] = 1 where the caller must ask the ball oracle */
+void oracle_fast32_eval(int fn, const float* x, long n, double* hi, double* lo, float* rn,
+                        uint8_t* undecided) {
+  for (long i = 0; i < n; ++i) {
+    dd v;
+    float r;
+    if (value(fn, x[i], &v, &r)) {
+      hi[i] = (double)r;
+      lo[i] = 0.0;
+      rn[i] = r;
+      undecided[i] = 0;
+      continue;
+    }
+    undecided[i] = (uint8_t)round_f32(v, REL, &r);
+    hi[i] = v.hi;
+    lo[i] = v.lo;
+    rn[i] = r;
+  }
+}
+
+static inline float from_bits(uint32_t b) {
+  float f;
+  memcpy(&f, &b, 4);
+  return f;
+}
+
+static inline uint32_t bits_of(float f) {
+  uint32_t b;
+  memcpy(&b, &f, 4);
+  return b;
+}
+
+/* glibc's binary64 function, rounded to binary32 */
+static float libm_double_rounded(int fn, float x) {
+  double d = (double)x;
+  switch (fn) {
+    case FN_SIN: return (float)sin(d);
+    case FN_EXP: return (float)exp(d);
+    default: return (float)log(d);
+  }
+}
+
+typedef struct {
+  long n, undecided, differ, differ_explained;
+} sweep_stats;
+
+/* every bit pattern in [start, start + count): the oracle against glibc's
+   binary64 result rounded to binary32.  Where the two differ, the binary64
+   result should lie within two of its own ulps of a binary32 midpoint (a
+   double rounding); those are counted as explained.  Inputs that differ or
+   are undecided are stored (up to cap each) for the ball oracle. */
+void oracle_fast32_sweep_libm(int fn, uint64_t start, uint64_t count, sweep_stats* st,
+                              uint32_t* differ, long differ_cap, uint32_t* undec, long undec_cap) {
+  memset(st, 0, sizeof(*st));
+  for (uint64_t i = 0; i < count; ++i) {
+    uint32_t b = (uint32_t)(start + i);
+    float x = from_bits(b);
+    dd v;
+    float r;
+    st->n++;
+    if (!value(fn, x, &v, &r)) {
+      if (round_f32(v, REL, &r)) {
+        if (st->undecided < undec_cap) undec[st->undecided] = b;
+        st->undecided++;
+        continue;
+      }
+    }
+    float g = libm_double_rounded(fn, x);
+    int same = (bits_of(g) == bits_of(r)) || (isnan(g) && isnan(r));
+    if (!same) {
+      if (st->differ < differ_cap) differ[st->differ] = b;
+      st->differ++;
+      double d = (fn == FN_SIN) ? sin((double)x) : (fn == FN_EXP ? exp((double)x) : log((double)x));
+      /* the binary32 midpoint between r and g */
+      double mid = 0.5 * ((double)r + (double)g);
+      double ulp_d = fabs(nextafter(d, INFINITY) - d);
+      if (!isinf(g) && !isinf(r) && fabs(d - mid) <= 2.0 * ulp_d) st->differ_explained++;
+    }
+  }
+}
+
+typedef struct {
+  long n, undecided, special_mismatch, violations;
+  double max_ulp, sum_ulp;
+  long n_reg;
+  uint32_t worst;
+} check_stats;
+
+/* GPU results y for the bit patterns [start, start + count) against the
+   oracle, with the ULP metric of tests/ulp.py: ulp(v) = 2^(max(floor(log2
+   |v|), -126) - 23) at the exact value v; NaN, +-inf, +-0 and subnormal
+   correctly rounded results must match bit for bit (NaN as a class). */
+void oracle_fast32_check(int fn, uint64_t start, uint64_t count, const float* y, double bound,
+                         check_stats* st, uint32_t* bad, long bad_cap, uint32_t* undec,
+                         long undec_cap) {
+  memset(st, 0, sizeof(*st));
+  for (uint64_t i = 0; i < count; ++i) {
+    uint32_t b = (uint32_t)(start + i);
+    float x = from_bits(b);
+    float yi = y[i];
+    dd v;
+    float r;
+    st->n++;
+    int special = value(fn, x, &v, &r);
+    if (!special && round_f32(v, REL, &r)) {
+      if (st->undecided < undec_cap) undec[st->undecided] = b;
+      st->undecided++;
+      continue;
+    }
+    int same = (bits_of(yi) == bits_of(r)) || (isnan(yi) && isnan(r));
+    if (special || isnan(r) || isinf(r) || r == 0.0f || fabsf(r) < 0x1p-126f) {
+      if (!same) {
+        if (st->special_mismatch + st->violations < bad_cap)
+          bad[st->special_mismatch + st->violations] = b;
+        st->special_mismatch++;
+      }
+      continue;
+    }
+    double av = fabs(v.hi);
+    int e;
+    frexp(av, &e);
+    e -= 1; /* floor(log2 |hi|) */
+    if (av == ldexp(1.0, e) && v.lo != 0.0 && (v.lo < 0) != (v.hi < 0)) e -= 1;
+    if (e < -126) e = -126;
+    double ulp = ldexp(1.0, e - 23);
+    double err;
+    if (isnan(yi)) {
+      err = INFINITY;
+    } else if (isinf(yi)) {
+      err = fabs((copysign(0x1p127, (double)yi) - 0.5 * v.hi) - 0.5 * v.lo) / (0.5 * ulp);
+    } else {
+      err = fabs(((double)yi - v.hi) - v.lo) / ulp;
+    }
+    if (same && err > 0.5) err = 0.5;
+    st->n_reg++;
+    st->sum_ulp += err;
+    if (err > st->max_ulp) {
+      st->max_ulp = err;
+      st->worst = b;
+    }
+    if (err > bound) {
+      if (st->special_mismatch + st->violations < bad_cap)
+        bad[st->special_mismatch + st->violations] = b;
+      st->violations++;
+    }
+  }
+}

@@ -1,0 +1,118 @@
+"""ctypes binding of the oracle's fast binary32 stage (``oracle/fast/fast32.c``)
+for sin, exp and log over many binary32 inputs.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  The C stage gives a
+double-double within 2^-90 relative of the exact value and the correctly
+rounded binary32 result where that bound decides it; ``evaluate`` sends the
+inputs it cannot decide to the ball oracle, so its results are the oracle's.
+Pinned against the ball oracle in ``tests/test_oracle_fast.py``.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "fast", "fast32.c")
+LIB = os.path.join(HERE, "liboracle_fast32.so")
+FNS = {"sin": 0, "exp": 1, "log": 2}
+
+_lib = None
+
+
+def build():
+    """Compile the C stage (gcc, IEEE binary64, no contraction; fma() as the
+    x86-64 fused multiply-add, which the hosts here have)."""
+    tmp = "%s.tmp%d" % (LIB, os.getpid())
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-mfma", "-ffp-contract=off",
+           "-fno-fast-math", "-o", tmp, SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+class SweepStats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_long), ("undecided", ctypes.c_long), ("differ", ctypes.c_long),
+                ("differ_explained", ctypes.c_long)]
+
+
+class CheckStats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_long), ("undecided", ctypes.c_long),
+                ("special_mismatch", ctypes.c_long), ("violations", ctypes.c_long),
+                ("max_ulp", ctypes.c_double), ("sum_ulp", ctypes.c_double),
+                ("n_reg", ctypes.c_long), ("worst", ctypes.c_uint32)]
+
+
+def load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        lib = ctypes.CDLL(LIB)
+        P = ctypes.c_void_p
+        lib.oracle_fast32_eval.restype = None
+        lib.oracle_fast32_eval.argtypes = [ctypes.c_int, P, ctypes.c_long, P, P, P, P]
+        lib.oracle_fast32_sweep_libm.restype = None
+        lib.oracle_fast32_sweep_libm.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                                 ctypes.POINTER(SweepStats), P, ctypes.c_long, P,
+                                                 ctypes.c_long]
+        lib.oracle_fast32_check.restype = None
+        lib.oracle_fast32_check.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, P,
+                                            ctypes.c_double, ctypes.POINTER(CheckStats), P,
+                                            ctypes.c_long, P, ctypes.c_long]
+        _lib = lib
+    return _lib
+
+
+def fast_eval(fn, x):
+    """The C stage alone: (rn, hi, lo, undecided) for binary32 inputs x."""
+    lib = load()
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    n = x.size
+    hi = np.empty(n, np.float64)
+    lo = np.empty(n, np.float64)
+    rn = np.empty(n, np.float32)
+    und = np.empty(n, np.uint8)
+    lib.oracle_fast32_eval(FNS[fn], x.ctypes.data, n, hi.ctypes.data, lo.ctypes.data,
+                           rn.ctypes.data, und.ctypes.data)
+    return rn, hi, lo, und.astype(bool)
+
+
+def evaluate(fn, x):
+    """(rn, hi, lo) as oracle.evaluate(fn, "f32", x): the C stage, and the ball
+    oracle for the inputs the C stage cannot decide."""
+    from . import evaluate as ball_evaluate
+    rn, hi, lo, und = fast_eval(fn, x)
+    rn = rn.astype(np.float64)
+    if und.any():
+        xs = np.asarray(x, dtype=np.float32)[und].astype(np.float64)
+        r2, h2, l2 = ball_evaluate(fn, "f32", xs)
+        rn[und], hi[und], lo[und] = r2, h2, l2
+    return rn, hi, lo
+
+
+def sweep_libm(fn, start, count, cap=1 << 16):
+    """Bit patterns [start, start + count) against the host libm's binary64
+    result rounded to binary32: (stats, differing inputs, undecided inputs)."""
+    lib = load()
+    st = SweepStats()
+    differ = np.empty(cap, np.uint32)
+    und = np.empty(cap, np.uint32)
+    lib.oracle_fast32_sweep_libm(FNS[fn], start, count, ctypes.byref(st), differ.ctypes.data, cap,
+                                 und.ctypes.data, cap)
+    return st, differ[:min(st.differ, cap)], und[:min(st.undecided, cap)]
+
+
+def check(fn, start, count, y, bound, cap=1 << 12):
+    """Results y of the bit patterns [start, start + count) against the oracle
+    (tests/ulp.py's metric): (stats, failing inputs, undecided inputs)."""
+    lib = load()
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    assert y.size == count
+    st = CheckStats()
+    bad = np.empty(cap, np.uint32)
+    und = np.empty(cap, np.uint32)
+    lib.oracle_fast32_check(FNS[fn], start, count, y.ctypes.data, bound, ctypes.byref(st),
+                            bad.ctypes.data, cap, und.ctypes.data, cap)
+    return st, bad[:min(st.special_mismatch + st.violations, cap)], und[:min(st.undecided, cap)]

@@ -1,0 +1,111 @@
+"""Pins of the oracle's fast binary32 stage (oracle/fast/fast32.c) for sin,
+exp and log, independently of its own arithmetic:
+
+* against mpmath at 300 bits: the double-double value within the claimed
+  2^-90 relative (random bit patterns, each function's domain, arguments
+  next to multiples of pi/2, exp near its overflow and underflow limits, log
+  next to 1);
+* against the ball oracle: the same correctly rounded binary32 result
+  (undecided inputs go to the ball oracle by construction);
+* the sweep against the host libm's binary64 results rounded to binary32
+  over 2^18-pattern stretches: every difference is a double rounding, and
+  the ball oracle sides with the fast stage on each;
+* the ULP check against known answers (the oracle's own results, results
+  one ulp away, a NaN where a number is due).
+"""
+import math
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+import oracle
+from oracle import fast32
+
+MPF = {"sin": mp.sin, "exp": mp.exp, "log": mp.log}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    fast32.load()                       # builds the C stage if it is missing
+
+
+def _inputs(fn, n=1200, seed=3):
+    rng = np.random.default_rng(seed + len(fn))
+    bits = rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)
+    parts = [bits.view(np.float32)]
+    if fn == "sin":
+        k = np.concatenate([np.arange(1, 400), rng.integers(1, 1 << 40, 300)]).astype(np.float64)
+        near = (k * (math.pi / 2)).astype(np.float32)
+        parts += [near, np.nextafter(near, np.float32(0)), rng.uniform(-10, 10, 300).astype(np.float32),
+                  np.float32([7.729179e28, 21999384576.0, 1.5458358e29, 1e-40, 3.4028235e38])]
+    elif fn == "exp":
+        parts += [rng.uniform(-104, 89, 600).astype(np.float32),
+                  np.float32([88.72283, 88.72284, -103.97208, -103.9721, -87.33655, 1e-30, -1e-30])]
+    else:
+        parts += [np.exp(rng.uniform(-100, 88, 600)).astype(np.float32),
+                  (1 + rng.uniform(-1e-3, 1e-3, 200)).astype(np.float32),
+                  np.float32([1.0, 0.99999994, 1.0000001, 1e-45, 3.4028235e38])]
+    return np.concatenate(parts).astype(np.float32)
+
+
+@pytest.mark.parametrize("fn", ["sin", "exp", "log"])
+def test_pair_within_claimed_bound_of_mpmath(fn):
+    x = _inputs(fn, n=300)
+    rn, hi, lo, und = fast32.fast_eval(fn, x)
+    mp.mp.prec = 300
+    worst = mp.mpf(0)
+    for xi, h, l in zip(x, hi, lo):
+        if not (np.isfinite(h) and np.isfinite(xi)) or h == 0:
+            continue
+        if fn == "log" and xi <= 0:
+            continue
+        exact = MPF[fn](mp.mpf(float(xi)))
+        if fn == "exp" and (exact > mp.mpf(2) ** 128 or exact < mp.mpf(2) ** -150):
+            continue
+        rel = abs((mp.mpf(float(h)) + mp.mpf(float(l))) - exact) / abs(exact)
+        worst = max(worst, rel)
+    assert worst <= mp.mpf(2) ** -90, (fn, float(mp.log(worst, 2)))
+
+
+@pytest.mark.parametrize("fn", ["sin", "exp", "log"])
+def test_rounded_results_match_the_ball_oracle(fn):
+    x = _inputs(fn)
+    rn, hi, lo = fast32.evaluate(fn, x)
+    rb = oracle.evaluate(fn, "f32", x.astype(np.float64))[0]
+    same = (rn == rb) | (np.isnan(rn) & np.isnan(rb))
+    same &= (np.signbit(rn) == np.signbit(rb)) | np.isnan(rb)
+    assert same.all(), x[~same][:5]
+
+
+@pytest.mark.parametrize("fn,start", [("sin", 0x3f800000), ("sin", 0x4e000000),
+                                      ("exp", 0x42000000), ("exp", 0xc2c00000),
+                                      ("log", 0x3f7f0000), ("log", 0x00000001)])
+def test_sweep_against_libm_double_rounded(fn, start):
+    st, differ, und = fast32.sweep_libm(fn, start, 1 << 18)
+    assert st.n == 1 << 18
+    assert st.differ == st.differ_explained, (st.differ, st.differ_explained)
+    # the ball oracle sides with the fast stage wherever they differ from libm
+    if differ.size:
+        x = differ[:64].view(np.float32)
+        rb = oracle.evaluate(fn, "f32", x.astype(np.float64))[0]
+        rf = fast32.fast_eval(fn, x)[0]
+        assert np.array_equal(rb, rf.astype(np.float64))
+    assert st.undecided == und.size
+
+
+def test_check_metric_on_known_answers():
+    start, n = 0x3f000000, 1 << 14
+    x = np.arange(start, start + n, dtype=np.uint64).astype(np.uint32).view(np.float32)
+    rn = fast32.evaluate("exp", x)[0].astype(np.float32)
+    st, bad, _ = fast32.check("exp", start, n, rn, 1.0)
+    assert st.violations == 0 and st.special_mismatch == 0 and st.max_ulp <= 0.5
+    up = np.nextafter(rn, np.float32(np.inf))
+    st, bad, _ = fast32.check("exp", start, n, up, 1.0)
+    assert 0.5 < st.max_ulp < 1.5
+    st, bad, _ = fast32.check("exp", start, n, up, 0.75)
+    assert st.violations > 0
+    y = rn.copy()
+    y[5] = np.nan
+    st, bad, _ = fast32.check("exp", start, n, y, 1.0)
+    assert st.violations == 1 and bad[0] == start + 5
