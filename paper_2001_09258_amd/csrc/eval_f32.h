@@ -985,43 +985,127 @@ LMH_INLINE float atanhf_u10(float x) {
   return isnan_(x) ? x : r;
 }
 
-// erf, erfc in binary64 working precision with the binary64 polynomials:
-// x (2/sqrt(pi) + z P(z)) below 1, e^(-x^2) g from the table above (e^(-x^2)
-// from the working-precision exp of the rounded square: relative error
-// below x^2 2^-52, 2^-45 for the |x| < 10.1 that binary32 reaches)
-LMH_INLINE double erf_ws_small(double x) {          // |x| < 0.75
-  double z = x * x;
-  return x * fma_(z, fma_(z, poly_estrin(z, ERF_P_F64), ERF_C1_D_H), TWO_OVER_SQRTPI_D_H);
+// erf, erfc in float-float, the binary64 forms' structure: |x| < 0.75:
+// erf x = c0 x + c1 x^3 + x^5 P(x^2) with c0 = 2/sqrt(pi) and c1 = -c0/3 as
+// pairs; 0.75 <= |x| < 10.1: erfc |x| = e^(-x^2) g(|x|) with g from the
+// binary32 rows of the generated table (fitted to 2^-30; constant and linear
+// coefficients as pairs), e^(-x^2) from the
+// exact square through the float-float exp, erf = 1 - erfc below 4 and
+// erfc(-|x|) = 2 - erfc|x|.  Results in or near the subnormal range take
+// binary64 rare paths (erfc above 9.1; erf below 2^-100, where c0 x must be
+// rounded from an exact product).
+constexpr float ERFF_SMALL = 0.75f;
+
+LMH_INLINE fff erff_small(float x) {                  // |x| < 0.75
+  fff x3 = dd2_mul(dd2_mul(x, x), x);
+  float z = x * x;
+  fff v = dd2_add(dd2_mul(mk(TWO_OVER_SQRTPI_F_H, TWO_OVER_SQRTPI_F_L), x),
+                  dd2_mul(x3, mk(ERF_C1_F_H, ERF_C1_F_L)));
+  return mk(v.hi, v.lo + (x3.hi * z) * poly_estrin(z, ERF_P_F32));
 }
-LMH_INLINE double erfc_ws_big(double a) {            // 0.75 <= a <= 10.1
+
+LMH_INLINE fff erfcf_poly(float a, bool& inv) {
+  int row = (a >= 1.0f) + (a >= 1.5f) + (a >= 2.25f) + (a >= 3.5f) + (a >= 6.0f);
+  inv = row >= 3;
+  float s = (inv ? rcp_refined(a) : a) - ERFCF_C[row];
+  const float* P = ERFCF_TAB + row;                  // column-major: entry k at P[k * ROWS]
+  float q[ERFCF_TERMS - 2];
+#pragma unroll
+  for (int i = 0; i < ERFCF_TERMS - 2; ++i) q[i] = P[(4 + i) * ERFCF_ROWS];
+  // g = c0 + s (c1 + s Q(s)), c0 and c1 as pairs: the linear term reaches
+  // about a third of g, so its product stays a pair
+  fff u = dd2_add(mk(P[2 * ERFCF_ROWS], P[3 * ERFCF_ROWS]), s * poly_estrin(s, q));
+  return dd2_add(mk(P[0], P[ERFCF_ROWS]), dd2_mul(u, s));
+}
+
+// erfc(a) = pair * 2^k for 0.75 <= a < 10.1
+LMH_INLINE fff erfcf_big(float a, float& k) {
   bool inv;
-  ddd g = erfc_poly(a, inv);
-  double v = exp_ws(-(a * a), 0) * (g.hi + g.lo);
-  return inv ? v / a : v;
+  fff g = erfcf_poly(a, inv);
+  fff x2 = dd2_mul(a, a);
+  fff e = expf_ff(mk(-x2.hi, -x2.lo), k);
+  fff r = dd2_mul(e, g);
+  return inv ? dd2_div(r, mk(a, 0.0f)) : r;
+}
+
+LMH_INLINE float erff_u10_main(float x, bool& rare) {
+  float a = fabs_(x);
+  fff sm = erff_small(a < ERFF_SMALL ? x : 0.0f);
+  float r = sm.hi + sm.lo;
+  bool mid = a >= ERFF_SMALL && a < 4.0f;             // above 4 erf rounds to +-1
+  if (any_lane(mid)) {
+    float k;
+    fff e = erfcf_big(mid ? a : 1.0f, k);
+    fff d = dd2_add(1.0f, mk(-ldexp_(e.hi, (int)k), -ldexp_(e.lo, (int)k)));
+    float v = copysign_(d.hi + d.lo, x);
+    r = mid ? v : r;
+  }
+  r = a >= 4.0f ? copysign_(1.0f, x) : r;
+  rare = a < 0x1p-100f && a != 0.0f;
+  return isnan_(x) || x == 0.0f ? x : r;              // keeps erf(-0) = -0
+}
+
+// erf x = c0 x below 2^-100 (the next term is 2^-200 smaller), where the
+// float pair's low word would fall below the normal range: subnormal
+// results (|x| < 2^-125) from the exact binary64 product pair of c0 and
+// x 2^149 rounded once to units of 2^-149, the others from the binary64
+// product rounded to binary32
+LMH_INLINE float erff_u10_rare(float x) {
+  double d;
+  ddd v = dd2_mul(mk(TWO_OVER_SQRTPI_D_H, TWO_OVER_SQRTPI_D_L), ldexp_((double)x, 149));
+  float sub = f32_from_units(f32_sub_units(v, -149, d));
+  float nrm = (float)(TWO_OVER_SQRTPI_D_H * (double)x);
+  return fabs_(x) < 0x1p-125f ? sub : nrm;
 }
 
 LMH_INLINE float erff_u10(float x) {
-  double a = fabs_((double)x);
-  double r = erf_ws_small((double)x);
-  bool mid = a >= ERF_SMALL && a < 4.0;              // above 4 erf rounds to +-1
-  if (any_lane(mid)) r = mid ? copysign_(1.0 - erfc_ws_big(mid ? a : 1.0), (double)x) : r;
-  float v = (float)r;
-  v = a >= 4.0 ? copysign_(1.0f, x) : v;
-  return isnan_(x) ? x : v;
+  bool rare;
+  float r = erff_u10_main(x, rare);
+  if (rare_lane(rare)) {
+    float rs = erff_u10_rare(rare ? x : 0.0f);
+    r = rare ? rs : r;
+  }
+  return r;
+}
+
+LMH_INLINE float erfcf_u10_main(float x, bool& rare) {
+  float a = fabs_(x);
+  fff sm = erff_small(a < ERFF_SMALL ? x : 0.0f);
+  fff one_m = dd2_add(1.0f, mk(-sm.hi, -sm.lo));
+  float r = one_m.hi + one_m.lo;
+  bool tab = a >= ERFF_SMALL && a < 10.1f;            // erfc(10.1) < 2^-150
+  if (any_lane(tab)) {
+    float k;
+    fff e = erfcf_big(tab ? a : 1.0f, k);
+    float pos = ldexp_(e.hi + e.lo, (int)k);
+    fff two_m = dd2_add(2.0f, mk(-ldexp_(e.hi, (int)k), -ldexp_(e.lo, (int)k)));
+    float v = x > 0.0f ? pos : two_m.hi + two_m.lo;
+    r = tab ? v : r;
+  }
+  r = x >= 10.1f ? 0.0f : r;
+  r = x <= -10.1f ? 2.0f : r;
+  rare = x > 9.1f && x < 10.1f;                       // results near or below 2^-126
+  return isnan_(x) ? x : r;
+}
+
+// binary32 erfc above 9.1 (results near or in the subnormal range): the
+// binary64 polynomials and exp in working precision, rounded once
+LMH_INLINE float erfcf_u10_rare(float x) {
+  double a = (double)x;
+  bool inv;
+  ddd g = erfc_poly(a, inv);
+  double v = exp_ws(-(a * a), 0) * (g.hi + g.lo);
+  return (float)(inv ? v / a : v);
 }
 
 LMH_INLINE float erfcf_u10(float x) {
-  double xd = (double)x, a = fabs_(xd);
-  double r = 1.0 - erf_ws_small(a < ERF_SMALL ? xd : 0.0);
-  bool tab = a >= ERF_SMALL && a < 10.1;             // erfc(10.1) < 2^-150
-  if (any_lane(tab)) {
-    double e = erfc_ws_big(tab ? a : 1.0);
-    r = tab ? (xd > 0.0 ? e : 2.0 - e) : r;
+  bool rare;
+  float r = erfcf_u10_main(x, rare);
+  if (rare_lane(rare)) {
+    float rs = erfcf_u10_rare(rare ? x : 9.5f);
+    r = rare ? rs : r;
   }
-  float v = (float)r;
-  v = x >= 10.1f ? 0.0f : v;
-  v = x <= -10.1f ? 2.0f : v;
-  return isnan_(x) ? x : v;
+  return r;
 }
 
 // cbrt in float-float: |x| = a 2^(3q) with a = m 2^i in [0.5, 4); y0 = a z^2
@@ -1093,12 +1177,6 @@ LMH_INLINE float hypotf_u10(float x, float y) {
 // ---------------------------------------------------------------------------
 // exact remainders in binary32 (same long division as binary64)
 // ---------------------------------------------------------------------------
-// binary32 erf and erfc have no rare path (their binary64 working precision
-// rounds subnormal results correctly): the split form reports no rare lane
-LMH_INLINE float erff_u10_main(float x, bool& rare) { rare = false; return erff_u10(x); }
-LMH_INLINE float erff_u10_rare(float x) { return erff_u10(x); }
-LMH_INLINE float erfcf_u10_main(float x, bool& rare) { rare = false; return erfcf_u10(x); }
-LMH_INLINE float erfcf_u10_rare(float x) { return erfcf_u10(x); }
 
 // lgamma and tgamma in binary32: the binary64 evaluators' pairs rounded once
 // into binary32 (lgamma never has a binary32 subnormal result; tgamma's
