@@ -1,4 +1,5 @@
-/* Fast first stage of the oracle for binary32 sin, exp and log.
+/* Fast first stage of the oracle for binary32 sin, cos, tan, exp, exp2, log,
+ * log2, sinh, cosh and tanh.
  *
  * TEST INFRASTRUCTURE ONLY: used by tests/ to sweep every binary32 input;
  * the GPU library never links or calls it, and it shares no code, header,
@@ -20,6 +21,11 @@
  *       e^r by its Taylor series in double-double, times 2^k.
  *  log: x = m 2^e, m in [1/sqrt 2, sqrt 2); log m = 2 atanh t,
  *       t = (m - 1)/(m + 1), by its series in double-double, plus e ln 2.
+ *  cos, tan: sin's reduction; cos |x| = sin(|x| + pi/2), tan = sin r / cos r
+ *       or -cos r / sin r by the quadrant's parity.
+ *  exp2: 2^(k + f) = 2^k e^(f ln 2); log2 = log / ln 2 (powers of two exact).
+ *  sinh, cosh, tanh: from e^|x| and its reciprocal as pairs; below 2^-4
+ *       sinh by its Taylor series and tanh = sinh / sqrt(1 + sinh^2).
  *
  * Error budget (relative): the double-double operations of a series of
  * n <= 40 terms contribute below n 2^-104; the reductions are exact or below
@@ -110,7 +116,10 @@ static inline dd dd_from(double a) {
 static dd INV_FACT[NFACT];
 static dd INV_ODD[NODD];
 
+static dd INV_LN2;
+
 __attribute__((constructor)) static void init_coefficients(void) {
+  INV_LN2 = dd_div(dd_from(1.0), (dd){LN2_D[0], LN2_D[1]});
   INV_FACT[0] = dd_from(1.0);
   for (int n = 1; n < NFACT; ++n) INV_FACT[n] = dd_div(INV_FACT[n - 1], dd_from((double)n));
   for (int k = 0; k < NODD; ++k) INV_ODD[k] = dd_div(dd_from(1.0), dd_from((double)(2 * k + 1)));
@@ -213,14 +222,14 @@ static dd reduce_2_over_pi(uint32_t m, int E, int* quadrant) {
 /* ---- the functions: pair values ---------------------------------------- */
 
 /* returns 0 and a pair for finite results that need rounding; 1 with *rn
-   set for exact or special results */
-static int sin_value(float x, dd* v, float* rn) {
+   set for exact or special results.  kind: 0 sin, 1 cos, 2 tan */
+static int trig_value(float x, int kind, dd* v, float* rn) {
   if (isnan(x) || isinf(x)) {
     *rn = NAN;
     return 1;
   }
   if (x == 0.0f) {
-    *rn = x;
+    *rn = kind == 1 ? 1.0f : x;
     return 1;
   }
   double ax = fabs((double)x);
@@ -236,9 +245,17 @@ static int sin_value(float x, dd* v, float* rn) {
     dd f = reduce_2_over_pi(m, e - 24, &k);
     r = dd_mul(f, (dd){PIO2_D[0], PIO2_D[1]});
   }
-  dd s = (k & 1) ? cos_series(r) : sin_series(r);
-  if (k & 2) s = dd_neg(s);
-  if (x < 0.0f) s = dd_neg(s);
+  /* |x| = k pi/2 + r */
+  dd s;
+  if (kind == 2) {
+    dd sn = sin_series(r), cs = cos_series(r);
+    s = (k & 1) ? dd_neg(dd_div(cs, sn)) : dd_div(sn, cs);
+  } else {
+    int q = (k + kind) & 3; /* cos |x| = sin(|x| + pi/2) */
+    s = (q & 1) ? cos_series(r) : sin_series(r);
+    if (q & 2) s = dd_neg(s);
+  }
+  if (x < 0.0f && kind != 1) s = dd_neg(s); /* sin and tan are odd, cos even */
   *v = s;
   return 0;
 }
@@ -312,6 +329,121 @@ static int log_value(float x, dd* v, float* rn) {
   return 0;
 }
 
+/* e^a as a pair times 2^k for a finite binary32 |a| <= 104 (the exp
+   reduction above) */
+static dd exp_pair(double a) {
+  double k = nearbyint(a / LN2_D[0]);
+  dd r = dd_add(dd_from(a), dd_neg(two_prod(k, LN2_D[0])));
+  r = dd_add(r, dd_neg(two_prod(k, LN2_D[1])));
+  r = dd_add(r, dd_from(-k * LN2_D[2]));
+  dd e = exp_series(r);
+  e.hi = ldexp(e.hi, (int)k);
+  e.lo = ldexp(e.lo, (int)k);
+  return e;
+}
+
+static int exp2_value(float x, dd* v, float* rn) {
+  if (isnan(x)) {
+    *rn = x;
+    return 1;
+  }
+  if (x > 128.5f) {
+    *rn = INFINITY;
+    return 1;
+  }
+  if (x < -151.0f) {
+    *rn = 0.0f;
+    return 1;
+  }
+  double xd = (double)x;
+  double k = nearbyint(xd);
+  if (xd == k) { /* exact powers of two */
+    *rn = (float)ldexp(1.0, (int)k);
+    return 1;
+  }
+  /* 2^f = e^(f ln 2), f = x - k exact, |f ln2| <= 0.35 */
+  dd a = dd_mul_d((dd){LN2_D[0], LN2_D[1]}, xd - k);
+  dd e = exp_series(a);
+  e.hi = ldexp(e.hi, (int)k);
+  e.lo = ldexp(e.lo, (int)k);
+  *v = e;
+  return 0;
+}
+
+static int log2_value(float x, dd* v, float* rn) {
+  int special = log_value(x, v, rn);
+  if (special) return 1;
+  int e;
+  double m = frexp((double)x, &e);
+  if (m == 0.5) { /* powers of two: exact */
+    *rn = (float)(e - 1);
+    return 1;
+  }
+  *v = dd_mul(*v, INV_LN2);
+  return 0;
+}
+
+/* sinh, cosh, tanh from E = e^|x| as a pair; below |x| = 2^-4 sinh and tanh
+   by their Taylor series (x + x^3/6 + ... and x - x^3/3 + ...), where E - 1/E
+   would cancel */
+static dd sinh_small(dd x) { /* |x| < 2^-4: sum x^(2n+1)/(2n+1)!, n <= 8 */
+  dd z = dd_mul(x, x);
+  dd s = INV_FACT[17];
+  for (int n = 7; n >= 0; --n) s = dd_add(dd_mul(s, z), INV_FACT[2 * n + 1]);
+  return dd_mul(s, x);
+}
+
+static int hyp_value(float x, int kind, dd* v, float* rn) { /* 0 sinh, 1 cosh, 2 tanh */
+  if (isnan(x)) {
+    *rn = x;
+    return 1;
+  }
+  double ax = fabs((double)x);
+  if (x == 0.0f) {
+    *rn = kind == 1 ? 1.0f : x;
+    return 1;
+  }
+  if (kind == 2 && ax > 20.0) { /* tanh = 1 - 2 e^(-2|x|) + ...: the pair (1, -2 e^(-2|x|)) */
+    dd t = {1.0, -2.0 * exp(-2.0 * ax)};
+    *v = x < 0.0f ? dd_neg(t) : t;
+    return 0;
+  }
+  if (kind != 2 && ax > 90.0) { /* e^90 / 2 > 2^128 */
+    *rn = kind == 1 ? INFINITY : copysignf(INFINITY, x);
+    return 1;
+  }
+  dd s;
+  if (kind != 1 && ax < 0.0625) {
+    dd sh = sinh_small(dd_from(ax));
+    if (kind == 0) {
+      s = sh;
+    } else { /* tanh = sinh / sqrt(1 + sinh^2) */
+      dd one = dd_add(dd_from(1.0), dd_mul(sh, sh));
+      double r0 = sqrt(one.hi);
+      dd q = dd_add(one, dd_neg(two_prod(r0, r0)));
+      dd root = dd_add(dd_from(r0), dd_from(q.hi / (2.0 * r0)));
+      s = dd_div(sh, root);
+    }
+  } else {
+    dd E = exp_pair(ax);
+    dd iE = dd_div(dd_from(1.0), E);
+    if (kind == 0) {
+      s = dd_add(E, dd_neg(iE));
+    } else if (kind == 1) {
+      s = dd_add(E, iE);
+    } else {
+      s = dd_div(dd_add(E, dd_neg(iE)), dd_add(E, iE));
+    }
+    if (kind != 2) {
+      s.hi *= 0.5;
+      s.lo *= 0.5;
+    }
+  }
+  if (x < 0.0f && kind != 1) s = dd_neg(s);
+  *v = s;
+  return 0;
+}
+
 /* ---- rounding to binary32 ----------------------------------------------- */
 
 /* distance |v - c| for a float candidate c (c = 2^128 stands for +inf) */
@@ -357,13 +489,20 @@ static int round_f32(dd v, double rel, float* out) {
 
 /* ---- exported entry points ---------------------------------------------- */
 
-enum { FN_SIN = 0, FN_EXP = 1, FN_LOG = 2 };
+enum { FN_SIN, FN_EXP, FN_LOG, FN_COS, FN_TAN, FN_EXP2, FN_LOG2, FN_SINH, FN_COSH, FN_TANH };
 
 static int value(int fn, float x, dd* v, float* rn) {
   switch (fn) {
-    case FN_SIN: return sin_value(x, v, rn);
+    case FN_SIN: return trig_value(x, 0, v, rn);
+    case FN_COS: return trig_value(x, 1, v, rn);
+    case FN_TAN: return trig_value(x, 2, v, rn);
     case FN_EXP: return exp_value(x, v, rn);
-    default: return log_value(x, v, rn);
+    case FN_EXP2: return exp2_value(x, v, rn);
+    case FN_LOG: return log_value(x, v, rn);
+    case FN_LOG2: return log2_value(x, v, rn);
+    case FN_SINH: return hyp_value(x, 0, v, rn);
+    case FN_COSH: return hyp_value(x, 1, v, rn);
+    default: return hyp_value(x, 2, v, rn);
   }
 }
 
@@ -402,13 +541,19 @@ static inline uint32_t bits_of(float f) {
   return b;
 }
 
-/* glibc's binary64 function, rounded to binary32 */
-static float libm_double_rounded(int fn, float x) {
-  double d = (double)x;
+/* the host libm's binary64 function */
+static double libm_double(int fn, double d) {
   switch (fn) {
-    case FN_SIN: return (float)sin(d);
-    case FN_EXP: return (float)exp(d);
-    default: return (float)log(d);
+    case FN_SIN: return sin(d);
+    case FN_COS: return cos(d);
+    case FN_TAN: return tan(d);
+    case FN_EXP: return exp(d);
+    case FN_EXP2: return exp2(d);
+    case FN_LOG: return log(d);
+    case FN_LOG2: return log2(d);
+    case FN_SINH: return sinh(d);
+    case FN_COSH: return cosh(d);
+    default: return tanh(d);
   }
 }
 
@@ -437,12 +582,12 @@ void oracle_fast32_sweep_libm(int fn, uint64_t start, uint64_t count, sweep_stat
         continue;
       }
     }
-    float g = libm_double_rounded(fn, x);
+    double d = libm_double(fn, (double)x);
+    float g = (float)d;
     int same = (bits_of(g) == bits_of(r)) || (isnan(g) && isnan(r));
     if (!same) {
       if (st->differ < differ_cap) differ[st->differ] = b;
       st->differ++;
-      double d = (fn == FN_SIN) ? sin((double)x) : (fn == FN_EXP ? exp((double)x) : log((double)x));
       /* the binary32 midpoint between r and g */
       double mid = 0.5 * ((double)r + (double)g);
       double ulp_d = fabs(nextafter(d, INFINITY) - d);
@@ -473,14 +618,17 @@ void oracle_fast32_check(int fn, uint64_t start, uint64_t count, const float* y,
     dd v;
     float r;
     st->n++;
-    int special = value(fn, x, &v, &r);
-    if (!special && round_f32(v, REL, &r)) {
+    int exact = value(fn, x, &v, &r);
+    if (exact) {
+      v.hi = (double)r; /* an exact result: the pair is the value itself */
+      v.lo = 0.0;
+    } else if (round_f32(v, REL, &r)) {
       if (st->undecided < undec_cap) undec[st->undecided] = b;
       st->undecided++;
       continue;
     }
     int same = (bits_of(yi) == bits_of(r)) || (isnan(yi) && isnan(r));
-    if (special || isnan(r) || isinf(r) || r == 0.0f || fabsf(r) < 0x1p-126f) {
+    if (isnan(r) || isinf(r) || r == 0.0f || fabsf(r) < 0x1p-126f) {
       if (!same) {
         if (st->special_mismatch + st->violations < bad_cap)
           bad[st->special_mismatch + st->violations] = b;

@@ -1,7 +1,8 @@
-"""Exhaustive sweeps over every binary32 bit pattern for sin, exp and log
-(test infrastructure; north of the seconds-long tests, so run by hand).
+"""Exhaustive sweeps over every binary32 bit pattern for sin, cos, tan, exp,
+exp2, log, log2, sinh, cosh and tanh (test infrastructure; minutes per
+function, so run by hand).
 
-    python -m tests.sweep32 libm [--fns sin,exp,log] [--threads N]
+    python -m tests.sweep32 libm [--fns sin,exp,log,...] [--threads N]
         the oracle's fast stage against the host libm's binary64 result
         rounded to binary32, all 2^32 inputs: where the two differ, the
         binary64 value must lie within two of its ulps of a binary32

@@ -1,5 +1,6 @@
 """Pins of the oracle's fast binary32 stage (oracle/fast/fast32.c) for sin,
-exp and log, independently of its own arithmetic:
+cos, tan, exp, exp2, log, log2, sinh, cosh and tanh, independently of its
+own arithmetic:
 
 * against mpmath at 300 bits: the double-double value within the claimed
   2^-90 relative (random bit patterns, each function's domain, arguments
@@ -22,7 +23,10 @@ import pytest
 import oracle
 from oracle import fast32
 
-MPF = {"sin": mp.sin, "exp": mp.exp, "log": mp.log}
+MPF = {"sin": mp.sin, "cos": mp.cos, "tan": mp.tan, "exp": mp.exp, "exp2": lambda v: mp.mpf(2) ** v,
+       "log": mp.log, "log2": lambda v: mp.log(v, 2), "sinh": mp.sinh, "cosh": mp.cosh,
+       "tanh": mp.tanh}
+FNS = list(MPF)
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -34,7 +38,7 @@ def _inputs(fn, n=1200, seed=3):
     rng = np.random.default_rng(seed + len(fn))
     bits = rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)
     parts = [bits.view(np.float32)]
-    if fn == "sin":
+    if fn in ("sin", "cos", "tan"):
         k = np.concatenate([np.arange(1, 400), rng.integers(1, 1 << 40, 300)]).astype(np.float64)
         near = (k * (math.pi / 2)).astype(np.float32)
         parts += [near, np.nextafter(near, np.float32(0)), rng.uniform(-10, 10, 300).astype(np.float32),
@@ -42,6 +46,13 @@ def _inputs(fn, n=1200, seed=3):
     elif fn == "exp":
         parts += [rng.uniform(-104, 89, 600).astype(np.float32),
                   np.float32([88.72283, 88.72284, -103.97208, -103.9721, -87.33655, 1e-30, -1e-30])]
+    elif fn == "exp2":
+        parts += [rng.uniform(-151, 129, 600).astype(np.float32),
+                  np.float32([127.99999, 128.0, -149.0, -149.5, -150.0, 0.5, 1e-30])]
+    elif fn in ("sinh", "cosh", "tanh"):
+        parts += [rng.uniform(-95, 95, 400).astype(np.float32),
+                  (np.exp(rng.uniform(-60, 0, 200)) * rng.choice([-1, 1], 200)).astype(np.float32),
+                  np.float32([0.0625, -0.0624999, 89.4, 89.5, 20.0, 9.0, 1e-40])]
     else:
         parts += [np.exp(rng.uniform(-100, 88, 600)).astype(np.float32),
                   (1 + rng.uniform(-1e-3, 1e-3, 200)).astype(np.float32),
@@ -49,7 +60,7 @@ def _inputs(fn, n=1200, seed=3):
     return np.concatenate(parts).astype(np.float32)
 
 
-@pytest.mark.parametrize("fn", ["sin", "exp", "log"])
+@pytest.mark.parametrize("fn", FNS)
 def test_pair_within_claimed_bound_of_mpmath(fn):
     x = _inputs(fn, n=300)
     rn, hi, lo, und = fast32.fast_eval(fn, x)
@@ -58,17 +69,17 @@ def test_pair_within_claimed_bound_of_mpmath(fn):
     for xi, h, l in zip(x, hi, lo):
         if not (np.isfinite(h) and np.isfinite(xi)) or h == 0:
             continue
-        if fn == "log" and xi <= 0:
+        if fn in ("log", "log2") and xi <= 0:
             continue
         exact = MPF[fn](mp.mpf(float(xi)))
-        if fn == "exp" and (exact > mp.mpf(2) ** 128 or exact < mp.mpf(2) ** -150):
+        if exact == 0 or abs(exact) > mp.mpf(2) ** 128 or abs(exact) < mp.mpf(2) ** -150:
             continue
         rel = abs((mp.mpf(float(h)) + mp.mpf(float(l))) - exact) / abs(exact)
         worst = max(worst, rel)
     assert worst <= mp.mpf(2) ** -90, (fn, float(mp.log(worst, 2)))
 
 
-@pytest.mark.parametrize("fn", ["sin", "exp", "log"])
+@pytest.mark.parametrize("fn", FNS)
 def test_rounded_results_match_the_ball_oracle(fn):
     x = _inputs(fn)
     rn, hi, lo = fast32.evaluate(fn, x)
@@ -79,8 +90,12 @@ def test_rounded_results_match_the_ball_oracle(fn):
 
 
 @pytest.mark.parametrize("fn,start", [("sin", 0x3f800000), ("sin", 0x4e000000),
+                                      ("cos", 0x40490000), ("tan", 0x3fc90000),
                                       ("exp", 0x42000000), ("exp", 0xc2c00000),
-                                      ("log", 0x3f7f0000), ("log", 0x00000001)])
+                                      ("exp2", 0xc3100000), ("log", 0x3f7f0000),
+                                      ("log", 0x00000001), ("log2", 0x3f800000),
+                                      ("sinh", 0x3d800000), ("cosh", 0x42b00000),
+                                      ("tanh", 0x3c000000)])
 def test_sweep_against_libm_double_rounded(fn, start):
     st, differ, und = fast32.sweep_libm(fn, start, 1 << 18)
     assert st.n == 1 << 18
