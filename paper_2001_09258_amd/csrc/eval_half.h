@@ -14,7 +14,9 @@
 //   pow: for bf16 and f16, 2^(y log2|x|) with the binary32 Annex F selects;
 //   sin, cos, tan, sincos: one Cody-Waite reduction by pi/2 below |x| =
 //     65536 (every finite f16), the binary32 kernels' Payne-Hanek reduction
-//     above (bf16 only), the same short polynomials after either.
+//     above (bf16 only), the same short polynomials after either;
+//   atan2, atan, asin, acos: one reciprocal-unit quotient and a short atan
+//     polynomial.
 #pragma once
 #include "eval_f32.h"
 
@@ -179,6 +181,38 @@ LMH_INLINE float ntan_fin(float x, Trig32 s) {
   float v = htan_finish(s);
   return x == 0.0f ? x : v;
 }
+
+// ---- atan2, atan, asin, acos -----------------------------------------------
+// t = min(|x|, |y|) / max(|x|, |y|) from the reciprocal unit on the larger
+// one's mantissa (d = m 2^e: t = (n 2^-e) rcp(m), both factors in range
+// whatever the exponents; a scaled numerator below the normal range rounds
+// once at 2^-149, finer than either format), atan t = t + t^3 A(t^2) with A
+// fitted to 2^-20.4 on [0, 1] (t within about 2^-22), then the binary32
+// form's quadrant selects and Annex F cases.  atan x = atan2(x, 1); asin and
+// acos from c = sqrt((1 - |x|)(1 + |x|)) by the square-root unit:
+// asin x = atan2(x, c), acos x = atan2(c, x) (NaN beyond |x| = 1 through c).
+LMH_INLINE float natan2(float y, float x) {
+  float ay = fabs_(y), ax = fabs_(x);
+  bool both_inf = isinf_(ax) && isinf_(ay);
+  ay = both_inf ? 1.0f : ay;
+  ax = both_inf ? 1.0f : ax;
+  bool swap = ay > ax;
+  float n = swap ? ax : ay, d = swap ? ay : ax;
+  int e = frexp_exp_(d);
+  float t = ldexp_(n, -e) * rcp_hw(frexp_mant_(d));
+  float z = t * t;
+  float a = fma_(t * z, poly_estrin(z, ATAN_N_F32), t);
+  return atan2f_u35_finish(y, x, a, swap);
+}
+
+LMH_INLINE float natan(float x) { return natan2(x, 1.0f); }
+
+LMH_INLINE float nasin_root(float x) {
+  float a = fabs_(x);
+  return __builtin_amdgcn_sqrtf((1.0f - a) * (1.0f + a));
+}
+LMH_INLINE float nasin(float x) { return natan2(x, nasin_root(x)); }
+LMH_INLINE float nacos(float x) { return natan2(nasin_root(x), x); }
 
 // f16: every finite argument is below 65536
 LMH_INLINE float hsin(float x) { return nsin_fin(x, hsincos_reduce(x)); }

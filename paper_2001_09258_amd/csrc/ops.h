@@ -299,9 +299,15 @@ LMH_OPN(OpNTanh, ntanh)
 LMH_OPN(OpHSin, hsin)
 LMH_OPN(OpHCos, hcos)
 LMH_OPN(OpHTan, htan)
+LMH_OPN(OpNAtan, natan)
+LMH_OPN(OpNAsin, nasin)
+LMH_OPN(OpNAcos, nacos)
 #undef LMH_OPN
 struct OpNPow {
   static __device__ __forceinline__ float f(float x, float y) { return lmh::npow(x, y); }
+};
+struct OpNAtan2 {
+  static __device__ __forceinline__ float f(float y, float x) { return lmh::natan2(y, x); }
 };
 // bf16 trig in the split kernel's interface (Payne-Hanek lanes gathered)
 #define LMH_NTRIG_OP(NAME, FIN)                                                                  \
@@ -362,10 +368,6 @@ struct EvalOp {
   struct EvalOp<IO, OP> {                             \
     typedef AS type;                                  \
   };
-#define LMH_NARROW_EVAL(OP10, OP35)                   \
-  LMH_EVAL_AS(IoBF16, OP10, OP35)                     \
-  LMH_EVAL_AS(IoF16, OP10, OP35)                      \
-  LMH_EVAL_AS(IoF32ViaF64, OP10, OP35)
 #define LMH_WIDE_AND_HALF(OP10, OP35, OPN)            \
   LMH_EVAL_AS(IoBF16, OP10, OPN)                      \
   LMH_EVAL_AS(IoF16, OP10, OPN)                       \
@@ -391,11 +393,10 @@ LMH_HALF_ONLY(OpExpU10, OpNExp)
 LMH_HALF_ONLY(OpExp2U10, OpNExp2)
 LMH_HALF_ONLY(OpLog2U10, OpNLog2)
 LMH_HALF_ONLY(OpPowU10, OpNPow)
-LMH_NARROW_EVAL(OpAsinU10, OpAsinU35)
-LMH_NARROW_EVAL(OpAcosU10, OpAcosU35)
-LMH_NARROW_EVAL(OpAtanU10, OpAtanU35)
-LMH_NARROW_EVAL(OpAtan2U10, OpAtan2U35)
-#undef LMH_NARROW_EVAL
+LMH_WIDE_AND_HALF(OpAsinU10, OpAsinU35, OpNAsin)
+LMH_WIDE_AND_HALF(OpAcosU10, OpAcosU35, OpNAcos)
+LMH_WIDE_AND_HALF(OpAtanU10, OpAtanU35, OpNAtan)
+LMH_WIDE_AND_HALF(OpAtan2U10, OpAtan2U35, OpNAtan2)
 #undef LMH_WIDE_AND_HALF
 #undef LMH_HALF_ONLY
 #undef LMH_TRIG_EVAL

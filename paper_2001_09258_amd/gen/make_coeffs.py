@@ -222,6 +222,7 @@ SPECS = [
     ("SINH_H_F32", sinh_h, "f32", -31, 2),
     ("ASIN_S_F32", asin_s, "f32", -29, 3),
     ("ERF_P_F32", erf_p, "f32", -28, 2),
+    ("ATAN_N_F32", atan_a, "f32", -19, 3),
     ("TANH_G_F32", tanh_g, "f32", -31, 4),
 ]
 

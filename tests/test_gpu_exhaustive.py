@@ -167,6 +167,34 @@ def test_narrow_pow_pairs(dt):
     print("pow %s pairs: max %.3f ulp" % (dt, res["max_ulp"]), flush=True)
 
 
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+def test_narrow_atan2_pairs(dt):
+    """atan2 on 2^18 pairs of the format: random bit patterns for both
+    operands (every sign, zero, infinity, NaN and subnormal combination
+    occurs), a quarter of them with y/x near 1 where the octant changes,
+    against the oracle."""
+    n = 1 << 18
+    rng = np.random.default_rng(29)
+    bits = rng.integers(0, 1 << 16, size=(2, n)).astype(np.uint32)
+    if dt == "bf16":
+        pat = (bits << 16).view(np.float32).astype(np.float64)
+    else:
+        pat = bits.astype(np.uint16).view(np.float16).astype(np.float64)
+    near = rng.random(n) < 0.25
+    y = pat[0]
+    x = np.where(near, y * rng.uniform(0.9, 1.1, n) * rng.choice([-1.0, 1.0], n), pat[1])
+    x = to_host(to_device(x, dt))
+    y = to_host(to_device(y, dt))
+    r = run_gpu("atan2", "u10", dt, y, x)
+    rn, hi, lo = run_oracle("atan2", dt, y, x)
+    res = compare(r, rn, hi, lo, dt, 1.0)
+    bad = res["bad_idx"][:4]
+    assert res["violations"] == 0 and res["special_mismatch"] == 0, \
+        "atan2 %s: y=%r x=%r got %r want %r (max %.3f ulp)" % (dt, y[bad], x[bad], r[bad], rn[bad],
+                                                             res["max_ulp"])
+    print("atan2 %s pairs: max %.3f ulp" % (dt, res["max_ulp"]), flush=True)
+
+
 def test_sqrt_correctly_rounded_sweep():
     """sqrt (exact variant: the correctly rounded square root) on every
     STRIDE-th binary32 pattern against numpy's binary32 square root (an IEEE
