@@ -49,7 +49,8 @@ class CheckStats(ctypes.Structure):
 def load():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        deps = [SRC, os.path.join(HERE, "fast", "common.h"), os.path.join(HERE, "fast", "tables.h")]
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(d) for d in deps):
             build()
         lib = ctypes.CDLL(LIB)
         P = ctypes.c_void_p
@@ -59,6 +60,10 @@ def load():
         lib.oracle_fast32_sweep_libm.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
                                                  ctypes.POINTER(SweepStats), P, ctypes.c_long, P,
                                                  ctypes.c_long]
+        lib.oracle_fast32_check_x.restype = None
+        lib.oracle_fast32_check_x.argtypes = [ctypes.c_int, P, P, ctypes.c_long, ctypes.c_double,
+                                              ctypes.POINTER(CheckStats), P, ctypes.c_long, P,
+                                              ctypes.c_long]
         lib.oracle_fast32_check.restype = None
         lib.oracle_fast32_check.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, P,
                                             ctypes.c_double, ctypes.POINTER(CheckStats), P,
@@ -118,3 +123,41 @@ def check(fn, start, count, y, bound, cap=1 << 12):
     lib.oracle_fast32_check(FNS[fn], start, count, y.ctypes.data, bound, ctypes.byref(st),
                             bad.ctypes.data, cap, und.ctypes.data, cap)
     return st, bad[:min(st.special_mismatch + st.violations, cap)], und[:min(st.undecided, cap)]
+
+
+def check_x(fn, x, y, bound, cap=1 << 10):
+    """Results y for arbitrary binary32 inputs x: (stats, failing indices,
+    undecided indices)."""
+    lib = load()
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    st = CheckStats()
+    bad = np.empty(cap, np.int64)
+    und = np.empty(cap, np.int64)
+    lib.oracle_fast32_check_x(FNS[fn], x.ctypes.data, y.ctypes.data, x.size, bound, ctypes.byref(st),
+                              bad.ctypes.data, cap, und.ctypes.data, cap)
+    return st, bad[:min(st.special_mismatch + st.violations, cap)], und[:min(st.undecided, cap)]
+
+
+def check_all(fn, x, y, bound, threads=16, chunk=1 << 20):
+    """check_x() over chunks on a thread pool: a dict of totals with failing
+    and undecided indices (up to 1024 each)."""
+    import concurrent.futures as cf
+    load()
+    tot = dict(n=0, undecided=0, special_mismatch=0, violations=0, n_reg=0, max_ulp=0.0,
+               sum_ulp=0.0)
+    bad, und = [], []
+    with cf.ThreadPoolExecutor(threads) as ex:
+        futs = [(s, ex.submit(check_x, fn, x[s:s + chunk], y[s:s + chunk], bound))
+                for s in range(0, x.size, chunk)]
+        for s, f in futs:
+            st, b, u = f.result()
+            for k in ("n", "undecided", "special_mismatch", "violations", "n_reg"):
+                tot[k] += getattr(st, k)
+            tot["sum_ulp"] += st.sum_ulp
+            tot["max_ulp"] = max(tot["max_ulp"], st.max_ulp)
+            bad.append(b + s)
+            und.append(u + s)
+    tot["bad"] = np.concatenate(bad)[:1024] if bad else np.zeros(0, np.int64)
+    tot["undecided_idx"] = np.concatenate(und)[:1024] if und else np.zeros(0, np.int64)
+    return tot

@@ -1,0 +1,119 @@
+"""ctypes binding of the oracle's fast binary64 stage (``oracle/fast/fast64.c``)
+for sin, cos, tan, exp, exp2, log, log2, sinh, cosh and tanh.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  The C stage gives the
+value within 2^-90 relative and the correctly rounded binary64 result where
+that bound decides it; ``evaluate`` and ``check_all`` send the inputs it
+cannot decide to the ball oracle.  Pinned against mpmath and the ball oracle
+in ``tests/test_oracle_fast.py``.
+"""
+import concurrent.futures as cf
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "fast", "fast64.c")
+DEPS = [SRC, os.path.join(HERE, "fast", "common.h"), os.path.join(HERE, "fast", "tables.h")]
+LIB = os.path.join(HERE, "liboracle_fast64.so")
+FNS = {"sin": 0, "exp": 1, "log": 2, "cos": 3, "tan": 4, "exp2": 5, "log2": 6, "sinh": 7,
+       "cosh": 8, "tanh": 9}
+
+_lib = None
+
+
+def build():
+    """Compile the C stage (gcc, IEEE binary64, no contraction; fma() as the
+    x86-64 fused multiply-add)."""
+    tmp = "%s.tmp%d" % (LIB, os.getpid())
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-mfma", "-ffp-contract=off",
+           "-fno-fast-math", "-o", tmp, SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+class CheckStats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_long), ("undecided", ctypes.c_long),
+                ("special_mismatch", ctypes.c_long), ("violations", ctypes.c_long),
+                ("max_ulp", ctypes.c_double), ("sum_ulp", ctypes.c_double),
+                ("n_reg", ctypes.c_long), ("worst", ctypes.c_long)]
+
+
+def load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(d) for d in DEPS):
+            build()
+        lib = ctypes.CDLL(LIB)
+        P = ctypes.c_void_p
+        lib.oracle_fast64_eval.restype = None
+        lib.oracle_fast64_eval.argtypes = [ctypes.c_int, P, ctypes.c_long, P, P, P, P]
+        lib.oracle_fast64_check.restype = None
+        lib.oracle_fast64_check.argtypes = [ctypes.c_int, P, P, ctypes.c_long, ctypes.c_double,
+                                            ctypes.POINTER(CheckStats), P, ctypes.c_long, P,
+                                            ctypes.c_long]
+        _lib = lib
+    return _lib
+
+
+def fast_eval(fn, x):
+    """The C stage alone: (rn, hi, lo, undecided) for binary64 inputs x."""
+    lib = load()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    n = x.size
+    hi, lo, rn = (np.empty(n, np.float64) for _ in range(3))
+    und = np.empty(n, np.uint8)
+    lib.oracle_fast64_eval(FNS[fn], x.ctypes.data, n, hi.ctypes.data, lo.ctypes.data,
+                           rn.ctypes.data, und.ctypes.data)
+    return rn, hi, lo, und.astype(bool)
+
+
+def evaluate(fn, x):
+    """(rn, hi, lo) as oracle.evaluate(fn, "f64", x), undecided inputs by the
+    ball oracle."""
+    from . import evaluate as ball_evaluate
+    rn, hi, lo, und = fast_eval(fn, x)
+    if und.any():
+        r2, h2, l2 = ball_evaluate(fn, "f64", np.asarray(x, np.float64)[und])
+        rn[und], hi[und], lo[und] = r2, h2, l2
+    return rn, hi, lo
+
+
+def check(fn, x, y, bound, cap=1 << 10):
+    """Results y for inputs x against the C stage (tests/ulp.py's metric):
+    (stats, failing indices, undecided indices)."""
+    lib = load()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    st = CheckStats()
+    bad = np.empty(cap, np.int64)
+    und = np.empty(cap, np.int64)
+    lib.oracle_fast64_check(FNS[fn], x.ctypes.data, y.ctypes.data, x.size, bound, ctypes.byref(st),
+                            bad.ctypes.data, cap, und.ctypes.data, cap)
+    return st, bad[:min(st.special_mismatch + st.violations, cap)], und[:min(st.undecided, cap)]
+
+
+def check_all(fn, x, y, bound, threads=16, chunk=1 << 20):
+    """check() over chunks on a thread pool; returns a dict of totals with
+    the failing and undecided indices (up to 1024 each)."""
+    load()
+    tot = dict(n=0, undecided=0, special_mismatch=0, violations=0, n_reg=0, max_ulp=0.0,
+               sum_ulp=0.0)
+    bad, und = [], []
+    with cf.ThreadPoolExecutor(threads) as ex:
+        futs = [(s, ex.submit(check, fn, x[s:s + chunk], y[s:s + chunk], bound))
+                for s in range(0, x.size, chunk)]
+        for s, f in futs:
+            st, b, u = f.result()
+            for k in ("n", "undecided", "special_mismatch", "violations", "n_reg"):
+                tot[k] += getattr(st, k)
+            tot["sum_ulp"] += st.sum_ulp
+            tot["max_ulp"] = max(tot["max_ulp"], st.max_ulp)
+            bad.append(b + s)
+            und.append(u + s)
+    tot["bad"] = np.concatenate(bad)[:1024] if bad else np.zeros(0, np.int64)
+    tot["undecided_idx"] = np.concatenate(und)[:1024] if und else np.zeros(0, np.int64)
+    return tot

@@ -124,3 +124,78 @@ def test_check_metric_on_known_answers():
     y[5] = np.nan
     st, bad, _ = fast32.check("exp", start, n, y, 1.0)
     assert st.violations == 1 and bad[0] == start + 5
+
+
+# ---- the binary64 stage (oracle/fast/fast64.c) -------------------------------
+
+from oracle import fast64  # noqa: E402
+import workloads as W  # noqa: E402
+
+
+def _inputs64(fn, n=800, seed=4):
+    rng = np.random.default_rng(seed + len(fn))
+    parts = [W.mixture(fn, "f64", n, 7), rng.integers(0, 1 << 63, n // 2, dtype=np.uint64).view(np.float64),
+             -rng.integers(0, 1 << 63, n // 4, dtype=np.uint64).view(np.float64)]
+    if fn in ("sin", "cos", "tan"):
+        k = rng.integers(1, 1 << 50, 200).astype(np.float64)
+        near = k * (math.pi / 2)
+        parts += [near, np.nextafter(near, 0.0),
+                  np.array([6381956970095103 * 2.0 ** 797, 5988794123081509 * 2.0 ** 816, 1e22,
+                            2.0 ** 1023, 0.7853981633974483, 5e-324])]
+    elif fn in ("exp", "exp2"):
+        lo, hi = (-746.0, 710.0) if fn == "exp" else (-1076.0, 1025.0)
+        parts += [rng.uniform(lo, hi, 400), np.array([709.78, 709.79, -745.13, -708.4, -1074.5, 1023.9])]
+    elif fn in ("sinh", "cosh", "tanh"):
+        parts += [rng.uniform(-715, 715, 300), np.exp(rng.uniform(-700, 0, 200)),
+                  np.array([0.0625, 40.0, 40.1, 710.4, 710.5, 1e-310])]
+    else:
+        parts += [np.exp(rng.uniform(-740, 709, 400)), 1 + rng.uniform(-1e-9, 1e-9, 100),
+                  np.array([1.0, 0.9999999999999999, 5e-324, 1.7976931348623157e308])]
+    return np.concatenate(parts)
+
+
+@pytest.mark.parametrize("fn", FNS)
+def test_fast64_pair_within_claimed_bound_of_mpmath(fn):
+    x = _inputs64(fn, n=150)
+    rn, hi, lo, und = fast64.fast_eval(fn, x)
+    mp.mp.prec = 300
+    worst = mp.mpf(0)
+    for xi, h, l in zip(x, hi, lo):
+        if not (np.isfinite(h) and np.isfinite(xi)) or h == 0:
+            continue
+        if fn in ("log", "log2") and xi <= 0:
+            continue
+        exact = MPF[fn](mp.mpf(float(xi)))
+        # the pair is returned scaled: below 2^-960 its low word loses bits
+        if exact == 0 or abs(exact) > mp.mpf(2) ** 1023 or abs(exact) < mp.mpf(2) ** -960:
+            continue
+        worst = max(worst, abs((mp.mpf(float(h)) + mp.mpf(float(l))) - exact) / abs(exact))
+    assert worst <= mp.mpf(2) ** -90, (fn, float(mp.log(worst, 2)))
+
+
+@pytest.mark.parametrize("fn", FNS)
+def test_fast64_rounded_results_match_the_ball_oracle(fn):
+    x = _inputs64(fn)
+    rn, hi, lo = fast64.evaluate(fn, x)
+    rb = oracle.evaluate(fn, "f64", x)[0]
+    same = (rn == rb) | (np.isnan(rn) & np.isnan(rb))
+    same &= (np.signbit(rn) == np.signbit(rb)) | np.isnan(rb)
+    assert same.all(), x[~same][:5]
+
+
+def test_fast64_check_metric_on_known_answers():
+    x = W.mixture("exp", "f64", 1 << 14, 3)
+    rn = fast64.evaluate("exp", x)[0]
+    tot = fast64.check_all("exp", x, rn, 1.0, threads=2, chunk=1 << 12)
+    assert tot["violations"] == 0 and tot["special_mismatch"] == 0 and tot["max_ulp"] <= 0.5
+    finite = np.isfinite(rn) & (np.abs(rn) >= 2.0 ** -1022)
+    # one ulp up, away from powers of two (where the binade below has half the ulp)
+    finite &= np.frexp(rn)[0] != 0.5
+    up = np.where(finite, np.nextafter(rn, np.inf), rn)
+    tot = fast64.check_all("exp", x, up, 1.0, threads=2, chunk=1 << 12)
+    assert 0.5 < tot["max_ulp"] < 1.5 and tot["special_mismatch"] == 0
+    y = rn.copy()
+    i = int(np.nonzero(finite)[0][3])
+    y[i] = np.nan
+    tot = fast64.check_all("exp", x, y, 1.0, threads=2, chunk=1 << 12)
+    assert tot["violations"] == 1 and tot["bad"][0] == i
