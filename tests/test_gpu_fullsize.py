@@ -7,7 +7,9 @@ elements) runs on its full-size input after the launch-shape tuner has
 picked its shape on those buffers, exactly as the benchmark does; 2^16
 sampled outputs plus the first and last are checked against the oracle one
 by one (ULP bound, special classes and binary64/binary32 subnormal results
-bit-exact; exact functions bit-exact).
+bit-exact; exact functions bit-exact), and every output of the unary
+functions the oracle's fast stages cover (sin, cos, tan, exp, exp2, log,
+log2, sinh, cosh, tanh) and of fmod is checked as well.
 """
 import concurrent.futures as cf
 
@@ -21,9 +23,11 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 import paper_2001_09258_amd as L  # noqa: E402
+from oracle import fast32, fast64  # noqa: E402
 
 N = 1 << 26
 SAMPLES = 1 << 16
+FAST_FNS = set(fast32.FNS)
 STEP = [("sin", "u10"), ("sin", "u35"), ("cos", "u10"), ("cos", "u35"), ("tan", "u10"),
         ("tan", "u35"), ("exp", "u10"), ("exp2", "u10"), ("log", "u10"), ("log2", "u10"),
         ("pow", "u10"), ("atan2", "u10"), ("sinh", "u10"), ("cosh", "u10"), ("tanh", "u10")]
@@ -63,3 +67,28 @@ def test_full_size_tuned_sampled(workload, fn, variant, dt):
     res = check_values(fn, variant, dt, a[idx], None if b is None else b[idx], y,
                        label="full size %s %s" % (workload, shape))
     print("  shape %s: %d checked, max %.3f ulp" % (shape, idx.size, res["max_ulp"]), flush=True)
+    # every output: the oracle's fast stage for the unary functions it
+    # covers (its undecided inputs through the ball oracle), the host's
+    # exact fmod for fmod
+    if fn in FAST_FNS or fn == "fmod":
+        y_all = to_host(out)
+        torch.cuda.synchronize()
+        if fn == "fmod":
+            want = np.fmod(a, b)
+            same = (y_all == want) | (np.isnan(y_all) & np.isnan(want))
+            same &= (np.signbit(y_all) == np.signbit(want)) | np.isnan(want)
+            assert same.all(), (a[~same][:3], b[~same][:3], y_all[~same][:3])
+            print("  all %d outputs bit-exact" % N, flush=True)
+            return
+        fast = fast64 if dt == "f64" else fast32
+        bound = 1.0 if variant == "u10" else 3.5
+        tot = fast.check_all(fn, a, y_all, bound)
+        if tot["undecided"]:
+            u = tot["undecided_idx"]
+            assert tot["undecided"] == u.size, "more undecided inputs than listed"
+            check_values(fn, variant, dt, a[u], None, y_all[u], label="full size, undecided")
+        assert tot["violations"] == 0 and tot["special_mismatch"] == 0, \
+            (fn, variant, dt, a[tot["bad"][:4]], y_all[tot["bad"][:4]])
+        print("  all %d outputs: max %.4f ulp, mean %.4f, %d by the ball oracle"
+              % (N, tot["max_ulp"], tot["sum_ulp"] / max(tot["n_reg"], 1), tot["undecided"]),
+              flush=True)
