@@ -124,14 +124,21 @@ LMH_INLINE float ntanh(float x) {
 }
 
 // ---- f16 trigonometry ----------------------------------------------------
-// k = rint(x 2/pi), r = x - k pi/2 by the binary32 kernels' float-float
-// Cody-Waite reduction (valid for |x| < 65536, which holds every finite
-// f16): r is within 2^-34 relative of the exact reduced argument, whose
-// magnitude over all f16 arguments is at least 2^-16 (x = 177.5).  inf and
-// NaN give a NaN r.
+// k = rint(x 2/pi), r = x - k pi/2 by three chained FMAs on the binary32
+// pieces of pi/2 (c0 the nearest float, c1 eight significant bits, c2 the
+// nearest float to the rest), for |x| < 65536, which holds every finite f16
+// and every bf16 the narrow kernels reduce this way.  Below 65536, |k| < 2^16
+// and a nonzero k means |x| > pi/4, where both formats' values are multiples
+// of 2^-11 or coarser: x - k c0 is then a multiple of 2^-23 below 1 in
+// magnitude, so the first FMA is exact.  The second and third round once
+// each, by at most 2^-24 of |r| + |k c2| (|k c2| < 2^-17), and the omitted
+// k (pi/2 - c0 - c1 - c2) is below 2^-41: against the smallest reduced
+// argument of these inputs, 2^-16 (x = 177.5), r is within 2^-23 relative.
+// inf and NaN give a NaN r.
 LMH_INLINE Trig32 hsincos_reduce(float x) {
   float k = rint_(x * TWO_OVER_PI_F);
-  return Trig32{cwf_reduce<false>(x, k, PIH_F_C0, PIH_F_C1, PIH_F_C2, PIH_F_C3), k};
+  float r = fma_(k, -PIH_F_C2, fma_(k, -PIH_F_C1, fma_(k, -PIH_F_C0, x)));
+  return Trig32{fff{r, 0.0f}, k};
 }
 
 // sin r and cos r for |r| <= pi/4 (a little more after k's rounding): Taylor
