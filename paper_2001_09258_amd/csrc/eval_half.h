@@ -19,6 +19,7 @@
 //     polynomial.
 #pragma once
 #include "eval_f32.h"
+#include "generated/ph_table_bf16.inc"
 
 #pragma STDC FP_CONTRACT OFF
 
@@ -226,14 +227,39 @@ LMH_INLINE float hsin(float x) { return nsin_fin(x, hsincos_reduce(x)); }
 LMH_INLINE float hcos(float x) { return ncos_fin(x, hsincos_reduce(x)); }
 LMH_INLINE float htan(float x) { return ntan_fin(x, hsincos_reduce(x)); }
 
-// bf16: from 65536 up (and for inf and NaN) the binary32 Payne-Hanek
-// reduction, whose state (r = x - k pi/2 as a pair, k mod 4, NaN r for a
-// non-finite x) has the same meaning
+// bf16 from 65536 up: Payne-Hanek in integer arithmetic.  |x| = m 2^(e-7)
+// with m < 2^8 an integer (bf16 keeps 8 significant bits); the table word
+// W(e) = floor(2^(e+55) 2/pi) mod 2^64 makes m W(e) mod 2^64 equal to
+// 2|x|/pi in units of 2^-62, modulo 4: the quadrant in the top two bits, the
+// fraction in the other 62, short of the exact value by less than m units
+// (2^-54).  The fraction, taken to [-1/2, 1/2) with the quadrant rounded
+// accordingly, is converted once to binary32 and multiplied by pi/2: r is
+// within about 2^-22 relative of x - j pi/2 wherever the fraction exceeds
+// 2^-30 (over all bf16 arguments it is at least 2^-13.3).  Negative x negates r
+// and j; inf and NaN give a NaN r.  The state has the Cody-Waite path's
+// meaning (r = x - j pi/2, j modulo 4).
+LMH_INLINE Trig32 nbtrig_big(float x) {
+  float a = fabs_(x);
+  bool fin = isfinite_(a);
+  int e = frexp_exp_(a) - 1;                          // a in [2^e, 2^(e+1))
+  int row = e - PH_BF16_E0;
+  row = row < 0 ? 0 : (row >= PH_BF16_ROWS ? PH_BF16_ROWS - 1 : row);
+  unsigned m = (unsigned)(fin ? ldexp_(frexp_mant_(a), 8) : 128.0f);
+  unsigned long long y = (unsigned long long)m * PH_WORDS_BF16[row];
+  long long g = (long long)(y << 2) >> 2;             // the fraction, sign-extended
+  float j = (float)(unsigned)(y >> 62) + (g < 0 ? 1.0f : 0.0f);
+  float r = ((float)g * 0x1p-62f) * PIH_F_C0;
+  r = fin ? r : __builtin_nanf("");
+  return Trig32{fff{x < 0.0f ? -r : r, 0.0f}, x < 0.0f ? -j : j};
+}
+
+// bf16: from 65536 up (and for inf and NaN) the integer Payne-Hanek
+// reduction above, below it the Cody-Waite reduction of f16
 LMH_INLINE bool nbtrig_slow(float x) { return !(fabs_(x) < 65536.0f); }
 LMH_INLINE Trig32 nbtrig_reduce(float x) {
   Trig32 s;
   if (nbtrig_slow(x))
-    s = tanf_slow(x);
+    s = nbtrig_big(x);
   else
     s = hsincos_reduce(x);
   return s;

@@ -309,15 +309,13 @@ struct OpNPow {
 struct OpNAtan2 {
   static __device__ __forceinline__ float f(float y, float x) { return lmh::natan2(y, x); }
 };
-// bf16 trig in the split kernel's interface (Payne-Hanek lanes gathered)
+// bf16 trig: each lane takes the reduction its argument needs; the integer
+// Payne-Hanek reduction is short enough that the plain kernel runs it
+// without gathering those lanes
 #define LMH_NTRIG_OP(NAME, FIN)                                                                  \
   struct NAME {                                                                                \
-    static constexpr bool kSplit = true;                                                       \
+    static constexpr bool kSplit = false;                                                      \
     static __device__ __forceinline__ float f(float x) { return lmh::FIN(x, lmh::nbtrig_reduce(x)); } \
-    static __device__ __forceinline__ bool is_slow(float x) { return lmh::nbtrig_slow(x); }     \
-    static __device__ __forceinline__ lmh::Trig32 fast(float x) { return lmh::hsincos_reduce(x); } \
-    static __device__ __forceinline__ lmh::Trig32 slow(float x) { return lmh::tanf_slow(x); }   \
-    static __device__ __forceinline__ float finish(float x, lmh::Trig32 s) { return lmh::FIN(x, s); } \
   };
 LMH_NTRIG_OP(OpNSin, nsin_fin)
 LMH_NTRIG_OP(OpNCos, ncos_fin)
@@ -334,7 +332,7 @@ struct OpNSinCos {
     lmh::Trig32 s = lmh::hsincos_reduce(x);
     return lmh::SinCos32{s, s};
   }
-  static __device__ __forceinline__ lmh::Trig32 slow(float x) { return lmh::tanf_slow(x); }
+  static __device__ __forceinline__ lmh::Trig32 slow(float x) { return lmh::nbtrig_big(x); }
   static __device__ __forceinline__ lmh::SinCos32 lift(float, lmh::Trig32 s) {
     return lmh::SinCos32{s, s};
   }

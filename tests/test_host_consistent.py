@@ -100,3 +100,18 @@ def test_host_pow_over_the_whole_result_range(dt):
     r = compare(y.astype(np.float64), rn, hi, lo, dt, 1.0)
     assert r["violations"] == 0 and r["special_mismatch"] == 0, (r["max_ulp"], a[r["bad_idx"][:3]],
                                                                  b[r["bad_idx"][:3]])
+
+
+def test_erfc_subnormal_results_rounded_from_the_checked_pair():
+    """erfc on [26.5, 27.3], where the binary64 result falls below 2^-1022:
+    the main path rounds a subnormal result from its pair when the pair's
+    error bound decides the rounding and leaves the rest to the accurate
+    path.  Every subnormal result must be the correctly rounded one (a
+    mis-decided rounding would be one unit off)."""
+    x = np.random.default_rng(71).uniform(26.5, 27.3, 1500)
+    y = L.host_consistent("erfc", x, None, "u10")
+    rn, hi, lo = oracle.evaluate("erfc", "f64", x)
+    sub = np.abs(rn) < 2.0 ** -1022
+    assert sub.sum() > 1300
+    bad = np.nonzero(y != rn)[0]
+    assert bad.size == 0, (x[bad[:3]], y[bad[:3]], rn[bad[:3]])
