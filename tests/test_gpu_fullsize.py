@@ -9,7 +9,7 @@ sampled outputs plus the first and last are checked against the oracle one
 by one (ULP bound, special classes and binary64/binary32 subnormal results
 bit-exact; exact functions bit-exact), and every output of the unary
 functions the oracle's fast stages cover (sin, cos, tan, exp, exp2, log,
-log2, sinh, cosh, tanh) and of fmod is checked as well.
+log2, sinh, cosh, tanh) and of fmod and remainder is checked as well.
 """
 import concurrent.futures as cf
 
@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from tests.exact_ref import fmod as exact_fmod, ieee_remainder
 from tests.gpu_common import check_values, to_device, to_host
 
 pytestmark = pytest.mark.gpu
@@ -69,12 +70,12 @@ def test_full_size_tuned_sampled(workload, fn, variant, dt):
     print("  shape %s: %d checked, max %.3f ulp" % (shape, idx.size, res["max_ulp"]), flush=True)
     # every output: the oracle's fast stage for the unary functions it
     # covers (its undecided inputs through the ball oracle), the host's
-    # exact fmod for fmod
-    if fn in FAST_FNS or fn == "fmod":
+    # exact fmod and the exact array remainder for the exact functions
+    if fn in FAST_FNS or fn in ("fmod", "remainder"):
         y_all = to_host(out)
         torch.cuda.synchronize()
-        if fn == "fmod":
-            want = np.fmod(a, b)
+        if fn in ("fmod", "remainder"):
+            want = exact_fmod(a, b) if fn == "fmod" else ieee_remainder(a, b).astype(a.dtype)
             same = (y_all == want) | (np.isnan(y_all) & np.isnan(want))
             same &= (np.signbit(y_all) == np.signbit(want)) | np.isnan(want)
             assert same.all(), (a[~same][:3], b[~same][:3], y_all[~same][:3])
