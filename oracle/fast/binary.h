@@ -1,0 +1,172 @@
+/* pow and atan2 for the oracle's fast C stages (fast32.c, fast64.c), in
+ * double-double.  TEST INFRASTRUCTURE ONLY, like the rest of oracle/.
+ *
+ * Each core returns 1 with *rn set for the special cases (C99 Annex F:
+ * NaN, infinities, zeros, and the values they fix), else 0 with the result
+ * as the pair v times 2^k.
+ *
+ *  pow(x, z): the Annex F cases first, then |x|^z = e^w with w = z log|x|:
+ *       log|x| = e ln 2 + 2 atanh((m - 1)/(m + 1)) for |x| = m 2^e,
+ *       m in [1/sqrt 2, sqrt 2) (ln 2 in three doubles, the atanh series as
+ *       in log), about 2^-100 relative; w = z log|x| as a pair; e^w =
+ *       e^r 2^j with j = rint(w / ln 2) and r = w - j ln 2 (the Taylor
+ *       series of e^r).  The error of w, at most |w| 2^-100 with |w| < 750
+ *       where the result is neither 0 nor infinite, sets the bound: 2^-86
+ *       relative.  The sign is negative for x < 0 and an odd integer z.
+ *       Beyond the thresholds the caller passes (w above which the format
+ *       overflows, below which it rounds to zero) the result is +-inf or
+ *       +-0.
+ *  atan2(y, x): the Annex F cases first; with a = |y|, b = |x| written
+ *       m 2^e, t = min(a, b) / max(a, b) = (mantissa quotient, a pair)
+ *       2^(difference of exponents); below 2^-62 atan t = t within 2^-124;
+ *       otherwise three halvings atan t = 2 atan(t / (1 + sqrt(1 + t^2)))
+ *       bring t under tan(pi/32) and the series t sum (-t^2)^k/(2k+1),
+ *       k <= 18, ends it (first omitted term below 2^-127 of the sum);
+ *       then pi/2 - atan for a > b, pi - atan for x < 0 and the sign of y,
+ *       all in pairs (pi/2 from three doubles): about 2^-98 relative,
+ *       bound 2^-90. */
+#pragma once
+#include "common.h"
+
+static int is_int_d(double z) { return isfinite(z) && nearbyint(z) == z; }
+static int is_odd_d(double z) { return is_int_d(z) && fabs(z) < 0x1p53 && fmod(z, 2.0) != 0.0; }
+
+/* sqrt of a pair a >= 1: one Newton step on the binary64 square root */
+static dd dd_sqrt(dd a) {
+  double r0 = sqrt(a.hi);
+  dd q = dd_add(a, dd_neg(two_prod(r0, r0)));
+  return dd_add(dd_from(r0), dd_from(q.hi / (2.0 * r0)));
+}
+
+/* log a for a finite a > 0, a != 1, as a pair */
+static dd log_pair(double a) {
+  int e;
+  double m = frexp(a, &e);
+  if (m < 0.70710678118654752) {
+    m *= 2.0;
+    e -= 1;
+  }
+  dd t = dd_div(dd_from(m - 1.0), two_sum(m, 1.0));
+  dd l = atanh2_series(t);
+  dd el = dd_add(two_prod((double)e, LN2_D[0]), two_prod((double)e, LN2_D[1]));
+  el = dd_add(el, dd_from((double)e * LN2_D[2]));
+  return dd_add(el, l);
+}
+
+static int pow_core(double x, double z, double w_over, double w_zero, dd* v, int* k, double* rn) {
+  *k = 0;
+  if (z == 0.0 || x == 1.0) {
+    *rn = 1.0;
+    return 1;
+  }
+  if (isnan(x) || isnan(z)) {
+    *rn = NAN;
+    return 1;
+  }
+  double ax = fabs(x);
+  int odd = is_odd_d(z);
+  if (isinf(z)) {
+    *rn = ax == 1.0 ? 1.0 : ((ax < 1.0) == (z < 0.0) ? INFINITY : 0.0);
+    return 1;
+  }
+  if (x == 0.0) {
+    *rn = z < 0.0 ? (odd ? copysign(INFINITY, x) : INFINITY) : (odd ? x : 0.0);
+    return 1;
+  }
+  if (isinf(x)) {
+    double mag = z < 0.0 ? 0.0 : INFINITY;
+    *rn = (x < 0.0 && odd) ? -mag : mag;
+    return 1;
+  }
+  if (x < 0.0 && !is_int_d(z)) {
+    *rn = NAN;
+    return 1;
+  }
+  double sgn = (x < 0.0 && odd) ? -1.0 : 1.0;
+  dd w = dd_mul_d(log_pair(ax), z);
+  if (w.hi > w_over) {
+    *rn = sgn * INFINITY;
+    return 1;
+  }
+  if (w.hi < w_zero) {
+    *rn = sgn * 0.0;
+    return 1;
+  }
+  double j = nearbyint(w.hi / LN2_D[0]);
+  dd r = dd_add(w, dd_neg(two_prod(j, LN2_D[0])));
+  r = dd_add(r, dd_neg(two_prod(j, LN2_D[1])));
+  r = dd_add(r, dd_from(-j * LN2_D[2]));
+  dd s = exp_series(r);
+  *v = sgn < 0.0 ? dd_neg(s) : s;
+  *k = (int)j;
+  return 0;
+}
+
+/* atan t for a pair 2^-62 <= t <= 1 */
+static dd atan_pair(dd t) {
+  for (int i = 0; i < 3; ++i) {
+    dd s = dd_sqrt(dd_add(dd_from(1.0), dd_mul(t, t)));
+    t = dd_div(t, dd_add(dd_from(1.0), s));
+  }
+  dd z = dd_neg(dd_mul(t, t));
+  dd a = dd_mul(horner(z, INV_ODD, 1, 0, 18, 9), t);
+  a.hi *= 8.0;
+  a.lo *= 8.0;
+  return a;
+}
+
+static int atan2_core(double y, double x, dd* v, int* k, double* rn) {
+  *k = 0;
+  dd pio2 = {PIO2_D[0], PIO2_D[1]};
+  dd pi = {2.0 * PIO2_D[0], 2.0 * PIO2_D[1]};
+  dd pio4 = {0.5 * PIO2_D[0], 0.5 * PIO2_D[1]};
+  if (isnan(x) || isnan(y)) {
+    *rn = NAN;
+    return 1;
+  }
+  int special = 0;
+  dd s = {0.0, 0.0};
+  if (y == 0.0) {
+    if (x > 0.0 || (x == 0.0 && !signbit(x))) {
+      *rn = y;
+      return 1;
+    }
+    s = pi;
+    special = 1;
+  } else if (isinf(y)) {
+    s = isinf(x) ? (x > 0.0 ? pio4 : dd_add(pio2, pio4)) : pio2;
+    special = 1;
+  } else if (x == 0.0) {
+    s = pio2;
+    special = 1;
+  } else if (isinf(x)) {
+    if (x > 0.0) {
+      *rn = copysign(0.0, y);
+      return 1;
+    }
+    s = pi;
+    special = 1;
+  }
+  if (special) {
+    *v = signbit(y) ? dd_neg(s) : s;
+    return 0;
+  }
+  double a = fabs(y), b = fabs(x);
+  int swap = a > b;
+  double n = swap ? b : a, d = swap ? a : b;
+  int en, ed;
+  double mn = frexp(n, &en), md = frexp(d, &ed);
+  dd q = dd_div(dd_from(mn), dd_from(md));
+  int sh = en - ed;
+  if (sh < -62 && !swap && x > 0.0) { /* atan t = t within 2^-124 */
+    *v = y < 0.0 ? dd_neg(q) : q;
+    *k = sh;
+    return 0;
+  }
+  dd t = {ldexp(q.hi, sh), ldexp(q.lo, sh)};
+  dd r = sh < -62 ? t : atan_pair(t);
+  if (swap) r = dd_add(pio2, dd_neg(r));
+  if (x < 0.0) r = dd_add(pi, dd_neg(r));
+  *v = y < 0.0 ? dd_neg(r) : r;
+  return 0;
+}

@@ -37,7 +37,7 @@
  * exact (the exact product's error term by C99 fma(), which -mfma makes the
  * host's fused multiply-add instruction).
  */
-#include "common.h"
+#include "binary.h"
 
 /* |x| = m 2^E (m < 2^24 an integer): 2|x|/pi = q + f with q an integer taken
    modulo 4 and |f| <= 1/2, f as a pair (absolute error below 2^-127) */
@@ -440,15 +440,25 @@ typedef struct {
    correctly rounded results must match bit for bit (NaN as a class). */
 /* one result y of input x into the statistics (the ULP metric of
    tests/ulp.py); returns 1 for an undecided input, 2 for a failure */
+static int check_value(int exact, dd v, float r, double rel, float x, float yi, double bound,
+                       check_stats* st);
+
 static int check_one(int fn, float x, float yi, double bound, check_stats* st) {
   dd v;
   float r;
-  st->n++;
   int exact = value(fn, x, &v, &r);
+  return check_value(exact, v, r, REL, x, yi, bound, st);
+}
+
+/* one result yi against the value v (or the exact r): 0 fine, 1 undecided,
+   2 outside the bound or a special mismatch */
+static int check_value(int exact, dd v, float r, double rel, float x, float yi, double bound,
+                       check_stats* st) {
+  st->n++;
   if (exact) {
     v.hi = (double)r; /* an exact result: the pair is the value itself */
     v.lo = 0.0;
-  } else if (round_f32(v, REL, &r)) {
+  } else if (round_f32(v, rel, &r)) {
     st->undecided++;
     return 1;
   }
@@ -513,6 +523,62 @@ void oracle_fast32_check_x(int fn, const float* x, const float* y, long n, doubl
   long nb = 0, nu = 0;
   for (long i = 0; i < n; ++i) {
     int c = check_one(fn, x[i], y[i], bound, st);
+    if (c == 1 && nu < undec_cap) undec[nu++] = i;
+    if (c == 2 && nb < bad_cap) bad[nb++] = i;
+  }
+}
+
+/* ---- pow and atan2 ----------------------------------------------------------- */
+
+enum { B_POW, B_ATAN2 };
+static const double REL_POW = 0x1p-86, REL_ATAN2 = 0x1p-90;
+
+/* the value for binary32 operands, unscaled (every such result that does
+   not round to 0 or overflow lies in the binary64 normal range) */
+static int value2(int fn, float a, float b, dd* v, float* rn) {
+  int k;
+  double r;
+  int sp = fn == B_POW ? pow_core(a, b, 89.5, -104.5, v, &k, &r) : atan2_core(a, b, v, &k, &r);
+  if (sp) {
+    *rn = (float)r;
+    return 1;
+  }
+  v->hi = ldexp(v->hi, k);
+  v->lo = ldexp(v->lo, k);
+  return 0;
+}
+
+void oracle_fast32_eval2(int fn, const float* a, const float* b, long n, double* hi, double* lo,
+                         float* rn, uint8_t* undecided) {
+  double rel = fn == B_POW ? REL_POW : REL_ATAN2;
+  for (long i = 0; i < n; ++i) {
+    dd v;
+    float r;
+    if (value2(fn, a[i], b[i], &v, &r)) {
+      hi[i] = (double)r;
+      lo[i] = 0.0;
+      rn[i] = r;
+      undecided[i] = 0;
+      continue;
+    }
+    undecided[i] = (uint8_t)round_f32(v, rel, &r);
+    hi[i] = v.hi;
+    lo[i] = v.lo;
+    rn[i] = r;
+  }
+}
+
+void oracle_fast32_check2(int fn, const float* a, const float* b, const float* y, long n,
+                          double bound, check_stats* st, long* bad, long bad_cap, long* undec,
+                          long undec_cap) {
+  memset(st, 0, sizeof(*st));
+  double rel = fn == B_POW ? REL_POW : REL_ATAN2;
+  long nb = 0, nu = 0;
+  for (long i = 0; i < n; ++i) {
+    dd v;
+    float r;
+    int exact = value2(fn, a[i], b[i], &v, &r);
+    int c = check_value(exact, v, r, rel, a[i], y[i], bound, st);
     if (c == 1 && nu < undec_cap) undec[nu++] = i;
     if (c == 2 && nb < bad_cap) bad[nb++] = i;
   }

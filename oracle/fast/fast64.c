@@ -20,7 +20,7 @@
  *  sinh, cosh, tanh: from e^|x| and its reciprocal below |x| = 40, Taylor
  *       below 2^-4 (sinh, tanh), e^|x| / 2 and 1 - 2 e^(-2|x|) above 40.
  */
-#include "common.h"
+#include "binary.h"
 
 /* |x| = m 2^E (m < 2^53 an integer): 2|x|/pi = q + f, q modulo 4, |f| <= 1/2
    as a pair (relative error below 2^-120) */
@@ -350,60 +350,124 @@ typedef struct {
    in binary64 (ulp(v) = 2^(max(floor(log2 |v|), -1022) - 52)); NaN, +-inf,
    +-0 and subnormal correctly rounded results bit for bit (NaN as a class).
    Undecided inputs are listed (their indices) for the ball oracle. */
+/* one result yi against the value v 2^k (or the exact r): 0 fine, 1
+   undecided (the ball oracle must answer), 2 outside the bound or a special
+   mismatch */
+static int check_elem(int exact, dd v, int k, double r, double rel, double yi, double bound,
+                      check64_stats* st, long i) {
+  st->n++;
+  if (exact) {
+    v = dd_from(r);
+    k = 0;
+  } else if (round_f64(v, k, rel, &r)) {
+    st->undecided++;
+    return 1;
+  }
+  int same = (bits64(yi) == bits64(r)) || (isnan(yi) && isnan(r));
+  if (isnan(r) || isinf(r) || r == 0.0 || fabs(r) < 0x1p-1022) {
+    if (!same) {
+      st->special_mismatch++;
+      return 2;
+    }
+    return 0;
+  }
+  /* floor(log2 |value|), the pair scaled by 2^k */
+  int e;
+  frexp(v.hi, &e);
+  int E = e - 1 + k;
+  if (fabs(v.hi) == ldexp(1.0, e - 1) && v.lo != 0.0 && (v.lo < 0) != (v.hi < 0)) E -= 1;
+  if (E < -1022) E = -1022;
+  /* error in ulps, computed in the scaled domain */
+  double err;
+  if (isnan(yi)) {
+    err = INFINITY;
+  } else if (isinf(yi)) {
+    /* 2^1024 against the value, halved to stay finite */
+    double yh = copysign(0x1p1023, yi);
+    err = fabs((ldexp(yh, -k) - 0.5 * v.hi) - 0.5 * v.lo) / ldexp(0.5, E - 52 - k);
+  } else {
+    double ys = ldexp(yi, -k);
+    err = fabs((ys - v.hi) - v.lo) / ldexp(1.0, E - 52 - k);
+  }
+  if (same && err > 0.5) err = 0.5;
+  st->n_reg++;
+  st->sum_ulp += err;
+  if (err > st->max_ulp) {
+    st->max_ulp = err;
+    st->worst = i;
+  }
+  if (err > bound) {
+    st->violations++;
+    return 2;
+  }
+  return 0;
+}
+
+/* results y of inputs x against the oracle, the ULP metric of tests/ulp.py
+   in binary64 (ulp(v) = 2^(max(floor(log2 |v|), -1022) - 52)); NaN, +-inf,
+   +-0 and subnormal correctly rounded results bit for bit (NaN as a class).
+   Undecided inputs are listed (their indices) for the ball oracle. */
 void oracle_fast64_check(int fn, const double* x, const double* y, long n, double bound,
                          check64_stats* st, long* bad, long bad_cap, long* undec, long undec_cap) {
   memset(st, 0, sizeof(*st));
   st->worst = -1;
+  long nb = 0, nu = 0;
   for (long i = 0; i < n; ++i) {
     dd v;
     int k;
-    double r, yi = y[i];
-    st->n++;
+    double r;
     int exact = value64(fn, x[i], &v, &k, &r);
-    if (exact) {
-      v = dd_from(r);
-      k = 0;
-    } else if (round_f64(v, k, REL64, &r)) {
-      if (st->undecided < undec_cap) undec[st->undecided] = i;
-      st->undecided++;
+    int c = check_elem(exact, v, k, r, REL64, y[i], bound, st, i);
+    if (c == 1 && nu < undec_cap) undec[nu++] = i;
+    if (c == 2 && nb < bad_cap) bad[nb++] = i;
+  }
+}
+
+/* ---- pow and atan2 --------------------------------------------------------- */
+
+enum { B_POW, B_ATAN2 };
+static const double REL_POW = 0x1p-86, REL_ATAN2 = 0x1p-90;
+
+static int value64_2(int fn, double a, double b, dd* v, int* k, double* rn) {
+  if (fn == B_POW) return pow_core(a, b, 710.5, -746.5, v, k, rn);
+  return atan2_core(a, b, v, k, rn);
+}
+
+void oracle_fast64_eval2(int fn, const double* a, const double* b, long n, double* hi, double* lo,
+                         double* rn, uint8_t* undecided) {
+  double rel = fn == B_POW ? REL_POW : REL_ATAN2;
+  for (long i = 0; i < n; ++i) {
+    dd v;
+    int k;
+    double r;
+    if (value64_2(fn, a[i], b[i], &v, &k, &r)) {
+      hi[i] = r;
+      lo[i] = 0.0;
+      rn[i] = r;
+      undecided[i] = 0;
       continue;
     }
-    int same = (bits64(yi) == bits64(r)) || (isnan(yi) && isnan(r));
-    if (isnan(r) || isinf(r) || r == 0.0 || fabs(r) < 0x1p-1022) {
-      if (!same) {
-        if (st->special_mismatch + st->violations < bad_cap) bad[st->special_mismatch + st->violations] = i;
-        st->special_mismatch++;
-      }
-      continue;
-    }
-    /* floor(log2 |value|), the pair scaled by 2^k */
-    int e;
-    frexp(v.hi, &e);
-    int E = e - 1 + k;
-    if (fabs(v.hi) == ldexp(1.0, e - 1) && v.lo != 0.0 && (v.lo < 0) != (v.hi < 0)) E -= 1;
-    if (E < -1022) E = -1022;
-    /* error in ulps, computed in the scaled domain */
-    double err;
-    if (isnan(yi)) {
-      err = INFINITY;
-    } else if (isinf(yi)) {
-      /* 2^1024 against the value, halved to stay finite */
-      double yh = copysign(0x1p1023, yi);
-      err = fabs((ldexp(yh, -k) - 0.5 * v.hi) - 0.5 * v.lo) / ldexp(0.5, E - 52 - k);
-    } else {
-      double ys = ldexp(yi, -k);
-      err = fabs((ys - v.hi) - v.lo) / ldexp(1.0, E - 52 - k);
-    }
-    if (same && err > 0.5) err = 0.5;
-    st->n_reg++;
-    st->sum_ulp += err;
-    if (err > st->max_ulp) {
-      st->max_ulp = err;
-      st->worst = i;
-    }
-    if (err > bound) {
-      if (st->special_mismatch + st->violations < bad_cap) bad[st->special_mismatch + st->violations] = i;
-      st->violations++;
-    }
+    undecided[i] = (uint8_t)round_f64(v, k, rel, &r);
+    hi[i] = ldexp(v.hi, k);
+    lo[i] = ldexp(v.lo, k);
+    rn[i] = r;
+  }
+}
+
+void oracle_fast64_check2(int fn, const double* a, const double* b, const double* y, long n,
+                          double bound, check64_stats* st, long* bad, long bad_cap, long* undec,
+                          long undec_cap) {
+  memset(st, 0, sizeof(*st));
+  st->worst = -1;
+  double rel = fn == B_POW ? REL_POW : REL_ATAN2;
+  long nb = 0, nu = 0;
+  for (long i = 0; i < n; ++i) {
+    dd v;
+    int k;
+    double r;
+    int exact = value64_2(fn, a[i], b[i], &v, &k, &r);
+    int c = check_elem(exact, v, k, r, rel, y[i], bound, st, i);
+    if (c == 1 && nu < undec_cap) undec[nu++] = i;
+    if (c == 2 && nb < bad_cap) bad[nb++] = i;
   }
 }

@@ -1,5 +1,5 @@
 """ctypes binding of the oracle's fast binary32 stage (``oracle/fast/fast32.c``)
-for sin, cos, tan, exp, exp2, log, log2, sinh, cosh and tanh over many
+for sin, cos, tan, exp, exp2, log, log2, sinh, cosh, tanh, pow and atan2 over many
 binary32 inputs.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).  The C stage gives a
@@ -19,6 +19,7 @@ SRC = os.path.join(HERE, "fast", "fast32.c")
 LIB = os.path.join(HERE, "liboracle_fast32.so")
 FNS = {"sin": 0, "exp": 1, "log": 2, "cos": 3, "tan": 4, "exp2": 5, "log2": 6, "sinh": 7,
        "cosh": 8, "tanh": 9}
+FNS2 = {"pow": 0, "atan2": 1}          # two operands (oracle/fast/binary.h)
 
 _lib = None
 
@@ -49,7 +50,8 @@ class CheckStats(ctypes.Structure):
 def load():
     global _lib
     if _lib is None:
-        deps = [SRC, os.path.join(HERE, "fast", "common.h"), os.path.join(HERE, "fast", "tables.h")]
+        deps = [SRC, os.path.join(HERE, "fast", "common.h"), os.path.join(HERE, "fast", "binary.h"),
+                os.path.join(HERE, "fast", "tables.h")]
         if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(d) for d in deps):
             build()
         lib = ctypes.CDLL(LIB)
@@ -68,12 +70,19 @@ def load():
         lib.oracle_fast32_check.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, P,
                                             ctypes.c_double, ctypes.POINTER(CheckStats), P,
                                             ctypes.c_long, P, ctypes.c_long]
+        lib.oracle_fast32_eval2.restype = None
+        lib.oracle_fast32_eval2.argtypes = [ctypes.c_int, P, P, ctypes.c_long, P, P, P, P]
+        lib.oracle_fast32_check2.restype = None
+        lib.oracle_fast32_check2.argtypes = [ctypes.c_int, P, P, P, ctypes.c_long, ctypes.c_double,
+                                             ctypes.POINTER(CheckStats), P, ctypes.c_long, P,
+                                             ctypes.c_long]
         _lib = lib
     return _lib
 
 
-def fast_eval(fn, x):
-    """The C stage alone: (rn, hi, lo, undecided) for binary32 inputs x."""
+def fast_eval(fn, x, z=None):
+    """The C stage alone: (rn, hi, lo, undecided) for binary32 inputs x (and
+    second operands z for pow and atan2)."""
     lib = load()
     x = np.ascontiguousarray(x, dtype=np.float32)
     n = x.size
@@ -81,20 +90,27 @@ def fast_eval(fn, x):
     lo = np.empty(n, np.float64)
     rn = np.empty(n, np.float32)
     und = np.empty(n, np.uint8)
-    lib.oracle_fast32_eval(FNS[fn], x.ctypes.data, n, hi.ctypes.data, lo.ctypes.data,
-                           rn.ctypes.data, und.ctypes.data)
+    if fn in FNS2:
+        z = np.ascontiguousarray(z, dtype=np.float32)
+        assert z.size == n
+        lib.oracle_fast32_eval2(FNS2[fn], x.ctypes.data, z.ctypes.data, n, hi.ctypes.data,
+                                lo.ctypes.data, rn.ctypes.data, und.ctypes.data)
+    else:
+        lib.oracle_fast32_eval(FNS[fn], x.ctypes.data, n, hi.ctypes.data, lo.ctypes.data,
+                               rn.ctypes.data, und.ctypes.data)
     return rn, hi, lo, und.astype(bool)
 
 
-def evaluate(fn, x):
-    """(rn, hi, lo) as oracle.evaluate(fn, "f32", x): the C stage, and the ball
-    oracle for the inputs the C stage cannot decide."""
+def evaluate(fn, x, z=None):
+    """(rn, hi, lo) as oracle.evaluate(fn, "f32", x[, z]): the C stage, and
+    the ball oracle for the inputs the C stage cannot decide."""
     from . import evaluate as ball_evaluate
-    rn, hi, lo, und = fast_eval(fn, x)
+    rn, hi, lo, und = fast_eval(fn, x, z)
     rn = rn.astype(np.float64)
     if und.any():
         xs = np.asarray(x, dtype=np.float32)[und].astype(np.float64)
-        r2, h2, l2 = ball_evaluate(fn, "f32", xs)
+        zs = None if z is None else np.asarray(z, dtype=np.float32)[und].astype(np.float64)
+        r2, h2, l2 = ball_evaluate(fn, "f32", xs, zs)
         rn[und], hi[und], lo[und] = r2, h2, l2
     return rn, hi, lo
 
@@ -125,21 +141,27 @@ def check(fn, start, count, y, bound, cap=1 << 12):
     return st, bad[:min(st.special_mismatch + st.violations, cap)], und[:min(st.undecided, cap)]
 
 
-def check_x(fn, x, y, bound, cap=1 << 10):
-    """Results y for arbitrary binary32 inputs x: (stats, failing indices,
-    undecided indices)."""
+def check_x(fn, x, y, bound, cap=1 << 10, z=None):
+    """Results y for arbitrary binary32 inputs x (and second operands z):
+    (stats, failing indices, undecided indices)."""
     lib = load()
     x = np.ascontiguousarray(x, dtype=np.float32)
     y = np.ascontiguousarray(y, dtype=np.float32)
     st = CheckStats()
     bad = np.empty(cap, np.int64)
     und = np.empty(cap, np.int64)
-    lib.oracle_fast32_check_x(FNS[fn], x.ctypes.data, y.ctypes.data, x.size, bound, ctypes.byref(st),
-                              bad.ctypes.data, cap, und.ctypes.data, cap)
+    if fn in FNS2:
+        z = np.ascontiguousarray(z, dtype=np.float32)
+        lib.oracle_fast32_check2(FNS2[fn], x.ctypes.data, z.ctypes.data, y.ctypes.data, x.size,
+                                 bound, ctypes.byref(st), bad.ctypes.data, cap, und.ctypes.data,
+                                 cap)
+    else:
+        lib.oracle_fast32_check_x(FNS[fn], x.ctypes.data, y.ctypes.data, x.size, bound,
+                                  ctypes.byref(st), bad.ctypes.data, cap, und.ctypes.data, cap)
     return st, bad[:min(st.special_mismatch + st.violations, cap)], und[:min(st.undecided, cap)]
 
 
-def check_all(fn, x, y, bound, threads=16, chunk=1 << 20):
+def check_all(fn, x, y, bound, threads=16, chunk=1 << 20, z=None):
     """check_x() over chunks on a thread pool: a dict of totals with failing
     and undecided indices (up to 1024 each)."""
     import concurrent.futures as cf
@@ -148,7 +170,8 @@ def check_all(fn, x, y, bound, threads=16, chunk=1 << 20):
                sum_ulp=0.0)
     bad, und = [], []
     with cf.ThreadPoolExecutor(threads) as ex:
-        futs = [(s, ex.submit(check_x, fn, x[s:s + chunk], y[s:s + chunk], bound))
+        futs = [(s, ex.submit(check_x, fn, x[s:s + chunk], y[s:s + chunk], bound,
+                              z=None if z is None else z[s:s + chunk]))
                 for s in range(0, x.size, chunk)]
         for s, f in futs:
             st, b, u = f.result()

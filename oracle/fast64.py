@@ -1,5 +1,5 @@
 """ctypes binding of the oracle's fast binary64 stage (``oracle/fast/fast64.c``)
-for sin, cos, tan, exp, exp2, log, log2, sinh, cosh and tanh.
+for sin, cos, tan, exp, exp2, log, log2, sinh, cosh, tanh, pow and atan2.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).  The C stage gives the
 value within 2^-90 relative and the correctly rounded binary64 result where
@@ -16,10 +16,12 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "fast", "fast64.c")
-DEPS = [SRC, os.path.join(HERE, "fast", "common.h"), os.path.join(HERE, "fast", "tables.h")]
+DEPS = [SRC, os.path.join(HERE, "fast", "common.h"), os.path.join(HERE, "fast", "binary.h"),
+        os.path.join(HERE, "fast", "tables.h")]
 LIB = os.path.join(HERE, "liboracle_fast64.so")
 FNS = {"sin": 0, "exp": 1, "log": 2, "cos": 3, "tan": 4, "exp2": 5, "log2": 6, "sinh": 7,
        "cosh": 8, "tanh": 9}
+FNS2 = {"pow": 0, "atan2": 1}          # two operands (oracle/fast/binary.h)
 
 _lib = None
 
@@ -55,48 +57,68 @@ def load():
         lib.oracle_fast64_check.argtypes = [ctypes.c_int, P, P, ctypes.c_long, ctypes.c_double,
                                             ctypes.POINTER(CheckStats), P, ctypes.c_long, P,
                                             ctypes.c_long]
+        lib.oracle_fast64_eval2.restype = None
+        lib.oracle_fast64_eval2.argtypes = [ctypes.c_int, P, P, ctypes.c_long, P, P, P, P]
+        lib.oracle_fast64_check2.restype = None
+        lib.oracle_fast64_check2.argtypes = [ctypes.c_int, P, P, P, ctypes.c_long, ctypes.c_double,
+                                             ctypes.POINTER(CheckStats), P, ctypes.c_long, P,
+                                             ctypes.c_long]
         _lib = lib
     return _lib
 
 
-def fast_eval(fn, x):
-    """The C stage alone: (rn, hi, lo, undecided) for binary64 inputs x."""
+def fast_eval(fn, x, z=None):
+    """The C stage alone: (rn, hi, lo, undecided) for binary64 inputs x (and
+    second operands z for pow and atan2)."""
     lib = load()
     x = np.ascontiguousarray(x, dtype=np.float64)
     n = x.size
     hi, lo, rn = (np.empty(n, np.float64) for _ in range(3))
     und = np.empty(n, np.uint8)
-    lib.oracle_fast64_eval(FNS[fn], x.ctypes.data, n, hi.ctypes.data, lo.ctypes.data,
-                           rn.ctypes.data, und.ctypes.data)
+    if fn in FNS2:
+        z = np.ascontiguousarray(z, dtype=np.float64)
+        assert z.size == n
+        lib.oracle_fast64_eval2(FNS2[fn], x.ctypes.data, z.ctypes.data, n, hi.ctypes.data,
+                                lo.ctypes.data, rn.ctypes.data, und.ctypes.data)
+    else:
+        lib.oracle_fast64_eval(FNS[fn], x.ctypes.data, n, hi.ctypes.data, lo.ctypes.data,
+                               rn.ctypes.data, und.ctypes.data)
     return rn, hi, lo, und.astype(bool)
 
 
-def evaluate(fn, x):
-    """(rn, hi, lo) as oracle.evaluate(fn, "f64", x), undecided inputs by the
-    ball oracle."""
+def evaluate(fn, x, z=None):
+    """(rn, hi, lo) as oracle.evaluate(fn, "f64", x[, z]), undecided inputs
+    by the ball oracle."""
     from . import evaluate as ball_evaluate
-    rn, hi, lo, und = fast_eval(fn, x)
+    rn, hi, lo, und = fast_eval(fn, x, z)
     if und.any():
-        r2, h2, l2 = ball_evaluate(fn, "f64", np.asarray(x, np.float64)[und])
+        zz = None if z is None else np.asarray(z, np.float64)[und]
+        r2, h2, l2 = ball_evaluate(fn, "f64", np.asarray(x, np.float64)[und], zz)
         rn[und], hi[und], lo[und] = r2, h2, l2
     return rn, hi, lo
 
 
-def check(fn, x, y, bound, cap=1 << 10):
-    """Results y for inputs x against the C stage (tests/ulp.py's metric):
-    (stats, failing indices, undecided indices)."""
+def check(fn, x, y, bound, cap=1 << 10, z=None):
+    """Results y for inputs x (and second operands z) against the C stage
+    (tests/ulp.py's metric): (stats, failing indices, undecided indices)."""
     lib = load()
     x = np.ascontiguousarray(x, dtype=np.float64)
     y = np.ascontiguousarray(y, dtype=np.float64)
     st = CheckStats()
     bad = np.empty(cap, np.int64)
     und = np.empty(cap, np.int64)
-    lib.oracle_fast64_check(FNS[fn], x.ctypes.data, y.ctypes.data, x.size, bound, ctypes.byref(st),
-                            bad.ctypes.data, cap, und.ctypes.data, cap)
+    if fn in FNS2:
+        z = np.ascontiguousarray(z, dtype=np.float64)
+        lib.oracle_fast64_check2(FNS2[fn], x.ctypes.data, z.ctypes.data, y.ctypes.data, x.size,
+                                 bound, ctypes.byref(st), bad.ctypes.data, cap, und.ctypes.data,
+                                 cap)
+    else:
+        lib.oracle_fast64_check(FNS[fn], x.ctypes.data, y.ctypes.data, x.size, bound,
+                                ctypes.byref(st), bad.ctypes.data, cap, und.ctypes.data, cap)
     return st, bad[:min(st.special_mismatch + st.violations, cap)], und[:min(st.undecided, cap)]
 
 
-def check_all(fn, x, y, bound, threads=16, chunk=1 << 20):
+def check_all(fn, x, y, bound, threads=16, chunk=1 << 20, z=None):
     """check() over chunks on a thread pool; returns a dict of totals with
     the failing and undecided indices (up to 1024 each)."""
     load()
@@ -104,7 +126,8 @@ def check_all(fn, x, y, bound, threads=16, chunk=1 << 20):
                sum_ulp=0.0)
     bad, und = [], []
     with cf.ThreadPoolExecutor(threads) as ex:
-        futs = [(s, ex.submit(check, fn, x[s:s + chunk], y[s:s + chunk], bound))
+        futs = [(s, ex.submit(check, fn, x[s:s + chunk], y[s:s + chunk], bound,
+                              z=None if z is None else z[s:s + chunk]))
                 for s in range(0, x.size, chunk)]
         for s, f in futs:
             st, b, u = f.result()

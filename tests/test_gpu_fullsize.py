@@ -7,9 +7,11 @@ elements) runs on its full-size input after the launch-shape tuner has
 picked its shape on those buffers, exactly as the benchmark does; 2^16
 sampled outputs plus the first and last are checked against the oracle one
 by one (ULP bound, special classes and binary64/binary32 subnormal results
-bit-exact; exact functions bit-exact), and every output of the unary
-functions the oracle's fast stages cover (sin, cos, tan, exp, exp2, log,
-log2, sinh, cosh, tanh) and of fmod and remainder is checked as well.
+bit-exact; exact functions bit-exact), and then every output of every
+kernel: through the oracle's fast stages (sin, cos, tan, exp, exp2, log,
+log2, sinh, cosh, tanh, pow, atan2; the inputs they cannot decide through
+the ball oracle), and bit-exact against the host's fmod and the exact
+array remainder.
 """
 import concurrent.futures as cf
 
@@ -28,7 +30,7 @@ from oracle import fast32, fast64  # noqa: E402
 
 N = 1 << 26
 SAMPLES = 1 << 16
-FAST_FNS = set(fast32.FNS)
+FAST_FNS = set(fast32.FNS) | set(fast32.FNS2)
 STEP = [("sin", "u10"), ("sin", "u35"), ("cos", "u10"), ("cos", "u35"), ("tan", "u10"),
         ("tan", "u35"), ("exp", "u10"), ("exp2", "u10"), ("log", "u10"), ("log2", "u10"),
         ("pow", "u10"), ("atan2", "u10"), ("sinh", "u10"), ("cosh", "u10"), ("tanh", "u10")]
@@ -83,11 +85,12 @@ def test_full_size_tuned_sampled(workload, fn, variant, dt):
             return
         fast = fast64 if dt == "f64" else fast32
         bound = 1.0 if variant == "u10" else 3.5
-        tot = fast.check_all(fn, a, y_all, bound)
+        tot = fast.check_all(fn, a, y_all, bound, z=b)
         if tot["undecided"]:
             u = tot["undecided_idx"]
             assert tot["undecided"] == u.size, "more undecided inputs than listed"
-            check_values(fn, variant, dt, a[u], None, y_all[u], label="full size, undecided")
+            check_values(fn, variant, dt, a[u], None if b is None else b[u], y_all[u],
+                         label="full size, undecided")
         assert tot["violations"] == 0 and tot["special_mismatch"] == 0, \
             (fn, variant, dt, a[tot["bad"][:4]], y_all[tot["bad"][:4]])
         print("  all %d outputs: max %.4f ulp, mean %.4f, %d by the ball oracle"

@@ -199,3 +199,123 @@ def test_fast64_check_metric_on_known_answers():
     y[i] = np.nan
     tot = fast64.check_all("exp", x, y, 1.0, threads=2, chunk=1 << 12)
     assert tot["violations"] == 1 and tot["bad"][0] == i
+
+
+# ---- pow and atan2 in the binary64 stage (oracle/fast/binary.h) ------------
+
+BIN_BOUND = {"pow": 2.0 ** -86, "atan2": 2.0 ** -90}
+
+
+def _inputs64_2(fn, n=600, seed=9):
+    rng = np.random.default_rng(seed + len(fn))
+    sp = W.specials("f64")
+    a = [W.mixture(fn, "f64", n, 11), np.repeat(sp, sp.size)]
+    b = [W.mixture(fn, "f64", n, 12), np.tile(sp, sp.size)]
+    if fn == "pow":
+        x = 1.0 + rng.uniform(-1e-6, 1e-6, 150)                  # near 1, large exponents
+        a += [x, np.exp(rng.uniform(-5, 5, 300))]
+        w = rng.uniform(-746.0, 710.0, 300)                       # every result range, subnormals too
+        b += [rng.uniform(-1e8, 1e8, 150), w / np.log(a[-1])]
+        m = rng.integers(1, 40, 150).astype(np.float64)           # exact results and negative bases
+        k = rng.integers(-30, 30, 150).astype(np.float64)
+        a += [m, -m, np.full(40, -1.0), 2.0 ** rng.integers(-1074, 1023, 40).astype(np.float64)]
+        b += [k, k, rng.integers(-2 ** 60, 2 ** 60, 40).astype(np.float64),
+              rng.uniform(-3, 3, 40)]
+    else:
+        y = rng.standard_normal(300) * 10.0 ** rng.uniform(-300, 300, 300)
+        x = rng.standard_normal(300) * 10.0 ** rng.uniform(-300, 300, 300)
+        near = y * (1 + rng.uniform(-1e-12, 1e-12, 300))          # |y| close to |x|
+        sub = rng.integers(1, 1 << 40, 100).astype(np.float64) * 5e-324
+        a += [y, near, sub, -sub, np.full(100, 1e-300)]
+        b += [x, y * np.sign(rng.standard_normal(300)), rng.uniform(1, 1e5, 100),
+              -rng.uniform(1, 1e5, 100), rng.uniform(1e10, 1e300, 100)]
+    return np.concatenate(a), np.concatenate(b)
+
+
+def _mp2(fn, a, b):
+    if fn == "atan2":
+        return mp.atan2(mp.mpf(float(a)), mp.mpf(float(b)))
+    return mp.power(mp.mpf(float(a)), mp.mpf(float(b)))
+
+
+@pytest.mark.parametrize("fn", ["pow", "atan2"])
+def test_fast64_binary_pair_within_claimed_bound_of_mpmath(fn):
+    a, b = _inputs64_2(fn, n=100)
+    rn, hi, lo, und = fast64.fast_eval(fn, a, b)
+    mp.mp.prec = 300
+    worst = mp.mpf(0)
+    checked = 0
+    for ai, bi, h, l, r in zip(a, b, hi, lo, rn):
+        if not (np.isfinite(h) and np.isfinite(r)) or h == 0 or r == 0 or ai == 0 or bi == 0:
+            continue                                              # signed zeros: see the next test
+        exact = _mp2(fn, ai, bi)
+        if exact == 0 or abs(exact) > mp.mpf(2) ** 1023 or abs(exact) < mp.mpf(2) ** -960:
+            continue
+        if l == 0 and mp.mpf(float(h)) == exact:
+            continue                                              # exact special value
+        worst = max(worst, abs((mp.mpf(float(h)) + mp.mpf(float(l))) - exact) / abs(exact))
+        checked += 1
+    assert checked > 500
+    assert worst <= BIN_BOUND[fn], (fn, float(mp.log(worst, 2)))
+
+
+@pytest.mark.parametrize("fn", ["pow", "atan2"])
+def test_fast64_binary_rounded_results_match_the_ball_oracle(fn):
+    a, b = _inputs64_2(fn)
+    rn, hi, lo = fast64.evaluate(fn, a, b)
+    rb = oracle.evaluate(fn, "f64", a, b)[0]
+    same = (rn == rb) | (np.isnan(rn) & np.isnan(rb))
+    same &= (np.signbit(rn) == np.signbit(rb)) | np.isnan(rb)
+    assert same.all(), (a[~same][:5], b[~same][:5], rn[~same][:5], rb[~same][:5])
+
+
+def _inputs32_2(fn, n=3000, seed=21):
+    rng = np.random.default_rng(seed + len(fn))
+    sp = W.specials("f32")
+    a = [W.mixture(fn, "f32", n, 13), np.repeat(sp, sp.size)]
+    b = [W.mixture(fn, "f32", n, 14), np.tile(sp, sp.size)]
+    if fn == "pow":
+        x = np.exp(rng.uniform(-5, 5, 1000)).astype(np.float32)
+        w = rng.uniform(-104.0, 89.0, 1000)                       # every result range, subnormals too
+        a += [x, rng.integers(1, 40, 300).astype(np.float32)]
+        b += [(w / np.log(x.astype(np.float64))).astype(np.float32),
+              rng.integers(-30, 30, 300).astype(np.float32)]
+        a += [-a[-1]]
+        b += [b[-1]]
+    else:
+        a += [(rng.standard_normal(1000) * 10.0 ** rng.uniform(-38, 38, 1000)).astype(np.float32),
+              (rng.integers(1, 1 << 20, 300) * 2.0 ** -149).astype(np.float32)]
+        b += [(rng.standard_normal(1000) * 10.0 ** rng.uniform(-38, 38, 1000)).astype(np.float32),
+              rng.uniform(1, 1e5, 300).astype(np.float32)]
+    return np.concatenate(a).astype(np.float32), np.concatenate(b).astype(np.float32)
+
+
+@pytest.mark.parametrize("fn", ["pow", "atan2"])
+def test_fast32_binary_rounded_results_match_the_ball_oracle(fn):
+    a, b = _inputs32_2(fn)
+    rn = fast32.evaluate(fn, a, b)[0]
+    rb = oracle.evaluate(fn, "f32", a.astype(np.float64), b.astype(np.float64))[0]
+    same = (rn == rb) | (np.isnan(rn) & np.isnan(rb))
+    same &= (np.signbit(rn) == np.signbit(rb)) | np.isnan(rb)
+    assert same.all(), (a[~same][:5], b[~same][:5], rn[~same][:5], rb[~same][:5])
+
+
+@pytest.mark.parametrize("fn", ["pow", "atan2"])
+def test_binary_check_metric_on_known_answers(fn):
+    """check_all over correctly rounded results, one ulp off, and a NaN."""
+    for dt, fast in (("f64", fast64), ("f32", fast32)):
+        a = W.mixture(fn, dt, 1 << 13, 31)
+        b = W.mixture(fn, dt, 1 << 13, 32)
+        rn = fast.evaluate(fn, a, b)[0].astype(a.dtype)
+        tot = fast.check_all(fn, a, rn, 1.0, threads=2, chunk=1 << 11, z=b)
+        assert tot["violations"] == 0 and tot["special_mismatch"] == 0 and tot["max_ulp"] <= 0.5
+        tiny = 2.0 ** (-1022 if dt == "f64" else -126)
+        ok = np.isfinite(rn) & (np.abs(rn) >= tiny) & (np.frexp(rn)[0] != 0.5)
+        up = np.where(ok, np.nextafter(rn, np.asarray(np.inf, rn.dtype)), rn)
+        tot = fast.check_all(fn, a, up, 1.0, threads=2, chunk=1 << 11, z=b)
+        assert 0.5 < tot["max_ulp"] < 1.5 and tot["special_mismatch"] == 0, (dt, tot["max_ulp"])
+        y = rn.copy()
+        i = int(np.nonzero(ok)[0][5])
+        y[i] = np.nan
+        tot = fast.check_all(fn, a, y, 1.0, threads=2, chunk=1 << 11, z=b)
+        assert tot["violations"] == 1 and tot["bad"][0] == i
