@@ -78,7 +78,7 @@ def parse():
                    help="skip the bf16/f16/via-f64, batched and autograd measurements")
     p.add_argument("--narrow-n", type=int, default=1 << 28,
                    help="elements per bf16/f16 function")
-    p.add_argument("--out", default=os.path.join("gpurun_out", "bench_full.json"),
+    p.add_argument("--out", default=os.path.join("bench_results", "bench_full.json"),
                    help="file for the full result (every extra); '' to skip")
     return p.parse_args()
 
