@@ -170,3 +170,77 @@ static int atan2_core(double y, double x, dd* v, int* k, double* rn) {
   *v = y < 0.0 ? dd_neg(r) : r;
   return 0;
 }
+
+/* asin, acos and atan for the fast stages: atan x = atan2(x, 1); asin and
+ * acos through s = sqrt((1 - |x|)(1 + |x|)) as a pair and the atan of the
+ * smaller-to-larger quotient of (|x|, s), as in atan2 (asin x = atan2(x, s),
+ * acos x = atan2(s, x)); below |x| = 2^-30, asin x = x + x^3/6 and acos x =
+ * pi/2 - x - x^3/6 (the next terms are under 2^-120 relative).  Bound
+ * 2^-90 relative, the same as atan2's. */
+
+/* atan2 of two pairs a, b >= 0 with max(a, b) > 0 */
+static dd atan2_pos(dd a, dd b) {
+  dd pio2 = {PIO2_D[0], PIO2_D[1]};
+  int swap = a.hi > b.hi;
+  dd n = swap ? b : a, d = swap ? a : b;
+  dd t = dd_div(n, d);
+  dd r = t.hi < 0x1p-62 ? t : atan_pair(t);
+  return swap ? dd_add(pio2, dd_neg(r)) : r;
+}
+
+/* sqrt((1 - a)(1 + a)) for 0 <= a < 1, as a pair */
+static dd cos_of_asin(double a) {
+  dd p = dd_mul(two_sum(1.0, -a), two_sum(1.0, a));
+  return dd_sqrt(p);
+}
+
+static int asin_core(double x, dd* v, int* k, double* rn) {
+  *k = 0;
+  double a = fabs(x);
+  if (isnan(x) || a > 1.0) {
+    *rn = NAN;
+    return 1;
+  }
+  if (x == 0.0) {
+    *rn = x;
+    return 1;
+  }
+  dd r;
+  if (a == 1.0) {
+    r = (dd){PIO2_D[0], PIO2_D[1]};
+  } else if (a < 0x1p-30) {
+    r = fast_two_sum(a, a * a * a / 6.0);
+  } else {
+    r = atan2_pos(dd_from(a), cos_of_asin(a));
+  }
+  *v = x < 0.0 ? dd_neg(r) : r;
+  return 0;
+}
+
+static int acos_core(double x, dd* v, int* k, double* rn) {
+  *k = 0;
+  double a = fabs(x);
+  dd pio2 = {PIO2_D[0], PIO2_D[1]};
+  dd pi = {2.0 * PIO2_D[0], 2.0 * PIO2_D[1]};
+  if (isnan(x) || a > 1.0) {
+    *rn = NAN;
+    return 1;
+  }
+  if (x == 1.0) {
+    *rn = 0.0;
+    return 1;
+  }
+  if (x == -1.0) {
+    *v = pi;
+    return 0;
+  }
+  if (a < 0x1p-30) {
+    *v = dd_add(pio2, dd_neg(fast_two_sum(x, x * x * x / 6.0)));
+    return 0;
+  }
+  dd r = atan2_pos(cos_of_asin(a), dd_from(a));
+  *v = x < 0.0 ? dd_add(pi, dd_neg(r)) : r;
+  return 0;
+}
+
+static int atan_core(double x, dd* v, int* k, double* rn) { return atan2_core(x, 1.0, v, k, rn); }

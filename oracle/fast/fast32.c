@@ -320,10 +320,29 @@ static int round_f32(dd v, double rel, float* out) {
 
 /* ---- exported entry points ---------------------------------------------- */
 
-enum { FN_SIN, FN_EXP, FN_LOG, FN_COS, FN_TAN, FN_EXP2, FN_LOG2, FN_SINH, FN_COSH, FN_TANH };
+enum { FN_SIN, FN_EXP, FN_LOG, FN_COS, FN_TAN, FN_EXP2, FN_LOG2, FN_SINH, FN_COSH, FN_TANH,
+       FN_ASIN, FN_ACOS, FN_ATAN };
+
+/* the inverse trig cores of binary.h for a binary32 argument, unscaled */
+static int inv_value(int fn, float x, dd* v, float* rn) {
+  int k;
+  double r;
+  int sp = fn == FN_ASIN ? asin_core(x, v, &k, &r)
+                         : (fn == FN_ACOS ? acos_core(x, v, &k, &r) : atan_core(x, v, &k, &r));
+  if (sp) {
+    *rn = (float)r;
+    return 1;
+  }
+  v->hi = ldexp(v->hi, k);
+  v->lo = ldexp(v->lo, k);
+  return 0;
+}
 
 static int value(int fn, float x, dd* v, float* rn) {
   switch (fn) {
+    case FN_ASIN:
+    case FN_ACOS:
+    case FN_ATAN: return inv_value(fn, x, v, rn);
     case FN_SIN: return trig_value(x, 0, v, rn);
     case FN_COS: return trig_value(x, 1, v, rn);
     case FN_TAN: return trig_value(x, 2, v, rn);
@@ -384,6 +403,9 @@ static double libm_double(int fn, double d) {
     case FN_LOG2: return log2(d);
     case FN_SINH: return sinh(d);
     case FN_COSH: return cosh(d);
+    case FN_ASIN: return asin(d);
+    case FN_ACOS: return acos(d);
+    case FN_ATAN: return atan(d);
     default: return tanh(d);
   }
 }

@@ -255,10 +255,14 @@ static int hyp64(double x, int kind, dd* v, int* k, double* rn) {
   return 0;
 }
 
-enum { G_SIN, G_EXP, G_LOG, G_COS, G_TAN, G_EXP2, G_LOG2, G_SINH, G_COSH, G_TANH };
+enum { G_SIN, G_EXP, G_LOG, G_COS, G_TAN, G_EXP2, G_LOG2, G_SINH, G_COSH, G_TANH, G_ASIN,
+       G_ACOS, G_ATAN };
 
 static int value64(int fn, double x, dd* v, int* k, double* rn) {
   switch (fn) {
+    case G_ASIN: return asin_core(x, v, k, rn);
+    case G_ACOS: return acos_core(x, v, k, rn);
+    case G_ATAN: return atan_core(x, v, k, rn);
     case G_SIN: return trig64(x, 0, v, k, rn);
     case G_COS: return trig64(x, 1, v, k, rn);
     case G_TAN: return trig64(x, 2, v, k, rn);

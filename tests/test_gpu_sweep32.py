@@ -1,5 +1,5 @@
-"""The GPU binary32 sin, cos, tan, exp, exp2, log, log2, sinh, cosh and
-tanh against the oracle's fast stage on 8 stretches of 2^20 consecutive bit
+"""The GPU binary32 sin, cos, tan, exp, exp2, log, log2, sinh, cosh, tanh,
+asin, acos and atan against the oracle's fast stage on 8 stretches of 2^20 consecutive bit
 patterns spread over all 2^32 (the full sweep over every pattern is
 tests/sweep32.py, run by hand): every result within its bound, NaN, inf,
 zero and subnormal results bit-exact."""
@@ -24,7 +24,8 @@ def _gpu():
 
 
 KINDS = [(f, "u10") for f in ("sin", "cos", "tan", "exp", "exp2", "log", "log2", "sinh", "cosh",
-                               "tanh")] + [(f, "u35") for f in ("sin", "cos", "tan")]
+                               "tanh", "asin", "acos", "atan")]
+KINDS += [(f, "u35") for f in ("sin", "cos", "tan", "asin", "acos", "atan")]
 
 
 @pytest.mark.parametrize("fn,variant", KINDS)

@@ -319,3 +319,68 @@ def test_binary_check_metric_on_known_answers(fn):
         y[i] = np.nan
         tot = fast.check_all(fn, a, y, 1.0, threads=2, chunk=1 << 11, z=b)
         assert tot["violations"] == 1 and tot["bad"][0] == i
+
+
+# ---- asin, acos and atan in both stages (oracle/fast/binary.h) ---------------
+
+INV = {"asin": mp.asin, "acos": mp.acos, "atan": mp.atan}
+
+
+def _inputs_inv(fn, dt, n=400, seed=41):
+    rng = np.random.default_rng(seed + len(fn) + len(dt))
+    npdt = np.float64 if dt == "f64" else np.float32
+    near1 = 1 - 10.0 ** -rng.uniform(0, 15 if dt == "f64" else 7, n // 4)
+    parts = [W.function_mixture(fn, dt, n, 43), W.specials(dt), rng.uniform(-1, 1, n),
+             near1, -near1, 10.0 ** -rng.uniform(0, 300 if dt == "f64" else 44, n // 4),
+             np.array([1.0, -1.0, 0.5, -0.5, 2.0 ** -30, 2.0 ** -31, 0.9999999])]
+    if fn == "atan":
+        parts += [np.sign(rng.standard_normal(n)) * 10.0 ** rng.uniform(-300, 300, n)]
+    return np.concatenate(parts).astype(npdt)
+
+
+@pytest.mark.parametrize("fn", list(INV))
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_inverse_trig_pair_within_claimed_bound_of_mpmath(fn, dt):
+    fast = fast64 if dt == "f64" else fast32
+    x = _inputs_inv(fn, dt, n=150)
+    rn, hi, lo, und = fast.fast_eval(fn, x)
+    mp.mp.prec = 300
+    worst = mp.mpf(0)
+    checked = 0
+    for xi, h, l in zip(x, hi, lo):
+        if not (np.isfinite(h) and np.isfinite(xi)) or h == 0 or abs(xi) > 1 and fn != "atan":
+            continue
+        exact = INV[fn](mp.mpf(float(xi)))
+        if exact == 0 or abs(exact) < mp.mpf(2) ** -960:
+            continue
+        worst = max(worst, abs((mp.mpf(float(h)) + mp.mpf(float(l))) - exact) / abs(exact))
+        checked += 1
+    assert checked > 300
+    assert worst <= mp.mpf(2) ** -90, (fn, dt, float(mp.log(worst, 2)))
+
+
+@pytest.mark.parametrize("fn", list(INV))
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_inverse_trig_rounded_results_match_the_ball_oracle(fn, dt):
+    fast = fast64 if dt == "f64" else fast32
+    x = _inputs_inv(fn, dt)
+    rn = fast.evaluate(fn, x)[0].astype(np.float64)
+    rb = oracle.evaluate(fn, dt, x.astype(np.float64))[0]
+    same = (rn == rb) | (np.isnan(rn) & np.isnan(rb))
+    same &= (np.signbit(rn) == np.signbit(rb)) | np.isnan(rb)
+    assert same.all(), (x[~same][:5], rn[~same][:5], rb[~same][:5])
+
+
+@pytest.mark.parametrize("fn,start", [("asin", 0x3f000000), ("asin", 0x3f7f0000),
+                                      ("acos", 0x3e800000), ("acos", 0xbf7f0000),
+                                      ("atan", 0x3f700000), ("atan", 0x4b000000)])
+def test_inverse_trig_sweep_against_libm_double_rounded(fn, start):
+    st, differ, und = fast32.sweep_libm(fn, start, 1 << 18)
+    assert st.n == 1 << 18
+    assert st.differ == st.differ_explained, (st.differ, st.differ_explained)
+    if differ.size:
+        x = differ[:64].view(np.float32)
+        rb = oracle.evaluate(fn, "f32", x.astype(np.float64))[0]
+        rf = fast32.fast_eval(fn, x)[0]
+        assert np.array_equal(rb, rf.astype(np.float64))
+    assert st.undecided == und.size
