@@ -53,6 +53,17 @@ static dd log_pair(double a) {
   return dd_add(el, l);
 }
 
+/* e^w for a pair |w| < 750 as v 2^k: j = rint(w / ln 2), r = w - j ln 2 (ln 2
+   in three doubles), the Taylor series of e^r */
+static void exp_of_pair(dd w, dd* v, int* k) {
+  double j = nearbyint(w.hi / LN2_D[0]);
+  dd r = dd_add(w, dd_neg(two_prod(j, LN2_D[0])));
+  r = dd_add(r, dd_neg(two_prod(j, LN2_D[1])));
+  r = dd_add(r, dd_from(-j * LN2_D[2]));
+  *v = exp_series(r);
+  *k = (int)j;
+}
+
 static int pow_core(double x, double z, double w_over, double w_zero, dd* v, int* k, double* rn) {
   *k = 0;
   if (z == 0.0 || x == 1.0) {
@@ -92,13 +103,9 @@ static int pow_core(double x, double z, double w_over, double w_zero, dd* v, int
     *rn = sgn * 0.0;
     return 1;
   }
-  double j = nearbyint(w.hi / LN2_D[0]);
-  dd r = dd_add(w, dd_neg(two_prod(j, LN2_D[0])));
-  r = dd_add(r, dd_neg(two_prod(j, LN2_D[1])));
-  r = dd_add(r, dd_from(-j * LN2_D[2]));
-  dd s = exp_series(r);
+  dd s;
+  exp_of_pair(w, &s, k);
   *v = sgn < 0.0 ? dd_neg(s) : s;
-  *k = (int)j;
   return 0;
 }
 
@@ -244,3 +251,159 @@ static int acos_core(double x, dd* v, int* k, double* rn) {
 }
 
 static int atan_core(double x, dd* v, int* k, double* rn) { return atan2_core(x, 1.0, v, k, rn); }
+
+
+/* log10, log1p, exp10, expm1 and cbrt for the fast stages (bound 2^-90):
+ *  log10 x = log x / ln 10 (1/ln 10 as a pair from log_pair(10));
+ *  log1p x = x - x^2/2 + x^3/3 below |x| = 2^-40, 2 atanh(x / (2 + x))
+ *       for -0.29 < x < 0.41 (the quotient as a pair, within 0.171), else
+ *       log(1 + x) with 1 + x an exact pair (log of a pair: log of its head
+ *       plus lo/hi);
+ *  exp10 x = e^(x ln 10) (ln 10 as a pair), as pow's exponential;
+ *  expm1 x = x sum x^n/(n+1)! for |x| < 0.3 (22 terms), else e^x - 1 with
+ *       the 1 subtracted from the scaled pair;
+ *  cbrt x: |x| = a 2^(3q) with a in [0.5, 4), one Newton step in pairs from
+ *       the host's cbrt of a (error squared: about 2^-103), times 2^q.
+ * Beyond the caller's thresholds (w above which the format overflows, below
+ * which e^w rounds to zero) exp10 and expm1 give inf, 0 or -1. */
+static dd LN10_P, INV_LN10_P;
+
+__attribute__((constructor)) static void init_ln10(void) {
+  LN10_P = log_pair(10.0);
+  INV_LN10_P = dd_div(dd_from(1.0), LN10_P);
+}
+
+static dd log_of_pair(dd a) {
+  dd l = a.hi == 1.0 ? dd_from(0.0) : log_pair(a.hi);
+  return dd_add(l, dd_from(a.lo / a.hi));
+}
+
+static int log_specials(double x, double* rn) {
+  if (isnan(x)) {
+    *rn = x;
+    return 1;
+  }
+  if (x < 0.0) {
+    *rn = NAN;
+    return 1;
+  }
+  if (x == 0.0) {
+    *rn = -INFINITY;
+    return 1;
+  }
+  if (isinf(x)) {
+    *rn = x;
+    return 1;
+  }
+  return 0;
+}
+
+static int log10_core(double x, dd* v, int* k, double* rn) {
+  *k = 0;
+  if (log_specials(x, rn)) return 1;
+  if (x == 1.0) {
+    *rn = 0.0;
+    return 1;
+  }
+  *v = dd_mul(log_pair(x), INV_LN10_P);
+  return 0;
+}
+
+static int log1p_core(double x, dd* v, int* k, double* rn) {
+  *k = 0;
+  if (isnan(x) || x < -1.0) {
+    *rn = NAN;
+    return 1;
+  }
+  if (x == -1.0) {
+    *rn = -INFINITY;
+    return 1;
+  }
+  if (x == 0.0 || isinf(x)) {
+    *rn = x;
+    return 1;
+  }
+  if (fabs(x) < 0x1p-40) {
+    double t = x * x;
+    *v = fast_two_sum(x, t * (x / 3.0 - 0.5));
+    return 0;
+  }
+  if (x > -0.29 && x < 0.41) { /* 2 atanh(x / (2 + x)), the quotient within 0.171 */
+    *v = atanh2_series(dd_div(dd_from(x), two_sum(2.0, x)));
+    return 0;
+  }
+  *v = log_of_pair(two_sum(1.0, x));
+  return 0;
+}
+
+static int exp10_core(double x, double w_over, double w_zero, dd* v, int* k, double* rn) {
+  *k = 0;
+  if (isnan(x)) {
+    *rn = x;
+    return 1;
+  }
+  if (x == 0.0 || isinf(x)) {
+    *rn = x == 0.0 ? 1.0 : (x > 0.0 ? x : 0.0);
+    return 1;
+  }
+  dd w = dd_mul_d(LN10_P, x);
+  if (w.hi > w_over) {
+    *rn = INFINITY;
+    return 1;
+  }
+  if (w.hi < w_zero) {
+    *rn = 0.0;
+    return 1;
+  }
+  exp_of_pair(w, v, k);
+  return 0;
+}
+
+static int expm1_core(double x, double w_over, dd* v, int* k, double* rn) {
+  *k = 0;
+  if (isnan(x) || x == 0.0) {
+    *rn = x;
+    return 1;
+  }
+  if (x > w_over) {
+    *rn = INFINITY;
+    return 1;
+  }
+  if (x < -800.0) {
+    *rn = -1.0;
+    return 1;
+  }
+  if (fabs(x) < 0.3) {
+    *v = dd_mul_d(horner(dd_from(x), INV_FACT, 1, 1, 21, 13), x);
+    return 0;
+  }
+  dd e;
+  int j;
+  exp_of_pair(dd_from(x), &e, &j);
+  if (x > 0.0) {
+    *v = dd_add(e, dd_from(-ldexp(1.0, -j)));
+    *k = j;
+  } else {
+    *v = dd_add(dd_from(-1.0), (dd){ldexp(e.hi, j), ldexp(e.lo, j)});
+  }
+  return 0;
+}
+
+static int cbrt_core(double x, dd* v, int* k, double* rn) {
+  *k = 0;
+  if (isnan(x) || x == 0.0 || isinf(x)) {
+    *rn = x;
+    return 1;
+  }
+  int e;
+  double m = frexp(fabs(x), &e);
+  int q = (e + 3000) / 3 - 1000; /* floor(e / 3) */
+  double a = ldexp(m, e - 3 * q); /* [0.5, 4) */
+  double y0 = cbrt(a);
+  dd y2 = two_prod(y0, y0);
+  dd t = dd_add(dd_mul_d(y2, y0), dd_from(-a));
+  dd y = fast_two_sum(y0, -t.hi / (3.0 * y2.hi));
+  *v = x < 0.0 ? dd_neg(y) : y;
+  *k = q;
+  return 0;
+}

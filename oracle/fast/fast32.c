@@ -37,6 +37,7 @@
  * exact (the exact product's error term by C99 fma(), which -mfma makes the
  * host's fused multiply-add instruction).
  */
+#define _GNU_SOURCE /* exp10 in the host libm */
 #include "binary.h"
 
 /* |x| = m 2^E (m < 2^24 an integer): 2|x|/pi = q + f with q an integer taken
@@ -321,14 +322,25 @@ static int round_f32(dd v, double rel, float* out) {
 /* ---- exported entry points ---------------------------------------------- */
 
 enum { FN_SIN, FN_EXP, FN_LOG, FN_COS, FN_TAN, FN_EXP2, FN_LOG2, FN_SINH, FN_COSH, FN_TANH,
-       FN_ASIN, FN_ACOS, FN_ATAN };
+       FN_ASIN, FN_ACOS, FN_ATAN, FN_LOG10, FN_LOG1P, FN_EXP10, FN_EXPM1, FN_CBRT };
 
-/* the inverse trig cores of binary.h for a binary32 argument, unscaled */
+/* the cores of binary.h for a binary32 argument, unscaled (binary32
+   results that neither overflow nor round to zero lie in the binary64
+   normal range) */
 static int inv_value(int fn, float x, dd* v, float* rn) {
   int k;
   double r;
-  int sp = fn == FN_ASIN ? asin_core(x, v, &k, &r)
-                         : (fn == FN_ACOS ? acos_core(x, v, &k, &r) : atan_core(x, v, &k, &r));
+  int sp;
+  switch (fn) {
+    case FN_ASIN: sp = asin_core(x, v, &k, &r); break;
+    case FN_ACOS: sp = acos_core(x, v, &k, &r); break;
+    case FN_ATAN: sp = atan_core(x, v, &k, &r); break;
+    case FN_LOG10: sp = log10_core(x, v, &k, &r); break;
+    case FN_LOG1P: sp = log1p_core(x, v, &k, &r); break;
+    case FN_EXP10: sp = exp10_core(x, 89.5, -104.5, v, &k, &r); break;
+    case FN_EXPM1: sp = expm1_core(x, 89.5, v, &k, &r); break;
+    default: sp = cbrt_core(x, v, &k, &r); break;
+  }
   if (sp) {
     *rn = (float)r;
     return 1;
@@ -342,7 +354,12 @@ static int value(int fn, float x, dd* v, float* rn) {
   switch (fn) {
     case FN_ASIN:
     case FN_ACOS:
-    case FN_ATAN: return inv_value(fn, x, v, rn);
+    case FN_ATAN:
+    case FN_LOG10:
+    case FN_LOG1P:
+    case FN_EXP10:
+    case FN_EXPM1:
+    case FN_CBRT: return inv_value(fn, x, v, rn);
     case FN_SIN: return trig_value(x, 0, v, rn);
     case FN_COS: return trig_value(x, 1, v, rn);
     case FN_TAN: return trig_value(x, 2, v, rn);
@@ -406,6 +423,11 @@ static double libm_double(int fn, double d) {
     case FN_ASIN: return asin(d);
     case FN_ACOS: return acos(d);
     case FN_ATAN: return atan(d);
+    case FN_LOG10: return log10(d);
+    case FN_LOG1P: return log1p(d);
+    case FN_EXP10: return exp10(d);
+    case FN_EXPM1: return expm1(d);
+    case FN_CBRT: return cbrt(d);
     default: return tanh(d);
   }
 }

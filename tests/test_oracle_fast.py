@@ -321,9 +321,12 @@ def test_binary_check_metric_on_known_answers(fn):
         assert tot["violations"] == 1 and tot["bad"][0] == i
 
 
-# ---- asin, acos and atan in both stages (oracle/fast/binary.h) ---------------
+# ---- asin, acos, atan, log10, log1p, exp10, expm1, cbrt in both stages -------
+# (oracle/fast/binary.h)
 
-INV = {"asin": mp.asin, "acos": mp.acos, "atan": mp.atan}
+INV = {"asin": mp.asin, "acos": mp.acos, "atan": mp.atan, "log10": mp.log10, "log1p": mp.log1p,
+       "exp10": lambda v: mp.mpf(10) ** v, "expm1": mp.expm1,
+       "cbrt": lambda v: mp.sign(v) * mp.cbrt(abs(v))}
 
 
 def _inputs_inv(fn, dt, n=400, seed=41):
@@ -333,14 +336,25 @@ def _inputs_inv(fn, dt, n=400, seed=41):
     parts = [W.function_mixture(fn, dt, n, 43), W.specials(dt), rng.uniform(-1, 1, n),
              near1, -near1, 10.0 ** -rng.uniform(0, 300 if dt == "f64" else 44, n // 4),
              np.array([1.0, -1.0, 0.5, -0.5, 2.0 ** -30, 2.0 ** -31, 0.9999999])]
-    if fn == "atan":
-        parts += [np.sign(rng.standard_normal(n)) * 10.0 ** rng.uniform(-300, 300, n)]
+    wide = np.sign(rng.standard_normal(n)) * 10.0 ** rng.uniform(-300 if dt == "f64" else -44,
+                                                                  300 if dt == "f64" else 38, n)
+    if fn in ("atan", "cbrt", "log10", "log1p"):
+        parts += [wide, np.abs(wide), 10.0 ** rng.integers(0, 22, 40), (np.arange(1, 60) ** 3)]
+    if fn in ("exp10", "expm1"):
+        lim = (310, 330) if dt == "f64" else (39, 46)
+        parts += [rng.uniform(-lim[1], lim[0], n), rng.uniform(-0.5, 0.5, n), wide[:n // 4],
+                  np.arange(-20, 23, dtype=np.float64)]
+    if fn == "expm1":
+        lim = 712 if dt == "f64" else 90
+        parts += [rng.uniform(-lim, lim, n), np.array([0.3, -0.3, 0.29999, 709.7, 88.7, -40.0])]
+    if fn == "log1p":
+        parts += [rng.uniform(-1, 0, n), -1 + 10.0 ** -rng.uniform(0, 15, n // 4)]
     return np.concatenate(parts).astype(npdt)
 
 
 @pytest.mark.parametrize("fn", list(INV))
 @pytest.mark.parametrize("dt", ["f64", "f32"])
-def test_inverse_trig_pair_within_claimed_bound_of_mpmath(fn, dt):
+def test_c99_pair_within_claimed_bound_of_mpmath(fn, dt):
     fast = fast64 if dt == "f64" else fast32
     x = _inputs_inv(fn, dt, n=150)
     rn, hi, lo, und = fast.fast_eval(fn, x)
@@ -348,11 +362,13 @@ def test_inverse_trig_pair_within_claimed_bound_of_mpmath(fn, dt):
     worst = mp.mpf(0)
     checked = 0
     for xi, h, l in zip(x, hi, lo):
-        if not (np.isfinite(h) and np.isfinite(xi)) or h == 0 or abs(xi) > 1 and fn != "atan":
+        if not (np.isfinite(h) and np.isfinite(xi)) or h == 0:
             continue
         exact = INV[fn](mp.mpf(float(xi)))
-        if exact == 0 or abs(exact) < mp.mpf(2) ** -960:
+        if exact == 0 or abs(exact) < mp.mpf(2) ** -960 or abs(exact) > mp.mpf(2) ** 1023:
             continue
+        if l == 0 and mp.mpf(float(h)) == exact:
+            continue                                              # an exact value
         worst = max(worst, abs((mp.mpf(float(h)) + mp.mpf(float(l))) - exact) / abs(exact))
         checked += 1
     assert checked > 300
@@ -361,7 +377,7 @@ def test_inverse_trig_pair_within_claimed_bound_of_mpmath(fn, dt):
 
 @pytest.mark.parametrize("fn", list(INV))
 @pytest.mark.parametrize("dt", ["f64", "f32"])
-def test_inverse_trig_rounded_results_match_the_ball_oracle(fn, dt):
+def test_c99_rounded_results_match_the_ball_oracle(fn, dt):
     fast = fast64 if dt == "f64" else fast32
     x = _inputs_inv(fn, dt)
     rn = fast.evaluate(fn, x)[0].astype(np.float64)
@@ -373,8 +389,13 @@ def test_inverse_trig_rounded_results_match_the_ball_oracle(fn, dt):
 
 @pytest.mark.parametrize("fn,start", [("asin", 0x3f000000), ("asin", 0x3f7f0000),
                                       ("acos", 0x3e800000), ("acos", 0xbf7f0000),
-                                      ("atan", 0x3f700000), ("atan", 0x4b000000)])
-def test_inverse_trig_sweep_against_libm_double_rounded(fn, start):
+                                      ("atan", 0x3f700000), ("atan", 0x4b000000),
+                                      ("log10", 0x3f7f0000), ("log10", 0x41200000),
+                                      ("log1p", 0x38000000), ("log1p", 0xbf000000),
+                                      ("exp10", 0x3f000000), ("exp10", 0xc2100000),
+                                      ("expm1", 0x3e800000), ("expm1", 0xbe900000),
+                                      ("cbrt", 0x3f800000), ("cbrt", 0x00400000)])
+def test_c99_sweep_against_libm_double_rounded(fn, start):
     st, differ, und = fast32.sweep_libm(fn, start, 1 << 18)
     assert st.n == 1 << 18
     assert st.differ == st.differ_explained, (st.differ, st.differ_explained)
