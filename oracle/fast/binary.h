@@ -407,3 +407,84 @@ static int cbrt_core(double x, dd* v, int* k, double* rn) {
   *k = q;
   return 0;
 }
+
+/* asinh, acosh and atanh for the fast stages (bound 2^-90), through
+ * log1p of a pair w in (-0.29, 0.41) as 2 atanh(w / (2 + w)) and log of a
+ * pair elsewhere:
+ *  asinh a (a = |x|) = x - x^3/6 below 2^-30, log1p(a + a^2/(1 + sqrt(1 +
+ *       a^2))) below 0.4, log(a + sqrt(a^2 + 1)) to 2^500, log 2a beyond;
+ *  acosh x = log1p((x - 1) + sqrt((x - 1)(x + 1))) while that argument is
+ *       below 0.41, log(x + sqrt(x^2 - 1)) to 2^500, log 2x beyond;
+ *  atanh x = (2 atanh x)/2 by the series to |x| = 0.171, else
+ *       log((1 + x)/(1 - x)) / 2 with the quotient as a pair. */
+static dd log1p_pair(dd w) { return atanh2_series(dd_div(w, dd_add(dd_from(2.0), w))); }
+
+static int asinh_core(double x, dd* v, int* k, double* rn) {
+  *k = 0;
+  if (isnan(x) || isinf(x) || x == 0.0) {
+    *rn = x;
+    return 1;
+  }
+  double a = fabs(x);
+  dd r;
+  if (a < 0x1p-30) {
+    r = fast_two_sum(a, -(a * a * a) / 6.0);
+  } else if (a > 0x1p500) {
+    r = dd_add(log_pair(a), (dd){LN2_D[0], LN2_D[1]});
+  } else {
+    dd a2 = two_prod(a, a);
+    dd s = dd_sqrt(dd_add(a2, dd_from(1.0)));
+    if (a < 0.4) {
+      dd w = dd_add(dd_from(a), dd_div(a2, dd_add(dd_from(1.0), s)));
+      r = log1p_pair(w);
+    } else {
+      r = log_of_pair(dd_add(dd_from(a), s));
+    }
+  }
+  *v = x < 0.0 ? dd_neg(r) : r;
+  return 0;
+}
+
+static int acosh_core(double x, dd* v, int* k, double* rn) {
+  *k = 0;
+  if (isnan(x) || x < 1.0) {
+    *rn = NAN;
+    return 1;
+  }
+  if (x == 1.0 || isinf(x)) {
+    *rn = x == 1.0 ? 0.0 : x;
+    return 1;
+  }
+  if (x > 0x1p500) {
+    *v = dd_add(log_pair(x), (dd){LN2_D[0], LN2_D[1]});
+    return 0;
+  }
+  dd xm = two_sum(x, -1.0);
+  dd s = dd_sqrt(dd_mul(xm, two_sum(x, 1.0)));
+  dd w = dd_add(xm, s);
+  *v = w.hi < 0.41 ? log1p_pair(w) : log_of_pair(dd_add(dd_from(x), s));
+  return 0;
+}
+
+static int atanh_core(double x, dd* v, int* k, double* rn) {
+  *k = 0;
+  double a = fabs(x);
+  if (isnan(x) || a > 1.0) {
+    *rn = NAN;
+    return 1;
+  }
+  if (x == 0.0 || a == 1.0) {
+    *rn = x == 0.0 ? x : copysign(INFINITY, x);
+    return 1;
+  }
+  dd r;
+  if (a <= 0.171) {
+    r = atanh2_series(dd_from(x));
+  } else {
+    r = log_of_pair(dd_div(two_sum(1.0, x), two_sum(1.0, -x)));
+  }
+  r.hi *= 0.5;
+  r.lo *= 0.5;
+  *v = r;
+  return 0;
+}

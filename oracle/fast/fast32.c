@@ -322,7 +322,8 @@ static int round_f32(dd v, double rel, float* out) {
 /* ---- exported entry points ---------------------------------------------- */
 
 enum { FN_SIN, FN_EXP, FN_LOG, FN_COS, FN_TAN, FN_EXP2, FN_LOG2, FN_SINH, FN_COSH, FN_TANH,
-       FN_ASIN, FN_ACOS, FN_ATAN, FN_LOG10, FN_LOG1P, FN_EXP10, FN_EXPM1, FN_CBRT };
+       FN_ASIN, FN_ACOS, FN_ATAN, FN_LOG10, FN_LOG1P, FN_EXP10, FN_EXPM1, FN_CBRT, FN_ASINH,
+       FN_ACOSH, FN_ATANH };
 
 /* the cores of binary.h for a binary32 argument, unscaled (binary32
    results that neither overflow nor round to zero lie in the binary64
@@ -339,6 +340,9 @@ static int inv_value(int fn, float x, dd* v, float* rn) {
     case FN_LOG1P: sp = log1p_core(x, v, &k, &r); break;
     case FN_EXP10: sp = exp10_core(x, 89.5, -104.5, v, &k, &r); break;
     case FN_EXPM1: sp = expm1_core(x, 89.5, v, &k, &r); break;
+    case FN_ASINH: sp = asinh_core(x, v, &k, &r); break;
+    case FN_ACOSH: sp = acosh_core(x, v, &k, &r); break;
+    case FN_ATANH: sp = atanh_core(x, v, &k, &r); break;
     default: sp = cbrt_core(x, v, &k, &r); break;
   }
   if (sp) {
@@ -359,7 +363,10 @@ static int value(int fn, float x, dd* v, float* rn) {
     case FN_LOG1P:
     case FN_EXP10:
     case FN_EXPM1:
-    case FN_CBRT: return inv_value(fn, x, v, rn);
+    case FN_CBRT:
+    case FN_ASINH:
+    case FN_ACOSH:
+    case FN_ATANH: return inv_value(fn, x, v, rn);
     case FN_SIN: return trig_value(x, 0, v, rn);
     case FN_COS: return trig_value(x, 1, v, rn);
     case FN_TAN: return trig_value(x, 2, v, rn);
@@ -428,6 +435,9 @@ static double libm_double(int fn, double d) {
     case FN_EXP10: return exp10(d);
     case FN_EXPM1: return expm1(d);
     case FN_CBRT: return cbrt(d);
+    case FN_ASINH: return asinh(d);
+    case FN_ACOSH: return acosh(d);
+    case FN_ATANH: return atanh(d);
     default: return tanh(d);
   }
 }
