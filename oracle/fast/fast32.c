@@ -323,7 +323,7 @@ static int round_f32(dd v, double rel, float* out) {
 
 enum { FN_SIN, FN_EXP, FN_LOG, FN_COS, FN_TAN, FN_EXP2, FN_LOG2, FN_SINH, FN_COSH, FN_TANH,
        FN_ASIN, FN_ACOS, FN_ATAN, FN_LOG10, FN_LOG1P, FN_EXP10, FN_EXPM1, FN_CBRT, FN_ASINH,
-       FN_ACOSH, FN_ATANH };
+       FN_ACOSH, FN_ATANH, FN_ERF, FN_ERFC };
 
 /* the cores of binary.h for a binary32 argument, unscaled (binary32
    results that neither overflow nor round to zero lie in the binary64
@@ -343,6 +343,8 @@ static int inv_value(int fn, float x, dd* v, float* rn) {
     case FN_ASINH: sp = asinh_core(x, v, &k, &r); break;
     case FN_ACOSH: sp = acosh_core(x, v, &k, &r); break;
     case FN_ATANH: sp = atanh_core(x, v, &k, &r); break;
+    case FN_ERF: sp = erf_core(x, v, &k, &r); break;
+    case FN_ERFC: sp = erfc_core(x, v, &k, &r); break;
     default: sp = cbrt_core(x, v, &k, &r); break;
   }
   if (sp) {
@@ -366,7 +368,9 @@ static int value(int fn, float x, dd* v, float* rn) {
     case FN_CBRT:
     case FN_ASINH:
     case FN_ACOSH:
-    case FN_ATANH: return inv_value(fn, x, v, rn);
+    case FN_ATANH:
+    case FN_ERF:
+    case FN_ERFC: return inv_value(fn, x, v, rn);
     case FN_SIN: return trig_value(x, 0, v, rn);
     case FN_COS: return trig_value(x, 1, v, rn);
     case FN_TAN: return trig_value(x, 2, v, rn);
@@ -438,6 +442,8 @@ static double libm_double(int fn, double d) {
     case FN_ASINH: return asinh(d);
     case FN_ACOSH: return acosh(d);
     case FN_ATANH: return atanh(d);
+    case FN_ERF: return erf(d);
+    case FN_ERFC: return erfc(d);
     default: return tanh(d);
   }
 }

@@ -256,7 +256,8 @@ static int hyp64(double x, int kind, dd* v, int* k, double* rn) {
 }
 
 enum { G_SIN, G_EXP, G_LOG, G_COS, G_TAN, G_EXP2, G_LOG2, G_SINH, G_COSH, G_TANH, G_ASIN,
-       G_ACOS, G_ATAN, G_LOG10, G_LOG1P, G_EXP10, G_EXPM1, G_CBRT, G_ASINH, G_ACOSH, G_ATANH };
+       G_ACOS, G_ATAN, G_LOG10, G_LOG1P, G_EXP10, G_EXPM1, G_CBRT, G_ASINH, G_ACOSH, G_ATANH,
+       G_ERF, G_ERFC };
 
 static int value64(int fn, double x, dd* v, int* k, double* rn) {
   switch (fn) {
@@ -271,6 +272,8 @@ static int value64(int fn, double x, dd* v, int* k, double* rn) {
     case G_ASINH: return asinh_core(x, v, k, rn);
     case G_ACOSH: return acosh_core(x, v, k, rn);
     case G_ATANH: return atanh_core(x, v, k, rn);
+    case G_ERF: return erf_core(x, v, k, rn);
+    case G_ERFC: return erfc_core(x, v, k, rn);
     case G_SIN: return trig64(x, 0, v, k, rn);
     case G_COS: return trig64(x, 1, v, k, rn);
     case G_TAN: return trig64(x, 2, v, k, rn);

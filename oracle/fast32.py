@@ -1,6 +1,6 @@
 """ctypes binding of the oracle's fast binary32 stage (``oracle/fast/fast32.c``)
 for sin, cos, tan, exp, exp2, log, log2, sinh, cosh, tanh, asin, acos, atan, log10,
-log1p, exp10, expm1, cbrt, asinh, acosh, atanh, pow and atan2 over many
+log1p, exp10, expm1, cbrt, asinh, acosh, atanh, erf, erfc, pow and atan2 over many
 binary32 inputs.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).  The C stage gives a
@@ -20,7 +20,8 @@ SRC = os.path.join(HERE, "fast", "fast32.c")
 LIB = os.path.join(HERE, "liboracle_fast32.so")
 FNS = {"sin": 0, "exp": 1, "log": 2, "cos": 3, "tan": 4, "exp2": 5, "log2": 6, "sinh": 7,
        "cosh": 8, "tanh": 9, "asin": 10, "acos": 11, "atan": 12, "log10": 13, "log1p": 14,
-       "exp10": 15, "expm1": 16, "cbrt": 17, "asinh": 18, "acosh": 19, "atanh": 20}
+       "exp10": 15, "expm1": 16, "cbrt": 17, "asinh": 18, "acosh": 19, "atanh": 20, "erf": 21,
+       "erfc": 22}
 FNS2 = {"pow": 0, "atan2": 1}          # two operands (oracle/fast/binary.h)
 
 _lib = None

@@ -1,7 +1,7 @@
 """Exhaustive sweeps over every binary32 bit pattern for sin, cos, tan, exp,
 exp2, log, log2, sinh, cosh, tanh, asin, acos, atan, log10, log1p, exp10,
-expm1, cbrt, asinh, acosh and atanh (test infrastructure; minutes per
-function, so run by hand).
+expm1, cbrt, asinh, acosh, atanh, erf and erfc (test infrastructure;
+minutes per function, so run by hand).
 
     python -m tests.sweep32 libm [--fns sin,exp,log,...] [--threads N]
         the oracle's fast stage against the host libm's binary64 result

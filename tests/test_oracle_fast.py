@@ -327,7 +327,7 @@ def test_binary_check_metric_on_known_answers(fn):
 INV = {"asin": mp.asin, "acos": mp.acos, "atan": mp.atan, "log10": mp.log10, "log1p": mp.log1p,
        "exp10": lambda v: mp.mpf(10) ** v, "expm1": mp.expm1,
        "cbrt": lambda v: mp.sign(v) * mp.cbrt(abs(v)), "asinh": mp.asinh, "acosh": mp.acosh,
-       "atanh": mp.atanh}
+       "atanh": mp.atanh, "erf": mp.erf, "erfc": mp.erfc}
 
 
 def _inputs_inv(fn, dt, n=400, seed=41):
@@ -355,6 +355,10 @@ def _inputs_inv(fn, dt, n=400, seed=41):
                   np.array([0.4, 0.39999, 1.0, 2.0 ** 500, 2.0 ** 501, 1e300])]
     if fn == "atanh":
         parts += [np.array([0.171, 0.17100001, -0.171, 0.5, -0.99999])]
+    if fn in ("erf", "erfc"):
+        top = 28 if dt == "f64" else 10.5
+        parts += [rng.uniform(-7, top, n), rng.uniform(1.9, 2.1, n // 4), rng.uniform(5.5, 6.5, n // 4),
+                  np.array([2.0, -2.0, 6.0, -6.0, 26.55, 27.2, 9.19, 10.05])]
     return np.concatenate(parts).astype(npdt)
 
 
@@ -403,7 +407,9 @@ def test_c99_rounded_results_match_the_ball_oracle(fn, dt):
                                       ("cbrt", 0x3f800000), ("cbrt", 0x00400000),
                                       ("asinh", 0x3e000000), ("asinh", 0x4f000000),
                                       ("acosh", 0x3f800000), ("acosh", 0x40000000),
-                                      ("atanh", 0x3e200000), ("atanh", 0xbf700000)])
+                                      ("atanh", 0x3e200000), ("atanh", 0xbf700000),
+                                      ("erf", 0x3f800000), ("erf", 0xc0000000),
+                                      ("erfc", 0x40000000), ("erfc", 0x41100000)])
 def test_c99_sweep_against_libm_double_rounded(fn, start):
     st, differ, und = fast32.sweep_libm(fn, start, 1 << 18)
     assert st.n == 1 << 18
