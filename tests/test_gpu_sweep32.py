@@ -27,7 +27,8 @@ def _gpu():
 KINDS = [(f, "u10") for f in ("sin", "cos", "tan", "exp", "exp2", "log", "log2", "sinh", "cosh",
                                "tanh", "asin", "acos", "atan", "log10", "log1p", "exp10", "expm1",
                                "cbrt", "asinh", "acosh", "atanh", "erf", "erfc")]
-KINDS += [(f, "u35") for f in ("sin", "cos", "tan", "asin", "acos", "atan")]
+KINDS += [(f, "u35") for f in ("sin", "cos", "tan", "asin", "acos", "atan", "log", "sinh", "cosh",
+                                "tanh")]
 
 
 @pytest.mark.parametrize("fn,variant", KINDS)
