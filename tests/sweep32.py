@@ -9,10 +9,11 @@ minutes per function, so run by hand).
         binary64 value must lie within two of its ulps of a binary32
         midpoint (a double rounding); every differing and every undecided
         input is re-evaluated by the ball oracle.
-    python -m tests.sweep32 gpu [--fns ...] [--variants u10,u35] [--threads N]
+    python -m tests.sweep32 gpu [--fns ...] [--variants u10,u35] [--threads N] [--via-f64]
         the GPU entry points on all 2^32 inputs against the oracle (ULP
         metric of tests/ulp.py; NaN, inf, zero and subnormal results
-        bit-exact).
+        bit-exact; with --via-f64 the binary32-through-binary64 forms, whose
+        subnormal results round twice and are counted as mismatches).
 Each prints one JSON line per function (and variant).
 """
 import argparse
@@ -73,7 +74,7 @@ def sweep_libm(fn, threads, total=TOTAL, start0=0):
     return agg
 
 
-def sweep_gpu(fn, variant, threads, total=TOTAL, gpu_chunk=1 << 26):
+def sweep_gpu(fn, variant, threads, total=TOTAL, gpu_chunk=1 << 26, via_f64=False):
     import torch
     import paper_2001_09258_amd as L
     L.load()
@@ -90,7 +91,7 @@ def sweep_gpu(fn, variant, threads, total=TOTAL, gpu_chunk=1 << 26):
             xb = torch.arange(g0, g0 + n, dtype=torch.int64, device="cuda")
             xb = torch.where(xb >= (1 << 31), xb - (1 << 32), xb).to(torch.int32)
             x = xb.view(torch.float32)
-            y = L.evaluate(fn, x, variant=variant)
+            y = L.evaluate(fn, x, variant=variant, via_f64=via_f64)
             yh = y.cpu().numpy()
             del xb, x, y
             for s in range(0, n, CHUNK):
@@ -120,7 +121,7 @@ def sweep_gpu(fn, variant, threads, total=TOTAL, gpu_chunk=1 << 26):
                 max_ulp, worst = st.max_ulp, st.worst
             bad_all.append(b)
             und_all.append(u)
-    agg.update(fn=fn, variant=variant, max_ulp=round(max_ulp, 4),
+    agg.update(fn=fn, variant=variant + ("_via_f64" if via_f64 else ""), max_ulp=round(max_ulp, 4),
                mean_ulp=round(sum_ulp / max(agg["n_reg"], 1), 4),
                worst_input=float(np.uint32(worst).view(np.float32)),
                bad_inputs=[float(v) for v in np.concatenate(bad_all)[:8].view(np.float32)] if bad_all else [],
@@ -135,13 +136,16 @@ def main():
     p.add_argument("--variants", default="u10")
     p.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 4))
     p.add_argument("--total", type=int, default=TOTAL, help="inputs from bit pattern 0 (testing)")
+    p.add_argument("--via-f64", action="store_true",
+                   help="the binary32-through-binary64 entry points (u10 names)")
     a = p.parse_args()
     for fn in a.fns.split(","):
         if a.mode == "libm":
             print(json.dumps(sweep_libm(fn, a.threads, a.total)), flush=True)
         else:
             for v in a.variants.split(","):
-                print(json.dumps(sweep_gpu(fn, v, a.threads, a.total)), flush=True)
+                print(json.dumps(sweep_gpu(fn, v, a.threads, a.total, via_f64=a.via_f64)),
+                      flush=True)
 
 
 if __name__ == "__main__":
