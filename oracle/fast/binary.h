@@ -94,7 +94,12 @@ static int pow_core(double x, double z, double w_over, double w_zero, dd* v, int
     return 1;
   }
   double sgn = (x < 0.0 && odd) ? -1.0 : 1.0;
-  dd w = dd_mul_d(log_pair(ax), z);
+  dd l = log_pair(ax);
+  if (!(fabs(l.hi * z) < 1e5)) { /* far beyond either threshold (the pair product would overflow) */
+    *rn = sgn * (l.hi * z > 0.0 ? INFINITY : 0.0);
+    return 1;
+  }
+  dd w = dd_mul_d(l, z);
   if (w.hi > w_over) {
     *rn = sgn * INFINITY;
     return 1;
@@ -342,8 +347,8 @@ static int exp10_core(double x, double w_over, double w_zero, dd* v, int* k, dou
     *rn = x;
     return 1;
   }
-  if (x == 0.0 || isinf(x)) {
-    *rn = x == 0.0 ? 1.0 : (x > 0.0 ? x : 0.0);
+  if (x == 0.0 || !(fabs(x) < 400.0)) { /* beyond 400 it overflows or rounds to 0 */
+    *rn = x == 0.0 ? 1.0 : (x > 0.0 ? INFINITY : 0.0);
     return 1;
   }
   dd w = dd_mul_d(LN10_P, x);
@@ -544,7 +549,11 @@ static int erf_core(double x, dd* v, int* k, double* rn) {
     return 1;
   }
   dd r;
-  if (a < 2.0) {
+  if (a < 0x1p-900) { /* (2/sqrt pi) a, formed at a 2^600 so that no part is subnormal */
+    dd tw = {2.0 * INV_SQRTPI_P.hi, 2.0 * INV_SQRTPI_P.lo};
+    r = dd_mul_d(tw, a * 0x1p600);
+    *k = -600;
+  } else if (a < 2.0) {
     r = erf_small(a);
   } else {
     dd c;
