@@ -323,7 +323,7 @@ static int round_f32(dd v, double rel, float* out) {
 
 enum { FN_SIN, FN_EXP, FN_LOG, FN_COS, FN_TAN, FN_EXP2, FN_LOG2, FN_SINH, FN_COSH, FN_TANH,
        FN_ASIN, FN_ACOS, FN_ATAN, FN_LOG10, FN_LOG1P, FN_EXP10, FN_EXPM1, FN_CBRT, FN_ASINH,
-       FN_ACOSH, FN_ATANH, FN_ERF, FN_ERFC };
+       FN_ACOSH, FN_ATANH, FN_ERF, FN_ERFC, FN_LGAMMA, FN_TGAMMA };
 
 /* the cores of binary.h for a binary32 argument, unscaled (binary32
    results that neither overflow nor round to zero lie in the binary64
@@ -356,8 +356,30 @@ static int inv_value(int fn, float x, dd* v, float* rn) {
   return 0;
 }
 
-static int value(int fn, float x, dd* v, float* rn) {
+static const double REL = 0x1p-90;
+
+/* lgamma and tgamma, unscaled, with their own relative bound *rel */
+static int gamma_value(int fn, float x, dd* v, float* rn, double* rel) {
+  double r;
+  int k = 0;
+  int sp = fn == FN_LGAMMA ? lgamma_core(x, v, rel, &r)
+                           : tgamma_core(x, 89.5, -104.5, v, &k, rel, &r);
+  if (sp) {
+    *rn = (float)r;
+    return 1;
+  }
+  v->hi = ldexp(v->hi, k);
+  v->lo = ldexp(v->lo, k);
+  return 0;
+}
+
+/* the value of fn at x: 1 with *rn for an exact result, else 0 with the
+   pair v and its relative error bound *rel */
+static int value(int fn, float x, dd* v, float* rn, double* rel) {
+  *rel = REL;
   switch (fn) {
+    case FN_LGAMMA:
+    case FN_TGAMMA: return gamma_value(fn, x, v, rn, rel);
     case FN_ASIN:
     case FN_ACOS:
     case FN_ATAN:
@@ -384,8 +406,6 @@ static int value(int fn, float x, dd* v, float* rn) {
   }
 }
 
-static const double REL = 0x1p-90;
-
 /* n inputs: hi/lo the pair (NaN for special results), rn the rounded value,
    undecided[i] = 1 where the caller must ask the ball oracle */
 void oracle_fast32_eval(int fn, const float* x, long n, double* hi, double* lo, float* rn,
@@ -393,17 +413,28 @@ void oracle_fast32_eval(int fn, const float* x, long n, double* hi, double* lo, 
   for (long i = 0; i < n; ++i) {
     dd v;
     float r;
-    if (value(fn, x[i], &v, &r)) {
+    double rel;
+    if (value(fn, x[i], &v, &r, &rel)) {
       hi[i] = (double)r;
       lo[i] = 0.0;
       rn[i] = r;
       undecided[i] = 0;
       continue;
     }
-    undecided[i] = (uint8_t)round_f32(v, REL, &r);
+    undecided[i] = (uint8_t)round_f32(v, rel, &r);
     hi[i] = v.hi;
     lo[i] = v.lo;
     rn[i] = r;
+  }
+}
+
+/* the relative error bound the stage claims for each input's pair (0 for
+   the exact results) */
+void oracle_fast32_rel(int fn, const float* x, long n, double* rel) {
+  for (long i = 0; i < n; ++i) {
+    dd v;
+    float r;
+    rel[i] = value(fn, x[i], &v, &r, &rel[i]) ? 0.0 : rel[i];
   }
 }
 
@@ -444,6 +475,8 @@ static double libm_double(int fn, double d) {
     case FN_ATANH: return atanh(d);
     case FN_ERF: return erf(d);
     case FN_ERFC: return erfc(d);
+    case FN_LGAMMA: return lgamma(d);
+    case FN_TGAMMA: return tgamma(d);
     default: return tanh(d);
   }
 }
@@ -465,9 +498,10 @@ void oracle_fast32_sweep_libm(int fn, uint64_t start, uint64_t count, sweep_stat
     float x = from_bits(b);
     dd v;
     float r;
+    double rel;
     st->n++;
-    if (!value(fn, x, &v, &r)) {
-      if (round_f32(v, REL, &r)) {
+    if (!value(fn, x, &v, &r, &rel)) {
+      if (round_f32(v, rel, &r)) {
         if (st->undecided < undec_cap) undec[st->undecided] = b;
         st->undecided++;
         continue;
@@ -506,8 +540,9 @@ static int check_value(int exact, dd v, float r, double rel, float x, float yi, 
 static int check_one(int fn, float x, float yi, double bound, check_stats* st) {
   dd v;
   float r;
-  int exact = value(fn, x, &v, &r);
-  return check_value(exact, v, r, REL, x, yi, bound, st);
+  double rel;
+  int exact = value(fn, x, &v, &r, &rel);
+  return check_value(exact, v, r, rel, x, yi, bound, st);
 }
 
 /* one result yi against the value v (or the exact r): 0 fine, 1 undecided,

@@ -1,10 +1,11 @@
 """ctypes binding of the oracle's fast binary32 stage (``oracle/fast/fast32.c``)
 for sin, cos, tan, exp, exp2, log, log2, sinh, cosh, tanh, asin, acos, atan, log10,
-log1p, exp10, expm1, cbrt, asinh, acosh, atanh, erf, erfc, pow and atan2 over many
-binary32 inputs.
+log1p, exp10, expm1, cbrt, asinh, acosh, atanh, erf, erfc, lgamma, tgamma, pow and
+atan2 over many binary32 inputs.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).  The C stage gives a
-double-double within 2^-90 relative of the exact value and the correctly
+double-double within 2^-90 relative of the exact value (lgamma and tgamma: a
+bound of its own per input, carried in the C stage) and the correctly
 rounded binary32 result where that bound decides it; ``evaluate`` sends the
 inputs it cannot decide to the ball oracle, so its results are the oracle's.
 Pinned against the ball oracle in ``tests/test_oracle_fast.py``.
@@ -21,7 +22,7 @@ LIB = os.path.join(HERE, "liboracle_fast32.so")
 FNS = {"sin": 0, "exp": 1, "log": 2, "cos": 3, "tan": 4, "exp2": 5, "log2": 6, "sinh": 7,
        "cosh": 8, "tanh": 9, "asin": 10, "acos": 11, "atan": 12, "log10": 13, "log1p": 14,
        "exp10": 15, "expm1": 16, "cbrt": 17, "asinh": 18, "acosh": 19, "atanh": 20, "erf": 21,
-       "erfc": 22}
+       "erfc": 22, "lgamma": 23, "tgamma": 24}
 FNS2 = {"pow": 0, "atan2": 1}          # two operands (oracle/fast/binary.h)
 
 _lib = None
@@ -60,6 +61,8 @@ def load():
         lib = ctypes.CDLL(LIB)
         P = ctypes.c_void_p
         lib.oracle_fast32_eval.restype = None
+        lib.oracle_fast32_rel.restype = None
+        lib.oracle_fast32_rel.argtypes = [ctypes.c_int, P, ctypes.c_long, P]
         lib.oracle_fast32_eval.argtypes = [ctypes.c_int, P, ctypes.c_long, P, P, P, P]
         lib.oracle_fast32_sweep_libm.restype = None
         lib.oracle_fast32_sweep_libm.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
@@ -102,6 +105,16 @@ def fast_eval(fn, x, z=None):
         lib.oracle_fast32_eval(FNS[fn], x.ctypes.data, n, hi.ctypes.data, lo.ctypes.data,
                                rn.ctypes.data, und.ctypes.data)
     return rn, hi, lo, und.astype(bool)
+
+
+def fast_rel(fn, x):
+    """The relative error bound the C stage claims for each input's pair
+    (0 where its result is exact), one-operand functions."""
+    lib = load()
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    rel = np.empty(x.size, np.float64)
+    lib.oracle_fast32_rel(FNS[fn], x.ctypes.data, x.size, rel.ctypes.data)
+    return rel
 
 
 def evaluate(fn, x, z=None):

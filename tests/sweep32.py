@@ -1,6 +1,6 @@
 """Exhaustive sweeps over every binary32 bit pattern for sin, cos, tan, exp,
 exp2, log, log2, sinh, cosh, tanh, asin, acos, atan, log10, log1p, exp10,
-expm1, cbrt, asinh, acosh, atanh, erf and erfc (test infrastructure;
+expm1, cbrt, asinh, acosh, atanh, erf, erfc, lgamma and tgamma (test infrastructure;
 minutes per function, so run by hand).
 
     python -m tests.sweep32 libm [--fns sin,exp,log,...] [--threads N]

@@ -420,3 +420,98 @@ def test_c99_sweep_against_libm_double_rounded(fn, start):
         rf = fast32.fast_eval(fn, x)[0]
         assert np.array_equal(rb, rf.astype(np.float64))
     assert st.undecided == und.size
+
+
+# ---- lgamma and tgamma in the binary32 stage (oracle/fast/binary.h) ----------
+
+def _gamma_exact(fn, v):
+    v = mp.mpf(v)
+    if fn == "lgamma":
+        return mp.loggamma(v) if v > 0 else mp.log(abs(mp.gamma(v)))
+    return mp.gamma(v)
+
+
+def _inputs_gamma(fn, n=400, seed=47):
+    rng = np.random.default_rng(seed + len(fn))
+    zeros = np.array([1.0, 2.0, -2.4570247, -2.7476826, -3.1435917, -3.9552288, -4.0390536,
+                      -4.9991650, -5.0008322])
+    near = (zeros[:, None] * (1 + rng.uniform(-2e-6, 2e-6, (zeros.size, n // 20)))).ravel()
+    parts = [W.function_mixture(fn, "f32", n, 43), W.specials("f32"), rng.uniform(0, 40, n),
+             rng.uniform(-45, 0, n), near, 10.0 ** -rng.uniform(0, 44, n // 4),
+             -(10.0 ** -rng.uniform(0, 44, n // 4)), 10.0 ** rng.uniform(0, 38, n // 4),
+             np.arange(-50, 60) + rng.uniform(-1e-5, 1e-5, 110), np.arange(-5.0, 40.0),
+             np.array([0.5, -0.5, 1.5, -1.5, 34.0, 35.04, 35.05, -38.0001, -41.99, 19.9999, 20.0,
+                       2.0 ** -127, 2.0 ** -128, -(2.0 ** -128), 4e36, 4.1e36])]
+    return np.concatenate(parts).astype(np.float32)
+
+
+@pytest.mark.parametrize("fn", ["lgamma", "tgamma"])
+def test_gamma_pair_within_its_claimed_bound_of_mpmath(fn):
+    x = _inputs_gamma(fn, n=200)
+    rn, hi, lo, und = fast32.fast_eval(fn, x)
+    rel = fast32.fast_rel(fn, x)
+    mp.mp.prec = 300
+    checked = 0
+    worst = 0.0
+    for xi, h, l, r in zip(x, hi, lo, rel):
+        if not (np.isfinite(h) and np.isfinite(xi)) or r == 0.0:
+            continue
+        exact = _gamma_exact(fn, float(xi))
+        err = abs((mp.mpf(float(h)) + mp.mpf(float(l))) - exact) / abs(exact)
+        assert err <= r, (fn, float(xi), float(mp.log(err, 2)), np.log2(r))
+        worst = max(worst, float(err / r))
+        checked += 1
+    assert checked > 300
+    # the bound is typically 2^-88 or tighter away from the zeros of log Gamma
+    far = np.isfinite(x) & (np.abs(x - np.round(np.nan_to_num(x))) > 0.1)
+    assert np.median(rel[far & (rel > 0)]) < 2.0 ** -88
+
+
+@pytest.mark.parametrize("fn", ["lgamma", "tgamma"])
+def test_gamma_rounded_results_match_the_ball_oracle(fn):
+    x = _inputs_gamma(fn)
+    rn = fast32.evaluate(fn, x)[0].astype(np.float64)
+    rb = oracle.evaluate(fn, "f32", x.astype(np.float64))[0]
+    same = (rn == rb) | (np.isnan(rn) & np.isnan(rb))
+    same &= (np.signbit(rn) == np.signbit(rb)) | np.isnan(rb)
+    assert same.all(), (x[~same][:5], rn[~same][:5], rb[~same][:5])
+
+
+def test_gamma_known_values():
+    """Closed forms: Gamma(n) = (n - 1)!, Gamma(1/2) = sqrt(pi),
+    Gamma(-1/2) = -2 sqrt(pi), log Gamma(3/2) = log(sqrt(pi)/2), the C99
+    special values, and the sign of Gamma on the negative intervals."""
+    n = np.arange(1, 35, dtype=np.float32)
+    fact = np.array([float(mp.factorial(k - 1)) for k in range(1, 35)])
+    assert np.array_equal(fast32.fast_eval("tgamma", n)[0], fact.astype(np.float32))
+    sp = np.float32(mp.sqrt(mp.pi))
+    x = np.array([0.5, -0.5], np.float32)
+    assert list(fast32.fast_eval("tgamma", x)[0]) == [sp, np.float32(-2 * mp.sqrt(mp.pi))]
+    assert fast32.fast_eval("lgamma", np.array([1.5], np.float32))[0][0] == \
+        np.float32(mp.log(mp.sqrt(mp.pi) / 2))
+    sv = np.array([0.0, -0.0, 1.0, 2.0, -1.0, -7.0, np.inf, -np.inf, np.nan], np.float32)
+    lg = fast32.fast_eval("lgamma", sv)[0]
+    assert np.array_equal(lg[:2], [np.inf, np.inf]) and lg[2] == 0 and lg[3] == 0
+    assert not np.signbit(lg[2]) and not np.signbit(lg[3])
+    assert np.all(lg[4:8] == np.inf) and np.isnan(lg[8])
+    tg = fast32.fast_eval("tgamma", sv)[0]
+    assert tg[0] == np.inf and tg[1] == -np.inf and tg[2] == 1 and tg[3] == 1
+    assert np.isnan(tg[4]) and np.isnan(tg[5]) and tg[6] == np.inf and np.isnan(tg[7])
+    mids = -np.arange(0, 30) - np.float32(0.5)
+    sg = np.sign(fast32.fast_eval("tgamma", mids.astype(np.float32))[0])
+    assert np.array_equal(sg[:20], [(-1.0) ** (k + 1) for k in range(20)])
+
+
+@pytest.mark.parametrize("fn,start", [("lgamma", 0x40400000), ("lgamma", 0x41a00000),
+                                      ("lgamma", 0xc0b00000), ("tgamma", 0x3f000000),
+                                      ("tgamma", 0x41000000), ("tgamma", 0xc1200000)])
+def test_gamma_sweep_against_libm_double_rounded(fn, start):
+    st, differ, und = fast32.sweep_libm(fn, start, 1 << 17)
+    assert st.n == 1 << 17
+    assert st.differ == st.differ_explained, (st.differ, st.differ_explained)
+    if differ.size:
+        x = differ[:64].view(np.float32)
+        rb = oracle.evaluate(fn, "f32", x.astype(np.float64))[0]
+        rf = fast32.fast_eval(fn, x)[0]
+        assert np.array_equal(rb, rf.astype(np.float64))
+    assert st.undecided == und.size
