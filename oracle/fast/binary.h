@@ -596,7 +596,7 @@ static int erfc_core(double x, dd* v, int* k, double* rn) {
 /* ---- lgamma and tgamma ------------------------------------------------------
  * C99's lgamma and tgamma (the paper's library covers the C99 real
  * functions, Section 1, and does not describe these two).  Textbook
- * definitions, in pairs, for binary32 arguments (the binary32 stage):
+ * definitions, in pairs:
  *
  *  log Gamma(z), z > 0: z + n = y with y >= 20 and n >= 0 the smallest such
  *       integer; log Gamma(z) = log Gamma(y) - log(z (z + 1) ... (z + n - 1))
@@ -666,12 +666,42 @@ static dd lgamma_pos(dd z, double* err) {
   return l;
 }
 
-/* log|Gamma(x)| for a finite x that is not 0 or a negative integer */
-static dd lgamma_any(double x, double* err) {
+/* log|Gamma(x)| for a finite x that is not 0 or a negative integer, as the
+   pair times 2^k (k = 16 above x = 2^1000, where the value nears or passes
+   the binary64 range; else 0), with *err the absolute error bound of the
+   pair.  Below |x| = 2^-500 (binary64 arguments only) log Gamma(x) =
+   log Gamma(1 + x) - log x and log|sin(pi x)| = log pi + log|x| (the
+   relative error of sin(pi x) ~ pi x there is below 2^-996), so that no
+   product runs through the subnormal range. */
+static dd lgamma_any(double x, double* err, int* k) {
+  *k = 0;
+  if (x > 0x1p1000) { /* Stirling's series alone; its sum is below 2^-1003 */
+    dd ly = log_pair(x);
+    dd ym = dd_add(dd_from(x), dd_from(-0.5));
+    ym.hi = ldexp(ym.hi, -16);
+    ym.lo = ldexp(ym.lo, -16);
+    dd a = dd_mul(ym, ly);
+    double ys = ldexp(x, -16);
+    dd c = {ldexp(HALF_LN_2PI.hi, -16), ldexp(HALF_LN_2PI.lo, -16)};
+    *k = 16;
+    *err = 0x1p-96 * (fabs(a.hi) + ys + 1.0);
+    return dd_add(dd_add(a, dd_from(-ys)), c);
+  }
+  if (x > 0.0 && x < 0x1p-500) {
+    double e1;
+    dd lg = lgamma_pos(two_sum(x, 1.0), &e1);
+    dd lx = log_pair(x);
+    *err = e1 + 0x1p-96 * (fabs(lx.hi) + 1.0);
+    return dd_add(lg, dd_neg(lx));
+  }
   if (x > 0.0) return lgamma_pos(dd_from(x), err);
   double f = fabs(x - nearbyint(x));
-  dd s = f <= 0.25 ? sin_series(dd_mul_d(PI_PAIR, f)) : cos_series(dd_mul_d(PI_PAIR, 0.5 - f));
-  dd ls = log_of_pair(s);
+  dd ls;
+  if (f < 0x1p-500)
+    ls = dd_add(LN_PI, log_pair(f));
+  else
+    ls = log_of_pair(f <= 0.25 ? sin_series(dd_mul_d(PI_PAIR, f))
+                               : cos_series(dd_mul_d(PI_PAIR, 0.5 - f)));
   double e1;
   dd lg = lgamma_pos(two_sum(1.0, -x), &e1);
   *err = e1 + 0x1p-96 * (fabs(LN_PI.hi) + fabs(ls.hi) + 1.0);
@@ -680,9 +710,9 @@ static dd lgamma_any(double x, double* err) {
 
 static int is_pole(double x) { return x == 0.0 || (x < 0.0 && nearbyint(x) == x); }
 
-/* lgamma: 1 with *rn for the exact cases, else 0 with v and *rel, the
-   relative error bound of v */
-static int lgamma_core(double x, dd* v, double* rel, double* rn) {
+/* lgamma: 1 with *rn for the exact cases, else 0 with the value v 2^k and
+   *rel, the relative error bound of v */
+static int lgamma_core(double x, dd* v, int* k, double* rel, double* rn) {
   if (isnan(x)) {
     *rn = x;
     return 1;
@@ -696,7 +726,7 @@ static int lgamma_core(double x, dd* v, double* rel, double* rn) {
     return 1;
   }
   double err;
-  *v = lgamma_any(x, &err);
+  *v = lgamma_any(x, &err, k);
   *rel = err / fabs(v->hi);
   return 0;
 }
@@ -724,9 +754,10 @@ static int tgamma_core(double x, double w_over, double w_zero, dd* v, int* k, do
   }
   double sgn = (x < 0.0 && fmod(floor(x), 2.0) != 0.0) ? -1.0 : 1.0;
   double err;
-  dd w = lgamma_any(x, &err);
-  if (w.hi > w_over || w.hi < w_zero) {
-    *rn = sgn * (w.hi > w_over ? INFINITY : 0.0);
+  int kw;
+  dd w = lgamma_any(x, &err, &kw);
+  if (kw || w.hi > w_over || w.hi < w_zero) { /* kw != 0: x > 2^1000 */
+    *rn = sgn * (kw || w.hi > w_over ? INFINITY : 0.0);
     return 1;
   }
   exp_of_pair(w, v, k);

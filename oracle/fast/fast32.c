@@ -362,7 +362,7 @@ static const double REL = 0x1p-90;
 static int gamma_value(int fn, float x, dd* v, float* rn, double* rel) {
   double r;
   int k = 0;
-  int sp = fn == FN_LGAMMA ? lgamma_core(x, v, rel, &r)
+  int sp = fn == FN_LGAMMA ? lgamma_core(x, v, &k, rel, &r)
                            : tgamma_core(x, 89.5, -104.5, v, &k, rel, &r);
   if (sp) {
     *rn = (float)r;

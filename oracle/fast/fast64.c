@@ -257,10 +257,18 @@ static int hyp64(double x, int kind, dd* v, int* k, double* rn) {
 
 enum { G_SIN, G_EXP, G_LOG, G_COS, G_TAN, G_EXP2, G_LOG2, G_SINH, G_COSH, G_TANH, G_ASIN,
        G_ACOS, G_ATAN, G_LOG10, G_LOG1P, G_EXP10, G_EXPM1, G_CBRT, G_ASINH, G_ACOSH, G_ATANH,
-       G_ERF, G_ERFC };
+       G_ERF, G_ERFC, G_LGAMMA, G_TGAMMA };
 
-static int value64(int fn, double x, dd* v, int* k, double* rn) {
+static const double REL64 = 0x1p-90;
+
+/* the value of fn at x: 1 with *rn for an exact result, else 0 with v 2^k
+   and *rel, the relative error bound of v (2^-90 but for lgamma and tgamma,
+   which carry their own) */
+static int value64(int fn, double x, dd* v, int* k, double* rn, double* rel) {
+  *rel = REL64;
   switch (fn) {
+    case G_LGAMMA: return lgamma_core(x, v, k, rel, rn);
+    case G_TGAMMA: return tgamma_core(x, 710.5, -746.5, v, k, rel, rn);
     case G_ASIN: return asin_core(x, v, k, rn);
     case G_ACOS: return acos_core(x, v, k, rn);
     case G_ATAN: return atan_core(x, v, k, rn);
@@ -323,8 +331,6 @@ static int round_f64(dd v, int k, double rel, double* out) {
   return undecided;
 }
 
-static const double REL64 = 0x1p-90;
-
 /* n inputs: rn the correctly rounded result, hi/lo the value as a pair
    (scaled, so rounded near the bottom of the range), undecided[i] = 1 where
    the ball oracle must answer */
@@ -333,15 +339,15 @@ void oracle_fast64_eval(int fn, const double* x, long n, double* hi, double* lo,
   for (long i = 0; i < n; ++i) {
     dd v;
     int k;
-    double r;
-    if (value64(fn, x[i], &v, &k, &r)) {
+    double r, rel;
+    if (value64(fn, x[i], &v, &k, &r, &rel)) {
       hi[i] = r;
       lo[i] = 0.0;
       rn[i] = r;
       undecided[i] = 0;
       continue;
     }
-    undecided[i] = (uint8_t)round_f64(v, k, REL64, &r);
+    undecided[i] = (uint8_t)round_f64(v, k, rel, &r);
     hi[i] = ldexp(v.hi, k);
     lo[i] = ldexp(v.lo, k);
     rn[i] = r;
@@ -430,11 +436,22 @@ void oracle_fast64_check(int fn, const double* x, const double* y, long n, doubl
   for (long i = 0; i < n; ++i) {
     dd v;
     int k;
-    double r;
-    int exact = value64(fn, x[i], &v, &k, &r);
-    int c = check_elem(exact, v, k, r, REL64, y[i], bound, st, i);
+    double r, rel;
+    int exact = value64(fn, x[i], &v, &k, &r, &rel);
+    int c = check_elem(exact, v, k, r, rel, y[i], bound, st, i);
     if (c == 1 && nu < undec_cap) undec[nu++] = i;
     if (c == 2 && nb < bad_cap) bad[nb++] = i;
+  }
+}
+
+/* the relative error bound the stage claims for each input's pair (0 for
+   the exact results) */
+void oracle_fast64_rel(int fn, const double* x, long n, double* rel) {
+  for (long i = 0; i < n; ++i) {
+    dd v;
+    int k;
+    double r;
+    rel[i] = value64(fn, x[i], &v, &k, &r, &rel[i]) ? 0.0 : rel[i];
   }
 }
 

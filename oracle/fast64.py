@@ -1,9 +1,11 @@
 """ctypes binding of the oracle's fast binary64 stage (``oracle/fast/fast64.c``)
 for sin, cos, tan, exp, exp2, log, log2, sinh, cosh, tanh, asin, acos, atan, log10,
-log1p, exp10, expm1, cbrt, asinh, acosh, atanh, erf, erfc, pow and atan2.
+log1p, exp10, expm1, cbrt, asinh, acosh, atanh, erf, erfc, lgamma, tgamma, pow and
+atan2.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).  The C stage gives the
-value within 2^-90 relative and the correctly rounded binary64 result where
+value within 2^-90 relative (lgamma and tgamma: a bound of its own per input)
+and the correctly rounded binary64 result where
 that bound decides it; ``evaluate`` and ``check_all`` send the inputs it
 cannot decide to the ball oracle.  Pinned against mpmath and the ball oracle
 in ``tests/test_oracle_fast.py``.
@@ -23,7 +25,7 @@ LIB = os.path.join(HERE, "liboracle_fast64.so")
 FNS = {"sin": 0, "exp": 1, "log": 2, "cos": 3, "tan": 4, "exp2": 5, "log2": 6, "sinh": 7,
        "cosh": 8, "tanh": 9, "asin": 10, "acos": 11, "atan": 12, "log10": 13, "log1p": 14,
        "exp10": 15, "expm1": 16, "cbrt": 17, "asinh": 18, "acosh": 19, "atanh": 20, "erf": 21,
-       "erfc": 22}
+       "erfc": 22, "lgamma": 23, "tgamma": 24}
 FNS2 = {"pow": 0, "atan2": 1}          # two operands (oracle/fast/binary.h)
 
 _lib = None
@@ -55,6 +57,8 @@ def load():
         lib = ctypes.CDLL(LIB)
         P = ctypes.c_void_p
         lib.oracle_fast64_eval.restype = None
+        lib.oracle_fast64_rel.restype = None
+        lib.oracle_fast64_rel.argtypes = [ctypes.c_int, P, ctypes.c_long, P]
         lib.oracle_fast64_eval.argtypes = [ctypes.c_int, P, ctypes.c_long, P, P, P, P]
         lib.oracle_fast64_check.restype = None
         lib.oracle_fast64_check.argtypes = [ctypes.c_int, P, P, ctypes.c_long, ctypes.c_double,
@@ -87,6 +91,16 @@ def fast_eval(fn, x, z=None):
         lib.oracle_fast64_eval(FNS[fn], x.ctypes.data, n, hi.ctypes.data, lo.ctypes.data,
                                rn.ctypes.data, und.ctypes.data)
     return rn, hi, lo, und.astype(bool)
+
+
+def fast_rel(fn, x):
+    """The relative error bound the C stage claims for each input's pair
+    (0 where its result is exact), one-operand functions."""
+    lib = load()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    rel = np.empty(x.size, np.float64)
+    lib.oracle_fast64_rel(FNS[fn], x.ctypes.data, x.size, rel.ctypes.data)
+    return rel
 
 
 def evaluate(fn, x, z=None):
