@@ -1,6 +1,6 @@
 """The GPU binary32 sin, cos, tan, exp, exp2, log, log2, sinh, cosh, tanh,
 asin, acos, atan, log10, log1p, exp10, expm1, cbrt, asinh, acosh, atanh,
-erf and erfc against the oracle's fast stage on 8 stretches of 2^20 consecutive bit
+erf, erfc, lgamma and tgamma against the oracle's fast stage on 8 stretches of 2^20 consecutive bit
 patterns spread over all 2^32 (the full sweep over every pattern is
 tests/sweep32.py, run by hand): every result within its bound, NaN, inf,
 zero and subnormal results bit-exact."""
@@ -26,7 +26,7 @@ def _gpu():
 
 KINDS = [(f, "u10") for f in ("sin", "cos", "tan", "exp", "exp2", "log", "log2", "sinh", "cosh",
                                "tanh", "asin", "acos", "atan", "log10", "log1p", "exp10", "expm1",
-                               "cbrt", "asinh", "acosh", "atanh", "erf", "erfc")]
+                               "cbrt", "asinh", "acosh", "atanh", "erf", "erfc", "lgamma", "tgamma")]
 KINDS += [(f, "u35") for f in ("sin", "cos", "tan", "asin", "acos", "atan", "log", "sinh", "cosh",
                                 "tanh")]
 
